@@ -1,0 +1,81 @@
+"""Closed forms of w* = phi_l(h J) v used to pin the oracle (not used by it).
+
+* diagonal J: w*_i = phi_l(h lambda_i) v_i (Sec. 1 definition, elementwise);
+* circulant J (periodic advection-diffusion or pure diffusion): J is
+  diagonalised by the 2D DFT, w* = IFFT(phi_l(h sigma) FFT(v)) with sigma the
+  stencil's Fourier symbol;
+* any small J: the Sec. 2.1 theorem -- phi_l(A) b is the top block of the last
+  column of exp of the augmented matrix [[A, b, 0], [0, 0, I], [0, 0, 0]] --
+  evaluated with scipy's Pade scaling-and-squaring expm (Sec. 1 names Pade and
+  scaling-and-squaring as the dense methods).
+
+Complex phi_l for the Fourier symbol is evaluated through the same theorem on
+the scalar (l+1)x(l+1) augmented matrix, so this module does not reuse the
+oracle's phi.
+"""
+from __future__ import annotations
+
+import numpy as np
+import scipy.linalg
+
+
+def augmented(A: np.ndarray, b: np.ndarray, l: int) -> np.ndarray:
+    """(n+l) x (n+l) matrix whose exponential holds phi_l(A) b (Sec. 2.1 theorem).
+
+    With p = l, B = [b, 0, ..., 0] (b in the column paired with phi_l) and the
+    shift block K, the last column of exp(A~) starts with phi_l(A) b.
+    """
+    n = A.shape[0]
+    M = np.zeros((n + l, n + l), dtype=np.result_type(A, b, np.float64))
+    M[:n, :n] = A
+    if l == 0:
+        return M
+    M[:n, n] = b
+    for i in range(l - 1):
+        M[n + i, n + i + 1] = 1.0
+    return M
+
+
+def phi_dense(A: np.ndarray, b: np.ndarray, l: int) -> np.ndarray:
+    """phi_l(A) b via Pade expm of the augmented matrix."""
+    n = A.shape[0]
+    if l == 0:
+        return scipy.linalg.expm(A) @ b
+    E = scipy.linalg.expm(augmented(A, b, l))
+    return E[:n, n + l - 1]
+
+
+def phi_scalar_expm(l: int, z: complex) -> complex:
+    """phi_l(z) for one (complex) z from the (l+1)x(l+1) augmented exponential."""
+    A = np.array([[z]], dtype=complex)
+    return complex(phi_dense(A, np.array([1.0 + 0j]), l)[0])
+
+
+def diag_closed_form(lam: np.ndarray, v: np.ndarray, l: int, h: float, phi_fn) -> np.ndarray:
+    """w*_i = phi_l(h lambda_i) v_i, phi_fn(l, z) a scalar phi evaluator."""
+    return np.array([phi_fn(l, h * x) * vi for x, vi in zip(lam, v)])
+
+
+def advdiff_symbol(nx, ny, dx, dy, nu, ax, ay) -> np.ndarray:
+    """Fourier symbol sigma[ky, kx] of nu*Lap - ax*Dx - ay*Dy (centred, periodic).
+
+    For the mode e^{i(theta_x i + theta_y j)}: the second difference gives
+    (2 cos theta - 2)/dx^2 and the centred first difference i sin(theta)/dx.
+    """
+    tx = 2.0 * np.pi * np.fft.fftfreq(nx)  # theta_x = 2 pi k / nx
+    ty = 2.0 * np.pi * np.fft.fftfreq(ny)
+    TX, TY = np.meshgrid(tx, ty, indexing="xy")
+    lap = (2.0 * np.cos(TX) - 2.0) / dx ** 2 + (2.0 * np.cos(TY) - 2.0) / dy ** 2
+    adv = 1j * (ax * np.sin(TX) / dx + ay * np.sin(TY) / dy)
+    return nu * lap - adv
+
+
+def fourier_closed_form(sigma: np.ndarray, v: np.ndarray, l: int, h: float) -> np.ndarray:
+    """w* = IFFT(phi_l(h sigma) FFT(v)) for a circulant operator with symbol sigma."""
+    ny, nx = sigma.shape
+    V = np.fft.fft2(np.asarray(v).reshape(ny, nx))
+    g = np.empty_like(V)
+    for idx, s in np.ndenumerate(sigma):
+        g[idx] = phi_scalar_expm(l, h * s)
+    w = np.fft.ifft2(g * V)
+    return w.real.ravel()

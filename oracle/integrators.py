@@ -1,0 +1,99 @@
+"""Exponential-integrator steps built on the Leja action (stage driver).
+
+Sec. 1: u_t = f(u) is linearised at u^n as J(u^n) u + F(u^n) and the
+nonlinear remainders enter through R(x) = F(x) - F(u^n).  The schemes:
+
+* EXPRB2: u_out = u + phi_1(h J) h f(u) (the first term of every scheme in
+  Sec. 5; exponential Rosenbrock-Euler).
+* EXPRB43 (Sec. 5.4 equation): internal stages a (coefficient 1/2) and b, the
+  third-order u_3 and the fourth-order u_4 = u_3 + phi_4 term.  phi_1(h/2 J) and
+  phi_1(h J) on h f(u) run vertically (Sec. 5.4 text).  'EXPRB43_U3' stops at u_3.
+* EPIRK4s3 (Sec. 5.1 equation): phi_1 at 1/8, 1/9 and 1 on h f(u) vertically,
+  then phi_3 and phi_4 individually (Sec. 5.1 text).
+
+One spectral bound is computed per step and shared by every action (J is fixed
+over the step; Sec. 4: the re-scaling is done once).  err = u_4 - u_3 for the
+embedded pairs.
+"""
+from __future__ import annotations
+
+from dataclasses import replace
+
+import numpy as np
+
+from .leja import Options, phi_vertical
+from .power import power_iteration
+
+
+def _bound(op, opt: Options) -> tuple[float, int]:
+    if opt.bound is not None and opt.bound > 0:
+        return float(opt.bound), 0
+    return power_iteration(op.jv, op.n, opt.power_iters, opt.power_seed), opt.power_iters
+
+
+def step(op, scheme: str, h: float, tol: float, opt: Options | None = None):
+    """One step from u = op.state.  Returns (u_out, err or None, list of action stats)."""
+    opt = opt or Options()
+    u = op.state
+    lam, pit = _bound(op, opt)
+    o = replace(opt, bound=lam)
+    fu = op.rhs(u)
+    v = h * fu
+    log = []
+
+    def act(vec, ls, As):
+        ws, st = phi_vertical(op, vec, ls, As, h, tol, o)
+        log.append(st)
+        return ws
+
+    if scheme == "EXPRB2":
+        (A,) = act(v, [1], [1.0])
+        out = (u + A, None)
+    elif scheme in ("EXPRB43", "EXPRB43_U3"):
+        A, B = act(v, [1, 1], [0.5, 1.0])
+        a = u + 0.5 * A
+        Ra = op.remainder(a, fu)
+        (C,) = act(h * Ra, [1], [1.0])
+        b = u + B + C
+        Rb = op.remainder(b, fu)
+        (D3,) = act(h * (16.0 * Ra - 2.0 * Rb), [3], [1.0])
+        u3 = u + B + D3
+        if scheme == "EXPRB43_U3":
+            out = (u3, None)
+        else:
+            (D4,) = act(h * (-48.0 * Ra + 12.0 * Rb), [4], [1.0])
+            u4 = u3 + D4
+            out = (u4, u4 - u3)
+    elif scheme == "EPIRK4S3":
+        A, B, C = act(v, [1, 1, 1], [1.0 / 8.0, 1.0 / 9.0, 1.0])
+        a = u + A / 8.0
+        b = u + B / 9.0
+        Ra = op.remainder(a, fu)
+        Rb = op.remainder(b, fu)
+        D3v = h * (1892.0 * Ra + 1458.0 * (Rb - 2.0 * Ra))
+        (D3,) = act(D3v, [3], [1.0])
+        u3 = u + C + D3
+        D4v = h * (-42336.0 * Ra - 34992.0 * (Rb - 2.0 * Ra))
+        (D4,) = act(D4v, [4], [1.0])
+        u4 = u3 + D4
+        out = (u4, u4 - u3)
+    else:
+        raise ValueError(scheme)
+    if log:
+        log[0].power_iters = pit
+    return out[0], out[1], log
+
+
+def rk_reference(op_factory, u0, T: float, nsteps: int) -> np.ndarray:
+    """Classical RK4 with many small steps: a plain reference solution of u_t = f(u)
+    used only by order tests (op_factory(u) -> operator linearised at u)."""
+    u = np.array(u0, dtype=np.float64)
+    dt = T / nsteps
+    f = lambda w: op_factory(w).rhs(w)  # noqa: E731
+    for _ in range(nsteps):
+        k1 = f(u)
+        k2 = f(u + 0.5 * dt * k1)
+        k3 = f(u + 0.5 * dt * k2)
+        k4 = f(u + dt * k3)
+        u = u + dt / 6.0 * (k1 + 2 * k2 + 2 * k3 + k4)
+    return u

@@ -1,0 +1,302 @@
+"""Pins of the oracle's Leja action against closed forms (elementwise phi for a
+diagonal J, Fourier diagonalisation, dense Pade expm of the Sec. 2.1 augmented
+matrix), the paper's qualitative claims, the substep identity and the
+rejection rules; and of the stage driver against e^{hJ} and its order."""
+from dataclasses import replace
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+import oracle.leja as leja
+from oracle.exact import advdiff_symbol, diag_closed_form, fourier_closed_form, phi_dense
+from oracle.integrators import rk_reference, step
+from oracle.leja import Options, phi_action, phi_vertical
+from oracle.operators import Operator
+from oracle.phi import phi
+from workloads import advdiff_bump, allen_cahn_noise, brusselator_perturbed, diag_problem
+from workloads.problems import Problem
+
+
+def rel(a, b):
+    return np.linalg.norm(np.asarray(a) - np.asarray(b)) / np.linalg.norm(b)
+
+
+@pytest.fixture(scope="module")
+def cfg1():
+    p, v = advdiff_bump()
+    op = Operator(p)
+    sig = advdiff_symbol(p.nx, p.ny, p.dx, p.dy, *p.coef)
+    return p, v, op, sig
+
+
+# --------------------------------------------------------------- closed forms
+@pytest.mark.parametrize("l", [0, 1, 2, 3, 4])
+def test_diagonal_closed_form(l):
+    p = diag_problem(400, -500.0, seed=3)
+    op = Operator(p)
+    v = np.random.default_rng(l).uniform(-1, 1, 400)
+    h = 0.2
+    ref = diag_closed_form(p.state, v, l, h, phi)
+    w, st = phi_action(op, v, l, h, 1e-14)
+    assert st.converged and rel(w, ref) <= 1e-12
+    w, st = phi_action(op, v, l, h, 1e-10)
+    assert rel(w, ref) <= 1e-9
+
+
+@pytest.mark.parametrize("l", [1, 2])
+def test_fourier_closed_form_config1(cfg1, l):
+    p, v, op, sig = cfg1
+    h = 10 * p.h_cfl
+    ref = fourier_closed_form(sig, v, l, h)
+    w, st = phi_action(op, v, l, h, 1e-10)
+    assert rel(w, ref) <= 1e-9
+    w, st = phi_action(op, v, l, h, 1e-14)
+    assert rel(w, ref) <= 1e-12
+
+
+def test_fourier_matches_dense_pade(cfg1):
+    p, v, op, sig = cfg1
+    h = 10 * p.h_cfl
+    ref_f = fourier_closed_form(sig, v, 1, h)
+    ref_d = phi_dense(h * op.dense(), v, 1)
+    assert rel(ref_f, ref_d) <= 1e-13
+
+
+@pytest.mark.parametrize("kind", ["allencahn", "brusselator", "burgers"])
+@pytest.mark.parametrize("l", [0, 1, 3])
+def test_dense_pade_small_grids(kind, l):
+    if kind == "allencahn":
+        p = allen_cahn_noise(16, eps=1e-2, seed=8)
+        p.state = p.state * 8  # reach the nonlinear range |u| <= 0.8
+    elif kind == "brusselator":
+        # diffusion-dominated, as at 1024^2 with D = 2e-3: the reaction's unstable
+        # pair (Re = 1/2) then sits just beyond the right end of the interval
+        p = brusselator_perturbed(12, D=0.1, seed=8, amp=0.3)
+    else:
+        # grid Peclet ~1.25: diffusion-dominated like the 2048^2 workload
+        p = Problem("burgers", 16, 16, 1, 1 / 16, 1 / 16, (5e-2,),
+                    np.sin(2 * np.pi * np.arange(256) / 256 * 3), (1 / 16) ** 2 / 0.2)
+    op = Operator(p)
+    v = np.random.default_rng(1).uniform(-1, 1, p.n)
+    h = 10 * p.h_cfl
+    ref = phi_dense(h * op.dense(), v, l)
+    w, st = phi_action(op, v, l, h, 1e-14)
+    assert st.converged and rel(w, ref) <= 1e-12
+    w, st = phi_action(op, v, l, h, 1e-10)
+    assert rel(w, ref) <= 1e-9
+
+
+# ------------------------------------------------- the paper's qualitative claims
+def test_more_points_for_larger_steps(cfg1):
+    # Sec. 2.2: larger step sizes need more Leja points
+    p, v, op, _ = cfg1
+    ms = [phi_action(op, v, 1, k * p.h_cfl, 1e-10)[1].m_star[0] for k in (1, 3, 10, 30)]
+    assert ms == sorted(ms) and ms[0] < ms[-1]
+
+
+def test_higher_phi_converges_faster():
+    # Appendix A: higher-order phi functions converge faster
+    p = allen_cahn_noise(64, eps=1e-3, seed=2)
+    op = Operator(p)
+    v = 10 * p.h_cfl * op.rhs(p.state)
+    ms = [phi_action(op, v, l, 30 * p.h_cfl, 1e-10)[1].m_star[0] for l in (1, 2, 3)]
+    assert ms[2] <= ms[1] <= ms[0]
+
+
+def test_vertical_shares_basis_and_saves_work():
+    # Sec. 4: phi_1 at 1/8, 1/9 and 1 on the same vector cost about one action
+    p = allen_cahn_noise(64, eps=1e-3, seed=2)
+    op = Operator(p)
+    h = 10 * p.h_cfl
+    v = h * op.rhs(p.state)
+    As = [1 / 8, 1 / 9, 1.0]
+    lam = leja.power_iteration(op.jv, p.n, 20)
+    o = Options(bound=lam)
+    ws, st = phi_vertical(op, v, [1, 1, 1], As, h, 1e-10, o)
+    single = [phi_vertical(op, v, [1], [a], h, 1e-10, o) for a in As]
+    for k in range(3):
+        # identical arithmetic on the shared basis: bit-identical results
+        assert np.array_equal(ws[k], single[k][0][0])
+        assert st.m_star[k] == single[k][1].m_star[0]
+    # smaller coefficient -> fewer points (Sec. 4, EPIRK4s3 vs EPIRK4s3A)
+    assert st.m_star[0] <= st.m_star[2] and st.m_star[1] <= st.m_star[2]
+    assert st.iters_total == max(st.m_star) < sum(s[1].iters_total for s in single)
+
+
+# ---------------------------------------------------------------- substepping
+@pytest.mark.parametrize("l", [0, 1, 2, 3])
+def test_substep_identity_diagonal(l):
+    p = diag_problem(300, -400.0, seed=4)
+    op = Operator(p)
+    v = np.random.default_rng(2).uniform(-1, 1, 300)
+    h = 0.25
+    ref = diag_closed_form(p.state, v, l, h, phi)
+    for s in (2, 4, 8):
+        w, st = phi_action(op, v, l, h, 1e-14, Options(substeps=s))
+        assert st.converged and st.substeps == [s]
+        assert rel(w, ref) <= 1e-12, (l, s)
+
+
+def test_substep_invariance_advdiff(cfg1):
+    p, v, op, sig = cfg1
+    h = 10 * p.h_cfl
+    base, _ = phi_action(op, v, 2, h, 1e-10)
+    for s in (2, 4, 8):
+        w, st = phi_action(op, v, 2, h, 1e-10, Options(substeps=s))
+        assert rel(w, base) <= s * 10 * 1e-10
+
+
+def test_rejection_then_substeps_config1_100cfl(cfg1):
+    p, v, op, sig = cfg1
+    h = 100 * p.h_cfl
+    w, st = phi_action(op, v, 1, h, 1e-10)
+    assert st.rejections >= 1 and st.substeps[0] >= 2 and st.converged
+    assert rel(w, fourier_closed_form(sig, v, 1, h)) <= 1e-8
+
+
+def test_forced_small_max_points_triggers_substepping(cfg1):
+    p, v, op, sig = cfg1
+    h = 10 * p.h_cfl
+    w, st = phi_action(op, v, 1, h, 1e-10, Options(max_points=12))
+    assert st.rejections >= 1 and st.substeps[0] > 1 and st.converged
+    assert rel(w, fourier_closed_form(sig, v, 1, h)) <= 1e-8
+
+
+def test_substeps_reach_dense_pade_on_burgers():
+    # advection-heavier Burgers: s = 1 is rejected, substeps recover the Pade result
+    p = Problem("burgers", 16, 16, 1, 1 / 16, 1 / 16, (2e-2,),
+                np.sin(2 * np.pi * np.arange(256) / 256 * 3), (1 / 16) ** 2 / 0.08)
+    op = Operator(p)
+    v = np.random.default_rng(1).uniform(-1, 1, p.n)
+    h = 10 * p.h_cfl
+    w, st = phi_action(op, v, 1, h, 1e-10)
+    assert st.converged and st.rejections >= 1 and st.substeps[0] >= 2
+    assert rel(w, phi_dense(h * op.dense(), v, 1)) <= 1e-9
+
+
+def test_no_substeps_allowed_reports_failure(cfg1):
+    p, v, op, _ = cfg1
+    w, st = phi_action(op, v, 1, 100 * p.h_cfl, 1e-10, Options(max_substeps=1))
+    assert not st.converged
+
+
+def test_zero_vector_and_nonfinite(cfg1):
+    p, v, op, _ = cfg1
+    w, st = phi_action(op, np.zeros(p.n), 1, 10 * p.h_cfl, 1e-10)
+    assert st.converged and np.all(w == 0) and st.m_star == [0]
+    bad = v.copy()
+    bad[17] = np.nan
+    w, st = phi_action(op, bad, 1, 10 * p.h_cfl, 1e-10, Options(max_substeps=2))
+    assert not st.converged
+
+
+# ------------------------------------------------------------ planted mistakes
+def test_planted_mistakes_are_caught(cfg1, monkeypatch):
+    """Each plausible slip in the oracle makes a pin fail: the Fourier closed
+    form for slips that change the result, the point count for slips in the
+    interval map (a Leja expansion of an entire function still converges on a
+    badly placed interval, only at a different cost)."""
+    p, v, op, sig = cfg1
+    h = 10 * p.h_cfl
+    ref = fourier_closed_form(sig, v, 1, h)
+
+    def run_with(patch):
+        with monkeypatch.context() as mp_:
+            patch(mp_)
+            leja._XI_CACHE.clear()
+            try:
+                w, st = phi_action(op, v, 1, h, 1e-10)
+                return rel(w, ref), st
+            except Exception:
+                return np.inf, None
+            finally:
+                leja._XI_CACHE.clear()
+
+    err0, st0 = run_with(lambda m: None)
+    assert err0 <= 1e-9 and st0.m_star == [28] and st0.rejections == 0
+    # gamma an eighth instead of a quarter of the interval length
+    _, st = run_with(lambda m: m.setattr(leja, "interval", lambda lam, s: (-0.5 * s * lam, 0.125 * s * lam)))
+    assert st is None or st.m_star != st0.m_star or st.rejections > 0
+    # wrong sign of the shift c
+    err, st = run_with(lambda m: m.setattr(leja, "interval", lambda lam, s: (0.5 * s * lam, 0.25 * s * lam)))
+    assert err > 1e-6 or st is None or st.iters_total > 3 * st0.iters_total
+    # a dropped divided-difference order (coefficients shifted by one)
+    orig = leja.divided_differences
+    err, _ = run_with(lambda m: m.setattr(leja, "divided_differences",
+                                          lambda f, xi: np.concatenate([orig(f, xi)[:5], orig(f, xi)[6:], [0.0]])))
+    assert err > 1e-6
+    # a moved node used consistently is still a valid interpolation: cost changes
+    _, st = run_with(lambda m: m.setattr(leja, "leja_points", lambda n: _moved_node(orig_points(n))))
+    assert st is None or st.m_star != st0.m_star or st.err != st0.err
+    # coefficients taken at nodes one index off from the recurrence's nodes
+    xi = orig_points(102)
+
+    def shifted(l, a, tau, c, gamma, npts):
+        f = [phi(l, a * tau * (c + gamma * x)) for x in xi[1:npts + 1]]
+        return orig(f, xi[1:npts + 1]), max(abs(x) for x in f)
+
+    err, _ = run_with(lambda m: m.setattr(leja, "coefficients", shifted))
+    assert err > 1e-6
+    # phi_l index off by one
+    err, _ = run_with(lambda m: m.setattr(leja, "phi", lambda l, z: phi(l + 1, z)))
+    assert err > 1e-6
+
+
+def _moved_node(x):
+    x = x.copy()
+    x[7] += 1e-3
+    return x
+
+
+def orig_points(n):
+    from oracle.points import leja_points
+    return leja_points(n)
+
+
+# --------------------------------------------------------------- stage driver
+@pytest.mark.parametrize("scheme", ["EXPRB2", "EXPRB43", "EXPRB43_U3", "EPIRK4S3"])
+def test_linear_problem_every_scheme_is_exact_exponential(cfg1, scheme):
+    # f(u) = J u  =>  R = 0 and u + h phi_1(hJ) J u = e^{hJ} u
+    p, v, op, sig = cfg1
+    lin = Operator(p, state=v)
+    h = 10 * p.h_cfl
+    u_out, err, _ = step(lin, scheme, h, 1e-12)
+    ref = fourier_closed_form(sig, v, 0, h)
+    assert rel(u_out, ref) <= 1e-10
+    if err is not None:
+        assert np.linalg.norm(err) <= 1e-10 * np.linalg.norm(ref)
+
+
+def test_printed_coefficients_satisfy_stiff_order_conditions():
+    # With R(U_i) = O(c_i^2) the weights b_i(z) must give sum b_i c_i^2 = 2 phi_3
+    # (order 3) and sum b_i c_i^3 = 6 phi_4 (order 4).  Weights as (phi_3, phi_4)
+    # coefficient pairs, from the equations of Sec. 5.1 and 5.4.
+    F = Fraction
+    epirk = {F(1, 8): (F(1892) - 2 * F(1458), F(-42336) + 2 * F(34992)), F(1, 9): (F(1458), F(-34992))}
+    exprb = {F(1, 2): (F(16), F(-48)), F(1): (F(-2), F(12))}
+    for tab in (epirk, exprb):
+        c2 = [sum(b[i] * c ** 2 for c, b in tab.items()) for i in (0, 1)]
+        c3 = [sum(b[i] * c ** 3 for c, b in tab.items()) for i in (0, 1)]
+        assert c2 == [2, 0] and c3 == [0, 6]
+
+
+@pytest.mark.slow
+def test_observed_order_allen_cahn():
+    # local error of one step vs a fine RK4 reference shrinks like h^(p+1)
+    n = 12
+    x = (np.arange(n) + 0.5) / n * 2 - 1
+    X, Y = np.meshgrid(x, x, indexing="xy")
+    u0 = (0.5 + 0.3 * np.cos(np.pi * X) * np.sin(np.pi * Y)).ravel()
+    base = Problem("allencahn", n, n, 1, 2 / n, 2 / n, (0.02,), u0, 1.0)
+    mk = lambda u: Operator(base, state=u)  # noqa: E731
+    expect = {"EXPRB2": 3, "EXPRB43_U3": 4, "EXPRB43": 5, "EPIRK4S3": 5}
+    for scheme, order in expect.items():
+        errs = []
+        hs = [0.4, 0.2, 0.1]
+        for h in hs:
+            u1, _, _ = step(mk(u0), scheme, h, 1e-14)
+            ref = rk_reference(mk, u0, h, 400)
+            errs.append(np.linalg.norm(u1 - ref))
+        rates = [np.log2(errs[i] / errs[i + 1]) for i in range(2)]
+        assert rates[-1] >= order - 0.6, (scheme, errs, rates)

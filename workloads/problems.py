@@ -1,0 +1,152 @@
+"""Seeded problem instances for the Leja phi-action workloads.
+
+Every instance is a periodic 2D grid problem of one of the families the paper
+uses as test problems (Section 3: advection-diffusion, Allen-Cahn, Brusselator;
+Burgers and a diagonal operator are added as a fifth family and as a closed-form
+check).  Grids are row-major with x fastest; two-component states are
+interleaved (u, v) per grid point.
+
+Only random draws and parameter bookkeeping live here: the operators, the
+right-hand sides and the method itself are implemented separately by the
+oracle and by the HIP library.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+
+import numpy as np
+
+KINDS = ("diag", "advdiff", "allencahn", "brusselator", "burgers")
+
+
+@dataclass
+class Problem:
+    """A linearisation point of one PDE family on a periodic grid.
+
+    kind   : one of KINDS
+    nx, ny : grid points per axis
+    ncomp  : components per grid point (2 for the Brusselator, else 1)
+    dx, dy : grid spacing
+    coef   : family parameters (see the constructors below for the order)
+    state  : the state u at which the Jacobian is taken (flat float64,
+             length nx*ny*ncomp); for 'diag' the diagonal itself; None for the
+             linear advection-diffusion operator
+    h_cfl  : the explicit (forward-Euler) diffusive stability step dx^2/(4 D)
+    """
+
+    kind: str
+    nx: int
+    ny: int
+    ncomp: int
+    dx: float
+    dy: float
+    coef: tuple
+    state: np.ndarray | None
+    h_cfl: float
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def n(self) -> int:
+        return self.nx * self.ny * self.ncomp
+
+
+def _rng(seed: int) -> np.random.Generator:
+    return np.random.Generator(np.random.PCG64(seed))
+
+
+def uniform_vector(n: int, lo: float, hi: float, seed: int) -> np.ndarray:
+    """n float64 draws from U[lo, hi) with PCG64(seed)."""
+    return _rng(seed).uniform(lo, hi, size=n).astype(np.float64)
+
+
+def diag_problem(n: int, lam_min: float, seed: int) -> Problem:
+    """Diagonal operator J = diag(lambda), lambda ~ U[lam_min, 0] (lam_min < 0)."""
+    lam = _rng(seed).uniform(lam_min, 0.0, size=n)
+    return Problem("diag", n, 1, 1, 1.0, 1.0, (), lam.astype(np.float64), 1.0 / abs(lam_min))
+
+
+def advdiff_bump(n: int = 32, nu: float = 1.0, peclet: float = 1.0, seed: int = 1,
+                 sigma: float = 0.1, noise: float = 1e-3):
+    """Linear advection-diffusion u_t = nu*Lap(u) - a.grad(u) on [0,1)^2.
+
+    The velocity a_x = a_y = peclet*nu/dx gives grid Peclet number |a| dx / nu
+    = peclet per axis.  Returns (problem, v) where v is a Gaussian bump of
+    width sigma at a random centre (periodic minimum-image distance) plus
+    U[0, noise) noise.  coef = (nu, a_x, a_y).
+    """
+    dx = 1.0 / n
+    a = peclet * nu / dx
+    rng = _rng(seed)
+    cx, cy = rng.uniform(0.0, 1.0, size=2)
+    x = (np.arange(n) + 0.0) * dx
+    X, Y = np.meshgrid(x, x, indexing="xy")  # X[j, i] = x_i, row j = y_j
+    ddx = np.abs(X - cx)
+    ddx = np.minimum(ddx, 1.0 - ddx)
+    ddy = np.abs(Y - cy)
+    ddy = np.minimum(ddy, 1.0 - ddy)
+    v = np.exp(-(ddx ** 2 + ddy ** 2) / (2.0 * sigma ** 2))
+    v = v + rng.uniform(0.0, noise, size=v.shape)
+    prob = Problem("advdiff", n, n, 1, dx, dx, (nu, a, a), None, dx * dx / (4.0 * nu),
+                   meta={"centre": (cx, cy)})
+    return prob, v.ravel().astype(np.float64)
+
+
+def allen_cahn_noise(n: int = 512, eps: float = 1e-3, seed: int = 2, amp: float = 0.1) -> Problem:
+    """Allen-Cahn u_t = eps*Lap(u) + u - u^3 on [-1,1)^2 (Section 3), periodic.
+
+    u0 ~ U[-amp, amp].  coef = (eps,).
+    """
+    dx = 2.0 / n
+    u = _rng(seed).uniform(-amp, amp, size=n * n)
+    return Problem("allencahn", n, n, 1, dx, dx, (eps,), u.astype(np.float64), dx * dx / (4.0 * eps))
+
+
+def brusselator_perturbed(n: int = 1024, D: float = 2e-3, a: float = 1.0, b: float = 3.0,
+                          seed: int = 3, amp: float = 1e-2) -> Problem:
+    """Brusselator u_t = D Lap u + a - (b+1)u + u^2 v, v_t = D Lap v + b u - u^2 v on [0,1)^2.
+
+    State interleaved (u, v) per point, perturbed by amp*U[-1,1] about the
+    steady state (a, b/a).  coef = (D_u, D_v, a, b).
+    """
+    dx = 1.0 / n
+    rng = _rng(seed)
+    st = np.empty((n * n, 2))
+    st[:, 0] = a + amp * rng.uniform(-1.0, 1.0, size=n * n)
+    st[:, 1] = b / a + amp * rng.uniform(-1.0, 1.0, size=n * n)
+    return Problem("brusselator", n, n, 2, dx, dx, (D, D, a, b), st.ravel(), dx * dx / (4.0 * D))
+
+
+def burgers_sines(n: int = 2048, nu: float = 1e-3, seed: int = 5, modes: int = 8) -> Problem:
+    """Viscous Burgers u_t = nu Lap u - (1/2)(d_x + d_y)(u^2) on [0,1)^2.
+
+    u0 = sum_k A_k sin(2 pi (m_k x + n_k y) + theta_k), m_k, n_k in {1..8},
+    theta ~ U[0, 2 pi), A ~ U[0, 1], scaled to max|u0| = 1.  coef = (nu,).
+    """
+    dx = 1.0 / n
+    rng = _rng(seed)
+    m = rng.integers(1, 9, size=modes)
+    k = rng.integers(1, 9, size=modes)
+    th = rng.uniform(0.0, 2 * np.pi, size=modes)
+    A = rng.uniform(0.0, 1.0, size=modes)
+    x = np.arange(n) * dx
+    X, Y = np.meshgrid(x, x, indexing="xy")
+    u = np.zeros((n, n))
+    for j in range(modes):
+        u += A[j] * np.sin(2 * np.pi * (m[j] * X + k[j] * Y) + th[j])
+    u /= np.abs(u).max()
+    return Problem("burgers", n, n, 1, dx, dx, (nu,), u.ravel().astype(np.float64), dx * dx / (4.0 * nu))
+
+
+def batch_instances(count: int = 256, seed: int = 4, sizes=(128, 192, 256, 384, 512),
+                    eps_range=(1e-4, 1e-2)):
+    """Uneven ensemble of Allen-Cahn instances: n uniform over sizes, eps log-uniform.
+
+    Instance i takes its noise from seed 4000 + i.  Returns a list of Problem.
+    """
+    rng = _rng(seed)
+    ns = rng.choice(np.asarray(sizes), size=count)
+    leps = rng.uniform(np.log(eps_range[0]), np.log(eps_range[1]), size=count)
+    out = []
+    for i in range(count):
+        out.append(allen_cahn_noise(int(ns[i]), float(np.exp(leps[i])), seed=4000 + i))
+    return out
