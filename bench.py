@@ -1,0 +1,208 @@
+"""Benchmark of the Leja phi-action hot path on one MI355X.
+
+One step is one pass of the whole path over the 512^2 Allen-Cahn workload
+(eps = 1e-3, u0 ~ U[-0.1, 0.1], h = 10x the explicit diffusive step, tol 1e-10):
+  * an EXPRB2 step         -- power iteration + phi_1(hJ) h f(u)
+  * an EPIRK4s3 step       -- power iteration + vertical phi_1 at 1/8, 1/9, 1 +
+                              phi_3 + phi_4 on the stage remainders
+  * a stand-alone phi_2(hJ) h f(u) (bound shared with the EPIRK4s3 step)
+i.e. 7 delivered phi-actions per step.  `value` is delivered phi-actions per
+second with inputs resident in HBM.  The roofline object describes the fused
+Leja iteration kernel, timed with HIP events on its launch stream over the
+timed region; `cpu_baseline` times the CPU oracle on a bounded sample.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+       python bench.py --copy-calibration   (plain copy kernel for counter scaling)
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+TOL = 1e-10
+CFL_MULT = 10.0
+ACTIONS_PER_STEP = 7
+KERNEL_SOURCES = ["paper_2211_08948_amd/csrc/kernels.hip", "paper_2211_08948_amd/csrc/device.hpp",
+                  "paper_2211_08948_amd/csrc/common.hpp"]
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "leja_kernel_allen_cahn_512_traffic.json")
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_hash() -> str:
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per fused-kernel launch from committed rocprofv3 counter runs,
+    if they were taken on the current kernel source; else None."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            t = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel_hash") != kernel_hash():
+        return None
+    return t.get("hbm_bytes_per_launch")
+
+
+def algorithmic_bytes(tm: dict, ncomp: int = 1) -> float:
+    """Bytes the Newton recurrence must move: per grid point and iteration, read
+    y_{m-1}, read the linearisation state, write y_m (24 B per component) and
+    read+write every active accumulator (16 B per component)."""
+    return ncomp * (24.0 * tm["point_iters"] + 16.0 * tm["accum_point_iters"])
+
+
+def copy_calibration():
+    import torch
+    n = 1 << 26  # 512 MiB of float64
+    x = torch.ones(n, dtype=torch.float64, device="cuda:0")
+    y = torch.empty_like(x)
+    for _ in range(3):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(10):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t) / 10
+    log(f"copy of {8 * n / 2**20:.0f} MiB: read {8 * n} B + write {8 * n} B per dispatch, "
+        f"{2 * 8 * n / dt / 1e9:.0f} GB/s")
+
+
+def cpu_baseline(prob, h):
+    """The CPU oracle on one full step of the same workload (a bounded sample)."""
+    os.environ.setdefault("OMP_NUM_THREADS", "1")
+    import numpy as np
+
+    from oracle.integrators import step as oracle_step
+    from oracle.leja import Options, phi_action
+    from oracle.operators import Operator
+    op = Operator(prob)
+    v = h * op.rhs(prob.state)
+    t = time.perf_counter()
+    steps = 0
+    while steps < 10 and (steps == 0 or time.perf_counter() - t < 10.0):
+        oracle_step(op, "EXPRB2", h, TOL)
+        _, _, log4 = oracle_step(op, "EPIRK4S3", h, TOL)
+        phi_action(op, v, 2, h, TOL, Options(bound=log4[0].bound))
+        steps += 1
+    dt = time.perf_counter() - t
+    np.asarray(0)
+    return {"value": round(ACTIONS_PER_STEP * steps / dt, 3), "unit": "phi-actions/s", "cores": 1,
+            "kind": "oracle",
+            "sample": f"{steps} full step(s) ({ACTIONS_PER_STEP * steps} actions) of the same 512^2 workload, "
+                      f"FP64 NumPy oracle on 1 core, {dt:.1f} s; host nproc={os.cpu_count()}"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--n", type=int, default=512, help="grid points per axis (default: the 512^2 workload)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (asked for {args.gpus}); multi-GPU runs are not part of "
+              "this build", file=sys.stderr)
+        sys.exit(2)
+    if args.copy_calibration:
+        copy_calibration()
+        return
+
+    import torch
+
+    import paper_2211_08948_amd as lj
+    from workloads import allen_cahn_noise
+
+    prob = allen_cahn_noise(args.n, eps=1e-3, seed=2)
+    h = CFL_MULT * prob.h_cfl
+    ctx = lj.Context(0)
+    op = lj.operator_from(prob, "cuda:0")
+    u_out = torch.empty(prob.n, dtype=torch.float64, device="cuda:0")
+    err = torch.empty_like(u_out)
+    f = torch.empty_like(u_out)
+    lj.lj_rhs(ctx, op, op.state, f)
+    v = (h * f).contiguous()
+    w2 = torch.empty_like(u_out)
+    opt = lj.lj_default_options()
+
+    def one_step():
+        _, s2 = lj.lj_step(ctx, "EXPRB2", op, h, TOL, u_out, None, opt)
+        _, s4 = lj.lj_step(ctx, "EPIRK4S3", op, h, TOL, u_out, err, opt)
+        lj.lj_phi_action(ctx, op, v, w2, 2, h, TOL, lj.lj_default_options(bound=s4[0]["bound"]))
+        return s2, s4
+
+    for _ in range(args.warmup):
+        one_step()
+    torch.cuda.synchronize()
+    lj.lj_timing_read(ctx, reset=True)
+    lj.lj_timing_enable(ctx, True)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        s2, s4 = one_step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    lj.lj_timing_enable(ctx, False)
+    tm = lj.lj_timing_read(ctx, reset=True)
+    dt = t1 - t0
+    value = ACTIONS_PER_STEP * args.steps / dt
+    launches = max(tm["launches"], 1)
+    avg_ms = tm["kernel_ms"] / launches
+    bytes_per_launch = algorithmic_bytes(tm) / launches
+    achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
+    traffic = measured_traffic()
+    log(f"step {dt / args.steps * 1e3:.3f} ms; fused kernel: {tm['launches'] / args.steps:.1f} launches/step, "
+        f"{avg_ms * 1e3:.1f} us avg, {tm['iterations'] / launches:.1f} iterations/launch, "
+        f"{avg_ms * 1e3 * launches / max(tm['iterations'], 1):.2f} us/iteration; power kernel "
+        f"{tm['power_ms'] / max(tm['power_launches'], 1) * 1e3:.1f} us avg over {tm['power_launches']} launches")
+    log(f"m* EXPRB2 {s2[0]['m_star'][0]}, EPIRK4s3 vertical {s4[0]['m_star'][:3]}, phi_3 {s4[1]['m_star'][0]}, "
+        f"phi_4 {s4[2]['m_star'][0]}")
+    out = {
+        "metric": "phi_l(hJ)v actions/sec, 512^2 Allen-Cahn, tol 1e-10",
+        "value": round(value, 2),
+        "unit": "phi-actions/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(dt / args.steps * 1e3, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"allen-cahn {args.n}x{args.n} periodic, eps 1e-3, u0~U[-0.1,0.1] seed 2, "
+                               f"h={CFL_MULT:g}x CFL, tol 1e-10: EXPRB2 + EPIRK4s3 steps + phi_2 action",
+                   "grid": [args.n, args.n], "actions_per_step": ACTIONS_PER_STEP},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": traffic, "kernel": "lj_leja_kernel (fused Newton recurrence)",
+                     "avg_launch_us": round(avg_ms * 1e3, 2),
+                     "algorithmic_bytes_per_launch": round(bytes_per_launch)},
+        "cpu_baseline": None,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(prob, h)
+    ctx.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,210 @@
+/*
+ * leja.h -- C ABI of the MI355X (gfx950) Leja phi-action library.
+ *
+ * The library computes w = phi_l(h J) v for a matrix-free stencil Jacobian J by
+ * polynomial interpolation at Leja points (Deka, Tokman, Einkemmer, "A
+ * comparison of Leja- and Krylov-based iterative schemes for Exponential
+ * Integrators", Sec. 2.2), in its vertical form (Sec. 4), with substepping on
+ * non-convergence, plus an exponential-integrator stage driver (the schemes of
+ * Sec. 5.1 and 5.4).
+ *
+ * Conventions for every entry point:
+ *   - Vector arguments are DEVICE pointers to contiguous IEEE float64 arrays on
+ *     the context's device, of length n = nx*ny*ncomp.  Grids are row-major
+ *     with x fastest; two-component states are interleaved (u, v) per point.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).  All
+ *     device work is enqueued on it.  Calls that return statistics or a
+ *     convergence verdict synchronise that stream once before returning.
+ *   - The caller owns every buffer it passes.  Output vectors must not alias
+ *     input vectors or the operator state.  The library owns the workspace it
+ *     keeps inside the context (grown on demand, freed by lj_destroy).
+ *   - A context is used by one host thread at a time; calls on one context are
+ *     serialised.  Contexts on different devices are independent.
+ *   - Return codes: LJ_OK (0); LJ_ENOTCONV (1): the expansion did not converge
+ *     within max_substeps (outputs hold the last attempt, statistics are
+ *     filled); LJ_EINVAL (-1): an argument is invalid, nothing was enqueued;
+ *     LJ_EHIP (-2): a HIP runtime call failed; LJ_ENOMEM (-3): workspace
+ *     allocation failed.  lj_last_error() describes the last failure.  No C++
+ *     exception crosses this interface.
+ */
+#ifndef LEJA_H
+#define LEJA_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define LJ_API __attribute__((visibility("default")))
+
+#define LJ_OK 0
+#define LJ_ENOTCONV 1
+#define LJ_EINVAL (-1)
+#define LJ_EHIP (-2)
+#define LJ_ENOMEM (-3)
+
+/* Most accumulators that share one Newton basis (vertical form, Sec. 4), and
+ * the highest phi index accepted (the schemes of Sec. 5 use phi_1..phi_4). */
+#define LJ_MAX_K 4
+#define LJ_MAX_L 4
+/* Most Leja points (the table holds LJ_MAX_POINTS + 1 nodes). */
+#define LJ_MAX_POINTS 100
+
+typedef struct lj_context lj_context;
+
+/* Operator families (Sec. 3 test problems on periodic grids, 2nd-order centred
+ * differences).  coef[] meaning per kind:
+ *   LJ_OP_DIAG          J = diag(state); nx = n, ny = 1; coef unused
+ *   LJ_OP_ADVDIFF2D     J = nu Lap - ax d/dx - ay d/dy;  coef = {nu, ax, ay}; state NULL
+ *   LJ_OP_ALLENCAHN2D   f = eps Lap u + u - u^3, J = eps Lap + diag(1 - 3u^2); coef = {eps}
+ *   LJ_OP_BRUSSELATOR2D f = (Du Lap u + a - (b+1)u + u^2 v, Dv Lap v + b u - u^2 v),
+ *                       ncomp = 2, coef = {Du, Dv, a, b}
+ *   LJ_OP_BURGERS2D     f = nu Lap u - (d/dx + d/dy)(u^2/2), J v = nu Lap v - (d/dx + d/dy)(u v);
+ *                       coef = {nu}
+ * J is the exact Jacobian of the semi-discrete right-hand side at `state`. */
+typedef enum {
+  LJ_OP_DIAG = 0,
+  LJ_OP_ADVDIFF2D = 1,
+  LJ_OP_ALLENCAHN2D = 2,
+  LJ_OP_BRUSSELATOR2D = 3,
+  LJ_OP_BURGERS2D = 4
+} lj_op_kind;
+
+typedef struct {
+  int32_t kind;          /* lj_op_kind */
+  int32_t nx, ny, ncomp; /* grid points per axis, components per point */
+  double dx, dy;         /* grid spacing */
+  double coef[8];        /* family parameters, see above */
+  const double* state;   /* device: linearisation state u (n entries) or the diagonal */
+} lj_operator;
+
+/* Options.  Fill with lj_default_options(); NULL means the defaults.
+ * The paper leaves every constant open; the defaults are this library's. */
+typedef struct {
+  double safety;          /* alpha = -safety * lambda_hat (Sec. 2.2 safety factor); 1.25 */
+  int32_t power_iters;    /* Jacobian products of the power iteration; 20 */
+  int32_t max_points;     /* most Newton terms per expansion, <= LJ_MAX_POINTS; 100 */
+  double hump_max;        /* reject when a term exceeds hump_max*||v||*max|f|; 1e4 */
+  int32_t max_substeps;   /* largest substep count tried after rejections; 64 */
+  int32_t relative_tol;   /* 1: stop when |d_m| ||y_m|| <= tol ||p||; 0: <= tol (Sec. 2.2); 1 */
+  double bound;           /* > 0: use as lambda_hat and skip the power iteration; 0 */
+  int32_t substeps;       /* > 1: start with this many substeps; 0 */
+  uint64_t power_seed;    /* SplitMix64 seed of the power-iteration start vector; 0x5EED */
+  const double* pi_start; /* device: explicit start vector (n entries) or NULL */
+} lj_options;
+
+/* Per-call statistics (host struct).  For a vertical call entry k describes
+ * accumulator k.  m_star[k]: Newton terms used when accumulator k converged on
+ * the shared basis; when it needed substeps, the Jacobian products of its
+ * successful substepped attempt; -1 if it never converged. */
+typedef struct {
+  int32_t m_star[LJ_MAX_K];
+  int32_t substeps[LJ_MAX_K]; /* substep count that produced accumulator k */
+  double err_est[LJ_MAX_K];   /* last |d_m| ||y_m|| of accumulator k on the shared basis */
+  int32_t iters_total;        /* Jacobian products in Newton recurrences, all attempts */
+  int32_t power_iters;        /* Jacobian products in the power iteration */
+  int32_t rejections;         /* failed attempts (shared basis or substepped) */
+  int32_t converged;          /* 1 if every accumulator converged */
+  double bound;               /* lambda_hat used */
+  double c, gamma;            /* interval centre and quarter-length (Sec. 2.2) */
+} lj_stats;
+
+/* ---- context --------------------------------------------------------- */
+
+/* Create a context on HIP device `hip_device` (makes it current).  Builds the
+ * Leja table and uploads it.  *out is NULL on failure. */
+LJ_API int lj_create(lj_context** out, int hip_device);
+/* Free the context and its workspace (NULL is a no-op). */
+LJ_API void lj_destroy(lj_context* ctx);
+/* Text of the last error on ctx (or of the last lj_create failure if ctx is NULL). */
+LJ_API const char* lj_last_error(const lj_context* ctx);
+/* Fill *opt with the defaults listed in lj_options. */
+LJ_API void lj_default_options(lj_options* opt);
+/* Library version string. */
+LJ_API const char* lj_version(void);
+
+/* ---- building blocks (each is a step of the path, callable on its own) -- */
+
+/* Leja points xi_0..xi_{count-1} on [-2, 2] (Sec. 2.2): xi_0 = 2 and each next
+ * point maximises prod_j |x - xi_j|; ties go to the leftmost point.  Host-only
+ * (needs no GPU); out is a host array of `count` doubles, 1 <= count <= 101. */
+LJ_API int lj_leja_points(double* out, int count);
+
+/* Power-iteration bound (Sec. 2.2): lambda_hat = ||J x_{K-1}|| / ||x_{K-1}||
+ * after K = iters products, x_k proportional to J^k x_0, x_0[i] = 0.5 + U_i
+ * with U_i the SplitMix64 uniform number i of `seed` (or x_0 = start, a device
+ * vector, when start != NULL).  Result written to *bound (host). */
+LJ_API int lj_spectral_bound(lj_context* ctx, const lj_operator* J, int iters, uint64_t seed,
+                             const double* start, double* bound, void* stream);
+
+/* Newton divided differences (Sec. 2.2) of phi_l(s (c + gamma xi)) at the
+ * first npts Leja points, computed on the device in FP64; d (host, npts
+ * doubles) receives d_0..d_{npts-1}.  Requires 1 <= npts <= LJ_MAX_POINTS+1. */
+LJ_API int lj_divided_differences(lj_context* ctx, int l, double s, double c, double gamma,
+                                  int npts, double* d, void* stream);
+
+/* f(u) of the operator family at u (device in, device out).  For LJ_OP_DIAG
+ * and LJ_OP_ADVDIFF2D this is J u. */
+LJ_API int lj_rhs(lj_context* ctx, const lj_operator* J, const double* u, double* f, void* stream);
+
+/* ---- the action ---------------------------------------------------------- */
+
+/* w = phi_l(h J) v to tolerance tol (Sec. 2.2), 0 <= l <= LJ_MAX_L.
+ * stats (host) may be NULL. */
+LJ_API int lj_phi_action(lj_context* ctx, const lj_operator* J, const double* v, double* w,
+                         int l, double h, double tol, const lj_options* opt, lj_stats* stats,
+                         void* stream);
+
+/* Vertical form (Sec. 4): w[k] = phi_{l[k]}(a[k] h J) v for k < K <= LJ_MAX_K,
+ * all on one Newton basis; l, a, w are host arrays of K entries (w[k] device
+ * pointers, pairwise distinct).  Accumulators that are rejected on the shared
+ * basis are redone one by one with substeps. */
+LJ_API int lj_phi_vertical(lj_context* ctx, const lj_operator* J, const double* v, int K,
+                           const int* l, const double* a, double h, double tol, double* const* w,
+                           const lj_options* opt, lj_stats* stats, void* stream);
+
+/* ---- stage driver ---------------------------------------------------------- */
+
+typedef enum {
+  LJ_EXPRB2 = 1,     /* u + phi_1(hJ) h f(u) */
+  LJ_EXPRB43_U3 = 2, /* third-order u_3 of EXPRB43 (Sec. 5.4 equation) */
+  LJ_EXPRB43 = 3,    /* fourth-order u_4 of EXPRB43, err = u_4 - u_3 */
+  LJ_EPIRK4S3 = 4    /* fourth-order u_4 of EPIRK4s3 (Sec. 5.1 equation), err = u_4 - u_3 */
+} lj_scheme;
+
+/* One step from u = J->state with step size h: u_out (device) receives the
+ * scheme's solution and err (device, may be NULL) the embedded difference
+ * u_4 - u_3 (zero-filled for schemes without one).  One power iteration per
+ * step is shared by all actions.  stats (host) may be NULL; otherwise it is an
+ * array of `nstats` entries receiving the statistics of the step's Leja calls
+ * in order (EXPRB2: 1, EXPRB43_U3: 3, EXPRB43: 4, EPIRK4S3: 3); *ncalls (may be
+ * NULL) receives that count. */
+LJ_API int lj_step(lj_context* ctx, int scheme, const lj_operator* J, double h, double tol,
+                   double* u_out, double* err, const lj_options* opt, lj_stats* stats,
+                   int nstats, int* ncalls, void* stream);
+
+/* ---- measurement ------------------------------------------------------------ */
+
+/* Kernel timing of the fused Leja iteration kernel.  While enabled, the
+ * library brackets every launch of that kernel with HIP events on the launch
+ * stream and accumulates its durations and the Newton iterations it ran. */
+typedef struct {
+  int64_t launches;        /* fused-iteration kernel launches */
+  int64_t iterations;      /* Newton iterations run by those launches */
+  int64_t point_iters;     /* grid points x iterations (algorithmic units) */
+  int64_t accum_point_iters; /* sum over iterations of active accumulators x points */
+  double kernel_ms;        /* summed event-measured duration */
+  int64_t power_launches;  /* power-iteration kernel launches */
+  double power_ms;         /* their summed duration */
+  int64_t power_point_iters;
+} lj_timing;
+
+LJ_API int lj_timing_enable(lj_context* ctx, int enable);
+LJ_API int lj_timing_read(lj_context* ctx, lj_timing* out, int reset);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LEJA_H */

@@ -1,0 +1,232 @@
+"""Python binding of the MI355X Leja phi-action library (libleja.so).
+
+Argument marshalling only: every step of phi_l(hJ)v -- power iteration,
+divided differences, the fused Newton recurrence, substepping, the stage
+driver -- runs in the HIP kernels behind the C ABI of include/leja.h.  PyTorch
+supplies device memory (float64 CUDA tensors) and streams.
+
+The functions carry the C names.  Tensors are checked (device, dtype, shape,
+contiguity) before their pointers cross the ABI.
+"""
+from __future__ import annotations
+
+import ctypes as C
+from dataclasses import dataclass
+from typing import Sequence
+
+from . import _lib
+from ._lib import (  # noqa: F401
+    LJ_EHIP, LJ_EINVAL, LJ_ENOMEM, LJ_ENOTCONV, LJ_EPIRK4S3, LJ_EXPRB2, LJ_EXPRB43, LJ_EXPRB43_U3,
+    LJ_MAX_K, LJ_MAX_L, LJ_OK, LJ_OP_ADVDIFF2D, LJ_OP_ALLENCAHN2D, LJ_OP_BRUSSELATOR2D, LJ_OP_BURGERS2D,
+    LJ_OP_DIAG, LejaLibraryError, lj_operator, lj_options, lj_stats, lj_timing,
+)
+
+KIND_CODES = {
+    "diag": LJ_OP_DIAG, "advdiff": LJ_OP_ADVDIFF2D, "allencahn": LJ_OP_ALLENCAHN2D,
+    "brusselator": LJ_OP_BRUSSELATOR2D, "burgers": LJ_OP_BURGERS2D,
+}
+SCHEMES = {"EXPRB2": LJ_EXPRB2, "EXPRB43_U3": LJ_EXPRB43_U3, "EXPRB43": LJ_EXPRB43, "EPIRK4S3": LJ_EPIRK4S3}
+
+
+class LejaError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"leja error {code}: {msg}")
+        self.code = code
+
+
+def lib():
+    return _lib.load()
+
+
+def _stream_ptr(stream) -> C.c_void_p:
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return C.c_void_p(int(stream.cuda_stream))
+
+
+def _tensor_ptr(t, n: int, what: str) -> C.c_void_p:
+    import torch
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{what} must be a torch.Tensor")
+    if not t.is_cuda or t.dtype != torch.float64 or not t.is_contiguous():
+        raise ValueError(f"{what} must be a contiguous float64 CUDA tensor")
+    if t.numel() != n:
+        raise ValueError(f"{what} has {t.numel()} entries, expected {n}")
+    return C.c_void_p(t.data_ptr())
+
+
+@dataclass
+class Operator:
+    """An lj_operator plus the tensor that keeps its state alive."""
+
+    kind: str
+    nx: int
+    ny: int
+    ncomp: int
+    dx: float
+    dy: float
+    coef: Sequence[float]
+    state: object = None  # float64 CUDA tensor or None
+
+    @property
+    def n(self) -> int:
+        return self.nx * self.ny * self.ncomp
+
+    def c_struct(self) -> lj_operator:
+        op = lj_operator()
+        op.kind = KIND_CODES[self.kind]
+        op.nx, op.ny, op.ncomp = self.nx, self.ny, self.ncomp
+        op.dx, op.dy = float(self.dx), float(self.dy)
+        for i in range(8):
+            op.coef[i] = float(self.coef[i]) if i < len(self.coef) else 0.0
+        op.state = _tensor_ptr(self.state, self.n, "operator state").value if self.state is not None else None
+        return op
+
+
+def lj_default_options(**overrides) -> lj_options:
+    o = lj_options()
+    lib().lj_default_options(C.byref(o))
+    for k, v in overrides.items():
+        if k == "pi_start":
+            v = C.c_void_p(v.data_ptr()) if v is not None else None
+        setattr(o, k, v)
+    return o
+
+
+def lj_leja_points(count: int = 101):
+    buf = (C.c_double * count)()
+    rc = lib().lj_leja_points(buf, count)
+    if rc != LJ_OK:
+        raise LejaError(rc, "lj_leja_points")
+    return list(buf)
+
+
+def lj_version() -> str:
+    return lib().lj_version().decode()
+
+
+class Context:
+    """Owns an lj_context on one HIP device."""
+
+    def __init__(self, device: int = 0):
+        self._lib = lib()
+        h = C.c_void_p()
+        rc = self._lib.lj_create(C.byref(h), int(device))
+        if rc != LJ_OK:
+            raise LejaError(rc, self._lib.lj_last_error(None).decode())
+        self.handle = h
+        self.device = device
+
+    def close(self):
+        if getattr(self, "handle", None):
+            self._lib.lj_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, rc: int, allow_notconv: bool = True) -> int:
+        if rc < 0 or (rc == LJ_ENOTCONV and not allow_notconv):
+            raise LejaError(rc, self._lib.lj_last_error(self.handle).decode())
+        return rc
+
+    def last_error(self) -> str:
+        return self._lib.lj_last_error(self.handle).decode()
+
+
+def lj_create(device: int = 0) -> Context:
+    return Context(device)
+
+
+def lj_spectral_bound(ctx: Context, J: Operator, iters: int = 20, seed: int = 0x5EED, start=None,
+                      stream=None) -> float:
+    op = J.c_struct()
+    out = C.c_double()
+    sp = _tensor_ptr(start, J.n, "start") if start is not None else None
+    ctx._check(ctx._lib.lj_spectral_bound(ctx.handle, C.byref(op), int(iters), C.c_uint64(seed), sp,
+                                          C.byref(out), _stream_ptr(stream)), False)
+    return out.value
+
+
+def lj_divided_differences(ctx: Context, l: int, s: float, c: float, gamma: float, npts: int = 101,
+                           stream=None):
+    buf = (C.c_double * npts)()
+    ctx._check(ctx._lib.lj_divided_differences(ctx.handle, int(l), float(s), float(c), float(gamma),
+                                               int(npts), buf, _stream_ptr(stream)), False)
+    return list(buf)
+
+
+def lj_rhs(ctx: Context, J: Operator, u, f, stream=None) -> None:
+    op = J.c_struct()
+    ctx._check(ctx._lib.lj_rhs(ctx.handle, C.byref(op), _tensor_ptr(u, J.n, "u"), _tensor_ptr(f, J.n, "f"),
+                               _stream_ptr(stream)), False)
+
+
+def lj_phi_action(ctx: Context, J: Operator, v, w, l: int, h: float, tol: float, opt: lj_options | None = None,
+                  stream=None):
+    """w = phi_l(h J) v.  Returns (return code, stats dict)."""
+    op = J.c_struct()
+    st = lj_stats()
+    rc = ctx._lib.lj_phi_action(ctx.handle, C.byref(op), _tensor_ptr(v, J.n, "v"), _tensor_ptr(w, J.n, "w"),
+                                int(l), float(h), float(tol), C.byref(opt) if opt is not None else None,
+                                C.byref(st), _stream_ptr(stream))
+    ctx._check(rc)
+    return rc, st.as_dict(1)
+
+
+def lj_phi_vertical(ctx: Context, J: Operator, v, ls: Sequence[int], As: Sequence[float], h: float, tol: float,
+                    ws: Sequence, opt: lj_options | None = None, stream=None):
+    """w[k] = phi_{l[k]}(a[k] h J) v on one Newton basis.  Returns (rc, stats dict)."""
+    K = len(ls)
+    if len(As) != K or len(ws) != K:
+        raise ValueError("ls, As and ws must have the same length")
+    op = J.c_struct()
+    st = lj_stats()
+    larr = (C.c_int * K)(*[int(x) for x in ls])
+    aarr = (C.c_double * K)(*[float(x) for x in As])
+    warr = (C.c_void_p * K)(*[_tensor_ptr(w, J.n, f"w[{k}]").value for k, w in enumerate(ws)])
+    rc = ctx._lib.lj_phi_vertical(ctx.handle, C.byref(op), _tensor_ptr(v, J.n, "v"), K, larr, aarr, float(h),
+                                  float(tol), warr, C.byref(opt) if opt is not None else None, C.byref(st),
+                                  _stream_ptr(stream))
+    ctx._check(rc)
+    return rc, st.as_dict(K)
+
+
+def lj_step(ctx: Context, scheme: str, J: Operator, h: float, tol: float, u_out, err=None,
+            opt: lj_options | None = None, stream=None):
+    """One exponential-integrator step from J.state.  Returns (rc, list of stats dicts)."""
+    op = J.c_struct()
+    stats = (lj_stats * 4)()
+    ncalls = C.c_int()
+    rc = ctx._lib.lj_step(ctx.handle, SCHEMES[scheme], C.byref(op), float(h), float(tol),
+                          _tensor_ptr(u_out, J.n, "u_out"),
+                          _tensor_ptr(err, J.n, "err") if err is not None else None,
+                          C.byref(opt) if opt is not None else None, stats, 4, C.byref(ncalls),
+                          _stream_ptr(stream))
+    ctx._check(rc)
+    return rc, [stats[i].as_dict() for i in range(ncalls.value)]
+
+
+def lj_timing_enable(ctx: Context, enable: bool = True) -> None:
+    ctx._check(ctx._lib.lj_timing_enable(ctx.handle, 1 if enable else 0), False)
+
+
+def lj_timing_read(ctx: Context, reset: bool = False) -> dict:
+    t = lj_timing()
+    ctx._check(ctx._lib.lj_timing_read(ctx.handle, C.byref(t), 1 if reset else 0), False)
+    return {f: getattr(t, f) for f, _ in t._fields_}
+
+
+def operator_from(prob, device: str = "cuda") -> Operator:
+    """Operator for any object with kind, nx, ny, ncomp, dx, dy, coef and a
+    numpy `state` (or None); the state is copied to a float64 device tensor."""
+    import torch
+    st = None
+    if prob.state is not None:
+        st = torch.as_tensor(prob.state, dtype=torch.float64).to(device).contiguous()
+    return Operator(prob.kind, int(prob.nx), int(prob.ny), int(prob.ncomp), float(prob.dx), float(prob.dy),
+                    tuple(float(c) for c in prob.coef), st)

@@ -1,0 +1,897 @@
+// Host control of the Leja phi-action library: context, workspace, argument
+// checks, the rejection / substep logic, the vertical form and the stage
+// driver.  Every numerical step runs in the kernels of kernels.hip; this file
+// only orchestrates launches on the caller's stream.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/leja.h"
+#include "common.hpp"
+#include "kernels.hpp"
+
+namespace lj {
+int leja_points_host(double* out, int count);
+}
+
+using namespace lj;
+
+// Workspace vectors, each sized to the current problem length on demand.
+enum Slot {
+  W_Y0, W_Y1,                      // Newton basis double buffer / power-iteration vectors
+  W_P0, W_P1, W_P2, W_P3,          // phi_j(tau J) v of a substepped action
+  W_SW0, W_SW1, W_SE,              // substep propagation buffers
+  W_FU, W_V, W_A, W_B, W_C,        // stage driver: f(u), h f(u), vertical results
+  W_XA, W_XB, W_D, W_RA, W_RB,     // stages a, b, x - u, R(a), R(b)
+  W_T3, W_D3, W_T4, W_D4, W_U3,    // phi_3 / phi_4 inputs and results, u_3
+  W_NSLOTS
+};
+
+struct lj_context {
+  int device = 0;
+  int num_cus = 0;
+  std::string err;
+  double* d_xi = nullptr;
+  double* vec[W_NSLOTS] = {};
+  size_t vec_cap[W_NSLOTS] = {};
+  double* d_coef = nullptr;
+  double* d_fmax = nullptr;
+  Scalars* d_scal = nullptr;
+  double* d_partials = nullptr;
+  int partial_cap = 0;  // blocks
+  unsigned int* d_barrier = nullptr;
+  LejaStatus* d_status = nullptr;
+  LejaStatus* h_status = nullptr;  // pinned
+  Scalars* h_scal = nullptr;       // pinned
+  double* h_coef = nullptr;        // pinned
+  int occ_leja[5] = {0, 0, 0, 0, 0};
+  int occ_power[5] = {0, 0, 0, 0, 0};
+  int grid_override = 0;
+  // timing
+  bool timing = false;
+  hipEvent_t ev[4] = {};
+  lj_timing tm = {};
+};
+
+static std::string g_create_error;
+
+namespace {
+
+struct Fail {
+  int code;
+};
+
+#define HIPCHK(ctx, expr)                                                                      \
+  do {                                                                                         \
+    hipError_t e_ = (expr);                                                                    \
+    if (e_ != hipSuccess) {                                                                    \
+      (ctx)->err = std::string(#expr) + ": " + hipGetErrorString(e_);                          \
+      throw Fail{LJ_EHIP};                                                                     \
+    }                                                                                          \
+  } while (0)
+
+[[noreturn]] void invalid(lj_context* ctx, const std::string& msg) {
+  ctx->err = msg;
+  throw Fail{LJ_EINVAL};
+}
+
+double* slot(lj_context* ctx, int s, size_t n) {
+  if (ctx->vec_cap[s] < n) {
+    if (ctx->vec[s]) (void)hipFree(ctx->vec[s]);
+    ctx->vec[s] = nullptr;
+    ctx->vec_cap[s] = 0;
+    hipError_t e = hipMalloc(&ctx->vec[s], n * sizeof(double));
+    if (e != hipSuccess) {
+      ctx->err = std::string("workspace allocation failed: ") + hipGetErrorString(e);
+      throw Fail{LJ_ENOMEM};
+    }
+    ctx->vec_cap[s] = n;
+  }
+  return ctx->vec[s];
+}
+
+struct Opts {
+  double safety;
+  int power_iters;
+  int max_points;
+  double hump;
+  int max_substeps;
+  int relative;
+  double bound;
+  int substeps;
+  uint64_t seed;
+  const double* pi_start;
+};
+
+Opts resolve(lj_context* ctx, const lj_options* o) {
+  lj_options d;
+  lj_default_options(&d);
+  if (!o) o = &d;
+  Opts r{o->safety, o->power_iters, o->max_points, o->hump_max, o->max_substeps, o->relative_tol,
+         o->bound, o->substeps, o->power_seed, o->pi_start};
+  if (!(r.safety > 0.0) || !std::isfinite(r.safety)) invalid(ctx, "options: safety must be > 0");
+  if (r.power_iters < 1 || r.power_iters > 100000) invalid(ctx, "options: power_iters out of range");
+  if (r.max_points < 1 || r.max_points > kMaxPoints) invalid(ctx, "options: max_points must be in [1, 100]");
+  if (!(r.hump > 0.0)) invalid(ctx, "options: hump_max must be > 0");
+  if (r.max_substeps < 1 || r.max_substeps > (1 << 20)) invalid(ctx, "options: max_substeps out of range");
+  if (!(r.bound >= 0.0) || !std::isfinite(r.bound)) invalid(ctx, "options: bound must be finite and >= 0");
+  if (r.substeps < 0) invalid(ctx, "options: substeps must be >= 0");
+  return r;
+}
+
+void check_range(lj_context* ctx, const void* p, size_t bytes, const std::string& what);
+
+OpDev make_op(lj_context* ctx, const lj_operator* J) {
+  if (!J) invalid(ctx, "operator is NULL");
+  if (J->kind < LJ_OP_DIAG || J->kind > LJ_OP_BURGERS2D) invalid(ctx, "operator: unknown kind");
+  if (J->nx < 1 || J->ny < 1) invalid(ctx, "operator: nx and ny must be >= 1");
+  const int want_nc = (J->kind == LJ_OP_BRUSSELATOR2D) ? 2 : 1;
+  if (J->ncomp != want_nc) invalid(ctx, "operator: ncomp must be 2 for the Brusselator and 1 otherwise");
+  const long long n = (long long)J->nx * J->ny * J->ncomp;
+  if (n > (1ll << 30)) invalid(ctx, "operator: grid too large (more than 2^30 unknowns)");
+  if (J->kind == LJ_OP_DIAG && J->ny != 1) invalid(ctx, "operator: DIAG needs ny == 1");
+  if (J->kind != LJ_OP_DIAG && J->kind != LJ_OP_ADVDIFF2D && J->state == nullptr)
+    invalid(ctx, "operator: state is NULL");
+  if (J->kind == LJ_OP_DIAG && J->state == nullptr) invalid(ctx, "operator: DIAG needs its diagonal in state");
+  if (J->kind != LJ_OP_DIAG && (!(J->dx > 0.0) || !(J->dy > 0.0) || !std::isfinite(J->dx) || !std::isfinite(J->dy)))
+    invalid(ctx, "operator: dx and dy must be finite and > 0");
+  for (int i = 0; i < 8; ++i)
+    if (!std::isfinite(J->coef[i])) invalid(ctx, "operator: non-finite coefficient");
+  OpDev op;
+  op.kind = J->kind;
+  op.nx = J->nx;
+  op.ny = J->ny;
+  op.ncomp = J->ncomp;
+  op.c0 = J->coef[0];
+  op.c1 = J->coef[1];
+  op.c2 = J->coef[2];
+  op.c3 = J->coef[3];
+  const double dx = (J->kind == LJ_OP_DIAG) ? 1.0 : J->dx;
+  const double dy = (J->kind == LJ_OP_DIAG) ? 1.0 : J->dy;
+  op.idx2 = 1.0 / (dx * dx);
+  op.idy2 = 1.0 / (dy * dy);
+  op.i2dx = 1.0 / (2.0 * dx);
+  op.i2dy = 1.0 / (2.0 * dy);
+  op.state = J->state;
+  op.npts = J->nx * J->ny;
+  if (op.state) {
+    if (reinterpret_cast<uintptr_t>(op.state) & (op.ncomp == 2 ? 15 : 7)) invalid(ctx, "operator: state is misaligned");
+    check_range(ctx, op.state, (size_t)op.npts * op.ncomp * sizeof(double), "operator state");
+  }
+  return op;
+}
+
+inline size_t nvals(const OpDev& op) { return (size_t)op.npts * op.ncomp; }
+
+// A vector argument must lie inside one device allocation of this context's
+// device: [p, p + n) is checked against the allocation's address range, so a
+// host pointer or a short buffer is an argument error, not a memory fault.
+void check_range(lj_context* ctx, const void* p, size_t bytes, const std::string& what) {
+  hipDeviceptr_t base = nullptr;
+  size_t size = 0;
+  if (hipMemGetAddressRange(&base, &size, const_cast<void*>(p)) != hipSuccess || base == nullptr) {
+    (void)hipGetLastError();
+    invalid(ctx, what + " is not a device allocation");
+  }
+  const uintptr_t b = reinterpret_cast<uintptr_t>(base);
+  const uintptr_t q = reinterpret_cast<uintptr_t>(p);
+  if (q < b || q + bytes > b + size) invalid(ctx, what + " is shorter than the operator's vector length");
+  hipPointerAttribute_t attr;
+  if (hipPointerGetAttributes(&attr, p) == hipSuccess && attr.device != ctx->device)
+    invalid(ctx, what + " lives on another device");
+  (void)hipGetLastError();
+}
+
+void check_vec(lj_context* ctx, const OpDev& op, const void* p, const char* what) {
+  if (!p) invalid(ctx, std::string(what) + " is NULL");
+  if (reinterpret_cast<uintptr_t>(p) & (op.ncomp == 2 ? 15 : 7))
+    invalid(ctx, std::string(what) + " is misaligned");
+  check_range(ctx, p, (size_t)op.npts * op.ncomp * sizeof(double), what);
+}
+
+void ensure_small(lj_context* ctx, int blocks) {
+  if (ctx->partial_cap < blocks) {
+    if (ctx->d_partials) (void)hipFree(ctx->d_partials);
+    ctx->d_partials = nullptr;
+    ctx->partial_cap = 0;
+    if (hipMalloc(&ctx->d_partials, (size_t)2 * blocks * (kMaxK + 1) * sizeof(double)) != hipSuccess) {
+      ctx->err = "partials allocation failed";
+      throw Fail{LJ_ENOMEM};
+    }
+    ctx->partial_cap = blocks;
+  }
+}
+
+// Blocks of a persistent launch: one per CU at most (barrier cost grows with
+// the block count), fewer for small grids, whole rounds over the 8 XCDs.
+int grid_for(lj_context* ctx, int occ, int npts) {
+  const int B = persistent_block();
+  int want = (npts + B - 1) / B;
+  int cap = ctx->num_cus;
+  if (ctx->grid_override > 0) cap = ctx->grid_override < ctx->num_cus * occ ? ctx->grid_override : ctx->num_cus * occ;
+  int g = want < cap ? want : cap;
+  if (g >= 64) g -= g % 8;
+  return g < 1 ? 1 : g;
+}
+
+int occupancy(lj_context* ctx, void* fn, int* cache, int kind) {
+  if (cache[kind] == 0) {
+    int nb = 0;
+    HIPCHK(ctx, hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, persistent_block(), 0));
+    if (nb < 1) {
+      ctx->err = "persistent kernel cannot be resident";
+      throw Fail{LJ_EHIP};
+    }
+    cache[kind] = nb;
+  }
+  return cache[kind];
+}
+
+// ---- power iteration ---------------------------------------------------
+void run_power(lj_context* ctx, const OpDev& op, int iters, uint64_t seed, const double* start, hipStream_t s) {
+  void* fn = power_kernel_ptr(op.kind);
+  const int occ = occupancy(ctx, fn, ctx->occ_power, op.kind);
+  const int G = grid_for(ctx, occ, op.npts);
+  ensure_small(ctx, G);
+  const size_t n = nvals(op);
+  PowerParams P;
+  P.op = op;
+  P.iters = iters;
+  P.seed = seed;
+  P.start = start;
+  P.buf0 = slot(ctx, W_Y0, n);
+  P.buf1 = slot(ctx, W_Y1, n);
+  P.partials = ctx->d_partials;
+  P.barrier = ctx->d_barrier;
+  P.scal = ctx->d_scal;
+  HIPCHK(ctx, launch_fill_u32(ctx->d_barrier, kBarrierWords, 0u, s));
+  void* args[] = {&P};
+  if (ctx->timing) HIPCHK(ctx, hipEventRecord(ctx->ev[2], s));
+  HIPCHK(ctx, hipLaunchCooperativeKernel(fn, dim3(G), dim3(persistent_block()), args, 0, s));
+  if (ctx->timing) {
+    HIPCHK(ctx, hipEventRecord(ctx->ev[3], s));
+    HIPCHK(ctx, hipEventSynchronize(ctx->ev[3]));
+    float ms = 0.f;
+    HIPCHK(ctx, hipEventElapsedTime(&ms, ctx->ev[2], ctx->ev[3]));
+    ctx->tm.power_launches += 1;
+    ctx->tm.power_ms += ms;
+    ctx->tm.power_point_iters += (int64_t)iters * op.npts;
+  }
+}
+
+// ---- one Newton recurrence (divided differences + fused kernel) ---------
+struct RecOut {
+  int state[kMaxK];
+  int m_star[kMaxK];
+  double err[kMaxK];
+  int iters;
+};
+
+RecOut run_recurrence(lj_context* ctx, const OpDev& op, const double* v, int K, const int* l,
+                      const double* s_k, double lam_host, double* const* outs, const Opts& o,
+                      double tol, hipStream_t s) {
+  DDParams D;
+  D.K = K;
+  for (int k = 0; k < kMaxK; ++k) {
+    D.l[k] = (k < K) ? l[k] : 0;
+    D.s[k] = (k < K) ? s_k[k] : 0.0;
+  }
+  D.npts = o.max_points + 1;
+  D.lam_host = lam_host;
+  D.safety = o.safety;
+  D.use_cg = 0;
+  D.c_in = 0.0;
+  D.gamma_in = 0.0;
+  D.xi = ctx->d_xi;
+  D.scal = ctx->d_scal;
+  D.coef = ctx->d_coef;
+  D.fmax = ctx->d_fmax;
+  HIPCHK(ctx, launch_divdiff(D, s));
+
+  void* fn = leja_kernel_ptr(op.kind);
+  const int occ = occupancy(ctx, fn, ctx->occ_leja, op.kind);
+  const int G = grid_for(ctx, occ, op.npts);
+  ensure_small(ctx, G);
+  const size_t n = nvals(op);
+  LejaParams P;
+  P.op = op;
+  P.v = v;
+  P.ybuf0 = slot(ctx, W_Y0, n);
+  P.ybuf1 = slot(ctx, W_Y1, n);
+  for (int k = 0; k < kMaxK; ++k) P.p[k] = (k < K) ? outs[k] : nullptr;
+  P.K = K;
+  P.max_points = o.max_points;
+  P.relative = o.relative;
+  P.tol = tol;
+  P.hump = o.hump;
+  P.coef = ctx->d_coef;
+  P.fmax = ctx->d_fmax;
+  P.xi = ctx->d_xi;
+  P.scal = ctx->d_scal;
+  P.partials = ctx->d_partials;
+  P.barrier = ctx->d_barrier + kBarrierWords;
+  P.status = ctx->d_status;
+  HIPCHK(ctx, launch_fill_u32(ctx->d_barrier + kBarrierWords, kBarrierWords, 0u, s));
+  void* args[] = {&P};
+  if (ctx->timing) HIPCHK(ctx, hipEventRecord(ctx->ev[0], s));
+  HIPCHK(ctx, hipLaunchCooperativeKernel(fn, dim3(G), dim3(persistent_block()), args, 0, s));
+  if (ctx->timing) HIPCHK(ctx, hipEventRecord(ctx->ev[1], s));
+  HIPCHK(ctx, hipMemcpyAsync(ctx->h_status, ctx->d_status, sizeof(LejaStatus), hipMemcpyDeviceToHost, s));
+  HIPCHK(ctx, hipStreamSynchronize(s));
+  RecOut r;
+  for (int k = 0; k < kMaxK; ++k) {
+    r.state[k] = ctx->h_status->state[k];
+    r.m_star[k] = ctx->h_status->m_star[k];
+    r.err[k] = ctx->h_status->err[k];
+  }
+  r.iters = ctx->h_status->iters;
+  if (ctx->timing) {
+    float ms = 0.f;
+    HIPCHK(ctx, hipEventElapsedTime(&ms, ctx->ev[0], ctx->ev[1]));
+    ctx->tm.launches += 1;
+    ctx->tm.iterations += r.iters;
+    ctx->tm.point_iters += (int64_t)r.iters * op.npts;
+    ctx->tm.accum_point_iters += (int64_t)ctx->h_status->accum_iters * op.npts;
+    ctx->tm.kernel_ms += ms;
+  }
+  return r;
+}
+
+void lincomb(lj_context* ctx, size_t n, double* out, int nin, const double* alpha, const double* const* x,
+             hipStream_t s) {
+  LinComb L;
+  L.n = (long)n;
+  L.nin = nin;
+  for (int q = 0; q < 5; ++q) {
+    L.alpha[q] = (q < nin) ? alpha[q] : 0.0;
+    L.x[q] = (q < nin) ? x[q] : nullptr;
+  }
+  L.out = out;
+  HIPCHK(ctx, launch_lincomb(L, s));
+}
+
+double factorial(int k) {
+  double f = 1.0;
+  for (int i = 2; i <= k; ++i) f *= (double)i;
+  return f;
+}
+
+// phi_l(T J) v with s = s_start, 2 s_start, ... substeps (the identity
+// w(t + tau) = e^{tau J} w(t) + sum_j tau^j t^{l-j}/(l-j)! phi_j(tau J) v for
+// w(t) = t^l phi_l(t J) v, scaled by T^l).  Returns true on success.
+bool substepped(lj_context* ctx, const OpDev& op, const double* v, int l, double T, int s_start,
+                double lam_host, const Opts& o, double tol, double* w_out, lj_stats* st, int k,
+                hipStream_t strm) {
+  const size_t n = nvals(op);
+  int s = s_start;
+  while (s <= o.max_substeps) {
+    const double tau = T / (double)s;
+    bool ok = true;
+    int used = 0;
+    if (l == 0) {
+      const double* in = v;
+      for (int i = 0; i < s && ok; ++i) {
+        double* out = (i == s - 1) ? w_out : slot(ctx, (i & 1) ? W_SW1 : W_SW0, n);
+        const int l0 = 0;
+        const double sk = tau;
+        RecOut r = run_recurrence(ctx, op, in, 1, &l0, &sk, lam_host, &out, o, tol, strm);
+        used += r.iters;
+        if (r.state[0] != ACC_CONVERGED) ok = false;
+        in = out;
+      }
+    } else {
+      double* P[kMaxK];
+      int ls[kMaxK];
+      double ss[kMaxK];
+      for (int j = 0; j < l; ++j) {
+        P[j] = slot(ctx, W_P0 + j, n);
+        ls[j] = j + 1;
+        ss[j] = tau;
+      }
+      RecOut r = run_recurrence(ctx, op, v, l, ls, ss, lam_host, P, o, tol, strm);
+      used += r.iters;
+      for (int j = 0; j < l; ++j)
+        if (r.state[j] != ACC_CONVERGED) ok = false;
+      if (ok) {
+        double* cur = (s == 1) ? w_out : slot(ctx, W_SW0, n);
+        {
+          const double a = 1.0 / std::pow((double)s, (double)l);
+          const double* x[1] = {P[l - 1]};
+          lincomb(ctx, n, cur, 1, &a, x, strm);
+        }
+        for (int i = 1; i < s && ok; ++i) {
+          double* e = slot(ctx, W_SE, n);
+          const int l0 = 0;
+          const double sk = tau;
+          RecOut r2 = run_recurrence(ctx, op, cur, 1, &l0, &sk, lam_host, &e, o, tol, strm);
+          used += r2.iters;
+          if (r2.state[0] != ACC_CONVERGED) {
+            ok = false;
+            break;
+          }
+          double* nxt = (i == s - 1) ? w_out : slot(ctx, (cur == ctx->vec[W_SW0]) ? W_SW1 : W_SW0, n);
+          double alpha[5];
+          const double* xs[5];
+          alpha[0] = 1.0;
+          xs[0] = e;
+          for (int j = 1; j <= l; ++j) {
+            alpha[j] = std::pow((double)i, (double)(l - j)) / (factorial(l - j) * std::pow((double)s, (double)l));
+            xs[j] = P[j - 1];
+          }
+          lincomb(ctx, n, nxt, l + 1, alpha, xs, strm);
+          cur = nxt;
+        }
+      }
+    }
+    st->iters_total += used;
+    if (ok) {
+      st->substeps[k] = s;
+      st->m_star[k] = used;
+      return true;
+    }
+    st->rejections += 1;
+    s *= 2;
+  }
+  st->substeps[k] = s / 2;
+  st->m_star[k] = -1;
+  return false;
+}
+
+void read_scalars(lj_context* ctx, lj_stats* st, hipStream_t s) {
+  HIPCHK(ctx, hipMemcpyAsync(ctx->h_scal, ctx->d_scal, sizeof(Scalars), hipMemcpyDeviceToHost, s));
+  HIPCHK(ctx, hipStreamSynchronize(s));
+  st->bound = ctx->h_scal->lam;
+  st->c = ctx->h_scal->c;
+  st->gamma = ctx->h_scal->gamma;
+}
+
+// Vertical action (the core of lj_phi_action / lj_phi_vertical / lj_step).
+int vertical_impl(lj_context* ctx, const OpDev& op, const double* v, int K, const int* l, const double* a,
+                  double h, double tol, double* const* w, const Opts& o, lj_stats* st, hipStream_t s) {
+  std::memset(st, 0, sizeof(*st));
+  for (int k = 0; k < LJ_MAX_K; ++k) {
+    st->m_star[k] = -1;
+    st->substeps[k] = 1;
+  }
+  double lam_host = 0.0;
+  if (o.bound > 0.0) {
+    lam_host = o.bound;
+  } else {
+    run_power(ctx, op, o.power_iters, o.seed, o.pi_start, s);
+    st->power_iters = o.power_iters;
+  }
+  int s0 = (o.substeps > 1) ? o.substeps : 1;
+  std::vector<int> pending;
+  if (s0 == 1) {
+    double sk[kMaxK];
+    for (int k = 0; k < K; ++k) sk[k] = a[k] * h;
+    RecOut r = run_recurrence(ctx, op, v, K, l, sk, lam_host, w, o, tol, s);
+    st->iters_total += r.iters;
+    for (int k = 0; k < K; ++k) {
+      if (r.state[k] == ACC_CONVERGED) {
+        st->m_star[k] = r.m_star[k];
+        st->err_est[k] = r.err[k];
+      } else {
+        pending.push_back(k);
+      }
+    }
+    if (!pending.empty()) st->rejections += 1;
+    s0 = 2;
+  } else {
+    for (int k = 0; k < K; ++k) pending.push_back(k);
+  }
+  bool all_ok = true;
+  for (int k : pending) {
+    if (!substepped(ctx, op, v, l[k], a[k] * h, s0, lam_host, o, tol, w[k], st, k, s)) all_ok = false;
+  }
+  st->converged = all_ok ? 1 : 0;
+  read_scalars(ctx, st, s);
+  return all_ok ? LJ_OK : LJ_ENOTCONV;
+}
+
+void check_action_args(lj_context* ctx, const OpDev& op, const double* v, int K, const int* l, const double* a,
+                       double h, double tol, double* const* w) {
+  if (K < 1 || K > LJ_MAX_K) invalid(ctx, "K must be in [1, 4]");
+  if (!l || !a || !w) invalid(ctx, "l, a and w must not be NULL");
+  if (!std::isfinite(h)) invalid(ctx, "h must be finite");
+  if (!(tol > 0.0) || !std::isfinite(tol)) invalid(ctx, "tol must be finite and > 0");
+  check_vec(ctx, op, v, "v");
+  for (int k = 0; k < K; ++k) {
+    if (l[k] < 0 || l[k] > LJ_MAX_L) invalid(ctx, "l must be in [0, 4]");
+    if (!std::isfinite(a[k])) invalid(ctx, "a[k] must be finite");
+    check_vec(ctx, op, w[k], "w[k]");
+    if (w[k] == v) invalid(ctx, "w must not alias v");
+    if (w[k] == op.state) invalid(ctx, "w must not alias the operator state");
+    for (int q = 0; q < k; ++q)
+      if (w[q] == w[k]) invalid(ctx, "the outputs w[k] must be distinct");
+  }
+}
+
+template <class F>
+int guarded(lj_context* ctx, F&& f) {
+  if (!ctx) return LJ_EINVAL;
+  try {
+    ctx->err.clear();
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev != ctx->device) HIPCHK(ctx, hipSetDevice(ctx->device));
+    return f();
+  } catch (const Fail& e) {
+    return e.code;
+  } catch (...) {
+    ctx->err = "unexpected internal error";
+    return LJ_EHIP;
+  }
+}
+
+}  // namespace
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+extern "C" {
+
+LJ_API const char* lj_version(void) { return "leja-mi355x 0.1 (gfx950)"; }
+
+LJ_API void lj_default_options(lj_options* opt) {
+  if (!opt) return;
+  std::memset(opt, 0, sizeof(*opt));
+  opt->safety = 1.25;
+  opt->power_iters = 20;
+  opt->max_points = 100;
+  opt->hump_max = 1e4;
+  opt->max_substeps = 64;
+  opt->relative_tol = 1;
+  opt->bound = 0.0;
+  opt->substeps = 0;
+  opt->power_seed = 0x5EED;
+  opt->pi_start = nullptr;
+}
+
+LJ_API const char* lj_last_error(const lj_context* ctx) {
+  return ctx ? ctx->err.c_str() : g_create_error.c_str();
+}
+
+LJ_API int lj_leja_points(double* out, int count) {
+  if (!out || count < 1 || count > kTable) return LJ_EINVAL;
+  return leja_points_host(out, count);
+}
+
+LJ_API int lj_create(lj_context** out, int hip_device) {
+  if (!out) return LJ_EINVAL;
+  *out = nullptr;
+  g_create_error.clear();
+  int ndev = 0;
+  hipError_t e = hipGetDeviceCount(&ndev);
+  if (e != hipSuccess || ndev < 1) {
+    g_create_error = std::string("no HIP device: ") + hipGetErrorString(e);
+    return LJ_EHIP;
+  }
+  if (hip_device < 0 || hip_device >= ndev) {
+    g_create_error = "device index out of range";
+    return LJ_EINVAL;
+  }
+  lj_context* ctx = new lj_context();
+  ctx->device = hip_device;
+  try {
+    HIPCHK(ctx, hipSetDevice(hip_device));
+    hipDeviceProp_t prop;
+    HIPCHK(ctx, hipGetDeviceProperties(&prop, hip_device));
+    ctx->num_cus = prop.multiProcessorCount;
+    int coop = 0;
+    HIPCHK(ctx, hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, hip_device));
+    if (!coop) {
+      ctx->err = "device does not support cooperative launches";
+      throw Fail{LJ_EHIP};
+    }
+    double xi[kTable];
+    leja_points_host(xi, kTable);
+    HIPCHK(ctx, hipMalloc(&ctx->d_xi, kTable * sizeof(double)));
+    HIPCHK(ctx, hipMemcpy(ctx->d_xi, xi, kTable * sizeof(double), hipMemcpyHostToDevice));
+    HIPCHK(ctx, hipMalloc(&ctx->d_coef, kMaxK * kTable * sizeof(double)));
+    HIPCHK(ctx, hipMalloc(&ctx->d_fmax, kMaxK * sizeof(double)));
+    HIPCHK(ctx, hipMalloc(&ctx->d_scal, sizeof(Scalars)));
+    HIPCHK(ctx, hipMalloc(&ctx->d_barrier, 2 * kBarrierWords * sizeof(unsigned int)));
+    HIPCHK(ctx, hipMalloc(&ctx->d_status, sizeof(LejaStatus)));
+    HIPCHK(ctx, hipHostMalloc(&ctx->h_status, sizeof(LejaStatus), hipHostMallocDefault));
+    HIPCHK(ctx, hipHostMalloc(&ctx->h_scal, sizeof(Scalars), hipHostMallocDefault));
+    HIPCHK(ctx, hipHostMalloc(&ctx->h_coef, kMaxK * kTable * sizeof(double), hipHostMallocDefault));
+    HIPCHK(ctx, hipMemset(ctx->d_scal, 0, sizeof(Scalars)));
+    for (int i = 0; i < 4; ++i) HIPCHK(ctx, hipEventCreate(&ctx->ev[i]));
+    if (const char* g = std::getenv("LJ_GRID")) ctx->grid_override = std::atoi(g);
+  } catch (const Fail& f) {
+    g_create_error = ctx->err;
+    lj_destroy(ctx);
+    return f.code;
+  }
+  *out = ctx;
+  return LJ_OK;
+}
+
+LJ_API void lj_destroy(lj_context* ctx) {
+  if (!ctx) return;
+  (void)hipSetDevice(ctx->device);
+  (void)hipDeviceSynchronize();
+  for (int i = 0; i < W_NSLOTS; ++i)
+    if (ctx->vec[i]) (void)hipFree(ctx->vec[i]);
+  if (ctx->d_xi) (void)hipFree(ctx->d_xi);
+  if (ctx->d_coef) (void)hipFree(ctx->d_coef);
+  if (ctx->d_fmax) (void)hipFree(ctx->d_fmax);
+  if (ctx->d_scal) (void)hipFree(ctx->d_scal);
+  if (ctx->d_partials) (void)hipFree(ctx->d_partials);
+  if (ctx->d_barrier) (void)hipFree(ctx->d_barrier);
+  if (ctx->d_status) (void)hipFree(ctx->d_status);
+  if (ctx->h_status) (void)hipHostFree(ctx->h_status);
+  if (ctx->h_scal) (void)hipHostFree(ctx->h_scal);
+  if (ctx->h_coef) (void)hipHostFree(ctx->h_coef);
+  for (int i = 0; i < 4; ++i)
+    if (ctx->ev[i]) (void)hipEventDestroy(ctx->ev[i]);
+  delete ctx;
+}
+
+LJ_API int lj_spectral_bound(lj_context* ctx, const lj_operator* J, int iters, uint64_t seed, const double* start,
+                             double* bound, void* stream) {
+  return guarded(ctx, [&]() {
+    const OpDev op = make_op(ctx, J);
+    if (!bound) invalid(ctx, "bound is NULL");
+    if (iters < 1 || iters > 100000) invalid(ctx, "iters out of range");
+    if (start) check_vec(ctx, op, start, "start");
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    run_power(ctx, op, iters, seed, start, s);
+    HIPCHK(ctx, hipMemcpyAsync(ctx->h_scal, ctx->d_scal, sizeof(Scalars), hipMemcpyDeviceToHost, s));
+    HIPCHK(ctx, hipStreamSynchronize(s));
+    *bound = ctx->h_scal->lam;
+    return LJ_OK;
+  });
+}
+
+LJ_API int lj_divided_differences(lj_context* ctx, int l, double s_, double c, double gamma, int npts, double* d,
+                                  void* stream) {
+  return guarded(ctx, [&]() {
+    if (!d) invalid(ctx, "d is NULL");
+    if (l < 0 || l > LJ_MAX_L) invalid(ctx, "l must be in [0, 4]");
+    if (npts < 1 || npts > kTable) invalid(ctx, "npts must be in [1, 101]");
+    if (!std::isfinite(s_) || !std::isfinite(c) || !std::isfinite(gamma)) invalid(ctx, "non-finite argument");
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    DDParams D;
+    std::memset(&D, 0, sizeof(D));
+    D.K = 1;
+    D.l[0] = l;
+    D.s[0] = s_;
+    D.npts = npts;
+    D.lam_host = 1.0;
+    D.safety = 1.0;
+    D.use_cg = 1;
+    D.c_in = c;
+    D.gamma_in = gamma;
+    D.xi = ctx->d_xi;
+    D.scal = nullptr;
+    D.coef = ctx->d_coef;
+    D.fmax = ctx->d_fmax;
+    HIPCHK(ctx, launch_divdiff(D, s));
+    HIPCHK(ctx, hipMemcpyAsync(ctx->h_coef, ctx->d_coef, npts * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(ctx, hipStreamSynchronize(s));
+    std::memcpy(d, ctx->h_coef, npts * sizeof(double));
+    return LJ_OK;
+  });
+}
+
+LJ_API int lj_rhs(lj_context* ctx, const lj_operator* J, const double* u, double* f, void* stream) {
+  return guarded(ctx, [&]() {
+    const OpDev op = make_op(ctx, J);
+    check_vec(ctx, op, u, "u");
+    check_vec(ctx, op, f, "f");
+    if (f == u) invalid(ctx, "f must not alias u");
+    HIPCHK(ctx, launch_rhs(op, u, f, reinterpret_cast<hipStream_t>(stream)));
+    return LJ_OK;
+  });
+}
+
+LJ_API int lj_phi_vertical(lj_context* ctx, const lj_operator* J, const double* v, int K, const int* l,
+                           const double* a, double h, double tol, double* const* w, const lj_options* opt,
+                           lj_stats* stats, void* stream) {
+  return guarded(ctx, [&]() {
+    const OpDev op = make_op(ctx, J);
+    const Opts o = resolve(ctx, opt);
+    check_action_args(ctx, op, v, K, l, a, h, tol, w);
+    if (o.pi_start) check_vec(ctx, op, o.pi_start, "pi_start");
+    lj_stats local;
+    lj_stats* st = stats ? stats : &local;
+    return vertical_impl(ctx, op, v, K, l, a, h, tol, w, o, st, reinterpret_cast<hipStream_t>(stream));
+  });
+}
+
+LJ_API int lj_phi_action(lj_context* ctx, const lj_operator* J, const double* v, double* w, int l, double h,
+                         double tol, const lj_options* opt, lj_stats* stats, void* stream) {
+  const double a = 1.0;
+  double* ws[1] = {w};
+  return lj_phi_vertical(ctx, J, v, 1, &l, &a, h, tol, ws, opt, stats, stream);
+}
+
+LJ_API int lj_step(lj_context* ctx, int scheme, const lj_operator* J, double h, double tol, double* u_out,
+                   double* err, const lj_options* opt, lj_stats* stats, int nstats, int* ncalls, void* stream) {
+  return guarded(ctx, [&]() {
+    const OpDev op = make_op(ctx, J);
+    Opts o = resolve(ctx, opt);
+    if (scheme < LJ_EXPRB2 || scheme > LJ_EPIRK4S3) invalid(ctx, "unknown scheme");
+    if (op.state == nullptr) invalid(ctx, "lj_step needs the state u in J->state");
+    if (!std::isfinite(h)) invalid(ctx, "h must be finite");
+    if (!(tol > 0.0) || !std::isfinite(tol)) invalid(ctx, "tol must be finite and > 0");
+    check_vec(ctx, op, u_out, "u_out");
+    if (u_out == op.state) invalid(ctx, "u_out must not alias the state");
+    if (err) {
+      check_vec(ctx, op, err, "err");
+      if (err == op.state || err == u_out) invalid(ctx, "err must not alias the state or u_out");
+    }
+    const int want = (scheme == LJ_EXPRB2) ? 1 : (scheme == LJ_EXPRB43) ? 4 : 3;
+    if (ncalls) *ncalls = want;
+    if (stats && nstats < want) invalid(ctx, "nstats is smaller than the number of Leja calls of the scheme");
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    const size_t n = nvals(op);
+    const double* u = op.state;
+    // one spectral bound for the whole step
+    int pit = 0;
+    if (!(o.bound > 0.0)) {
+      run_power(ctx, op, o.power_iters, o.seed, o.pi_start, s);
+      HIPCHK(ctx, hipMemcpyAsync(ctx->h_scal, ctx->d_scal, sizeof(Scalars), hipMemcpyDeviceToHost, s));
+      HIPCHK(ctx, hipStreamSynchronize(s));
+      o.bound = ctx->h_scal->lam;
+      pit = o.power_iters;
+    }
+    std::vector<lj_stats> log;
+    bool ok = true;
+    auto act = [&](const double* vec, int K, const int* ls, const double* as, double* const* outs) {
+      lj_stats st;
+      const int rc = vertical_impl(ctx, op, vec, K, ls, as, h, tol, outs, o, &st, s);
+      if (rc != LJ_OK) ok = false;
+      log.push_back(st);
+    };
+    double* fu = slot(ctx, W_FU, n);
+    double* v = slot(ctx, W_V, n);
+    HIPCHK(ctx, launch_rhs(op, u, fu, s));
+    {
+      const double al[1] = {h};
+      const double* xs[1] = {fu};
+      lincomb(ctx, n, v, 1, al, xs, s);
+    }
+    auto comb2 = [&](double* out, double a0, const double* x0, double a1, const double* x1) {
+      const double al[2] = {a0, a1};
+      const double* xs[2] = {x0, x1};
+      lincomb(ctx, n, out, 2, al, xs, s);
+    };
+    auto comb3 = [&](double* out, double a0, const double* x0, double a1, const double* x1, double a2,
+                     const double* x2) {
+      const double al[3] = {a0, a1, a2};
+      const double* xs[3] = {x0, x1, x2};
+      lincomb(ctx, n, out, 3, al, xs, s);
+    };
+    // R(x) = f(x) - f(u) - J(u)(x - u)
+    auto remainder = [&](const double* x, double* r) {
+      double* d = slot(ctx, W_D, n);
+      comb2(d, 1.0, x, -1.0, u);
+      HIPCHK(ctx, launch_remainder(op, x, d, fu, r, s));
+    };
+    if (scheme == LJ_EXPRB2) {
+      double* A = slot(ctx, W_A, n);
+      const int ls[1] = {1};
+      const double as[1] = {1.0};
+      act(v, 1, ls, as, &A);
+      comb2(u_out, 1.0, u, 1.0, A);
+      if (err) comb2(err, 0.0, u, 0.0, u);
+    } else if (scheme == LJ_EXPRB43 || scheme == LJ_EXPRB43_U3) {
+      double* A = slot(ctx, W_A, n);
+      double* B = slot(ctx, W_B, n);
+      double* C = slot(ctx, W_C, n);
+      double* xa = slot(ctx, W_XA, n);
+      double* xb = slot(ctx, W_XB, n);
+      double* Ra = slot(ctx, W_RA, n);
+      double* Rb = slot(ctx, W_RB, n);
+      double* T3 = slot(ctx, W_T3, n);
+      double* D3 = slot(ctx, W_D3, n);
+      double* u3 = (scheme == LJ_EXPRB43_U3) ? u_out : slot(ctx, W_U3, n);
+      {
+        const int ls[2] = {1, 1};
+        const double as[2] = {0.5, 1.0};
+        double* outs[2] = {A, B};
+        act(v, 2, ls, as, outs);
+      }
+      comb2(xa, 1.0, u, 0.5, A);
+      remainder(xa, Ra);
+      double* T1 = slot(ctx, W_T4, n);
+      {
+        const double al[1] = {h};
+        const double* xs[1] = {Ra};
+        lincomb(ctx, n, T1, 1, al, xs, s);
+      }
+      {
+        const int ls[1] = {1};
+        const double as[1] = {1.0};
+        act(T1, 1, ls, as, &C);
+      }
+      comb3(xb, 1.0, u, 1.0, B, 1.0, C);
+      remainder(xb, Rb);
+      comb2(T3, 16.0 * h, Ra, -2.0 * h, Rb);
+      {
+        const int ls[1] = {3};
+        const double as[1] = {1.0};
+        act(T3, 1, ls, as, &D3);
+      }
+      comb3(u3, 1.0, u, 1.0, B, 1.0, D3);
+      if (scheme == LJ_EXPRB43) {
+        double* T4 = slot(ctx, W_T4, n);
+        double* D4 = slot(ctx, W_D4, n);
+        comb2(T4, -48.0 * h, Ra, 12.0 * h, Rb);
+        const int ls[1] = {4};
+        const double as[1] = {1.0};
+        act(T4, 1, ls, as, &D4);
+        comb2(u_out, 1.0, u3, 1.0, D4);
+        if (err) comb2(err, 1.0, u_out, -1.0, u3);
+      } else if (err) {
+        comb2(err, 0.0, u, 0.0, u);
+      }
+    } else {  // EPIRK4s3
+      double* A = slot(ctx, W_A, n);
+      double* B = slot(ctx, W_B, n);
+      double* C = slot(ctx, W_C, n);
+      double* xa = slot(ctx, W_XA, n);
+      double* xb = slot(ctx, W_XB, n);
+      double* Ra = slot(ctx, W_RA, n);
+      double* Rb = slot(ctx, W_RB, n);
+      double* T3 = slot(ctx, W_T3, n);
+      double* D3 = slot(ctx, W_D3, n);
+      double* T4 = slot(ctx, W_T4, n);
+      double* D4 = slot(ctx, W_D4, n);
+      double* u3 = slot(ctx, W_U3, n);
+      {
+        const int ls[3] = {1, 1, 1};
+        const double as[3] = {1.0 / 8.0, 1.0 / 9.0, 1.0};
+        double* outs[3] = {A, B, C};
+        act(v, 3, ls, as, outs);
+      }
+      comb2(xa, 1.0, u, 1.0 / 8.0, A);
+      comb2(xb, 1.0, u, 1.0 / 9.0, B);
+      remainder(xa, Ra);
+      remainder(xb, Rb);
+      // h (1892 Ra + 1458 (Rb - 2 Ra)) and h (-42336 Ra - 34992 (Rb - 2 Ra))
+      comb2(T3, h * (1892.0 - 2.0 * 1458.0), Ra, h * 1458.0, Rb);
+      comb2(T4, h * (-42336.0 + 2.0 * 34992.0), Ra, h * -34992.0, Rb);
+      {
+        const int ls[1] = {3};
+        const double as[1] = {1.0};
+        act(T3, 1, ls, as, &D3);
+      }
+      comb3(u3, 1.0, u, 1.0, C, 1.0, D3);
+      {
+        const int ls[1] = {4};
+        const double as[1] = {1.0};
+        act(T4, 1, ls, as, &D4);
+      }
+      comb2(u_out, 1.0, u3, 1.0, D4);
+      if (err) comb2(err, 1.0, u_out, -1.0, u3);
+    }
+    HIPCHK(ctx, hipStreamSynchronize(s));
+    if (!log.empty()) log[0].power_iters = pit;
+    if (stats)
+      for (size_t i = 0; i < log.size(); ++i) stats[i] = log[i];
+    return ok ? LJ_OK : LJ_ENOTCONV;
+  });
+}
+
+LJ_API int lj_timing_enable(lj_context* ctx, int enable) {
+  if (!ctx) return LJ_EINVAL;
+  ctx->timing = enable != 0;
+  return LJ_OK;
+}
+
+LJ_API int lj_timing_read(lj_context* ctx, lj_timing* out, int reset) {
+  if (!ctx || !out) return LJ_EINVAL;
+  *out = ctx->tm;
+  if (reset) std::memset(&ctx->tm, 0, sizeof(ctx->tm));
+  return LJ_OK;
+}
+
+}  // extern "C"

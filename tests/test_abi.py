@@ -1,0 +1,109 @@
+"""Boundary checks that need no GPU: the library loads, exports every symbol
+include/leja.h declares, its structs match the ctypes mirrors, the host Leja
+table matches the oracle's, and calls without a device fail cleanly."""
+import ctypes as C
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "leja.h")
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_2211_08948_amd import _lib
+    if not os.path.exists(_lib.LIB_PATH):
+        pytest.fail("libleja.so is not built (run __graft_entry__.build())")
+    return _lib.load()
+
+
+def declared_symbols():
+    src = open(HEADER).read()
+    return sorted(set(re.findall(r"LJ_API\s+[\w\s\*]+?\b(lj_\w+)\s*\(", src)))
+
+
+def test_every_declared_symbol_is_exported(lib):
+    names = declared_symbols()
+    assert len(names) >= 14
+    for n in names:
+        assert hasattr(lib, n), n
+    from paper_2211_08948_amd._lib import _PROTOS
+    assert sorted(_PROTOS) == names  # binding covers exactly the ABI
+
+
+def test_struct_layout_matches_c(tmp_path):
+    from paper_2211_08948_amd._lib import lj_operator, lj_options, lj_stats, lj_timing
+    prog = tmp_path / "sz.c"
+    fields = {
+        "lj_operator": ["kind", "nx", "dx", "coef", "state"],
+        "lj_options": ["safety", "power_iters", "hump_max", "bound", "substeps", "power_seed", "pi_start"],
+        "lj_stats": ["m_star", "substeps", "err_est", "iters_total", "converged", "bound", "gamma"],
+        "lj_timing": ["launches", "kernel_ms", "power_ms", "power_point_iters"],
+    }
+    lines = ['#include <stdio.h>', '#include <stddef.h>', f'#include "{HEADER}"', "int main(void){"]
+    for s, fs in fields.items():
+        lines.append(f'printf("{s} %zu\\n", sizeof({s}));')
+        for f in fs:
+            lines.append(f'printf("{s}.{f} %zu\\n", offsetof({s}, {f}));')
+    lines.append("return 0;}")
+    prog.write_text("\n".join(lines))
+    exe = tmp_path / "sz"
+    subprocess.run(["gcc", "-o", str(exe), str(prog)], check=True)
+    out = dict(l.rsplit(" ", 1) for l in subprocess.run([str(exe)], capture_output=True, text=True,
+                                                          check=True).stdout.split("\n") if l)
+    py = {"lj_operator": lj_operator, "lj_options": lj_options, "lj_stats": lj_stats, "lj_timing": lj_timing}
+    for s, fs in fields.items():
+        assert int(out[s]) == C.sizeof(py[s]), s
+        for f in fs:
+            assert int(out[f"{s}.{f}"]) == getattr(py[s], f).offset, (s, f)
+
+
+def test_host_leja_table_matches_oracle(lib, xi101):
+    # independent generators (grid search + Newton in C++, gap bisection in the
+    # oracle) agree to a few ulps and in order
+    buf = (C.c_double * 101)()
+    assert lib.lj_leja_points(buf, 101) == 0
+    cpp = np.array(list(buf))
+    assert cpp[0] == 2.0 and cpp[1] == -2.0 and cpp[2] == 0.0
+    assert np.max(np.abs(cpp - xi101)) <= 4 * np.finfo(float).eps * 2.0
+    assert lib.lj_leja_points(buf, 0) == -1
+    assert lib.lj_leja_points(buf, 102) == -1
+
+
+def test_default_options(lib):
+    from paper_2211_08948_amd._lib import lj_options
+    o = lj_options()
+    lib.lj_default_options(C.byref(o))
+    assert (o.safety, o.power_iters, o.max_points, o.hump_max, o.max_substeps, o.relative_tol) == \
+        (1.25, 20, 100, 1e4, 64, 1)
+    assert o.bound == 0.0 and o.substeps == 0 and o.power_seed == 0x5EED and not o.pi_start
+
+
+def test_null_arguments_are_rejected_without_device(lib):
+    assert lib.lj_create(None, 0) == -1
+    assert lib.lj_phi_action(None, None, None, None, 1, 1.0, 1e-10, None, None, None) == -1
+    assert lib.lj_step(None, 1, None, 1.0, 1e-10, None, None, None, None, 0, None, None) == -1
+    assert lib.lj_timing_enable(None, 1) == -1
+    lib.lj_destroy(None)
+
+
+def test_create_without_gpu_reports_error(lib):
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    h = C.c_void_p()
+    rc = lib.lj_create(C.byref(h), 0)
+    assert rc in (-2, -1) and not h.value
+    assert len(lib.lj_last_error(None)) > 0
+
+
+def test_python_binding_fails_loudly_without_library(monkeypatch, tmp_path):
+    from paper_2211_08948_amd import _lib
+    monkeypatch.setattr(_lib, "_lib", None)
+    monkeypatch.setattr(_lib, "LIB_PATH", str(tmp_path / "missing.so"))
+    with pytest.raises(_lib.LejaLibraryError):
+        _lib.load()

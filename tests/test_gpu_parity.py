@@ -1,0 +1,384 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle on the
+same seeded inputs.  Floating-point results must agree to 1e-10 relative
+(2-norm) with the spectral bound forced equal; the number of Newton terms m*
+and the substep counts must be identical."""
+import numpy as np
+import pytest
+
+from gpu_util import GpuRunner, rel, say
+from oracle.divdiff import divided_differences
+from oracle.integrators import step as oracle_step
+from oracle.leja import Options, phi_action, phi_vertical
+from oracle.operators import Operator
+from oracle.phi import phi
+from oracle.points import leja_points
+from oracle.power import power_iteration
+from workloads import (advdiff_bump, allen_cahn_noise, brusselator_perturbed, burgers_sines,
+                       diag_problem)
+from workloads.problems import Problem
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-10
+
+
+@pytest.fixture(scope="module")
+def gpu():
+    r = GpuRunner()
+    yield r
+    r.ctx.close()
+
+
+def small_problems():
+    """One instance of every family at a size the oracle finishes in a blink;
+    odd/ragged grids so the last block is partial.  Diffusion coefficients are
+    scaled so that, as on the full-size grids, the spectral radius is in the
+    hundreds: the reaction eigenvalues with positive real part (up to +1 for
+    Allen-Cahn, 1/2 for the Brusselator) then stay near the right end of the
+    interval [-2, 2] after scaling (see test_spectrum_beyond_interval)."""
+    p1, _ = advdiff_bump()
+    return {
+        "diag": diag_problem(1000, -300.0, seed=3),
+        "advdiff": p1,
+        "allencahn": allen_cahn_noise(96, eps=2e-2, seed=2),
+        "allencahn_ragged": allen_cahn_noise(37, eps=1e-1, seed=7),
+        "brusselator": brusselator_perturbed(48, D=2e-2, seed=3),
+        "burgers": burgers_sines(64, nu=3e-2, seed=5),
+    }
+
+
+def _v_for(prob, h):
+    op = Operator(prob)
+    if prob.kind == "advdiff":
+        return advdiff_bump()[1]  # the workload's own vector (Gaussian bump + noise)
+    if prob.kind == "diag":
+        return np.random.default_rng(11).uniform(-1, 1, prob.n)
+    return h * op.rhs(prob.state)
+
+
+# ----------------------------------------------------------- building blocks
+def test_divided_differences_parity(gpu, xi101):
+    for l in range(5):
+        for s in (1e-3, 1.0, 50.0, 400.0):
+            say("divdiff", l, s)
+            c, gamma = -1.0, 0.5
+            d_gpu = np.array(gpu.lj.lj_divided_differences(gpu.ctx, l, s, c, gamma, 101))
+            f = [phi(l, s * (c + gamma * x)) for x in xi101]
+            d_orc = divided_differences(f, xi101)
+            assert np.max(np.abs(d_gpu - d_orc)) <= 1e-13 * max(abs(x) for x in f), (l, s)
+
+
+def test_device_leja_table_matches_host(gpu, xi101):
+    host = np.array(gpu.lj.lj_leja_points(101))
+    assert np.max(np.abs(host - xi101)) <= 1e-15
+
+
+@pytest.mark.parametrize("name", list(small_problems()))
+def test_rhs_parity(gpu, name):
+    prob = small_problems()[name]
+    say("rhs", name)
+    u = prob.state if prob.state is not None else np.random.default_rng(1).uniform(-1, 1, prob.n)
+    f_gpu = gpu.rhs(prob, u)
+    f_orc = Operator(prob).rhs(u)
+    assert rel(f_gpu, f_orc) <= 1e-14
+
+
+@pytest.mark.parametrize("name", list(small_problems()))
+def test_power_iteration_parity(gpu, name):
+    prob = small_problems()[name]
+    say("power", name)
+    lam_gpu = gpu.bound(prob, 20)
+    lam_orc = power_iteration(Operator(prob).jv, prob.n, 20)
+    assert abs(lam_gpu - lam_orc) <= 1e-12 * lam_orc
+
+
+# -------------------------------------------------------------------- actions
+@pytest.mark.parametrize("name", list(small_problems()))
+@pytest.mark.parametrize("l", [0, 1, 3])
+def test_action_parity_small(gpu, name, l):
+    prob = small_problems()[name]
+    h = 10 * prob.h_cfl if prob.kind != "diag" else 0.2
+    v = _v_for(prob, h)
+    op = Operator(prob)
+    w_orc, st_orc = phi_action(op, v, l, h, TOL)
+    say("action", name, l, "m*", st_orc.m_star, "s", st_orc.substeps)
+    rc, st, w = gpu.action(prob, v, l, h, TOL, bound=st_orc.bound)
+    assert rc == 0 and st["converged"]
+    assert st["m_star"] == st_orc.m_star and st["substeps"] == st_orc.substeps
+    assert st["iters_total"] == st_orc.iters_total
+    assert rel(w, w_orc) <= TOL
+    assert st["c"] == st_orc.c and st["gamma"] == st_orc.gamma
+
+
+def test_action_own_power_iteration(gpu):
+    # without a forced bound both sides run their own power iteration
+    prob, v = advdiff_bump()
+    h = 10 * prob.h_cfl
+    w_orc, st_orc = phi_action(Operator(prob), v, 1, h, TOL)
+    say("action own bound")
+    rc, st, w = gpu.action(prob, v, 1, h, TOL)
+    assert st["power_iters"] == 20 and abs(st["bound"] - st_orc.bound) <= 1e-12 * st_orc.bound
+    assert st["m_star"] == st_orc.m_star and rel(w, w_orc) <= TOL
+
+
+@pytest.mark.parametrize("mult", [1, 10, 100])
+@pytest.mark.parametrize("l", [1, 2, 3])
+def test_action_parity_allen_cahn_512(gpu, mult, l):
+    # the full-size 512^2 Allen-Cahn workload, stiffness 1x..100x the CFL step
+    prob = allen_cahn_noise(512, eps=1e-3, seed=2)
+    op = Operator(prob)
+    h = mult * prob.h_cfl
+    v = h * op.rhs(prob.state)
+    lam = power_iteration(op.jv, prob.n, 20)
+    w_orc, st_orc = phi_action(op, v, l, h, TOL, Options(bound=lam))
+    say("allen-cahn 512", mult, l, st_orc.m_star)
+    rc, st, w = gpu.action(prob, v, l, h, TOL, bound=lam)
+    assert rc == 0 and st["m_star"] == st_orc.m_star
+    assert rel(w, w_orc) <= TOL
+
+
+def test_vertical_parity_epirk_coefficients(gpu):
+    prob = allen_cahn_noise(512, eps=1e-3, seed=2)
+    op = Operator(prob)
+    h = 10 * prob.h_cfl
+    v = h * op.rhs(prob.state)
+    lam = power_iteration(op.jv, prob.n, 20)
+    As = [1 / 8, 1 / 9, 1.0]
+    ws_orc, st_orc = phi_vertical(op, v, [1, 1, 1], As, h, TOL, Options(bound=lam))
+    say("vertical 512", st_orc.m_star)
+    rc, st, ws = gpu.vertical(prob, v, [1, 1, 1], As, h, TOL, bound=lam)
+    assert rc == 0 and st["m_star"] == st_orc.m_star and st["iters_total"] == st_orc.iters_total
+    for k in range(3):
+        assert rel(ws[k], ws_orc[k]) <= TOL
+
+
+def test_vertical_mixed_l_parity(gpu):
+    prob = allen_cahn_noise(96, eps=2e-2, seed=2)
+    op = Operator(prob)
+    h = 30 * prob.h_cfl
+    v = h * op.rhs(prob.state)
+    ls, As = [1, 2, 3, 4], [1.0, 0.5, 1.0, 0.25]
+    ws_orc, st_orc = phi_vertical(op, v, ls, As, h, TOL)
+    say("vertical mixed l")
+    rc, st, ws = gpu.vertical(prob, v, ls, As, h, TOL, bound=st_orc.bound)
+    assert st["m_star"] == st_orc.m_star
+    for k in range(4):
+        assert rel(ws[k], ws_orc[k]) <= TOL
+
+
+def test_spectrum_beyond_interval(gpu):
+    """Allen-Cahn on a coarse 64^2 grid with eps = 1e-3: the spectral radius is
+    only ~7, so the reaction eigenvalue +1 maps to xi ~ 2.45, outside [-2, 2].
+    The Newton basis then grows ~1.9x per term and the FP64 rounding of the
+    divided differences is amplified on both sides (Sec. 2.2 warns of this
+    round-off).  Neither side reaches 1e-10 against the exact result, so the
+    check is against dense Pade: the GPU is as accurate as the oracle."""
+    from oracle.exact import phi_dense
+    prob = allen_cahn_noise(64, eps=1e-3, seed=2)
+    op = Operator(prob)
+    h = 10 * prob.h_cfl
+    v = h * op.rhs(prob.state)
+    w_orc, st_orc = phi_action(op, v, 1, h, TOL)
+    exact = phi_dense(h * op.dense(), v, 1)
+    say("spectrum beyond interval")
+    rc, st, w = gpu.action(prob, v, 1, h, TOL, bound=st_orc.bound)
+    assert st["m_star"] == st_orc.m_star
+    e_orc, e_gpu = rel(w_orc, exact), rel(w, exact)
+    assert e_orc > TOL  # the regime is real
+    assert e_gpu <= 10 * e_orc
+
+
+# ---------------------------------------------------------------- substepping
+@pytest.mark.parametrize("mult,l", [(200, 0), (200, 1), (500, 2), (1000, 2), (500, 3)])
+def test_rejection_and_substeps_parity(gpu, mult, l):
+    # real spectrum, steps far beyond 100 Leja points: s = 1 is rejected and
+    # substeps (s = 2 or 4) finish the action; every count must agree exactly
+    prob = allen_cahn_noise(96, eps=2e-2, seed=2)
+    op = Operator(prob)
+    h = mult * prob.h_cfl
+    v = h * op.rhs(prob.state)
+    lam = power_iteration(op.jv, prob.n, 20)
+    w_orc, st_orc = phi_action(op, v, l, h, TOL, Options(bound=lam))
+    say("substeps allen-cahn", mult, l, st_orc.substeps, st_orc.rejections)
+    assert st_orc.rejections >= 1
+    rc, st, w = gpu.action(prob, v, l, h, TOL, bound=lam)
+    assert rc == 0
+    assert (st["substeps"], st["rejections"], st["iters_total"], st["m_star"]) == \
+        (st_orc.substeps, st_orc.rejections, st_orc.iters_total, st_orc.m_star)
+    assert rel(w, w_orc) <= TOL
+
+
+def test_noise_floor_regime_advdiff_100cfl(gpu):
+    """Advection-diffusion at 100x the CFL step: the spectrum is complex, the
+    expansion's terms fall to a rounding floor near 1e-12 and rise again, and
+    s = 1, 2 are rejected.  Inside each of the s = 4 substep expansions the
+    step at which the terms first dip under tol is decided in that rounding
+    noise, so the point counts of two correct FP64 implementations may differ
+    by a few.  Unique here are the substep count and the action itself: each
+    of the s expansions is truncated within tol of its exact value, so two
+    valid results differ by at most ~2 s tol, and both stay within that of
+    the Fourier closed form."""
+    from oracle.exact import advdiff_symbol, fourier_closed_form
+    prob, v = advdiff_bump()
+    op = Operator(prob)
+    h = 100 * prob.h_cfl
+    sig = advdiff_symbol(prob.nx, prob.ny, prob.dx, prob.dy, *prob.coef)
+    for l in (0, 1, 2):
+        w_orc, st_orc = phi_action(op, v, l, h, TOL)
+        exact = fourier_closed_form(sig, v, l, h)
+        say("noise floor advdiff 100x", l, st_orc.substeps, st_orc.rejections, st_orc.iters_total)
+        rc, st, w = gpu.action(prob, v, l, h, TOL, bound=st_orc.bound)
+        s_ = st_orc.substeps[0]
+        assert rc == 0 and st["substeps"] == st_orc.substeps and st["rejections"] == st_orc.rejections
+        assert abs(st["iters_total"] - st_orc.iters_total) <= 0.05 * st_orc.iters_total
+        assert rel(w, w_orc) <= 2 * s_ * TOL
+        assert rel(w, exact) <= 10 * s_ * TOL and rel(w_orc, exact) <= 10 * s_ * TOL
+
+
+@pytest.mark.parametrize("l", [0, 1, 3])
+def test_forced_substeps_parity(gpu, l):
+    prob = allen_cahn_noise(64, eps=5e-2, seed=2)
+    op = Operator(prob)
+    h = 10 * prob.h_cfl
+    v = h * op.rhs(prob.state)
+    for s in (3, 4):
+        w_orc, st_orc = phi_action(op, v, l, h, TOL, Options(substeps=s))
+        say("forced substeps", l, s)
+        rc, st, w = gpu.action(prob, v, l, h, TOL, bound=st_orc.bound, substeps=s)
+        assert st["substeps"] == st_orc.substeps and st["iters_total"] == st_orc.iters_total
+        assert rel(w, w_orc) <= TOL
+
+
+def test_small_max_points_forces_substeps(gpu):
+    prob = allen_cahn_noise(96, eps=2e-2, seed=2)
+    op = Operator(prob)
+    v = 10 * prob.h_cfl * op.rhs(prob.state)
+    h = 10 * prob.h_cfl
+    w_orc, st_orc = phi_action(op, v, 1, h, TOL, Options(max_points=12))
+    say("max_points 12", st_orc.substeps)
+    rc, st, w = gpu.action(prob, v, 1, h, TOL, bound=st_orc.bound, max_points=12)
+    assert st["substeps"] == st_orc.substeps and st["rejections"] == st_orc.rejections
+    assert rel(w, w_orc) <= TOL
+
+
+def test_absolute_tolerance_parity(gpu):
+    prob = allen_cahn_noise(96, eps=2e-2, seed=2)
+    op = Operator(prob)
+    h = 10 * prob.h_cfl
+    v = h * op.rhs(prob.state)
+    w_orc, st_orc = phi_action(op, v, 1, h, 1e-12, Options(relative_tol=False))
+    say("absolute tol")
+    rc, st, w = gpu.action(prob, v, 1, h, 1e-12, bound=st_orc.bound, relative_tol=0)
+    assert st["m_star"] == st_orc.m_star and rel(w, w_orc) <= TOL
+
+
+# ----------------------------------------------------------------- edge cases
+def test_zero_vector(gpu):
+    prob = allen_cahn_noise(40, seed=2)
+    say("zero vector")
+    rc, st, w = gpu.action(prob, np.zeros(prob.n), 1, 10 * prob.h_cfl, TOL)
+    assert rc == 0 and st["m_star"] == [0] and np.all(w == 0.0)
+
+
+def test_nonfinite_input_reports_not_converged(gpu):
+    prob = allen_cahn_noise(40, seed=2)
+    v = np.ones(prob.n)
+    v[5] = np.nan
+    say("nan input")
+    rc, st, w = gpu.action(prob, v, 1, 10 * prob.h_cfl, TOL, max_substeps=2)
+    assert rc == gpu.lj.LJ_ENOTCONV and not st["converged"]
+
+
+def test_degenerate_grids(gpu):
+    # one-row and one-point periodic grids: neighbours wrap onto the point itself
+    for nx, ny in ((5, 1), (1, 7), (1, 1)):
+        prob = Problem("allencahn", nx, ny, 1, 0.1, 0.1, (1.0,), np.linspace(-0.5, 0.5, nx * ny), 1.0)
+        v = np.linspace(1.0, 2.0, nx * ny)
+        w_orc, st_orc = phi_action(Operator(prob), v, 1, 0.5, TOL)
+        say("degenerate", nx, ny)
+        rc, st, w = gpu.action(prob, v, 1, 0.5, TOL, bound=st_orc.bound)
+        assert st["m_star"] == st_orc.m_star and rel(w, w_orc) <= TOL
+
+
+def test_invalid_arguments_raise(gpu):
+    import torch
+    prob = allen_cahn_noise(40, seed=2)
+    op = gpu.op(prob)
+    v = gpu.dev(np.ones(prob.n))
+    with pytest.raises(gpu.lj.LejaError):
+        gpu.lj.lj_phi_action(gpu.ctx, op, v, v, 1, 0.1, TOL)  # aliasing
+    with pytest.raises(gpu.lj.LejaError):
+        gpu.lj.lj_phi_action(gpu.ctx, op, v, torch.empty_like(v), 7, 0.1, TOL)  # l out of range
+    with pytest.raises(gpu.lj.LejaError):
+        gpu.lj.lj_phi_action(gpu.ctx, op, v, torch.empty_like(v), 1, 0.1, -1.0)  # tol
+    # Pointers that must be refused by the library's device-range check.  Each
+    # call also passes w == v, so even if that check let the pointer through,
+    # the aliasing check would refuse the call before anything is launched; the
+    # error text shows which check fired.
+    import ctypes as C
+    torch.cuda.empty_cache()
+    big_prob = Problem("allencahn", 2048, 2048, 1, 1e-3, 1e-3, (1e-3,), None, 1.0)
+    big_state = torch.zeros(2048 * 2048, dtype=torch.float64, device="cuda:0")
+    short = torch.empty(2048 * 512, dtype=torch.float64, device="cuda:0")
+    op_big = gpu.lj.Operator("allencahn", 2048, 2048, 1, 1e-3, 1e-3, (1e-3,), big_state).c_struct()
+    host = np.ones(2048 * 2048)
+    for ptr, expect in ((host.ctypes.data, "not a device allocation"), (short.data_ptr(), "shorter")):
+        rc = gpu.ctx._lib.lj_phi_action(gpu.ctx.handle, C.byref(op_big), C.c_void_p(ptr), C.c_void_p(ptr),
+                                        1, 0.1, TOL, None, None, None)
+        assert rc == gpu.lj.LJ_EINVAL
+        assert expect in gpu.ctx.last_error(), gpu.ctx.last_error()
+    del big_prob
+
+
+# --------------------------------------------------------------- stage driver
+@pytest.mark.parametrize("scheme", ["EXPRB2", "EXPRB43_U3", "EXPRB43", "EPIRK4S3"])
+def test_step_parity_allen_cahn(gpu, scheme):
+    prob = allen_cahn_noise(96, eps=2e-2, seed=2)
+    op = Operator(prob)
+    h = 10 * prob.h_cfl
+    lam = power_iteration(op.jv, prob.n, 20)
+    u_orc, e_orc, log = oracle_step(op, scheme, h, TOL, Options(bound=lam))
+    say("step", scheme)
+    rc, sts, u, e = gpu.step(prob, scheme, h, TOL, bound=lam)
+    assert rc == 0 and len(sts) == len(log)
+    for a, b in zip(sts, log):
+        assert a["m_star"][:len(b.m_star)] == b.m_star
+    assert rel(u, u_orc) <= TOL
+    if e_orc is not None:
+        assert np.linalg.norm(e - e_orc) <= 1e-8 * np.linalg.norm(e_orc) + 1e-12 * np.linalg.norm(u_orc)
+
+
+def test_step_parity_brusselator(gpu):
+    prob = brusselator_perturbed(64, D=2e-2, seed=3)
+    op = Operator(prob)
+    h = 10 * prob.h_cfl
+    u_orc, _, log = oracle_step(op, "EXPRB43_U3", h, TOL)
+    say("step brusselator")
+    rc, sts, u, _ = gpu.step(prob, "EXPRB43_U3", h, TOL)
+    assert rc == 0 and [s["m_star"][:len(b.m_star)] for s, b in zip(sts, log)] == [b.m_star for b in log]
+    assert rel(u, u_orc) <= TOL
+
+
+def test_step_parity_brusselator_full_size(gpu):
+    # the 1024^2 two-species workload, one EXPRB3 step
+    prob = brusselator_perturbed(1024, D=2e-3, seed=3)
+    op = Operator(prob)
+    h = 10 * prob.h_cfl
+    lam = power_iteration(op.jv, prob.n, 20)
+    u_orc, _, log = oracle_step(op, "EXPRB43_U3", h, TOL, Options(bound=lam))
+    say("step brusselator 1024", [b.m_star for b in log])
+    rc, sts, u, _ = gpu.step(prob, "EXPRB43_U3", h, TOL, bound=lam)
+    assert rc == 0 and [s["m_star"][:len(b.m_star)] for s, b in zip(sts, log)] == [b.m_star for b in log]
+    assert rel(u, u_orc) <= TOL
+
+
+def test_action_parity_burgers_full_size(gpu):
+    prob = burgers_sines(2048, nu=1e-3, seed=5)
+    op = Operator(prob)
+    h = 10 * prob.h_cfl
+    v = h * op.rhs(prob.state)
+    lam = power_iteration(op.jv, prob.n, 20)
+    w_orc, st_orc = phi_action(op, v, 1, h, TOL, Options(bound=lam))
+    say("burgers 2048", st_orc.m_star, st_orc.substeps)
+    rc, st, w = gpu.action(prob, v, 1, h, TOL, bound=lam)
+    assert st["m_star"] == st_orc.m_star and st["substeps"] == st_orc.substeps
+    assert rel(w, w_orc) <= TOL
