@@ -186,19 +186,32 @@ LJ_API int lj_step(lj_context* ctx, int scheme, const lj_operator* J, double h, 
 
 /* ---- measurement ------------------------------------------------------------ */
 
-/* Kernel timing of the fused Leja iteration kernel.  While enabled, the
- * library brackets every launch of that kernel with HIP events on the launch
- * stream and accumulates its durations and the Newton iterations it ran. */
+/* Kernel timing of the phi-action kernel.  While enabled, the library
+ * brackets every launch of that kernel (power iteration + divided differences
+ * + Newton recurrence in one persistent launch) with HIP events on the launch
+ * stream and accumulates its durations and the work it did. */
 typedef struct {
-  int64_t launches;        /* fused-iteration kernel launches */
-  int64_t iterations;      /* Newton iterations run by those launches */
-  int64_t point_iters;     /* grid points x iterations (algorithmic units) */
-  int64_t accum_point_iters; /* sum over iterations of active accumulators x points */
-  double kernel_ms;        /* summed event-measured duration */
-  int64_t power_launches;  /* power-iteration kernel launches */
-  double power_ms;         /* their summed duration */
-  int64_t power_point_iters;
+  int64_t launches;          /* action-kernel launches */
+  int64_t iterations;        /* Newton iterations run by those launches */
+  int64_t point_iters;       /* grid points x Newton iterations */
+  int64_t accum_point_iters; /* grid points x sum over iterations of active accumulators */
+  int64_t power_point_iters; /* grid points x power-iteration products */
+  int64_t tiled_launches;    /* launches that used the LDS-tiled kernel */
+  double kernel_ms;          /* summed event-measured duration */
 } lj_timing;
+
+/* Diagnostics: the reduced norms the last Newton recurrence on ctx decided
+ * on.  Row m-1 (m = 1..iterations) holds ||y_m||_2^2 followed by ||p_k||_2^2
+ * (k < LJ_MAX_K) after term m, as summed on the device.  out is a host array
+ * of rows x (1 + LJ_MAX_K) doubles; returns the number of rows written. */
+LJ_API int lj_last_trace(lj_context* ctx, double* out, int rows);
+
+/* Diagnostics: where block 0 of the last action launch spent its time, in
+ * microseconds of the device wall clock: us[0] set-up, [1] power iteration,
+ * [2] divided differences, [3] Newton steps, [4] publishing partial sums,
+ * [5] waiting in grid barriers, [6] reductions and stop decisions, [7] halo
+ * reloads (LDS-tiled kernel).  us is a host array of 8 doubles. */
+LJ_API int lj_last_profile(lj_context* ctx, double* us);
 
 LJ_API int lj_timing_enable(lj_context* ctx, int enable);
 LJ_API int lj_timing_read(lj_context* ctx, lj_timing* out, int reset);

@@ -211,6 +211,26 @@ def lj_step(ctx: Context, scheme: str, J: Operator, h: float, tol: float, u_out,
     return rc, [stats[i].as_dict() for i in range(ncalls.value)]
 
 
+def lj_last_trace(ctx: Context, rows: int = 100):
+    """Per-iteration device totals of the last Newton recurrence: a list of
+    rows [||y_m||^2, ||p_0||^2, ..., ||p_3||^2] for m = 1..iterations."""
+    buf = (C.c_double * (rows * (1 + LJ_MAX_K)))()
+    n = ctx._lib.lj_last_trace(ctx.handle, buf, int(rows))
+    if n < 0:
+        raise LejaError(n, "lj_last_trace")
+    return [list(buf[i * (1 + LJ_MAX_K):(i + 1) * (1 + LJ_MAX_K)]) for i in range(n)]
+
+
+PROFILE_PHASES = ("setup", "power", "divdiff", "steps", "publish", "barrier", "decide", "halo")
+
+
+def lj_last_profile(ctx: Context) -> dict:
+    """Microseconds block 0 of the last action launch spent per phase."""
+    buf = (C.c_double * 8)()
+    ctx._check(ctx._lib.lj_last_profile(ctx.handle, buf), False)
+    return dict(zip(PROFILE_PHASES, list(buf)))
+
+
 def lj_timing_enable(ctx: Context, enable: bool = True) -> None:
     ctx._check(ctx._lib.lj_timing_enable(ctx.handle, 1 if enable else 0), False)
 

@@ -60,8 +60,8 @@ class lj_stats(C.Structure):
 class lj_timing(C.Structure):
     _fields_ = [
         ("launches", C.c_int64), ("iterations", C.c_int64), ("point_iters", C.c_int64),
-        ("accum_point_iters", C.c_int64), ("kernel_ms", C.c_double), ("power_launches", C.c_int64),
-        ("power_ms", C.c_double), ("power_point_iters", C.c_int64),
+        ("accum_point_iters", C.c_int64), ("power_point_iters", C.c_int64), ("tiled_launches", C.c_int64),
+        ("kernel_ms", C.c_double),
     ]
 
 
@@ -85,6 +85,8 @@ _PROTOS = {
                                   C.POINTER(lj_options), C.POINTER(lj_stats), _P]),
     "lj_step": (C.c_int, [_P, C.c_int, C.POINTER(lj_operator), C.c_double, C.c_double, _P, _P,
                           C.POINTER(lj_options), C.POINTER(lj_stats), C.c_int, C.POINTER(C.c_int), _P]),
+    "lj_last_trace": (C.c_int, [_P, C.POINTER(C.c_double), C.c_int]),
+    "lj_last_profile": (C.c_int, [_P, C.POINTER(C.c_double)]),
     "lj_timing_enable": (C.c_int, [_P, C.c_int]),
     "lj_timing_read": (C.c_int, [_P, C.POINTER(lj_timing), C.c_int]),
 }

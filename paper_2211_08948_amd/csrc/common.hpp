@@ -7,11 +7,13 @@ namespace lj {
 
 enum OpKind { OP_DIAG = 0, OP_ADVDIFF = 1, OP_ALLENCAHN = 2, OP_BRUSSELATOR = 3, OP_BURGERS = 4 };
 
-constexpr int kMaxK = 4;          // accumulators sharing one Newton basis
-constexpr int kMaxL = 4;          // highest phi index
-constexpr int kMaxPoints = 100;   // most Newton terms
+constexpr int kMaxK = 4;                // accumulators sharing one Newton basis
+constexpr int kMaxL = 4;                // highest phi index
+constexpr int kMaxPoints = 100;         // most Newton terms
 constexpr int kTable = kMaxPoints + 1;  // Leja nodes kept on the device
-constexpr int kBarrierWords = 32 * 17;  // words of one grid-barrier state (zero at launch)
+constexpr int kBarrierWords = 32 * 18;  // words of one grid-barrier state (zero at launch)
+constexpr int kPartStride = 48;         // partial sums per block and barrier slot
+constexpr int kMaxSuper = 8;            // Newton steps per barrier in the tiled kernel (max)
 
 // Operator as the kernels see it: coefficients plus precomputed reciprocals.
 struct OpDev {
@@ -32,62 +34,61 @@ struct LejaStatus {
   double err[kMaxK];
   int iters;            // Newton iterations run (Jacobian products)
   int accum_iters;      // sum over iterations of active accumulators
+  int power_iters;      // Jacobian products of the power iteration (0 if skipped)
+  int barriers;         // grid barriers used
   double vnorm;         // ||v||_2
+  double lam, c, gamma; // bound used and the interval it gives
+  // reduced totals of every decided Newton step m = 1..iters:
+  // trace[m-1][0] = ||y_m||^2, trace[m-1][1+k] = ||p_k||^2 after term m
+  double trace[kMaxPoints][1 + kMaxK];
+  // wall-clock ticks spent by block 0 per phase (see kProf*), for tuning
+  unsigned long long prof[8];
 };
 
-// Device scalars shared between kernels of one call.
-struct Scalars {
-  double lam;    // lambda_hat
-  double c;      // interval centre
-  double gamma;  // interval quarter-length
-  double pad;
-};
+enum ProfPhase { kProfSetup = 0, kProfPower, kProfDivdiff, kProfSteps, kProfPublish, kProfBarrier, kProfDecide, kProfHalo };
 
+// Divided differences on their own (the lj_divided_differences entry point).
 struct DDParams {
   int K;
   int l[kMaxK];
   double s[kMaxK];        // a_k * tau
   int npts;               // coefficients per accumulator (<= kTable)
-  double lam_host;        // > 0: use this lambda_hat instead of Scalars::lam
-  double safety;
-  int use_cg;             // 1: take c_in, gamma_in as given (scal unused)
-  double c_in, gamma_in;
+  double c, gamma;        // interval centre and quarter-length
   const double* xi;       // Leja table (device, kTable entries)
-  Scalars* scal;          // in: lam (unless lam_host > 0); out: lam, c, gamma
   double* coef;           // out: K x kTable divided differences
   double* fmax;           // out: K values max_j |f_j|
 };
 
-struct LejaParams {
+// One phi-action launch: optional power iteration, divided differences and the
+// whole Newton recurrence.
+struct ActionParams {
   OpDev op;
+  // spectral bound
+  int do_power;           // 1: run the power iteration; 0: use lam_in
+  int power_iters;
+  uint64_t seed;
+  const double* start;    // explicit power-iteration start vector or nullptr
+  double lam_in;
+  double safety;
+  // expansion
   const double* v;        // y_0 (device)
-  double* ybuf0;          // Newton basis double buffer (device, n each)
-  double* ybuf1;
-  double* p[kMaxK];       // accumulators = outputs (device, n each)
   int K;
+  int l[kMaxK];
+  double s[kMaxK];        // a_k * tau
+  double* p[kMaxK];       // accumulators = outputs (device)
   int max_points;
   int relative;
   double tol;
   double hump;
-  const double* coef;     // K x kTable (device)
-  const double* fmax;     // K (device)
   const double* xi;       // Leja table (device)
-  const Scalars* scal;    // c, gamma (device)
-  double* partials;       // 2 x gridDim x (K+1) (device)
-  unsigned int* barrier;  // zero at launch
+  // workspace
+  double* ybuf0;          // two device vectors of n entries
+  double* ybuf1;
+  double* partials;       // 2 x kPartStride x gridDim, slot-major: [parity][slot][block]
+  unsigned int* barrier;  // kBarrierWords words, zero at launch; left zero at exit
   LejaStatus* status;     // out
-};
-
-struct PowerParams {
-  OpDev op;
-  int iters;
-  uint64_t seed;
-  const double* start;    // explicit x_0 or nullptr (SplitMix64 start vector)
-  double* buf0;           // two work vectors (device, n each)
-  double* buf1;
-  double* partials;       // 2 x gridDim x 2
-  unsigned int* barrier;  // zero at launch
-  Scalars* scal;          // out: lam
+  // tiling of the LDS-resident kernel
+  int tx, ty, ntx, nty;   // tile size and tiles per axis (gridDim = ntx * nty)
 };
 
 }  // namespace lj

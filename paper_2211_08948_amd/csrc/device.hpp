@@ -14,9 +14,52 @@ namespace lj {
 // ---------------------------------------------------------------------------
 // Stencils.  Sec. 3: centred second-order differences; the grids are periodic.
 // Point p = j*nx + i; components of a two-component state are interleaved.
-// jv_point returns (J x)(p) for every component in out[] and the centre values
-// x(p) in xc[] (the Newton recurrence needs both).
+//
+// stencil_jv evaluates (J x) at one point from values: x at the centre and the
+// four neighbours (index 0 centre, 1 west, 2 east, 3 south, 4 north; NC
+// components each) and the linearisation state at the same five places.  The
+// global-memory kernels and the LDS-tiled kernel both call it, so both perform
+// exactly the same arithmetic per point.
 // ---------------------------------------------------------------------------
+__device__ __forceinline__ double lap5(const OpDev& op, double xc, double xw, double xe, double xs,
+                                       double xn) {
+  return (xw - 2.0 * xc + xe) * op.idx2 + (xs - 2.0 * xc + xn) * op.idy2;
+}
+
+template <int KIND>
+__device__ __forceinline__ void stencil_jv(const OpDev& op, const double (&x)[5][2], const double (&u)[5][2],
+                                           double out[2]) {
+  if constexpr (KIND == OP_DIAG) {
+    out[0] = u[0][0] * x[0][0];
+  } else if constexpr (KIND == OP_ADVDIFF) {
+    out[0] = op.c0 * lap5(op, x[0][0], x[1][0], x[2][0], x[3][0], x[4][0]) -
+             op.c1 * ((x[2][0] - x[1][0]) * op.i2dx) - op.c2 * ((x[4][0] - x[3][0]) * op.i2dy);
+  } else if constexpr (KIND == OP_ALLENCAHN) {
+    const double uc = u[0][0];
+    out[0] = op.c0 * lap5(op, x[0][0], x[1][0], x[2][0], x[3][0], x[4][0]) + (1.0 - 3.0 * uc * uc) * x[0][0];
+  } else if constexpr (KIND == OP_BRUSSELATOR) {
+    const double U = u[0][0], V = u[0][1];
+    const double Du = op.c0, Dv = op.c1, b = op.c3;
+    // d/du (a - (b+1)u + u^2 v) = -(b+1) + 2uv,  d/dv = u^2
+    out[0] = Du * lap5(op, x[0][0], x[1][0], x[2][0], x[3][0], x[4][0]) + (-(b + 1.0) + 2.0 * U * V) * x[0][0] +
+             U * U * x[0][1];
+    // d/du (b u - u^2 v) = b - 2uv,  d/dv = -u^2
+    out[1] = Dv * lap5(op, x[0][1], x[1][1], x[2][1], x[3][1], x[4][1]) + (b - 2.0 * U * V) * x[0][0] -
+             U * U * x[0][1];
+  } else {  // OP_BURGERS: nu Lap x - (d/dx + d/dy)(u x)
+    const double qe = u[2][0] * x[2][0], qw = u[1][0] * x[1][0];
+    const double qn = u[4][0] * x[4][0], qs = u[3][0] * x[3][0];
+    out[0] = op.c0 * lap5(op, x[0][0], x[1][0], x[2][0], x[3][0], x[4][0]) -
+             ((qe - qw) * op.i2dx + (qn - qs) * op.i2dy);
+  }
+}
+
+// which state values a family's Jacobian reads: none, the centre, or all five
+template <int KIND>
+struct StateUse {
+  static constexpr int value = (KIND == OP_ADVDIFF) ? 0 : (KIND == OP_BURGERS ? 5 : 1);
+};
+
 struct Nbr {
   int c, w, e, s, n;  // flat point indices of centre and the four neighbours
 };
@@ -34,49 +77,32 @@ __device__ __forceinline__ Nbr neighbours(const OpDev& op, int p) {
   return r;
 }
 
-// (Lap x)(p) from centre/neighbour values
-__device__ __forceinline__ double lap5(const OpDev& op, double xc, double xw, double xe, double xs,
-                                       double xn) {
-  return (xw - 2.0 * xc + xe) * op.idx2 + (xs - 2.0 * xc + xn) * op.idy2;
-}
-
-template <int KIND>
-__device__ __forceinline__ void jv_point(const OpDev& op, const double* __restrict__ x, int p,
-                                         double out[2], double xc[2]) {
+// (J x)(p) from global memory; xc[] receives x(p) (the recurrence needs it)
+template <int KIND, int NC>
+__device__ __forceinline__ void jv_point(const OpDev& op, const double* __restrict__ x, int p, double out[2],
+                                         double xc[2]) {
+  double xv[5][2] = {}, uv[5][2] = {};
   if constexpr (KIND == OP_DIAG) {
-    xc[0] = x[p];
-    out[0] = op.state[p] * xc[0];
-  } else if constexpr (KIND == OP_BRUSSELATOR) {
-    const Nbr q = neighbours(op, p);
-    const double2 C = *reinterpret_cast<const double2*>(x + 2 * q.c);
-    const double2 W = *reinterpret_cast<const double2*>(x + 2 * q.w);
-    const double2 E = *reinterpret_cast<const double2*>(x + 2 * q.e);
-    const double2 S = *reinterpret_cast<const double2*>(x + 2 * q.s);
-    const double2 N = *reinterpret_cast<const double2*>(x + 2 * q.n);
-    const double2 st = *reinterpret_cast<const double2*>(op.state + 2 * q.c);
-    const double U = st.x, V = st.y;
-    const double Du = op.c0, Dv = op.c1, b = op.c3;
-    xc[0] = C.x;
-    xc[1] = C.y;
-    // d/du (a - (b+1)u + u^2 v) = -(b+1) + 2uv,  d/dv = u^2
-    out[0] = Du * lap5(op, C.x, W.x, E.x, S.x, N.x) + (-(b + 1.0) + 2.0 * U * V) * C.x + U * U * C.y;
-    // d/du (b u - u^2 v) = b - 2uv,  d/dv = -u^2
-    out[1] = Dv * lap5(op, C.y, W.y, E.y, S.y, N.y) + (b - 2.0 * U * V) * C.x - U * U * C.y;
+    xv[0][0] = x[p];
+    uv[0][0] = op.state[p];
   } else {
     const Nbr q = neighbours(op, p);
-    const double c = x[q.c], w = x[q.w], e = x[q.e], s = x[q.s], n = x[q.n];
-    xc[0] = c;
-    if constexpr (KIND == OP_ADVDIFF) {
-      out[0] = op.c0 * lap5(op, c, w, e, s, n) - op.c1 * ((e - w) * op.i2dx) - op.c2 * ((n - s) * op.i2dy);
-    } else if constexpr (KIND == OP_ALLENCAHN) {
-      const double u = op.state[q.c];
-      out[0] = op.c0 * lap5(op, c, w, e, s, n) + (1.0 - 3.0 * u * u) * c;
-    } else {  // OP_BURGERS: nu Lap x - (d/dx + d/dy)(u x)
-      const double* __restrict__ u = op.state;
-      const double qe = u[q.e] * e, qw = u[q.w] * w, qn = u[q.n] * n, qs = u[q.s] * s;
-      out[0] = op.c0 * lap5(op, c, w, e, s, n) - ((qe - qw) * op.i2dx + (qn - qs) * op.i2dy);
+    const int idx[5] = {q.c, q.w, q.e, q.s, q.n};
+#pragma unroll
+    for (int t = 0; t < 5; ++t) {
+#pragma unroll
+      for (int c = 0; c < NC; ++c) xv[t][c] = x[NC * idx[t] + c];
+    }
+    constexpr int su = StateUse<KIND>::value;
+#pragma unroll
+    for (int t = 0; t < su; ++t) {
+#pragma unroll
+      for (int c = 0; c < NC; ++c) uv[t][c] = op.state[NC * idx[t] + c];
     }
   }
+  stencil_jv<KIND>(op, xv, uv, out);
+#pragma unroll
+  for (int c = 0; c < NC; ++c) xc[c] = xv[0][c];
 }
 
 // Right-hand side f(x)(p) of each family.
@@ -110,22 +136,42 @@ __device__ __forceinline__ void rhs_point(const OpDev& op, const double* __restr
 }
 
 // ---------------------------------------------------------------------------
-// phi_l(z) in FP64 (Sec. 1 definition).  |z| <= 2: Taylor series
-// sum_{k<=40} z^k/(k+l)! by Horner (2^41/41! < 1e-37, far below one ulp);
+// phi_l(z) in FP64 (Sec. 1 definition).  |z| <= 2: the Taylor series
+// sum_{k<=40} z^k/(k+l)! by Horner (2^41/41! < 1e-37, far below one ulp), with
+// the coefficients 1/(l+k)! formed at compile time by successive division;
 // |z| > 2: the defining recurrence from exp(z), phi_{k+1} = (phi_k - 1/k!)/z,
 // which only mildly amplifies rounding once |z| > 2.
 // ---------------------------------------------------------------------------
+template <int L>
+struct InvFactorials {
+  double v[41];  // v[k] = 1/(L+k)!
+  constexpr InvFactorials() : v() {
+    double f = 1.0;
+    for (int k = 2; k <= L; ++k) f /= (double)k;
+    v[0] = f;
+    for (int k = 1; k <= 40; ++k) v[k] = v[k - 1] / (double)(L + k);
+  }
+};
+
+template <int L>
+__device__ __forceinline__ double phi_series(double z) {
+  constexpr InvFactorials<L> c{};
+  double s = c.v[40];
+#pragma unroll
+  for (int k = 39; k >= 0; --k) s = s * z + c.v[k];
+  return s;
+}
+
+// l in [0, kMaxL]; the callers validate it
 __device__ inline double phi_dev(int l, double z) {
   if (fabs(z) <= 2.0) {
-    // 1/(l+k)! for k = 0..40 via successive division from 1/l!
-    double inv[41];
-    double f = 1.0;
-    for (int k = 2; k <= l; ++k) f /= (double)k;
-    inv[0] = f;
-    for (int k = 1; k <= 40; ++k) inv[k] = inv[k - 1] / (double)(l + k);
-    double s = inv[40];
-    for (int k = 39; k >= 0; --k) s = s * z + inv[k];
-    return s;
+    switch (l) {
+      case 0: return phi_series<0>(z);
+      case 1: return phi_series<1>(z);
+      case 2: return phi_series<2>(z);
+      case 3: return phi_series<3>(z);
+      default: return phi_series<4>(z);
+    }
   }
   double p = exp(z);
   double invfact = 1.0;  // 1/k!
@@ -137,13 +183,49 @@ __device__ inline double phi_dev(int l, double z) {
 }
 
 // ---------------------------------------------------------------------------
-// Reductions.  Fixed association order for a given launch shape, so every
-// block that reduces the same data gets bit-identical totals.
+// Cross-lane moves and reductions on DPP (data-parallel primitives: lane
+// permutations applied on the ALU's operand path, a few cycles each, instead
+// of the LDS crossbar behind ds_bpermute).  All lanes of the wave must be
+// active.  Fixed association order for a given launch shape, so every block
+// that reduces the same data gets bit-identical totals.
 // ---------------------------------------------------------------------------
+template <int CTRL, int ROW_MASK = 0xf>
+__device__ __forceinline__ double dpp_move(double v) {
+  const int2 x = __builtin_bit_cast(int2, v);
+  int2 r;
+  r.x = __builtin_amdgcn_update_dpp(0, x.x, CTRL, ROW_MASK, 0xf, true);
+  r.y = __builtin_amdgcn_update_dpp(0, x.y, CTRL, ROW_MASK, 0xf, true);
+  return __builtin_bit_cast(double, r);  // lanes outside ROW_MASK or without a source: 0
+}
+
+__device__ __forceinline__ double read_lane(double v, int lane) {
+  const int2 x = __builtin_bit_cast(int2, v);
+  int2 r;
+  r.x = __builtin_amdgcn_readlane(x.x, lane);
+  r.y = __builtin_amdgcn_readlane(x.y, lane);
+  return __builtin_bit_cast(double, r);
+}
+
+// the value held by lane (i - 1), for lane i > 0; lane 0 receives 0
+__device__ __forceinline__ double wave_shift_up(double v) { return dpp_move<0x138>(v); }  // wave_shr:1
+
+// Sum over the 64 lanes, returned in every lane: inclusive scans within each
+// row of 16 lanes (row_shr 1, 2, 4, 8), then row 0 added into row 1 and row 2
+// into row 3 (row_bcast:15), then rows 0-1 into rows 2-3 (row_bcast:31); lane
+// 63 then holds the total.
 __device__ __forceinline__ double wave_sum(double v) {
-  // butterfly over the 64 lanes; lane 0's value is the canonical result
+  v += dpp_move<0x111>(v);
+  v += dpp_move<0x112>(v);
+  v += dpp_move<0x114>(v);
+  v += dpp_move<0x118>(v);
+  v += dpp_move<0x142, 0xa>(v);
+  v += dpp_move<0x143, 0xc>(v);
+  return read_lane(v, 63);
+}
+
+__device__ __forceinline__ double wave_max(double v) {
 #pragma unroll
-  for (int off = 32; off >= 1; off >>= 1) v += __shfl_down(v, off, 64);
+  for (int off = 32; off >= 1; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
   return v;
 }
 
@@ -187,14 +269,16 @@ __device__ __forceinline__ void block_sum(double (&v)[NV], double* red) {
 //   base[0]            global counter
 //   base[32*(1+g)]     group g arrival counter
 //   base[32*(9+g)]     group g release flag (holds the last completed epoch)
-// and everything must be zero at launch (kBarrierWords words).
+//   base[32*17]        exit counter (grid_exit)
+// Everything must be zero at launch; grid_exit leaves it zero again.
 // ---------------------------------------------------------------------------
-
+// `epoch` counts the barriers this block has passed; every thread of the block
+// advances its copy (callers use it to pick double-buffered slots).
 __device__ __forceinline__ void grid_barrier(unsigned int* base, unsigned int& epoch) {
   __builtin_amdgcn_s_waitcnt(0);  // this thread's loads and stores have completed
   __syncthreads();
+  epoch += 1u;
   if (threadIdx.x == 0) {
-    epoch += 1u;
     const unsigned int G = gridDim.x;
     const unsigned int ng = G < 8u ? G : 8u;
     const unsigned int g = blockIdx.x % ng;
@@ -204,6 +288,9 @@ __device__ __forceinline__ void grid_barrier(unsigned int* base, unsigned int& e
     const unsigned int old = __hip_atomic_fetch_add(gc, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     if (old == epoch * gsize - 1u) {
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+      // the release is an L2 write-back; arrive only once it has completed
+      // (the compiler does not wait for it before the next atomic by itself)
+      __asm__ volatile("s_waitcnt vmcnt(0)" ::: "memory");
       __hip_atomic_fetch_add(base, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       while (__hip_atomic_load(base, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < epoch * ng) {
         __builtin_amdgcn_s_sleep(1);
@@ -218,6 +305,26 @@ __device__ __forceinline__ void grid_barrier(unsigned int* base, unsigned int& e
     }
   }
   __syncthreads();
+}
+
+// Call once per block after its last grid_barrier.  The last block to arrive
+// here knows every block has left every barrier wait, so it can zero the
+// barrier words for the next launch on the stream.
+__device__ __forceinline__ void grid_exit(unsigned int* base) {
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const unsigned int old = __hip_atomic_fetch_add(base + 32 * 17, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (old == gridDim.x - 1u) {
+      for (int i = 0; i < 18; ++i) __hip_atomic_store(base + 32 * i, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+  }
+}
+
+// Partial sums exchanged through a grid barrier are stored with agent-scope
+// atomics, written through to memory independent of the L2 write-back; after
+// the barrier's acquire, plain loads read them from memory.
+__device__ __forceinline__ void put_partial(double* p, double v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // SplitMix64 (Steele, Lea, Flood 2014): output number i of the stream seeded

@@ -1,16 +1,25 @@
 // Kernels of the Leja phi-action library for gfx950 (CDNA4, wave64).
 //
-//  * lj_power_kernel   -- persistent power iteration (Sec. 2.2 spectral estimate)
-//  * lj_divdiff_kernel -- phi_l at the scaled Leja nodes + Newton divided
-//                         differences (Sec. 2.2), one workgroup per accumulator
-//  * lj_leja_kernel    -- persistent fused Newton recurrence (Sec. 2.2 display,
-//                         vertical form of Sec. 4): stencil J y, basis update,
-//                         K accumulator axpys, norm partials, grid barrier,
-//                         stop/reject decision -- all iterations in one launch
-//  * small streaming kernels for f(u), remainders and linear combinations
-//
-// All arithmetic is FP64 (vector ALU); the path is bandwidth/latency bound and
-// has no dense contraction, so no MFMA is used.
+// One phi-action is one persistent, cooperatively launched kernel that runs
+//   (1) the power-iteration spectral bound (Sec. 2.2), unless a bound is given,
+//   (2) phi_l at the scaled Leja nodes and the Newton divided differences
+//       (Sec. 2.2), redundantly in every block, one wave per accumulator,
+//   (3) the Newton recurrence y_m = ((J - c)/gamma - xi_{m-1}) y_{m-1},
+//       p_k += d_{k,m} y_m for K accumulators sharing y_m (Sec. 2.2 display,
+//       vertical form of Sec. 4), with the stop/reject test on FP64 norms.
+// Two shapes of the same computation:
+//   * lj_action_stream: every Newton step is a pass over the vectors in HBM
+//     (any grid size); one grid barrier per step carries the norm partials;
+//   * lj_action_tile: each block keeps one tile of the grid plus an S-wide
+//     halo in LDS and runs S steps between grid barriers (temporal blocking):
+//     step j recomputes the halo ring that step j+1 needs, so the only global
+//     traffic per S steps is one halo exchange and the norm partials.  The
+//     S basis values of the block's own points stay in registers; after the
+//     barrier every block replays the stop decisions of those S steps from the
+//     reduced norms and commits each accumulator's terms up to its own stop
+//     index, so the result is the untiled recurrence's, term for term.
+// All arithmetic is FP64 on the vector ALU: the path is bandwidth/latency
+// bound and has no dense contraction, so no MFMA is used.
 #include <hip/hip_runtime.h>
 
 #include "device.hpp"
@@ -18,13 +27,12 @@
 
 namespace lj {
 
-constexpr int kBlock = 1024;    // threads per block of the persistent kernels (one block per CU)
+constexpr int kBlock = 1024;  // threads per block of the persistent kernels (one block per CU)
 constexpr int kWaves = kBlock / 64;
-constexpr int kNV = kMaxK + 1;  // reduced values per iteration: ||y||^2 and K ||p_k||^2
+constexpr int kQ = 1 + kMaxK;  // reduced values per Newton step: ||y||^2 and K ||p_k||^2
 
 // Blocks are dispatched round-robin over the 8 XCDs; give each XCD a run of
-// consecutive chunks so that halo rows shared by neighbouring chunks mostly
-// stay inside one XCD's L2.
+// consecutive chunks / tiles so that neighbouring work shares an L2.
 __device__ __forceinline__ int xcd_chunk(int b, int G) {
   if (G % 8 != 0) return b;
   return (b % 8) * (G / 8) + (b / 8);
@@ -38,217 +46,380 @@ __device__ __forceinline__ void point_range(int npts, int& p0, int& p1) {
   p1 = min(npts, p0 + chunk);
 }
 
-// Every block sums the per-block partials of one slot in the same fixed order;
-// totals land in tot[0..nq) for all threads.
-__device__ __forceinline__ void grid_totals(const double* __restrict__ part, int nq, double* red,
-                                            double (&tot)[kNV]) {
-  const int G = gridDim.x;
-#pragma unroll
-  for (int q = 0; q < kNV; ++q) tot[q] = 0.0;
-  for (int b = threadIdx.x; b < G; b += blockDim.x) {
-#pragma unroll
-    for (int q = 0; q < kNV; ++q)
-      if (q < nq) tot[q] += part[b * kNV + q];
-  }
-  block_sum<kNV>(tot, red);
+// Partial sums of one barrier slot-set are stored slot-major,
+// part[q * gridDim.x + b] = block b's value of slot q.
+__device__ __forceinline__ double* partial_slots(double* partials, unsigned int epoch) {
+  return partials + (size_t)(epoch & 1u) * kPartStride * gridDim.x;
 }
 
-// ---------------------------------------------------------------------------
-// Power iteration: x_{k+1} = J x_k / ||J x_k||, lambda = ||J x_{K-1}|| / ||x_{K-1}||.
-// The normalisation of x_k is folded into the next product (J(s y) = s J y).
-// ---------------------------------------------------------------------------
-template <int KIND, int NC>
-__global__ __launch_bounds__(kBlock) void lj_power_kernel(PowerParams P) {
-  __shared__ double red[kNV * kWaves + kNV];
-  const OpDev& op = P.op;
-  const int npts = op.npts;
+// Totals of nq <= kPartStride slots over all blocks, summed by every block in
+// the same fixed order: wave w reduces slots w, w + 16, w + 32; lane t adds
+// the blocks t, t + 64, ... of a slot in turn (coalesced loads, all in flight
+// at once), then the wave sums its lanes.  Result in tot[0..nq) (LDS).
+__device__ __forceinline__ void grid_totals(const double* __restrict__ part, int nq, double* tot) {
   const int G = gridDim.x;
-  int p0, p1;
-  point_range(npts, p0, p1);
-  unsigned int epoch = 0;
-  const double* x0 = P.start;
-  if (x0 == nullptr) {
-    for (int p = p0 + (int)threadIdx.x; p < p1; p += blockDim.x) {
+  const int lane = threadIdx.x & 63;
+  const int wid = threadIdx.x >> 6;
+  double a[3] = {0.0, 0.0, 0.0};
 #pragma unroll
-      for (int cc = 0; cc < NC; ++cc) {
-        const int idx = NC * p + cc;
-        P.buf1[idx] = 0.5 + splitmix_uniform(P.seed, (uint64_t)idx);
-      }
-    }
-    x0 = P.buf1;
-    grid_barrier(P.barrier, epoch);
-  }
-  double scale = 1.0;
-  double lam = 0.0;
-  for (int k = 0; k < P.iters; ++k) {
-    const double* src = (k == 0) ? x0 : ((k & 1) ? P.buf0 : P.buf1);
-    double* dst = (k & 1) ? P.buf1 : P.buf0;
-    double acc[kNV] = {0.0, 0.0, 0.0, 0.0, 0.0};
-    for (int p = p0 + (int)threadIdx.x; p < p1; p += blockDim.x) {
-      double out[2], xc[2];
-      jv_point<KIND>(op, src, p, out, xc);
+  for (int i = 0; i < 3; ++i) {
+    const int q = wid + kWaves * i;
+    if (q >= nq) continue;
+    const double* __restrict__ row = part + (size_t)q * G;
 #pragma unroll
-      for (int cc = 0; cc < NC; ++cc) {
-        const double x = scale * xc[cc];
-        const double y = scale * out[cc];
-        dst[NC * p + cc] = y;
-        acc[0] += x * x;
-        acc[1] += y * y;
-      }
-    }
-    block_sum<kNV>(acc, red);
-    double* part = P.partials + (size_t)(k & 1) * G * kNV;
-    if (threadIdx.x == 0) {
-      part[blockIdx.x * kNV + 0] = acc[0];
-      part[blockIdx.x * kNV + 1] = acc[1];
-    }
-    grid_barrier(P.barrier, epoch);
-    double tot[kNV];
-    grid_totals(part, 2, red, tot);
-    const double nx = sqrt(tot[0]);
-    const double ny = sqrt(tot[1]);
-    lam = ny / nx;
-    if (ny == 0.0) {
-      lam = 0.0;
-      break;
-    }
-    scale = 1.0 / ny;
+    for (int r = 0; r < 4; ++r)
+      if (lane + 64 * r < G) a[i] += row[lane + 64 * r];
+    for (int b = lane + 256; b < G; b += 64) a[i] += row[b];
   }
-  if (blockIdx.x == 0 && threadIdx.x == 0) P.scal->lam = lam;
-}
-
-// ---------------------------------------------------------------------------
-// Divided differences of phi_l(s (c + gamma xi_j)), j < npts, one block per
-// accumulator.  Also fixes the interval: alpha = -safety*lambda, beta = 0,
-// c = (alpha+beta)/2, gamma = (beta-alpha)/4 (Sec. 2.2).
-// ---------------------------------------------------------------------------
-__global__ __launch_bounds__(128) void lj_divdiff_kernel(DDParams P) {
-#pragma clang fp contract(off)
-  __shared__ double d[kTable + 1];
-  __shared__ double xs[kTable + 1];
-  __shared__ double fm[2];
-  const int k = blockIdx.x;
-  const int j = threadIdx.x;
-  const double lam = P.use_cg ? 0.0 : ((P.lam_host > 0.0) ? P.lam_host : P.scal->lam);
-  const double alpha = -P.safety * lam;
-  const double beta = 0.0;
-  const double c = P.use_cg ? P.c_in : 0.5 * (alpha + beta);
-  const double gamma = P.use_cg ? P.gamma_in : 0.25 * (beta - alpha);
-  const int n = P.npts;
-  const double s = P.s[k];
-  double f = 0.0;
-  if (j < n) {
-    const double x = P.xi[j];
-    xs[j] = x;
-    const double z = s * (c + gamma * x);
-    f = phi_dev(P.l[k], z);
-    d[j] = f;
-  }
-  // max |f_j| over the block (two waves)
-  double a = fabs(f);
 #pragma unroll
-  for (int off = 32; off >= 1; off >>= 1) a = fmax(a, __shfl_down(a, off, 64));
-  if ((j & 63) == 0) fm[j >> 6] = a;
+  for (int i = 0; i < 3; ++i) {
+    const int q = wid + kWaves * i;
+    if (q >= nq) continue;  // uniform per wave
+    const double t = wave_sum(a[i]);
+    if (lane == 0) tot[q] = t;
+  }
   __syncthreads();
-  for (int order = 1; order < n; ++order) {
-    double t = 0.0;
-    if (j < n && j >= order) t = (d[j] - d[j - 1]) / (xs[j] - xs[j - order]);
-    __syncthreads();
-    if (j < n && j >= order) d[j] = t;
-    __syncthreads();
-  }
-  if (j < n) P.coef[k * kTable + j] = d[j];
-  if (j == 0) {
-    P.fmax[k] = fmax(fm[0], fm[1]);
-    if (k == 0 && !P.use_cg) {
-      P.scal->lam = lam;
-      P.scal->c = c;
-      P.scal->gamma = gamma;
-    }
-  }
 }
 
 // ---------------------------------------------------------------------------
-// Fused Leja recurrence.  One launch runs every iteration m = 1..max_points:
-//   y_m = ((J - c) / gamma - xi_{m-1}) y_{m-1},  p_k += d_{k,m} y_m (active k),
-// with ||y_m||^2 and ||p_k||^2 reduced per block, published to a slot of the
-// partials array, summed by every block after the grid barrier in one fixed
-// order, and the stop/reject decision taken identically by every block.
+// Divided differences of phi_{l_k}(s_k (c + gamma xi_j)), j < n, for K
+// accumulators: wave k computes accumulator k, lane t holding nodes t and t+64.
+// Order by order, d_j <- (d_j - d_{j-1}) / (xi_j - xi_{j-order}) for j >= order
+// (the standard table, Sec. 2.2), with d_{j-1} taken from the neighbouring
+// lane by a DPP wave shift.  Writes coef[k * kTable + j] and fmax[k] = max_j |f_j|.
 // ---------------------------------------------------------------------------
+__device__ void block_divdiff(int K, const int* l, const double* s, int n, double c, double gamma,
+                              const double* xi, double* coef, double* fmax_out) {
+#pragma clang fp contract(off)
+  const int wid = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
+  if (wid >= K) return;
+  const int lk = l[wid];
+  const double sk = s[wid];
+  const int j0 = lane, j1 = lane + 64;
+  const double x0 = xi[j0];
+  const double x1 = (j1 < kTable) ? xi[j1] : 0.0;
+  double d0 = 0.0, d1 = 0.0;
+  if (j0 < n) d0 = phi_dev(lk, sk * (c + gamma * x0));
+  if (j1 < n) d1 = phi_dev(lk, sk * (c + gamma * x1));
+  const double m = wave_max(fmax(fabs(d0), fabs(d1)));
+  for (int order = 1; order < n; ++order) {
+    const double p0 = wave_shift_up(d0);
+    double p1 = wave_shift_up(d1);
+    const double last0 = read_lane(d0, 63);
+    if (lane == 0) p1 = last0;
+    if (j0 >= order && j0 < n) d0 = (d0 - p0) / (x0 - xi[j0 - order]);
+    if (j1 >= order && j1 < n) d1 = (d1 - p1) / (x1 - xi[j1 - order]);
+  }
+  if (j0 < n) coef[wid * kTable + j0] = d0;
+  if (j1 < n) coef[wid * kTable + j1] = d1;
+  if (lane == 0) fmax_out[wid] = m;
+}
+
+// The interval of Sec. 2.2: alpha = -safety * lambda, beta = 0, c the midpoint,
+// gamma a quarter of the length.
+__device__ __forceinline__ void interval(double lam, double safety, double& c, double& gamma) {
+#pragma clang fp contract(off)
+  const double alpha = -safety * lam;
+  const double beta = 0.0;
+  c = 0.5 * (alpha + beta);
+  gamma = 0.25 * (beta - alpha);
+}
+
+// ---------------------------------------------------------------------------
+// Stop / reject decision of one Newton step m (identical in every block):
+// accumulator k freezes at the first m with |d_{k,m}| ||y_m|| <= tol ||p_k||
+// (or <= tol in the absolute form); it is rejected when that term exceeds
+// hump_max ||v|| max|f_k|, when a value is not finite, or at max_points.
+// ---------------------------------------------------------------------------
+struct Decision {
+  int st[kMaxK];
+  int mst[kMaxK];
+  double err[kMaxK];
+  double hump[kMaxK];
+  int n_active;
+  int iters;
+  int accum_iters;
+};
+
+__device__ __forceinline__ void decision_init(Decision& D, int K, double nv, double hump_max, const double* fmaxk) {
+  D.n_active = 0;
+  D.iters = 0;
+  D.accum_iters = 0;
+#pragma unroll
+  for (int k = 0; k < kMaxK; ++k) {
+    D.st[k] = (k < K) ? ACC_RUNNING : ACC_CONVERGED;
+    D.mst[k] = -1;
+    D.err[k] = 0.0;
+    D.hump[k] = (k < K) ? hump_max * nv * fmaxk[k] : 0.0;
+    if (k < K) ++D.n_active;
+  }
+  if (nv == 0.0) {  // v = 0: every phi_l(hJ) v is 0, no term is needed
+#pragma unroll
+    for (int k = 0; k < kMaxK; ++k) {
+      D.st[k] = ACC_CONVERGED;
+      D.mst[k] = (k < K) ? 0 : -1;
+    }
+    D.n_active = 0;
+  }
+}
+
+// pp[k] = ||p_k||^2 after adding term m; dk[k] = d_{k,m}
+__device__ __forceinline__ void decide_step(Decision& D, int m, double yy, const double* pp, const double* dk,
+                                            double tol, int relative, int max_points) {
+  D.iters = m;
+  D.accum_iters += D.n_active;
+  const double ny = sqrt(yy);
+  int n = 0;
+#pragma unroll
+  for (int k = 0; k < kMaxK; ++k) {
+    if (D.st[k] != ACC_RUNNING) continue;
+    const double e = fabs(dk[k]) * ny;
+    const double np = sqrt(pp[k]);
+    if (!(isfinite(e) && isfinite(np))) {
+      D.st[k] = ACC_NONFINITE;
+    } else if (e > D.hump[k]) {
+      D.st[k] = ACC_HUMP;
+    } else if (e <= (relative ? tol * np : tol)) {
+      D.st[k] = ACC_CONVERGED;
+      D.mst[k] = m;
+      D.err[k] = e;
+    } else if (m == max_points) {
+      D.st[k] = ACC_MAXPTS;
+    } else {
+      ++n;
+    }
+  }
+  D.n_active = n;
+}
+
+// Stop decisions of the steps m0+1 .. m0+steps of one super-step, from the
+// reduced totals tot[(j-1)*kQ + q] of step m0+j, taken by the lanes of one
+// wave in parallel over (step, accumulator).  An accumulator's test at a step
+// depends only on its own state, which does not change until it stops, so its
+// stopping step is the lowest one whose test does not continue; the outcome
+// equals decide_step applied to the steps in order.  D is in LDS; commit[k]
+// (LDS) receives how many of the super-step's terms accumulator k adds; trace
+// (optional) receives the totals of the steps that were decided.  Called by
+// all 64 lanes of one wave, with steps <= 16.
+__device__ void replay_decisions(Decision& D, int K, int m0, int steps, const double* tot, const double* coef,
+                                 double tol, int relative, int max_points, int* commit,
+                                 double (*trace)[1 + kMaxK]) {
+  const int lane = threadIdx.x & 63;
+  const int j = lane >> 2, k = lane & 3;  // step m0 + j + 1, accumulator k
+  const int m = m0 + j + 1;
+  const bool run0 = (k < K) && (D.st[k] == ACC_RUNNING);
+  int oc = ACC_RUNNING;
+  double e = 0.0;
+  if (run0 && j < steps) {
+    const double ny = sqrt(tot[j * kQ]);
+    e = fabs(coef[k * kTable + m]) * ny;
+    const double np = sqrt(tot[j * kQ + 1 + k]);
+    if (!(isfinite(e) && isfinite(np))) {
+      oc = ACC_NONFINITE;
+    } else if (e > D.hump[k]) {
+      oc = ACC_HUMP;
+    } else if (e <= (relative ? tol * np : tol)) {
+      oc = ACC_CONVERGED;
+    } else if (m == max_points) {
+      oc = ACC_MAXPTS;
+    }
+  }
+  const unsigned long long stop = __ballot(oc != ACC_RUNNING);
+  const unsigned long long mine = stop & (0x1111111111111111ull << k);
+  const int first = mine ? (int)__builtin_ctzll(mine) : -1;  // lane of the stopping step
+  const int src = first >= 0 ? first : lane;
+  const int oc_f = __shfl(oc, src, 64);
+  const double e_f = __shfl(e, src, 64);
+  const int cm = run0 ? (first >= 0 ? (first >> 2) + 1 : steps) : 0;
+  const bool still = run0 && first < 0;
+  const unsigned long long alive = __ballot(lane < kMaxK && still);
+  const int c0 = __shfl(cm, 0, 64), c1 = __shfl(cm, 1, 64), c2 = __shfl(cm, 2, 64), c3 = __shfl(cm, 3, 64);
+  const int cmax = max(max(c0, c1), max(c2, c3));
+  if (lane < kMaxK) {
+    commit[k] = cm;
+    if (run0 && first >= 0) {
+      D.st[k] = oc_f;
+      if (oc_f == ACC_CONVERGED) {
+        D.mst[k] = m0 + (first >> 2) + 1;
+        D.err[k] = e_f;
+      }
+    }
+  }
+  if (lane == 0) {
+    D.n_active = __builtin_popcountll(alive);
+    if (cmax > 0) D.iters = m0 + cmax;
+    D.accum_iters += c0 + c1 + c2 + c3;
+  }
+  if (trace != nullptr) {
+    for (int t = lane; t < cmax * kQ; t += 64) trace[m0 + t / kQ][t % kQ] = tot[t];
+  }
+}
+
+__device__ __forceinline__ void write_status(LejaStatus* S, const Decision& D, int pit, int barriers, double nv,
+                                             double lam, double c, double gamma) {
+#pragma unroll
+  for (int k = 0; k < kMaxK; ++k) {
+    S->state[k] = D.st[k];
+    S->m_star[k] = D.mst[k];
+    S->err[k] = D.err[k];
+  }
+  S->iters = D.iters;
+  S->accum_iters = D.accum_iters;
+  S->power_iters = pit;
+  S->barriers = barriers;
+  S->vnorm = nv;
+  S->lam = lam;
+  S->c = c;
+  S->gamma = gamma;
+}
+
+// per-block shared state of both action kernels
+struct ActionShared {
+  double xi[kTable];
+  double coef[kMaxK * kTable];
+  double fmax[kMaxK];
+  double tot[64];
+  double red[kPartStride * kWaves];  // staged wave sums, slot-major
+};
+
+// ===========================================================================
+// Streaming action kernel (any grid size): one pass over HBM per Newton step.
+// ===========================================================================
 template <int KIND, int NC>
-__global__ __launch_bounds__(kBlock) void lj_leja_kernel(LejaParams P) {
-  __shared__ double s_coef[kMaxK * kTable];
-  __shared__ double red[kNV * kWaves + kNV];
+__global__ __launch_bounds__(kBlock) void lj_action_stream(ActionParams P) {
+  __shared__ ActionShared sh;
   const OpDev& op = P.op;
   const int npts = op.npts;
   const int K = P.K;
-  const int G = gridDim.x;
+  for (int i = threadIdx.x; i < kTable; i += blockDim.x) sh.xi[i] = P.xi[i];
   int p0, p1;
   point_range(npts, p0, p1);
-  for (int i = threadIdx.x; i < K * kTable; i += blockDim.x) s_coef[i] = P.coef[i];
-  const double c = P.scal->c;
-  const double gamma = P.scal->gamma;
-  __syncthreads();
   unsigned int epoch = 0;
+  double wred[kQ];
+  unsigned long long prof[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  unsigned long long t_last = wall_clock64();
+  auto tick = [&](int phase) {
+    const unsigned long long t = wall_clock64();
+    prof[phase] += t - t_last;
+    t_last = t;
+  };
 
-  // m = 0: p_k = d_{k,0} v, and ||v||^2
+  // (1) spectral bound
+  double lam = P.lam_in;
+  int pit = 0;
+  if (P.do_power) {
+    const double* x0 = P.start;
+    if (x0 == nullptr) {
+      for (int p = p0 + (int)threadIdx.x; p < p1; p += blockDim.x)
+#pragma unroll
+        for (int cc = 0; cc < NC; ++cc) P.ybuf1[NC * p + cc] = 0.5 + splitmix_uniform(P.seed, (uint64_t)(NC * p + cc));
+      x0 = P.ybuf1;
+      grid_barrier(P.barrier, epoch);
+    }
+    double scale = 1.0;
+    for (int k = 0; k < P.power_iters; ++k) {
+      const double* src = (k == 0) ? x0 : ((k & 1) ? P.ybuf0 : P.ybuf1);
+      double* dst = (k & 1) ? P.ybuf1 : P.ybuf0;
+      double a0 = 0.0, a1 = 0.0;
+      for (int p = p0 + (int)threadIdx.x; p < p1; p += blockDim.x) {
+        double out[2], xc[2];
+        jv_point<KIND, NC>(op, src, p, out, xc);
+#pragma unroll
+        for (int cc = 0; cc < NC; ++cc) {
+          const double x = scale * xc[cc];
+          const double y = scale * out[cc];
+          dst[NC * p + cc] = y;
+          a0 += x * x;
+          a1 += y * y;
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < kQ; ++q) wred[q] = 0.0;
+      wred[0] = a0;
+      wred[1] = a1;
+      block_sum<kQ>(wred, sh.red);
+      double* part = partial_slots(P.partials, epoch);
+      if (threadIdx.x == 0) {
+        put_partial(part + blockIdx.x, wred[0]);
+        put_partial(part + gridDim.x + blockIdx.x, wred[1]);
+      }
+      grid_barrier(P.barrier, epoch);
+      grid_totals(part, 2, sh.tot);
+      const double nx = sqrt(sh.tot[0]);
+      const double ny = sqrt(sh.tot[1]);
+      lam = ny / nx;
+      pit = k + 1;
+      if (ny == 0.0) {
+        lam = 0.0;
+        break;
+      }
+      scale = 1.0 / ny;
+    }
+  }
+  double c, gamma;
+  interval(lam, P.safety, c, gamma);
+  tick(kProfPower);
+  if (K == 0) {  // bound only
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      Decision D;
+      decision_init(D, 0, 1.0, 0.0, sh.fmax);
+      write_status(P.status, D, pit, (int)epoch, 0.0, lam, c, gamma);
+    }
+    grid_exit(P.barrier);
+    return;
+  }
+
+  // (2) divided differences, every block for itself
+  __syncthreads();
+  block_divdiff(K, P.l, P.s, P.max_points + 1, c, gamma, sh.xi, sh.coef, sh.fmax);
+  __syncthreads();
+  tick(kProfDivdiff);
+
+  // (3) m = 0: p_k = d_{k,0} v and ||v||^2
   {
-    double acc[kNV] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    double a0 = 0.0;
     for (int p = p0 + (int)threadIdx.x; p < p1; p += blockDim.x) {
 #pragma unroll
       for (int cc = 0; cc < NC; ++cc) {
         const int idx = NC * p + cc;
         const double vv = P.v[idx];
-        acc[0] += vv * vv;
+        a0 += vv * vv;
 #pragma unroll
         for (int k = 0; k < kMaxK; ++k)
-          if (k < K) P.p[k][idx] = s_coef[k * kTable] * vv;
+          if (k < K) P.p[k][idx] = sh.coef[k * kTable] * vv;
       }
     }
-    block_sum<kNV>(acc, red);
-    if (threadIdx.x == 0) P.partials[blockIdx.x * kNV] = acc[0];
-  }
-  grid_barrier(P.barrier, epoch);
-  double tot[kNV];
-  grid_totals(P.partials, 1, red, tot);
-  const double nv = sqrt(tot[0]);
-
-  int st[kMaxK], mst[kMaxK];
-  double err[kMaxK], hump[kMaxK];
-  int n_active = 0;
 #pragma unroll
-  for (int k = 0; k < kMaxK; ++k) {
-    st[k] = (k < K) ? ACC_RUNNING : ACC_CONVERGED;
-    mst[k] = -1;
-    err[k] = 0.0;
-    hump[k] = (k < K) ? P.hump * nv * P.fmax[k] : 0.0;
-    if (k < K) ++n_active;
+    for (int q = 0; q < kQ; ++q) wred[q] = 0.0;
+    wred[0] = a0;
+    block_sum<kQ>(wred, sh.red);
+    if (threadIdx.x == 0) put_partial(partial_slots(P.partials, epoch) + blockIdx.x, wred[0]);
   }
-  int iters = 0, accum_iters = 0;
-  if (nv == 0.0) {
-#pragma unroll
-    for (int k = 0; k < kMaxK; ++k) {
-      st[k] = ACC_CONVERGED;
-      mst[k] = (k < K) ? 0 : -1;
-    }
-    n_active = 0;
+  {
+    const double* part = partial_slots(P.partials, epoch);
+    grid_barrier(P.barrier, epoch);
+    grid_totals(part, 1, sh.tot);
   }
+  const double nv = sqrt(sh.tot[0]);
+  Decision D;
+  decision_init(D, K, nv, P.hump, sh.fmax);
 
-  for (int m = 1; m <= P.max_points && n_active > 0; ++m) {
+  for (int m = 1; m <= P.max_points && D.n_active > 0; ++m) {
     const double* __restrict__ src = (m == 1) ? P.v : ((m & 1) ? P.ybuf0 : P.ybuf1);
     double* __restrict__ dst = (m & 1) ? P.ybuf1 : P.ybuf0;
-    const double xim = P.xi[m - 1];
+    const double xim = sh.xi[m - 1];
     double dk[kMaxK];
     bool act[kMaxK];
 #pragma unroll
     for (int k = 0; k < kMaxK; ++k) {
-      act[k] = (k < K) && (st[k] == ACC_RUNNING);
-      dk[k] = act[k] ? s_coef[k * kTable + m] : 0.0;
+      act[k] = (k < K) && (D.st[k] == ACC_RUNNING);
+      dk[k] = act[k] ? sh.coef[k * kTable + m] : 0.0;
     }
-    double acc[kNV] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    double acc[kQ] = {0.0, 0.0, 0.0, 0.0, 0.0};
     for (int p = p0 + (int)threadIdx.x; p < p1; p += blockDim.x) {
       double out[2], xc[2];
-      jv_point<KIND>(op, src, p, out, xc);
+      jv_point<KIND, NC>(op, src, p, out, xc);
 #pragma unroll
       for (int cc = 0; cc < NC; ++cc) {
         const int idx = NC * p + cc;
@@ -265,59 +436,314 @@ __global__ __launch_bounds__(kBlock) void lj_leja_kernel(LejaParams P) {
         }
       }
     }
-    block_sum<kNV>(acc, red);
-    double* part = P.partials + (size_t)(m & 1) * G * kNV;
+    tick(kProfSteps);
+    block_sum<kQ>(acc, sh.red);
+    double* part = partial_slots(P.partials, epoch);
     if (threadIdx.x == 0) {
 #pragma unroll
-      for (int q = 0; q < kNV; ++q) part[blockIdx.x * kNV + q] = acc[q];
+      for (int q = 0; q < kQ; ++q) put_partial(part + q * gridDim.x + blockIdx.x, acc[q]);
     }
+    tick(kProfPublish);
     grid_barrier(P.barrier, epoch);
-    grid_totals(part, 1 + K, red, tot);
-    ++iters;
-    accum_iters += n_active;
-    const double ny = sqrt(tot[0]);
-    n_active = 0;
+    tick(kProfBarrier);
+    grid_totals(part, kQ, sh.tot);
+    if (blockIdx.x == 0 && threadIdx.x == 0)
+      for (int q = 0; q < kQ; ++q) P.status->trace[m - 1][q] = sh.tot[q];
+    decide_step(D, m, sh.tot[0], sh.tot + 1, dk, P.tol, P.relative, P.max_points);
+    tick(kProfDecide);
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    write_status(P.status, D, pit, (int)epoch, nv, lam, c, gamma);
+    for (int q = 0; q < 8; ++q) P.status->prof[q] = prof[q];
+  }
+  grid_exit(P.barrier);
+}
+
+// ===========================================================================
+// LDS-tiled action kernel with temporal blocking: one tile per block, one
+// owned point per thread, scalar families whose Jacobian reads the state at
+// the centre only.  EPT: extended (tile + halo) points per thread.
+// ===========================================================================
+template <int KIND, int S, int EPT>
+__global__ __launch_bounds__(kBlock) void lj_action_tile(ActionParams P) {
+  static_assert(KIND == OP_ADVDIFF || KIND == OP_ALLENCAHN, "tiled kernel: scalar centre-state families");
+  extern __shared__ double lds[];
+  __shared__ ActionShared sh;
+  const OpDev& op = P.op;
+  const int K = P.K;
+  const int nx = op.nx, ny = op.ny;
+  for (int i = threadIdx.x; i < kTable; i += blockDim.x) sh.xi[i] = P.xi[i];
+
+  // ---- tile geometry: owned w x h points at (x0, y0), extended by S per side
+  const int tb = xcd_chunk(blockIdx.x, gridDim.x);
+  const int x0 = (tb % P.ntx) * P.tx, y0 = (tb / P.ntx) * P.ty;
+  const int w = min(P.tx, nx - x0), h = min(P.ty, ny - y0);
+  const int EW = w + 2 * S, EH = h + 2 * S, NE = EW * EH;
+  double* Y[2] = {lds, lds + NE};
+  // extended points of this thread: e = threadIdx.x + k * kBlock (valid if < NE),
+  // tile coordinates packed as ex | ey << 16, linearisation state in registers
+  int e_xy[EPT];
+  double e_u[EPT];
+  auto gidx = [&](int k) {
+    const int ex = e_xy[k] & 0xffff, ey = e_xy[k] >> 16;
+    int gx = (x0 - S + ex) % nx;
+    if (gx < 0) gx += nx;
+    int gy = (y0 - S + ey) % ny;
+    if (gy < 0) gy += ny;
+    return gy * nx + gx;
+  };
 #pragma unroll
-    for (int k = 0; k < kMaxK; ++k) {
-      if (!act[k]) continue;
-      const double e = fabs(dk[k]) * ny;
-      const double np = sqrt(tot[1 + k]);
-      if (!(isfinite(e) && isfinite(np))) {
-        st[k] = ACC_NONFINITE;
-      } else if (e > hump[k]) {
-        st[k] = ACC_HUMP;
-      } else if (e <= (P.relative ? P.tol * np : P.tol)) {
-        st[k] = ACC_CONVERGED;
-        mst[k] = m;
-        err[k] = e;
-      } else if (m == P.max_points) {
-        st[k] = ACC_MAXPTS;
+  for (int k = 0; k < EPT; ++k) {
+    const int e = threadIdx.x + k * kBlock;
+    const int ey = e / EW;
+    e_xy[k] = (e - ey * EW) | (ey << 16);
+    e_u[k] = (e < NE && StateUse<KIND>::value > 0) ? op.state[gidx(k)] : 0.0;
+  }
+  const int o = threadIdx.x;
+  const bool own = o < w * h;
+  const int lx = own ? o % w : 0, ly = own ? o / w : 0;
+  const int eo = (ly + S) * EW + lx + S;
+  const int go = (y0 + ly) * nx + x0 + lx;
+
+  unsigned int epoch = 0;
+  int cur = 0, par = 0;
+  unsigned long long prof[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  unsigned long long t_last = wall_clock64();
+  auto tick = [&](int phase) {
+    const unsigned long long t = wall_clock64();
+    prof[phase] += t - t_last;
+    t_last = t;
+  };
+
+  // one Newton (leja) or power step on the region still exact after j steps
+  auto step = [&](int j, double shift, double gam, double xim, bool leja) {
+    const double* src = Y[cur];
+    double* dst = Y[cur ^ 1];
+#pragma unroll
+    for (int k = 0; k < EPT; ++k) {
+      const int e = threadIdx.x + k * kBlock;
+      if (e >= NE) continue;
+      const int ex = e_xy[k] & 0xffff, ey = e_xy[k] >> 16;
+      if (ex < j || ex >= EW - j || ey < j || ey >= EH - j) continue;
+      double xv[5][2] = {}, uv[5][2] = {};
+      xv[0][0] = src[e];
+      xv[1][0] = src[e - 1];
+      xv[2][0] = src[e + 1];
+      xv[3][0] = src[e - EW];
+      xv[4][0] = src[e + EW];
+      uv[0][0] = e_u[k];
+      double out[2];
+      stencil_jv<KIND>(op, xv, uv, out);
+      dst[e] = leja ? (out[0] - shift * xv[0][0]) / gam - xim * xv[0][0] : out[0];
+    }
+    __syncthreads();
+    cur ^= 1;
+  };
+  // refill the halo ring of the current buffer from a global vector and
+  // scale the owned points (scale 1: halo only)
+  auto load_halo = [&](const double* g, double scale) {
+#pragma unroll
+    for (int k = 0; k < EPT; ++k) {
+      const int e = threadIdx.x + k * kBlock;
+      if (e >= NE) continue;
+      const int ex = e_xy[k] & 0xffff, ey = e_xy[k] >> 16;
+      const bool inner = ex >= S && ex < S + w && ey >= S && ey < S + h;
+      if (inner) {
+        if (scale != 1.0) Y[cur][e] *= scale;
       } else {
-        ++n_active;
+        Y[cur][e] = scale * g[gidx(k)];
+      }
+    }
+    __syncthreads();
+  };
+  // wave sums of one value per thread into staging slot `slot`
+  auto stage = [&](int slot, double v) {
+    const double s = wave_sum(v);
+    if ((threadIdx.x & 63) == 0) sh.red[slot * kWaves + (threadIdx.x >> 6)] = s;
+  };
+  // block totals of staged slots [0, nslots) -> this barrier's partials
+  auto publish = [&](int nslots) {
+    __syncthreads();
+    double* part = partial_slots(P.partials, epoch);
+    if ((int)threadIdx.x < nslots) {
+      double t = 0.0;
+#pragma unroll
+      for (int wv = 0; wv < kWaves; ++wv) t += sh.red[threadIdx.x * kWaves + wv];
+      put_partial(part + threadIdx.x * gridDim.x + blockIdx.x, t);
+    }
+    __syncthreads();
+    return part;
+  };
+
+  // ---- (1) spectral bound: S products between barriers, normalised per barrier
+  double lam = P.lam_in;
+  int pit = 0;
+  tick(kProfSetup);
+  if (P.do_power) {
+#pragma unroll
+    for (int k = 0; k < EPT; ++k) {
+      const int e = threadIdx.x + k * kBlock;
+      if (e >= NE) continue;
+      const int g = gidx(k);
+      Y[0][e] = P.start ? P.start[g] : 0.5 + splitmix_uniform(P.seed, (uint64_t)g);
+    }
+    __syncthreads();
+    int done = 0;
+    while (done < P.power_iters) {
+      const int steps = min(S, P.power_iters - done);
+      {
+        const double x = own ? Y[cur][eo] : 0.0;
+        stage(0, x * x);
+      }
+      for (int j = 1; j <= steps; ++j) {
+        step(j, 0.0, 1.0, 0.0, false);
+        const double y = own ? Y[cur][eo] : 0.0;
+        stage(j, y * y);
+      }
+      double* part = publish(steps + 1);
+      if (own) ((par == 0) ? P.ybuf0 : P.ybuf1)[go] = Y[cur][eo];
+      grid_barrier(P.barrier, epoch);
+      grid_totals(part, steps + 1, sh.tot);
+      const double nprev = sh.tot[steps - 1], nlast = sh.tot[steps];
+      done += steps;
+      pit = done;
+      lam = sqrt(nlast) / sqrt(nprev);
+      if (nlast == 0.0) {
+        lam = 0.0;
+        break;
+      }
+      if (done < P.power_iters) {
+        load_halo((par == 0) ? P.ybuf0 : P.ybuf1, 1.0 / sqrt(nlast));
+        par ^= 1;
       }
     }
   }
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
+  double c, gamma;
+  interval(lam, P.safety, c, gamma);
+  tick(kProfPower);
+  if (K == 0) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      Decision D;
+      decision_init(D, 0, 1.0, 0.0, sh.fmax);
+      write_status(P.status, D, pit, (int)epoch, 0.0, lam, c, gamma);
+      for (int q = 0; q < 8; ++q) P.status->prof[q] = prof[q];
+    }
+    grid_exit(P.barrier);
+    return;
+  }
+
+  // ---- (2) divided differences, and y_0 = v on the extended tile
+  __syncthreads();
+  block_divdiff(K, P.l, P.s, P.max_points + 1, c, gamma, sh.xi, sh.coef, sh.fmax);
+  cur = 0;
+#pragma unroll
+  for (int k = 0; k < EPT; ++k)
+    if ((int)threadIdx.x + k * kBlock < NE) Y[0][threadIdx.x + k * kBlock] = P.v[gidx(k)];
+  __syncthreads();
+  tick(kProfDivdiff);
+
+  // ---- (3) Newton recurrence in super-steps of S.  The decision state is the
+  // same in every thread, so it lives once per block in LDS: wave 0 replays
+  // the decisions, everyone reads the outcome.
+  __shared__ Decision sD;
+  __shared__ int s_commit[kMaxK];
+  double pk[kMaxK];
+  const double v_own = own ? Y[0][eo] : 0.0;
+#pragma unroll
+  for (int k = 0; k < kMaxK; ++k) pk[k] = sh.coef[k * kTable] * v_own;
+  if (threadIdx.x == 0) decision_init(sD, K, 1.0, 0.0, sh.fmax);  // redone once ||v|| is known
+  __syncthreads();
+  double nv = 0.0;
+  bool first = true;
+  int m0 = 0;
+  double hist[S];
+  while (true) {
+    const int steps = min(S, P.max_points - m0);
+    bool act0[kMaxK];
+#pragma unroll
+    for (int k = 0; k < kMaxK; ++k) act0[k] = (k < K) && (sD.st[k] == ACC_RUNNING);
+    double ps[kMaxK];
+#pragma unroll
+    for (int k = 0; k < kMaxK; ++k) ps[k] = pk[k];
+#pragma unroll
+    for (int j = 1; j <= S; ++j) {
+      if (j > steps) break;
+      const int m = m0 + j;
+      step(j, c, gamma, sh.xi[m - 1], true);
+      const double y = own ? Y[cur][eo] : 0.0;
+      hist[j - 1] = y;
+      stage((j - 1) * kQ, y * y);
+#pragma unroll
+      for (int k = 0; k < kMaxK; ++k) {
+        if (!act0[k]) continue;
+        ps[k] = ps[k] + sh.coef[k * kTable + m] * y;
+        stage((j - 1) * kQ + 1 + k, ps[k] * ps[k]);
+      }
+    }
+    tick(kProfSteps);
+    if (first) stage(kPartStride - 1, v_own * v_own);  // ||v||^2 rides on the first barrier
+    double* part = publish(first ? kPartStride : steps * kQ);
+    if (own) ((par == 0) ? P.ybuf0 : P.ybuf1)[go] = Y[cur][eo];
+    tick(kProfPublish);
+    grid_barrier(P.barrier, epoch);
+    tick(kProfBarrier);
+    grid_totals(part, first ? kPartStride : steps * kQ, sh.tot);
+    if (threadIdx.x < 64) {
+      if (first) {
+        nv = sqrt(sh.tot[kPartStride - 1]);
+        decision_init(sD, K, nv, P.hump, sh.fmax);
+      }
+      replay_decisions(sD, K, m0, steps, sh.tot, sh.coef, P.tol, P.relative, P.max_points, s_commit,
+                       blockIdx.x == 0 ? P.status->trace : nullptr);
+    }
+    first = false;
+    __syncthreads();
+    // commit each accumulator's terms up to its stop index
 #pragma unroll
     for (int k = 0; k < kMaxK; ++k) {
-      P.status->state[k] = st[k];
-      P.status->m_star[k] = mst[k];
-      P.status->err[k] = err[k];
+      const int ck = s_commit[k];
+#pragma unroll
+      for (int j = 1; j <= S; ++j)
+        if (j <= ck) pk[k] = pk[k] + sh.coef[k * kTable + m0 + j] * hist[j - 1];
     }
-    P.status->iters = iters;
-    P.status->accum_iters = accum_iters;
-    P.status->vnorm = nv;
+    m0 += steps;
+    tick(kProfDecide);
+    if (sD.n_active == 0 || m0 >= P.max_points) break;
+    load_halo((par == 0) ? P.ybuf0 : P.ybuf1, 1.0);
+    par ^= 1;
+    tick(kProfHalo);
   }
+  if (own) {
+#pragma unroll
+    for (int k = 0; k < kMaxK; ++k)
+      if (k < K) P.p[k][go] = pk[k];
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    write_status(P.status, sD, pit, (int)epoch, nv, lam, c, gamma);
+    for (int q = 0; q < 8; ++q) P.status->prof[q] = prof[q];
+  }
+  grid_exit(P.barrier);
+}
+
+// ---------------------------------------------------------------------------
+// Stand-alone divided differences (the lj_divided_differences entry point);
+// the same block_divdiff the action kernels run.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void lj_divdiff_kernel(DDParams P) {
+  __shared__ double xi[kTable];
+  __shared__ double coef[kMaxK * kTable];
+  __shared__ double fm[kMaxK];
+  for (int i = threadIdx.x; i < kTable; i += blockDim.x) xi[i] = P.xi[i];
+  __syncthreads();
+  block_divdiff(P.K, P.l, P.s, P.npts, P.c, P.gamma, xi, coef, fm);
+  __syncthreads();
+  for (int i = threadIdx.x; i < P.K * kTable; i += blockDim.x) P.coef[i] = coef[i];
+  if ((int)threadIdx.x < P.K) P.fmax[threadIdx.x] = fm[threadIdx.x];
 }
 
 // ---------------------------------------------------------------------------
 // Streaming helpers.
 // ---------------------------------------------------------------------------
-__global__ void lj_fill_u32_kernel(unsigned int* p, int n, unsigned int value) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) p[i] = value;
-}
-
 template <int KIND, int NC>
 __global__ __launch_bounds__(256) void lj_rhs_kernel(OpDev op, const double* __restrict__ u,
                                                      double* __restrict__ f) {
@@ -338,7 +764,7 @@ __global__ __launch_bounds__(256) void lj_remainder_kernel(OpDev op, const doubl
   for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < op.npts; p += gridDim.x * blockDim.x) {
     double fx[2], jd[2], dc[2];
     rhs_point<KIND>(op, x, p, fx);
-    jv_point<KIND>(op, d, p, jd, dc);
+    jv_point<KIND, NC>(op, d, p, jd, dc);
 #pragma unroll
     for (int cc = 0; cc < NC; ++cc) r[NC * p + cc] = (fx[cc] - fu[NC * p + cc]) - jd[cc];
   }
@@ -355,42 +781,39 @@ __global__ __launch_bounds__(256) void lj_lincomb_kernel(LinComb L) {
 // ---------------------------------------------------------------------------
 // Launch wrappers (host side).
 // ---------------------------------------------------------------------------
-template <int KIND, int NC>
-static void* leja_fn() { return reinterpret_cast<void*>(&lj_leja_kernel<KIND, NC>); }
-template <int KIND, int NC>
-static void* power_fn() { return reinterpret_cast<void*>(&lj_power_kernel<KIND, NC>); }
-
-void* leja_kernel_ptr(int kind) {
-  switch (kind) {
-    case OP_DIAG: return leja_fn<OP_DIAG, 1>();
-    case OP_ADVDIFF: return leja_fn<OP_ADVDIFF, 1>();
-    case OP_ALLENCAHN: return leja_fn<OP_ALLENCAHN, 1>();
-    case OP_BRUSSELATOR: return leja_fn<OP_BRUSSELATOR, 2>();
-    case OP_BURGERS: return leja_fn<OP_BURGERS, 1>();
-  }
-  return nullptr;
-}
-
-void* power_kernel_ptr(int kind) {
-  switch (kind) {
-    case OP_DIAG: return power_fn<OP_DIAG, 1>();
-    case OP_ADVDIFF: return power_fn<OP_ADVDIFF, 1>();
-    case OP_ALLENCAHN: return power_fn<OP_ALLENCAHN, 1>();
-    case OP_BRUSSELATOR: return power_fn<OP_BRUSSELATOR, 2>();
-    case OP_BURGERS: return power_fn<OP_BURGERS, 1>();
-  }
-  return nullptr;
-}
-
 int persistent_block() { return kBlock; }
+int tile_halo() { return kMaxSuper; }
 
-hipError_t launch_fill_u32(unsigned int* p, int n, unsigned int value, hipStream_t s) {
-  hipLaunchKernelGGL(lj_fill_u32_kernel, dim3((n + 255) / 256), dim3(256), 0, s, p, n, value);
-  return hipGetLastError();
+void* action_stream_ptr(int kind) {
+  switch (kind) {
+    case OP_DIAG: return reinterpret_cast<void*>(&lj_action_stream<OP_DIAG, 1>);
+    case OP_ADVDIFF: return reinterpret_cast<void*>(&lj_action_stream<OP_ADVDIFF, 1>);
+    case OP_ALLENCAHN: return reinterpret_cast<void*>(&lj_action_stream<OP_ALLENCAHN, 1>);
+    case OP_BRUSSELATOR: return reinterpret_cast<void*>(&lj_action_stream<OP_BRUSSELATOR, 2>);
+    case OP_BURGERS: return reinterpret_cast<void*>(&lj_action_stream<OP_BURGERS, 1>);
+  }
+  return nullptr;
+}
+
+void* action_tile_ptr(int kind, int ept) {
+  if (kind == OP_ALLENCAHN) {
+    switch (ept) {
+      case 1: return reinterpret_cast<void*>(&lj_action_tile<OP_ALLENCAHN, kMaxSuper, 1>);
+      case 2: return reinterpret_cast<void*>(&lj_action_tile<OP_ALLENCAHN, kMaxSuper, 2>);
+      case 3: return reinterpret_cast<void*>(&lj_action_tile<OP_ALLENCAHN, kMaxSuper, 3>);
+    }
+  } else if (kind == OP_ADVDIFF) {
+    switch (ept) {
+      case 1: return reinterpret_cast<void*>(&lj_action_tile<OP_ADVDIFF, kMaxSuper, 1>);
+      case 2: return reinterpret_cast<void*>(&lj_action_tile<OP_ADVDIFF, kMaxSuper, 2>);
+      case 3: return reinterpret_cast<void*>(&lj_action_tile<OP_ADVDIFF, kMaxSuper, 3>);
+    }
+  }
+  return nullptr;
 }
 
 hipError_t launch_divdiff(const DDParams& P, hipStream_t s) {
-  hipLaunchKernelGGL(lj_divdiff_kernel, dim3(P.K), dim3(128), 0, s, P);
+  hipLaunchKernelGGL(lj_divdiff_kernel, dim3(1), dim3(256), 0, s, P);
   return hipGetLastError();
 }
 

@@ -16,11 +16,11 @@ struct LinComb {
   double* out;
 };
 
-void* leja_kernel_ptr(int kind);
-void* power_kernel_ptr(int kind);
-int persistent_block();
+int persistent_block();  // threads per block of the action kernels
+int tile_halo();         // halo width = Newton steps per barrier of the tiled kernel
+void* action_stream_ptr(int kind);
+void* action_tile_ptr(int kind, int ept);  // nullptr if the family has no tiled kernel
 
-hipError_t launch_fill_u32(unsigned int* p, int n, unsigned int value, hipStream_t s);
 hipError_t launch_divdiff(const DDParams& P, hipStream_t s);
 hipError_t launch_rhs(const OpDev& op, const double* u, double* f, hipStream_t s);
 hipError_t launch_remainder(const OpDev& op, const double* x, const double* d, const double* fu,

@@ -41,17 +41,16 @@ struct lj_context {
   size_t vec_cap[W_NSLOTS] = {};
   double* d_coef = nullptr;
   double* d_fmax = nullptr;
-  Scalars* d_scal = nullptr;
   double* d_partials = nullptr;
   int partial_cap = 0;  // blocks
   unsigned int* d_barrier = nullptr;
   LejaStatus* d_status = nullptr;
   LejaStatus* h_status = nullptr;  // pinned
-  Scalars* h_scal = nullptr;       // pinned
   double* h_coef = nullptr;        // pinned
-  int occ_leja[5] = {0, 0, 0, 0, 0};
-  int occ_power[5] = {0, 0, 0, 0, 0};
-  int grid_override = 0;
+  int grid_override = 0;   // LJ_GRID: blocks of the streaming kernel
+  int force_stream = 0;    // LJ_NO_TILE=1: never use the LDS-tiled kernel
+  int tile_override_x = 0; // LJ_TILE=tx,ty: tile shape of the LDS-tiled kernel
+  int tile_override_y = 0;
   // timing
   bool timing = false;
   hipEvent_t ev[4] = {};
@@ -199,7 +198,7 @@ void ensure_small(lj_context* ctx, int blocks) {
     if (ctx->d_partials) (void)hipFree(ctx->d_partials);
     ctx->d_partials = nullptr;
     ctx->partial_cap = 0;
-    if (hipMalloc(&ctx->d_partials, (size_t)2 * blocks * (kMaxK + 1) * sizeof(double)) != hipSuccess) {
+    if (hipMalloc(&ctx->d_partials, (size_t)2 * blocks * kPartStride * sizeof(double)) != hipSuccess) {
       ctx->err = "partials allocation failed";
       throw Fail{LJ_ENOMEM};
     }
@@ -207,139 +206,160 @@ void ensure_small(lj_context* ctx, int blocks) {
   }
 }
 
-// Blocks of a persistent launch: one per CU at most (barrier cost grows with
+// Blocks of a streaming launch: one per CU at most (barrier cost grows with
 // the block count), fewer for small grids, whole rounds over the 8 XCDs.
-int grid_for(lj_context* ctx, int occ, int npts) {
+int grid_for(lj_context* ctx, int npts) {
   const int B = persistent_block();
   int want = (npts + B - 1) / B;
   int cap = ctx->num_cus;
-  if (ctx->grid_override > 0) cap = ctx->grid_override < ctx->num_cus * occ ? ctx->grid_override : ctx->num_cus * occ;
+  if (ctx->grid_override > 0 && ctx->grid_override < cap) cap = ctx->grid_override;
   int g = want < cap ? want : cap;
   if (g >= 64) g -= g % 8;
   return g < 1 ? 1 : g;
 }
 
-int occupancy(lj_context* ctx, void* fn, int* cache, int kind) {
-  if (cache[kind] == 0) {
-    int nb = 0;
-    HIPCHK(ctx, hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, persistent_block(), 0));
-    if (nb < 1) {
-      ctx->err = "persistent kernel cannot be resident";
-      throw Fail{LJ_EHIP};
+// Tile plan of the LDS-resident kernel: one owned point per thread, halo S,
+// at most 3 extended points per thread, LDS (two buffers) within 64 KiB with
+// the kernel's static LDS, at most one tile per CU.  The largest tile that
+// fits wins (fewest blocks: the barrier is the per-super-step cost).
+struct TilePlan {
+  bool ok = false;
+  int tx = 0, ty = 0, ntx = 0, nty = 0, ept = 0;
+  size_t lds = 0;
+};
+
+TilePlan tile_plan(lj_context* ctx, const OpDev& op) {
+  TilePlan best;
+  if (ctx->force_stream || action_tile_ptr(op.kind, 1) == nullptr) return best;
+  const int S = tile_halo();
+  const int B = persistent_block();
+  static const int cand[][2] = {{32, 32}, {64, 16}, {32, 16}, {16, 16}, {16, 8}, {8, 8}};
+  for (const auto& c : cand) {
+    int tx = c[0], ty = c[1];
+    if (ctx->tile_override_x > 0) {
+      tx = ctx->tile_override_x;
+      ty = ctx->tile_override_y;
     }
-    cache[kind] = nb;
+    const int w = tx < op.nx ? tx : op.nx, h = ty < op.ny ? ty : op.ny;
+    const int ntx = (op.nx + tx - 1) / tx, nty = (op.ny + ty - 1) / ty;
+    const long ne = (long)(w + 2 * S) * (h + 2 * S);
+    const int ept = (int)((ne + B - 1) / B);
+    const size_t lds = (size_t)2 * ne * sizeof(double);
+    const bool fits = tx * ty <= B && ept <= 3 && lds + 20 * 1024 <= 64 * 1024 &&
+                      (long)ntx * nty <= ctx->num_cus;
+    if (fits) {
+      best.ok = true;
+      best.tx = tx;
+      best.ty = ty;
+      best.ntx = ntx;
+      best.nty = nty;
+      best.ept = ept;
+      best.lds = lds;
+      return best;
+    }
+    if (ctx->tile_override_x > 0) return best;
   }
-  return cache[kind];
+  return best;
 }
 
-// ---- power iteration ---------------------------------------------------
-void run_power(lj_context* ctx, const OpDev& op, int iters, uint64_t seed, const double* start, hipStream_t s) {
-  void* fn = power_kernel_ptr(op.kind);
-  const int occ = occupancy(ctx, fn, ctx->occ_power, op.kind);
-  const int G = grid_for(ctx, occ, op.npts);
-  ensure_small(ctx, G);
-  const size_t n = nvals(op);
-  PowerParams P;
-  P.op = op;
-  P.iters = iters;
-  P.seed = seed;
-  P.start = start;
-  P.buf0 = slot(ctx, W_Y0, n);
-  P.buf1 = slot(ctx, W_Y1, n);
-  P.partials = ctx->d_partials;
-  P.barrier = ctx->d_barrier;
-  P.scal = ctx->d_scal;
-  HIPCHK(ctx, launch_fill_u32(ctx->d_barrier, kBarrierWords, 0u, s));
-  void* args[] = {&P};
-  if (ctx->timing) HIPCHK(ctx, hipEventRecord(ctx->ev[2], s));
-  HIPCHK(ctx, hipLaunchCooperativeKernel(fn, dim3(G), dim3(persistent_block()), args, 0, s));
-  if (ctx->timing) {
-    HIPCHK(ctx, hipEventRecord(ctx->ev[3], s));
-    HIPCHK(ctx, hipEventSynchronize(ctx->ev[3]));
-    float ms = 0.f;
-    HIPCHK(ctx, hipEventElapsedTime(&ms, ctx->ev[2], ctx->ev[3]));
-    ctx->tm.power_launches += 1;
-    ctx->tm.power_ms += ms;
-    ctx->tm.power_point_iters += (int64_t)iters * op.npts;
-  }
-}
-
-// ---- one Newton recurrence (divided differences + fused kernel) ---------
-struct RecOut {
+// ---- one phi-action launch ------------------------------------------------
+struct ActOut {
   int state[kMaxK];
   int m_star[kMaxK];
   double err[kMaxK];
   int iters;
+  int power_iters;
+  double lam, c, gamma, vnorm;
 };
 
-RecOut run_recurrence(lj_context* ctx, const OpDev& op, const double* v, int K, const int* l,
-                      const double* s_k, double lam_host, double* const* outs, const Opts& o,
-                      double tol, hipStream_t s) {
-  DDParams D;
-  D.K = K;
-  for (int k = 0; k < kMaxK; ++k) {
-    D.l[k] = (k < K) ? l[k] : 0;
-    D.s[k] = (k < K) ? s_k[k] : 0.0;
-  }
-  D.npts = o.max_points + 1;
-  D.lam_host = lam_host;
-  D.safety = o.safety;
-  D.use_cg = 0;
-  D.c_in = 0.0;
-  D.gamma_in = 0.0;
-  D.xi = ctx->d_xi;
-  D.scal = ctx->d_scal;
-  D.coef = ctx->d_coef;
-  D.fmax = ctx->d_fmax;
-  HIPCHK(ctx, launch_divdiff(D, s));
-
-  void* fn = leja_kernel_ptr(op.kind);
-  const int occ = occupancy(ctx, fn, ctx->occ_leja, op.kind);
-  const int G = grid_for(ctx, occ, op.npts);
-  ensure_small(ctx, G);
+// K accumulators phi_{l_k}(s_k J) v (K = 0: power iteration only).  The bound
+// is lam_host when > 0, else the power iteration runs inside the launch.
+ActOut run_action(lj_context* ctx, const OpDev& op, const double* v, int K, const int* l, const double* s_k,
+                  double lam_host, uint64_t seed, const double* start, double* const* outs, const Opts& o,
+                  double tol, hipStream_t s) {
   const size_t n = nvals(op);
-  LejaParams P;
+  ActionParams P;
+  std::memset(&P, 0, sizeof(P));
   P.op = op;
+  P.do_power = lam_host > 0.0 ? 0 : 1;
+  P.power_iters = o.power_iters;
+  P.seed = seed;
+  P.start = start;
+  P.lam_in = lam_host;
+  P.safety = o.safety;
   P.v = v;
-  P.ybuf0 = slot(ctx, W_Y0, n);
-  P.ybuf1 = slot(ctx, W_Y1, n);
-  for (int k = 0; k < kMaxK; ++k) P.p[k] = (k < K) ? outs[k] : nullptr;
   P.K = K;
+  for (int k = 0; k < kMaxK; ++k) {
+    P.l[k] = (k < K) ? l[k] : 0;
+    P.s[k] = (k < K) ? s_k[k] : 0.0;
+    P.p[k] = (k < K) ? outs[k] : nullptr;
+  }
   P.max_points = o.max_points;
   P.relative = o.relative;
   P.tol = tol;
   P.hump = o.hump;
-  P.coef = ctx->d_coef;
-  P.fmax = ctx->d_fmax;
   P.xi = ctx->d_xi;
-  P.scal = ctx->d_scal;
-  P.partials = ctx->d_partials;
-  P.barrier = ctx->d_barrier + kBarrierWords;
+  P.ybuf0 = slot(ctx, W_Y0, n);
+  P.ybuf1 = slot(ctx, W_Y1, n);
+  P.barrier = ctx->d_barrier;
   P.status = ctx->d_status;
-  HIPCHK(ctx, launch_fill_u32(ctx->d_barrier + kBarrierWords, kBarrierWords, 0u, s));
+  const TilePlan tp = tile_plan(ctx, op);
+  void* fn = nullptr;
+  int G = 0;
+  size_t dyn = 0;
+  if (tp.ok) {
+    fn = action_tile_ptr(op.kind, tp.ept);
+    P.tx = tp.tx;
+    P.ty = tp.ty;
+    P.ntx = tp.ntx;
+    P.nty = tp.nty;
+    G = tp.ntx * tp.nty;
+    dyn = tp.lds;
+  } else {
+    fn = action_stream_ptr(op.kind);
+    G = grid_for(ctx, op.npts);
+  }
+  ensure_small(ctx, G);
+  P.partials = ctx->d_partials;
   void* args[] = {&P};
   if (ctx->timing) HIPCHK(ctx, hipEventRecord(ctx->ev[0], s));
-  HIPCHK(ctx, hipLaunchCooperativeKernel(fn, dim3(G), dim3(persistent_block()), args, 0, s));
+  HIPCHK(ctx, hipLaunchCooperativeKernel(fn, dim3(G), dim3(persistent_block()), args, (unsigned)dyn, s));
   if (ctx->timing) HIPCHK(ctx, hipEventRecord(ctx->ev[1], s));
   HIPCHK(ctx, hipMemcpyAsync(ctx->h_status, ctx->d_status, sizeof(LejaStatus), hipMemcpyDeviceToHost, s));
   HIPCHK(ctx, hipStreamSynchronize(s));
-  RecOut r;
+  const LejaStatus& S = *ctx->h_status;
+  ActOut r;
   for (int k = 0; k < kMaxK; ++k) {
-    r.state[k] = ctx->h_status->state[k];
-    r.m_star[k] = ctx->h_status->m_star[k];
-    r.err[k] = ctx->h_status->err[k];
+    r.state[k] = S.state[k];
+    r.m_star[k] = S.m_star[k];
+    r.err[k] = S.err[k];
   }
-  r.iters = ctx->h_status->iters;
+  r.iters = S.iters;
+  r.power_iters = S.power_iters;
+  r.lam = S.lam;
+  r.c = S.c;
+  r.gamma = S.gamma;
+  r.vnorm = S.vnorm;
   if (ctx->timing) {
     float ms = 0.f;
     HIPCHK(ctx, hipEventElapsedTime(&ms, ctx->ev[0], ctx->ev[1]));
     ctx->tm.launches += 1;
-    ctx->tm.iterations += r.iters;
-    ctx->tm.point_iters += (int64_t)r.iters * op.npts;
-    ctx->tm.accum_point_iters += (int64_t)ctx->h_status->accum_iters * op.npts;
+    ctx->tm.iterations += S.iters;
+    ctx->tm.point_iters += (int64_t)S.iters * op.npts;
+    ctx->tm.accum_point_iters += (int64_t)S.accum_iters * op.npts;
+    ctx->tm.power_point_iters += (int64_t)S.power_iters * op.npts;
+    ctx->tm.tiled_launches += tp.ok ? 1 : 0;
     ctx->tm.kernel_ms += ms;
   }
   return r;
+}
+
+double run_bound(lj_context* ctx, const OpDev& op, const Opts& o, int iters, uint64_t seed, const double* start,
+                 hipStream_t s) {
+  Opts q = o;
+  q.power_iters = iters;
+  ActOut r = run_action(ctx, op, nullptr, 0, nullptr, nullptr, 0.0, seed, start, nullptr, q, 1.0, s);
+  return r.lam;
 }
 
 void lincomb(lj_context* ctx, size_t n, double* out, int nin, const double* alpha, const double* const* x,
@@ -365,7 +385,7 @@ double factorial(int k) {
 // w(t + tau) = e^{tau J} w(t) + sum_j tau^j t^{l-j}/(l-j)! phi_j(tau J) v for
 // w(t) = t^l phi_l(t J) v, scaled by T^l).  Returns true on success.
 bool substepped(lj_context* ctx, const OpDev& op, const double* v, int l, double T, int s_start,
-                double lam_host, const Opts& o, double tol, double* w_out, lj_stats* st, int k,
+                double lam, const Opts& o, double tol, double* w_out, lj_stats* st, int k,
                 hipStream_t strm) {
   const size_t n = nvals(op);
   int s = s_start;
@@ -379,7 +399,7 @@ bool substepped(lj_context* ctx, const OpDev& op, const double* v, int l, double
         double* out = (i == s - 1) ? w_out : slot(ctx, (i & 1) ? W_SW1 : W_SW0, n);
         const int l0 = 0;
         const double sk = tau;
-        RecOut r = run_recurrence(ctx, op, in, 1, &l0, &sk, lam_host, &out, o, tol, strm);
+        ActOut r = run_action(ctx, op, in, 1, &l0, &sk, lam, 0, nullptr, &out, o, tol, strm);
         used += r.iters;
         if (r.state[0] != ACC_CONVERGED) ok = false;
         in = out;
@@ -393,7 +413,7 @@ bool substepped(lj_context* ctx, const OpDev& op, const double* v, int l, double
         ls[j] = j + 1;
         ss[j] = tau;
       }
-      RecOut r = run_recurrence(ctx, op, v, l, ls, ss, lam_host, P, o, tol, strm);
+      ActOut r = run_action(ctx, op, v, l, ls, ss, lam, 0, nullptr, P, o, tol, strm);
       used += r.iters;
       for (int j = 0; j < l; ++j)
         if (r.state[j] != ACC_CONVERGED) ok = false;
@@ -408,7 +428,7 @@ bool substepped(lj_context* ctx, const OpDev& op, const double* v, int l, double
           double* e = slot(ctx, W_SE, n);
           const int l0 = 0;
           const double sk = tau;
-          RecOut r2 = run_recurrence(ctx, op, cur, 1, &l0, &sk, lam_host, &e, o, tol, strm);
+          ActOut r2 = run_action(ctx, op, cur, 1, &l0, &sk, lam, 0, nullptr, &e, o, tol, strm);
           used += r2.iters;
           if (r2.state[0] != ACC_CONVERGED) {
             ok = false;
@@ -442,14 +462,6 @@ bool substepped(lj_context* ctx, const OpDev& op, const double* v, int l, double
   return false;
 }
 
-void read_scalars(lj_context* ctx, lj_stats* st, hipStream_t s) {
-  HIPCHK(ctx, hipMemcpyAsync(ctx->h_scal, ctx->d_scal, sizeof(Scalars), hipMemcpyDeviceToHost, s));
-  HIPCHK(ctx, hipStreamSynchronize(s));
-  st->bound = ctx->h_scal->lam;
-  st->c = ctx->h_scal->c;
-  st->gamma = ctx->h_scal->gamma;
-}
-
 // Vertical action (the core of lj_phi_action / lj_phi_vertical / lj_step).
 int vertical_impl(lj_context* ctx, const OpDev& op, const double* v, int K, const int* l, const double* a,
                   double h, double tol, double* const* w, const Opts& o, lj_stats* st, hipStream_t s) {
@@ -458,20 +470,19 @@ int vertical_impl(lj_context* ctx, const OpDev& op, const double* v, int K, cons
     st->m_star[k] = -1;
     st->substeps[k] = 1;
   }
-  double lam_host = 0.0;
-  if (o.bound > 0.0) {
-    lam_host = o.bound;
-  } else {
-    run_power(ctx, op, o.power_iters, o.seed, o.pi_start, s);
-    st->power_iters = o.power_iters;
-  }
+  double lam = o.bound > 0.0 ? o.bound : 0.0;
   int s0 = (o.substeps > 1) ? o.substeps : 1;
   std::vector<int> pending;
   if (s0 == 1) {
     double sk[kMaxK];
     for (int k = 0; k < K; ++k) sk[k] = a[k] * h;
-    RecOut r = run_recurrence(ctx, op, v, K, l, sk, lam_host, w, o, tol, s);
+    ActOut r = run_action(ctx, op, v, K, l, sk, lam, o.seed, o.pi_start, w, o, tol, s);
+    st->power_iters = r.power_iters;
     st->iters_total += r.iters;
+    lam = r.lam;
+    st->bound = r.lam;
+    st->c = r.c;
+    st->gamma = r.gamma;
     for (int k = 0; k < K; ++k) {
       if (r.state[k] == ACC_CONVERGED) {
         st->m_star[k] = r.m_star[k];
@@ -483,14 +494,26 @@ int vertical_impl(lj_context* ctx, const OpDev& op, const double* v, int K, cons
     if (!pending.empty()) st->rejections += 1;
     s0 = 2;
   } else {
+    if (!(lam > 0.0)) {
+      lam = run_bound(ctx, op, o, o.power_iters, o.seed, o.pi_start, s);
+      st->power_iters = o.power_iters;
+    }
+    double c = 0.0, gamma = 0.0;
+    {
+      const double alpha = -o.safety * lam;
+      c = 0.5 * (alpha + 0.0);
+      gamma = 0.25 * (0.0 - alpha);
+    }
+    st->bound = lam;
+    st->c = c;
+    st->gamma = gamma;
     for (int k = 0; k < K; ++k) pending.push_back(k);
   }
   bool all_ok = true;
   for (int k : pending) {
-    if (!substepped(ctx, op, v, l[k], a[k] * h, s0, lam_host, o, tol, w[k], st, k, s)) all_ok = false;
+    if (!substepped(ctx, op, v, l[k], a[k] * h, s0, lam, o, tol, w[k], st, k, s)) all_ok = false;
   }
   st->converged = all_ok ? 1 : 0;
-  read_scalars(ctx, st, s);
   return all_ok ? LJ_OK : LJ_ENOTCONV;
 }
 
@@ -594,15 +617,21 @@ LJ_API int lj_create(lj_context** out, int hip_device) {
     HIPCHK(ctx, hipMemcpy(ctx->d_xi, xi, kTable * sizeof(double), hipMemcpyHostToDevice));
     HIPCHK(ctx, hipMalloc(&ctx->d_coef, kMaxK * kTable * sizeof(double)));
     HIPCHK(ctx, hipMalloc(&ctx->d_fmax, kMaxK * sizeof(double)));
-    HIPCHK(ctx, hipMalloc(&ctx->d_scal, sizeof(Scalars)));
-    HIPCHK(ctx, hipMalloc(&ctx->d_barrier, 2 * kBarrierWords * sizeof(unsigned int)));
+    HIPCHK(ctx, hipMalloc(&ctx->d_barrier, kBarrierWords * sizeof(unsigned int)));
+    HIPCHK(ctx, hipMemset(ctx->d_barrier, 0, kBarrierWords * sizeof(unsigned int)));
     HIPCHK(ctx, hipMalloc(&ctx->d_status, sizeof(LejaStatus)));
     HIPCHK(ctx, hipHostMalloc(&ctx->h_status, sizeof(LejaStatus), hipHostMallocDefault));
-    HIPCHK(ctx, hipHostMalloc(&ctx->h_scal, sizeof(Scalars), hipHostMallocDefault));
     HIPCHK(ctx, hipHostMalloc(&ctx->h_coef, kMaxK * kTable * sizeof(double), hipHostMallocDefault));
-    HIPCHK(ctx, hipMemset(ctx->d_scal, 0, sizeof(Scalars)));
     for (int i = 0; i < 4; ++i) HIPCHK(ctx, hipEventCreate(&ctx->ev[i]));
     if (const char* g = std::getenv("LJ_GRID")) ctx->grid_override = std::atoi(g);
+    if (const char* g = std::getenv("LJ_NO_TILE")) ctx->force_stream = std::atoi(g);
+    if (const char* g = std::getenv("LJ_TILE")) {
+      int tx = 0, ty = 0;
+      if (std::sscanf(g, "%d,%d", &tx, &ty) == 2 && tx > 0 && ty > 0) {
+        ctx->tile_override_x = tx;
+        ctx->tile_override_y = ty;
+      }
+    }
   } catch (const Fail& f) {
     g_create_error = ctx->err;
     lj_destroy(ctx);
@@ -621,12 +650,10 @@ LJ_API void lj_destroy(lj_context* ctx) {
   if (ctx->d_xi) (void)hipFree(ctx->d_xi);
   if (ctx->d_coef) (void)hipFree(ctx->d_coef);
   if (ctx->d_fmax) (void)hipFree(ctx->d_fmax);
-  if (ctx->d_scal) (void)hipFree(ctx->d_scal);
   if (ctx->d_partials) (void)hipFree(ctx->d_partials);
   if (ctx->d_barrier) (void)hipFree(ctx->d_barrier);
   if (ctx->d_status) (void)hipFree(ctx->d_status);
   if (ctx->h_status) (void)hipHostFree(ctx->h_status);
-  if (ctx->h_scal) (void)hipHostFree(ctx->h_scal);
   if (ctx->h_coef) (void)hipHostFree(ctx->h_coef);
   for (int i = 0; i < 4; ++i)
     if (ctx->ev[i]) (void)hipEventDestroy(ctx->ev[i]);
@@ -640,11 +667,8 @@ LJ_API int lj_spectral_bound(lj_context* ctx, const lj_operator* J, int iters, u
     if (!bound) invalid(ctx, "bound is NULL");
     if (iters < 1 || iters > 100000) invalid(ctx, "iters out of range");
     if (start) check_vec(ctx, op, start, "start");
-    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-    run_power(ctx, op, iters, seed, start, s);
-    HIPCHK(ctx, hipMemcpyAsync(ctx->h_scal, ctx->d_scal, sizeof(Scalars), hipMemcpyDeviceToHost, s));
-    HIPCHK(ctx, hipStreamSynchronize(s));
-    *bound = ctx->h_scal->lam;
+    const Opts o = resolve(ctx, nullptr);
+    *bound = run_bound(ctx, op, o, iters, seed, start, reinterpret_cast<hipStream_t>(stream));
     return LJ_OK;
   });
 }
@@ -663,13 +687,9 @@ LJ_API int lj_divided_differences(lj_context* ctx, int l, double s_, double c, d
     D.l[0] = l;
     D.s[0] = s_;
     D.npts = npts;
-    D.lam_host = 1.0;
-    D.safety = 1.0;
-    D.use_cg = 1;
-    D.c_in = c;
-    D.gamma_in = gamma;
+    D.c = c;
+    D.gamma = gamma;
     D.xi = ctx->d_xi;
-    D.scal = nullptr;
     D.coef = ctx->d_coef;
     D.fmax = ctx->d_fmax;
     HIPCHK(ctx, launch_divdiff(D, s));
@@ -736,10 +756,7 @@ LJ_API int lj_step(lj_context* ctx, int scheme, const lj_operator* J, double h, 
     // one spectral bound for the whole step
     int pit = 0;
     if (!(o.bound > 0.0)) {
-      run_power(ctx, op, o.power_iters, o.seed, o.pi_start, s);
-      HIPCHK(ctx, hipMemcpyAsync(ctx->h_scal, ctx->d_scal, sizeof(Scalars), hipMemcpyDeviceToHost, s));
-      HIPCHK(ctx, hipStreamSynchronize(s));
-      o.bound = ctx->h_scal->lam;
+      o.bound = run_bound(ctx, op, o, o.power_iters, o.seed, o.pi_start, s);
       pit = o.power_iters;
     }
     std::vector<lj_stats> log;
@@ -879,6 +896,24 @@ LJ_API int lj_step(lj_context* ctx, int scheme, const lj_operator* J, double h, 
       for (size_t i = 0; i < log.size(); ++i) stats[i] = log[i];
     return ok ? LJ_OK : LJ_ENOTCONV;
   });
+}
+
+LJ_API int lj_last_trace(lj_context* ctx, double* out, int rows) {
+  if (!ctx || !out || rows < 0) return LJ_EINVAL;
+  const int have = ctx->h_status->iters;
+  const int n = rows < have ? rows : have;
+  for (int m = 0; m < n; ++m)
+    for (int q = 0; q < 1 + kMaxK; ++q) out[m * (1 + kMaxK) + q] = ctx->h_status->trace[m][q];
+  return n;
+}
+
+LJ_API int lj_last_profile(lj_context* ctx, double* us) {
+  if (!ctx || !us) return LJ_EINVAL;
+  int khz = 0;
+  if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, ctx->device) != hipSuccess || khz <= 0)
+    return LJ_EHIP;
+  for (int q = 0; q < 8; ++q) us[q] = (double)ctx->h_status->prof[q] * 1e3 / (double)khz;
+  return LJ_OK;
 }
 
 LJ_API int lj_timing_enable(lj_context* ctx, int enable) {

@@ -42,7 +42,7 @@ def test_struct_layout_matches_c(tmp_path):
         "lj_operator": ["kind", "nx", "dx", "coef", "state"],
         "lj_options": ["safety", "power_iters", "hump_max", "bound", "substeps", "power_seed", "pi_start"],
         "lj_stats": ["m_star", "substeps", "err_est", "iters_total", "converged", "bound", "gamma"],
-        "lj_timing": ["launches", "kernel_ms", "power_ms", "power_point_iters"],
+        "lj_timing": ["launches", "power_point_iters", "tiled_launches", "kernel_ms"],
     }
     lines = ['#include <stdio.h>', '#include <stddef.h>', f'#include "{HEADER}"', "int main(void){"]
     for s, fs in fields.items():
