@@ -207,10 +207,11 @@ typedef struct {
 LJ_API int lj_last_trace(lj_context* ctx, double* out, int rows);
 
 /* Diagnostics: where block 0 of the last action launch spent its time, in
- * microseconds of the device wall clock: us[0] set-up, [1] power iteration,
- * [2] divided differences, [3] Newton steps, [4] publishing partial sums,
- * [5] waiting in grid barriers, [6] reductions and stop decisions, [7] halo
- * reloads (LDS-tiled kernel).  us is a host array of 8 doubles. */
+ * microseconds of the device wall clock: us[0] set-up and power iteration,
+ * [1] divided differences, [2] Newton steps, [3] publishing partial sums,
+ * [4] grid barriers with the reduction of the partial sums, [5] stop
+ * decisions, [6] term commits and [7] halo reloads (LDS-tiled kernel).
+ * us is a host array of 8 doubles. */
 LJ_API int lj_last_profile(lj_context* ctx, double* us);
 
 LJ_API int lj_timing_enable(lj_context* ctx, int enable);

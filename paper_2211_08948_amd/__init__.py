@@ -221,7 +221,7 @@ def lj_last_trace(ctx: Context, rows: int = 100):
     return [list(buf[i * (1 + LJ_MAX_K):(i + 1) * (1 + LJ_MAX_K)]) for i in range(n)]
 
 
-PROFILE_PHASES = ("setup", "power", "divdiff", "steps", "publish", "barrier", "decide", "halo")
+PROFILE_PHASES = ("power", "divdiff", "steps", "publish", "barrier", "decide", "commit", "halo")
 
 
 def lj_last_profile(ctx: Context) -> dict:

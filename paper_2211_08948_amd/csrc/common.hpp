@@ -45,7 +45,7 @@ struct LejaStatus {
   unsigned long long prof[8];
 };
 
-enum ProfPhase { kProfSetup = 0, kProfPower, kProfDivdiff, kProfSteps, kProfPublish, kProfBarrier, kProfDecide, kProfHalo };
+enum ProfPhase { kProfPower = 0, kProfDivdiff, kProfSteps, kProfPublish, kProfBarrier, kProfDecide, kProfCommit, kProfHalo };
 
 // Divided differences on their own (the lj_divided_differences entry point).
 struct DDParams {
@@ -84,11 +84,12 @@ struct ActionParams {
   // workspace
   double* ybuf0;          // two device vectors of n entries
   double* ybuf1;
-  double* partials;       // 2 x kPartStride x gridDim, slot-major: [parity][slot][block]
+  double* partials;       // 2 x kPartStride x (gridDim + 16): partial sums and group sums
   unsigned int* barrier;  // kBarrierWords words, zero at launch; left zero at exit
   LejaStatus* status;     // out
   // tiling of the LDS-resident kernel
   int tx, ty, ntx, nty;   // tile size and tiles per axis (gridDim = ntx * nty)
+  int lds_h;              // offset (doubles) of the step history in dynamic LDS
 };
 
 }  // namespace lj

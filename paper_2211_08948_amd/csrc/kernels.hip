@@ -46,74 +46,106 @@ __device__ __forceinline__ void point_range(int npts, int& p0, int& p1) {
   p1 = min(npts, p0 + chunk);
 }
 
-// Partial sums of one barrier slot-set are stored slot-major,
-// part[q * gridDim.x + b] = block b's value of slot q.
-__device__ __forceinline__ double* partial_slots(double* partials, unsigned int epoch) {
-  return partials + (size_t)(epoch & 1u) * kPartStride * gridDim.x;
-}
-
-// Totals of nq <= kPartStride slots over all blocks, summed by every block in
-// the same fixed order: wave w reduces slots w, w + 16, w + 32; lane t adds
-// the blocks t, t + 64, ... of a slot in turn (coalesced loads, all in flight
-// at once), then the wave sums its lanes.  Result in tot[0..nq) (LDS).
-__device__ __forceinline__ void grid_totals(const double* __restrict__ part, int nq, double* tot) {
-  const int G = gridDim.x;
-  const int lane = threadIdx.x & 63;
-  const int wid = threadIdx.x >> 6;
-  double a[3] = {0.0, 0.0, 0.0};
-#pragma unroll
-  for (int i = 0; i < 3; ++i) {
-    const int q = wid + kWaves * i;
-    if (q >= nq) continue;
-    const double* __restrict__ row = part + (size_t)q * G;
-#pragma unroll
-    for (int r = 0; r < 4; ++r)
-      if (lane + 64 * r < G) a[i] += row[lane + 64 * r];
-    for (int b = lane + 256; b < G; b += 64) a[i] += row[b];
-  }
-#pragma unroll
-  for (int i = 0; i < 3; ++i) {
-    const int q = wid + kWaves * i;
-    if (q >= nq) continue;  // uniform per wave
-    const double t = wave_sum(a[i]);
-    if (lane == 0) tot[q] = t;
-  }
-  __syncthreads();
-}
-
 // ---------------------------------------------------------------------------
 // Divided differences of phi_{l_k}(s_k (c + gamma xi_j)), j < n, for K
 // accumulators: wave k computes accumulator k, lane t holding nodes t and t+64.
 // Order by order, d_j <- (d_j - d_{j-1}) / (xi_j - xi_{j-order}) for j >= order
 // (the standard table, Sec. 2.2), with d_{j-1} taken from the neighbouring
-// lane by a DPP wave shift.  Writes coef[k * kTable + j] and fmax[k] = max_j |f_j|.
+// lane by a DPP wave shift.  The quotient is formed as q = t * r with
+// r = 1/den correctly rounded, then corrected once by its exact residual
+// t - q den (an FMA); by Markstein's theorem (r within half an ulp of 1/den,
+// q within one ulp of t/den) the corrected q is the correctly rounded t/den,
+// the same value a division gives.  The reciprocals do not depend on d, so
+// those of the next order are formed while the current order's chain runs.
+//
+// After `order` orders the entries d_0..d_order are final, so the table can be
+// advanced lazily: the Newton step m needs d_m only, and the action kernels
+// advance it a few orders at a time while their blocks wait at a grid
+// barrier.  The state lives in the registers of waves 0..K-1.
 // ---------------------------------------------------------------------------
-__device__ void block_divdiff(int K, const int* l, const double* s, int n, double c, double gamma,
-                              const double* xi, double* coef, double* fmax_out) {
+struct DivDiff {
+  double d0, d1;  // current column at nodes j0 = lane, j1 = lane + 64
+  int order;      // orders done
+  int n;          // nodes
+};
+
+__device__ __forceinline__ void dd_denoms(int n, double x0, double x1, const double* xi, int order, double& den0,
+                                          double& den1) {
+  const int lane = threadIdx.x & 63;
+  const int j0 = lane, j1 = lane + 64;
+  const double xa = xi[min(max(j0 - order, 0), kTable - 1)];
+  const double xb = xi[min(max(j1 - order, 0), kTable - 1)];
+  den0 = (j0 >= order && j0 < n) ? x0 - xa : 1.0;
+  den1 = (j1 >= order && j1 < n) ? x1 - xb : 1.0;
+}
+
+// phi values at the nodes, fmax[k] = max_j |f_j|, coef[k * kTable] = d_0.
+// Called by every thread; waves >= K do nothing.
+__device__ void dd_init(DivDiff& D, int K, const int* l, const double* s, int n, double c, double gamma,
+                        const double* xi, double* coef, double* fmax_out) {
 #pragma clang fp contract(off)
   const int wid = threadIdx.x >> 6;
   const int lane = threadIdx.x & 63;
+  D.order = 0;
+  D.n = n;
+  D.d0 = 0.0;
+  D.d1 = 0.0;
   if (wid >= K) return;
   const int lk = l[wid];
   const double sk = s[wid];
   const int j0 = lane, j1 = lane + 64;
   const double x0 = xi[j0];
   const double x1 = (j1 < kTable) ? xi[j1] : 0.0;
-  double d0 = 0.0, d1 = 0.0;
-  if (j0 < n) d0 = phi_dev(lk, sk * (c + gamma * x0));
-  if (j1 < n) d1 = phi_dev(lk, sk * (c + gamma * x1));
-  const double m = wave_max(fmax(fabs(d0), fabs(d1)));
-  for (int order = 1; order < n; ++order) {
+  if (j0 < n) D.d0 = phi_dev(lk, sk * (c + gamma * x0));
+  if (j1 < n) D.d1 = phi_dev(lk, sk * (c + gamma * x1));
+  const double m = wave_max(fmax(fabs(D.d0), fabs(D.d1)));
+  if (lane == 0) {
+    fmax_out[wid] = m;
+    coef[wid * kTable] = D.d0;
+  }
+}
+
+// Orders up to min(upto, n - 1); writes the entries that became final.
+__device__ void dd_advance(DivDiff& D, int K, int upto, const double* xi, double* coef) {
+#pragma clang fp contract(off)
+  const int wid = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
+  if (wid >= K) return;
+  const int n = D.n;
+  const int last = min(upto, n - 1);
+  if (last <= D.order) return;
+  const int first = D.order + 1;
+  const int j0 = lane, j1 = lane + 64;
+  const double x0 = xi[j0];
+  const double x1 = (j1 < kTable) ? xi[j1] : 0.0;
+  double d0 = D.d0, d1 = D.d1;
+  double den0, den1;
+  dd_denoms(n, x0, x1, xi, first, den0, den1);
+  double r0 = 1.0 / den0, r1 = 1.0 / den1;
+  for (int order = first; order <= last; ++order) {
+    double nden0, nden1;
+    dd_denoms(n, x0, x1, xi, order + 1, nden0, nden1);
+    const double nr0 = 1.0 / nden0, nr1 = 1.0 / nden1;
     const double p0 = wave_shift_up(d0);
     double p1 = wave_shift_up(d1);
     const double last0 = read_lane(d0, 63);
     if (lane == 0) p1 = last0;
-    if (j0 >= order && j0 < n) d0 = (d0 - p0) / (x0 - xi[j0 - order]);
-    if (j1 >= order && j1 < n) d1 = (d1 - p1) / (x1 - xi[j1 - order]);
+    const double t0 = d0 - p0, t1 = d1 - p1;
+    double q0 = t0 * r0, q1 = t1 * r1;
+    q0 = fma(fma(-q0, den0, t0), r0, q0);
+    q1 = fma(fma(-q1, den1, t1), r1, q1);
+    if (j0 >= order && j0 < n) d0 = q0;
+    if (j1 >= order && j1 < n) d1 = q1;
+    den0 = nden0;
+    den1 = nden1;
+    r0 = nr0;
+    r1 = nr1;
   }
-  if (j0 < n) coef[wid * kTable + j0] = d0;
-  if (j1 < n) coef[wid * kTable + j1] = d1;
-  if (lane == 0) fmax_out[wid] = m;
+  D.d0 = d0;
+  D.d1 = d1;
+  D.order = last;
+  if (j0 >= first && j0 <= last) coef[wid * kTable + j0] = d0;
+  if (j1 >= first && j1 <= last) coef[wid * kTable + j1] = d1;
 }
 
 // The interval of Sec. 2.2: alpha = -safety * lambda, beta = 0, c the midpoint,
@@ -164,41 +196,12 @@ __device__ __forceinline__ void decision_init(Decision& D, int K, double nv, dou
   }
 }
 
-// pp[k] = ||p_k||^2 after adding term m; dk[k] = d_{k,m}
-__device__ __forceinline__ void decide_step(Decision& D, int m, double yy, const double* pp, const double* dk,
-                                            double tol, int relative, int max_points) {
-  D.iters = m;
-  D.accum_iters += D.n_active;
-  const double ny = sqrt(yy);
-  int n = 0;
-#pragma unroll
-  for (int k = 0; k < kMaxK; ++k) {
-    if (D.st[k] != ACC_RUNNING) continue;
-    const double e = fabs(dk[k]) * ny;
-    const double np = sqrt(pp[k]);
-    if (!(isfinite(e) && isfinite(np))) {
-      D.st[k] = ACC_NONFINITE;
-    } else if (e > D.hump[k]) {
-      D.st[k] = ACC_HUMP;
-    } else if (e <= (relative ? tol * np : tol)) {
-      D.st[k] = ACC_CONVERGED;
-      D.mst[k] = m;
-      D.err[k] = e;
-    } else if (m == max_points) {
-      D.st[k] = ACC_MAXPTS;
-    } else {
-      ++n;
-    }
-  }
-  D.n_active = n;
-}
-
 // Stop decisions of the steps m0+1 .. m0+steps of one super-step, from the
 // reduced totals tot[(j-1)*kQ + q] of step m0+j, taken by the lanes of one
 // wave in parallel over (step, accumulator).  An accumulator's test at a step
 // depends only on its own state, which does not change until it stops, so its
-// stopping step is the lowest one whose test does not continue; the outcome
-// equals decide_step applied to the steps in order.  D is in LDS; commit[k]
+// stopping step is the lowest one whose test does not continue, exactly as if
+// the steps were decided one after another.  D is in LDS; commit[k]
 // (LDS) receives how many of the super-step's terms accumulator k adds; trace
 // (optional) receives the totals of the steps that were decided.  Called by
 // all 64 lanes of one wave, with steps <= 16.
@@ -339,13 +342,12 @@ __global__ __launch_bounds__(kBlock) void lj_action_stream(ActionParams P) {
       wred[0] = a0;
       wred[1] = a1;
       block_sum<kQ>(wred, sh.red);
-      double* part = partial_slots(P.partials, epoch);
+      double* area = partial_area(P.partials, epoch);
       if (threadIdx.x == 0) {
-        put_partial(part + blockIdx.x, wred[0]);
-        put_partial(part + gridDim.x + blockIdx.x, wred[1]);
+        put_partial(my_partial(area, 0), wred[0]);
+        put_partial(my_partial(area, 1), wred[1]);
       }
-      grid_barrier(P.barrier, epoch);
-      grid_totals(part, 2, sh.tot);
+      grid_allreduce(P.barrier, epoch, area, 2, sh.tot);
       const double nx = sqrt(sh.tot[0]);
       const double ny = sqrt(sh.tot[1]);
       lam = ny / nx;
@@ -357,6 +359,7 @@ __global__ __launch_bounds__(kBlock) void lj_action_stream(ActionParams P) {
       scale = 1.0 / ny;
     }
   }
+  lam = uniform(lam);
   double c, gamma;
   interval(lam, P.safety, c, gamma);
   tick(kProfPower);
@@ -370,9 +373,12 @@ __global__ __launch_bounds__(kBlock) void lj_action_stream(ActionParams P) {
     return;
   }
 
-  // (2) divided differences, every block for itself
+  // (2) divided differences, every block for itself: d_0, d_1 now, then one
+  // order more while each step's barrier is pending
   __syncthreads();
-  block_divdiff(K, P.l, P.s, P.max_points + 1, c, gamma, sh.xi, sh.coef, sh.fmax);
+  DivDiff dd;
+  dd_init(dd, K, P.l, P.s, P.max_points + 1, c, gamma, sh.xi, sh.coef, sh.fmax);
+  dd_advance(dd, K, 1, sh.xi, sh.coef);
   __syncthreads();
   tick(kProfDivdiff);
 
@@ -394,27 +400,28 @@ __global__ __launch_bounds__(kBlock) void lj_action_stream(ActionParams P) {
     for (int q = 0; q < kQ; ++q) wred[q] = 0.0;
     wred[0] = a0;
     block_sum<kQ>(wred, sh.red);
-    if (threadIdx.x == 0) put_partial(partial_slots(P.partials, epoch) + blockIdx.x, wred[0]);
+    if (threadIdx.x == 0) put_partial(my_partial(partial_area(P.partials, epoch), 0), wred[0]);
   }
-  {
-    const double* part = partial_slots(P.partials, epoch);
-    grid_barrier(P.barrier, epoch);
-    grid_totals(part, 1, sh.tot);
-  }
+  grid_allreduce(P.barrier, epoch, partial_area(P.partials, epoch), 1, sh.tot,
+                 [&] { dd_advance(dd, K, 2, sh.xi, sh.coef); });
   const double nv = sqrt(sh.tot[0]);
-  Decision D;
-  decision_init(D, K, nv, P.hump, sh.fmax);
+  // The decision state is the same in every thread, so it lives once per block
+  // in LDS: wave 0 takes the decisions, everyone reads the outcome.
+  __shared__ Decision sD;
+  __shared__ int s_commit[kMaxK];
+  if (threadIdx.x < 64) decision_init(sD, K, nv, P.hump, sh.fmax);
+  __syncthreads();
 
-  for (int m = 1; m <= P.max_points && D.n_active > 0; ++m) {
+  for (int m = 1; m <= P.max_points && uniform(sD.n_active) > 0; ++m) {
     const double* __restrict__ src = (m == 1) ? P.v : ((m & 1) ? P.ybuf0 : P.ybuf1);
     double* __restrict__ dst = (m & 1) ? P.ybuf1 : P.ybuf0;
-    const double xim = sh.xi[m - 1];
+    const double xim = uniform(sh.xi[m - 1]);
     double dk[kMaxK];
     bool act[kMaxK];
 #pragma unroll
     for (int k = 0; k < kMaxK; ++k) {
-      act[k] = (k < K) && (D.st[k] == ACC_RUNNING);
-      dk[k] = act[k] ? sh.coef[k * kTable + m] : 0.0;
+      act[k] = (k < K) && (uniform(sD.st[k]) == ACC_RUNNING);
+      dk[k] = act[k] ? uniform(sh.coef[k * kTable + m]) : 0.0;
     }
     double acc[kQ] = {0.0, 0.0, 0.0, 0.0, 0.0};
     for (int p = p0 + (int)threadIdx.x; p < p1; p += blockDim.x) {
@@ -438,22 +445,22 @@ __global__ __launch_bounds__(kBlock) void lj_action_stream(ActionParams P) {
     }
     tick(kProfSteps);
     block_sum<kQ>(acc, sh.red);
-    double* part = partial_slots(P.partials, epoch);
+    double* area = partial_area(P.partials, epoch);
     if (threadIdx.x == 0) {
 #pragma unroll
-      for (int q = 0; q < kQ; ++q) put_partial(part + q * gridDim.x + blockIdx.x, acc[q]);
+      for (int q = 0; q < kQ; ++q) put_partial(my_partial(area, q), acc[q]);
     }
     tick(kProfPublish);
-    grid_barrier(P.barrier, epoch);
+    grid_allreduce(P.barrier, epoch, area, kQ, sh.tot, [&] { dd_advance(dd, K, m + 2, sh.xi, sh.coef); });
     tick(kProfBarrier);
-    grid_totals(part, kQ, sh.tot);
-    if (blockIdx.x == 0 && threadIdx.x == 0)
-      for (int q = 0; q < kQ; ++q) P.status->trace[m - 1][q] = sh.tot[q];
-    decide_step(D, m, sh.tot[0], sh.tot + 1, dk, P.tol, P.relative, P.max_points);
+    if (threadIdx.x < 64)
+      replay_decisions(sD, K, m - 1, 1, sh.tot, sh.coef, P.tol, P.relative, P.max_points, s_commit,
+                       blockIdx.x == 0 ? P.status->trace : nullptr);
+    __syncthreads();
     tick(kProfDecide);
   }
   if (blockIdx.x == 0 && threadIdx.x == 0) {
-    write_status(P.status, D, pit, (int)epoch, nv, lam, c, gamma);
+    write_status(P.status, sD, pit, (int)epoch, nv, lam, c, gamma);
     for (int q = 0; q < 8; ++q) P.status->prof[q] = prof[q];
   }
   grid_exit(P.barrier);
@@ -479,7 +486,10 @@ __global__ __launch_bounds__(kBlock) void lj_action_tile(ActionParams P) {
   const int x0 = (tb % P.ntx) * P.tx, y0 = (tb / P.ntx) * P.ty;
   const int w = min(P.tx, nx - x0), h = min(P.ty, ny - y0);
   const int EW = w + 2 * S, EH = h + 2 * S, NE = EW * EH;
+  // dynamic LDS: two buffers of the extended tile, then the owned point's
+  // basis values of the current super-step, H[(j-1) * kBlock + thread]
   double* Y[2] = {lds, lds + NE};
+  double* H = lds + P.lds_h;
   // extended points of this thread: e = threadIdx.x + k * kBlock (valid if < NE),
   // tile coordinates packed as ex | ey << 16, linearisation state in registers
   int e_xy[EPT];
@@ -564,21 +574,20 @@ __global__ __launch_bounds__(kBlock) void lj_action_tile(ActionParams P) {
   // block totals of staged slots [0, nslots) -> this barrier's partials
   auto publish = [&](int nslots) {
     __syncthreads();
-    double* part = partial_slots(P.partials, epoch);
+    double* area = partial_area(P.partials, epoch);
     if ((int)threadIdx.x < nslots) {
       double t = 0.0;
 #pragma unroll
       for (int wv = 0; wv < kWaves; ++wv) t += sh.red[threadIdx.x * kWaves + wv];
-      put_partial(part + threadIdx.x * gridDim.x + blockIdx.x, t);
+      put_partial(my_partial(area, threadIdx.x), t);
     }
     __syncthreads();
-    return part;
+    return area;
   };
 
   // ---- (1) spectral bound: S products between barriers, normalised per barrier
   double lam = P.lam_in;
   int pit = 0;
-  tick(kProfSetup);
   if (P.do_power) {
 #pragma unroll
     for (int k = 0; k < EPT; ++k) {
@@ -600,10 +609,9 @@ __global__ __launch_bounds__(kBlock) void lj_action_tile(ActionParams P) {
         const double y = own ? Y[cur][eo] : 0.0;
         stage(j, y * y);
       }
-      double* part = publish(steps + 1);
+      double* area = publish(steps + 1);
       if (own) ((par == 0) ? P.ybuf0 : P.ybuf1)[go] = Y[cur][eo];
-      grid_barrier(P.barrier, epoch);
-      grid_totals(part, steps + 1, sh.tot);
+      grid_allreduce(P.barrier, epoch, area, steps + 1, sh.tot);
       const double nprev = sh.tot[steps - 1], nlast = sh.tot[steps];
       done += steps;
       pit = done;
@@ -618,6 +626,7 @@ __global__ __launch_bounds__(kBlock) void lj_action_tile(ActionParams P) {
       }
     }
   }
+  lam = uniform(lam);
   double c, gamma;
   interval(lam, P.safety, c, gamma);
   tick(kProfPower);
@@ -632,9 +641,12 @@ __global__ __launch_bounds__(kBlock) void lj_action_tile(ActionParams P) {
     return;
   }
 
-  // ---- (2) divided differences, and y_0 = v on the extended tile
+  // ---- (2) divided differences up to the first super-step's last term (the
+  // rest while barriers are pending), and y_0 = v on the extended tile
   __syncthreads();
-  block_divdiff(K, P.l, P.s, P.max_points + 1, c, gamma, sh.xi, sh.coef, sh.fmax);
+  DivDiff dd;
+  dd_init(dd, K, P.l, P.s, P.max_points + 1, c, gamma, sh.xi, sh.coef, sh.fmax);
+  dd_advance(dd, K, S, sh.xi, sh.coef);
   cur = 0;
 #pragma unroll
   for (int k = 0; k < EPT; ++k)
@@ -656,12 +668,11 @@ __global__ __launch_bounds__(kBlock) void lj_action_tile(ActionParams P) {
   double nv = 0.0;
   bool first = true;
   int m0 = 0;
-  double hist[S];
   while (true) {
     const int steps = min(S, P.max_points - m0);
     bool act0[kMaxK];
 #pragma unroll
-    for (int k = 0; k < kMaxK; ++k) act0[k] = (k < K) && (sD.st[k] == ACC_RUNNING);
+    for (int k = 0; k < kMaxK; ++k) act0[k] = (k < K) && (uniform(sD.st[k]) == ACC_RUNNING);
     double ps[kMaxK];
 #pragma unroll
     for (int k = 0; k < kMaxK; ++k) ps[k] = pk[k];
@@ -669,25 +680,25 @@ __global__ __launch_bounds__(kBlock) void lj_action_tile(ActionParams P) {
     for (int j = 1; j <= S; ++j) {
       if (j > steps) break;
       const int m = m0 + j;
-      step(j, c, gamma, sh.xi[m - 1], true);
+      step(j, c, gamma, uniform(sh.xi[m - 1]), true);
       const double y = own ? Y[cur][eo] : 0.0;
-      hist[j - 1] = y;
+      H[(j - 1) * kBlock + threadIdx.x] = y;
       stage((j - 1) * kQ, y * y);
 #pragma unroll
       for (int k = 0; k < kMaxK; ++k) {
         if (!act0[k]) continue;
-        ps[k] = ps[k] + sh.coef[k * kTable + m] * y;
+        ps[k] = ps[k] + uniform(sh.coef[k * kTable + m]) * y;
         stage((j - 1) * kQ + 1 + k, ps[k] * ps[k]);
       }
     }
     tick(kProfSteps);
     if (first) stage(kPartStride - 1, v_own * v_own);  // ||v||^2 rides on the first barrier
-    double* part = publish(first ? kPartStride : steps * kQ);
+    const int nq = first ? kPartStride : steps * kQ;
+    double* area = publish(nq);
     if (own) ((par == 0) ? P.ybuf0 : P.ybuf1)[go] = Y[cur][eo];
     tick(kProfPublish);
-    grid_barrier(P.barrier, epoch);
+    grid_allreduce(P.barrier, epoch, area, nq, sh.tot, [&] { dd_advance(dd, K, m0 + steps + S, sh.xi, sh.coef); });
     tick(kProfBarrier);
-    grid_totals(part, first ? kPartStride : steps * kQ, sh.tot);
     if (threadIdx.x < 64) {
       if (first) {
         nv = sqrt(sh.tot[kPartStride - 1]);
@@ -698,16 +709,17 @@ __global__ __launch_bounds__(kBlock) void lj_action_tile(ActionParams P) {
     }
     first = false;
     __syncthreads();
+    tick(kProfDecide);
     // commit each accumulator's terms up to its stop index
 #pragma unroll
     for (int k = 0; k < kMaxK; ++k) {
-      const int ck = s_commit[k];
+      const int ck = uniform(s_commit[k]);
 #pragma unroll
       for (int j = 1; j <= S; ++j)
-        if (j <= ck) pk[k] = pk[k] + sh.coef[k * kTable + m0 + j] * hist[j - 1];
+        if (j <= ck) pk[k] = pk[k] + uniform(sh.coef[k * kTable + m0 + j]) * H[(j - 1) * kBlock + threadIdx.x];
     }
     m0 += steps;
-    tick(kProfDecide);
+    tick(kProfCommit);
     if (sD.n_active == 0 || m0 >= P.max_points) break;
     load_halo((par == 0) ? P.ybuf0 : P.ybuf1, 1.0);
     par ^= 1;
@@ -727,7 +739,7 @@ __global__ __launch_bounds__(kBlock) void lj_action_tile(ActionParams P) {
 
 // ---------------------------------------------------------------------------
 // Stand-alone divided differences (the lj_divided_differences entry point);
-// the same block_divdiff the action kernels run.
+// the same dd_init / dd_advance the action kernels run.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void lj_divdiff_kernel(DDParams P) {
   __shared__ double xi[kTable];
@@ -735,7 +747,9 @@ __global__ __launch_bounds__(256) void lj_divdiff_kernel(DDParams P) {
   __shared__ double fm[kMaxK];
   for (int i = threadIdx.x; i < kTable; i += blockDim.x) xi[i] = P.xi[i];
   __syncthreads();
-  block_divdiff(P.K, P.l, P.s, P.npts, P.c, P.gamma, xi, coef, fm);
+  DivDiff dd;
+  dd_init(dd, P.K, P.l, P.s, P.npts, P.c, P.gamma, xi, coef, fm);
+  dd_advance(dd, P.K, P.npts - 1, xi, coef);
   __syncthreads();
   for (int i = threadIdx.x; i < P.K * kTable; i += blockDim.x) P.coef[i] = coef[i];
   if ((int)threadIdx.x < P.K) P.fmax[threadIdx.x] = fm[threadIdx.x];

@@ -32,9 +32,13 @@ enum Slot {
   W_NSLOTS
 };
 
+// LDS held back from the tiled kernel's dynamic allocation for its static arrays
+constexpr size_t kStaticLdsReserve = 20 * 1024;
+
 struct lj_context {
   int device = 0;
   int num_cus = 0;
+  int lds_max = 64 * 1024;  // LDS bytes one workgroup may use
   std::string err;
   double* d_xi = nullptr;
   double* vec[W_NSLOTS] = {};
@@ -198,7 +202,8 @@ void ensure_small(lj_context* ctx, int blocks) {
     if (ctx->d_partials) (void)hipFree(ctx->d_partials);
     ctx->d_partials = nullptr;
     ctx->partial_cap = 0;
-    if (hipMalloc(&ctx->d_partials, (size_t)2 * blocks * kPartStride * sizeof(double)) != hipSuccess) {
+    // two partial-sum areas of kPartStride * (blocks + 16) doubles (see grid_allreduce)
+    if (hipMalloc(&ctx->d_partials, (size_t)2 * (blocks + 16) * kPartStride * sizeof(double)) != hipSuccess) {
       ctx->err = "partials allocation failed";
       throw Fail{LJ_ENOMEM};
     }
@@ -225,7 +230,8 @@ int grid_for(lj_context* ctx, int npts) {
 struct TilePlan {
   bool ok = false;
   int tx = 0, ty = 0, ntx = 0, nty = 0, ept = 0;
-  size_t lds = 0;
+  size_t lds = 0;   // dynamic LDS bytes
+  int lds_h = 0;    // offset of the step history (doubles)
 };
 
 TilePlan tile_plan(lj_context* ctx, const OpDev& op) {
@@ -244,8 +250,9 @@ TilePlan tile_plan(lj_context* ctx, const OpDev& op) {
     const int ntx = (op.nx + tx - 1) / tx, nty = (op.ny + ty - 1) / ty;
     const long ne = (long)(w + 2 * S) * (h + 2 * S);
     const int ept = (int)((ne + B - 1) / B);
-    const size_t lds = (size_t)2 * ne * sizeof(double);
-    const bool fits = tx * ty <= B && ept <= 3 && lds + 20 * 1024 <= 64 * 1024 &&
+    // two extended-tile buffers and S owned values per thread
+    const size_t lds = ((size_t)2 * ne + (size_t)S * B) * sizeof(double);
+    const bool fits = tx * ty <= B && ept <= 3 && lds + kStaticLdsReserve <= (size_t)ctx->lds_max &&
                       (long)ntx * nty <= ctx->num_cus;
     if (fits) {
       best.ok = true;
@@ -255,6 +262,7 @@ TilePlan tile_plan(lj_context* ctx, const OpDev& op) {
       best.nty = nty;
       best.ept = ept;
       best.lds = lds;
+      best.lds_h = (int)(2 * ne);
       return best;
     }
     if (ctx->tile_override_x > 0) return best;
@@ -313,8 +321,11 @@ ActOut run_action(lj_context* ctx, const OpDev& op, const double* v, int K, cons
     P.ty = tp.ty;
     P.ntx = tp.ntx;
     P.nty = tp.nty;
+    P.lds_h = tp.lds_h;
     G = tp.ntx * tp.nty;
     dyn = tp.lds;
+    if (dyn > 64 * 1024)
+      HIPCHK(ctx, hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn));
   } else {
     fn = action_stream_ptr(op.kind);
     G = grid_for(ctx, op.npts);
@@ -605,6 +616,7 @@ LJ_API int lj_create(lj_context** out, int hip_device) {
     hipDeviceProp_t prop;
     HIPCHK(ctx, hipGetDeviceProperties(&prop, hip_device));
     ctx->num_cus = prop.multiProcessorCount;
+    ctx->lds_max = (int)prop.sharedMemPerBlock;
     int coop = 0;
     HIPCHK(ctx, hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, hip_device));
     if (!coop) {
