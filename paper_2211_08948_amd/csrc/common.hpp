@@ -84,7 +84,7 @@ struct ActionParams {
   // workspace
   double* ybuf0;          // two device vectors of n entries
   double* ybuf1;
-  double* partials;       // 2 x kPartStride x (gridDim + 16): partial sums and group sums
+  double* partials;       // 2 x kPartStride x gridDim partial sums, slot-major
   unsigned int* barrier;  // kBarrierWords words, zero at launch; left zero at exit
   LejaStatus* status;     // out
   // tiling of the LDS-resident kernel

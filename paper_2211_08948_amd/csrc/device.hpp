@@ -265,17 +265,19 @@ __device__ __forceinline__ void block_sum(double (&v)[NV], double* red) {
 
 // ---------------------------------------------------------------------------
 // Grid barrier with an all-reduce of per-block partial sums, for a
-// cooperatively launched (co-resident) grid; two-level to match the chip:
-// workgroups are dispatched round-robin over the XCDs, so block b belongs to
-// group g = b % 8 (one group per XCD).  Each block drains its own memory
-// operations and arrives on its group counter.  The group's last arrival (the
-// leader) sums the group's partials slot by slot, in block order, stores the
-// group sums, publishes its XCD's L2 with one agent-scope release, arrives on
-// the global counter and waits for all groups.  After the barrier every block
-// adds the (at most 8) group sums of each slot in group order, so all blocks
-// obtain bit-identical totals.  A per-block release on a flat counter costs
-// one L2 write-back per block, serialised per XCD; a flat reduction makes
-// every block read every block's partials after the barrier.
+// cooperatively launched (co-resident) grid.
+//
+// Everything one block writes for another block to read inside a launch (the
+// Newton basis vectors, halo rows, partial sums) is stored with device-scope
+// stores (store_shared), which write through the XCD's L2 to the device's
+// coherence point.  So a barrier needs no L2 write-back: each block drains its
+// stores (s_waitcnt), and an acquire after the barrier drops the CU's and the
+// L2's stale lines before the block reads what the others wrote.  (A release
+// per block would write back the whole L2 of its XCD, serialised per XCD.)
+// Arrival is two-level to spread the atomic traffic: block b belongs to group
+// g = b % 8 (workgroups are dispatched round-robin over the 8 XCDs, so a group
+// is one XCD); the group's last arrival arrives on the global counter, waits
+// for all groups and raises the group's flag, on which the others wait.
 //
 // Counters are monotonic (barrier e completes at e arrivals per member), so no
 // reset is needed inside a launch; the layout (128-byte spaced words) is
@@ -285,30 +287,24 @@ __device__ __forceinline__ void block_sum(double (&v)[NV], double* red) {
 //   base[32*17]        exit counter (grid_exit)
 // Everything must be zero at launch; grid_exit leaves it zero again.
 //
-// Partial-sum area of one barrier (two alternate, by epoch parity; each
-// kPartStride * (gridDim.x + 16) doubles): block b = i * ng + g stores slot q
-// at [(g * kPartStride + q) * gcap + i], gcap = ceil(G / ng); the group sums
-// follow at [ng * kPartStride * gcap + g * kPartStride + q].
+// Partial sums: two areas alternate by epoch parity, each kPartStride x
+// gridDim.x doubles, slot-major (slot q of block b at [q * gridDim.x + b]).
+// After the barrier every block adds slot q over the blocks in the same fixed
+// order (lane t takes blocks t, t + 64, ..., then the wave sums its lanes), so
+// all blocks obtain bit-identical totals.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ int barrier_groups() { return gridDim.x < 8u ? (int)gridDim.x : 8; }
+__device__ __forceinline__ void store_shared(double* p, double v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
 
 __device__ __forceinline__ double* partial_area(double* partials, unsigned int epoch) {
-  return partials + (size_t)(epoch & 1u) * kPartStride * (gridDim.x + 16);
+  return partials + (size_t)(epoch & 1u) * kPartStride * gridDim.x;
 }
 
 // where this block stores slot q of a partial-sum area
-__device__ __forceinline__ double* my_partial(double* area, int q) {
-  const int ng = barrier_groups();
-  const int gcap = ((int)gridDim.x + ng - 1) / ng;
-  const int g = blockIdx.x % ng, i = blockIdx.x / ng;
-  return area + (size_t)(g * kPartStride + q) * gcap + i;
-}
+__device__ __forceinline__ double* my_partial(double* area, int q) { return area + (size_t)q * gridDim.x + blockIdx.x; }
 
-// Partial sums are stored with agent-scope atomics, written through to memory
-// independent of the L2 write-back; the readers load them after an acquire.
-__device__ __forceinline__ void put_partial(double* p, double v) {
-  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
+__device__ __forceinline__ void put_partial(double* p, double v) { store_shared(p, v); }
 
 struct NoOverlap {
   __device__ void operator()() const {}
@@ -318,68 +314,52 @@ struct NoOverlap {
 // advances its copy (callers pick the partial-sum area with it before the
 // call).  nq slots (nq <= kPartStride) of `area` are reduced into tot[0..nq)
 // (LDS); nq = 0 makes it a plain barrier.  The barrier itself is run by the
-// block's last wave; meanwhile the other waves run `overlap` (work that touches
-// no global memory another block writes before this barrier).
+// first lane of the block's last wave; meanwhile the other waves run `overlap`
+// (work that touches no global memory another block writes before this
+// barrier).
 template <class Overlap = NoOverlap>
 __device__ __forceinline__ void grid_allreduce(unsigned int* base, unsigned int& epoch, double* area, int nq,
                                                double* tot, Overlap&& overlap = Overlap{}) {
   __builtin_amdgcn_s_waitcnt(0);  // this thread's loads and stores have completed
   __syncthreads();
   epoch += 1u;
-  const int G = gridDim.x;
-  const int ng = barrier_groups();
-  const int gcap = (G + ng - 1) / ng;
-  const int g = blockIdx.x % ng;
-  double* gsum = area + (size_t)ng * kPartStride * gcap;
-  if (threadIdx.x >= blockDim.x - 64u) {
-    const int lane = threadIdx.x & 63;
-    const unsigned int gsize = (unsigned int)((G - g + ng - 1) / ng);
+  const unsigned int agent = blockDim.x - 64u;
+  if (threadIdx.x == agent) {
+    const unsigned int G = gridDim.x;
+    const unsigned int ng = G < 8u ? G : 8u;
+    const unsigned int g = blockIdx.x % ng;
+    const unsigned int gsize = (G - g + ng - 1u) / ng;
     unsigned int* gc = base + 32 * (1 + g);
     unsigned int* gf = base + 32 * (9 + g);
-    unsigned int old = 0;
-    if (lane == 0) old = __hip_atomic_fetch_add(gc, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    old = __builtin_amdgcn_readfirstlane(old);
+    const unsigned int old = __hip_atomic_fetch_add(gc, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     if (old == epoch * gsize - 1u) {
-      if (nq > 0) {
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");  // the members' partials
-        if (lane < nq) {
-          const double* __restrict__ row = area + (size_t)(g * kPartStride + lane) * gcap;
-          double t = 0.0;
-#pragma unroll 8
-          for (int i = 0; i < (int)gsize; ++i) t += row[i];
-          put_partial(gsum + g * kPartStride + lane, t);
-        }
+      __hip_atomic_fetch_add(base, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      while (__hip_atomic_load(base, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < epoch * ng) {
+        __builtin_amdgcn_s_sleep(1);
       }
-      if (lane == 0) {
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-        // the release is an L2 write-back; arrive only once it has completed
-        // (the compiler does not wait for it before the next atomic by itself)
-        __asm__ volatile("s_waitcnt vmcnt(0)" ::: "memory");
-        __hip_atomic_fetch_add(base, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        while (__hip_atomic_load(base, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < epoch * (unsigned int)ng) {
-          __builtin_amdgcn_s_sleep(1);
-        }
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-        __hip_atomic_store(gf, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      }
-    } else if (lane == 0) {
+      __hip_atomic_store(gf, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    } else {
       while (__hip_atomic_load(gf, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < epoch) {
         __builtin_amdgcn_s_sleep(1);
       }
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     }
-  } else {
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  } else if (threadIdx.x < agent) {
     overlap();
   }
   __syncthreads();
   if (nq > 0) {
-    // tot[q] = sum of the group sums of slot q in group order; wave w takes
-    // slots w, w + nw, w + 2 nw, ...
+    const int G = gridDim.x;
     const int lane = threadIdx.x & 63;
     const int nw = blockDim.x >> 6;
     for (int q = threadIdx.x >> 6; q < nq; q += nw) {
-      const double v = (lane < ng) ? gsum[lane * kPartStride + q] : 0.0;
-      const double t = wave_sum(v);
+      const double* __restrict__ row = area + (size_t)q * G;
+      double a = 0.0;
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+        if (lane + 64 * r < G) a += row[lane + 64 * r];
+      for (int b = lane + 256; b < G; b += 64) a += row[b];
+      const double t = wave_sum(a);
       if (lane == 0) tot[q] = t;
     }
     __syncthreads();

@@ -197,7 +197,8 @@ __device__ __forceinline__ void decision_init(Decision& D, int K, double nv, dou
 }
 
 // Stop decisions of the steps m0+1 .. m0+steps of one super-step, from the
-// reduced totals tot[(j-1)*kQ + q] of step m0+j, taken by the lanes of one
+// reduced totals tot[(j-1)*Q + q] of step m0+j (Q = 1 + K: ||y||^2, then
+// ||p_k||^2 after the term), taken by the lanes of one
 // wave in parallel over (step, accumulator).  An accumulator's test at a step
 // depends only on its own state, which does not change until it stops, so its
 // stopping step is the lowest one whose test does not continue, exactly as if
@@ -205,7 +206,7 @@ __device__ __forceinline__ void decision_init(Decision& D, int K, double nv, dou
 // (LDS) receives how many of the super-step's terms accumulator k adds; trace
 // (optional) receives the totals of the steps that were decided.  Called by
 // all 64 lanes of one wave, with steps <= 16.
-__device__ void replay_decisions(Decision& D, int K, int m0, int steps, const double* tot, const double* coef,
+__device__ void replay_decisions(Decision& D, int K, int m0, int steps, int Q, const double* tot, const double* coef,
                                  double tol, int relative, int max_points, int* commit,
                                  double (*trace)[1 + kMaxK]) {
   const int lane = threadIdx.x & 63;
@@ -215,9 +216,9 @@ __device__ void replay_decisions(Decision& D, int K, int m0, int steps, const do
   int oc = ACC_RUNNING;
   double e = 0.0;
   if (run0 && j < steps) {
-    const double ny = sqrt(tot[j * kQ]);
+    const double ny = sqrt(tot[j * Q]);
     e = fabs(coef[k * kTable + m]) * ny;
-    const double np = sqrt(tot[j * kQ + 1 + k]);
+    const double np = sqrt(tot[j * Q + 1 + k]);
     if (!(isfinite(e) && isfinite(np))) {
       oc = ACC_NONFINITE;
     } else if (e > D.hump[k]) {
@@ -255,7 +256,10 @@ __device__ void replay_decisions(Decision& D, int K, int m0, int steps, const do
     D.accum_iters += c0 + c1 + c2 + c3;
   }
   if (trace != nullptr) {
-    for (int t = lane; t < cmax * kQ; t += 64) trace[m0 + t / kQ][t % kQ] = tot[t];
+    for (int t = lane; t < cmax * kQ; t += 64) {
+      const int jj = t / kQ, q = t % kQ;
+      trace[m0 + jj][q] = (q < Q) ? tot[jj * Q + q] : 0.0;
+    }
   }
 }
 
@@ -316,7 +320,8 @@ __global__ __launch_bounds__(kBlock) void lj_action_stream(ActionParams P) {
     if (x0 == nullptr) {
       for (int p = p0 + (int)threadIdx.x; p < p1; p += blockDim.x)
 #pragma unroll
-        for (int cc = 0; cc < NC; ++cc) P.ybuf1[NC * p + cc] = 0.5 + splitmix_uniform(P.seed, (uint64_t)(NC * p + cc));
+        for (int cc = 0; cc < NC; ++cc)
+          store_shared(P.ybuf1 + NC * p + cc, 0.5 + splitmix_uniform(P.seed, (uint64_t)(NC * p + cc)));
       x0 = P.ybuf1;
       grid_barrier(P.barrier, epoch);
     }
@@ -332,7 +337,7 @@ __global__ __launch_bounds__(kBlock) void lj_action_stream(ActionParams P) {
         for (int cc = 0; cc < NC; ++cc) {
           const double x = scale * xc[cc];
           const double y = scale * out[cc];
-          dst[NC * p + cc] = y;
+          store_shared(dst + NC * p + cc, y);
           a0 += x * x;
           a1 += y * y;
         }
@@ -431,7 +436,7 @@ __global__ __launch_bounds__(kBlock) void lj_action_stream(ActionParams P) {
       for (int cc = 0; cc < NC; ++cc) {
         const int idx = NC * p + cc;
         const double y = (out[cc] - c * xc[cc]) / gamma - xim * xc[cc];
-        dst[idx] = y;
+        store_shared(dst + idx, y);
         acc[0] += y * y;
 #pragma unroll
         for (int k = 0; k < kMaxK; ++k) {
@@ -448,13 +453,14 @@ __global__ __launch_bounds__(kBlock) void lj_action_stream(ActionParams P) {
     double* area = partial_area(P.partials, epoch);
     if (threadIdx.x == 0) {
 #pragma unroll
-      for (int q = 0; q < kQ; ++q) put_partial(my_partial(area, q), acc[q]);
+      for (int q = 0; q < kQ; ++q)
+        if (q <= K) put_partial(my_partial(area, q), acc[q]);
     }
     tick(kProfPublish);
-    grid_allreduce(P.barrier, epoch, area, kQ, sh.tot, [&] { dd_advance(dd, K, m + 2, sh.xi, sh.coef); });
+    grid_allreduce(P.barrier, epoch, area, 1 + K, sh.tot, [&] { dd_advance(dd, K, m + 2, sh.xi, sh.coef); });
     tick(kProfBarrier);
     if (threadIdx.x < 64)
-      replay_decisions(sD, K, m - 1, 1, sh.tot, sh.coef, P.tol, P.relative, P.max_points, s_commit,
+      replay_decisions(sD, K, m - 1, 1, 1 + K, sh.tot, sh.coef, P.tol, P.relative, P.max_points, s_commit,
                        blockIdx.x == 0 ? P.status->trace : nullptr);
     __syncthreads();
     tick(kProfDecide);
@@ -478,6 +484,7 @@ __global__ __launch_bounds__(kBlock) void lj_action_tile(ActionParams P) {
   __shared__ ActionShared sh;
   const OpDev& op = P.op;
   const int K = P.K;
+  const int Q = 1 + K;  // reduced values per Newton step: ||y||^2, then K ||p_k||^2
   const int nx = op.nx, ny = op.ny;
   for (int i = threadIdx.x; i < kTable; i += blockDim.x) sh.xi[i] = P.xi[i];
 
@@ -610,7 +617,7 @@ __global__ __launch_bounds__(kBlock) void lj_action_tile(ActionParams P) {
         stage(j, y * y);
       }
       double* area = publish(steps + 1);
-      if (own) ((par == 0) ? P.ybuf0 : P.ybuf1)[go] = Y[cur][eo];
+      if (own) store_shared(((par == 0) ? P.ybuf0 : P.ybuf1) + go, Y[cur][eo]);
       grid_allreduce(P.barrier, epoch, area, steps + 1, sh.tot);
       const double nprev = sh.tot[steps - 1], nlast = sh.tot[steps];
       done += steps;
@@ -683,28 +690,28 @@ __global__ __launch_bounds__(kBlock) void lj_action_tile(ActionParams P) {
       step(j, c, gamma, uniform(sh.xi[m - 1]), true);
       const double y = own ? Y[cur][eo] : 0.0;
       H[(j - 1) * kBlock + threadIdx.x] = y;
-      stage((j - 1) * kQ, y * y);
+      stage((j - 1) * Q, y * y);
 #pragma unroll
       for (int k = 0; k < kMaxK; ++k) {
         if (!act0[k]) continue;
         ps[k] = ps[k] + uniform(sh.coef[k * kTable + m]) * y;
-        stage((j - 1) * kQ + 1 + k, ps[k] * ps[k]);
+        stage((j - 1) * Q + 1 + k, ps[k] * ps[k]);
       }
     }
     tick(kProfSteps);
-    if (first) stage(kPartStride - 1, v_own * v_own);  // ||v||^2 rides on the first barrier
-    const int nq = first ? kPartStride : steps * kQ;
+    if (first) stage(steps * Q, v_own * v_own);  // ||v||^2 rides on the first barrier
+    const int nq = steps * Q + (first ? 1 : 0);
     double* area = publish(nq);
-    if (own) ((par == 0) ? P.ybuf0 : P.ybuf1)[go] = Y[cur][eo];
+    if (own) store_shared(((par == 0) ? P.ybuf0 : P.ybuf1) + go, Y[cur][eo]);
     tick(kProfPublish);
     grid_allreduce(P.barrier, epoch, area, nq, sh.tot, [&] { dd_advance(dd, K, m0 + steps + S, sh.xi, sh.coef); });
     tick(kProfBarrier);
     if (threadIdx.x < 64) {
       if (first) {
-        nv = sqrt(sh.tot[kPartStride - 1]);
+        nv = sqrt(sh.tot[steps * Q]);
         decision_init(sD, K, nv, P.hump, sh.fmax);
       }
-      replay_decisions(sD, K, m0, steps, sh.tot, sh.coef, P.tol, P.relative, P.max_points, s_commit,
+      replay_decisions(sD, K, m0, steps, Q, sh.tot, sh.coef, P.tol, P.relative, P.max_points, s_commit,
                        blockIdx.x == 0 ? P.status->trace : nullptr);
     }
     first = false;

@@ -202,8 +202,8 @@ void ensure_small(lj_context* ctx, int blocks) {
     if (ctx->d_partials) (void)hipFree(ctx->d_partials);
     ctx->d_partials = nullptr;
     ctx->partial_cap = 0;
-    // two partial-sum areas of kPartStride * (blocks + 16) doubles (see grid_allreduce)
-    if (hipMalloc(&ctx->d_partials, (size_t)2 * (blocks + 16) * kPartStride * sizeof(double)) != hipSuccess) {
+    // two partial-sum areas of kPartStride * blocks doubles (see grid_allreduce)
+    if (hipMalloc(&ctx->d_partials, (size_t)2 * blocks * kPartStride * sizeof(double)) != hipSuccess) {
       ctx->err = "partials allocation failed";
       throw Fail{LJ_ENOMEM};
     }
