@@ -184,6 +184,62 @@ LJ_API int lj_step(lj_context* ctx, int scheme, const lj_operator* J, double h, 
                    double* u_out, double* err, const lj_options* opt, lj_stats* stats,
                    int nstats, int* ncalls, void* stream);
 
+/* ---- batching form --------------------------------------------------------- */
+
+/* Many independent instances in one launch: for each instance i < n and each
+ * k < K, w[i*K + k] = phi_{l[k]}(a[k] h[i] J_i) v[i] (the vertical form of
+ * Sec. 4 per instance, every step of Sec. 2.2 -- power iteration unless a
+ * bound is given, divided differences, Newton recurrence and stop test -- run
+ * per instance inside one persistent kernel).  A block of the launch takes one
+ * instance at a time from a work queue, so instances of uneven size need no
+ * grid-wide synchronisation.
+ *
+ * lj_batch_create validates every argument, allocates the batch's workspace
+ * (two vectors per instance), times the candidate schedules (threads per
+ * block, blocks per CU, order of the queue) on the batch itself and keeps the
+ * fastest (the choice is cached in the context per batch shape; the timing
+ * runs write the outputs), then captures the launch -- a queue reset and the
+ * kernel -- in a HIP graph.  ops: host array of n operators of ONE family;
+ * v, w: host arrays of device pointers (n and n*K entries); h: host array of n
+ * step sizes; l, a: host arrays of K entries; bounds: host array of n spectral
+ * bounds (> 0: used; 0: power iteration for that instance) or NULL; opt: the
+ * power-iteration, stop and reject settings (NULL = defaults; opt->bound > 0
+ * applies to instances without their own bound).  The buffers must stay valid
+ * while the batch exists.
+ *
+ * lj_batch_run replays the graph on `stream` without synchronising.
+ * lj_batch_stats synchronises `stream`, reads the per-instance outcome into
+ * per_instance (n entries, may be NULL) and redoes every accumulator the batch
+ * rejected with the plain path and substeps (on the bound the batch found),
+ * counting the batch attempt as a rejection; returns LJ_ENOTCONV if some
+ * accumulator still failed.  lj_batch_destroy synchronises the device first. */
+typedef struct lj_batch lj_batch;
+
+typedef struct {
+  int32_t schedule;      /* index of the schedule in use */
+  int32_t block_size;    /* threads per block */
+  int32_t blocks;        /* blocks of the persistent launch */
+  int32_t largest_first; /* 1: the queue hands out the largest instances first */
+  int32_t nschedules;    /* schedules the tuner considered */
+  int32_t pad;
+  float tune_ms[8];      /* tuned time per schedule in ms (0 when the choice came from the cache) */
+  int64_t total_values;  /* sum of the instances' vector lengths */
+  double alg_bytes;      /* algorithmic bytes of the run last read by lj_batch_stats */
+} lj_batch_info_t;
+
+LJ_API int lj_batch_create(lj_context* ctx, const lj_operator* ops, int n, const double* const* v,
+                           const double* h, int K, const int* l, const double* a, double tol,
+                           double* const* w, const double* bounds, const lj_options* opt,
+                           lj_batch** out);
+LJ_API int lj_batch_run(lj_batch* b, void* stream);
+LJ_API int lj_batch_stats(lj_batch* b, lj_stats* per_instance, void* stream);
+LJ_API int lj_batch_info(const lj_batch* b, lj_batch_info_t* out);
+/* Diagnostics of the run last read by lj_batch_stats: for each instance the
+ * block that ran it and its start and end on the device wall clock, in
+ * microseconds after the earliest start (host arrays of n entries). */
+LJ_API int lj_batch_timeline(const lj_batch* b, int* block, double* start_us, double* end_us);
+LJ_API void lj_batch_destroy(lj_batch* b);
+
 /* ---- measurement ------------------------------------------------------------ */
 
 /* Kernel timing of the phi-action kernel.  While enabled, the library

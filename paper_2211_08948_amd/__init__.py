@@ -241,6 +241,78 @@ def lj_timing_read(ctx: Context, reset: bool = False) -> dict:
     return {f: getattr(t, f) for f, _ in t._fields_}
 
 
+class Batch:
+    """A batch of independent instances run in one persistent, graph-captured
+    launch (lj_batch_*).  Keeps the operators, inputs and outputs alive."""
+
+    def __init__(self, ctx: Context, ops: Sequence[Operator], vs: Sequence, hs: Sequence[float],
+                 ls: Sequence[int], As: Sequence[float], tol: float, ws: Sequence[Sequence],
+                 bounds: Sequence[float] | None = None, opt: lj_options | None = None):
+        n, K = len(ops), len(ls)
+        if len(vs) != n or len(hs) != n or len(ws) != n or len(As) != K:
+            raise ValueError("ops, vs, hs and ws need n entries; ls and As K entries")
+        self.ctx, self.n, self.K = ctx, n, K
+        self._keep = (list(ops), list(vs), [list(w) for w in ws])
+        self._ops = (lj_operator * n)(*[J.c_struct() for J in ops])
+        vp = (C.c_void_p * n)(*[_tensor_ptr(v, J.n, f"v[{i}]").value for i, (J, v) in enumerate(zip(ops, vs))])
+        wp = (C.c_void_p * (n * K))()
+        for i, (J, wi) in enumerate(zip(ops, ws)):
+            if len(wi) != K:
+                raise ValueError(f"ws[{i}] needs {K} tensors")
+            for k, w in enumerate(wi):
+                wp[i * K + k] = _tensor_ptr(w, J.n, f"w[{i}][{k}]").value
+        harr = (C.c_double * n)(*[float(x) for x in hs])
+        larr = (C.c_int * K)(*[int(x) for x in ls])
+        aarr = (C.c_double * K)(*[float(x) for x in As])
+        barr = (C.c_double * n)(*[float(x) for x in bounds]) if bounds is not None else None
+        h = C.c_void_p()
+        rc = ctx._lib.lj_batch_create(ctx.handle, self._ops, n, vp, harr, K, larr, aarr, float(tol), wp, barr,
+                                      C.byref(opt) if opt is not None else None, C.byref(h))
+        ctx._check(rc, False)
+        self.handle = h
+
+    def run(self, stream=None) -> None:
+        self.ctx._check(self.ctx._lib.lj_batch_run(self.handle, _stream_ptr(stream)), False)
+
+    def stats(self, stream=None):
+        """Synchronises, returns (rc, per-instance stats dicts); rejected
+        accumulators are redone by the plain path first."""
+        st = (lj_stats * self.n)()
+        rc = self.ctx._lib.lj_batch_stats(self.handle, st, _stream_ptr(stream))
+        self.ctx._check(rc)
+        return rc, [st[i].as_dict(self.K) for i in range(self.n)]
+
+    def info(self) -> dict:
+        i = _lib.lj_batch_info_t()
+        self.ctx._check(self.ctx._lib.lj_batch_info(self.handle, C.byref(i)), False)
+        d = {f: getattr(i, f) for f, _ in i._fields_ if f not in ("pad", "tune_ms")}
+        d["tune_ms"] = list(i.tune_ms)[:i.nschedules]
+        return d
+
+    def timeline(self):
+        """(block, start_us, end_us) per instance of the run last read by stats()."""
+        blk = (C.c_int * self.n)()
+        t0 = (C.c_double * self.n)()
+        t1 = (C.c_double * self.n)()
+        self.ctx._check(self.ctx._lib.lj_batch_timeline(self.handle, blk, t0, t1), False)
+        return list(blk), list(t0), list(t1)
+
+    def close(self) -> None:
+        if getattr(self, "handle", None):
+            self.ctx._lib.lj_batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def lj_batch_create(ctx: Context, ops, vs, hs, ls, As, tol, ws, bounds=None, opt=None) -> Batch:
+    return Batch(ctx, ops, vs, hs, ls, As, tol, ws, bounds, opt)
+
+
 def operator_from(prob, device: str = "cuda") -> Operator:
     """Operator for any object with kind, nx, ny, ncomp, dx, dy, coef and a
     numpy `state` (or None); the state is copied to a float64 device tensor."""

@@ -65,6 +65,14 @@ class lj_timing(C.Structure):
     ]
 
 
+class lj_batch_info_t(C.Structure):
+    _fields_ = [
+        ("schedule", C.c_int32), ("block_size", C.c_int32), ("blocks", C.c_int32),
+        ("largest_first", C.c_int32), ("nschedules", C.c_int32), ("pad", C.c_int32),
+        ("tune_ms", C.c_float * 8), ("total_values", C.c_int64), ("alg_bytes", C.c_double),
+    ]
+
+
 _P = C.c_void_p
 _PROTOS = {
     "lj_create": (C.c_int, [C.POINTER(_P), C.c_int]),
@@ -89,6 +97,14 @@ _PROTOS = {
     "lj_last_profile": (C.c_int, [_P, C.POINTER(C.c_double)]),
     "lj_timing_enable": (C.c_int, [_P, C.c_int]),
     "lj_timing_read": (C.c_int, [_P, C.POINTER(lj_timing), C.c_int]),
+    "lj_batch_create": (C.c_int, [_P, C.POINTER(lj_operator), C.c_int, C.POINTER(_P), C.POINTER(C.c_double),
+                                  C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_double), C.c_double,
+                                  C.POINTER(_P), C.POINTER(C.c_double), C.POINTER(lj_options), C.POINTER(_P)]),
+    "lj_batch_run": (C.c_int, [_P, _P]),
+    "lj_batch_stats": (C.c_int, [_P, C.POINTER(lj_stats), _P]),
+    "lj_batch_info": (C.c_int, [_P, C.POINTER(lj_batch_info_t)]),
+    "lj_batch_timeline": (C.c_int, [_P, C.POINTER(C.c_int), C.POINTER(C.c_double), C.POINTER(C.c_double)]),
+    "lj_batch_destroy": (None, [_P]),
 }
 
 _lib = None

@@ -92,4 +92,48 @@ struct ActionParams {
   int lds_h;              // offset (doubles) of the step history in dynamic LDS
 };
 
+// ---- batching form ---------------------------------------------------------
+// One instance of a batch: its operator, input, outputs and two workspace
+// vectors of its own length (device pointers).
+struct BatchItem {
+  OpDev op;
+  const double* v;
+  double* p[kMaxK];   // outputs phi_{l_k}(s_k J) v
+  double* y0;         // Newton basis / power-iteration double buffer
+  double* y1;
+  double s[kMaxK];    // a_k * h of this instance
+  double lam_in;      // > 0: spectral bound given; else power iteration
+};
+
+// What the batch kernel reports per instance.
+struct BatchStatus {
+  int state[kMaxK];
+  int m_star[kMaxK];
+  double err[kMaxK];
+  int iters;
+  int accum_iters;
+  int power_iters;
+  int block;                   // block that ran the instance
+  double vnorm, lam, c, gamma;
+  unsigned long long t0, t1;   // device wall clock at the start and end of the instance
+};
+
+struct BatchParams {
+  const BatchItem* items;
+  BatchStatus* status;
+  const int* order;       // processing order (a permutation of 0..n-1)
+  int n;
+  int K;
+  int l[kMaxK];
+  int power_iters;
+  uint64_t seed;
+  double safety;
+  int max_points;
+  int relative;
+  double tol;
+  double hump;
+  const double* xi;       // Leja table (device)
+  unsigned int* queue;    // work counter, zero at launch
+};
+
 }  // namespace lj

@@ -77,11 +77,16 @@ __device__ __forceinline__ Nbr neighbours(const OpDev& op, int p) {
   return r;
 }
 
-// (J x)(p) from global memory; xc[] receives x(p) (the recurrence needs it)
+// Gathers what (J x)(p) needs from global memory: x at p and its four
+// neighbours, and the state values the family reads (unused entries zero).
 template <int KIND, int NC>
-__device__ __forceinline__ void jv_point(const OpDev& op, const double* __restrict__ x, int p, double out[2],
-                                         double xc[2]) {
-  double xv[5][2] = {}, uv[5][2] = {};
+__device__ __forceinline__ void gather_point(const OpDev& op, const double* __restrict__ x, int p,
+                                             double (&xv)[5][2], double (&uv)[5][2]) {
+#pragma unroll
+  for (int t = 0; t < 5; ++t) {
+    xv[t][0] = xv[t][1] = 0.0;
+    uv[t][0] = uv[t][1] = 0.0;
+  }
   if constexpr (KIND == OP_DIAG) {
     xv[0][0] = x[p];
     uv[0][0] = op.state[p];
@@ -100,6 +105,14 @@ __device__ __forceinline__ void jv_point(const OpDev& op, const double* __restri
       for (int c = 0; c < NC; ++c) uv[t][c] = op.state[NC * idx[t] + c];
     }
   }
+}
+
+// (J x)(p) from global memory; xc[] receives x(p) (the recurrence needs it)
+template <int KIND, int NC>
+__device__ __forceinline__ void jv_point(const OpDev& op, const double* __restrict__ x, int p, double out[2],
+                                         double xc[2]) {
+  double xv[5][2], uv[5][2];
+  gather_point<KIND, NC>(op, x, p, xv, uv);
   stencil_jv<KIND>(op, xv, uv, out);
 #pragma unroll
   for (int c = 0; c < NC; ++c) xc[c] = xv[0][c];
@@ -163,7 +176,7 @@ __device__ __forceinline__ double phi_series(double z) {
 }
 
 // l in [0, kMaxL]; the callers validate it
-__device__ inline double phi_dev(int l, double z) {
+__device__ __noinline__ double phi_dev(int l, double z) {
   if (fabs(z) <= 2.0) {
     switch (l) {
       case 0: return phi_series<0>(z);

@@ -281,6 +281,96 @@ __device__ __forceinline__ void write_status(LejaStatus* S, const Decision& D, i
   S->gamma = gamma;
 }
 
+// ---------------------------------------------------------------------------
+// Streaming passes over points p = pbeg, pbeg + stride, ... < pend, kUnroll
+// points per thread at a time: every load of those points (stencil values,
+// state, accumulators) is issued before any arithmetic or store, so a thread
+// keeps all of them in flight at once.  The points are visited, and the
+// per-thread sums accumulated, in the same order as a one-point loop.
+// ---------------------------------------------------------------------------
+constexpr int kUnroll = 2;
+
+// y(p) = scale * J x(p); sums of (scale x)^2 and y^2 (power iteration, Sec. 2.2)
+template <int KIND, int NC, bool SHARED>
+__device__ __forceinline__ void power_pass(const OpDev& op, const double* __restrict__ src, double* __restrict__ dst,
+                                           double scale, int pbeg, int pend, int stride, double& a0, double& a1) {
+  for (int p0 = pbeg; p0 < pend; p0 += stride * kUnroll) {
+    double xv[kUnroll][5][2], uv[kUnroll][5][2];
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u)
+      if (p0 + u * stride < pend) gather_point<KIND, NC>(op, src, p0 + u * stride, xv[u], uv[u]);
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) {
+      const int p = p0 + u * stride;
+      if (p >= pend) continue;
+      double out[2];
+      stencil_jv<KIND>(op, xv[u], uv[u], out);
+#pragma unroll
+      for (int cc = 0; cc < NC; ++cc) {
+        const double x = scale * xv[u][0][cc];
+        const double y = scale * out[cc];
+        if constexpr (SHARED) {
+          store_shared(dst + NC * p + cc, y);
+        } else {
+          dst[NC * p + cc] = y;
+        }
+        a0 += x * x;
+        a1 += y * y;
+      }
+    }
+  }
+}
+
+// One Newton step (Sec. 2.2 display): y = ((J - c) x)/gamma - xi x, and for
+// every active accumulator p_k += d_k y; acc[0] += y^2, acc[1+k] += p_k^2.
+template <int KIND, int NC, bool SHARED>
+__device__ __forceinline__ void newton_pass(const OpDev& op, const double* __restrict__ src,
+                                            double* __restrict__ dst, double* const (&pp)[kMaxK],
+                                            const bool (&act)[kMaxK], const double (&dk)[kMaxK], double c,
+                                            double gamma, double xim, int pbeg, int pend, int stride,
+                                            double (&acc)[kQ]) {
+  for (int p0 = pbeg; p0 < pend; p0 += stride * kUnroll) {
+    double xv[kUnroll][5][2], uv[kUnroll][5][2], pv[kUnroll][kMaxK][2];
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) {
+      const int p = p0 + u * stride;
+      if (p >= pend) continue;
+      gather_point<KIND, NC>(op, src, p, xv[u], uv[u]);
+#pragma unroll
+      for (int k = 0; k < kMaxK; ++k)
+#pragma unroll
+        for (int cc = 0; cc < NC; ++cc) pv[u][k][cc] = act[k] ? pp[k][NC * p + cc] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) {
+      const int p = p0 + u * stride;
+      if (p >= pend) continue;
+      double out[2];
+      stencil_jv<KIND>(op, xv[u], uv[u], out);
+#pragma unroll
+      for (int cc = 0; cc < NC; ++cc) {
+        const int idx = NC * p + cc;
+        const double xc = xv[u][0][cc];
+        const double y = (out[cc] - c * xc) / gamma - xim * xc;
+        if constexpr (SHARED) {
+          store_shared(dst + idx, y);
+        } else {
+          dst[idx] = y;
+        }
+        acc[0] += y * y;
+#pragma unroll
+        for (int k = 0; k < kMaxK; ++k) {
+          if (act[k]) {
+            const double pk = pv[u][k][cc] + dk[k] * y;
+            pp[k][idx] = pk;
+            acc[1 + k] += pk * pk;
+          }
+        }
+      }
+    }
+  }
+}
+
 // per-block shared state of both action kernels
 struct ActionShared {
   double xi[kTable];
@@ -330,18 +420,7 @@ __global__ __launch_bounds__(kBlock) void lj_action_stream(ActionParams P) {
       const double* src = (k == 0) ? x0 : ((k & 1) ? P.ybuf0 : P.ybuf1);
       double* dst = (k & 1) ? P.ybuf1 : P.ybuf0;
       double a0 = 0.0, a1 = 0.0;
-      for (int p = p0 + (int)threadIdx.x; p < p1; p += blockDim.x) {
-        double out[2], xc[2];
-        jv_point<KIND, NC>(op, src, p, out, xc);
-#pragma unroll
-        for (int cc = 0; cc < NC; ++cc) {
-          const double x = scale * xc[cc];
-          const double y = scale * out[cc];
-          store_shared(dst + NC * p + cc, y);
-          a0 += x * x;
-          a1 += y * y;
-        }
-      }
+      power_pass<KIND, NC, true>(op, src, dst, scale, p0 + (int)threadIdx.x, p1, blockDim.x, a0, a1);
 #pragma unroll
       for (int q = 0; q < kQ; ++q) wred[q] = 0.0;
       wred[0] = a0;
@@ -429,25 +508,8 @@ __global__ __launch_bounds__(kBlock) void lj_action_stream(ActionParams P) {
       dk[k] = act[k] ? uniform(sh.coef[k * kTable + m]) : 0.0;
     }
     double acc[kQ] = {0.0, 0.0, 0.0, 0.0, 0.0};
-    for (int p = p0 + (int)threadIdx.x; p < p1; p += blockDim.x) {
-      double out[2], xc[2];
-      jv_point<KIND, NC>(op, src, p, out, xc);
-#pragma unroll
-      for (int cc = 0; cc < NC; ++cc) {
-        const int idx = NC * p + cc;
-        const double y = (out[cc] - c * xc[cc]) / gamma - xim * xc[cc];
-        store_shared(dst + idx, y);
-        acc[0] += y * y;
-#pragma unroll
-        for (int k = 0; k < kMaxK; ++k) {
-          if (act[k]) {
-            const double pk = P.p[k][idx] + dk[k] * y;
-            P.p[k][idx] = pk;
-            acc[1 + k] += pk * pk;
-          }
-        }
-      }
-    }
+    newton_pass<KIND, NC, true>(op, src, dst, P.p, act, dk, c, gamma, xim, p0 + (int)threadIdx.x, p1, blockDim.x,
+                                acc);
     tick(kProfSteps);
     block_sum<kQ>(acc, sh.red);
     double* area = partial_area(P.partials, epoch);
@@ -762,6 +824,155 @@ __global__ __launch_bounds__(256) void lj_divdiff_kernel(DDParams P) {
   if ((int)threadIdx.x < P.K) P.fmax[threadIdx.x] = fm[threadIdx.x];
 }
 
+// ===========================================================================
+// Batched actions (the batching form): many independent instances, each run
+// by one block from start to end -- power iteration, divided differences and
+// the whole Newton recurrence with its stop decisions -- so an instance needs
+// only block-level synchronisation.  Blocks take instances from a work queue
+// (one atomic counter) in the order the host gives (largest first), so the
+// long instances start first and short ones fill the tail.  The arithmetic of
+// every step is that of lj_action_stream; only the reductions run over one
+// block instead of the grid.
+// ===========================================================================
+template <int KIND, int NC, int BS>
+__global__ __launch_bounds__(BS) void lj_batch_kernel(BatchParams B) {
+  constexpr int NW = BS / 64;
+  __shared__ double xi[kTable];
+  __shared__ double coef[kMaxK * kTable];
+  __shared__ double fmaxk[kMaxK];
+  __shared__ double red[kQ * NW + kQ];
+  __shared__ Decision sD;
+  __shared__ int s_commit[kMaxK];
+  __shared__ int s_job;
+  __shared__ double s_s[kMaxK];
+  for (int i = threadIdx.x; i < kTable; i += BS) xi[i] = B.xi[i];
+  const int K = B.K;
+  const double* tot = red + kQ * NW;  // block totals left by block_sum
+  for (;;) {
+    __syncthreads();
+    if (threadIdx.x == 0) s_job = (int)atomicAdd(B.queue, 1u);
+    __syncthreads();
+    const int job = uniform(s_job);
+    if (job >= B.n) break;
+    const int inst = uniform(B.order[job]);
+    const BatchItem* __restrict__ it = B.items + inst;
+    const unsigned long long t_start = wall_clock64();
+    const OpDev op = it->op;
+    const int npts = op.npts;
+    double* __restrict__ y0 = it->y0;
+    double* __restrict__ y1 = it->y1;
+    const double* __restrict__ v = it->v;
+    double* pp[kMaxK];
+#pragma unroll
+    for (int k = 0; k < kMaxK; ++k) pp[k] = (k < K) ? it->p[k] : nullptr;
+    if (threadIdx.x < kMaxK) s_s[threadIdx.x] = ((int)threadIdx.x < K) ? it->s[threadIdx.x] : 0.0;
+
+    // (1) spectral bound
+    double lam = it->lam_in;
+    int pit = 0;
+    if (!(lam > 0.0)) {
+      for (int p = threadIdx.x; p < npts; p += BS)
+#pragma unroll
+        for (int cc = 0; cc < NC; ++cc) y1[NC * p + cc] = 0.5 + splitmix_uniform(B.seed, (uint64_t)(NC * p + cc));
+      __syncthreads();
+      double scale = 1.0;
+      for (int k = 0; k < B.power_iters; ++k) {
+        const double* src = (k & 1) ? y0 : y1;
+        double* dst = (k & 1) ? y1 : y0;
+        double w2[2] = {0.0, 0.0};
+        power_pass<KIND, NC, false>(op, src, dst, scale, threadIdx.x, npts, BS, w2[0], w2[1]);
+        block_sum<2>(w2, red);
+        const double nx = sqrt(w2[0]);
+        const double ny = sqrt(w2[1]);
+        lam = ny / nx;
+        pit = k + 1;
+        if (ny == 0.0) {
+          lam = 0.0;
+          break;
+        }
+        scale = 1.0 / ny;
+      }
+    }
+    lam = uniform(lam);
+    double c, gamma;
+    interval(lam, B.safety, c, gamma);
+
+    // (2) divided differences
+    __syncthreads();
+    {
+      DivDiff dd;
+      dd_init(dd, K, B.l, s_s, B.max_points + 1, c, gamma, xi, coef, fmaxk);
+      dd_advance(dd, K, B.max_points, xi, coef);
+    }
+    __syncthreads();
+
+    // (3) m = 0: p_k = d_{k,0} v and ||v||^2
+    double a0[1] = {0.0};
+    for (int p = threadIdx.x; p < npts; p += BS) {
+#pragma unroll
+      for (int cc = 0; cc < NC; ++cc) {
+        const int idx = NC * p + cc;
+        const double vv = v[idx];
+        a0[0] += vv * vv;
+#pragma unroll
+        for (int k = 0; k < kMaxK; ++k)
+          if (k < K) pp[k][idx] = coef[k * kTable] * vv;
+      }
+    }
+    block_sum<1>(a0, red);
+    const double nv = sqrt(a0[0]);
+    if (threadIdx.x < 64) decision_init(sD, K, nv, B.hump, fmaxk);
+    __syncthreads();
+
+    // (4) Newton recurrence
+    const double* src = v;
+    for (int m = 1; m <= B.max_points && uniform(sD.n_active) > 0; ++m) {
+      double* __restrict__ dst = (m & 1) ? y1 : y0;
+      const double xim = uniform(xi[m - 1]);
+      double dk[kMaxK];
+      bool act[kMaxK];
+#pragma unroll
+      for (int k = 0; k < kMaxK; ++k) {
+        act[k] = (k < K) && (uniform(sD.st[k]) == ACC_RUNNING);
+        dk[k] = act[k] ? uniform(coef[k * kTable + m]) : 0.0;
+      }
+      double acc[kQ] = {0.0, 0.0, 0.0, 0.0, 0.0};
+      newton_pass<KIND, NC, false>(op, src, dst, pp, act, dk, c, gamma, xim, threadIdx.x, npts, BS, acc);
+      block_sum<kQ>(acc, red);
+      if (threadIdx.x < 64)
+        replay_decisions(sD, K, m - 1, 1, 1 + K, tot, coef, B.tol, B.relative, B.max_points, s_commit, nullptr);
+      __syncthreads();
+      src = dst;
+    }
+
+    // (5) outcome of this instance
+    if (threadIdx.x == 0) {
+      BatchStatus* S = B.status + inst;
+#pragma unroll
+      for (int k = 0; k < kMaxK; ++k) {
+        S->state[k] = sD.st[k];
+        S->m_star[k] = sD.mst[k];
+        S->err[k] = sD.err[k];
+      }
+      S->iters = sD.iters;
+      S->accum_iters = sD.accum_iters;
+      S->power_iters = pit;
+      S->vnorm = nv;
+      S->lam = lam;
+      S->c = c;
+      S->gamma = gamma;
+      S->block = blockIdx.x;
+      S->t0 = t_start;
+      S->t1 = wall_clock64();
+    }
+  }
+}
+
+// zeroes n words (graph-capturable replacement of a memset node)
+__global__ void lj_fill_u32(unsigned int* p, int n, unsigned int v) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = v;
+}
+
 // ---------------------------------------------------------------------------
 // Streaming helpers.
 // ---------------------------------------------------------------------------
@@ -831,6 +1042,29 @@ void* action_tile_ptr(int kind, int ept) {
     }
   }
   return nullptr;
+}
+
+void* batch_kernel_ptr(int kind, int bs) {
+#define LJ_BATCH_CASE(K_, NC_)                                                          \
+  case K_:                                                                              \
+    if (bs == 256) return reinterpret_cast<void*>(&lj_batch_kernel<K_, NC_, 256>);     \
+    if (bs == 512) return reinterpret_cast<void*>(&lj_batch_kernel<K_, NC_, 512>);     \
+    if (bs == 1024) return reinterpret_cast<void*>(&lj_batch_kernel<K_, NC_, 1024>);   \
+    return nullptr;
+  switch (kind) {
+    LJ_BATCH_CASE(OP_DIAG, 1)
+    LJ_BATCH_CASE(OP_ADVDIFF, 1)
+    LJ_BATCH_CASE(OP_ALLENCAHN, 1)
+    LJ_BATCH_CASE(OP_BRUSSELATOR, 2)
+    LJ_BATCH_CASE(OP_BURGERS, 1)
+  }
+#undef LJ_BATCH_CASE
+  return nullptr;
+}
+
+hipError_t launch_fill_u32(unsigned int* p, int n, unsigned int v, hipStream_t s) {
+  hipLaunchKernelGGL(lj_fill_u32, dim3(1), dim3(64), 0, s, p, n, v);
+  return hipGetLastError();
 }
 
 hipError_t launch_divdiff(const DDParams& P, hipStream_t s) {

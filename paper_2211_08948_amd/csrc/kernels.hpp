@@ -22,6 +22,8 @@ void* action_stream_ptr(int kind);
 void* action_tile_ptr(int kind, int ept);  // nullptr if the family has no tiled kernel
 
 hipError_t launch_divdiff(const DDParams& P, hipStream_t s);
+void* batch_kernel_ptr(int kind, int block_size);  // block_size in {256, 512, 1024}
+hipError_t launch_fill_u32(unsigned int* p, int n, unsigned int v, hipStream_t s);
 hipError_t launch_rhs(const OpDev& op, const double* u, double* f, hipStream_t s);
 hipError_t launch_remainder(const OpDev& op, const double* x, const double* d, const double* fu,
                             double* r, hipStream_t s);

@@ -7,7 +7,10 @@
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
+#include <algorithm>
 #include <cstring>
+#include <map>
+#include <numeric>
 #include <string>
 #include <vector>
 
@@ -59,6 +62,8 @@ struct lj_context {
   bool timing = false;
   hipEvent_t ev[4] = {};
   lj_timing tm = {};
+  // batching form: schedule picked by the tuner, per batch shape
+  std::map<std::string, int> batch_schedule;
 };
 
 static std::string g_create_error;
@@ -562,6 +567,134 @@ int guarded(lj_context* ctx, F&& f) {
   }
 }
 
+// ---- batching form -----------------------------------------------------------
+// Schedules the tuner chooses among: threads per block, blocks per CU and the
+// order in which blocks take instances from the queue (largest first, or as
+// given).
+struct BatchSchedule {
+  int block;
+  int per_cu;
+  int largest_first;
+};
+constexpr BatchSchedule kBatchSchedules[] = {
+    {1024, 1, 1}, {512, 2, 1}, {256, 4, 1}, {512, 1, 1}, {1024, 1, 0},
+};
+constexpr int kNumBatchSchedules = (int)(sizeof(kBatchSchedules) / sizeof(kBatchSchedules[0]));
+
+}  // namespace
+
+struct lj_batch {
+  lj_context* ctx = nullptr;
+  int n = 0, K = 0, kind = 0;
+  int l[kMaxK] = {};
+  double a[kMaxK] = {};
+  double tol = 0.0;
+  Opts o{};
+  std::vector<OpDev> ops;
+  std::vector<const double*> v;
+  std::vector<double> h;
+  std::vector<double*> w;  // n * K
+  std::vector<long long> nval;
+  long long total_values = 0;
+  BatchItem* d_items = nullptr;
+  BatchStatus* d_status = nullptr;
+  BatchStatus* h_status = nullptr;  // pinned
+  int* d_order = nullptr;
+  unsigned int* d_queue = nullptr;
+  double* d_work = nullptr;
+  hipStream_t cs = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  BatchParams P{};
+  int schedule = 0;
+  float tune_ms[kNumBatchSchedules] = {};
+  double alg_bytes = 0.0;
+};
+
+namespace {
+
+void batch_release(lj_batch* b) {
+  if (!b) return;
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  if (b->cs) (void)hipStreamDestroy(b->cs);
+  if (b->d_items) (void)hipFree(b->d_items);
+  if (b->d_status) (void)hipFree(b->d_status);
+  if (b->h_status) (void)hipHostFree(b->h_status);
+  if (b->d_order) (void)hipFree(b->d_order);
+  if (b->d_queue) (void)hipFree(b->d_queue);
+  if (b->d_work) (void)hipFree(b->d_work);
+  delete b;
+}
+
+// order of the schedule: instance indices, largest first or as given
+std::vector<int> batch_order(const lj_batch* b, int largest_first) {
+  std::vector<int> ord(b->n);
+  std::iota(ord.begin(), ord.end(), 0);
+  if (largest_first)
+    std::stable_sort(ord.begin(), ord.end(), [&](int x, int y) { return b->nval[x] > b->nval[y]; });
+  return ord;
+}
+
+void batch_launch(lj_batch* b, int sched, hipStream_t s) {
+  lj_context* ctx = b->ctx;
+  const BatchSchedule& S = kBatchSchedules[sched];
+  void* fn = batch_kernel_ptr(b->kind, S.block);
+  if (!fn) invalid(ctx, "no batch kernel for this operator family / block size");
+  HIPCHK(ctx, launch_fill_u32(b->d_queue, 1, 0u, s));
+  BatchParams P = b->P;
+  void* args[] = {&P};
+  HIPCHK(ctx, hipLaunchKernel(fn, dim3(ctx->num_cus * S.per_cu), dim3(S.block), args, 0, s));
+}
+
+void batch_set_order(lj_batch* b, int sched) {
+  const std::vector<int> ord = batch_order(b, kBatchSchedules[sched].largest_first);
+  HIPCHK(b->ctx, hipMemcpy(b->d_order, ord.data(), ord.size() * sizeof(int), hipMemcpyHostToDevice));
+}
+
+std::string batch_key(const lj_batch* b) {
+  std::string k = std::to_string(b->kind) + ":" + std::to_string(b->n) + ":" + std::to_string(b->K) + ":" +
+                  std::to_string(b->total_values);
+  for (int q = 0; q < b->K; ++q) k += ":" + std::to_string(b->l[q]);
+  return k;
+}
+
+// Times every schedule on the batch itself (each twice, the faster counts) and
+// keeps the fastest; the choice is cached in the context per batch shape.
+int batch_tune(lj_batch* b) {
+  lj_context* ctx = b->ctx;
+  if (const char* e = std::getenv("LJ_BATCH_SCHEDULE")) {
+    const int i = std::atoi(e);
+    if (i >= 0 && i < kNumBatchSchedules) return i;
+  }
+  const std::string key = batch_key(b);
+  auto it = ctx->batch_schedule.find(key);
+  if (it != ctx->batch_schedule.end()) return it->second;
+  hipEvent_t e0, e1;
+  HIPCHK(ctx, hipEventCreate(&e0));
+  HIPCHK(ctx, hipEventCreate(&e1));
+  int best = 0;
+  for (int i = 0; i < kNumBatchSchedules; ++i) {
+    batch_set_order(b, i);
+    float t = 1e30f;
+    for (int rep = 0; rep < 2; ++rep) {
+      HIPCHK(ctx, hipEventRecord(e0, b->cs));
+      batch_launch(b, i, b->cs);
+      HIPCHK(ctx, hipEventRecord(e1, b->cs));
+      HIPCHK(ctx, hipEventSynchronize(e1));
+      float ms = 0.0f;
+      HIPCHK(ctx, hipEventElapsedTime(&ms, e0, e1));
+      t = std::min(t, ms);
+    }
+    b->tune_ms[i] = t;
+    if (t < b->tune_ms[best]) best = i;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  ctx->batch_schedule[key] = best;
+  return best;
+}
+
 }  // namespace
 
 // ===========================================================================
@@ -939,6 +1072,228 @@ LJ_API int lj_timing_read(lj_context* ctx, lj_timing* out, int reset) {
   *out = ctx->tm;
   if (reset) std::memset(&ctx->tm, 0, sizeof(ctx->tm));
   return LJ_OK;
+}
+
+// ---- batching form ---------------------------------------------------------
+LJ_API int lj_batch_create(lj_context* ctx, const lj_operator* ops, int n, const double* const* v, const double* h,
+                           int K, const int* l, const double* a, double tol, double* const* w, const double* bounds,
+                           const lj_options* opt, lj_batch** out) {
+  if (out) *out = nullptr;
+  lj_batch* b = nullptr;
+  const int rc = guarded(ctx, [&]() {
+    if (!out) invalid(ctx, "out is NULL");
+    if (n < 1) invalid(ctx, "n must be >= 1");
+    if (!ops || !v || !h || !w) invalid(ctx, "ops, v, h and w must not be NULL");
+    if (K < 1 || K > LJ_MAX_K) invalid(ctx, "K must be in [1, 4]");
+    if (!l || !a) invalid(ctx, "l and a must not be NULL");
+    if (!(tol > 0.0) || !std::isfinite(tol)) invalid(ctx, "tol must be finite and > 0");
+    for (int k = 0; k < K; ++k) {
+      if (l[k] < 0 || l[k] > LJ_MAX_L) invalid(ctx, "l must be in [0, 4]");
+      if (!std::isfinite(a[k])) invalid(ctx, "a[k] must be finite");
+    }
+    b = new lj_batch();
+    b->ctx = ctx;
+    b->n = n;
+    b->K = K;
+    b->kind = ops[0].kind;
+    b->tol = tol;
+    b->o = resolve(ctx, opt);
+    for (int k = 0; k < K; ++k) {
+      b->l[k] = l[k];
+      b->a[k] = a[k];
+    }
+    for (int i = 0; i < n; ++i) {
+      if (ops[i].kind != b->kind) invalid(ctx, "all operators of a batch must be of one family");
+      const OpDev op = make_op(ctx, &ops[i]);
+      if (!std::isfinite(h[i])) invalid(ctx, "h[i] must be finite");
+      check_vec(ctx, op, v[i], "v[i]");
+      for (int k = 0; k < K; ++k) {
+        double* wk = w[(size_t)i * K + k];
+        check_vec(ctx, op, wk, "w[i*K+k]");
+        if (wk == v[i] || wk == op.state) invalid(ctx, "w must not alias v or the operator state");
+        for (int q = 0; q < k; ++q)
+          if (w[(size_t)i * K + q] == wk) invalid(ctx, "the outputs of an instance must be distinct");
+      }
+      if (bounds && (!(bounds[i] >= 0.0) || !std::isfinite(bounds[i])))
+        invalid(ctx, "bounds[i] must be finite and >= 0");
+      b->ops.push_back(op);
+      b->v.push_back(v[i]);
+      b->h.push_back(h[i]);
+      for (int k = 0; k < K; ++k) b->w.push_back(w[(size_t)i * K + k]);
+      b->nval.push_back((long long)nvals(op));
+      b->total_values += (long long)nvals(op);
+    }
+    // device-side description
+    HIPCHK(ctx, hipMalloc(&b->d_work, (size_t)2 * b->total_values * sizeof(double)));
+    std::vector<BatchItem> items(n);
+    size_t off = 0;
+    for (int i = 0; i < n; ++i) {
+      BatchItem& it = items[i];
+      std::memset(&it, 0, sizeof(it));
+      it.op = b->ops[i];
+      it.v = v[i];
+      for (int k = 0; k < K; ++k) {
+        it.p[k] = w[(size_t)i * K + k];
+        it.s[k] = a[k] * h[i];
+      }
+      it.y0 = b->d_work + off;
+      it.y1 = b->d_work + off + b->nval[i];
+      off += 2 * (size_t)b->nval[i];
+      it.lam_in = (bounds && bounds[i] > 0.0) ? bounds[i] : (b->o.bound > 0.0 ? b->o.bound : 0.0);
+    }
+    HIPCHK(ctx, hipMalloc(&b->d_items, n * sizeof(BatchItem)));
+    HIPCHK(ctx, hipMemcpy(b->d_items, items.data(), n * sizeof(BatchItem), hipMemcpyHostToDevice));
+    HIPCHK(ctx, hipMalloc(&b->d_status, n * sizeof(BatchStatus)));
+    HIPCHK(ctx, hipMemset(b->d_status, 0, n * sizeof(BatchStatus)));
+    HIPCHK(ctx, hipHostMalloc(&b->h_status, n * sizeof(BatchStatus), hipHostMallocDefault));
+    HIPCHK(ctx, hipMalloc(&b->d_order, n * sizeof(int)));
+    HIPCHK(ctx, hipMalloc(&b->d_queue, 64 * sizeof(unsigned int)));
+    HIPCHK(ctx, hipStreamCreateWithFlags(&b->cs, hipStreamNonBlocking));
+    BatchParams& P = b->P;
+    P.items = b->d_items;
+    P.status = b->d_status;
+    P.order = b->d_order;
+    P.n = n;
+    P.K = K;
+    for (int k = 0; k < kMaxK; ++k) P.l[k] = (k < K) ? l[k] : 0;
+    P.power_iters = b->o.power_iters;
+    P.seed = b->o.seed;
+    P.safety = b->o.safety;
+    P.max_points = b->o.max_points;
+    P.relative = b->o.relative;
+    P.tol = tol;
+    P.hump = b->o.hump;
+    P.xi = ctx->d_xi;
+    P.queue = b->d_queue;
+    // pick the schedule, then capture its launch (queue reset + kernel) in a graph
+    b->schedule = batch_tune(b);
+    batch_set_order(b, b->schedule);
+    HIPCHK(ctx, hipStreamBeginCapture(b->cs, hipStreamCaptureModeThreadLocal));
+    batch_launch(b, b->schedule, b->cs);
+    HIPCHK(ctx, hipStreamEndCapture(b->cs, &b->graph));
+    HIPCHK(ctx, hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
+    HIPCHK(ctx, hipStreamSynchronize(b->cs));
+    *out = b;
+    b = nullptr;
+    return LJ_OK;
+  });
+  if (b) batch_release(b);
+  return rc;
+}
+
+LJ_API int lj_batch_run(lj_batch* b, void* stream) {
+  if (!b) return LJ_EINVAL;
+  return guarded(b->ctx, [&]() {
+    HIPCHK(b->ctx, hipGraphLaunch(b->exec, reinterpret_cast<hipStream_t>(stream)));
+    return LJ_OK;
+  });
+}
+
+LJ_API int lj_batch_stats(lj_batch* b, lj_stats* per_instance, void* stream) {
+  if (!b) return LJ_EINVAL;
+  lj_context* ctx = b->ctx;
+  return guarded(ctx, [&]() {
+    const hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    HIPCHK(ctx, hipStreamSynchronize(s));
+    HIPCHK(ctx, hipMemcpy(b->h_status, b->d_status, b->n * sizeof(BatchStatus), hipMemcpyDeviceToHost));
+    bool all_ok = true;
+    double bytes = 0.0;
+    for (int i = 0; i < b->n; ++i) {
+      const BatchStatus& S = b->h_status[i];
+      bytes += (double)b->nval[i] *
+               (24.0 * S.iters + 16.0 * S.accum_iters + 24.0 * S.power_iters + 8.0 + 8.0 * b->K);
+      lj_stats st;
+      std::memset(&st, 0, sizeof(st));
+      for (int k = 0; k < LJ_MAX_K; ++k) {
+        st.m_star[k] = -1;
+        st.substeps[k] = 1;
+      }
+      st.iters_total = S.iters;
+      st.power_iters = S.power_iters;
+      st.bound = S.lam;
+      st.c = S.c;
+      st.gamma = S.gamma;
+      std::vector<int> pend_l;
+      std::vector<double> pend_a;
+      std::vector<double*> pend_w;
+      std::vector<int> pend_k;
+      for (int k = 0; k < b->K; ++k) {
+        if (S.state[k] == ACC_CONVERGED) {
+          st.m_star[k] = S.m_star[k];
+          st.err_est[k] = S.err[k];
+        } else {
+          pend_k.push_back(k);
+          pend_l.push_back(b->l[k]);
+          pend_a.push_back(b->a[k]);
+          pend_w.push_back(b->w[(size_t)i * b->K + k]);
+        }
+      }
+      st.converged = 1;
+      if (!pend_k.empty()) {
+        // the batch attempt was rejected: redo those accumulators with the
+        // plain path and substeps, on the bound the batch found
+        st.rejections = 1;
+        Opts o = b->o;
+        o.bound = S.lam;
+        o.substeps = 2;
+        lj_stats fb;
+        const int r = vertical_impl(ctx, b->ops[i], b->v[i], (int)pend_k.size(), pend_l.data(), pend_a.data(),
+                                    b->h[i], b->tol, pend_w.data(), o, &fb, s);
+        st.iters_total += fb.iters_total;
+        st.rejections += fb.rejections;
+        for (size_t q = 0; q < pend_k.size(); ++q) {
+          st.m_star[pend_k[q]] = fb.m_star[q];
+          st.substeps[pend_k[q]] = fb.substeps[q];
+          st.err_est[pend_k[q]] = fb.err_est[q];
+        }
+        if (r != LJ_OK) {
+          st.converged = 0;
+          all_ok = false;
+        }
+      }
+      if (per_instance) per_instance[i] = st;
+    }
+    b->alg_bytes = bytes;
+    return all_ok ? LJ_OK : LJ_ENOTCONV;
+  });
+}
+
+LJ_API int lj_batch_info(const lj_batch* b, lj_batch_info_t* out) {
+  if (!b || !out) return LJ_EINVAL;
+  std::memset(out, 0, sizeof(*out));
+  const BatchSchedule& S = kBatchSchedules[b->schedule];
+  out->schedule = b->schedule;
+  out->block_size = S.block;
+  out->blocks = b->ctx->num_cus * S.per_cu;
+  out->largest_first = S.largest_first;
+  out->nschedules = kNumBatchSchedules;
+  for (int i = 0; i < kNumBatchSchedules && i < 8; ++i) out->tune_ms[i] = b->tune_ms[i];
+  out->total_values = b->total_values;
+  out->alg_bytes = b->alg_bytes;
+  return LJ_OK;
+}
+
+LJ_API int lj_batch_timeline(const lj_batch* b, int* block, double* start_us, double* end_us) {
+  if (!b || !block || !start_us || !end_us) return LJ_EINVAL;
+  int khz = 0;
+  if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, b->ctx->device) != hipSuccess || khz <= 0)
+    return LJ_EHIP;
+  unsigned long long t_min = ~0ull;
+  for (int i = 0; i < b->n; ++i) t_min = std::min(t_min, b->h_status[i].t0);
+  for (int i = 0; i < b->n; ++i) {
+    const BatchStatus& S = b->h_status[i];
+    block[i] = S.block;
+    start_us[i] = (double)(S.t0 - t_min) * 1e3 / khz;
+    end_us[i] = (double)(S.t1 - t_min) * 1e3 / khz;
+  }
+  return LJ_OK;
+}
+
+LJ_API void lj_batch_destroy(lj_batch* b) {
+  if (!b) return;
+  (void)hipSetDevice(b->ctx->device);
+  (void)hipDeviceSynchronize();
+  batch_release(b);
 }
 
 }  // extern "C"

@@ -36,13 +36,14 @@ def test_every_declared_symbol_is_exported(lib):
 
 
 def test_struct_layout_matches_c(tmp_path):
-    from paper_2211_08948_amd._lib import lj_operator, lj_options, lj_stats, lj_timing
+    from paper_2211_08948_amd._lib import lj_batch_info_t, lj_operator, lj_options, lj_stats, lj_timing
     prog = tmp_path / "sz.c"
     fields = {
         "lj_operator": ["kind", "nx", "dx", "coef", "state"],
         "lj_options": ["safety", "power_iters", "hump_max", "bound", "substeps", "power_seed", "pi_start"],
         "lj_stats": ["m_star", "substeps", "err_est", "iters_total", "converged", "bound", "gamma"],
         "lj_timing": ["launches", "power_point_iters", "tiled_launches", "kernel_ms"],
+        "lj_batch_info_t": ["schedule", "nschedules", "tune_ms", "total_values", "alg_bytes"],
     }
     lines = ['#include <stdio.h>', '#include <stddef.h>', f'#include "{HEADER}"', "int main(void){"]
     for s, fs in fields.items():
@@ -55,7 +56,8 @@ def test_struct_layout_matches_c(tmp_path):
     subprocess.run(["gcc", "-o", str(exe), str(prog)], check=True)
     out = dict(l.rsplit(" ", 1) for l in subprocess.run([str(exe)], capture_output=True, text=True,
                                                           check=True).stdout.split("\n") if l)
-    py = {"lj_operator": lj_operator, "lj_options": lj_options, "lj_stats": lj_stats, "lj_timing": lj_timing}
+    py = {"lj_operator": lj_operator, "lj_options": lj_options, "lj_stats": lj_stats, "lj_timing": lj_timing,
+          "lj_batch_info_t": lj_batch_info_t}
     for s, fs in fields.items():
         assert int(out[s]) == C.sizeof(py[s]), s
         for f in fs:
@@ -88,6 +90,11 @@ def test_null_arguments_are_rejected_without_device(lib):
     assert lib.lj_phi_action(None, None, None, None, 1, 1.0, 1e-10, None, None, None) == -1
     assert lib.lj_step(None, 1, None, 1.0, 1e-10, None, None, None, None, 0, None, None) == -1
     assert lib.lj_timing_enable(None, 1) == -1
+    assert lib.lj_batch_run(None, None) == -1
+    assert lib.lj_batch_stats(None, None, None) == -1
+    assert lib.lj_batch_info(None, None) == -1
+    assert lib.lj_batch_create(None, None, 0, None, None, 0, None, None, 1e-10, None, None, None, None) == -1
+    lib.lj_batch_destroy(None)
     lib.lj_destroy(None)
 
 
