@@ -196,7 +196,8 @@ LJ_API int lj_step(lj_context* ctx, int scheme, const lj_operator* J, double h, 
  *
  * lj_batch_create validates every argument, allocates the batch's workspace
  * (two vectors per instance), times the candidate schedules (threads per
- * block, blocks per CU, order of the queue) on the batch itself and keeps the
+ * block, blocks per CU, blocks per instance, order of the queue) on the batch
+ * itself and keeps the
  * fastest (the choice is cached in the context per batch shape; the timing
  * runs write the outputs), then captures the launch -- a queue reset and the
  * kernel -- in a HIP graph.  ops: host array of n operators of ONE family;
@@ -221,7 +222,7 @@ typedef struct {
   int32_t blocks;        /* blocks of the persistent launch */
   int32_t largest_first; /* 1: the queue hands out the largest instances first */
   int32_t nschedules;    /* schedules the tuner considered */
-  int32_t pad;
+  int32_t team;          /* blocks (on one XCD) that share an instance */
   float tune_ms[8];      /* tuned time per schedule in ms (0 when the choice came from the cache) */
   int64_t total_values;  /* sum of the instances' vector lengths */
   double alg_bytes;      /* algorithmic bytes of the run last read by lj_batch_stats */

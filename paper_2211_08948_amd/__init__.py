@@ -285,7 +285,7 @@ class Batch:
     def info(self) -> dict:
         i = _lib.lj_batch_info_t()
         self.ctx._check(self.ctx._lib.lj_batch_info(self.handle, C.byref(i)), False)
-        d = {f: getattr(i, f) for f, _ in i._fields_ if f not in ("pad", "tune_ms")}
+        d = {f: getattr(i, f) for f, _ in i._fields_ if f != "tune_ms"}
         d["tune_ms"] = list(i.tune_ms)[:i.nschedules]
         return d
 

@@ -68,7 +68,7 @@ class lj_timing(C.Structure):
 class lj_batch_info_t(C.Structure):
     _fields_ = [
         ("schedule", C.c_int32), ("block_size", C.c_int32), ("blocks", C.c_int32),
-        ("largest_first", C.c_int32), ("nschedules", C.c_int32), ("pad", C.c_int32),
+        ("largest_first", C.c_int32), ("nschedules", C.c_int32), ("team", C.c_int32),
         ("tune_ms", C.c_float * 8), ("total_values", C.c_int64), ("alg_bytes", C.c_double),
     ]
 

@@ -133,7 +133,13 @@ struct BatchParams {
   double tol;
   double hump;
   const double* xi;       // Leja table (device)
-  unsigned int* queue;    // work counter, zero at launch
+  unsigned int* queue;    // [0] work counter, [1] abort word; zero at launch
+  // teams: `team` blocks of one XCD share an instance (team = 1: one block)
+  int team;
+  unsigned int* team_words;  // per team kTeamWords words, zero at launch (barrier counter, mailbox)
+  double* team_part;         // per team 2 x kQ x team partial sums
 };
+
+constexpr int kTeamWords = 64;
 
 }  // namespace lj

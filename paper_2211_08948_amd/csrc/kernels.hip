@@ -282,25 +282,24 @@ __device__ __forceinline__ void write_status(LejaStatus* S, const Decision& D, i
 }
 
 // ---------------------------------------------------------------------------
-// Streaming passes over points p = pbeg, pbeg + stride, ... < pend, kUnroll
-// points per thread at a time: every load of those points (stencil values,
-// state, accumulators) is issued before any arithmetic or store, so a thread
-// keeps all of them in flight at once.  The points are visited, and the
-// per-thread sums accumulated, in the same order as a one-point loop.
+// Streaming passes over points p = pbeg, pbeg + stride, ... < pend, U points
+// per thread at a time: every load of those points (stencil values, state,
+// accumulators) is issued before any arithmetic or store, so a thread keeps
+// all of them in flight at once.  The points are visited, and the per-thread
+// sums accumulated, in the same order as a one-point loop, for every U.
 // ---------------------------------------------------------------------------
-constexpr int kUnroll = 2;
 
 // y(p) = scale * J x(p); sums of (scale x)^2 and y^2 (power iteration, Sec. 2.2)
-template <int KIND, int NC, bool SHARED>
+template <int KIND, int NC, bool SHARED, int U>
 __device__ __forceinline__ void power_pass(const OpDev& op, const double* __restrict__ src, double* __restrict__ dst,
                                            double scale, int pbeg, int pend, int stride, double& a0, double& a1) {
-  for (int p0 = pbeg; p0 < pend; p0 += stride * kUnroll) {
-    double xv[kUnroll][5][2], uv[kUnroll][5][2];
+  for (int p0 = pbeg; p0 < pend; p0 += stride * U) {
+    double xv[U][5][2], uv[U][5][2];
 #pragma unroll
-    for (int u = 0; u < kUnroll; ++u)
+    for (int u = 0; u < U; ++u)
       if (p0 + u * stride < pend) gather_point<KIND, NC>(op, src, p0 + u * stride, xv[u], uv[u]);
 #pragma unroll
-    for (int u = 0; u < kUnroll; ++u) {
+    for (int u = 0; u < U; ++u) {
       const int p = p0 + u * stride;
       if (p >= pend) continue;
       double out[2];
@@ -323,16 +322,16 @@ __device__ __forceinline__ void power_pass(const OpDev& op, const double* __rest
 
 // One Newton step (Sec. 2.2 display): y = ((J - c) x)/gamma - xi x, and for
 // every active accumulator p_k += d_k y; acc[0] += y^2, acc[1+k] += p_k^2.
-template <int KIND, int NC, bool SHARED>
+template <int KIND, int NC, bool SHARED, int U>
 __device__ __forceinline__ void newton_pass(const OpDev& op, const double* __restrict__ src,
                                             double* __restrict__ dst, double* const (&pp)[kMaxK],
                                             const bool (&act)[kMaxK], const double (&dk)[kMaxK], double c,
                                             double gamma, double xim, int pbeg, int pend, int stride,
                                             double (&acc)[kQ]) {
-  for (int p0 = pbeg; p0 < pend; p0 += stride * kUnroll) {
-    double xv[kUnroll][5][2], uv[kUnroll][5][2], pv[kUnroll][kMaxK][2];
+  for (int p0 = pbeg; p0 < pend; p0 += stride * U) {
+    double xv[U][5][2], uv[U][5][2], pv[U][kMaxK][2];
 #pragma unroll
-    for (int u = 0; u < kUnroll; ++u) {
+    for (int u = 0; u < U; ++u) {
       const int p = p0 + u * stride;
       if (p >= pend) continue;
       gather_point<KIND, NC>(op, src, p, xv[u], uv[u]);
@@ -342,7 +341,7 @@ __device__ __forceinline__ void newton_pass(const OpDev& op, const double* __res
         for (int cc = 0; cc < NC; ++cc) pv[u][k][cc] = act[k] ? pp[k][NC * p + cc] : 0.0;
     }
 #pragma unroll
-    for (int u = 0; u < kUnroll; ++u) {
+    for (int u = 0; u < U; ++u) {
       const int p = p0 + u * stride;
       if (p >= pend) continue;
       double out[2];
@@ -420,7 +419,7 @@ __global__ __launch_bounds__(kBlock) void lj_action_stream(ActionParams P) {
       const double* src = (k == 0) ? x0 : ((k & 1) ? P.ybuf0 : P.ybuf1);
       double* dst = (k & 1) ? P.ybuf1 : P.ybuf0;
       double a0 = 0.0, a1 = 0.0;
-      power_pass<KIND, NC, true>(op, src, dst, scale, p0 + (int)threadIdx.x, p1, blockDim.x, a0, a1);
+      power_pass<KIND, NC, true, 1>(op, src, dst, scale, p0 + (int)threadIdx.x, p1, blockDim.x, a0, a1);
 #pragma unroll
       for (int q = 0; q < kQ; ++q) wred[q] = 0.0;
       wred[0] = a0;
@@ -508,8 +507,8 @@ __global__ __launch_bounds__(kBlock) void lj_action_stream(ActionParams P) {
       dk[k] = act[k] ? uniform(sh.coef[k * kTable + m]) : 0.0;
     }
     double acc[kQ] = {0.0, 0.0, 0.0, 0.0, 0.0};
-    newton_pass<KIND, NC, true>(op, src, dst, P.p, act, dk, c, gamma, xim, p0 + (int)threadIdx.x, p1, blockDim.x,
-                                acc);
+    newton_pass<KIND, NC, true, 1>(op, src, dst, P.p, act, dk, c, gamma, xim, p0 + (int)threadIdx.x, p1,
+                                   blockDim.x, acc);
     tick(kProfSteps);
     block_sum<kQ>(acc, sh.red);
     double* area = partial_area(P.partials, epoch);
@@ -825,43 +824,116 @@ __global__ __launch_bounds__(256) void lj_divdiff_kernel(DDParams P) {
 }
 
 // ===========================================================================
-// Batched actions (the batching form): many independent instances, each run
-// by one block from start to end -- power iteration, divided differences and
-// the whole Newton recurrence with its stop decisions -- so an instance needs
-// only block-level synchronisation.  Blocks take instances from a work queue
-// (one atomic counter) in the order the host gives (largest first), so the
-// long instances start first and short ones fill the tail.  The arithmetic of
-// every step is that of lj_action_stream; only the reductions run over one
-// block instead of the grid.
+// Batched actions (the batching form): many independent instances; each is
+// run from start to end -- power iteration, divided differences and the whole
+// Newton recurrence with its stop decisions -- by one team of blocks.  A team
+// is `team` blocks that run on one XCD (blocks b, b + 8, b + 16, ... of a
+// launch are dispatched to the same XCD, so they share its L2) and
+// synchronise through a counter of their own: no grid-wide barrier.  Each member streams its chunk of the instance's
+// points, team reductions sum the members' partials in rank order, and every
+// member takes the same stop decisions.  Team leaders take instances from a
+// work queue (one atomic counter) in the order the host gives (largest
+// first), so the long instances start first and short ones fill the tail.
+// The arithmetic of every step is that of lj_action_stream.
 // ===========================================================================
+
+// Team barrier: drain this block's stores, arrive on the team counter, wait
+// for all members, then an agent-scope acquire drops stale cache lines.  The
+// wait is bounded: the host launches only schedules whose blocks are all
+// co-resident, but should a member never arrive, the waiting block raises the
+// batch's abort word (and every later wait returns at once), so the launch
+// ends and the host reports the failure instead of the device hanging.
+constexpr unsigned int kTeamSpinLimit = 1u << 22;
+
+__device__ __forceinline__ void team_barrier(unsigned int* ctr, unsigned int& epoch, int T,
+                                             unsigned int* abort_word) {
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+  if (T == 1) return;
+  epoch += 1u;
+  if (threadIdx.x == 0) {
+    __hip_atomic_fetch_add(ctr, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    unsigned int spins = 0;
+    while (__hip_atomic_load(ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < epoch * (unsigned int)T) {
+      if (__hip_atomic_load(abort_word, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) break;
+      if (++spins > kTeamSpinLimit) {
+        __hip_atomic_store(abort_word, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        break;
+      }
+      __builtin_amdgcn_s_sleep(1);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  }
+  __syncthreads();
+}
+
 template <int KIND, int NC, int BS>
 __global__ __launch_bounds__(BS) void lj_batch_kernel(BatchParams B) {
   constexpr int NW = BS / 64;
+  // two points in flight per thread where the register budget allows it
+  constexpr int kBatchUnroll = (BS >= 1024) ? 1 : 2;
   __shared__ double xi[kTable];
   __shared__ double coef[kMaxK * kTable];
   __shared__ double fmaxk[kMaxK];
   __shared__ double red[kQ * NW + kQ];
+  __shared__ double tot[kQ];
   __shared__ Decision sD;
   __shared__ int s_commit[kMaxK];
-  __shared__ int s_job;
   __shared__ double s_s[kMaxK];
+  __shared__ int s_flag;
   for (int i = threadIdx.x; i < kTable; i += BS) xi[i] = B.xi[i];
   const int K = B.K;
-  const double* tot = red + kQ * NW;  // block totals left by block_sum
+  const int T = B.team;
+  // team geometry: members share blockIdx.x % 8 (one XCD)
+  const int grp = blockIdx.x & 7, q8 = blockIdx.x >> 3;
+  const int rank = q8 % T;
+  const int team = (q8 / T) * 8 + grp;
+  unsigned int* tw = B.team_words + (size_t)team * kTeamWords;
+  unsigned int* ctr = tw;
+  unsigned int* mailbox = tw + 16;
+  double* tpart = B.team_part + (size_t)team * 2 * kQ * T;
+  unsigned int tepoch = 0;
+  // team all-reduce of nq block totals (LDS, as block_sum leaves them) into
+  // tot[0..nq): members' values added in rank order
+  auto team_sum = [&](const double* btot, int nq) {
+    if (T == 1) {
+      if ((int)threadIdx.x < nq) tot[threadIdx.x] = btot[threadIdx.x];
+      __syncthreads();
+      return;
+    }
+    double* area = tpart + (size_t)(tepoch & 1u) * kQ * T;
+    if ((int)threadIdx.x < nq) area[threadIdx.x * T + rank] = btot[threadIdx.x];
+    team_barrier(ctr, tepoch, T, B.queue + 1);
+    if ((int)threadIdx.x < nq) {
+      double t = 0.0;
+      for (int r = 0; r < T; ++r) t += area[threadIdx.x * T + r];
+      tot[threadIdx.x] = t;
+    }
+    __syncthreads();
+  };
+
   for (;;) {
+    if (rank == 0 && threadIdx.x == 0) {
+      const unsigned int job = atomicAdd(B.queue, 1u);
+      __hip_atomic_store(mailbox, job, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      s_flag = (int)job;
+    }
+    team_barrier(ctr, tepoch, T, B.queue + 1);
+    if (threadIdx.x == 0 && rank != 0) s_flag = (int)__hip_atomic_load(mailbox, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     __syncthreads();
-    if (threadIdx.x == 0) s_job = (int)atomicAdd(B.queue, 1u);
-    __syncthreads();
-    const int job = uniform(s_job);
+    const int job = uniform(s_flag);
     if (job >= B.n) break;
+    const unsigned long long t_start = wall_clock64();
     const int inst = uniform(B.order[job]);
     const BatchItem* __restrict__ it = B.items + inst;
-    const unsigned long long t_start = wall_clock64();
     const OpDev op = it->op;
     const int npts = op.npts;
-    double* __restrict__ y0 = it->y0;
-    double* __restrict__ y1 = it->y1;
-    const double* __restrict__ v = it->v;
+    // this member's chunk of the points
+    const int chunk = ((npts + T - 1) / T + 63) & ~63;
+    const int pb = min(npts, rank * chunk), pe = min(npts, pb + chunk);
+    double* y0 = it->y0;
+    double* y1 = it->y1;
+    const double* v = it->v;
     double* pp[kMaxK];
 #pragma unroll
     for (int k = 0; k < kMaxK; ++k) pp[k] = (k < K) ? it->p[k] : nullptr;
@@ -871,19 +943,21 @@ __global__ __launch_bounds__(BS) void lj_batch_kernel(BatchParams B) {
     double lam = it->lam_in;
     int pit = 0;
     if (!(lam > 0.0)) {
-      for (int p = threadIdx.x; p < npts; p += BS)
+      for (int p = pb + (int)threadIdx.x; p < pe; p += BS)
 #pragma unroll
-        for (int cc = 0; cc < NC; ++cc) y1[NC * p + cc] = 0.5 + splitmix_uniform(B.seed, (uint64_t)(NC * p + cc));
-      __syncthreads();
+        for (int cc = 0; cc < NC; ++cc)
+          store_shared(y1 + NC * p + cc, 0.5 + splitmix_uniform(B.seed, (uint64_t)(NC * p + cc)));
+      team_barrier(ctr, tepoch, T, B.queue + 1);
       double scale = 1.0;
       for (int k = 0; k < B.power_iters; ++k) {
         const double* src = (k & 1) ? y0 : y1;
         double* dst = (k & 1) ? y1 : y0;
         double w2[2] = {0.0, 0.0};
-        power_pass<KIND, NC, false>(op, src, dst, scale, threadIdx.x, npts, BS, w2[0], w2[1]);
+        power_pass<KIND, NC, true, kBatchUnroll>(op, src, dst, scale, pb + (int)threadIdx.x, pe, BS, w2[0], w2[1]);
         block_sum<2>(w2, red);
-        const double nx = sqrt(w2[0]);
-        const double ny = sqrt(w2[1]);
+        team_sum(red + 2 * NW, 2);
+        const double nx = sqrt(tot[0]);
+        const double ny = sqrt(tot[1]);
         lam = ny / nx;
         pit = k + 1;
         if (ny == 0.0) {
@@ -897,7 +971,7 @@ __global__ __launch_bounds__(BS) void lj_batch_kernel(BatchParams B) {
     double c, gamma;
     interval(lam, B.safety, c, gamma);
 
-    // (2) divided differences
+    // (2) divided differences, every member for itself
     __syncthreads();
     {
       DivDiff dd;
@@ -908,7 +982,7 @@ __global__ __launch_bounds__(BS) void lj_batch_kernel(BatchParams B) {
 
     // (3) m = 0: p_k = d_{k,0} v and ||v||^2
     double a0[1] = {0.0};
-    for (int p = threadIdx.x; p < npts; p += BS) {
+    for (int p = pb + (int)threadIdx.x; p < pe; p += BS) {
 #pragma unroll
       for (int cc = 0; cc < NC; ++cc) {
         const int idx = NC * p + cc;
@@ -920,14 +994,15 @@ __global__ __launch_bounds__(BS) void lj_batch_kernel(BatchParams B) {
       }
     }
     block_sum<1>(a0, red);
-    const double nv = sqrt(a0[0]);
+    team_sum(red + NW, 1);
+    const double nv = sqrt(tot[0]);
     if (threadIdx.x < 64) decision_init(sD, K, nv, B.hump, fmaxk);
     __syncthreads();
 
     // (4) Newton recurrence
     const double* src = v;
     for (int m = 1; m <= B.max_points && uniform(sD.n_active) > 0; ++m) {
-      double* __restrict__ dst = (m & 1) ? y1 : y0;
+      double* dst = (m & 1) ? y1 : y0;
       const double xim = uniform(xi[m - 1]);
       double dk[kMaxK];
       bool act[kMaxK];
@@ -937,8 +1012,10 @@ __global__ __launch_bounds__(BS) void lj_batch_kernel(BatchParams B) {
         dk[k] = act[k] ? uniform(coef[k * kTable + m]) : 0.0;
       }
       double acc[kQ] = {0.0, 0.0, 0.0, 0.0, 0.0};
-      newton_pass<KIND, NC, false>(op, src, dst, pp, act, dk, c, gamma, xim, threadIdx.x, npts, BS, acc);
+      newton_pass<KIND, NC, true, kBatchUnroll>(op, src, dst, pp, act, dk, c, gamma, xim, pb + (int)threadIdx.x, pe,
+                                                BS, acc);
       block_sum<kQ>(acc, red);
+      team_sum(red + kQ * NW, 1 + K);
       if (threadIdx.x < 64)
         replay_decisions(sD, K, m - 1, 1, 1 + K, tot, coef, B.tol, B.relative, B.max_points, s_commit, nullptr);
       __syncthreads();
@@ -946,7 +1023,7 @@ __global__ __launch_bounds__(BS) void lj_batch_kernel(BatchParams B) {
     }
 
     // (5) outcome of this instance
-    if (threadIdx.x == 0) {
+    if (rank == 0 && threadIdx.x == 0) {
       BatchStatus* S = B.status + inst;
 #pragma unroll
       for (int k = 0; k < kMaxK; ++k) {
@@ -1063,7 +1140,10 @@ void* batch_kernel_ptr(int kind, int bs) {
 }
 
 hipError_t launch_fill_u32(unsigned int* p, int n, unsigned int v, hipStream_t s) {
-  hipLaunchKernelGGL(lj_fill_u32, dim3(1), dim3(64), 0, s, p, n, v);
+  int g = (n + 255) / 256;
+  if (g > 64) g = 64;
+  if (g < 1) g = 1;
+  hipLaunchKernelGGL(lj_fill_u32, dim3(g), dim3(256), 0, s, p, n, v);
   return hipGetLastError();
 }
 

@@ -37,6 +37,7 @@ enum Slot {
 
 // LDS held back from the tiled kernel's dynamic allocation for its static arrays
 constexpr size_t kStaticLdsReserve = 20 * 1024;
+constexpr int kQ_batch = 1 + kMaxK;  // team partial sums per reduction
 
 struct lj_context {
   int device = 0;
@@ -568,16 +569,18 @@ int guarded(lj_context* ctx, F&& f) {
 }
 
 // ---- batching form -----------------------------------------------------------
-// Schedules the tuner chooses among: threads per block, blocks per CU and the
-// order in which blocks take instances from the queue (largest first, or as
-// given).
+// Schedules the tuner chooses among: threads per block, blocks per CU, blocks
+// per team (one instance at a time per team) and the order in which teams
+// take instances from the queue (largest first, or as given).
 struct BatchSchedule {
   int block;
   int per_cu;
+  int team;  // blocks (of one XCD) per instance
   int largest_first;
 };
 constexpr BatchSchedule kBatchSchedules[] = {
-    {1024, 1, 1}, {512, 2, 1}, {256, 4, 1}, {512, 1, 1}, {1024, 1, 0},
+    {1024, 1, 1, 1}, {1024, 1, 2, 1}, {1024, 1, 4, 1}, {1024, 1, 8, 1},
+    {512, 1, 1, 1},  {512, 1, 4, 1},  {512, 1, 8, 1},  {512, 1, 16, 1},
 };
 constexpr int kNumBatchSchedules = (int)(sizeof(kBatchSchedules) / sizeof(kBatchSchedules[0]));
 
@@ -600,7 +603,9 @@ struct lj_batch {
   BatchStatus* d_status = nullptr;
   BatchStatus* h_status = nullptr;  // pinned
   int* d_order = nullptr;
-  unsigned int* d_queue = nullptr;
+  unsigned int* d_queue = nullptr;  // queue counter, then the team words (zeroed per launch)
+  double* d_team_part = nullptr;
+  int max_blocks = 0;
   double* d_work = nullptr;
   hipStream_t cs = nullptr;
   hipGraph_t graph = nullptr;
@@ -623,6 +628,7 @@ void batch_release(lj_batch* b) {
   if (b->h_status) (void)hipHostFree(b->h_status);
   if (b->d_order) (void)hipFree(b->d_order);
   if (b->d_queue) (void)hipFree(b->d_queue);
+  if (b->d_team_part) (void)hipFree(b->d_team_part);
   if (b->d_work) (void)hipFree(b->d_work);
   delete b;
 }
@@ -641,15 +647,37 @@ void batch_launch(lj_batch* b, int sched, hipStream_t s) {
   const BatchSchedule& S = kBatchSchedules[sched];
   void* fn = batch_kernel_ptr(b->kind, S.block);
   if (!fn) invalid(ctx, "no batch kernel for this operator family / block size");
-  HIPCHK(ctx, launch_fill_u32(b->d_queue, 1, 0u, s));
+  const int G = ctx->num_cus * S.per_cu;
+  const int teams = G / S.team;
+  HIPCHK(ctx, launch_fill_u32(b->d_queue, kTeamWords + teams * kTeamWords, 0u, s));
   BatchParams P = b->P;
+  P.team = S.team;
+  P.team_words = b->d_queue + kTeamWords;
+  P.team_part = b->d_team_part;
   void* args[] = {&P};
-  HIPCHK(ctx, hipLaunchKernel(fn, dim3(ctx->num_cus * S.per_cu), dim3(S.block), args, 0, s));
+  HIPCHK(ctx, hipLaunchKernel(fn, dim3(G), dim3(S.block), args, 0, s));
 }
 
 void batch_set_order(lj_batch* b, int sched) {
   const std::vector<int> ord = batch_order(b, kBatchSchedules[sched].largest_first);
   HIPCHK(b->ctx, hipMemcpy(b->d_order, ord.data(), ord.size() * sizeof(int), hipMemcpyHostToDevice));
+}
+
+// A team's blocks must share blockIdx % 8 (one XCD), so 8 * team | blocks,
+// and all blocks of the launch must be co-resident (team members wait for
+// each other): per_cu blocks of this kernel must fit on one CU.
+bool batch_schedule_fits(const lj_batch* b, int i) {
+  const BatchSchedule& S = kBatchSchedules[i];
+  const int G = b->ctx->num_cus * S.per_cu;
+  if (G % (8 * S.team) != 0 || G > b->max_blocks) return false;
+  void* fn = batch_kernel_ptr(b->kind, S.block);
+  int per_cu = 0;
+  if (!fn || hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(fn), S.block, 0) !=
+                 hipSuccess) {
+    (void)hipGetLastError();
+    return false;
+  }
+  return per_cu >= S.per_cu;
 }
 
 std::string batch_key(const lj_batch* b) {
@@ -665,7 +693,7 @@ int batch_tune(lj_batch* b) {
   lj_context* ctx = b->ctx;
   if (const char* e = std::getenv("LJ_BATCH_SCHEDULE")) {
     const int i = std::atoi(e);
-    if (i >= 0 && i < kNumBatchSchedules) return i;
+    if (i >= 0 && i < kNumBatchSchedules && batch_schedule_fits(b, i)) return i;
   }
   const std::string key = batch_key(b);
   auto it = ctx->batch_schedule.find(key);
@@ -673,8 +701,9 @@ int batch_tune(lj_batch* b) {
   hipEvent_t e0, e1;
   HIPCHK(ctx, hipEventCreate(&e0));
   HIPCHK(ctx, hipEventCreate(&e1));
-  int best = 0;
+  int best = -1;
   for (int i = 0; i < kNumBatchSchedules; ++i) {
+    if (!batch_schedule_fits(b, i)) continue;
     batch_set_order(b, i);
     float t = 1e30f;
     for (int rep = 0; rep < 2; ++rep) {
@@ -684,11 +713,19 @@ int batch_tune(lj_batch* b) {
       HIPCHK(ctx, hipEventSynchronize(e1));
       float ms = 0.0f;
       HIPCHK(ctx, hipEventElapsedTime(&ms, e0, e1));
+      unsigned int qw[2] = {0, 0};
+      HIPCHK(ctx, hipMemcpy(qw, b->d_queue, sizeof(qw), hipMemcpyDeviceToHost));
+      if (qw[1] != 0u) ms = 1e30f;  // aborted: a team never assembled
       t = std::min(t, ms);
     }
+    if (t >= 1e30f) {
+      b->tune_ms[i] = 0.0f;
+      continue;
+    }
     b->tune_ms[i] = t;
-    if (t < b->tune_ms[best]) best = i;
+    if (best < 0 || t < b->tune_ms[best]) best = i;
   }
+  if (best < 0) invalid(ctx, "no batch schedule fits this device");
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   ctx->batch_schedule[key] = best;
@@ -1147,7 +1184,11 @@ LJ_API int lj_batch_create(lj_context* ctx, const lj_operator* ops, int n, const
     HIPCHK(ctx, hipMemset(b->d_status, 0, n * sizeof(BatchStatus)));
     HIPCHK(ctx, hipHostMalloc(&b->h_status, n * sizeof(BatchStatus), hipHostMallocDefault));
     HIPCHK(ctx, hipMalloc(&b->d_order, n * sizeof(int)));
-    HIPCHK(ctx, hipMalloc(&b->d_queue, 64 * sizeof(unsigned int)));
+    b->max_blocks = 0;
+    for (int i = 0; i < kNumBatchSchedules; ++i)
+      b->max_blocks = std::max(b->max_blocks, ctx->num_cus * kBatchSchedules[i].per_cu);
+    HIPCHK(ctx, hipMalloc(&b->d_queue, (size_t)(1 + b->max_blocks) * kTeamWords * sizeof(unsigned int)));
+    HIPCHK(ctx, hipMalloc(&b->d_team_part, (size_t)2 * kQ_batch * b->max_blocks * sizeof(double)));
     HIPCHK(ctx, hipStreamCreateWithFlags(&b->cs, hipStreamNonBlocking));
     BatchParams& P = b->P;
     P.items = b->d_items;
@@ -1195,6 +1236,12 @@ LJ_API int lj_batch_stats(lj_batch* b, lj_stats* per_instance, void* stream) {
   return guarded(ctx, [&]() {
     const hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     HIPCHK(ctx, hipStreamSynchronize(s));
+    unsigned int qw[2] = {0, 0};
+    HIPCHK(ctx, hipMemcpy(qw, b->d_queue, sizeof(qw), hipMemcpyDeviceToHost));
+    if (qw[1] != 0u) {
+      ctx->err = "batch launch aborted: a team barrier timed out (blocks of a team were not co-resident)";
+      throw Fail{LJ_EHIP};
+    }
     HIPCHK(ctx, hipMemcpy(b->h_status, b->d_status, b->n * sizeof(BatchStatus), hipMemcpyDeviceToHost));
     bool all_ok = true;
     double bytes = 0.0;
@@ -1265,6 +1312,7 @@ LJ_API int lj_batch_info(const lj_batch* b, lj_batch_info_t* out) {
   out->schedule = b->schedule;
   out->block_size = S.block;
   out->blocks = b->ctx->num_cus * S.per_cu;
+  out->team = S.team;
   out->largest_first = S.largest_first;
   out->nschedules = kNumBatchSchedules;
   for (int i = 0; i < kNumBatchSchedules && i < 8; ++i) out->tune_ms[i] = b->tune_ms[i];

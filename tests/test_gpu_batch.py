@@ -97,11 +97,13 @@ def test_batch_schedules_agree_and_tuner_reports(env):
     bounds = [power_iteration(Operator(p).jv, p.n) for p in probs]
     ref = None
     try:
-        for sched in range(5):
+        for sched in range(8):
             os.environ["LJ_BATCH_SCHEDULE"] = str(sched)
             b, ws, _ = make_batch(lj, torch, ctx, probs, hs, vs, bounds=bounds)
             info = b.info()
+            say("schedule", sched, info["block_size"], info["team"])
             assert info["schedule"] == sched and info["block_size"] in (256, 512, 1024)
+            assert info["team"] in (1, 2, 4, 8, 16)
             b.run()
             rc, sts = b.stats()
             assert rc == 0
@@ -123,7 +125,7 @@ def test_batch_schedules_agree_and_tuner_reports(env):
     vs2 = [h * Operator(p).rhs(p.state) for p, h in zip(probs2, hs2)]
     b1, _, _ = make_batch(lj, torch, ctx, probs2, hs2, vs2)
     i1 = b1.info()
-    assert len(i1["tune_ms"]) == i1["nschedules"] == 5 and all(t > 0 for t in i1["tune_ms"])
+    assert len(i1["tune_ms"]) == i1["nschedules"] == 8 and all(t > 0 for t in i1["tune_ms"])
     assert i1["tune_ms"][i1["schedule"]] == min(i1["tune_ms"])
     b2, _, _ = make_batch(lj, torch, ctx, probs2, hs2, vs2)
     i2 = b2.info()
