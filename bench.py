@@ -12,6 +12,10 @@ Leja iteration kernel, timed with HIP events on its launch stream over the
 timed region; `cpu_baseline` times the CPU oracle on a bounded sample.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+       python bench.py --form batch [--steps K] [--warmup W]
+                        (the batching form: 256 uneven Allen-Cahn instances,
+                         phi_1..phi_3 per instance in one graph-captured launch,
+                         against the per-instance plain path)
        python bench.py --copy-calibration   (plain copy kernel for counter scaling)
 """
 from __future__ import annotations
@@ -32,17 +36,18 @@ CFL_MULT = 10.0
 ACTIONS_PER_STEP = 7
 METRIC = "\u03c6_l(hJ)v actions/sec + HBM GB/s (% peak), 512\u00b2 Allen\u2013Cahn, tol 1e-10"
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "leja_kernel_allen_cahn_512_traffic.json")
+BATCH_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "batch_kernel_allen_cahn_256_instances_traffic.json")
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def measured_traffic():
+def measured_traffic(path=TRAFFIC_FILE):
     """HBM bytes per fused-kernel launch from committed rocprofv3 counter runs,
     if they were taken on the current kernel source; else None."""
     try:
-        with open(TRAFFIC_FILE) as fh:
+        with open(path) as fh:
             t = json.load(fh)
     except (OSError, ValueError):
         return None
@@ -103,6 +108,75 @@ def cpu_baseline(prob, h):
                       f"FP64 NumPy oracle on 1 core, {dt:.1f} s; host nproc={os.cpu_count()}"}
 
 
+def bench_batch(args):
+    """The batching form on the 256-instance ensemble: one graph replay runs
+    phi_1, phi_2, phi_3 of h_i f(u_i) for every instance (768 actions)."""
+    import torch
+
+    import paper_2211_08948_amd as lj
+    from workloads import batch_instances
+    probs = batch_instances()
+    hs = [CFL_MULT * p.h_cfl for p in probs]
+    ctx = lj.Context(0)
+    ops = [lj.operator_from(p, "cuda:0") for p in probs]
+    vs = []
+    for J, h in zip(ops, hs):
+        f = torch.empty_like(J.state)
+        lj.lj_rhs(ctx, J, J.state, f)
+        vs.append((h * f).contiguous())
+    ws = [[torch.empty_like(v) for _ in range(3)] for v in vs]
+    b = lj.Batch(ctx, ops, vs, hs, [1, 2, 3], [1.0, 1.0, 1.0], TOL, ws)
+    for _ in range(args.warmup):
+        b.run()
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record(stream)
+    for _ in range(args.steps):
+        b.run(stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    ms = e0.elapsed_time(e1) / args.steps
+    rc, sts = b.stats(stream)
+    info = b.info()
+    rejected = sum(1 for st in sts if st["rejections"] > 0)
+    # the same work through the plain path: one vertical call per instance
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for i in range(len(probs)):
+        lj.lj_phi_vertical(ctx, ops[i], vs[i], [1, 2, 3], [1.0] * 3, hs[i], TOL, ws[i])
+    torch.cuda.synchronize()
+    plain_ms = (time.perf_counter() - t) * 1e3
+    actions = 3 * len(probs)
+    achieved = info["alg_bytes"] / (ms * 1e-3) / 1e9
+    traffic = measured_traffic(BATCH_TRAFFIC_FILE)
+    log(f"batch {ms:.3f} ms per launch (schedule {info['schedule']}: {info['block_size']} threads, team "
+        f"{info['team']}), {info['alg_bytes'] / 1e9:.2f} GB algorithmic, {rejected} instances redone with "
+        f"substeps; plain path {plain_ms:.1f} ms")
+    out = {
+        "metric": "\u03c6_l(hJ)v actions/sec, batching form: 256 uneven Allen\u2013Cahn instances, tol 1e-10",
+        "value": round(actions / (ms * 1e-3), 1), "unit": "phi-actions/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(dt / args.steps * 1e3, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "256 Allen-Cahn instances, n in {128,192,256,384,512} uniform, eps log-uniform "
+                               "[1e-4,1e-2] (seed 4), u0 seed 4000+i, h_i = 10x CFL_i, phi_1..phi_3 vertical, "
+                               "tol 1e-10, one graph-captured launch",
+                   "instances": len(probs), "total_points": int(info["total_values"]),
+                   "schedule": {"block_size": info["block_size"], "team": info["team"]}},
+        "speedup_vs_plain_vertical": round(plain_ms / ms, 2),
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                     "kernel": "lj_batch_kernel", "avg_launch_us": round(ms * 1e3, 1),
+                     "algorithmic_bytes_per_launch": round(info["alg_bytes"])},
+        "cpu_baseline": None,
+    }
+    b.close()
+    ctx.close()
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -111,6 +185,7 @@ def main():
     ap.add_argument("--n", type=int, default=512, help="grid points per axis (default: the 512^2 workload)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true")
+    ap.add_argument("--form", choices=["plain", "batch"], default="plain")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}): the multi-GPU path is not "
@@ -118,6 +193,9 @@ def main():
         sys.exit(2)
     if args.copy_calibration:
         copy_calibration()
+        return
+    if args.form == "batch":
+        bench_batch(args)
         return
 
     import torch

@@ -1,0 +1,124 @@
+"""Features of the learned proposal -- TEST INFRASTRUCTURE (plain FP64 NumPy).
+
+The learned form (not in the paper; it replaces the power iteration of
+Sec. 2.2 and the rejected expansions of its last paragraph when it can)
+predicts the spectral bound and the substep count of a phi_l(hJ)v action from
+16 dimensionless numbers of the operator, the state and h.  This module is the
+plain definition the HIP feature kernel is checked against.
+
+Scales of one problem (grid spacing dx, dy; diffusion coefficient D):
+  sigma = D (1/dx^2 + 1/dy^2)           diffusive rate
+  A                                    advective rate: |a_x|/dx + |a_y|/dy for
+                                       advection-diffusion, max|u| (1/dx + 1/dy)
+                                       for Burgers, 0 otherwise
+  r(x)                                 local reaction rate of J: 1 - 3u^2
+                                       (Allen-Cahn), -(d_x u + d_y u) with centred
+                                       differences (Burgers), -(b+1) + 2uv
+                                       (Brusselator, first species), 0 otherwise
+  D = nu (adv.-diff., Burgers), eps (Allen-Cahn), max(Du, Dv) (Brusselator);
+  for a diagonal operator sigma = max|lambda| and A = r = 0.
+State statistics (first component u, over all grid points): mean, standard
+deviation (population), max|u|, and g = max |grad u| dx in grid units,
+g = max sqrt(((u_E - u_W)/2)^2 + ((u_N - u_S)/2)^2).
+
+features[0..15] =
+  log10(h sigma), l/4, log10(1 + A/sigma), log10(1 + max(r_max,0)/sigma),
+  log10(1 + max(-r_min,0)/sigma), log10(1 + h A), log10(1 + h max(r_max,0)),
+  log10(1 + h max(-r_min,0)), mean/max|u|, std/max|u|, log10(1 + max|u|),
+  log10(1 + g), log10(nx ny)/7, log10(dx/dy), log10(1 + h sigma), ncomp - 1
+(the state ratios are 0 for an operator without state or a zero state).
+
+Targets of the network: ln(bound / sigma) and log2(accepted substeps).
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+NFEAT = 16
+
+
+def scales(prob):
+    """(sigma, A, r) of a workloads.Problem; r is an array over grid points (or None)."""
+    kind, nx, ny = prob.kind, prob.nx, prob.ny
+    if kind == "diag":
+        lam = np.asarray(prob.state, dtype=np.float64)
+        return float(np.max(np.abs(lam))), 0.0, None
+    dx, dy = prob.dx, prob.dy
+    c = prob.coef
+    if kind == "advdiff":
+        D = c[0]
+        A = abs(c[1]) / dx + abs(c[2]) / dy
+        r = None
+    elif kind == "allencahn":
+        D = c[0]
+        u = np.asarray(prob.state, dtype=np.float64)
+        A = 0.0
+        r = 1.0 - 3.0 * u * u
+    elif kind == "burgers":
+        D = c[0]
+        U = np.asarray(prob.state, dtype=np.float64).reshape(ny, nx)
+        A = float(np.max(np.abs(U))) * (1.0 / dx + 1.0 / dy)
+        dudx = (np.roll(U, -1, axis=1) - np.roll(U, 1, axis=1)) / (2.0 * dx)
+        dudy = (np.roll(U, -1, axis=0) - np.roll(U, 1, axis=0)) / (2.0 * dy)
+        r = -(dudx + dudy).ravel()
+    elif kind == "brusselator":
+        D = max(c[0], c[1])
+        st = np.asarray(prob.state, dtype=np.float64)
+        u, v = st[0::2], st[1::2]
+        A = 0.0
+        r = -(c[3] + 1.0) + 2.0 * u * v
+    else:
+        raise ValueError(kind)
+    sigma = D * (1.0 / (dx * dx) + 1.0 / (dy * dy))
+    return sigma, A, r
+
+
+def state_stats(prob):
+    """(mean, std, max|u|, g) of the first state component; zeros without state."""
+    if prob.kind in ("advdiff", "diag") or prob.state is None:
+        return 0.0, 0.0, 0.0, 0.0
+    st = np.asarray(prob.state, dtype=np.float64)
+    u = st[0::prob.ncomp]
+    U = u.reshape(prob.ny, prob.nx)
+    gx = (np.roll(U, -1, axis=1) - np.roll(U, 1, axis=1)) / 2.0
+    gy = (np.roll(U, -1, axis=0) - np.roll(U, 1, axis=0)) / 2.0
+    g = float(np.max(np.sqrt(gx * gx + gy * gy)))
+    return float(np.mean(u)), float(np.std(u)), float(np.max(np.abs(u))), g
+
+
+def features(prob, h: float, l: int) -> np.ndarray:
+    """The 16 features of (operator at state, h, l), in FP64."""
+    sigma, A, r = scales(prob)
+    rmax = float(np.max(r)) if r is not None else 0.0
+    rmin = float(np.min(r)) if r is not None else 0.0
+    mean, std, umax, g = state_stats(prob)
+    dx = prob.dx if prob.kind != "diag" else 1.0
+    dy = prob.dy if prob.kind != "diag" else 1.0
+    den = umax if umax > 0.0 else math.inf
+    f = [
+        math.log10(h * sigma),
+        l / 4.0,
+        math.log10(1.0 + A / sigma),
+        math.log10(1.0 + max(rmax, 0.0) / sigma),
+        math.log10(1.0 + max(-rmin, 0.0) / sigma),
+        math.log10(1.0 + h * A),
+        math.log10(1.0 + h * max(rmax, 0.0)),
+        math.log10(1.0 + h * max(-rmin, 0.0)),
+        mean / den,
+        std / den,
+        math.log10(1.0 + umax),
+        math.log10(1.0 + g),
+        math.log10(prob.nx * prob.ny) / 7.0,
+        math.log10(dx / dy),
+        math.log10(1.0 + h * sigma),
+        float(prob.ncomp - 1),
+    ]
+    return np.asarray(f, dtype=np.float64)
+
+
+def targets(prob, bound: float, substeps: int) -> np.ndarray:
+    """(ln(bound / sigma), log2(substeps))."""
+    sigma, _, _ = scales(prob)
+    return np.asarray([math.log(bound / sigma), math.log2(substeps)], dtype=np.float64)
