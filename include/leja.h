@@ -92,6 +92,9 @@ typedef struct {
   int32_t substeps;       /* > 1: start with this many substeps; 0 */
   uint64_t power_seed;    /* SplitMix64 seed of the power-iteration start vector; 0x5EED */
   const double* pi_start; /* device: explicit start vector (n entries) or NULL */
+  int32_t use_proposal;   /* 1: the learned proposal supplies the bound and the substep count
+                             (lj_phi_action / lj_phi_vertical); the plain path is the fallback; 0 */
+  int32_t reserved;
 } lj_options;
 
 /* Per-call statistics (host struct).  For a vertical call entry k describes
@@ -108,6 +111,9 @@ typedef struct {
   int32_t converged;          /* 1 if every accumulator converged */
   double bound;               /* lambda_hat used */
   double c, gamma;            /* interval centre and quarter-length (Sec. 2.2) */
+  int32_t fallbacks;          /* 1 if the learned proposal failed and the plain path ran */
+  int32_t proposal_substeps;  /* substeps the proposal chose (0: no proposal) */
+  double proposal_bound;      /* bound the proposal chose (0: no proposal) */
 } lj_stats;
 
 /* ---- context --------------------------------------------------------- */
@@ -240,6 +246,55 @@ LJ_API int lj_batch_info(const lj_batch* b, lj_batch_info_t* out);
  * microseconds after the earliest start (host arrays of n entries). */
 LJ_API int lj_batch_timeline(const lj_batch* b, int* block, double* start_us, double* end_us);
 LJ_API void lj_batch_destroy(lj_batch* b);
+
+/* ---- learned proposal ---------------------------------------------------- */
+
+/* Not in the paper: a small network proposes, for an action phi_l(hJ)v, the
+ * spectral bound (replacing the power iteration of Sec. 2.2) and the substep
+ * count (skipping expansions that would be rejected).  With
+ * opt->use_proposal = 1, lj_phi_action / lj_phi_vertical compute the features,
+ * run the network, and attempt the expansion once with bound =
+ * LJ_PROPOSAL_MARGIN * sigma * exp(out[0]) (sigma the diffusive rate of the
+ * features) and s = 2^round(out[1]) substeps; every accumulator that this
+ * attempt does not converge is redone by the plain path (power iteration,
+ * then s = 1, 2, 4, ...), whose stop test remains the judge of the error.
+ *
+ * Network: 16 -> 64 -> 64 -> 2, tanh hidden units, FP32; inputs and targets
+ * standardised with constants kept in the model.  Model layout (floats):
+ * W1 (64x16, row-major), b1 (64), W2 (64x64), b2 (64), W3 (2x64), b3 (2),
+ * feature mean (16), feature std (16), target mean (2), target std (2).
+ * Targets: ln(bound / sigma) and log2(accepted substeps).  Features: 16
+ * dimensionless numbers of the operator, its state, h and l (the 16 values
+ * are documented with the CPU reference implementation). */
+#define LJ_NFEATURES 16
+#define LJ_MLP_NPARAM 5378
+#define LJ_MLP_MODEL_FLOATS 5414
+#define LJ_PROPOSAL_MARGIN 1.1
+
+/* feats (device, 16 floats) = the features of phi_l(h J) v. */
+LJ_API int lj_features(lj_context* ctx, const lj_operator* J, double h, int l, float* feats, void* stream);
+/* Glorot-uniform weights from SplitMix64(seed) in parameter order, zero
+ * biases, identity standardisation, Adam state cleared. */
+LJ_API int lj_mlp_init(lj_context* ctx, uint64_t seed);
+/* Trains on n samples (feats: device n x 16, targets: device n x 2) for
+ * `epochs` passes in minibatches of `batch` (<= 512) samples, in order, one
+ * Adam step (learning rate lr) per minibatch; with fit_normalization = 1 the
+ * standardisation constants are first set from the data.  loss_per_epoch
+ * (host, epochs floats, may be NULL) receives the mean squared error of each
+ * epoch in standardised units.  Synchronises the stream. */
+LJ_API int lj_mlp_train(lj_context* ctx, const float* feats, const float* targets, int n, int epochs, int batch,
+                        float lr, int fit_normalization, float* loss_per_epoch, void* stream);
+/* out (device, n x 2) = network outputs in target units for n feature rows. */
+LJ_API int lj_mlp_predict(lj_context* ctx, const float* feats, int n, float* out, void* stream);
+/* grad (device, LJ_MLP_NPARAM floats) = gradient of the mean loss over the n
+ * samples at the current weights; *loss (host) = that loss.  Synchronises. */
+LJ_API int lj_mlp_grad(lj_context* ctx, const float* feats, const float* targets, int n, float* grad, float* loss,
+                       void* stream);
+/* Model transfer (host arrays of LJ_MLP_MODEL_FLOATS floats) and files. */
+LJ_API int lj_mlp_get(lj_context* ctx, float* model);
+LJ_API int lj_mlp_set(lj_context* ctx, const float* model);
+LJ_API int lj_mlp_save(lj_context* ctx, const char* path);
+LJ_API int lj_mlp_load(lj_context* ctx, const char* path);
 
 /* ---- measurement ------------------------------------------------------------ */
 

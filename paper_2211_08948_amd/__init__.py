@@ -313,6 +313,73 @@ def lj_batch_create(ctx: Context, ops, vs, hs, ls, As, tol, ws, bounds=None, opt
     return Batch(ctx, ops, vs, hs, ls, As, tol, ws, bounds, opt)
 
 
+# ---- learned proposal -------------------------------------------------------
+def _ftensor_ptr(t, n: int, what: str) -> C.c_void_p:
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != torch.float32 or not t.is_contiguous():
+        raise ValueError(f"{what} must be a contiguous float32 CUDA tensor")
+    if t.numel() != n:
+        raise ValueError(f"{what} has {t.numel()} entries, expected {n}")
+    return C.c_void_p(t.data_ptr())
+
+
+def lj_features(ctx: Context, J: Operator, h: float, l: int, feats, stream=None) -> None:
+    """feats (float32 CUDA tensor of 16) = features of phi_l(h J) v."""
+    op = J.c_struct()
+    ctx._check(ctx._lib.lj_features(ctx.handle, C.byref(op), float(h), int(l),
+                                    _ftensor_ptr(feats, _lib.LJ_NFEATURES, "feats"), _stream_ptr(stream)), False)
+
+
+def lj_mlp_init(ctx: Context, seed: int = 6) -> None:
+    ctx._check(ctx._lib.lj_mlp_init(ctx.handle, C.c_uint64(seed)), False)
+
+
+def lj_mlp_train(ctx: Context, feats, targets, epochs: int, batch: int = 256, lr: float = 1e-3,
+                 fit_normalization: bool = True, stream=None):
+    """Trains on (feats n x 16, targets n x 2) float32 CUDA tensors; returns the per-epoch losses."""
+    n = feats.shape[0]
+    losses = (C.c_float * epochs)()
+    ctx._check(ctx._lib.lj_mlp_train(ctx.handle, _ftensor_ptr(feats, n * 16, "feats"),
+                                     _ftensor_ptr(targets, n * 2, "targets"), int(n), int(epochs), int(batch),
+                                     float(lr), 1 if fit_normalization else 0, losses, _stream_ptr(stream)), False)
+    return list(losses)
+
+
+def lj_mlp_predict(ctx: Context, feats, out, stream=None) -> None:
+    n = feats.shape[0]
+    ctx._check(ctx._lib.lj_mlp_predict(ctx.handle, _ftensor_ptr(feats, n * 16, "feats"), int(n),
+                                       _ftensor_ptr(out, n * 2, "out"), _stream_ptr(stream)), False)
+
+
+def lj_mlp_grad(ctx: Context, feats, targets, grad, stream=None) -> float:
+    n = feats.shape[0]
+    loss = C.c_float()
+    ctx._check(ctx._lib.lj_mlp_grad(ctx.handle, _ftensor_ptr(feats, n * 16, "feats"),
+                                    _ftensor_ptr(targets, n * 2, "targets"), int(n),
+                                    _ftensor_ptr(grad, _lib.LJ_MLP_NPARAM, "grad"), C.byref(loss),
+                                    _stream_ptr(stream)), False)
+    return loss.value
+
+
+def lj_mlp_get(ctx: Context):
+    buf = (C.c_float * _lib.LJ_MLP_MODEL_FLOATS)()
+    ctx._check(ctx._lib.lj_mlp_get(ctx.handle, buf), False)
+    return list(buf)
+
+
+def lj_mlp_set(ctx: Context, model) -> None:
+    buf = (C.c_float * _lib.LJ_MLP_MODEL_FLOATS)(*[float(x) for x in model])
+    ctx._check(ctx._lib.lj_mlp_set(ctx.handle, buf), False)
+
+
+def lj_mlp_save(ctx: Context, path: str) -> None:
+    ctx._check(ctx._lib.lj_mlp_save(ctx.handle, str(path).encode()), False)
+
+
+def lj_mlp_load(ctx: Context, path: str) -> None:
+    ctx._check(ctx._lib.lj_mlp_load(ctx.handle, str(path).encode()), False)
+
+
 def operator_from(prob, device: str = "cuda") -> Operator:
     """Operator for any object with kind, nx, ny, ncomp, dx, dy, coef and a
     numpy `state` (or None); the state is copied to a float64 device tensor."""

@@ -15,6 +15,9 @@ LJ_OK, LJ_ENOTCONV, LJ_EINVAL, LJ_EHIP, LJ_ENOMEM = 0, 1, -1, -2, -3
 LJ_MAX_K = 4
 LJ_MAX_L = 4
 LJ_MAX_POINTS = 100
+LJ_NFEATURES = 16
+LJ_MLP_NPARAM = 5378
+LJ_MLP_MODEL_FLOATS = 5414
 
 LJ_OP_DIAG, LJ_OP_ADVDIFF2D, LJ_OP_ALLENCAHN2D, LJ_OP_BRUSSELATOR2D, LJ_OP_BURGERS2D = range(5)
 LJ_EXPRB2, LJ_EXPRB43_U3, LJ_EXPRB43, LJ_EPIRK4S3 = 1, 2, 3, 4
@@ -36,7 +39,7 @@ class lj_options(C.Structure):
         ("safety", C.c_double), ("power_iters", C.c_int32), ("max_points", C.c_int32),
         ("hump_max", C.c_double), ("max_substeps", C.c_int32), ("relative_tol", C.c_int32),
         ("bound", C.c_double), ("substeps", C.c_int32), ("power_seed", C.c_uint64),
-        ("pi_start", C.c_void_p),
+        ("pi_start", C.c_void_p), ("use_proposal", C.c_int32), ("reserved", C.c_int32),
     ]
 
 
@@ -45,7 +48,8 @@ class lj_stats(C.Structure):
         ("m_star", C.c_int32 * LJ_MAX_K), ("substeps", C.c_int32 * LJ_MAX_K),
         ("err_est", C.c_double * LJ_MAX_K), ("iters_total", C.c_int32), ("power_iters", C.c_int32),
         ("rejections", C.c_int32), ("converged", C.c_int32), ("bound", C.c_double),
-        ("c", C.c_double), ("gamma", C.c_double),
+        ("c", C.c_double), ("gamma", C.c_double), ("fallbacks", C.c_int32),
+        ("proposal_substeps", C.c_int32), ("proposal_bound", C.c_double),
     ]
 
     def as_dict(self, K: int = LJ_MAX_K) -> dict:
@@ -54,6 +58,8 @@ class lj_stats(C.Structure):
             "err_est": list(self.err_est)[:K], "iters_total": self.iters_total,
             "power_iters": self.power_iters, "rejections": self.rejections,
             "converged": bool(self.converged), "bound": self.bound, "c": self.c, "gamma": self.gamma,
+            "fallbacks": self.fallbacks, "proposal_substeps": self.proposal_substeps,
+            "proposal_bound": self.proposal_bound,
         }
 
 
@@ -105,6 +111,15 @@ _PROTOS = {
     "lj_batch_info": (C.c_int, [_P, C.POINTER(lj_batch_info_t)]),
     "lj_batch_timeline": (C.c_int, [_P, C.POINTER(C.c_int), C.POINTER(C.c_double), C.POINTER(C.c_double)]),
     "lj_batch_destroy": (None, [_P]),
+    "lj_features": (C.c_int, [_P, C.POINTER(lj_operator), C.c_double, C.c_int, _P, _P]),
+    "lj_mlp_init": (C.c_int, [_P, C.c_uint64]),
+    "lj_mlp_train": (C.c_int, [_P, _P, _P, C.c_int, C.c_int, C.c_int, C.c_float, C.c_int, C.POINTER(C.c_float), _P]),
+    "lj_mlp_predict": (C.c_int, [_P, _P, C.c_int, _P, _P]),
+    "lj_mlp_grad": (C.c_int, [_P, _P, _P, C.c_int, _P, C.POINTER(C.c_float), _P]),
+    "lj_mlp_get": (C.c_int, [_P, C.POINTER(C.c_float)]),
+    "lj_mlp_set": (C.c_int, [_P, C.POINTER(C.c_float)]),
+    "lj_mlp_save": (C.c_int, [_P, C.c_char_p]),
+    "lj_mlp_load": (C.c_int, [_P, C.c_char_p]),
 }
 
 _lib = None

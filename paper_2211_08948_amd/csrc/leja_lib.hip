@@ -17,6 +17,7 @@
 #include "../../include/leja.h"
 #include "common.hpp"
 #include "kernels.hpp"
+#include "mlp.hpp"
 
 namespace lj {
 int leja_points_host(double* out, int count);
@@ -65,6 +66,17 @@ struct lj_context {
   lj_timing tm = {};
   // batching form: schedule picked by the tuner, per batch shape
   std::map<std::string, int> batch_schedule;
+  // learned proposal
+  float* d_model = nullptr;  // kModelFloats
+  float* d_adam = nullptr;   // m | v (kMlpParams each)
+  int* d_adam_t = nullptr;
+  float* d_rows = nullptr;   // kMlpBlock x kMlpRowFloats training scratch
+  float* d_scalars = nullptr;  // loss of lj_mlp_grad, epoch losses (kMaxEpochs)
+  void* d_featpart = nullptr;
+  float* d_feats = nullptr;  // kMaxK x 16
+  float* d_pred = nullptr;   // kMaxK x 2
+  double* d_sigma = nullptr;
+  bool mlp_ready = false;
 };
 
 static std::string g_create_error;
@@ -105,6 +117,7 @@ double* slot(lj_context* ctx, int s, size_t n) {
 }
 
 struct Opts {
+  int use_proposal;
   double safety;
   int power_iters;
   int max_points;
@@ -121,8 +134,8 @@ Opts resolve(lj_context* ctx, const lj_options* o) {
   lj_options d;
   lj_default_options(&d);
   if (!o) o = &d;
-  Opts r{o->safety, o->power_iters, o->max_points, o->hump_max, o->max_substeps, o->relative_tol,
-         o->bound, o->substeps, o->power_seed, o->pi_start};
+  Opts r{o->use_proposal, o->safety, o->power_iters, o->max_points, o->hump_max, o->max_substeps,
+         o->relative_tol, o->bound, o->substeps, o->power_seed, o->pi_start};
   if (!(r.safety > 0.0) || !std::isfinite(r.safety)) invalid(ctx, "options: safety must be > 0");
   if (r.power_iters < 1 || r.power_iters > 100000) invalid(ctx, "options: power_iters out of range");
   if (r.max_points < 1 || r.max_points > kMaxPoints) invalid(ctx, "options: max_points must be in [1, 100]");
@@ -552,6 +565,81 @@ void check_action_args(lj_context* ctx, const OpDev& op, const double* v, int K,
   }
 }
 
+// ---- learned proposal --------------------------------------------------------
+constexpr int kMaxEpochs = 4096;
+
+void mlp_alloc(lj_context* ctx) {
+  if (ctx->d_model) return;
+  HIPCHK(ctx, hipMalloc(&ctx->d_model, kModelFloats * sizeof(float)));
+  HIPCHK(ctx, hipMalloc(&ctx->d_adam, 2 * kMlpParams * sizeof(float)));
+  HIPCHK(ctx, hipMalloc(&ctx->d_adam_t, sizeof(int)));
+  HIPCHK(ctx, hipMalloc(&ctx->d_rows, (size_t)kMlpBlock * kMlpRowFloats * sizeof(float)));
+  HIPCHK(ctx, hipMalloc(&ctx->d_scalars, (1 + kMaxEpochs) * sizeof(float)));
+  HIPCHK(ctx, hipMalloc(&ctx->d_featpart, feature_partial_bytes()));
+  HIPCHK(ctx, hipMalloc(&ctx->d_feats, kMaxK * kMlpIn * sizeof(float)));
+  HIPCHK(ctx, hipMalloc(&ctx->d_pred, kMaxK * kMlpOut * sizeof(float)));
+  HIPCHK(ctx, hipMalloc(&ctx->d_sigma, sizeof(double)));
+}
+
+// Glorot uniform weights a (2U - 1), a = sqrt(6 / (fan_in + fan_out)), U the
+// SplitMix64 uniforms of the seed in parameter order; zero biases; identity
+// standardisation.
+void mlp_host_init(uint64_t seed, std::vector<float>& m) {
+  m.assign(kModelFloats, 0.0f);
+  auto fill = [&](int off, int fo, int fi) {
+    const double a = std::sqrt(6.0 / (fo + fi));
+    for (int i = 0; i < fo * fi; ++i) {
+      uint64_t z = seed + (uint64_t)(off + i + 1) * 0x9E3779B97F4A7C15ull;
+      z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+      z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+      z = z ^ (z >> 31);
+      const double u = (double)(z >> 11) * 0x1.0p-53;
+      m[off + i] = (float)(a * (2.0 * u - 1.0));
+    }
+  };
+  fill(kOffW1, kMlpHidden, kMlpIn);
+  fill(kOffW2, kMlpHidden, kMlpHidden);
+  fill(kOffW3, kMlpOut, kMlpHidden);
+  for (int k = 0; k < kMlpIn; ++k) m[kMlpParams + kMlpIn + k] = 1.0f;             // sd
+  for (int k = 0; k < kMlpOut; ++k) m[kMlpParams + 2 * kMlpIn + kMlpOut + k] = 1.0f;  // tsd
+}
+
+void check_fvec(lj_context* ctx, const void* p, size_t count, const char* what) {
+  if (!p) invalid(ctx, std::string(what) + " is NULL");
+  if (reinterpret_cast<uintptr_t>(p) & 3) invalid(ctx, std::string(what) + " is misaligned");
+  check_range(ctx, p, count * sizeof(float), what);
+}
+
+// The proposal for the K actions phi_{l_k}(a_k h J) v: bound and substeps.
+void propose(lj_context* ctx, const OpDev& op, int K, const int* l, const double* a, double h, hipStream_t s,
+             double& bound, int& substeps) {
+  if (!ctx->mlp_ready) invalid(ctx, "use_proposal: no trained network (lj_mlp_train, lj_mlp_set or lj_mlp_load)");
+  FeatureJob J;
+  std::memset(&J, 0, sizeof(J));
+  J.op = op;
+  J.K = K;
+  for (int k = 0; k < K; ++k) {
+    J.h[k] = a[k] * h;
+    J.l[k] = l[k];
+  }
+  HIPCHK(ctx, launch_features(J, ctx->d_featpart, ctx->d_feats, ctx->d_sigma, s));
+  HIPCHK(ctx, launch_mlp_forward(ctx->d_model, ctx->d_feats, K, ctx->d_pred, s));
+  float pred[kMaxK * kMlpOut];
+  double sigma = 0.0;
+  HIPCHK(ctx, hipMemcpyAsync(pred, ctx->d_pred, K * kMlpOut * sizeof(float), hipMemcpyDeviceToHost, s));
+  HIPCHK(ctx, hipMemcpyAsync(&sigma, ctx->d_sigma, sizeof(double), hipMemcpyDeviceToHost, s));
+  HIPCHK(ctx, hipStreamSynchronize(s));
+  double lb = pred[0], ls = pred[1];
+  for (int k = 1; k < K; ++k) {
+    lb = std::max(lb, (double)pred[kMlpOut * k]);
+    ls = std::max(ls, (double)pred[kMlpOut * k + 1]);
+  }
+  bound = LJ_PROPOSAL_MARGIN * sigma * std::exp(std::min(lb, 50.0));
+  if (!(bound > 0.0) || !std::isfinite(bound)) bound = 0.0;  // unusable: the plain path decides
+  const int e = (int)std::lround(std::min(std::max(ls, 0.0), 20.0));
+  substeps = 1 << e;
+}
+
 template <class F>
 int guarded(lj_context* ctx, F&& f) {
   if (!ctx) return LJ_EINVAL;
@@ -835,6 +923,15 @@ LJ_API void lj_destroy(lj_context* ctx) {
   if (ctx->d_partials) (void)hipFree(ctx->d_partials);
   if (ctx->d_barrier) (void)hipFree(ctx->d_barrier);
   if (ctx->d_status) (void)hipFree(ctx->d_status);
+  if (ctx->d_model) (void)hipFree(ctx->d_model);
+  if (ctx->d_adam) (void)hipFree(ctx->d_adam);
+  if (ctx->d_adam_t) (void)hipFree(ctx->d_adam_t);
+  if (ctx->d_rows) (void)hipFree(ctx->d_rows);
+  if (ctx->d_scalars) (void)hipFree(ctx->d_scalars);
+  if (ctx->d_featpart) (void)hipFree(ctx->d_featpart);
+  if (ctx->d_feats) (void)hipFree(ctx->d_feats);
+  if (ctx->d_pred) (void)hipFree(ctx->d_pred);
+  if (ctx->d_sigma) (void)hipFree(ctx->d_sigma);
   if (ctx->h_status) (void)hipHostFree(ctx->h_status);
   if (ctx->h_coef) (void)hipHostFree(ctx->h_coef);
   for (int i = 0; i < 4; ++i)
@@ -903,7 +1000,53 @@ LJ_API int lj_phi_vertical(lj_context* ctx, const lj_operator* J, const double* 
     if (o.pi_start) check_vec(ctx, op, o.pi_start, "pi_start");
     lj_stats local;
     lj_stats* st = stats ? stats : &local;
-    return vertical_impl(ctx, op, v, K, l, a, h, tol, w, o, st, reinterpret_cast<hipStream_t>(stream));
+    const hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    if (!o.use_proposal) return vertical_impl(ctx, op, v, K, l, a, h, tol, w, o, st, s);
+    // learned proposal: one attempt with the proposed bound and substeps ...
+    double pb = 0.0;
+    int ps = 1;
+    propose(ctx, op, K, l, a, h, s, pb, ps);
+    int rc = LJ_ENOTCONV;
+    if (pb > 0.0 && ps <= o.max_substeps) {
+      Opts o1 = o;
+      o1.bound = pb;
+      o1.substeps = (ps > 1) ? ps : 0;
+      o1.max_substeps = ps;
+      rc = vertical_impl(ctx, op, v, K, l, a, h, tol, w, o1, st, s);
+    } else {
+      std::memset(st, 0, sizeof(*st));
+      for (int k = 0; k < LJ_MAX_K; ++k) st->m_star[k] = -1;
+    }
+    st->proposal_bound = pb;
+    st->proposal_substeps = ps;
+    if (rc == LJ_OK) return LJ_OK;
+    // ... and the plain path for every accumulator it did not converge
+    std::vector<int> pk, pl;
+    std::vector<double> pa;
+    std::vector<double*> pw;
+    for (int k = 0; k < K; ++k) {
+      if (st->m_star[k] >= 0) continue;
+      pk.push_back(k);
+      pl.push_back(l[k]);
+      pa.push_back(a[k]);
+      pw.push_back(w[k]);
+    }
+    lj_stats fb;
+    const int rc2 = vertical_impl(ctx, op, v, (int)pk.size(), pl.data(), pa.data(), h, tol, pw.data(), o, &fb, s);
+    st->fallbacks = 1;
+    st->rejections += fb.rejections;  // the proposal's failed attempt is already counted
+    st->iters_total += fb.iters_total;
+    st->power_iters += fb.power_iters;
+    st->bound = fb.bound;
+    st->c = fb.c;
+    st->gamma = fb.gamma;
+    for (size_t q = 0; q < pk.size(); ++q) {
+      st->m_star[pk[q]] = fb.m_star[q];
+      st->substeps[pk[q]] = fb.substeps[q];
+      st->err_est[pk[q]] = fb.err_est[q];
+    }
+    st->converged = fb.converged;
+    return rc2;
   });
 }
 
@@ -1109,6 +1252,152 @@ LJ_API int lj_timing_read(lj_context* ctx, lj_timing* out, int reset) {
   *out = ctx->tm;
   if (reset) std::memset(&ctx->tm, 0, sizeof(ctx->tm));
   return LJ_OK;
+}
+
+// ---- learned proposal ------------------------------------------------------
+LJ_API int lj_features(lj_context* ctx, const lj_operator* J, double h, int l, float* feats, void* stream) {
+  return guarded(ctx, [&]() {
+    const OpDev op = make_op(ctx, J);
+    if (!std::isfinite(h) || !(h > 0.0)) invalid(ctx, "h must be finite and > 0");
+    if (l < 0 || l > LJ_MAX_L) invalid(ctx, "l must be in [0, 4]");
+    check_fvec(ctx, feats, kMlpIn, "feats");
+    mlp_alloc(ctx);
+    FeatureJob Jb;
+    std::memset(&Jb, 0, sizeof(Jb));
+    Jb.op = op;
+    Jb.K = 1;
+    Jb.h[0] = h;
+    Jb.l[0] = l;
+    HIPCHK(ctx, launch_features(Jb, ctx->d_featpart, feats, ctx->d_sigma, reinterpret_cast<hipStream_t>(stream)));
+    return LJ_OK;
+  });
+}
+
+LJ_API int lj_mlp_init(lj_context* ctx, uint64_t seed) {
+  return guarded(ctx, [&]() {
+    mlp_alloc(ctx);
+    std::vector<float> m;
+    mlp_host_init(seed, m);
+    HIPCHK(ctx, hipMemcpy(ctx->d_model, m.data(), kModelFloats * sizeof(float), hipMemcpyHostToDevice));
+    HIPCHK(ctx, hipMemset(ctx->d_adam, 0, 2 * kMlpParams * sizeof(float)));
+    HIPCHK(ctx, hipMemset(ctx->d_adam_t, 0, sizeof(int)));
+    ctx->mlp_ready = false;
+    return LJ_OK;
+  });
+}
+
+LJ_API int lj_mlp_train(lj_context* ctx, const float* feats, const float* targets, int n, int epochs, int batch,
+                        float lr, int fit_normalization, float* loss_per_epoch, void* stream) {
+  return guarded(ctx, [&]() {
+    if (!ctx->d_model) invalid(ctx, "lj_mlp_train: call lj_mlp_init (or lj_mlp_set / lj_mlp_load) first");
+    if (n < 1) invalid(ctx, "n must be >= 1");
+    if (epochs < 1 || epochs > kMaxEpochs) invalid(ctx, "epochs must be in [1, 4096]");
+    if (batch < 1 || batch > kMlpBlock) invalid(ctx, "batch must be in [1, 512]");
+    if (!(lr > 0.0f) || !std::isfinite(lr)) invalid(ctx, "lr must be finite and > 0");
+    check_fvec(ctx, feats, (size_t)n * kMlpIn, "feats");
+    check_fvec(ctx, targets, (size_t)n * kMlpOut, "targets");
+    const hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    if (fit_normalization) HIPCHK(ctx, launch_mlp_normalize(ctx->d_model, feats, targets, n, s));
+    HIPCHK(ctx, launch_mlp_train(ctx->d_model, ctx->d_adam, ctx->d_adam + kMlpParams, ctx->d_adam_t, feats, targets, n,
+                                 epochs, batch, lr, ctx->d_rows, ctx->d_scalars + 1, s));
+    if (loss_per_epoch)
+      HIPCHK(ctx, hipMemcpyAsync(loss_per_epoch, ctx->d_scalars + 1, epochs * sizeof(float), hipMemcpyDeviceToHost, s));
+    HIPCHK(ctx, hipStreamSynchronize(s));
+    ctx->mlp_ready = true;
+    return LJ_OK;
+  });
+}
+
+LJ_API int lj_mlp_predict(lj_context* ctx, const float* feats, int n, float* out, void* stream) {
+  return guarded(ctx, [&]() {
+    if (!ctx->d_model) invalid(ctx, "no network (lj_mlp_init, lj_mlp_set or lj_mlp_load first)");
+    if (n < 1) invalid(ctx, "n must be >= 1");
+    check_fvec(ctx, feats, (size_t)n * kMlpIn, "feats");
+    check_fvec(ctx, out, (size_t)n * kMlpOut, "out");
+    HIPCHK(ctx, launch_mlp_forward(ctx->d_model, feats, n, out, reinterpret_cast<hipStream_t>(stream)));
+    return LJ_OK;
+  });
+}
+
+LJ_API int lj_mlp_grad(lj_context* ctx, const float* feats, const float* targets, int n, float* grad, float* loss,
+                       void* stream) {
+  return guarded(ctx, [&]() {
+    if (!ctx->d_model) invalid(ctx, "no network (lj_mlp_init, lj_mlp_set or lj_mlp_load first)");
+    if (n < 1) invalid(ctx, "n must be >= 1");
+    check_fvec(ctx, feats, (size_t)n * kMlpIn, "feats");
+    check_fvec(ctx, targets, (size_t)n * kMlpOut, "targets");
+    check_fvec(ctx, grad, kMlpParams, "grad");
+    const hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    HIPCHK(ctx, launch_mlp_grad(ctx->d_model, feats, targets, n, ctx->d_rows, grad, ctx->d_scalars, s));
+    float l = 0.0f;
+    HIPCHK(ctx, hipMemcpyAsync(&l, ctx->d_scalars, sizeof(float), hipMemcpyDeviceToHost, s));
+    HIPCHK(ctx, hipStreamSynchronize(s));
+    if (loss) *loss = l;
+    return LJ_OK;
+  });
+}
+
+LJ_API int lj_mlp_get(lj_context* ctx, float* model) {
+  return guarded(ctx, [&]() {
+    if (!model) invalid(ctx, "model is NULL");
+    if (!ctx->d_model) invalid(ctx, "no network");
+    HIPCHK(ctx, hipMemcpy(model, ctx->d_model, kModelFloats * sizeof(float), hipMemcpyDeviceToHost));
+    return LJ_OK;
+  });
+}
+
+LJ_API int lj_mlp_set(lj_context* ctx, const float* model) {
+  return guarded(ctx, [&]() {
+    if (!model) invalid(ctx, "model is NULL");
+    for (int i = 0; i < kModelFloats; ++i)
+      if (!std::isfinite(model[i])) invalid(ctx, "model has a non-finite value");
+    for (int i = 0; i < kMlpIn; ++i)
+      if (!(model[kMlpParams + kMlpIn + i] > 0.0f)) invalid(ctx, "model: feature std must be > 0");
+    for (int i = 0; i < kMlpOut; ++i)
+      if (!(model[kMlpParams + 2 * kMlpIn + kMlpOut + i] > 0.0f)) invalid(ctx, "model: target std must be > 0");
+    mlp_alloc(ctx);
+    HIPCHK(ctx, hipMemcpy(ctx->d_model, model, kModelFloats * sizeof(float), hipMemcpyHostToDevice));
+    HIPCHK(ctx, hipMemset(ctx->d_adam, 0, 2 * kMlpParams * sizeof(float)));
+    HIPCHK(ctx, hipMemset(ctx->d_adam_t, 0, sizeof(int)));
+    ctx->mlp_ready = true;
+    return LJ_OK;
+  });
+}
+
+// File: 8-byte tag "LJMLP001", int32 float count, then the model floats
+// (little-endian IEEE single).
+LJ_API int lj_mlp_save(lj_context* ctx, const char* path) {
+  return guarded(ctx, [&]() {
+    if (!path) invalid(ctx, "path is NULL");
+    if (!ctx->d_model) invalid(ctx, "no network");
+    std::vector<float> m(kModelFloats);
+    HIPCHK(ctx, hipMemcpy(m.data(), ctx->d_model, kModelFloats * sizeof(float), hipMemcpyDeviceToHost));
+    FILE* f = std::fopen(path, "wb");
+    if (!f) invalid(ctx, std::string("cannot open ") + path);
+    const int32_t cnt = kModelFloats;
+    const bool ok = std::fwrite("LJMLP001", 1, 8, f) == 8 && std::fwrite(&cnt, 4, 1, f) == 1 &&
+                    std::fwrite(m.data(), sizeof(float), m.size(), f) == m.size();
+    std::fclose(f);
+    if (!ok) invalid(ctx, std::string("cannot write ") + path);
+    return LJ_OK;
+  });
+}
+
+LJ_API int lj_mlp_load(lj_context* ctx, const char* path) {
+  return guarded(ctx, [&]() {
+    if (!path) invalid(ctx, "path is NULL");
+    FILE* f = std::fopen(path, "rb");
+    if (!f) invalid(ctx, std::string("cannot open ") + path);
+    char tag[8];
+    int32_t cnt = 0;
+    std::vector<float> m(kModelFloats);
+    const bool ok = std::fread(tag, 1, 8, f) == 8 && std::memcmp(tag, "LJMLP001", 8) == 0 &&
+                    std::fread(&cnt, 4, 1, f) == 1 && cnt == kModelFloats &&
+                    std::fread(m.data(), sizeof(float), m.size(), f) == m.size();
+    std::fclose(f);
+    if (!ok) invalid(ctx, std::string("not a network file of this library: ") + path);
+    return lj_mlp_set(ctx, m.data());
+  });
 }
 
 // ---- batching form ---------------------------------------------------------

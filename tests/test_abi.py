@@ -40,8 +40,10 @@ def test_struct_layout_matches_c(tmp_path):
     prog = tmp_path / "sz.c"
     fields = {
         "lj_operator": ["kind", "nx", "dx", "coef", "state"],
-        "lj_options": ["safety", "power_iters", "hump_max", "bound", "substeps", "power_seed", "pi_start"],
-        "lj_stats": ["m_star", "substeps", "err_est", "iters_total", "converged", "bound", "gamma"],
+        "lj_options": ["safety", "power_iters", "hump_max", "bound", "substeps", "power_seed", "pi_start",
+                       "use_proposal"],
+        "lj_stats": ["m_star", "substeps", "err_est", "iters_total", "converged", "bound", "gamma", "fallbacks",
+                     "proposal_bound"],
         "lj_timing": ["launches", "power_point_iters", "tiled_launches", "kernel_ms"],
         "lj_batch_info_t": ["schedule", "nschedules", "tune_ms", "total_values", "alg_bytes"],
     }
@@ -83,6 +85,7 @@ def test_default_options(lib):
     assert (o.safety, o.power_iters, o.max_points, o.hump_max, o.max_substeps, o.relative_tol) == \
         (1.25, 20, 100, 1e4, 64, 1)
     assert o.bound == 0.0 and o.substeps == 0 and o.power_seed == 0x5EED and not o.pi_start
+    assert o.use_proposal == 0
 
 
 def test_null_arguments_are_rejected_without_device(lib):
@@ -95,6 +98,9 @@ def test_null_arguments_are_rejected_without_device(lib):
     assert lib.lj_batch_info(None, None) == -1
     assert lib.lj_batch_create(None, None, 0, None, None, 0, None, None, 1e-10, None, None, None, None) == -1
     lib.lj_batch_destroy(None)
+    assert lib.lj_mlp_init(None, 6) == -1
+    assert lib.lj_mlp_train(None, None, None, 1, 1, 1, 1e-3, 1, None, None) == -1
+    assert lib.lj_mlp_load(None, b"x") == -1
     lib.lj_destroy(None)
 
 

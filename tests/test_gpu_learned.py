@@ -1,0 +1,200 @@
+"""GPU tests of the learned proposal: feature kernel against the FP64 oracle,
+the FP32 network's forward pass, back-propagated gradient and Adam step
+against the oracle network, training on the GPU, model files, and what the
+trained proposal gains over the plain method (and that it falls back to it)."""
+import math
+
+import numpy as np
+import pytest
+
+from gpu_util import say
+from oracle import features as OF
+from oracle import mlp as OM
+from workloads import (advdiff_bump, allen_cahn_noise, brusselator_perturbed, burgers_sines, diag_problem,
+                       proposal_training_set)
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-10
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+
+    import paper_2211_08948_amd as lj
+    ctx = lj.Context(0)
+    yield lj, torch, ctx
+    ctx.close()
+
+
+def _model_with_norm(seed=6):
+    rng = np.random.default_rng(seed)
+    th = OM.init(seed) + rng.normal(size=OM.NPARAM) * 0.02
+    mu = rng.normal(size=16)
+    sd = rng.uniform(0.5, 2.0, size=16)
+    tmu = rng.normal(size=2)
+    tsd = rng.uniform(0.5, 2.0, size=2)
+    flat = np.concatenate([th, mu, sd, tmu, tsd]).astype(np.float32)
+    # the oracle sees exactly the FP32 values the device holds
+    f64 = flat.astype(np.float64)
+    return flat, f64[:OM.NPARAM], f64[OM.NPARAM:OM.NPARAM + 16], f64[OM.NPARAM + 16:OM.NPARAM + 32], \
+        f64[OM.NPARAM + 32:OM.NPARAM + 34], f64[OM.NPARAM + 34:]
+
+
+def _rows(n, seed):
+    rng = np.random.default_rng(seed)
+    X = (rng.normal(size=(n, 16)) * 1.5 + 0.5).astype(np.float32)
+    T = rng.normal(size=(n, 2)).astype(np.float32)
+    return X, T
+
+
+def test_features_match_oracle(env):
+    lj, torch, ctx = env
+    p1, _ = advdiff_bump()
+    probs = [p1, allen_cahn_noise(64, eps=1e-2, seed=3), burgers_sines(64, nu=2e-3, seed=4),
+             brusselator_perturbed(32, D=1e-2, seed=5), diag_problem(500, -40.0, seed=6),
+             allen_cahn_noise(37, eps=3e-4, seed=8, amp=0.9)]
+    for p in probs:
+        op = lj.operator_from(p, "cuda:0")
+        for hm in (1.0, 37.0):
+            for l in (0, 2, 4):
+                h = hm * p.h_cfl
+                f = torch.empty(16, dtype=torch.float32, device="cuda:0")
+                lj.lj_features(ctx, op, h, l, f)
+                ref = OF.features(p, h, l)
+                got = f.cpu().numpy().astype(np.float64)
+                say("features", p.kind, hm, l)
+                np.testing.assert_allclose(got, ref, rtol=2e-6, atol=2e-6)
+
+
+def test_forward_matches_oracle(env):
+    lj, torch, ctx = env
+    flat, th, mu, sd, tmu, tsd = _model_with_norm()
+    lj.lj_mlp_set(ctx, flat)
+    X, _ = _rows(300, 1)
+    Xd = torch.as_tensor(X, device="cuda:0")
+    out = torch.empty((300, 2), dtype=torch.float32, device="cuda:0")
+    lj.lj_mlp_predict(ctx, Xd, out)
+    ref = OM.predict(th, X.astype(np.float64), mu, sd, tmu, tsd)
+    np.testing.assert_allclose(out.cpu().numpy(), ref, rtol=2e-5, atol=2e-5)
+    assert lj.lj_mlp_get(ctx) == pytest.approx(list(flat), rel=0, abs=0)
+
+
+def test_gradient_matches_oracle(env):
+    """FP32 back-propagation on the device against the FP64 chain rule of the
+    oracle (itself checked against finite differences), over 700 samples
+    (two chunks of the gradient kernel)."""
+    lj, torch, ctx = env
+    flat, th, mu, sd, tmu, tsd = _model_with_norm(9)
+    lj.lj_mlp_set(ctx, flat)
+    X, T = _rows(700, 2)
+    g = torch.empty(OM.NPARAM, dtype=torch.float32, device="cuda:0")
+    loss = lj.lj_mlp_grad(ctx, torch.as_tensor(X, device="cuda:0"), torch.as_tensor(T, device="cuda:0"), g)
+    L, gref = OM.grad(th, X.astype(np.float64), T.astype(np.float64), mu, sd, tmu, tsd)
+    gg = g.cpu().numpy().astype(np.float64)
+    say("grad", loss, L, np.linalg.norm(gg - gref) / np.linalg.norm(gref))
+    assert loss == pytest.approx(L, rel=1e-5)
+    assert np.linalg.norm(gg - gref) <= 1e-4 * np.linalg.norm(gref)
+    # every parameter block is right, not just the large ones
+    for a, b in ((0, 1024), (1024, 1088), (1088, 5184), (5184, 5248), (5248, 5376), (5376, 5378)):
+        assert np.linalg.norm(gg[a:b] - gref[a:b]) <= 1e-4 * np.linalg.norm(gref[a:b]) + 1e-9
+
+
+def test_adam_step_matches_oracle(env):
+    lj, torch, ctx = env
+    flat, th, mu, sd, tmu, tsd = _model_with_norm(11)
+    lj.lj_mlp_set(ctx, flat)  # clears the Adam state
+    X, T = _rows(300, 3)
+    lr = 1e-3
+    lj.lj_mlp_train(ctx, torch.as_tensor(X, device="cuda:0"), torch.as_tensor(T, device="cuda:0"), epochs=1,
+                    batch=300, lr=lr, fit_normalization=False)
+    new = np.asarray(lj.lj_mlp_get(ctx), dtype=np.float64)[:OM.NPARAM]
+    _, g = OM.grad(th, X.astype(np.float64), T.astype(np.float64), mu, sd, tmu, tsd)
+    ref, _, _ = OM.adam_step(th, np.zeros_like(th), np.zeros_like(th), g, 1, lr)
+    big = np.abs(g) > 1e-5  # where |g| >> eps the first step is lr * sign(g)
+    assert big.sum() > 1000
+    np.testing.assert_allclose(new[big] - th[big], ref[big] - th[big], rtol=0, atol=1e-3 * lr)
+
+
+def test_training_reduces_loss(env):
+    lj, torch, ctx = env
+    rng = np.random.default_rng(5)
+    X = rng.normal(size=(3000, 16)).astype(np.float32)
+    T = np.stack([0.3 * X[:, :4].sum(axis=1), np.tanh(X[:, 0] - X[:, 5])], axis=1).astype(np.float32)
+    lj.lj_mlp_init(ctx, 6)
+    losses = lj.lj_mlp_train(ctx, torch.as_tensor(X, device="cuda:0"), torch.as_tensor(T, device="cuda:0"),
+                             epochs=40, batch=256, lr=3e-3)
+    say("losses", losses[0], losses[-1])
+    assert all(np.isfinite(losses)) and losses[-1] < 0.05 * losses[0]
+
+
+def test_model_files_and_validation(env, tmp_path):
+    lj, torch, ctx = env
+    flat, *_ = _model_with_norm(13)
+    lj.lj_mlp_set(ctx, flat)
+    path = tmp_path / "m.bin"
+    lj.lj_mlp_save(ctx, path)
+    lj.lj_mlp_init(ctx, 1)
+    lj.lj_mlp_load(ctx, path)
+    assert np.array_equal(np.asarray(lj.lj_mlp_get(ctx), dtype=np.float32), flat)
+    bad = flat.copy()
+    bad[7] = np.nan
+    with pytest.raises(lj.LejaError, match="non-finite"):
+        lj.lj_mlp_set(ctx, bad)
+    (tmp_path / "junk.bin").write_bytes(b"not a model")
+    with pytest.raises(lj.LejaError, match="not a network file"):
+        lj.lj_mlp_load(ctx, tmp_path / "junk.bin")
+
+
+def test_untrained_proposal_is_rejected_or_falls_back(env):
+    lj, torch, ctx = env
+    p = allen_cahn_noise(48, eps=1e-2, seed=4)
+    op = lj.operator_from(p, "cuda:0")
+    f = torch.empty_like(op.state)
+    lj.lj_rhs(ctx, op, op.state, f)
+    h = 10 * p.h_cfl
+    v = (h * f).contiguous()
+    w0, w1 = torch.empty_like(v), torch.empty_like(v)
+    lj.lj_mlp_init(ctx, 6)  # weights but no training: not usable
+    with pytest.raises(lj.LejaError, match="no trained network"):
+        lj.lj_phi_action(ctx, op, v, w1, 1, h, TOL, lj.lj_default_options(use_proposal=1))
+    # a badly scaled network: whatever it proposes, the result is the plain one or converges to tol
+    flat, *_ = _model_with_norm(17)
+    flat[OM.NPARAM + 32:OM.NPARAM + 34] = [8.0, -5.0]  # target means: a huge bound, s < 1
+    lj.lj_mlp_set(ctx, flat)
+    _, s0 = lj.lj_phi_action(ctx, op, v, w0, 1, h, TOL)
+    rc, s1 = lj.lj_phi_action(ctx, op, v, w1, 1, h, TOL, lj.lj_default_options(use_proposal=1))
+    say("bad proposal", s1)
+    assert rc == 0 and s1["converged"] and s1["proposal_bound"] > 0
+    assert float(torch.linalg.norm(w1 - w0) / torch.linalg.norm(w0)) <= 1e-8
+
+
+def test_trained_proposal_saves_work(env):
+    """Train on plain-method records of the two training families, then on
+    held-out problems -- other seeds of those families and Burgers, which the
+    network never saw -- the proposal must use fewer Jacobian products than
+    power iteration + plain expansion, and agree with the plain result to the
+    accuracy both deliver."""
+    lj, torch, ctx = env
+    from paper_2211_08948_amd.proposal import compare, make_records
+    X, T = make_records(ctx, 3000, seed=21, log=lambda *a, **k: None)
+    say("records", X.shape[0], int((T[:, 1] > 0).sum()))
+    lj.lj_mlp_init(ctx, 6)
+    losses = lj.lj_mlp_train(ctx, X, T, epochs=120, batch=256, lr=2e-3)
+    say("train loss", losses[0], losses[-1])
+    assert losses[-1] < 0.2 * losses[0]
+    held = [(p, h, v) for p, h, v in proposal_training_set(8, seed=99)]
+    held += [(burgers_sines(256, nu=1e-3, seed=5), hm * burgers_sines(256, nu=1e-3, seed=5).h_cfl, None)
+             for hm in (3.0, 30.0)]
+    plain = prop = 0
+    for p, h, v in held:
+        for l in (1, 3):
+            r = compare(ctx, p, h, l, v)
+            say("held-out", p.kind, p.nx, round(h / p.h_cfl, 1), l, r["plain"]["products"], r["proposal"]["products"],
+                r["proposal"]["fallbacks"], r["rel_diff"])
+            assert r["plain"]["rc"] == 0 and r["proposal"]["rc"] == 0 and r["proposal"]["converged"]
+            assert r["rel_diff"] <= 1e-8
+            plain += r["plain"]["products"]
+            prop += r["proposal"]["products"]
+    say("products plain vs proposal", plain, prop)
+    assert prop < 0.85 * plain

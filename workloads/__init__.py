@@ -13,5 +13,6 @@ from .problems import (  # noqa: F401
     burgers_sines,
     diag_problem,
     batch_instances,
+    proposal_training_set,
     uniform_vector,
 )
