@@ -32,13 +32,14 @@ def _lj():
     return lj
 
 
-def make_records(ctx, count: int, seed: int = 7, chunk: int = 512, log=print):
-    """(feats n x 16, targets n x 2) float32 CUDA tensors, 3 records per problem."""
+def make_records(ctx, count: int, seed: int = 7, chunk: int = 512, hmult=(1.0, 100.0), log=print):
+    """(feats n x 16, targets n x 2) float32 CUDA tensors, 3 records per problem;
+    h / h_cfl log-uniform on `hmult`."""
     import torch
 
     from workloads import proposal_training_set
     lj = _lj()
-    items = proposal_training_set((count + 2) // 3, seed=seed)
+    items = proposal_training_set((count + 2) // 3, seed=seed, hmult=hmult)
     feats, targs = [], []
     os.environ["LJ_BATCH_SCHEDULE"] = "0"  # no per-chunk tuning: one block per instance
     try:
@@ -145,6 +146,7 @@ def main(argv=None):
     t.add_argument("--batch", type=int, default=256)
     t.add_argument("--lr", type=float, default=2e-3)
     t.add_argument("--seed", type=int, default=7)
+    t.add_argument("--hmax", type=float, default=1000.0, help="largest h / h_cfl of the training sweep")
     t.add_argument("--out", default=MODEL_FILE)
     e = sub.add_parser("evaluate")
     e.add_argument("--model", default=MODEL_FILE)
@@ -154,7 +156,7 @@ def main(argv=None):
     ctx = lj.Context(0)
     if args.cmd == "train":
         t0 = time.perf_counter()
-        X, T = make_records(ctx, args.records, seed=args.seed)
+        X, T = make_records(ctx, args.records, seed=args.seed, hmult=(1.0, args.hmax))
         t1 = time.perf_counter()
         print(f"{X.shape[0]} records in {t1 - t0:.1f} s; substeps>1: {int((T[:, 1] > 0).sum())}", flush=True)
         lj.lj_mlp_init(ctx, 6)
