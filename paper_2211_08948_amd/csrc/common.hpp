@@ -69,6 +69,8 @@ struct ActionParams {
   uint64_t seed;
   const double* start;    // explicit power-iteration start vector or nullptr
   double lam_in;
+  const double* lam_src;  // if set (and do_power == 0): the bound is read from here (device)
+  double* lam_out;        // if set: the bound used is written here (device)
   double safety;
   // expansion
   const double* v;        // y_0 (device)

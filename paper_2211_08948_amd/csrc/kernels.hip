@@ -402,7 +402,7 @@ __global__ __launch_bounds__(kBlock) void lj_action_stream(ActionParams P) {
   };
 
   // (1) spectral bound
-  double lam = P.lam_in;
+  double lam = (P.lam_src != nullptr && !P.do_power) ? *P.lam_src : P.lam_in;
   int pit = 0;
   if (P.do_power) {
     const double* x0 = P.start;
@@ -443,6 +443,7 @@ __global__ __launch_bounds__(kBlock) void lj_action_stream(ActionParams P) {
     }
   }
   lam = uniform(lam);
+  if (P.lam_out != nullptr && blockIdx.x == 0 && threadIdx.x == 0) *P.lam_out = lam;
   double c, gamma;
   interval(lam, P.safety, c, gamma);
   tick(kProfPower);
@@ -654,7 +655,7 @@ __global__ __launch_bounds__(kBlock) void lj_action_tile(ActionParams P) {
   };
 
   // ---- (1) spectral bound: S products between barriers, normalised per barrier
-  double lam = P.lam_in;
+  double lam = (P.lam_src != nullptr && !P.do_power) ? *P.lam_src : P.lam_in;
   int pit = 0;
   if (P.do_power) {
 #pragma unroll
@@ -695,6 +696,7 @@ __global__ __launch_bounds__(kBlock) void lj_action_tile(ActionParams P) {
     }
   }
   lam = uniform(lam);
+  if (P.lam_out != nullptr && blockIdx.x == 0 && threadIdx.x == 0) *P.lam_out = lam;
   double c, gamma;
   interval(lam, P.safety, c, gamma);
   tick(kProfPower);

@@ -39,6 +39,7 @@ enum Slot {
 // LDS held back from the tiled kernel's dynamic allocation for its static arrays
 constexpr size_t kStaticLdsReserve = 20 * 1024;
 constexpr int kQ_batch = 1 + kMaxK;  // team partial sums per reduction
+constexpr int kAsyncSlots = 8;       // most action launches of one step
 
 struct lj_context {
   int device = 0;
@@ -64,6 +65,11 @@ struct lj_context {
   bool timing = false;
   hipEvent_t ev[4] = {};
   lj_timing tm = {};
+  // launches of a step enqueued back to back: their status heads, event pairs
+  // and the bound the first one leaves for the others
+  LejaStatus* h_pool = nullptr;  // pinned, kAsyncSlots entries
+  hipEvent_t ev_pool[2 * 8] = {};
+  double* d_bound = nullptr;
   // batching form: schedule picked by the tuner, per batch shape
   std::map<std::string, int> batch_schedule;
   // learned proposal
@@ -299,20 +305,30 @@ struct ActOut {
   double lam, c, gamma, vnorm;
 };
 
-// K accumulators phi_{l_k}(s_k J) v (K = 0: power iteration only).  The bound
-// is lam_host when > 0, else the power iteration runs inside the launch.
-ActOut run_action(lj_context* ctx, const OpDev& op, const double* v, int K, const int* l, const double* s_k,
-                  double lam_host, uint64_t seed, const double* start, double* const* outs, const Opts& o,
-                  double tol, hipStream_t s) {
+// Where the bound of a launch comes from and goes to (device pointers, or none).
+struct BoundLink {
+  const double* src = nullptr;  // read the bound here (no power iteration)
+  double* dst = nullptr;        // write the bound used here
+};
+
+// Enqueues one action launch and the copy of its status head (everything but
+// the trace) into `status_dst` (pinned host memory), without waiting.  `ev` (may be
+// NULL) receives a start / end event pair around the launch.
+void launch_action(lj_context* ctx, const OpDev& op, const double* v, int K, const int* l, const double* s_k,
+                   double lam_host, uint64_t seed, const double* start, double* const* outs, const Opts& o,
+                   double tol, hipStream_t s, const BoundLink& link, LejaStatus* status_dst, size_t status_bytes,
+                   hipEvent_t* ev, bool* tiled) {
   const size_t n = nvals(op);
   ActionParams P;
   std::memset(&P, 0, sizeof(P));
   P.op = op;
-  P.do_power = lam_host > 0.0 ? 0 : 1;
+  P.do_power = (lam_host > 0.0 || link.src != nullptr) ? 0 : 1;
   P.power_iters = o.power_iters;
   P.seed = seed;
   P.start = start;
   P.lam_in = lam_host;
+  P.lam_src = link.src;
+  P.lam_out = link.dst;
   P.safety = o.safety;
   P.v = v;
   P.K = K;
@@ -352,12 +368,16 @@ ActOut run_action(lj_context* ctx, const OpDev& op, const double* v, int K, cons
   ensure_small(ctx, G);
   P.partials = ctx->d_partials;
   void* args[] = {&P};
-  if (ctx->timing) HIPCHK(ctx, hipEventRecord(ctx->ev[0], s));
+  if (ev) HIPCHK(ctx, hipEventRecord(ev[0], s));
   HIPCHK(ctx, hipLaunchCooperativeKernel(fn, dim3(G), dim3(persistent_block()), args, (unsigned)dyn, s));
-  if (ctx->timing) HIPCHK(ctx, hipEventRecord(ctx->ev[1], s));
-  HIPCHK(ctx, hipMemcpyAsync(ctx->h_status, ctx->d_status, sizeof(LejaStatus), hipMemcpyDeviceToHost, s));
-  HIPCHK(ctx, hipStreamSynchronize(s));
-  const LejaStatus& S = *ctx->h_status;
+  if (ev) HIPCHK(ctx, hipEventRecord(ev[1], s));
+  HIPCHK(ctx, hipMemcpyAsync(status_dst, ctx->d_status, status_bytes, hipMemcpyDeviceToHost, s));
+  if (tiled) *tiled = tp.ok;
+}
+
+// Outcome of a launch whose status has arrived; accumulates the timing
+// counters when `ev` holds its (completed) event pair.
+ActOut finish_action(lj_context* ctx, const OpDev& op, const LejaStatus& S, hipEvent_t* ev, bool tiled) {
   ActOut r;
   for (int k = 0; k < kMaxK; ++k) {
     r.state[k] = S.state[k];
@@ -370,18 +390,31 @@ ActOut run_action(lj_context* ctx, const OpDev& op, const double* v, int K, cons
   r.c = S.c;
   r.gamma = S.gamma;
   r.vnorm = S.vnorm;
-  if (ctx->timing) {
+  if (ev) {
     float ms = 0.f;
-    HIPCHK(ctx, hipEventElapsedTime(&ms, ctx->ev[0], ctx->ev[1]));
+    HIPCHK(ctx, hipEventElapsedTime(&ms, ev[0], ev[1]));
     ctx->tm.launches += 1;
     ctx->tm.iterations += S.iters;
     ctx->tm.point_iters += (int64_t)S.iters * op.npts;
     ctx->tm.accum_point_iters += (int64_t)S.accum_iters * op.npts;
     ctx->tm.power_point_iters += (int64_t)S.power_iters * op.npts;
-    ctx->tm.tiled_launches += tp.ok ? 1 : 0;
+    ctx->tm.tiled_launches += tiled ? 1 : 0;
     ctx->tm.kernel_ms += ms;
   }
   return r;
+}
+
+// K accumulators phi_{l_k}(s_k J) v (K = 0: power iteration only), one
+// launch, synchronised.  The bound is lam_host when > 0, else the power
+// iteration runs inside the launch.
+ActOut run_action(lj_context* ctx, const OpDev& op, const double* v, int K, const int* l, const double* s_k,
+                  double lam_host, uint64_t seed, const double* start, double* const* outs, const Opts& o,
+                  double tol, hipStream_t s) {
+  bool tiled = false;
+  launch_action(ctx, op, v, K, l, s_k, lam_host, seed, start, outs, o, tol, s, BoundLink{}, ctx->h_status,
+                sizeof(LejaStatus), ctx->timing ? ctx->ev : nullptr, &tiled);
+  HIPCHK(ctx, hipStreamSynchronize(s));
+  return finish_action(ctx, op, *ctx->h_status, ctx->timing ? ctx->ev : nullptr, tiled);
 }
 
 double run_bound(lj_context* ctx, const OpDev& op, const Opts& o, int iters, uint64_t seed, const double* start,
@@ -893,6 +926,9 @@ LJ_API int lj_create(lj_context** out, int hip_device) {
     HIPCHK(ctx, hipHostMalloc(&ctx->h_status, sizeof(LejaStatus), hipHostMallocDefault));
     HIPCHK(ctx, hipHostMalloc(&ctx->h_coef, kMaxK * kTable * sizeof(double), hipHostMallocDefault));
     for (int i = 0; i < 4; ++i) HIPCHK(ctx, hipEventCreate(&ctx->ev[i]));
+    for (int i = 0; i < 2 * kAsyncSlots; ++i) HIPCHK(ctx, hipEventCreate(&ctx->ev_pool[i]));
+    HIPCHK(ctx, hipHostMalloc(&ctx->h_pool, kAsyncSlots * sizeof(LejaStatus), hipHostMallocDefault));
+    HIPCHK(ctx, hipMalloc(&ctx->d_bound, sizeof(double)));
     if (const char* g = std::getenv("LJ_GRID")) ctx->grid_override = std::atoi(g);
     if (const char* g = std::getenv("LJ_NO_TILE")) ctx->force_stream = std::atoi(g);
     if (const char* g = std::getenv("LJ_TILE")) {
@@ -936,6 +972,10 @@ LJ_API void lj_destroy(lj_context* ctx) {
   if (ctx->h_coef) (void)hipHostFree(ctx->h_coef);
   for (int i = 0; i < 4; ++i)
     if (ctx->ev[i]) (void)hipEventDestroy(ctx->ev[i]);
+  for (int i = 0; i < 2 * kAsyncSlots; ++i)
+    if (ctx->ev_pool[i]) (void)hipEventDestroy(ctx->ev_pool[i]);
+  if (ctx->h_pool) (void)hipHostFree(ctx->h_pool);
+  if (ctx->d_bound) (void)hipFree(ctx->d_bound);
   delete ctx;
 }
 
@@ -1078,143 +1118,222 @@ LJ_API int lj_step(lj_context* ctx, int scheme, const lj_operator* J, double h, 
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     const size_t n = nvals(op);
     const double* u = op.state;
-    // one spectral bound for the whole step
+    // the scheme's stages; `act` runs one (vertical) Leja call
+    auto scheme_steps = [&](auto&& act) {
+      double* fu = slot(ctx, W_FU, n);
+      double* v = slot(ctx, W_V, n);
+      HIPCHK(ctx, launch_rhs(op, u, fu, s));
+      {
+        const double al[1] = {h};
+        const double* xs[1] = {fu};
+        lincomb(ctx, n, v, 1, al, xs, s);
+      }
+      auto comb2 = [&](double* out, double a0, const double* x0, double a1, const double* x1) {
+        const double al[2] = {a0, a1};
+        const double* xs[2] = {x0, x1};
+        lincomb(ctx, n, out, 2, al, xs, s);
+      };
+      auto comb3 = [&](double* out, double a0, const double* x0, double a1, const double* x1, double a2,
+                       const double* x2) {
+        const double al[3] = {a0, a1, a2};
+        const double* xs[3] = {x0, x1, x2};
+        lincomb(ctx, n, out, 3, al, xs, s);
+      };
+      // R(x) = f(x) - f(u) - J(u)(x - u)
+      auto remainder = [&](const double* x, double* r) {
+        double* d = slot(ctx, W_D, n);
+        comb2(d, 1.0, x, -1.0, u);
+        HIPCHK(ctx, launch_remainder(op, x, d, fu, r, s));
+      };
+      if (scheme == LJ_EXPRB2) {
+        double* A = slot(ctx, W_A, n);
+        const int ls[1] = {1};
+        const double as[1] = {1.0};
+        act(v, 1, ls, as, &A);
+        comb2(u_out, 1.0, u, 1.0, A);
+        if (err) comb2(err, 0.0, u, 0.0, u);
+      } else if (scheme == LJ_EXPRB43 || scheme == LJ_EXPRB43_U3) {
+        double* A = slot(ctx, W_A, n);
+        double* B = slot(ctx, W_B, n);
+        double* C = slot(ctx, W_C, n);
+        double* xa = slot(ctx, W_XA, n);
+        double* xb = slot(ctx, W_XB, n);
+        double* Ra = slot(ctx, W_RA, n);
+        double* Rb = slot(ctx, W_RB, n);
+        double* T3 = slot(ctx, W_T3, n);
+        double* D3 = slot(ctx, W_D3, n);
+        double* u3 = (scheme == LJ_EXPRB43_U3) ? u_out : slot(ctx, W_U3, n);
+        {
+          const int ls[2] = {1, 1};
+          const double as[2] = {0.5, 1.0};
+          double* outs[2] = {A, B};
+          act(v, 2, ls, as, outs);
+        }
+        comb2(xa, 1.0, u, 0.5, A);
+        remainder(xa, Ra);
+        double* T1 = slot(ctx, W_T4, n);
+        {
+          const double al[1] = {h};
+          const double* xs[1] = {Ra};
+          lincomb(ctx, n, T1, 1, al, xs, s);
+        }
+        {
+          const int ls[1] = {1};
+          const double as[1] = {1.0};
+          act(T1, 1, ls, as, &C);
+        }
+        comb3(xb, 1.0, u, 1.0, B, 1.0, C);
+        remainder(xb, Rb);
+        comb2(T3, 16.0 * h, Ra, -2.0 * h, Rb);
+        {
+          const int ls[1] = {3};
+          const double as[1] = {1.0};
+          act(T3, 1, ls, as, &D3);
+        }
+        comb3(u3, 1.0, u, 1.0, B, 1.0, D3);
+        if (scheme == LJ_EXPRB43) {
+          double* T4 = slot(ctx, W_T4, n);
+          double* D4 = slot(ctx, W_D4, n);
+          comb2(T4, -48.0 * h, Ra, 12.0 * h, Rb);
+          const int ls[1] = {4};
+          const double as[1] = {1.0};
+          act(T4, 1, ls, as, &D4);
+          comb2(u_out, 1.0, u3, 1.0, D4);
+          if (err) comb2(err, 1.0, u_out, -1.0, u3);
+        } else if (err) {
+          comb2(err, 0.0, u, 0.0, u);
+        }
+      } else {  // EPIRK4s3
+        double* A = slot(ctx, W_A, n);
+        double* B = slot(ctx, W_B, n);
+        double* C = slot(ctx, W_C, n);
+        double* xa = slot(ctx, W_XA, n);
+        double* xb = slot(ctx, W_XB, n);
+        double* Ra = slot(ctx, W_RA, n);
+        double* Rb = slot(ctx, W_RB, n);
+        double* T3 = slot(ctx, W_T3, n);
+        double* D3 = slot(ctx, W_D3, n);
+        double* T4 = slot(ctx, W_T4, n);
+        double* D4 = slot(ctx, W_D4, n);
+        double* u3 = slot(ctx, W_U3, n);
+        {
+          const int ls[3] = {1, 1, 1};
+          const double as[3] = {1.0 / 8.0, 1.0 / 9.0, 1.0};
+          double* outs[3] = {A, B, C};
+          act(v, 3, ls, as, outs);
+        }
+        comb2(xa, 1.0, u, 1.0 / 8.0, A);
+        comb2(xb, 1.0, u, 1.0 / 9.0, B);
+        remainder(xa, Ra);
+        remainder(xb, Rb);
+        // h (1892 Ra + 1458 (Rb - 2 Ra)) and h (-42336 Ra - 34992 (Rb - 2 Ra))
+        comb2(T3, h * (1892.0 - 2.0 * 1458.0), Ra, h * 1458.0, Rb);
+        comb2(T4, h * (-42336.0 + 2.0 * 34992.0), Ra, h * -34992.0, Rb);
+        {
+          const int ls[1] = {3};
+          const double as[1] = {1.0};
+          act(T3, 1, ls, as, &D3);
+        }
+        comb3(u3, 1.0, u, 1.0, C, 1.0, D3);
+        {
+          const int ls[1] = {4};
+          const double as[1] = {1.0};
+          act(T4, 1, ls, as, &D4);
+        }
+        comb2(u_out, 1.0, u3, 1.0, D4);
+        if (err) comb2(err, 1.0, u_out, -1.0, u3);
+      }
+    };
+    std::vector<lj_stats> log;
+    bool ok = true;
     int pit = 0;
+    // ---- first try: every launch of the step enqueued back to back.  The
+    // first action runs the power iteration (unless a bound is given) and
+    // leaves the bound on the device for the others; statuses are read once
+    // at the end.  If some expansion was rejected, the step is redone below
+    // synchronously, with substeps, on the bound found.
+    const bool try_async = o.substeps <= 1 && !o.use_proposal;
+    double lam_found = o.bound;
+    if (try_async) {
+      struct Pending {
+        int K;
+        bool tiled;
+        const OpDev* op;
+      };
+      std::vector<Pending> pend;
+      auto act_async = [&](const double* vec, int K, const int* ls, const double* as, double* const* outs) {
+        const int i = (int)pend.size();
+        if (i >= kAsyncSlots) invalid(ctx, "internal: too many launches in one step");
+        double sk[kMaxK];
+        for (int k = 0; k < K; ++k) sk[k] = as[k] * h;
+        BoundLink link;
+        double lam_host = 0.0;
+        if (o.bound > 0.0) {
+          lam_host = o.bound;
+        } else if (i == 0) {
+          link.dst = ctx->d_bound;
+        } else {
+          link.src = ctx->d_bound;
+        }
+        bool tiled = false;
+        launch_action(ctx, op, vec, K, ls, sk, lam_host, o.seed, o.pi_start, outs, o, tol, s, link, &ctx->h_pool[i],
+                      offsetof(LejaStatus, trace), ctx->timing ? &ctx->ev_pool[2 * i] : nullptr, &tiled);
+        pend.push_back({K, tiled, &op});
+      };
+      scheme_steps(act_async);
+      HIPCHK(ctx, hipStreamSynchronize(s));
+      bool all = true;
+      for (size_t i = 0; i < pend.size(); ++i) {
+        const ActOut r = finish_action(ctx, op, ctx->h_pool[i], ctx->timing ? &ctx->ev_pool[2 * i] : nullptr,
+                                       pend[i].tiled);
+        lj_stats st;
+        std::memset(&st, 0, sizeof(st));
+        for (int k = 0; k < LJ_MAX_K; ++k) {
+          st.m_star[k] = -1;
+          st.substeps[k] = 1;
+        }
+        st.iters_total = r.iters;
+        st.power_iters = r.power_iters;
+        st.bound = r.lam;
+        st.c = r.c;
+        st.gamma = r.gamma;
+        st.converged = 1;
+        for (int k = 0; k < pend[i].K; ++k) {
+          if (r.state[k] == ACC_CONVERGED) {
+            st.m_star[k] = r.m_star[k];
+            st.err_est[k] = r.err[k];
+          } else {
+            st.converged = 0;
+            st.rejections = 1;
+            all = false;
+          }
+        }
+        if (i == 0) {
+          lam_found = r.lam;
+          pit = r.power_iters;
+        }
+        log.push_back(st);
+      }
+      if (all) {
+        if (stats)
+          for (size_t i = 0; i < log.size(); ++i) stats[i] = log[i];
+        return LJ_OK;
+      }
+      log.clear();
+      o.bound = lam_found;
+    }
+    // ---- the step, synchronously: one spectral bound for the whole step
     if (!(o.bound > 0.0)) {
       o.bound = run_bound(ctx, op, o, o.power_iters, o.seed, o.pi_start, s);
       pit = o.power_iters;
     }
-    std::vector<lj_stats> log;
-    bool ok = true;
     auto act = [&](const double* vec, int K, const int* ls, const double* as, double* const* outs) {
       lj_stats st;
       const int rc = vertical_impl(ctx, op, vec, K, ls, as, h, tol, outs, o, &st, s);
       if (rc != LJ_OK) ok = false;
       log.push_back(st);
     };
-    double* fu = slot(ctx, W_FU, n);
-    double* v = slot(ctx, W_V, n);
-    HIPCHK(ctx, launch_rhs(op, u, fu, s));
-    {
-      const double al[1] = {h};
-      const double* xs[1] = {fu};
-      lincomb(ctx, n, v, 1, al, xs, s);
-    }
-    auto comb2 = [&](double* out, double a0, const double* x0, double a1, const double* x1) {
-      const double al[2] = {a0, a1};
-      const double* xs[2] = {x0, x1};
-      lincomb(ctx, n, out, 2, al, xs, s);
-    };
-    auto comb3 = [&](double* out, double a0, const double* x0, double a1, const double* x1, double a2,
-                     const double* x2) {
-      const double al[3] = {a0, a1, a2};
-      const double* xs[3] = {x0, x1, x2};
-      lincomb(ctx, n, out, 3, al, xs, s);
-    };
-    // R(x) = f(x) - f(u) - J(u)(x - u)
-    auto remainder = [&](const double* x, double* r) {
-      double* d = slot(ctx, W_D, n);
-      comb2(d, 1.0, x, -1.0, u);
-      HIPCHK(ctx, launch_remainder(op, x, d, fu, r, s));
-    };
-    if (scheme == LJ_EXPRB2) {
-      double* A = slot(ctx, W_A, n);
-      const int ls[1] = {1};
-      const double as[1] = {1.0};
-      act(v, 1, ls, as, &A);
-      comb2(u_out, 1.0, u, 1.0, A);
-      if (err) comb2(err, 0.0, u, 0.0, u);
-    } else if (scheme == LJ_EXPRB43 || scheme == LJ_EXPRB43_U3) {
-      double* A = slot(ctx, W_A, n);
-      double* B = slot(ctx, W_B, n);
-      double* C = slot(ctx, W_C, n);
-      double* xa = slot(ctx, W_XA, n);
-      double* xb = slot(ctx, W_XB, n);
-      double* Ra = slot(ctx, W_RA, n);
-      double* Rb = slot(ctx, W_RB, n);
-      double* T3 = slot(ctx, W_T3, n);
-      double* D3 = slot(ctx, W_D3, n);
-      double* u3 = (scheme == LJ_EXPRB43_U3) ? u_out : slot(ctx, W_U3, n);
-      {
-        const int ls[2] = {1, 1};
-        const double as[2] = {0.5, 1.0};
-        double* outs[2] = {A, B};
-        act(v, 2, ls, as, outs);
-      }
-      comb2(xa, 1.0, u, 0.5, A);
-      remainder(xa, Ra);
-      double* T1 = slot(ctx, W_T4, n);
-      {
-        const double al[1] = {h};
-        const double* xs[1] = {Ra};
-        lincomb(ctx, n, T1, 1, al, xs, s);
-      }
-      {
-        const int ls[1] = {1};
-        const double as[1] = {1.0};
-        act(T1, 1, ls, as, &C);
-      }
-      comb3(xb, 1.0, u, 1.0, B, 1.0, C);
-      remainder(xb, Rb);
-      comb2(T3, 16.0 * h, Ra, -2.0 * h, Rb);
-      {
-        const int ls[1] = {3};
-        const double as[1] = {1.0};
-        act(T3, 1, ls, as, &D3);
-      }
-      comb3(u3, 1.0, u, 1.0, B, 1.0, D3);
-      if (scheme == LJ_EXPRB43) {
-        double* T4 = slot(ctx, W_T4, n);
-        double* D4 = slot(ctx, W_D4, n);
-        comb2(T4, -48.0 * h, Ra, 12.0 * h, Rb);
-        const int ls[1] = {4};
-        const double as[1] = {1.0};
-        act(T4, 1, ls, as, &D4);
-        comb2(u_out, 1.0, u3, 1.0, D4);
-        if (err) comb2(err, 1.0, u_out, -1.0, u3);
-      } else if (err) {
-        comb2(err, 0.0, u, 0.0, u);
-      }
-    } else {  // EPIRK4s3
-      double* A = slot(ctx, W_A, n);
-      double* B = slot(ctx, W_B, n);
-      double* C = slot(ctx, W_C, n);
-      double* xa = slot(ctx, W_XA, n);
-      double* xb = slot(ctx, W_XB, n);
-      double* Ra = slot(ctx, W_RA, n);
-      double* Rb = slot(ctx, W_RB, n);
-      double* T3 = slot(ctx, W_T3, n);
-      double* D3 = slot(ctx, W_D3, n);
-      double* T4 = slot(ctx, W_T4, n);
-      double* D4 = slot(ctx, W_D4, n);
-      double* u3 = slot(ctx, W_U3, n);
-      {
-        const int ls[3] = {1, 1, 1};
-        const double as[3] = {1.0 / 8.0, 1.0 / 9.0, 1.0};
-        double* outs[3] = {A, B, C};
-        act(v, 3, ls, as, outs);
-      }
-      comb2(xa, 1.0, u, 1.0 / 8.0, A);
-      comb2(xb, 1.0, u, 1.0 / 9.0, B);
-      remainder(xa, Ra);
-      remainder(xb, Rb);
-      // h (1892 Ra + 1458 (Rb - 2 Ra)) and h (-42336 Ra - 34992 (Rb - 2 Ra))
-      comb2(T3, h * (1892.0 - 2.0 * 1458.0), Ra, h * 1458.0, Rb);
-      comb2(T4, h * (-42336.0 + 2.0 * 34992.0), Ra, h * -34992.0, Rb);
-      {
-        const int ls[1] = {3};
-        const double as[1] = {1.0};
-        act(T3, 1, ls, as, &D3);
-      }
-      comb3(u3, 1.0, u, 1.0, C, 1.0, D3);
-      {
-        const int ls[1] = {4};
-        const double as[1] = {1.0};
-        act(T4, 1, ls, as, &D4);
-      }
-      comb2(u_out, 1.0, u3, 1.0, D4);
-      if (err) comb2(err, 1.0, u_out, -1.0, u3);
-    }
+    scheme_steps(act);
     HIPCHK(ctx, hipStreamSynchronize(s));
     if (!log.empty()) log[0].power_iters = pit;
     if (stats)
