@@ -11,7 +11,7 @@ constexpr int kMaxK = 4;                // accumulators sharing one Newton basis
 constexpr int kMaxL = 4;                // highest phi index
 constexpr int kMaxPoints = 100;         // most Newton terms
 constexpr int kTable = kMaxPoints + 1;  // Leja nodes kept on the device
-constexpr int kBarrierWords = 32 * 18;  // words of one grid-barrier state (zero at launch)
+constexpr int kBarrierWords = 32 * 19;  // words of one grid-barrier state (zero at launch)
 constexpr int kPartStride = 48;         // partial sums per block and barrier slot
 constexpr int kMaxSuper = 8;            // Newton steps per barrier in the tiled kernel (max)
 
@@ -36,6 +36,8 @@ struct LejaStatus {
   int accum_iters;      // sum over iterations of active accumulators
   int power_iters;      // Jacobian products of the power iteration (0 if skipped)
   int barriers;         // grid barriers used
+  int aborted;          // 1: a grid barrier timed out (blocks not co-resident); results invalid
+  int pad;
   double vnorm;         // ||v||_2
   double lam, c, gamma; // bound used and the interval it gives
   // reduced totals of every decided Newton step m = 1..iters:

@@ -298,6 +298,7 @@ __device__ __forceinline__ void block_sum(double (&v)[NV], double* red) {
 //   base[32*(1+g)]     group g arrival counter
 //   base[32*(9+g)]     group g release flag (holds the last completed epoch)
 //   base[32*17]        exit counter (grid_exit)
+//   base[32*18]        abort word (see wait_at_least)
 // Everything must be zero at launch; grid_exit leaves it zero again.
 //
 // Partial sums: two areas alternate by epoch parity, each kPartStride x
@@ -323,6 +324,31 @@ struct NoOverlap {
   __device__ void operator()() const {}
 };
 
+// Waits until *word >= target.  The wait is bounded: the host launches a grid
+// without the cooperative guarantee only when all its blocks fit on the
+// device at once, but should some block never arrive, the waiter raises the
+// abort word after kGridSpinLimit polls, every later wait returns at once, the
+// launch runs to its end, and the host sees the abort in the status and
+// relaunches cooperatively.  Returns false on abort.
+constexpr unsigned int kGridSpinLimit = 1u << 22;
+
+__device__ __forceinline__ bool wait_at_least(unsigned int* word, unsigned int target, unsigned int* abort_word) {
+  unsigned int spins = 0;
+  while (__hip_atomic_load(word, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+    if (__hip_atomic_load(abort_word, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) return false;
+    if (++spins > kGridSpinLimit) {
+      __hip_atomic_store(abort_word, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      return false;
+    }
+    __builtin_amdgcn_s_sleep(1);
+  }
+  return true;
+}
+
+__device__ __forceinline__ unsigned int grid_aborted(unsigned int* base) {
+  return __hip_atomic_load(base + 32 * 18, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 // `epoch` counts the barriers this block has passed; every thread of the block
 // advances its copy (callers pick the partial-sum area with it before the
 // call).  nq slots (nq <= kPartStride) of `area` are reduced into tot[0..nq)
@@ -344,17 +370,14 @@ __device__ __forceinline__ void grid_allreduce(unsigned int* base, unsigned int&
     const unsigned int gsize = (G - g + ng - 1u) / ng;
     unsigned int* gc = base + 32 * (1 + g);
     unsigned int* gf = base + 32 * (9 + g);
+    unsigned int* abort_word = base + 32 * 18;
     const unsigned int old = __hip_atomic_fetch_add(gc, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     if (old == epoch * gsize - 1u) {
       __hip_atomic_fetch_add(base, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      while (__hip_atomic_load(base, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < epoch * ng) {
-        __builtin_amdgcn_s_sleep(1);
-      }
+      (void)wait_at_least(base, epoch * ng, abort_word);
       __hip_atomic_store(gf, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     } else {
-      while (__hip_atomic_load(gf, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < epoch) {
-        __builtin_amdgcn_s_sleep(1);
-      }
+      (void)wait_at_least(gf, epoch, abort_word);
     }
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
   } else if (threadIdx.x < agent) {
@@ -391,7 +414,7 @@ __device__ __forceinline__ void grid_exit(unsigned int* base) {
   if (threadIdx.x == 0) {
     const unsigned int old = __hip_atomic_fetch_add(base + 32 * 17, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     if (old == gridDim.x - 1u) {
-      for (int i = 0; i < 18; ++i) __hip_atomic_store(base + 32 * i, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      for (int i = 0; i < 19; ++i) __hip_atomic_store(base + 32 * i, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
   }
 }

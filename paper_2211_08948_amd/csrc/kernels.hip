@@ -264,7 +264,7 @@ __device__ void replay_decisions(Decision& D, int K, int m0, int steps, int Q, c
 }
 
 __device__ __forceinline__ void write_status(LejaStatus* S, const Decision& D, int pit, int barriers, double nv,
-                                             double lam, double c, double gamma) {
+                                             double lam, double c, double gamma, unsigned int* barrier_base) {
 #pragma unroll
   for (int k = 0; k < kMaxK; ++k) {
     S->state[k] = D.st[k];
@@ -275,6 +275,7 @@ __device__ __forceinline__ void write_status(LejaStatus* S, const Decision& D, i
   S->accum_iters = D.accum_iters;
   S->power_iters = pit;
   S->barriers = barriers;
+  S->aborted = grid_aborted(barrier_base) != 0u ? 1 : 0;
   S->vnorm = nv;
   S->lam = lam;
   S->c = c;
@@ -451,7 +452,7 @@ __global__ __launch_bounds__(kBlock) void lj_action_stream(ActionParams P) {
     if (blockIdx.x == 0 && threadIdx.x == 0) {
       Decision D;
       decision_init(D, 0, 1.0, 0.0, sh.fmax);
-      write_status(P.status, D, pit, (int)epoch, 0.0, lam, c, gamma);
+      write_status(P.status, D, pit, (int)epoch, 0.0, lam, c, gamma, P.barrier);
     }
     grid_exit(P.barrier);
     return;
@@ -528,7 +529,7 @@ __global__ __launch_bounds__(kBlock) void lj_action_stream(ActionParams P) {
     tick(kProfDecide);
   }
   if (blockIdx.x == 0 && threadIdx.x == 0) {
-    write_status(P.status, sD, pit, (int)epoch, nv, lam, c, gamma);
+    write_status(P.status, sD, pit, (int)epoch, nv, lam, c, gamma, P.barrier);
     for (int q = 0; q < 8; ++q) P.status->prof[q] = prof[q];
   }
   grid_exit(P.barrier);
@@ -704,7 +705,7 @@ __global__ __launch_bounds__(kBlock) void lj_action_tile(ActionParams P) {
     if (blockIdx.x == 0 && threadIdx.x == 0) {
       Decision D;
       decision_init(D, 0, 1.0, 0.0, sh.fmax);
-      write_status(P.status, D, pit, (int)epoch, 0.0, lam, c, gamma);
+      write_status(P.status, D, pit, (int)epoch, 0.0, lam, c, gamma, P.barrier);
       for (int q = 0; q < 8; ++q) P.status->prof[q] = prof[q];
     }
     grid_exit(P.barrier);
@@ -801,7 +802,7 @@ __global__ __launch_bounds__(kBlock) void lj_action_tile(ActionParams P) {
       if (k < K) P.p[k][go] = pk[k];
   }
   if (blockIdx.x == 0 && threadIdx.x == 0) {
-    write_status(P.status, sD, pit, (int)epoch, nv, lam, c, gamma);
+    write_status(P.status, sD, pit, (int)epoch, nv, lam, c, gamma, P.barrier);
     for (int q = 0; q < 8; ++q) P.status->prof[q] = prof[q];
   }
   grid_exit(P.barrier);

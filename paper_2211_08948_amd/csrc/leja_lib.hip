@@ -59,6 +59,8 @@ struct lj_context {
   double* h_coef = nullptr;        // pinned
   int grid_override = 0;   // LJ_GRID: blocks of the streaming kernel
   int force_stream = 0;    // LJ_NO_TILE=1: never use the LDS-tiled kernel
+  int force_coop = 0;      // LJ_COOP=1: always launch the action kernels cooperatively
+  std::map<std::pair<const void*, size_t>, int> occupancy;  // blocks per CU of (kernel, dynamic LDS)
   int tile_override_x = 0; // LJ_TILE=tx,ty: tile shape of the LDS-tiled kernel
   int tile_override_y = 0;
   // timing
@@ -297,6 +299,7 @@ TilePlan tile_plan(lj_context* ctx, const OpDev& op) {
 
 // ---- one phi-action launch ------------------------------------------------
 struct ActOut {
+  bool aborted;  // a grid barrier timed out: the launch must be repeated cooperatively
   int state[kMaxK];
   int m_star[kMaxK];
   double err[kMaxK];
@@ -311,13 +314,33 @@ struct BoundLink {
   double* dst = nullptr;        // write the bound used here
 };
 
+// Whether every block of a G-block launch of `fn` fits on the device at once,
+// so that a plain launch keeps them co-resident (the cooperative launch
+// guarantees it but costs ~12 us more per launch).
+bool coresident(lj_context* ctx, const void* fn, int G, size_t dyn) {
+  if (ctx->force_coop) return false;
+  const auto key = std::make_pair(fn, dyn);
+  auto it = ctx->occupancy.find(key);
+  int nb = 0;
+  if (it == ctx->occupancy.end()) {
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, persistent_block(), dyn) != hipSuccess) {
+      (void)hipGetLastError();
+      nb = 0;
+    }
+    ctx->occupancy[key] = nb;
+  } else {
+    nb = it->second;
+  }
+  return nb >= 1 && G <= ctx->num_cus * nb;
+}
+
 // Enqueues one action launch and the copy of its status head (everything but
 // the trace) into `status_dst` (pinned host memory), without waiting.  `ev` (may be
 // NULL) receives a start / end event pair around the launch.
 void launch_action(lj_context* ctx, const OpDev& op, const double* v, int K, const int* l, const double* s_k,
                    double lam_host, uint64_t seed, const double* start, double* const* outs, const Opts& o,
                    double tol, hipStream_t s, const BoundLink& link, LejaStatus* status_dst, size_t status_bytes,
-                   hipEvent_t* ev, bool* tiled) {
+                   hipEvent_t* ev, bool* tiled, bool cooperative = false) {
   const size_t n = nvals(op);
   ActionParams P;
   std::memset(&P, 0, sizeof(P));
@@ -369,7 +392,11 @@ void launch_action(lj_context* ctx, const OpDev& op, const double* v, int K, con
   P.partials = ctx->d_partials;
   void* args[] = {&P};
   if (ev) HIPCHK(ctx, hipEventRecord(ev[0], s));
-  HIPCHK(ctx, hipLaunchCooperativeKernel(fn, dim3(G), dim3(persistent_block()), args, (unsigned)dyn, s));
+  if (cooperative || !coresident(ctx, fn, G, dyn)) {
+    HIPCHK(ctx, hipLaunchCooperativeKernel(fn, dim3(G), dim3(persistent_block()), args, (unsigned)dyn, s));
+  } else {
+    HIPCHK(ctx, hipLaunchKernel(fn, dim3(G), dim3(persistent_block()), args, (unsigned)dyn, s));
+  }
   if (ev) HIPCHK(ctx, hipEventRecord(ev[1], s));
   HIPCHK(ctx, hipMemcpyAsync(status_dst, ctx->d_status, status_bytes, hipMemcpyDeviceToHost, s));
   if (tiled) *tiled = tp.ok;
@@ -379,6 +406,7 @@ void launch_action(lj_context* ctx, const OpDev& op, const double* v, int K, con
 // counters when `ev` holds its (completed) event pair.
 ActOut finish_action(lj_context* ctx, const OpDev& op, const LejaStatus& S, hipEvent_t* ev, bool tiled) {
   ActOut r;
+  r.aborted = S.aborted != 0;
   for (int k = 0; k < kMaxK; ++k) {
     r.state[k] = S.state[k];
     r.m_star[k] = S.m_star[k];
@@ -411,10 +439,15 @@ ActOut run_action(lj_context* ctx, const OpDev& op, const double* v, int K, cons
                   double lam_host, uint64_t seed, const double* start, double* const* outs, const Opts& o,
                   double tol, hipStream_t s) {
   bool tiled = false;
-  launch_action(ctx, op, v, K, l, s_k, lam_host, seed, start, outs, o, tol, s, BoundLink{}, ctx->h_status,
-                sizeof(LejaStatus), ctx->timing ? ctx->ev : nullptr, &tiled);
-  HIPCHK(ctx, hipStreamSynchronize(s));
-  return finish_action(ctx, op, *ctx->h_status, ctx->timing ? ctx->ev : nullptr, tiled);
+  for (int attempt = 0; attempt < 2; ++attempt) {
+    launch_action(ctx, op, v, K, l, s_k, lam_host, seed, start, outs, o, tol, s, BoundLink{}, ctx->h_status,
+                  sizeof(LejaStatus), ctx->timing ? ctx->ev : nullptr, &tiled, attempt == 1);
+    HIPCHK(ctx, hipStreamSynchronize(s));
+    const ActOut r = finish_action(ctx, op, *ctx->h_status, ctx->timing ? ctx->ev : nullptr, tiled);
+    if (!r.aborted) return r;
+  }
+  ctx->err = "an action launch aborted twice (grid barrier timed out)";
+  throw Fail{LJ_EHIP};
 }
 
 double run_bound(lj_context* ctx, const OpDev& op, const Opts& o, int iters, uint64_t seed, const double* start,
@@ -931,6 +964,7 @@ LJ_API int lj_create(lj_context** out, int hip_device) {
     HIPCHK(ctx, hipMalloc(&ctx->d_bound, sizeof(double)));
     if (const char* g = std::getenv("LJ_GRID")) ctx->grid_override = std::atoi(g);
     if (const char* g = std::getenv("LJ_NO_TILE")) ctx->force_stream = std::atoi(g);
+    if (const char* g = std::getenv("LJ_COOP")) ctx->force_coop = std::atoi(g);
     if (const char* g = std::getenv("LJ_TILE")) {
       int tx = 0, ty = 0;
       if (std::sscanf(g, "%d,%d", &tx, &ty) == 2 && tx > 0 && ty > 0) {
@@ -1286,6 +1320,7 @@ LJ_API int lj_step(lj_context* ctx, int scheme, const lj_operator* J, double h, 
       for (size_t i = 0; i < pend.size(); ++i) {
         const ActOut r = finish_action(ctx, op, ctx->h_pool[i], ctx->timing ? &ctx->ev_pool[2 * i] : nullptr,
                                        pend[i].tiled);
+        if (r.aborted) all = false;
         lj_stats st;
         std::memset(&st, 0, sizeof(st));
         for (int k = 0; k < LJ_MAX_K; ++k) {
