@@ -5,7 +5,7 @@ the HBM bytes per launch of one kernel.
 
     python -m paper_2211_08948_amd.rocprof_summary stats STATS_CSV --title T --command C --out MD
     python -m paper_2211_08948_amd.rocprof_summary traffic --fetch CSV --write CSV \
-        --copy-fetch CSV --copy-write CSV --copy-bytes N --kernel SUBSTR --command C --out JSON
+        --copy-fetch CSV --copy-write CSV --copy-bytes N --kernel SUBSTR --command C --out JSON [--last N]
 
 Counter values are KiB per dispatch.  Each is scaled by the ratio of the copy's
 known bytes to what the same counter reads for the copy, so the figure is in
@@ -53,8 +53,10 @@ def stats_markdown(path: str, title: str, command: str, top: int = 12) -> str:
     return "\n".join(out) + "\n"
 
 
-def _counter_avg(path: str, counter: str, kernel_substr: str):
-    """Mean over the matching dispatches of one counter (KiB per dispatch)."""
+def _counter_avg(path: str, counter: str, kernel_substr: str, last: int = 0):
+    """Mean over the matching dispatches of one counter (KiB per dispatch);
+    with last > 0 only over the last `last` of them (the timed launches, not
+    the autotuner's trial launches before them)."""
     per_dispatch = {}
     for r in _rows(path):
         if r.get("Counter_Name") != counter or kernel_substr not in r.get("Kernel_Name", ""):
@@ -63,13 +65,16 @@ def _counter_avg(path: str, counter: str, kernel_substr: str):
         per_dispatch[key] = per_dispatch.get(key, 0.0) + float(r["Counter_Value"])
     if not per_dispatch:
         raise SystemExit(f"no {counter} rows for kernels matching {kernel_substr!r} in {path}")
-    vals = list(per_dispatch.values())
+    keys = sorted(per_dispatch, key=lambda k: int(k))
+    if last > 0:
+        keys = keys[-last:]
+    vals = [per_dispatch[k] for k in keys]
     return sum(vals) / len(vals), len(vals)
 
 
 def traffic(args) -> dict:
-    f_kib, nf = _counter_avg(args.fetch, "FETCH_SIZE", args.kernel)
-    w_kib, nw = _counter_avg(args.write, "WRITE_SIZE", args.kernel)
+    f_kib, nf = _counter_avg(args.fetch, "FETCH_SIZE", args.kernel, args.last)
+    w_kib, nw = _counter_avg(args.write, "WRITE_SIZE", args.kernel, args.last)
     cf_kib, _ = _counter_avg(args.copy_fetch, "FETCH_SIZE", args.copy_kernel)
     cw_kib, _ = _counter_avg(args.copy_write, "WRITE_SIZE", args.copy_kernel)
     fetch_scale = args.copy_bytes / (cf_kib * 1024.0)
@@ -101,6 +106,7 @@ def main(argv=None):
         t.add_argument("--" + k, required=True)
     t.add_argument("--copy-kernel", default="copy")
     t.add_argument("--copy-bytes", type=float, required=True)
+    t.add_argument("--last", type=int, default=0, help="use only the last N matching dispatches")
     args = ap.parse_args(argv)
     if args.cmd == "stats":
         text = stats_markdown(args.csv, args.title, args.command)
