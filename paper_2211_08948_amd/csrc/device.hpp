@@ -149,6 +149,19 @@ __device__ __forceinline__ void rhs_point(const OpDev& op, const double* __restr
 }
 
 // ---------------------------------------------------------------------------
+// t / den from r = 1/den (correctly rounded, formed once by a division):
+// q = t r, then one correction by the exact FMA residual t - q den
+// (Markstein 1990).  The result is the correctly rounded quotient, the value
+// an IEEE division returns, at three FMA-unit instructions instead of the
+// division's scaled Newton sequence; the CPU tests check the identity on
+// random and near-boundary operands.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double div_rn(double t, double den, double r) {
+  const double q = t * r;
+  return fma(fma(-q, den, t), r, q);
+}
+
+// ---------------------------------------------------------------------------
 // phi_l(z) in FP64 (Sec. 1 definition).  |z| <= 2: the Taylor series
 // sum_{k<=40} z^k/(k+l)! by Horner (2^41/41! < 1e-37, far below one ulp), with
 // the coefficients 1/(l+k)! formed at compile time by successive division;

@@ -51,12 +51,10 @@ __device__ __forceinline__ void point_range(int npts, int& p0, int& p1) {
 // accumulators: wave k computes accumulator k, lane t holding nodes t and t+64.
 // Order by order, d_j <- (d_j - d_{j-1}) / (xi_j - xi_{j-order}) for j >= order
 // (the standard table, Sec. 2.2), with d_{j-1} taken from the neighbouring
-// lane by a DPP wave shift.  The quotient is formed as q = t * r with
-// r = 1/den correctly rounded, then corrected once by its exact residual
-// t - q den (an FMA); by Markstein's theorem (r within half an ulp of 1/den,
-// q within one ulp of t/den) the corrected q is the correctly rounded t/den,
-// the same value a division gives.  The reciprocals do not depend on d, so
-// those of the next order are formed while the current order's chain runs.
+// lane by a DPP wave shift.  The quotient is div_rn (reciprocal + one
+// Markstein correction), the same value a division gives.  The reciprocals do
+// not depend on d, so those of the next order are formed while the current
+// order's chain runs.
 //
 // After `order` orders the entries d_0..d_order are final, so the table can be
 // advanced lazily: the Newton step m needs d_m only, and the action kernels
@@ -131,9 +129,7 @@ __device__ void dd_advance(DivDiff& D, int K, int upto, const double* xi, double
     const double last0 = read_lane(d0, 63);
     if (lane == 0) p1 = last0;
     const double t0 = d0 - p0, t1 = d1 - p1;
-    double q0 = t0 * r0, q1 = t1 * r1;
-    q0 = fma(fma(-q0, den0, t0), r0, q0);
-    q1 = fma(fma(-q1, den1, t1), r1, q1);
+    const double q0 = div_rn(t0, den0, r0), q1 = div_rn(t1, den1, r1);
     if (j0 >= order && j0 < n) d0 = q0;
     if (j1 >= order && j1 < n) d1 = q1;
     den0 = nden0;
@@ -323,12 +319,13 @@ __device__ __forceinline__ void power_pass(const OpDev& op, const double* __rest
 
 // One Newton step (Sec. 2.2 display): y = ((J - c) x)/gamma - xi x, and for
 // every active accumulator p_k += d_k y; acc[0] += y^2, acc[1+k] += p_k^2.
+// rgamma = 1/gamma (the quotient is div_rn).
 template <int KIND, int NC, bool SHARED, int U>
 __device__ __forceinline__ void newton_pass(const OpDev& op, const double* __restrict__ src,
                                             double* __restrict__ dst, double* const (&pp)[kMaxK],
                                             const bool (&act)[kMaxK], const double (&dk)[kMaxK], double c,
-                                            double gamma, double xim, int pbeg, int pend, int stride,
-                                            double (&acc)[kQ]) {
+                                            double gamma, double rgamma, double xim, int pbeg, int pend,
+                                            int stride, double (&acc)[kQ]) {
   for (int p0 = pbeg; p0 < pend; p0 += stride * U) {
     double xv[U][5][2], uv[U][5][2], pv[U][kMaxK][2];
 #pragma unroll
@@ -351,7 +348,7 @@ __device__ __forceinline__ void newton_pass(const OpDev& op, const double* __res
       for (int cc = 0; cc < NC; ++cc) {
         const int idx = NC * p + cc;
         const double xc = xv[u][0][cc];
-        const double y = (out[cc] - c * xc) / gamma - xim * xc;
+        const double y = div_rn(out[cc] - c * xc, gamma, rgamma) - xim * xc;
         if constexpr (SHARED) {
           store_shared(dst + idx, y);
         } else {
@@ -447,6 +444,7 @@ __global__ __launch_bounds__(kBlock) void lj_action_stream(ActionParams P) {
   if (P.lam_out != nullptr && blockIdx.x == 0 && threadIdx.x == 0) *P.lam_out = lam;
   double c, gamma;
   interval(lam, P.safety, c, gamma);
+  const double rgamma = uniform(1.0 / gamma);
   tick(kProfPower);
   if (K == 0) {  // bound only
     if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -509,8 +507,8 @@ __global__ __launch_bounds__(kBlock) void lj_action_stream(ActionParams P) {
       dk[k] = act[k] ? uniform(sh.coef[k * kTable + m]) : 0.0;
     }
     double acc[kQ] = {0.0, 0.0, 0.0, 0.0, 0.0};
-    newton_pass<KIND, NC, true, 1>(op, src, dst, P.p, act, dk, c, gamma, xim, p0 + (int)threadIdx.x, p1,
-                                   blockDim.x, acc);
+    newton_pass<KIND, NC, true, 1>(op, src, dst, P.p, act, dk, c, gamma, rgamma, xim, p0 + (int)threadIdx.x,
+                                   p1, blockDim.x, acc);
     tick(kProfSteps);
     block_sum<kQ>(acc, sh.red);
     double* area = partial_area(P.partials, epoch);
@@ -557,8 +555,10 @@ __global__ __launch_bounds__(kBlock) void lj_action_tile(ActionParams P) {
   const int w = min(P.tx, nx - x0), h = min(P.ty, ny - y0);
   const int EW = w + 2 * S, EH = h + 2 * S, NE = EW * EH;
   // dynamic LDS: two buffers of the extended tile, then the owned point's
-  // basis values of the current super-step, H[(j-1) * kBlock + thread]
-  double* Y[2] = {lds, lds + NE};
+  // basis values of the current super-step, H[(j-1) * kBlock + thread].
+  // Buffers are addressed by offsets from `lds` (never through a pointer
+  // table) so that the accesses compile to LDS instructions, not flat ones.
+  auto Y = [&](int b) { return lds + b * NE; };
   double* H = lds + P.lds_h;
   // extended points of this thread: e = threadIdx.x + k * kBlock (valid if < NE),
   // tile coordinates packed as ex | ey << 16, linearisation state in registers
@@ -596,9 +596,9 @@ __global__ __launch_bounds__(kBlock) void lj_action_tile(ActionParams P) {
   };
 
   // one Newton (leja) or power step on the region still exact after j steps
-  auto step = [&](int j, double shift, double gam, double xim, bool leja) {
-    const double* src = Y[cur];
-    double* dst = Y[cur ^ 1];
+  auto step = [&](int j, double shift, double gam, double rgam, double xim, bool leja) {
+    const double* src = Y(cur);
+    double* dst = Y(cur ^ 1);
 #pragma unroll
     for (int k = 0; k < EPT; ++k) {
       const int e = threadIdx.x + k * kBlock;
@@ -614,7 +614,7 @@ __global__ __launch_bounds__(kBlock) void lj_action_tile(ActionParams P) {
       uv[0][0] = e_u[k];
       double out[2];
       stencil_jv<KIND>(op, xv, uv, out);
-      dst[e] = leja ? (out[0] - shift * xv[0][0]) / gam - xim * xv[0][0] : out[0];
+      dst[e] = leja ? div_rn(out[0] - shift * xv[0][0], gam, rgam) - xim * xv[0][0] : out[0];
     }
     __syncthreads();
     cur ^= 1;
@@ -629,9 +629,9 @@ __global__ __launch_bounds__(kBlock) void lj_action_tile(ActionParams P) {
       const int ex = e_xy[k] & 0xffff, ey = e_xy[k] >> 16;
       const bool inner = ex >= S && ex < S + w && ey >= S && ey < S + h;
       if (inner) {
-        if (scale != 1.0) Y[cur][e] *= scale;
+        if (scale != 1.0) Y(cur)[e] *= scale;
       } else {
-        Y[cur][e] = scale * g[gidx(k)];
+        Y(cur)[e] = scale * g[gidx(k)];
       }
     }
     __syncthreads();
@@ -664,23 +664,23 @@ __global__ __launch_bounds__(kBlock) void lj_action_tile(ActionParams P) {
       const int e = threadIdx.x + k * kBlock;
       if (e >= NE) continue;
       const int g = gidx(k);
-      Y[0][e] = P.start ? P.start[g] : 0.5 + splitmix_uniform(P.seed, (uint64_t)g);
+      Y(0)[e] = P.start ? P.start[g] : 0.5 + splitmix_uniform(P.seed, (uint64_t)g);
     }
     __syncthreads();
     int done = 0;
     while (done < P.power_iters) {
       const int steps = min(S, P.power_iters - done);
       {
-        const double x = own ? Y[cur][eo] : 0.0;
+        const double x = own ? Y(cur)[eo] : 0.0;
         stage(0, x * x);
       }
       for (int j = 1; j <= steps; ++j) {
-        step(j, 0.0, 1.0, 0.0, false);
-        const double y = own ? Y[cur][eo] : 0.0;
+        step(j, 0.0, 1.0, 1.0, 0.0, false);
+        const double y = own ? Y(cur)[eo] : 0.0;
         stage(j, y * y);
       }
       double* area = publish(steps + 1);
-      if (own) store_shared(((par == 0) ? P.ybuf0 : P.ybuf1) + go, Y[cur][eo]);
+      if (own) store_shared(((par == 0) ? P.ybuf0 : P.ybuf1) + go, Y(cur)[eo]);
       grid_allreduce(P.barrier, epoch, area, steps + 1, sh.tot);
       const double nprev = sh.tot[steps - 1], nlast = sh.tot[steps];
       done += steps;
@@ -700,6 +700,7 @@ __global__ __launch_bounds__(kBlock) void lj_action_tile(ActionParams P) {
   if (P.lam_out != nullptr && blockIdx.x == 0 && threadIdx.x == 0) *P.lam_out = lam;
   double c, gamma;
   interval(lam, P.safety, c, gamma);
+  const double rgamma = uniform(1.0 / gamma);
   tick(kProfPower);
   if (K == 0) {
     if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -721,7 +722,7 @@ __global__ __launch_bounds__(kBlock) void lj_action_tile(ActionParams P) {
   cur = 0;
 #pragma unroll
   for (int k = 0; k < EPT; ++k)
-    if ((int)threadIdx.x + k * kBlock < NE) Y[0][threadIdx.x + k * kBlock] = P.v[gidx(k)];
+    if ((int)threadIdx.x + k * kBlock < NE) Y(0)[threadIdx.x + k * kBlock] = P.v[gidx(k)];
   __syncthreads();
   tick(kProfDivdiff);
 
@@ -731,7 +732,7 @@ __global__ __launch_bounds__(kBlock) void lj_action_tile(ActionParams P) {
   __shared__ Decision sD;
   __shared__ int s_commit[kMaxK];
   double pk[kMaxK];
-  const double v_own = own ? Y[0][eo] : 0.0;
+  const double v_own = own ? Y(0)[eo] : 0.0;
 #pragma unroll
   for (int k = 0; k < kMaxK; ++k) pk[k] = sh.coef[k * kTable] * v_own;
   if (threadIdx.x == 0) decision_init(sD, K, 1.0, 0.0, sh.fmax);  // redone once ||v|| is known
@@ -751,8 +752,8 @@ __global__ __launch_bounds__(kBlock) void lj_action_tile(ActionParams P) {
     for (int j = 1; j <= S; ++j) {
       if (j > steps) break;
       const int m = m0 + j;
-      step(j, c, gamma, uniform(sh.xi[m - 1]), true);
-      const double y = own ? Y[cur][eo] : 0.0;
+      step(j, c, gamma, rgamma, uniform(sh.xi[m - 1]), true);
+      const double y = own ? Y(cur)[eo] : 0.0;
       H[(j - 1) * kBlock + threadIdx.x] = y;
       stage((j - 1) * Q, y * y);
 #pragma unroll
@@ -766,7 +767,7 @@ __global__ __launch_bounds__(kBlock) void lj_action_tile(ActionParams P) {
     if (first) stage(steps * Q, v_own * v_own);  // ||v||^2 rides on the first barrier
     const int nq = steps * Q + (first ? 1 : 0);
     double* area = publish(nq);
-    if (own) store_shared(((par == 0) ? P.ybuf0 : P.ybuf1) + go, Y[cur][eo]);
+    if (own) store_shared(((par == 0) ? P.ybuf0 : P.ybuf1) + go, Y(cur)[eo]);
     tick(kProfPublish);
     grid_allreduce(P.barrier, epoch, area, nq, sh.tot, [&] { dd_advance(dd, K, m0 + steps + S, sh.xi, sh.coef); });
     tick(kProfBarrier);
@@ -973,6 +974,7 @@ __global__ __launch_bounds__(BS) void lj_batch_kernel(BatchParams B) {
     lam = uniform(lam);
     double c, gamma;
     interval(lam, B.safety, c, gamma);
+    const double rgamma = uniform(1.0 / gamma);
 
     // (2) divided differences, every member for itself
     __syncthreads();
@@ -1015,8 +1017,8 @@ __global__ __launch_bounds__(BS) void lj_batch_kernel(BatchParams B) {
         dk[k] = act[k] ? uniform(coef[k * kTable + m]) : 0.0;
       }
       double acc[kQ] = {0.0, 0.0, 0.0, 0.0, 0.0};
-      newton_pass<KIND, NC, true, kBatchUnroll>(op, src, dst, pp, act, dk, c, gamma, xim, pb + (int)threadIdx.x, pe,
-                                                BS, acc);
+      newton_pass<KIND, NC, true, kBatchUnroll>(op, src, dst, pp, act, dk, c, gamma, rgamma, xim,
+                                                pb + (int)threadIdx.x, pe, BS, acc);
       block_sum<kQ>(acc, red);
       team_sum(red + kQ * NW, 1 + K);
       if (threadIdx.x < 64)
