@@ -16,6 +16,8 @@ Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
                         (the batching form: 256 uneven Allen-Cahn instances,
                          phi_1..phi_3 per instance in one graph-captured launch,
                          against the per-instance plain path)
+       python bench.py --form sweep   (the other workloads: advection-diffusion 32^2,
+                        Brusselator 1024^2 steps, Allen-Cahn 1024^2..4096^2)
        python bench.py --copy-calibration   (plain copy kernel for counter scaling)
 """
 from __future__ import annotations
@@ -177,6 +179,95 @@ def bench_batch(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_sweep(args):
+    """The other measured workloads, one JSON line each (not the headline
+    metric): advection-diffusion 32^2 phi_1 (latency: us per action), the
+    Brusselator 1024^2 (EXPRB43-u3 steps + a stand-alone phi_2), and phi_1 on
+    Allen-Cahn grids from 1024^2 to 4096^2 (the HBM-bound regime)."""
+    import statistics
+
+    import torch
+
+    import paper_2211_08948_amd as lj
+    from workloads import advdiff_bump, allen_cahn_noise, brusselator_perturbed
+    ctx = lj.Context(0)
+
+    def timed(fn, reps):
+        for _ in range(2):
+            fn()
+        torch.cuda.synchronize()
+        lj.lj_timing_read(ctx, reset=True)
+        lj.lj_timing_enable(ctx, True)
+        ts = []
+        for _ in range(reps):
+            t = time.perf_counter()
+            out = fn()
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t)
+        lj.lj_timing_enable(ctx, False)
+        return statistics.median(ts), lj.lj_timing_read(ctx, reset=True), out
+
+    def line(workload, metric, value, unit, ms, tm, ncomp, extra):
+        launches = max(tm["launches"], 1)
+        avg_ms = tm["kernel_ms"] / launches
+        bpl = algorithmic_bytes(tm, ncomp) / launches
+        ach = bpl / (avg_ms * 1e-3) / 1e9
+        rec = {"metric": metric, "value": round(value, 2), "unit": unit, "n_gpus": 1, "ms_per_step": round(ms, 4),
+               "dtype": "f64", "data": "synthetic", "config": {"workload": workload},
+               "roofline": {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                            "frac": round(ach / HBM_PEAK_GBS, 4), "avg_launch_us": round(avg_ms * 1e3, 2),
+                            "algorithmic_bytes_per_launch": round(bpl)}}
+        rec.update(extra)
+        print(json.dumps(rec), flush=True)
+
+    # advection-diffusion 32^2, grid Peclet 1, phi_1 at 10x CFL
+    prob, v0 = advdiff_bump()
+    op = lj.operator_from(prob, "cuda:0")
+    v = torch.as_tensor(v0, dtype=torch.float64, device="cuda:0")
+    w = torch.empty_like(v)
+    h = CFL_MULT * prob.h_cfl
+    dt, tm, (rc, st) = timed(lambda: lj.lj_phi_action(ctx, op, v, w, 1, h, TOL), 50)
+    line("advection-diffusion 32x32, nu 1, grid Peclet 1, bump + noise seed 1, phi_1 at 10x CFL, tol 1e-10",
+         "\u00b5s per \u03c6_1 action", dt * 1e6, "us", dt * 1e3, tm, 1, {"m_star": st["m_star"][0]})
+
+    # Brusselator 1024^2: EXPRB43-u3 steps + a stand-alone phi_2
+    prob = brusselator_perturbed()
+    op = lj.operator_from(prob, "cuda:0")
+    h = CFL_MULT * prob.h_cfl
+    u_out = torch.empty(prob.n, dtype=torch.float64, device="cuda:0")
+    f = torch.empty_like(u_out)
+    lj.lj_rhs(ctx, op, op.state, f)
+    v = (h * f).contiguous()
+    w = torch.empty_like(v)
+
+    def bstep():
+        _, s3 = lj.lj_step(ctx, "EXPRB43_U3", op, h, TOL, u_out)
+        lj.lj_phi_action(ctx, op, v, w, 2, h, TOL, lj.lj_default_options(bound=s3[0]["bound"]))
+        return s3
+
+    dt, tm, s3 = timed(bstep, 10)
+    line("brusselator 1024x1024 periodic, D 2e-3, a 1, b 3, perturbation seed 3, h 10x CFL, tol 1e-10: "
+         "one EXPRB43-u3 step + a phi_2 action (5 actions)", "\u03c6_l(hJ)v actions/sec", 5 / dt,
+         "phi-actions/s", dt * 1e3, tm, 2, {"m_star": [s["m_star"][:2] for s in s3]})
+
+    # Allen-Cahn n^2, phi_1 of h f(u) at 10x CFL, bound given (Newton recurrence only)
+    for n in (1024, 2048, 4096):
+        prob = allen_cahn_noise(n, eps=1e-3, seed=2)
+        op = lj.operator_from(prob, "cuda:0")
+        h = CFL_MULT * prob.h_cfl
+        f = torch.empty(prob.n, dtype=torch.float64, device="cuda:0")
+        lj.lj_rhs(ctx, op, op.state, f)
+        v = (h * f).contiguous()
+        w = torch.empty_like(v)
+        lam = lj.lj_spectral_bound(ctx, op, 20)
+        o = lj.lj_default_options(bound=lam)
+        dt, tm, (rc, st) = timed(lambda: lj.lj_phi_action(ctx, op, v, w, 1, h, TOL, o), 10)
+        line(f"allen-cahn {n}x{n} periodic, eps 1e-3, u0~U[-0.1,0.1] seed 2, phi_1 at 10x CFL, bound given, "
+             "tol 1e-10", "\u03c6_l(hJ)v actions/sec", 1 / dt, "phi-actions/s", dt * 1e3, tm, 1,
+             {"m_star": st["m_star"][0]})
+    ctx.close()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -185,7 +276,7 @@ def main():
     ap.add_argument("--n", type=int, default=512, help="grid points per axis (default: the 512^2 workload)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true")
-    ap.add_argument("--form", choices=["plain", "batch"], default="plain")
+    ap.add_argument("--form", choices=["plain", "batch", "sweep"], default="plain")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}): the multi-GPU path is not "
@@ -196,6 +287,9 @@ def main():
         return
     if args.form == "batch":
         bench_batch(args)
+        return
+    if args.form == "sweep":
+        bench_sweep(args)
         return
 
     import torch

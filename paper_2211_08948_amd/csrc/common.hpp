@@ -91,6 +91,7 @@ struct ActionParams {
   double* partials;       // 2 x kPartStride x gridDim partial sums, slot-major
   unsigned int* barrier;  // kBarrierWords words, zero at launch; left zero at exit
   LejaStatus* status;     // out
+  LejaStatus* status_host;  // optional: the status header also here (pinned host memory)
   // tiling of the LDS-resident kernel
   int tx, ty, ntx, nty;   // tile size and tiles per axis (gridDim = ntx * nty)
   int lds_h;              // offset (doubles) of the step history in dynamic LDS

@@ -118,26 +118,20 @@ __device__ __forceinline__ void jv_point(const OpDev& op, const double* __restri
   for (int c = 0; c < NC; ++c) xc[c] = xv[0][c];
 }
 
-// Right-hand side f(x)(p) of each family.
+// Right-hand side f(x) at one point from x at the centre and its four
+// neighbours (index 0 centre, 1 west, 2 east, 3 south, 4 north), and for the
+// diagonal family the diagonal entry there.
 template <int KIND>
-__device__ __forceinline__ void rhs_point(const OpDev& op, const double* __restrict__ x, int p,
-                                          double out[2]) {
+__device__ __forceinline__ void rhs_values(const OpDev& op, const double (&x)[5][2], double diag, double out[2]) {
   if constexpr (KIND == OP_DIAG) {
-    out[0] = op.state[p] * x[p];
+    out[0] = diag * x[0][0];
   } else if constexpr (KIND == OP_BRUSSELATOR) {
-    const Nbr q = neighbours(op, p);
-    const double2 C = *reinterpret_cast<const double2*>(x + 2 * q.c);
-    const double2 W = *reinterpret_cast<const double2*>(x + 2 * q.w);
-    const double2 E = *reinterpret_cast<const double2*>(x + 2 * q.e);
-    const double2 S = *reinterpret_cast<const double2*>(x + 2 * q.s);
-    const double2 N = *reinterpret_cast<const double2*>(x + 2 * q.n);
     const double Du = op.c0, Dv = op.c1, a = op.c2, b = op.c3;
-    const double uuv = C.x * C.x * C.y;
-    out[0] = Du * lap5(op, C.x, W.x, E.x, S.x, N.x) + a - (b + 1.0) * C.x + uuv;
-    out[1] = Dv * lap5(op, C.y, W.y, E.y, S.y, N.y) + b * C.x - uuv;
+    const double uuv = x[0][0] * x[0][0] * x[0][1];
+    out[0] = Du * lap5(op, x[0][0], x[1][0], x[2][0], x[3][0], x[4][0]) + a - (b + 1.0) * x[0][0] + uuv;
+    out[1] = Dv * lap5(op, x[0][1], x[1][1], x[2][1], x[3][1], x[4][1]) + b * x[0][0] - uuv;
   } else {
-    const Nbr q = neighbours(op, p);
-    const double c = x[q.c], w = x[q.w], e = x[q.e], s = x[q.s], n = x[q.n];
+    const double c = x[0][0], w = x[1][0], e = x[2][0], s = x[3][0], n = x[4][0];
     if constexpr (KIND == OP_ADVDIFF) {
       out[0] = op.c0 * lap5(op, c, w, e, s, n) - op.c1 * ((e - w) * op.i2dx) - op.c2 * ((n - s) * op.i2dy);
     } else if constexpr (KIND == OP_ALLENCAHN) {
@@ -146,6 +140,33 @@ __device__ __forceinline__ void rhs_point(const OpDev& op, const double* __restr
       out[0] = op.c0 * lap5(op, c, w, e, s, n) - 0.5 * ((e * e - w * w) * op.i2dx + (n * n - s * s) * op.i2dy);
     }
   }
+}
+
+// x at a point and its four neighbours (the diagonal family: the point only)
+template <int KIND, int NC>
+__device__ __forceinline__ void gather_x(const OpDev& op, const double* __restrict__ x, int p, double (&xv)[5][2]) {
+#pragma unroll
+  for (int t = 0; t < 5; ++t) xv[t][0] = xv[t][1] = 0.0;
+  if constexpr (KIND == OP_DIAG) {
+    xv[0][0] = x[p];
+  } else {
+    const Nbr q = neighbours(op, p);
+    const int idx[5] = {q.c, q.w, q.e, q.s, q.n};
+#pragma unroll
+    for (int t = 0; t < 5; ++t)
+#pragma unroll
+      for (int c = 0; c < NC; ++c) xv[t][c] = x[NC * idx[t] + c];
+  }
+}
+
+// Right-hand side f(x)(p) of each family.
+template <int KIND>
+__device__ __forceinline__ void rhs_point(const OpDev& op, const double* __restrict__ x, int p,
+                                          double out[2]) {
+  constexpr int NC = (KIND == OP_BRUSSELATOR) ? 2 : 1;
+  double xv[5][2];
+  gather_x<KIND, NC>(op, x, p, xv);
+  rhs_values<KIND>(op, xv, (KIND == OP_DIAG) ? op.state[p] : 0.0, out);
 }
 
 // ---------------------------------------------------------------------------
@@ -259,14 +280,25 @@ __device__ __forceinline__ double wave_sum(double v) {
   return read_lane(v, 63);
 }
 
+// Inclusive sums within each row of 16 lanes (row_shr 1, 2, 4, 8): lane 15 of
+// a row then holds the sum of the row's 16 values.
+__device__ __forceinline__ double row_sum(double v) {
+  v += dpp_move<0x111>(v);
+  v += dpp_move<0x112>(v);
+  v += dpp_move<0x114>(v);
+  v += dpp_move<0x118>(v);
+  return v;
+}
+
 __device__ __forceinline__ double wave_max(double v) {
 #pragma unroll
   for (int off = 32; off >= 1; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
   return v;
 }
 
-// Sum NV values per thread over the block; result valid in red[0..NV) (LDS)
-// after the call for all threads.  red must hold NV * (blockDim.x/64) doubles.
+// Sum NV values per thread over the block; every thread's v[] holds the block
+// totals after the call.  red (LDS) must hold NV * (blockDim.x/64 + 1)
+// doubles: the wave sums, then the totals.
 template <int NV>
 __device__ __forceinline__ void block_sum(double (&v)[NV], double* red) {
   const int lane = threadIdx.x & 63;
@@ -368,10 +400,15 @@ __device__ __forceinline__ unsigned int grid_aborted(unsigned int* base) {
 // (LDS); nq = 0 makes it a plain barrier.  The barrier itself is run by the
 // first lane of the block's last wave; meanwhile the other waves run `overlap`
 // (work that touches no global memory another block writes before this
-// barrier).
-template <class Overlap = NoOverlap>
+// barrier).  Right after the barrier every thread runs `prefetch`, which may
+// issue loads of data the other blocks wrote before it (their latency then
+// overlaps that of the partial sums').  Each wave issues the loads of all its
+// rows of partials before summing any, so the reduction costs one memory
+// round trip.
+template <class Overlap = NoOverlap, class Prefetch = NoOverlap>
 __device__ __forceinline__ void grid_allreduce(unsigned int* base, unsigned int& epoch, double* area, int nq,
-                                               double* tot, Overlap&& overlap = Overlap{}) {
+                                               double* tot, Overlap&& overlap = Overlap{},
+                                               Prefetch&& prefetch = Prefetch{}) {
   __builtin_amdgcn_s_waitcnt(0);  // this thread's loads and stores have completed
   __syncthreads();
   epoch += 1u;
@@ -397,19 +434,44 @@ __device__ __forceinline__ void grid_allreduce(unsigned int* base, unsigned int&
     overlap();
   }
   __syncthreads();
+  prefetch();
   if (nq > 0) {
+    // slot q: lane t adds blocks t, t + 64, t + 128, ... in that order, then
+    // the wave sums its lanes (zeros stand in for absent blocks; the sums are
+    // of squares, never -0, so adding +0 changes nothing)
     const int G = gridDim.x;
     const int lane = threadIdx.x & 63;
     const int nw = blockDim.x >> 6;
-    for (int q = threadIdx.x >> 6; q < nq; q += nw) {
-      const double* __restrict__ row = area + (size_t)q * G;
-      double a = 0.0;
+    const int w = threadIdx.x >> 6;
+    if (G <= 256 && nq <= 3 * nw) {
+      double v[3][4];
 #pragma unroll
-      for (int r = 0; r < 4; ++r)
-        if (lane + 64 * r < G) a += row[lane + 64 * r];
-      for (int b = lane + 256; b < G; b += 64) a += row[b];
-      const double t = wave_sum(a);
-      if (lane == 0) tot[q] = t;
+      for (int r = 0; r < 3; ++r) {
+        const int q = w + r * nw;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          const int b = lane + 64 * c;
+          v[r][c] = (q < nq && b < G) ? area[(size_t)q * G + b] : 0.0;
+        }
+      }
+#pragma unroll
+      for (int r = 0; r < 3; ++r) {
+        const int q = w + r * nw;
+        if (q >= nq) break;
+        double a = 0.0;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) a += v[r][c];
+        const double t = wave_sum(a);
+        if (lane == 0) tot[q] = t;
+      }
+    } else {
+      for (int q = w; q < nq; q += nw) {
+        const double* __restrict__ row = area + (size_t)q * G;
+        double a = 0.0;
+        for (int b = lane; b < G; b += 64) a += row[b];
+        const double t = wave_sum(a);
+        if (lane == 0) tot[q] = t;
+      }
     }
     __syncthreads();
   }

@@ -168,12 +168,14 @@ struct Decision {
   int n_active;
   int iters;
   int accum_iters;
+  int next;  // predicted steps to the last stop (a length for the next super-step)
 };
 
 __device__ __forceinline__ void decision_init(Decision& D, int K, double nv, double hump_max, const double* fmaxk) {
   D.n_active = 0;
   D.iters = 0;
   D.accum_iters = 0;
+  D.next = kMaxPoints;
 #pragma unroll
   for (int k = 0; k < kMaxK; ++k) {
     D.st[k] = (k < K) ? ACC_RUNNING : ACC_CONVERGED;
@@ -246,10 +248,33 @@ __device__ void replay_decisions(Decision& D, int K, int m0, int steps, int Q, c
       }
     }
   }
+  // How many more steps the accumulators still running are likely to need:
+  // each extrapolates the decay of its ratio e / (stop threshold) over this
+  // batch of steps geometrically, plus one step of margin.  Only the length
+  // of the next batch of speculative steps depends on it, never a decision.
+  // (single precision suffices for a length; the same inputs give the same
+  // length in every block)
+  int need = 0;
+  {
+    float lq = 0.0f;
+    if (run0 && j < steps && oc == ACC_RUNNING) {
+      const double thr = relative ? tol * sqrt(tot[j * Q + 1 + k]) : tol;
+      lq = __log2f((float)e) - __log2f((float)thr);
+    }
+    const float l_first = __shfl(lq, k, 64);
+    const float l_last = __shfl(lq, 4 * max(steps - 1, 0) + k, 64);
+    if (lane < kMaxK && still) {
+      const float rate = (steps > 1) ? (l_first - l_last) / (float)(steps - 1) : 0.0f;
+      need = (rate > 0.0f && l_last < 64.0f * rate) ? (int)ceilf(l_last / rate) + 1 : kMaxPoints;
+      need = max(need, 1);
+    }
+  }
+  const int need_all = max(max(__shfl(need, 0, 64), __shfl(need, 1, 64)), max(__shfl(need, 2, 64), __shfl(need, 3, 64)));
   if (lane == 0) {
     D.n_active = __builtin_popcountll(alive);
     if (cmax > 0) D.iters = m0 + cmax;
     D.accum_iters += c0 + c1 + c2 + c3;
+    D.next = need_all;
   }
   if (trace != nullptr) {
     for (int t = lane; t < cmax * kQ; t += 64) {
@@ -276,6 +301,20 @@ __device__ __forceinline__ void write_status(LejaStatus* S, const Decision& D, i
   S->lam = lam;
   S->c = c;
   S->gamma = gamma;
+}
+
+// The launch's status, written by one thread: the device status block and,
+// when the caller passed a host slot (pinned host memory), the same header
+// there, so that the host needs no copy after the launch.
+__device__ __forceinline__ void store_status(const ActionParams& P, const Decision& D, int pit, int barriers,
+                                             double nv, double lam, double c, double gamma,
+                                             const unsigned long long (&prof)[8]) {
+  write_status(P.status, D, pit, barriers, nv, lam, c, gamma, P.barrier);
+  for (int q = 0; q < 8; ++q) P.status->prof[q] = prof[q];
+  if (P.status_host != nullptr) {
+    write_status(P.status_host, D, pit, barriers, nv, lam, c, gamma, P.barrier);
+    for (int q = 0; q < 8; ++q) P.status_host->prof[q] = prof[q];
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -374,7 +413,7 @@ struct ActionShared {
   double coef[kMaxK * kTable];
   double fmax[kMaxK];
   double tot[64];
-  double red[kPartStride * kWaves];  // staged wave sums, slot-major
+  double red[kQ * (kWaves + 1)];  // block_sum: wave sums, then totals
 };
 
 // ===========================================================================
@@ -450,7 +489,7 @@ __global__ __launch_bounds__(kBlock) void lj_action_stream(ActionParams P) {
     if (blockIdx.x == 0 && threadIdx.x == 0) {
       Decision D;
       decision_init(D, 0, 1.0, 0.0, sh.fmax);
-      write_status(P.status, D, pit, (int)epoch, 0.0, lam, c, gamma, P.barrier);
+      store_status(P, D, pit, (int)epoch, 0.0, lam, c, gamma, prof);
     }
     grid_exit(P.barrier);
     return;
@@ -527,8 +566,7 @@ __global__ __launch_bounds__(kBlock) void lj_action_stream(ActionParams P) {
     tick(kProfDecide);
   }
   if (blockIdx.x == 0 && threadIdx.x == 0) {
-    write_status(P.status, sD, pit, (int)epoch, nv, lam, c, gamma, P.barrier);
-    for (int q = 0; q < 8; ++q) P.status->prof[q] = prof[q];
+    store_status(P, sD, pit, (int)epoch, nv, lam, c, gamma, prof);
   }
   grid_exit(P.barrier);
 }
@@ -619,37 +657,54 @@ __global__ __launch_bounds__(kBlock) void lj_action_tile(ActionParams P) {
     __syncthreads();
     cur ^= 1;
   };
-  // refill the halo ring of the current buffer from a global vector and
-  // scale the owned points (scale 1: halo only)
-  auto load_halo = [&](const double* g, double scale) {
+  // halo ring of the extended tile: fetched from a global vector into
+  // registers right after a barrier (its loads overlap the partial sums'),
+  // written into the current buffer once the stop decisions are taken, the
+  // owned points scaled alongside (scale 1: halo only)
+  auto inner = [&](int k) {
+    const int ex = e_xy[k] & 0xffff, ey = e_xy[k] >> 16;
+    return ex >= S && ex < S + w && ey >= S && ey < S + h;
+  };
+  double hv[EPT];
+  auto fetch_halo = [&](const double* g) {
+#pragma unroll
+    for (int k = 0; k < EPT; ++k) {
+      const int e = threadIdx.x + k * kBlock;
+      hv[k] = (e < NE && !inner(k)) ? g[gidx(k)] : 0.0;
+    }
+  };
+  auto put_halo = [&](double scale) {
 #pragma unroll
     for (int k = 0; k < EPT; ++k) {
       const int e = threadIdx.x + k * kBlock;
       if (e >= NE) continue;
-      const int ex = e_xy[k] & 0xffff, ey = e_xy[k] >> 16;
-      const bool inner = ex >= S && ex < S + w && ey >= S && ey < S + h;
-      if (inner) {
+      if (inner(k)) {
         if (scale != 1.0) Y(cur)[e] *= scale;
       } else {
-        Y(cur)[e] = scale * g[gidx(k)];
+        Y(cur)[e] = scale * hv[k];
       }
     }
     __syncthreads();
   };
-  // wave sums of one value per thread into staging slot `slot`
+  // Block sums of one value per thread for each step of a super-step: per
+  // step only the 16-lane row sums are formed (four DPP adds) and staged,
+  // rowred[slot * 64 + 4 * wave + row]; the block totals of all the
+  // super-step's slots are formed at once before the barrier, one wave per
+  // slot summing its 64 row sums.
+  static_assert(4 * kWaves == 64, "one lane per row sum of a slot");
+  __shared__ double rowred[kPartStride * 4 * kWaves];
   auto stage = [&](int slot, double v) {
-    const double s = wave_sum(v);
-    if ((threadIdx.x & 63) == 0) sh.red[slot * kWaves + (threadIdx.x >> 6)] = s;
+    const double s = row_sum(v);
+    if ((threadIdx.x & 15) == 15) rowred[slot * 4 * kWaves + (threadIdx.x >> 4)] = s;
   };
   // block totals of staged slots [0, nslots) -> this barrier's partials
   auto publish = [&](int nslots) {
     __syncthreads();
     double* area = partial_area(P.partials, epoch);
-    if ((int)threadIdx.x < nslots) {
-      double t = 0.0;
-#pragma unroll
-      for (int wv = 0; wv < kWaves; ++wv) t += sh.red[threadIdx.x * kWaves + wv];
-      put_partial(my_partial(area, threadIdx.x), t);
+    const int lane = threadIdx.x & 63;
+    for (int q = threadIdx.x >> 6; q < nslots; q += kWaves) {
+      const double t = wave_sum(rowred[q * 4 * kWaves + lane]);
+      if (lane == 0) put_partial(my_partial(area, q), t);
     }
     __syncthreads();
     return area;
@@ -680,8 +735,12 @@ __global__ __launch_bounds__(kBlock) void lj_action_tile(ActionParams P) {
         stage(j, y * y);
       }
       double* area = publish(steps + 1);
-      if (own) store_shared(((par == 0) ? P.ybuf0 : P.ybuf1) + go, Y(cur)[eo]);
-      grid_allreduce(P.barrier, epoch, area, steps + 1, sh.tot);
+      double* yb = (par == 0) ? P.ybuf0 : P.ybuf1;
+      if (own) store_shared(yb + go, Y(cur)[eo]);
+      const bool more = done + steps < P.power_iters;
+      grid_allreduce(P.barrier, epoch, area, steps + 1, sh.tot, NoOverlap{}, [&] {
+        if (more) fetch_halo(yb);
+      });
       const double nprev = sh.tot[steps - 1], nlast = sh.tot[steps];
       done += steps;
       pit = done;
@@ -690,8 +749,8 @@ __global__ __launch_bounds__(kBlock) void lj_action_tile(ActionParams P) {
         lam = 0.0;
         break;
       }
-      if (done < P.power_iters) {
-        load_halo((par == 0) ? P.ybuf0 : P.ybuf1, 1.0 / sqrt(nlast));
+      if (more) {
+        put_halo(1.0 / sqrt(nlast));
         par ^= 1;
       }
     }
@@ -706,8 +765,7 @@ __global__ __launch_bounds__(kBlock) void lj_action_tile(ActionParams P) {
     if (blockIdx.x == 0 && threadIdx.x == 0) {
       Decision D;
       decision_init(D, 0, 1.0, 0.0, sh.fmax);
-      write_status(P.status, D, pit, (int)epoch, 0.0, lam, c, gamma, P.barrier);
-      for (int q = 0; q < 8; ++q) P.status->prof[q] = prof[q];
+      store_status(P, D, pit, (int)epoch, 0.0, lam, c, gamma, prof);
     }
     grid_exit(P.barrier);
     return;
@@ -741,7 +799,7 @@ __global__ __launch_bounds__(kBlock) void lj_action_tile(ActionParams P) {
   bool first = true;
   int m0 = 0;
   while (true) {
-    const int steps = min(S, P.max_points - m0);
+    const int steps = min(min(S, P.max_points - m0), uniform(sD.next));
     bool act0[kMaxK];
 #pragma unroll
     for (int k = 0; k < kMaxK; ++k) act0[k] = (k < K) && (uniform(sD.st[k]) == ACC_RUNNING);
@@ -767,9 +825,12 @@ __global__ __launch_bounds__(kBlock) void lj_action_tile(ActionParams P) {
     if (first) stage(steps * Q, v_own * v_own);  // ||v||^2 rides on the first barrier
     const int nq = steps * Q + (first ? 1 : 0);
     double* area = publish(nq);
-    if (own) store_shared(((par == 0) ? P.ybuf0 : P.ybuf1) + go, Y(cur)[eo]);
+    double* yb = (par == 0) ? P.ybuf0 : P.ybuf1;
+    if (own) store_shared(yb + go, Y(cur)[eo]);
     tick(kProfPublish);
-    grid_allreduce(P.barrier, epoch, area, nq, sh.tot, [&] { dd_advance(dd, K, m0 + steps + S, sh.xi, sh.coef); });
+    grid_allreduce(
+        P.barrier, epoch, area, nq, sh.tot, [&] { dd_advance(dd, K, m0 + steps + S, sh.xi, sh.coef); },
+        [&] { fetch_halo(yb); });
     tick(kProfBarrier);
     if (threadIdx.x < 64) {
       if (first) {
@@ -793,7 +854,7 @@ __global__ __launch_bounds__(kBlock) void lj_action_tile(ActionParams P) {
     m0 += steps;
     tick(kProfCommit);
     if (sD.n_active == 0 || m0 >= P.max_points) break;
-    load_halo((par == 0) ? P.ybuf0 : P.ybuf1, 1.0);
+    put_halo(1.0);
     par ^= 1;
     tick(kProfHalo);
   }
@@ -803,8 +864,7 @@ __global__ __launch_bounds__(kBlock) void lj_action_tile(ActionParams P) {
       if (k < K) P.p[k][go] = pk[k];
   }
   if (blockIdx.x == 0 && threadIdx.x == 0) {
-    write_status(P.status, sD, pit, (int)epoch, nv, lam, c, gamma, P.barrier);
-    for (int q = 0; q < 8; ++q) P.status->prof[q] = prof[q];
+    store_status(P, sD, pit, (int)epoch, nv, lam, c, gamma, prof);
   }
   grid_exit(P.barrier);
 }
@@ -1069,26 +1129,105 @@ __global__ __launch_bounds__(256) void lj_rhs_kernel(OpDev op, const double* __r
   }
 }
 
-// R = f(x) - fu - J(state) d with d = x - state precomputed (Sec. 1 remainder)
-template <int KIND, int NC>
-__global__ __launch_bounds__(256) void lj_remainder_kernel(OpDev op, const double* __restrict__ x,
-                                                           const double* __restrict__ d,
-                                                           const double* __restrict__ fu,
-                                                           double* __restrict__ r) {
-  for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < op.npts; p += gridDim.x * blockDim.x) {
-    double fx[2], jd[2], dc[2];
-    rhs_point<KIND>(op, x, p, fx);
-    jv_point<KIND, NC>(op, d, p, jd, dc);
-#pragma unroll
-    for (int cc = 0; cc < NC; ++cc) r[NC * p + cc] = (fx[cc] - fu[NC * p + cc]) - jd[cc];
-  }
-}
-
+// out = alpha_0 x_0, then out = fma(alpha_q, x_q, out) for q = 1, 2, ...
 __global__ __launch_bounds__(256) void lj_lincomb_kernel(LinComb L) {
   for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < L.n; i += (long)gridDim.x * blockDim.x) {
     double s = L.alpha[0] * L.x[0][i];
-    for (int q = 1; q < L.nin; ++q) s += L.alpha[q] * L.x[q][i];
+    for (int q = 1; q < L.nin; ++q) s = fma(L.alpha[q], L.x[q][i], s);
     L.out[i] = s;
+  }
+}
+
+// f = f(u) and v = h f in one pass (the first stage of every scheme)
+template <int KIND, int NC>
+__global__ __launch_bounds__(256) void lj_rhs_scaled_kernel(OpDev op, double h, double* __restrict__ f,
+                                                            double* __restrict__ v) {
+  for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < op.npts; p += gridDim.x * blockDim.x) {
+    double out[2];
+    rhs_point<KIND>(op, op.state, p, out);
+#pragma unroll
+    for (int cc = 0; cc < NC; ++cc) {
+      f[NC * p + cc] = out[cc];
+      v[NC * p + cc] = h * out[cc];
+    }
+  }
+}
+
+// The stage arguments of the exponential Rosenbrock / EPIRK schemes in one
+// pass: up to two remainders R_r = f(x_r) - f(u) - J(u)(x_r - u) (Sec. 1) at
+// x_r = u + sum_t a[r][t] X[r][t], formed point by point (x_r and x_r - u are
+// recomputed at the stencil neighbours from u and the X's), then up to two
+// combinations of R_0, R_1 and an extra vector P.  Each combination is formed
+// as the linear-combination kernel forms one (a product, then FMAs in order).
+template <int KIND, int NC>
+__global__ __launch_bounds__(256) void lj_stage_kernel(StageArgs A) {
+  const OpDev& op = A.op;
+  const double* __restrict__ u = op.state;
+  for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < op.npts; p += gridDim.x * blockDim.x) {
+    int idx[5] = {p, p, p, p, p};
+    if constexpr (KIND != OP_DIAG) {
+      const Nbr q = neighbours(op, p);
+      idx[1] = q.w;
+      idx[2] = q.e;
+      idx[3] = q.s;
+      idx[4] = q.n;
+    }
+    constexpr int NT = (KIND == OP_DIAG) ? 1 : 5;
+    double uv[5][2] = {};
+#pragma unroll
+    for (int t = 0; t < NT; ++t)
+#pragma unroll
+      for (int c = 0; c < NC; ++c) uv[t][c] = u[NC * idx[t] + c];
+    double R[2][2] = {};
+    for (int r = 0; r < A.nrem; ++r) {
+      double xv[5][2] = {}, dv[5][2] = {};
+#pragma unroll
+      for (int t = 0; t < NT; ++t)
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+          const int i = NC * idx[t] + c;
+          double x = 1.0 * uv[t][c];
+          x = fma(A.a[r][0], A.X[r][0][i], x);
+          if (A.nterm[r] > 1) x = fma(A.a[r][1], A.X[r][1][i], x);
+          xv[t][c] = x;
+          dv[t][c] = fma(-1.0, uv[t][c], 1.0 * x);
+        }
+      double fx[2], jd[2];
+      rhs_values<KIND>(op, xv, uv[0][0], fx);
+      stencil_jv<KIND>(op, dv, uv, jd);
+#pragma unroll
+      for (int c = 0; c < NC; ++c) R[r][c] = (fx[c] - A.fu[NC * p + c]) - jd[c];
+    }
+    for (int o = 0; o < A.nout; ++o) {
+#pragma unroll
+      for (int c = 0; c < NC; ++c) {
+        const int i = NC * p + c;
+        auto src = [&](int t) { return A.src[o][t] == 2 ? A.P[i] : R[A.src[o][t]][c]; };
+        double y = A.c[o][0] * src(0);
+        if (A.nsrc[o] > 1) y = fma(A.c[o][1], src(1), y);
+        A.out[o][i] = y;
+      }
+    }
+  }
+}
+
+// The step's result from its stages: u3 = u + X1 (+ X2); with X3,
+// u_out = u3 + X3 and err = u_out - u3; without, u_out = u3 and err = 0 u + 0 u
+// (the same operations as the linear-combination kernel's).
+__global__ __launch_bounds__(256) void lj_finish_kernel(FinishArgs F) {
+  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < F.n; i += (long)gridDim.x * blockDim.x) {
+    const double uu = F.u[i];
+    double u3 = 1.0 * uu;
+    u3 = fma(1.0, F.X1[i], u3);
+    if (F.X2) u3 = fma(1.0, F.X2[i], u3);
+    if (F.X3) {
+      const double uo = fma(1.0, F.X3[i], 1.0 * u3);
+      F.u_out[i] = uo;
+      if (F.err) F.err[i] = fma(-1.0, u3, 1.0 * uo);
+    } else {
+      F.u_out[i] = u3;
+      if (F.err) F.err[i] = fma(0.0, uu, 0.0 * uu);
+    }
   }
 }
 
@@ -1168,13 +1307,6 @@ template <int KIND, int NC>
 static void rhs_t(const OpDev& op, const double* u, double* f, hipStream_t s) {
   hipLaunchKernelGGL((lj_rhs_kernel<KIND, NC>), dim3(stream_grid(op.npts)), dim3(256), 0, s, op, u, f);
 }
-template <int KIND, int NC>
-static void rem_t(const OpDev& op, const double* x, const double* d, const double* fu, double* r,
-                  hipStream_t s) {
-  hipLaunchKernelGGL((lj_remainder_kernel<KIND, NC>), dim3(stream_grid(op.npts)), dim3(256), 0, s, op,
-                     x, d, fu, r);
-}
-
 hipError_t launch_rhs(const OpDev& op, const double* u, double* f, hipStream_t s) {
   switch (op.kind) {
     case OP_DIAG: rhs_t<OP_DIAG, 1>(op, u, f, s); break;
@@ -1187,16 +1319,41 @@ hipError_t launch_rhs(const OpDev& op, const double* u, double* f, hipStream_t s
   return hipGetLastError();
 }
 
-hipError_t launch_remainder(const OpDev& op, const double* x, const double* d, const double* fu,
-                            double* r, hipStream_t s) {
+template <int KIND, int NC>
+static void rhs_scaled_t(const OpDev& op, double h, double* f, double* v, hipStream_t s) {
+  hipLaunchKernelGGL((lj_rhs_scaled_kernel<KIND, NC>), dim3(stream_grid(op.npts)), dim3(256), 0, s, op, h, f, v);
+}
+template <int KIND, int NC>
+static void stage_t(const StageArgs& A, hipStream_t s) {
+  hipLaunchKernelGGL((lj_stage_kernel<KIND, NC>), dim3(stream_grid(A.op.npts)), dim3(256), 0, s, A);
+}
+
+hipError_t launch_rhs_scaled(const OpDev& op, double h, double* f, double* v, hipStream_t s) {
   switch (op.kind) {
-    case OP_DIAG: rem_t<OP_DIAG, 1>(op, x, d, fu, r, s); break;
-    case OP_ADVDIFF: rem_t<OP_ADVDIFF, 1>(op, x, d, fu, r, s); break;
-    case OP_ALLENCAHN: rem_t<OP_ALLENCAHN, 1>(op, x, d, fu, r, s); break;
-    case OP_BRUSSELATOR: rem_t<OP_BRUSSELATOR, 2>(op, x, d, fu, r, s); break;
-    case OP_BURGERS: rem_t<OP_BURGERS, 1>(op, x, d, fu, r, s); break;
+    case OP_DIAG: rhs_scaled_t<OP_DIAG, 1>(op, h, f, v, s); break;
+    case OP_ADVDIFF: rhs_scaled_t<OP_ADVDIFF, 1>(op, h, f, v, s); break;
+    case OP_ALLENCAHN: rhs_scaled_t<OP_ALLENCAHN, 1>(op, h, f, v, s); break;
+    case OP_BRUSSELATOR: rhs_scaled_t<OP_BRUSSELATOR, 2>(op, h, f, v, s); break;
+    case OP_BURGERS: rhs_scaled_t<OP_BURGERS, 1>(op, h, f, v, s); break;
     default: return hipErrorInvalidValue;
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_stage(const StageArgs& A, hipStream_t s) {
+  switch (A.op.kind) {
+    case OP_DIAG: stage_t<OP_DIAG, 1>(A, s); break;
+    case OP_ADVDIFF: stage_t<OP_ADVDIFF, 1>(A, s); break;
+    case OP_ALLENCAHN: stage_t<OP_ALLENCAHN, 1>(A, s); break;
+    case OP_BRUSSELATOR: stage_t<OP_BRUSSELATOR, 2>(A, s); break;
+    case OP_BURGERS: stage_t<OP_BURGERS, 1>(A, s); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_finish(const FinishArgs& F, hipStream_t s) {
+  hipLaunchKernelGGL(lj_finish_kernel, dim3(stream_grid(F.n)), dim3(256), 0, s, F);
   return hipGetLastError();
 }
 

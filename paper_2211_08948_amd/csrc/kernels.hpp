@@ -16,6 +16,37 @@ struct LinComb {
   double* out;
 };
 
+// Stage arguments of a scheme in one pass (see lj_stage_kernel): remainders
+// R_r at x_r = state + sum_{t < nterm[r]} a[r][t] X[r][t], r < nrem <= 2, then
+// out[o] = sum_{t < nsrc[o]} c[o][t] S_{src[o][t]}, o < nout <= 2, with
+// S_0 = R_0, S_1 = R_1, S_2 = P.
+struct StageArgs {
+  OpDev op;
+  const double* fu;
+  int nrem;
+  int nterm[2];
+  double a[2][2];
+  const double* X[2][2];
+  const double* P;
+  int nout;
+  int nsrc[2];
+  int src[2][2];
+  double c[2][2];
+  double* out[2];
+};
+
+// u_out = u + X1 (+ X2) (+ X3), err = u_out - (u + X1 (+ X2)) if X3 is given,
+// else 0 (see lj_finish_kernel); n values
+struct FinishArgs {
+  long n;
+  const double* u;
+  const double* X1;
+  const double* X2;
+  const double* X3;
+  double* u_out;
+  double* err;
+};
+
 int persistent_block();  // threads per block of the action kernels
 int tile_halo();         // halo width = Newton steps per barrier of the tiled kernel
 void* action_stream_ptr(int kind);
@@ -25,8 +56,9 @@ hipError_t launch_divdiff(const DDParams& P, hipStream_t s);
 void* batch_kernel_ptr(int kind, int block_size);  // block_size in {256, 512, 1024}
 hipError_t launch_fill_u32(unsigned int* p, int n, unsigned int v, hipStream_t s);
 hipError_t launch_rhs(const OpDev& op, const double* u, double* f, hipStream_t s);
-hipError_t launch_remainder(const OpDev& op, const double* x, const double* d, const double* fu,
-                            double* r, hipStream_t s);
 hipError_t launch_lincomb(const LinComb& L, hipStream_t s);
+hipError_t launch_rhs_scaled(const OpDev& op, double h, double* f, double* v, hipStream_t s);  // f(state), h f
+hipError_t launch_stage(const StageArgs& A, hipStream_t s);
+hipError_t launch_finish(const FinishArgs& F, hipStream_t s);
 
 }  // namespace lj

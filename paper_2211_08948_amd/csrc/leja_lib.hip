@@ -31,13 +31,13 @@ enum Slot {
   W_P0, W_P1, W_P2, W_P3,          // phi_j(tau J) v of a substepped action
   W_SW0, W_SW1, W_SE,              // substep propagation buffers
   W_FU, W_V, W_A, W_B, W_C,        // stage driver: f(u), h f(u), vertical results
-  W_XA, W_XB, W_D, W_RA, W_RB,     // stages a, b, x - u, R(a), R(b)
-  W_T3, W_D3, W_T4, W_D4, W_U3,    // phi_3 / phi_4 inputs and results, u_3
+  W_RA, W_T1,                      // R(a) kept for a later stage, the phi_1 input of EXPRB43
+  W_T3, W_D3, W_T4, W_D4,          // phi_3 / phi_4 inputs and results
   W_NSLOTS
 };
 
 // LDS held back from the tiled kernel's dynamic allocation for its static arrays
-constexpr size_t kStaticLdsReserve = 20 * 1024;
+constexpr size_t kStaticLdsReserve = 40 * 1024;
 constexpr int kQ_batch = 1 + kMaxK;  // team partial sums per reduction
 constexpr int kAsyncSlots = 8;       // most action launches of one step
 
@@ -340,7 +340,7 @@ bool coresident(lj_context* ctx, const void* fn, int G, size_t dyn) {
 void launch_action(lj_context* ctx, const OpDev& op, const double* v, int K, const int* l, const double* s_k,
                    double lam_host, uint64_t seed, const double* start, double* const* outs, const Opts& o,
                    double tol, hipStream_t s, const BoundLink& link, LejaStatus* status_dst, size_t status_bytes,
-                   hipEvent_t* ev, bool* tiled, bool cooperative = false) {
+                   hipEvent_t* ev, bool* tiled, bool cooperative = false, bool direct_status = false) {
   const size_t n = nvals(op);
   ActionParams P;
   std::memset(&P, 0, sizeof(P));
@@ -369,6 +369,9 @@ void launch_action(lj_context* ctx, const OpDev& op, const double* v, int K, con
   P.ybuf1 = slot(ctx, W_Y1, n);
   P.barrier = ctx->d_barrier;
   P.status = ctx->d_status;
+  // a header-only status into a slot of the pinned pool is written by the
+  // kernel itself; otherwise it is copied after the launch
+  P.status_host = direct_status ? status_dst : nullptr;
   const TilePlan tp = tile_plan(ctx, op);
   void* fn = nullptr;
   int G = 0;
@@ -398,7 +401,7 @@ void launch_action(lj_context* ctx, const OpDev& op, const double* v, int K, con
     HIPCHK(ctx, hipLaunchKernel(fn, dim3(G), dim3(persistent_block()), args, (unsigned)dyn, s));
   }
   if (ev) HIPCHK(ctx, hipEventRecord(ev[1], s));
-  HIPCHK(ctx, hipMemcpyAsync(status_dst, ctx->d_status, status_bytes, hipMemcpyDeviceToHost, s));
+  if (!direct_status) HIPCHK(ctx, hipMemcpyAsync(status_dst, ctx->d_status, status_bytes, hipMemcpyDeviceToHost, s));
   if (tiled) *tiled = tp.ok;
 }
 
@@ -960,7 +963,8 @@ LJ_API int lj_create(lj_context** out, int hip_device) {
     HIPCHK(ctx, hipHostMalloc(&ctx->h_coef, kMaxK * kTable * sizeof(double), hipHostMallocDefault));
     for (int i = 0; i < 4; ++i) HIPCHK(ctx, hipEventCreate(&ctx->ev[i]));
     for (int i = 0; i < 2 * kAsyncSlots; ++i) HIPCHK(ctx, hipEventCreate(&ctx->ev_pool[i]));
-    HIPCHK(ctx, hipHostMalloc(&ctx->h_pool, kAsyncSlots * sizeof(LejaStatus), hipHostMallocDefault));
+    // fine-grained: the action kernels write their status headers here directly
+    HIPCHK(ctx, hipHostMalloc(&ctx->h_pool, kAsyncSlots * sizeof(LejaStatus), hipHostMallocCoherent));
     HIPCHK(ctx, hipMalloc(&ctx->d_bound, sizeof(double)));
     if (const char* g = std::getenv("LJ_GRID")) ctx->grid_override = std::atoi(g);
     if (const char* g = std::getenv("LJ_NO_TILE")) ctx->force_stream = std::atoi(g);
@@ -1153,129 +1157,163 @@ LJ_API int lj_step(lj_context* ctx, int scheme, const lj_operator* J, double h, 
     const size_t n = nvals(op);
     const double* u = op.state;
     // the scheme's stages; `act` runs one (vertical) Leja call
+    // The scheme's stages; `act` runs one (vertical) Leja call.  Between the
+    // Leja calls: f(u) and v = h f(u) in one pass, the remainders and the
+    // vectors the next calls act on in one pass, the result and error
+    // estimate in one pass.
     auto scheme_steps = [&](auto&& act) {
       double* fu = slot(ctx, W_FU, n);
       double* v = slot(ctx, W_V, n);
-      HIPCHK(ctx, launch_rhs(op, u, fu, s));
-      {
-        const double al[1] = {h};
-        const double* xs[1] = {fu};
-        lincomb(ctx, n, v, 1, al, xs, s);
-      }
-      auto comb2 = [&](double* out, double a0, const double* x0, double a1, const double* x1) {
-        const double al[2] = {a0, a1};
-        const double* xs[2] = {x0, x1};
-        lincomb(ctx, n, out, 2, al, xs, s);
+      HIPCHK(ctx, launch_rhs_scaled(op, h, fu, v, s));
+      auto finish = [&](const double* X1, const double* X2, const double* X3) {
+        FinishArgs F;
+        F.n = (long)n;
+        F.u = u;
+        F.X1 = X1;
+        F.X2 = X2;
+        F.X3 = X3;
+        F.u_out = u_out;
+        F.err = err;
+        HIPCHK(ctx, launch_finish(F, s));
       };
-      auto comb3 = [&](double* out, double a0, const double* x0, double a1, const double* x1, double a2,
-                       const double* x2) {
-        const double al[3] = {a0, a1, a2};
-        const double* xs[3] = {x0, x1, x2};
-        lincomb(ctx, n, out, 3, al, xs, s);
-      };
-      // R(x) = f(x) - f(u) - J(u)(x - u)
-      auto remainder = [&](const double* x, double* r) {
-        double* d = slot(ctx, W_D, n);
-        comb2(d, 1.0, x, -1.0, u);
-        HIPCHK(ctx, launch_remainder(op, x, d, fu, r, s));
+      auto stage_args = [&]() {
+        StageArgs A;
+        std::memset(&A, 0, sizeof(A));
+        A.op = op;
+        A.fu = fu;
+        return A;
       };
       if (scheme == LJ_EXPRB2) {
         double* A = slot(ctx, W_A, n);
         const int ls[1] = {1};
         const double as[1] = {1.0};
         act(v, 1, ls, as, &A);
-        comb2(u_out, 1.0, u, 1.0, A);
-        if (err) comb2(err, 0.0, u, 0.0, u);
+        finish(A, nullptr, nullptr);
       } else if (scheme == LJ_EXPRB43 || scheme == LJ_EXPRB43_U3) {
         double* A = slot(ctx, W_A, n);
         double* B = slot(ctx, W_B, n);
         double* C = slot(ctx, W_C, n);
-        double* xa = slot(ctx, W_XA, n);
-        double* xb = slot(ctx, W_XB, n);
         double* Ra = slot(ctx, W_RA, n);
-        double* Rb = slot(ctx, W_RB, n);
+        double* T1 = slot(ctx, W_T1, n);
         double* T3 = slot(ctx, W_T3, n);
+        double* T4 = slot(ctx, W_T4, n);
         double* D3 = slot(ctx, W_D3, n);
-        double* u3 = (scheme == LJ_EXPRB43_U3) ? u_out : slot(ctx, W_U3, n);
         {
           const int ls[2] = {1, 1};
           const double as[2] = {0.5, 1.0};
           double* outs[2] = {A, B};
           act(v, 2, ls, as, outs);
         }
-        comb2(xa, 1.0, u, 0.5, A);
-        remainder(xa, Ra);
-        double* T1 = slot(ctx, W_T4, n);
-        {
-          const double al[1] = {h};
-          const double* xs[1] = {Ra};
-          lincomb(ctx, n, T1, 1, al, xs, s);
+        {  // R_a at u + A/2; T1 = h R_a (and R_a kept)
+          StageArgs S = stage_args();
+          S.nrem = 1;
+          S.nterm[0] = 1;
+          S.a[0][0] = 0.5;
+          S.X[0][0] = A;
+          S.nout = 2;
+          S.nsrc[0] = 1;
+          S.src[0][0] = 0;
+          S.c[0][0] = h;
+          S.out[0] = T1;
+          S.nsrc[1] = 1;
+          S.src[1][0] = 0;
+          S.c[1][0] = 1.0;
+          S.out[1] = Ra;
+          HIPCHK(ctx, launch_stage(S, s));
         }
         {
           const int ls[1] = {1};
           const double as[1] = {1.0};
           act(T1, 1, ls, as, &C);
         }
-        comb3(xb, 1.0, u, 1.0, B, 1.0, C);
-        remainder(xb, Rb);
-        comb2(T3, 16.0 * h, Ra, -2.0 * h, Rb);
+        {  // R_b at u + B + C; T3 = 16 h R_a - 2 h R_b (and T4 = -48 h R_a + 12 h R_b)
+          StageArgs S = stage_args();
+          S.nrem = 1;
+          S.nterm[0] = 2;
+          S.a[0][0] = 1.0;
+          S.X[0][0] = B;
+          S.a[0][1] = 1.0;
+          S.X[0][1] = C;
+          S.P = Ra;
+          S.nout = (scheme == LJ_EXPRB43) ? 2 : 1;
+          S.nsrc[0] = 2;
+          S.src[0][0] = 2;
+          S.c[0][0] = 16.0 * h;
+          S.src[0][1] = 0;
+          S.c[0][1] = -2.0 * h;
+          S.out[0] = T3;
+          S.nsrc[1] = 2;
+          S.src[1][0] = 2;
+          S.c[1][0] = -48.0 * h;
+          S.src[1][1] = 0;
+          S.c[1][1] = 12.0 * h;
+          S.out[1] = T4;
+          HIPCHK(ctx, launch_stage(S, s));
+        }
         {
           const int ls[1] = {3};
           const double as[1] = {1.0};
           act(T3, 1, ls, as, &D3);
         }
-        comb3(u3, 1.0, u, 1.0, B, 1.0, D3);
         if (scheme == LJ_EXPRB43) {
-          double* T4 = slot(ctx, W_T4, n);
           double* D4 = slot(ctx, W_D4, n);
-          comb2(T4, -48.0 * h, Ra, 12.0 * h, Rb);
           const int ls[1] = {4};
           const double as[1] = {1.0};
           act(T4, 1, ls, as, &D4);
-          comb2(u_out, 1.0, u3, 1.0, D4);
-          if (err) comb2(err, 1.0, u_out, -1.0, u3);
-        } else if (err) {
-          comb2(err, 0.0, u, 0.0, u);
+          finish(B, D3, D4);
+        } else {
+          finish(B, D3, nullptr);
         }
       } else {  // EPIRK4s3
         double* A = slot(ctx, W_A, n);
         double* B = slot(ctx, W_B, n);
         double* C = slot(ctx, W_C, n);
-        double* xa = slot(ctx, W_XA, n);
-        double* xb = slot(ctx, W_XB, n);
-        double* Ra = slot(ctx, W_RA, n);
-        double* Rb = slot(ctx, W_RB, n);
         double* T3 = slot(ctx, W_T3, n);
         double* D3 = slot(ctx, W_D3, n);
         double* T4 = slot(ctx, W_T4, n);
         double* D4 = slot(ctx, W_D4, n);
-        double* u3 = slot(ctx, W_U3, n);
         {
           const int ls[3] = {1, 1, 1};
           const double as[3] = {1.0 / 8.0, 1.0 / 9.0, 1.0};
           double* outs[3] = {A, B, C};
           act(v, 3, ls, as, outs);
         }
-        comb2(xa, 1.0, u, 1.0 / 8.0, A);
-        comb2(xb, 1.0, u, 1.0 / 9.0, B);
-        remainder(xa, Ra);
-        remainder(xb, Rb);
-        // h (1892 Ra + 1458 (Rb - 2 Ra)) and h (-42336 Ra - 34992 (Rb - 2 Ra))
-        comb2(T3, h * (1892.0 - 2.0 * 1458.0), Ra, h * 1458.0, Rb);
-        comb2(T4, h * (-42336.0 + 2.0 * 34992.0), Ra, h * -34992.0, Rb);
+        {  // R_a at u + A/8, R_b at u + B/9;
+           // h (1892 Ra + 1458 (Rb - 2 Ra)) and h (-42336 Ra - 34992 (Rb - 2 Ra))
+          StageArgs S = stage_args();
+          S.nrem = 2;
+          S.nterm[0] = 1;
+          S.a[0][0] = 1.0 / 8.0;
+          S.X[0][0] = A;
+          S.nterm[1] = 1;
+          S.a[1][0] = 1.0 / 9.0;
+          S.X[1][0] = B;
+          S.nout = 2;
+          S.nsrc[0] = 2;
+          S.src[0][0] = 0;
+          S.c[0][0] = h * (1892.0 - 2.0 * 1458.0);
+          S.src[0][1] = 1;
+          S.c[0][1] = h * 1458.0;
+          S.out[0] = T3;
+          S.nsrc[1] = 2;
+          S.src[1][0] = 0;
+          S.c[1][0] = h * (-42336.0 + 2.0 * 34992.0);
+          S.src[1][1] = 1;
+          S.c[1][1] = h * -34992.0;
+          S.out[1] = T4;
+          HIPCHK(ctx, launch_stage(S, s));
+        }
         {
           const int ls[1] = {3};
           const double as[1] = {1.0};
           act(T3, 1, ls, as, &D3);
         }
-        comb3(u3, 1.0, u, 1.0, C, 1.0, D3);
         {
           const int ls[1] = {4};
           const double as[1] = {1.0};
           act(T4, 1, ls, as, &D4);
         }
-        comb2(u_out, 1.0, u3, 1.0, D4);
-        if (err) comb2(err, 1.0, u_out, -1.0, u3);
+        finish(C, D3, D4);
       }
     };
     std::vector<lj_stats> log;
@@ -1311,7 +1349,8 @@ LJ_API int lj_step(lj_context* ctx, int scheme, const lj_operator* J, double h, 
         }
         bool tiled = false;
         launch_action(ctx, op, vec, K, ls, sk, lam_host, o.seed, o.pi_start, outs, o, tol, s, link, &ctx->h_pool[i],
-                      offsetof(LejaStatus, trace), ctx->timing ? &ctx->ev_pool[2 * i] : nullptr, &tiled);
+                      offsetof(LejaStatus, trace), ctx->timing ? &ctx->ev_pool[2 * i] : nullptr, &tiled, false,
+                      true);
         pend.push_back({K, tiled, &op});
       };
       scheme_steps(act_async);

@@ -90,9 +90,39 @@ def make_records(ctx, count: int, seed: int = 7, chunk: int = 512, hmult=(1.0, 1
     return X[perm].contiguous(), T[perm].contiguous()
 
 
-def compare(ctx, prob, h, l, v=None):
-    """One action by the plain method and by the proposal: statistics, wall
-    time of each, and the relative difference of the two results."""
+def gershgorin_bound(prob) -> float:
+    """A closed-form bound of the spectral radius of J (Gershgorin discs of the
+    5-point Jacobian at the problem's state), the no-iteration baseline the
+    proposal is compared with.  Host-side NumPy over the state."""
+    import numpy as np
+    dx, dy = prob.dx, prob.dy
+    if prob.kind == "burgers":
+        nu = prob.coef[0]
+        U = np.asarray(prob.state, dtype=np.float64).reshape(prob.ny, prob.nx)
+        diag = 2.0 * nu * (1.0 / dx ** 2 + 1.0 / dy ** 2)
+        off = (np.abs(nu / dx ** 2 - np.roll(U, -1, axis=1) / (2 * dx))
+               + np.abs(nu / dx ** 2 + np.roll(U, 1, axis=1) / (2 * dx))
+               + np.abs(nu / dy ** 2 - np.roll(U, -1, axis=0) / (2 * dy))
+               + np.abs(nu / dy ** 2 + np.roll(U, 1, axis=0) / (2 * dy)))
+        return float(np.max(diag + off))
+    if prob.kind == "allencahn":
+        eps = prob.coef[0]
+        u = np.asarray(prob.state, dtype=np.float64)
+        lap = 2.0 * eps * (1.0 / dx ** 2 + 1.0 / dy ** 2)
+        return float(np.max(np.abs(-lap + 1.0 - 3.0 * u * u)) + lap)
+    if prob.kind == "advdiff":
+        nu, ax, ay = prob.coef[0], prob.coef[1], prob.coef[2]
+        diag = 2.0 * nu * (1.0 / dx ** 2 + 1.0 / dy ** 2)
+        return diag + abs(nu / dx ** 2 - ax / (2 * dx)) + abs(nu / dx ** 2 + ax / (2 * dx)) \
+            + abs(nu / dy ** 2 - ay / (2 * dy)) + abs(nu / dy ** 2 + ay / (2 * dy))
+    raise ValueError(f"no Gershgorin bound for {prob.kind}")
+
+
+def compare(ctx, prob, h, l, v=None, gershgorin=False):
+    """One action by the plain method and by the proposal (and, if asked, with
+    the closed-form Gershgorin bound and no power iteration): statistics, wall
+    time of each, and the relative difference of the proposal's result to the
+    plain one."""
     import torch
     lj = _lj()
     op = lj.operator_from(prob, "cuda:0")
@@ -104,12 +134,15 @@ def compare(ctx, prob, h, l, v=None):
         vd = torch.as_tensor(v, dtype=torch.float64, device="cuda:0").contiguous()
     out = {}
     res = {}
-    for name, use in (("plain", 0), ("proposal", 1)):
+    variants = [("plain", lj.lj_default_options()), ("proposal", lj.lj_default_options(use_proposal=1))]
+    if gershgorin:
+        variants.append(("gershgorin", lj.lj_default_options(bound=gershgorin_bound(prob))))
+    for name, opt in variants:
         w = torch.empty_like(vd)
-        lj.lj_phi_action(ctx, op, vd, w, l, h, TOL, lj.lj_default_options(use_proposal=use))  # warm-up
+        lj.lj_phi_action(ctx, op, vd, w, l, h, TOL, opt)  # warm-up
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        rc, st = lj.lj_phi_action(ctx, op, vd, w, l, h, TOL, lj.lj_default_options(use_proposal=use))
+        rc, st = lj.lj_phi_action(ctx, op, vd, w, l, h, TOL, opt)
         torch.cuda.synchronize()
         st["ms"] = (time.perf_counter() - t0) * 1e3
         st["rc"] = rc
@@ -128,10 +161,11 @@ def evaluate(ctx, n: int = 2048, hmults=(1, 10, 30, 100, 300), log=print):
     rows = []
     for hm in hmults:
         for l in LS:
-            r = compare(ctx, prob, hm * prob.h_cfl, l)
-            rows.append({"hmult": hm, "l": l, **{f"{k}_{f}": r[k][f] for k in ("plain", "proposal")
+            r = compare(ctx, prob, hm * prob.h_cfl, l, gershgorin=True)
+            rows.append({"hmult": hm, "l": l, **{f"{k}_{f}": r[k][f] for k in ("plain", "proposal", "gershgorin")
                                                   for f in ("ms", "products", "rejections", "substeps", "rc")},
-                         "fallback": r["proposal"]["fallbacks"], "rel_diff": r["rel_diff"]})
+                         "fallback": r["proposal"]["fallbacks"], "rel_diff": r["rel_diff"],
+                         "gershgorin_bound": r["gershgorin"]["bound"], "plain_bound": r["plain"]["bound"]})
             log(json.dumps(rows[-1]), flush=True)
     return rows
 
