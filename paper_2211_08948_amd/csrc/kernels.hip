@@ -236,7 +236,8 @@ __device__ void replay_decisions(Decision& D, int K, int m0, int steps, int Q, c
   const int cm = run0 ? (first >= 0 ? (first >> 2) + 1 : steps) : 0;
   const bool still = run0 && first < 0;
   const unsigned long long alive = __ballot(lane < kMaxK && still);
-  const int c0 = __shfl(cm, 0, 64), c1 = __shfl(cm, 1, 64), c2 = __shfl(cm, 2, 64), c3 = __shfl(cm, 3, 64);
+  const int c0 = __builtin_amdgcn_readlane(cm, 0), c1 = __builtin_amdgcn_readlane(cm, 1);
+  const int c2 = __builtin_amdgcn_readlane(cm, 2), c3 = __builtin_amdgcn_readlane(cm, 3);
   const int cmax = max(max(c0, c1), max(c2, c3));
   if (lane < kMaxK) {
     commit[k] = cm;
@@ -261,7 +262,7 @@ __device__ void replay_decisions(Decision& D, int K, int m0, int steps, int Q, c
       const double thr = relative ? tol * sqrt(tot[j * Q + 1 + k]) : tol;
       lq = __log2f((float)e) - __log2f((float)thr);
     }
-    const float l_first = __shfl(lq, k, 64);
+    const float l_first = lq;  // lanes k < 4 hold step m0 + 1 of accumulator k themselves
     const float l_last = __shfl(lq, 4 * max(steps - 1, 0) + k, 64);
     if (lane < kMaxK && still) {
       const float rate = (steps > 1) ? (l_first - l_last) / (float)(steps - 1) : 0.0f;
@@ -269,7 +270,8 @@ __device__ void replay_decisions(Decision& D, int K, int m0, int steps, int Q, c
       need = max(need, 1);
     }
   }
-  const int need_all = max(max(__shfl(need, 0, 64), __shfl(need, 1, 64)), max(__shfl(need, 2, 64), __shfl(need, 3, 64)));
+  const int need_all = max(max(__builtin_amdgcn_readlane(need, 0), __builtin_amdgcn_readlane(need, 1)),
+                           max(__builtin_amdgcn_readlane(need, 2), __builtin_amdgcn_readlane(need, 3)));
   if (lane == 0) {
     D.n_active = __builtin_popcountll(alive);
     if (cmax > 0) D.iters = m0 + cmax;

@@ -12,6 +12,7 @@
 #include <map>
 #include <numeric>
 #include <string>
+#include <unordered_map>
 #include <vector>
 
 #include "../../include/leja.h"
@@ -40,6 +41,7 @@ enum Slot {
 constexpr size_t kStaticLdsReserve = 40 * 1024;
 constexpr int kQ_batch = 1 + kMaxK;  // team partial sums per reduction
 constexpr int kAsyncSlots = 8;       // most action launches of one step
+constexpr int kTimingPairs = 1024;   // event pairs of the timing pool
 
 struct lj_context {
   int device = 0;
@@ -63,14 +65,17 @@ struct lj_context {
   std::map<std::pair<const void*, size_t>, int> occupancy;  // blocks per CU of (kernel, dynamic LDS)
   int tile_override_x = 0; // LJ_TILE=tx,ty: tile shape of the LDS-tiled kernel
   int tile_override_y = 0;
-  // timing
+  // timing: an event pair around each action launch; the elapsed times are
+  // read when the counters are (lj_timing_read), not after every launch
   bool timing = false;
-  hipEvent_t ev[4] = {};
+  std::vector<hipEvent_t> tev;  // 2 * kTimingPairs, created when timing is first enabled
+  int tev_next = 0;             // next free pair
+  std::vector<int> tev_pending; // pairs whose launches finished but whose times are unread
   lj_timing tm = {};
+  std::unordered_map<const void*, size_t> dyn_lds;  // dynamic LDS limit set per kernel
   // launches of a step enqueued back to back: their status heads, event pairs
   // and the bound the first one leaves for the others
   LejaStatus* h_pool = nullptr;  // pinned, kAsyncSlots entries
-  hipEvent_t ev_pool[2 * 8] = {};
   double* d_bound = nullptr;
   // batching form: schedule picked by the tuner, per batch shape
   std::map<std::string, int> batch_schedule;
@@ -385,8 +390,10 @@ void launch_action(lj_context* ctx, const OpDev& op, const double* v, int K, con
     P.lds_h = tp.lds_h;
     G = tp.ntx * tp.nty;
     dyn = tp.lds;
-    if (dyn > 64 * 1024)
+    if (dyn > 64 * 1024 && ctx->dyn_lds[fn] < dyn) {
       HIPCHK(ctx, hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn));
+      ctx->dyn_lds[fn] = dyn;
+    }
   } else {
     fn = action_stream_ptr(op.kind);
     G = grid_for(ctx, op.npts);
@@ -422,17 +429,37 @@ ActOut finish_action(lj_context* ctx, const OpDev& op, const LejaStatus& S, hipE
   r.gamma = S.gamma;
   r.vnorm = S.vnorm;
   if (ev) {
-    float ms = 0.f;
-    HIPCHK(ctx, hipEventElapsedTime(&ms, ev[0], ev[1]));
+    ctx->tev_pending.push_back((int)((ev - ctx->tev.data()) / 2));
     ctx->tm.launches += 1;
     ctx->tm.iterations += S.iters;
     ctx->tm.point_iters += (int64_t)S.iters * op.npts;
     ctx->tm.accum_point_iters += (int64_t)S.accum_iters * op.npts;
     ctx->tm.power_point_iters += (int64_t)S.power_iters * op.npts;
     ctx->tm.tiled_launches += tiled ? 1 : 0;
-    ctx->tm.kernel_ms += ms;
   }
   return r;
+}
+
+// Adds the elapsed times of the finished, unread launches to the counters and
+// frees the pool.
+void timing_flush(lj_context* ctx) {
+  for (int pair : ctx->tev_pending) {
+    float ms = 0.f;
+    HIPCHK(ctx, hipEventSynchronize(ctx->tev[2 * pair + 1]));
+    HIPCHK(ctx, hipEventElapsedTime(&ms, ctx->tev[2 * pair], ctx->tev[2 * pair + 1]));
+    ctx->tm.kernel_ms += ms;
+  }
+  ctx->tev_pending.clear();
+  ctx->tev_next = 0;
+}
+
+// The event pair for the next timed launch (nullptr when timing is off).  A
+// full pool is read out first; launches still in flight then hold pairs the
+// caller has not finished yet, so the pool is only recycled between steps.
+hipEvent_t* timing_pair(lj_context* ctx) {
+  if (!ctx->timing) return nullptr;
+  if (ctx->tev_next >= kTimingPairs) timing_flush(ctx);
+  return &ctx->tev[2 * ctx->tev_next++];
 }
 
 // K accumulators phi_{l_k}(s_k J) v (K = 0: power iteration only), one
@@ -443,10 +470,11 @@ ActOut run_action(lj_context* ctx, const OpDev& op, const double* v, int K, cons
                   double tol, hipStream_t s) {
   bool tiled = false;
   for (int attempt = 0; attempt < 2; ++attempt) {
+    hipEvent_t* ev = timing_pair(ctx);
     launch_action(ctx, op, v, K, l, s_k, lam_host, seed, start, outs, o, tol, s, BoundLink{}, ctx->h_status,
-                  sizeof(LejaStatus), ctx->timing ? ctx->ev : nullptr, &tiled, attempt == 1);
+                  sizeof(LejaStatus), ev, &tiled, attempt == 1);
     HIPCHK(ctx, hipStreamSynchronize(s));
-    const ActOut r = finish_action(ctx, op, *ctx->h_status, ctx->timing ? ctx->ev : nullptr, tiled);
+    const ActOut r = finish_action(ctx, op, *ctx->h_status, ev, tiled);
     if (!r.aborted) return r;
   }
   ctx->err = "an action launch aborted twice (grid barrier timed out)";
@@ -961,8 +989,6 @@ LJ_API int lj_create(lj_context** out, int hip_device) {
     HIPCHK(ctx, hipMalloc(&ctx->d_status, sizeof(LejaStatus)));
     HIPCHK(ctx, hipHostMalloc(&ctx->h_status, sizeof(LejaStatus), hipHostMallocDefault));
     HIPCHK(ctx, hipHostMalloc(&ctx->h_coef, kMaxK * kTable * sizeof(double), hipHostMallocDefault));
-    for (int i = 0; i < 4; ++i) HIPCHK(ctx, hipEventCreate(&ctx->ev[i]));
-    for (int i = 0; i < 2 * kAsyncSlots; ++i) HIPCHK(ctx, hipEventCreate(&ctx->ev_pool[i]));
     // fine-grained: the action kernels write their status headers here directly
     HIPCHK(ctx, hipHostMalloc(&ctx->h_pool, kAsyncSlots * sizeof(LejaStatus), hipHostMallocCoherent));
     HIPCHK(ctx, hipMalloc(&ctx->d_bound, sizeof(double)));
@@ -1008,10 +1034,8 @@ LJ_API void lj_destroy(lj_context* ctx) {
   if (ctx->d_sigma) (void)hipFree(ctx->d_sigma);
   if (ctx->h_status) (void)hipHostFree(ctx->h_status);
   if (ctx->h_coef) (void)hipHostFree(ctx->h_coef);
-  for (int i = 0; i < 4; ++i)
-    if (ctx->ev[i]) (void)hipEventDestroy(ctx->ev[i]);
-  for (int i = 0; i < 2 * kAsyncSlots; ++i)
-    if (ctx->ev_pool[i]) (void)hipEventDestroy(ctx->ev_pool[i]);
+  for (hipEvent_t e : ctx->tev)
+    if (e) (void)hipEventDestroy(e);
   if (ctx->h_pool) (void)hipHostFree(ctx->h_pool);
   if (ctx->d_bound) (void)hipFree(ctx->d_bound);
   delete ctx;
@@ -1330,8 +1354,11 @@ LJ_API int lj_step(lj_context* ctx, int scheme, const lj_operator* J, double h, 
       struct Pending {
         int K;
         bool tiled;
-        const OpDev* op;
+        hipEvent_t* ev;
       };
+      // pairs for every launch of the step up front, so a pool flush cannot
+      // fall between a launch and its finish
+      if (ctx->timing && ctx->tev_next + kAsyncSlots > kTimingPairs) timing_flush(ctx);
       std::vector<Pending> pend;
       auto act_async = [&](const double* vec, int K, const int* ls, const double* as, double* const* outs) {
         const int i = (int)pend.size();
@@ -1348,17 +1375,16 @@ LJ_API int lj_step(lj_context* ctx, int scheme, const lj_operator* J, double h, 
           link.src = ctx->d_bound;
         }
         bool tiled = false;
+        hipEvent_t* ev = timing_pair(ctx);
         launch_action(ctx, op, vec, K, ls, sk, lam_host, o.seed, o.pi_start, outs, o, tol, s, link, &ctx->h_pool[i],
-                      offsetof(LejaStatus, trace), ctx->timing ? &ctx->ev_pool[2 * i] : nullptr, &tiled, false,
-                      true);
-        pend.push_back({K, tiled, &op});
+                      offsetof(LejaStatus, trace), ev, &tiled, false, true);
+        pend.push_back({K, tiled, ev});
       };
       scheme_steps(act_async);
       HIPCHK(ctx, hipStreamSynchronize(s));
       bool all = true;
       for (size_t i = 0; i < pend.size(); ++i) {
-        const ActOut r = finish_action(ctx, op, ctx->h_pool[i], ctx->timing ? &ctx->ev_pool[2 * i] : nullptr,
-                                       pend[i].tiled);
+        const ActOut r = finish_action(ctx, op, ctx->h_pool[i], pend[i].ev, pend[i].tiled);
         if (r.aborted) all = false;
         lj_stats st;
         std::memset(&st, 0, sizeof(st));
@@ -1435,16 +1461,24 @@ LJ_API int lj_last_profile(lj_context* ctx, double* us) {
 }
 
 LJ_API int lj_timing_enable(lj_context* ctx, int enable) {
-  if (!ctx) return LJ_EINVAL;
-  ctx->timing = enable != 0;
-  return LJ_OK;
+  return guarded(ctx, [&]() {
+    if (enable && ctx->tev.empty()) {
+      ctx->tev.assign(2 * kTimingPairs, nullptr);
+      for (auto& e : ctx->tev) HIPCHK(ctx, hipEventCreate(&e));
+    }
+    ctx->timing = enable != 0;
+    return LJ_OK;
+  });
 }
 
 LJ_API int lj_timing_read(lj_context* ctx, lj_timing* out, int reset) {
-  if (!ctx || !out) return LJ_EINVAL;
-  *out = ctx->tm;
-  if (reset) std::memset(&ctx->tm, 0, sizeof(ctx->tm));
-  return LJ_OK;
+  if (!out) return LJ_EINVAL;
+  return guarded(ctx, [&]() {
+    timing_flush(ctx);
+    *out = ctx->tm;
+    if (reset) std::memset(&ctx->tm, 0, sizeof(ctx->tm));
+    return LJ_OK;
+  });
 }
 
 // ---- learned proposal ------------------------------------------------------
