@@ -41,6 +41,9 @@ def lib():
 def _stream_ptr(stream) -> C.c_void_p:
     import torch
     if stream is None:
+        raw = getattr(torch._C, "_cuda_getCurrentRawStream", None)
+        if raw is not None:  # the current stream's handle without building a Stream object
+            return C.c_void_p(raw(torch.cuda.current_device()))
         stream = torch.cuda.current_stream()
     return C.c_void_p(int(stream.cuda_stream))
 
@@ -74,6 +77,18 @@ class Operator:
         return self.nx * self.ny * self.ncomp
 
     def c_struct(self) -> lj_operator:
+        # rebuilt only when a field or the state tensor's storage changed
+        key = (self.kind, self.nx, self.ny, self.ncomp, self.dx, self.dy, tuple(self.coef),
+               None if self.state is None else (self.state.data_ptr(), self.state.numel(), self.state.dtype,
+                                                self.state.is_contiguous(), self.state.device))
+        cached = self.__dict__.get("_c_cache")
+        if cached is not None and cached[0] == key:
+            return cached[1]
+        op = self._build_c_struct()
+        self.__dict__["_c_cache"] = (key, op)
+        return op
+
+    def _build_c_struct(self) -> lj_operator:
         op = lj_operator()
         op.kind = KIND_CODES[self.kind]
         op.nx, op.ny, op.ncomp = self.nx, self.ny, self.ncomp

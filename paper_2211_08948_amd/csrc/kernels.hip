@@ -775,14 +775,19 @@ __global__ __launch_bounds__(kBlock) void lj_action_tile(ActionParams P) {
 
   // ---- (2) divided differences up to the first super-step's last term (the
   // rest while barriers are pending), and y_0 = v on the extended tile
+  // (v's loads are issued after the node values -- whose function calls
+  // would wait for them -- and are in flight while the table advances)
   __syncthreads();
   DivDiff dd;
   dd_init(dd, K, P.l, P.s, P.max_points + 1, c, gamma, sh.xi, sh.coef, sh.fmax);
+  double v_in[EPT];
+#pragma unroll
+  for (int k = 0; k < EPT; ++k) v_in[k] = ((int)threadIdx.x + k * kBlock < NE) ? P.v[gidx(k)] : 0.0;
   dd_advance(dd, K, S, sh.xi, sh.coef);
   cur = 0;
 #pragma unroll
   for (int k = 0; k < EPT; ++k)
-    if ((int)threadIdx.x + k * kBlock < NE) Y(0)[threadIdx.x + k * kBlock] = P.v[gidx(k)];
+    if ((int)threadIdx.x + k * kBlock < NE) Y(0)[threadIdx.x + k * kBlock] = v_in[k];
   __syncthreads();
   tick(kProfDivdiff);
 

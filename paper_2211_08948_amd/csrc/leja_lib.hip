@@ -1464,7 +1464,9 @@ LJ_API int lj_timing_enable(lj_context* ctx, int enable) {
   return guarded(ctx, [&]() {
     if (enable && ctx->tev.empty()) {
       ctx->tev.assign(2 * kTimingPairs, nullptr);
-      for (auto& e : ctx->tev) HIPCHK(ctx, hipEventCreate(&e));
+      // timing-only events: no system-scope fence (cache write-back and
+      // invalidation) when they are recorded between the launches of a step
+      for (auto& e : ctx->tev) HIPCHK(ctx, hipEventCreateWithFlags(&e, hipEventDisableSystemFence));
     }
     ctx->timing = enable != 0;
     return LJ_OK;
