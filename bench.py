@@ -18,6 +18,7 @@ Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
                          against the per-instance plain path)
        python bench.py --form sweep   (the other workloads: advection-diffusion 32^2,
                         Brusselator 1024^2 steps, Allen-Cahn 1024^2..4096^2)
+       python bench.py --form adaptive   (variable step sizes, EPIRK4s3 on 512^2 Allen-Cahn)
        python bench.py --copy-calibration   (plain copy kernel for counter scaling)
 """
 from __future__ import annotations
@@ -268,6 +269,49 @@ def bench_sweep(args):
     ctx.close()
 
 
+def bench_adaptive(args):
+    """Variable step sizes (Sec. 2.3) on the 512^2 Allen-Cahn workload: EPIRK4s3
+    from u0 to T = 100 explicit diffusive steps, step tolerance 1e-6, phi
+    actions to 1e-10; one JSON line (not the headline metric)."""
+    import torch
+
+    import paper_2211_08948_amd as lj
+    from workloads import allen_cahn_noise
+    prob = allen_cahn_noise(args.n, eps=1e-3, seed=2)
+    ctx = lj.Context(0)
+    op = lj.operator_from(prob, "cuda:0")
+    out = torch.empty_like(op.state)
+    T, dt0, tol = 100.0 * prob.h_cfl, CFL_MULT * prob.h_cfl, 1e-6
+    lj.lj_integrate(ctx, "EPIRK4S3", op, 5 * prob.h_cfl, dt0, tol, TOL, out)  # warm-up
+    torch.cuda.synchronize()
+    lj.lj_timing_read(ctx, reset=True)
+    lj.lj_timing_enable(ctx, True)
+    t0 = time.perf_counter()
+    rc, st, recs = lj.lj_integrate(ctx, "EPIRK4S3", op, T, dt0, tol, TOL, out)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    lj.lj_timing_enable(ctx, False)
+    tm = lj.lj_timing_read(ctx, reset=True)
+    launches = max(tm["launches"], 1)
+    avg_ms = tm["kernel_ms"] / launches
+    bpl = algorithmic_bytes(tm) / launches
+    ach = bpl / (avg_ms * 1e-3) / 1e9
+    actions = 5 * (st["accepted"] + st["rejected"])  # phi_1 x3 (vertical), phi_3, phi_4 per attempt
+    rec = {"metric": "time to solution, variable steps", "value": round(dt * 1e3, 3), "unit": "ms", "n_gpus": 1,
+           "higher_is_better": False, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": f"allen-cahn {args.n}x{args.n} periodic, eps 1e-3, u0~U[-0.1,0.1] seed 2, EPIRK4s3 "
+                                  "from t = 0 to 100x the explicit diffusive step, step tol 1e-6 (relative "
+                                  "embedded estimate), phi actions to 1e-10, first attempt 10x CFL"},
+           "accepted": st["accepted"], "rejected": st["rejected"], "products": st["products"], "rc": rc,
+           "actions_per_s": round(actions / dt, 1),
+           "dt_over_cfl": [round(r["dt"] / prob.h_cfl, 3) for r in recs],
+           "roofline": {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": round(ach / HBM_PEAK_GBS, 4), "avg_launch_us": round(avg_ms * 1e3, 2),
+                        "algorithmic_bytes_per_launch": round(bpl)}}
+    ctx.close()
+    print(json.dumps(rec), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -276,7 +320,7 @@ def main():
     ap.add_argument("--n", type=int, default=512, help="grid points per axis (default: the 512^2 workload)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true")
-    ap.add_argument("--form", choices=["plain", "batch", "sweep"], default="plain")
+    ap.add_argument("--form", choices=["plain", "batch", "sweep", "adaptive"], default="plain")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}): the multi-GPU path is not "
@@ -290,6 +334,9 @@ def main():
         return
     if args.form == "sweep":
         bench_sweep(args)
+        return
+    if args.form == "adaptive":
+        bench_adaptive(args)
         return
 
     import torch

@@ -190,6 +190,44 @@ LJ_API int lj_step(lj_context* ctx, int scheme, const lj_operator* J, double h, 
                    double* u_out, double* err, const lj_options* opt, lj_stats* stats,
                    int nstats, int* ncalls, void* stream);
 
+/* ---- variable step sizes (Sec. 2.3) ------------------------------------------ */
+
+/* Outcome of lj_integrate (host struct). */
+typedef struct {
+  int32_t accepted;  /* accepted steps */
+  int32_t rejected;  /* rejected attempts (error estimate above tol, or an expansion that failed) */
+  int64_t products;  /* Jacobian-vector products of every attempt (power iteration + Newton terms) */
+  double t;          /* time reached: T on success */
+  double dt_next;    /* the controller's step size after the last accepted step */
+} lj_integrate_stats;
+
+/* One attempted step (host struct). */
+typedef struct {
+  double t;          /* start time of the attempt */
+  double dt;         /* its step size */
+  double err;        /* e = ||u_4 - u_3||_2 / ||u_4||_2 (infinity if an expansion failed) */
+  int32_t products;  /* its Jacobian-vector products */
+  int32_t accepted;
+} lj_step_record;
+
+/* u(T) of u_t = f(u), u(0) = J->state, with the embedded schemes (LJ_EPIRK4S3
+ * or LJ_EXPRB43) and the step size control of Sec. 2.3: a step is accepted when
+ * e = ||u_4 - u_3||_2 / ||u_4||_2 <= tol; the next size is the smaller of the
+ * traditional controller's dt (tol/e)^{1/(p+1)} (p = 3, the embedded order)
+ * and the cost controller's, whose cost is the step's Jacobian-vector
+ * products per unit time (constants as printed in Sec. 2.3).  A rejected
+ * attempt is retried with 0.9 times the traditional size, one whose
+ * expansions fail with half the size; the last step ends exactly at T.  Each step linearises
+ * at the current state and runs its phi actions to leja_tol.
+ * J->state (device, not modified) holds u(0); u_out (device, n values, not
+ * aliasing the state) receives u(T).  dt0 > 0 is the first attempt's size.
+ * stats (host) may be NULL; log (host, may be NULL) receives the first
+ * log_cap attempts.  At most max_attempts attempts (LJ_ENOTCONV beyond, with
+ * u_out holding the state reached and stats->t its time). */
+LJ_API int lj_integrate(lj_context* ctx, int scheme, const lj_operator* J, double T, double dt0, double tol,
+                        double leja_tol, double* u_out, const lj_options* opt, lj_integrate_stats* stats,
+                        lj_step_record* log, int log_cap, int max_attempts, void* stream);
+
 /* ---- batching form --------------------------------------------------------- */
 
 /* Many independent instances in one launch: for each instance i < n and each

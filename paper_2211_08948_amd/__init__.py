@@ -18,7 +18,8 @@ from . import _lib
 from ._lib import (  # noqa: F401
     LJ_EHIP, LJ_EINVAL, LJ_ENOMEM, LJ_ENOTCONV, LJ_EPIRK4S3, LJ_EXPRB2, LJ_EXPRB43, LJ_EXPRB43_U3,
     LJ_MAX_K, LJ_MAX_L, LJ_OK, LJ_OP_ADVDIFF2D, LJ_OP_ALLENCAHN2D, LJ_OP_BRUSSELATOR2D, LJ_OP_BURGERS2D,
-    LJ_OP_DIAG, LejaLibraryError, lj_operator, lj_options, lj_stats, lj_timing,
+    LJ_OP_DIAG, LejaLibraryError, lj_integrate_stats, lj_operator, lj_options, lj_stats, lj_step_record,
+    lj_timing,
 )
 
 KIND_CODES = {
@@ -224,6 +225,21 @@ def lj_step(ctx: Context, scheme: str, J: Operator, h: float, tol: float, u_out,
                           _stream_ptr(stream))
     ctx._check(rc)
     return rc, [stats[i].as_dict() for i in range(ncalls.value)]
+
+
+def lj_integrate(ctx: Context, scheme: str, J: Operator, T: float, dt0: float, tol: float, leja_tol: float, u_out,
+                 opt: lj_options | None = None, log_cap: int = 1000, max_attempts: int = 100000, stream=None):
+    """u(T) from u(0) = J.state with variable steps (Sec. 2.3).  Returns
+    (rc, stats dict, list of attempted steps)."""
+    st = lj_integrate_stats()
+    recs = (lj_step_record * max(log_cap, 1))()
+    rc = ctx._lib.lj_integrate(ctx.handle, SCHEMES[scheme], C.byref(J.c_struct()), float(T), float(dt0), float(tol),
+                               float(leja_tol), _tensor_ptr(u_out, J.n, "u_out"),
+                               C.byref(opt) if opt is not None else None, C.byref(st), recs, int(log_cap),
+                               int(max_attempts), _stream_ptr(stream))
+    ctx._check(rc)
+    n = min(st.accepted + st.rejected, log_cap)
+    return rc, st.as_dict(), [recs[i].as_dict() for i in range(n)]
 
 
 def lj_last_trace(ctx: Context, rows: int = 100):

@@ -71,6 +71,23 @@ class lj_timing(C.Structure):
     ]
 
 
+class lj_integrate_stats(C.Structure):
+    _fields_ = [("accepted", C.c_int32), ("rejected", C.c_int32), ("products", C.c_int64), ("t", C.c_double),
+                ("dt_next", C.c_double)]
+
+    def as_dict(self) -> dict:
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+class lj_step_record(C.Structure):
+    _fields_ = [("t", C.c_double), ("dt", C.c_double), ("err", C.c_double), ("products", C.c_int32),
+                ("accepted", C.c_int32)]
+
+    def as_dict(self) -> dict:
+        return {"t": self.t, "dt": self.dt, "err": self.err, "products": self.products,
+                "accepted": bool(self.accepted)}
+
+
 class lj_batch_info_t(C.Structure):
     _fields_ = [
         ("schedule", C.c_int32), ("block_size", C.c_int32), ("blocks", C.c_int32),
@@ -99,6 +116,9 @@ _PROTOS = {
                                   C.POINTER(lj_options), C.POINTER(lj_stats), _P]),
     "lj_step": (C.c_int, [_P, C.c_int, C.POINTER(lj_operator), C.c_double, C.c_double, _P, _P,
                           C.POINTER(lj_options), C.POINTER(lj_stats), C.c_int, C.POINTER(C.c_int), _P]),
+    "lj_integrate": (C.c_int, [_P, C.c_int, C.POINTER(lj_operator), C.c_double, C.c_double, C.c_double,
+                               C.c_double, _P, C.POINTER(lj_options), C.POINTER(lj_integrate_stats),
+                               C.POINTER(lj_step_record), C.c_int, C.c_int, _P]),
     "lj_last_trace": (C.c_int, [_P, C.POINTER(C.c_double), C.c_int]),
     "lj_last_profile": (C.c_int, [_P, C.POINTER(C.c_double)]),
     "lj_timing_enable": (C.c_int, [_P, C.c_int]),

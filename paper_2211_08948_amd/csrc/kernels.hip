@@ -22,6 +22,8 @@
 // bound and has no dense contraction, so no MFMA is used.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "device.hpp"
 #include "kernels.hpp"
 
@@ -1238,6 +1240,50 @@ __global__ __launch_bounds__(256) void lj_finish_kernel(FinishArgs F) {
   }
 }
 
+// Sums of squares of two vectors (the step controller's error and solution
+// norms), in a fixed order: block g sums a contiguous chunk (thread t every
+// 256th value from t, then the waves' DPP sums in wave order) into
+// part[2 g], part[2 g + 1]; one block then adds the partials in block order.
+__global__ __launch_bounds__(256) void lj_sumsq2_partial(const double* __restrict__ a, const double* __restrict__ b,
+                                                         long n, double* __restrict__ part) {
+  __shared__ double red[2 * 4];
+  const long chunk = (n + gridDim.x - 1) / gridDim.x;
+  const long i0 = blockIdx.x * chunk, i1 = min(n, i0 + chunk);
+  double sa = 0.0, sb = 0.0;
+  for (long i = i0 + threadIdx.x; i < i1; i += blockDim.x) {
+    sa += a[i] * a[i];
+    sb += b[i] * b[i];
+  }
+  sa = wave_sum(sa);
+  sb = wave_sum(sb);
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) {
+    red[2 * w] = sa;
+    red[2 * w + 1] = sb;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double ta = 0.0, tb = 0.0;
+    for (int q = 0; q < (int)(blockDim.x >> 6); ++q) {
+      ta += red[2 * q];
+      tb += red[2 * q + 1];
+    }
+    part[2 * blockIdx.x] = ta;
+    part[2 * blockIdx.x + 1] = tb;
+  }
+}
+
+__global__ void lj_sumsq2_final(const double* __restrict__ part, int G, double* __restrict__ out) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  double ta = 0.0, tb = 0.0;
+  for (int g = 0; g < G; ++g) {
+    ta += part[2 * g];
+    tb += part[2 * g + 1];
+  }
+  out[0] = ta;
+  out[1] = tb;
+}
+
 // ---------------------------------------------------------------------------
 // Launch wrappers (host side).
 // ---------------------------------------------------------------------------
@@ -1356,6 +1402,13 @@ hipError_t launch_stage(const StageArgs& A, hipStream_t s) {
     case OP_BURGERS: stage_t<OP_BURGERS, 1>(A, s); break;
     default: return hipErrorInvalidValue;
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_sumsq2(const double* a, const double* b, long n, double* part, double* out, hipStream_t s) {
+  const int G = (int)std::min<long>(kSumsqBlocks, std::max<long>(1, (n + 255) / 256));
+  hipLaunchKernelGGL(lj_sumsq2_partial, dim3(G), dim3(256), 0, s, a, b, n, part);
+  hipLaunchKernelGGL(lj_sumsq2_final, dim3(1), dim3(64), 0, s, part, G, out);
   return hipGetLastError();
 }
 

@@ -60,5 +60,8 @@ hipError_t launch_lincomb(const LinComb& L, hipStream_t s);
 hipError_t launch_rhs_scaled(const OpDev& op, double h, double* f, double* v, hipStream_t s);  // f(state), h f
 hipError_t launch_stage(const StageArgs& A, hipStream_t s);
 hipError_t launch_finish(const FinishArgs& F, hipStream_t s);
+// out[0] = sum a^2, out[1] = sum b^2 over n values; part holds 2 * kSumsqBlocks doubles
+constexpr int kSumsqBlocks = 256;
+hipError_t launch_sumsq2(const double* a, const double* b, long n, double* part, double* out, hipStream_t s);
 
 }  // namespace lj

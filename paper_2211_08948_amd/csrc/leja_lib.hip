@@ -34,6 +34,7 @@ enum Slot {
   W_FU, W_V, W_A, W_B, W_C,        // stage driver: f(u), h f(u), vertical results
   W_RA, W_T1,                      // R(a) kept for a later stage, the phi_1 input of EXPRB43
   W_T3, W_D3, W_T4, W_D4,          // phi_3 / phi_4 inputs and results
+  W_IU0, W_IU1, W_IERR,            // variable-step integration: state ping-pong, error estimate
   W_NSLOTS
 };
 
@@ -77,6 +78,8 @@ struct lj_context {
   // and the bound the first one leaves for the others
   LejaStatus* h_pool = nullptr;  // pinned, kAsyncSlots entries
   double* d_bound = nullptr;
+  double* d_sumsq = nullptr;   // 2 * kSumsqBlocks partials + 2 totals
+  double* h_sumsq = nullptr;   // pinned, 2 totals
   // batching form: schedule picked by the tuner, per batch shape
   std::map<std::string, int> batch_schedule;
   // learned proposal
@@ -992,6 +995,8 @@ LJ_API int lj_create(lj_context** out, int hip_device) {
     // fine-grained: the action kernels write their status headers here directly
     HIPCHK(ctx, hipHostMalloc(&ctx->h_pool, kAsyncSlots * sizeof(LejaStatus), hipHostMallocCoherent));
     HIPCHK(ctx, hipMalloc(&ctx->d_bound, sizeof(double)));
+    HIPCHK(ctx, hipMalloc(&ctx->d_sumsq, (2 * kSumsqBlocks + 2) * sizeof(double)));
+    HIPCHK(ctx, hipHostMalloc(&ctx->h_sumsq, 2 * sizeof(double), hipHostMallocDefault));
     if (const char* g = std::getenv("LJ_GRID")) ctx->grid_override = std::atoi(g);
     if (const char* g = std::getenv("LJ_NO_TILE")) ctx->force_stream = std::atoi(g);
     if (const char* g = std::getenv("LJ_COOP")) ctx->force_coop = std::atoi(g);
@@ -1038,6 +1043,8 @@ LJ_API void lj_destroy(lj_context* ctx) {
     if (e) (void)hipEventDestroy(e);
   if (ctx->h_pool) (void)hipHostFree(ctx->h_pool);
   if (ctx->d_bound) (void)hipFree(ctx->d_bound);
+  if (ctx->d_sumsq) (void)hipFree(ctx->d_sumsq);
+  if (ctx->h_sumsq) (void)hipHostFree(ctx->h_sumsq);
   delete ctx;
 }
 
@@ -1159,6 +1166,272 @@ LJ_API int lj_phi_action(lj_context* ctx, const lj_operator* J, const double* v,
   return lj_phi_vertical(ctx, J, v, 1, &l, &a, h, tol, ws, opt, stats, stream);
 }
 
+// One step of `scheme` from u = op.state (arguments validated by the caller):
+// u_out, err (nullable) and the stats of the scheme's Leja calls.
+int step_impl(lj_context* ctx, int scheme, const OpDev& op, Opts o, double h, double tol, double* u_out, double* err,
+              lj_stats* stats, hipStream_t s) {
+  const size_t n = nvals(op);
+  const double* u = op.state;
+  // The scheme's stages; `act` runs one (vertical) Leja call.  Between the
+  // Leja calls: f(u) and v = h f(u) in one pass, the remainders and the
+  // vectors the next calls act on in one pass, the result and error
+  // estimate in one pass.
+  auto scheme_steps = [&](auto&& act) {
+    double* fu = slot(ctx, W_FU, n);
+    double* v = slot(ctx, W_V, n);
+    HIPCHK(ctx, launch_rhs_scaled(op, h, fu, v, s));
+    auto finish = [&](const double* X1, const double* X2, const double* X3) {
+      FinishArgs F;
+      F.n = (long)n;
+      F.u = u;
+      F.X1 = X1;
+      F.X2 = X2;
+      F.X3 = X3;
+      F.u_out = u_out;
+      F.err = err;
+      HIPCHK(ctx, launch_finish(F, s));
+    };
+    auto stage_args = [&]() {
+      StageArgs A;
+      std::memset(&A, 0, sizeof(A));
+      A.op = op;
+      A.fu = fu;
+      return A;
+    };
+    if (scheme == LJ_EXPRB2) {
+      double* A = slot(ctx, W_A, n);
+      const int ls[1] = {1};
+      const double as[1] = {1.0};
+      act(v, 1, ls, as, &A);
+      finish(A, nullptr, nullptr);
+    } else if (scheme == LJ_EXPRB43 || scheme == LJ_EXPRB43_U3) {
+      double* A = slot(ctx, W_A, n);
+      double* B = slot(ctx, W_B, n);
+      double* C = slot(ctx, W_C, n);
+      double* Ra = slot(ctx, W_RA, n);
+      double* T1 = slot(ctx, W_T1, n);
+      double* T3 = slot(ctx, W_T3, n);
+      double* T4 = slot(ctx, W_T4, n);
+      double* D3 = slot(ctx, W_D3, n);
+      {
+        const int ls[2] = {1, 1};
+        const double as[2] = {0.5, 1.0};
+        double* outs[2] = {A, B};
+        act(v, 2, ls, as, outs);
+      }
+      {  // R_a at u + A/2; T1 = h R_a (and R_a kept)
+        StageArgs S = stage_args();
+        S.nrem = 1;
+        S.nterm[0] = 1;
+        S.a[0][0] = 0.5;
+        S.X[0][0] = A;
+        S.nout = 2;
+        S.nsrc[0] = 1;
+        S.src[0][0] = 0;
+        S.c[0][0] = h;
+        S.out[0] = T1;
+        S.nsrc[1] = 1;
+        S.src[1][0] = 0;
+        S.c[1][0] = 1.0;
+        S.out[1] = Ra;
+        HIPCHK(ctx, launch_stage(S, s));
+      }
+      {
+        const int ls[1] = {1};
+        const double as[1] = {1.0};
+        act(T1, 1, ls, as, &C);
+      }
+      {  // R_b at u + B + C; T3 = 16 h R_a - 2 h R_b (and T4 = -48 h R_a + 12 h R_b)
+        StageArgs S = stage_args();
+        S.nrem = 1;
+        S.nterm[0] = 2;
+        S.a[0][0] = 1.0;
+        S.X[0][0] = B;
+        S.a[0][1] = 1.0;
+        S.X[0][1] = C;
+        S.P = Ra;
+        S.nout = (scheme == LJ_EXPRB43) ? 2 : 1;
+        S.nsrc[0] = 2;
+        S.src[0][0] = 2;
+        S.c[0][0] = 16.0 * h;
+        S.src[0][1] = 0;
+        S.c[0][1] = -2.0 * h;
+        S.out[0] = T3;
+        S.nsrc[1] = 2;
+        S.src[1][0] = 2;
+        S.c[1][0] = -48.0 * h;
+        S.src[1][1] = 0;
+        S.c[1][1] = 12.0 * h;
+        S.out[1] = T4;
+        HIPCHK(ctx, launch_stage(S, s));
+      }
+      {
+        const int ls[1] = {3};
+        const double as[1] = {1.0};
+        act(T3, 1, ls, as, &D3);
+      }
+      if (scheme == LJ_EXPRB43) {
+        double* D4 = slot(ctx, W_D4, n);
+        const int ls[1] = {4};
+        const double as[1] = {1.0};
+        act(T4, 1, ls, as, &D4);
+        finish(B, D3, D4);
+      } else {
+        finish(B, D3, nullptr);
+      }
+    } else {  // EPIRK4s3
+      double* A = slot(ctx, W_A, n);
+      double* B = slot(ctx, W_B, n);
+      double* C = slot(ctx, W_C, n);
+      double* T3 = slot(ctx, W_T3, n);
+      double* D3 = slot(ctx, W_D3, n);
+      double* T4 = slot(ctx, W_T4, n);
+      double* D4 = slot(ctx, W_D4, n);
+      {
+        const int ls[3] = {1, 1, 1};
+        const double as[3] = {1.0 / 8.0, 1.0 / 9.0, 1.0};
+        double* outs[3] = {A, B, C};
+        act(v, 3, ls, as, outs);
+      }
+      {  // R_a at u + A/8, R_b at u + B/9;
+         // h (1892 Ra + 1458 (Rb - 2 Ra)) and h (-42336 Ra - 34992 (Rb - 2 Ra))
+        StageArgs S = stage_args();
+        S.nrem = 2;
+        S.nterm[0] = 1;
+        S.a[0][0] = 1.0 / 8.0;
+        S.X[0][0] = A;
+        S.nterm[1] = 1;
+        S.a[1][0] = 1.0 / 9.0;
+        S.X[1][0] = B;
+        S.nout = 2;
+        S.nsrc[0] = 2;
+        S.src[0][0] = 0;
+        S.c[0][0] = h * (1892.0 - 2.0 * 1458.0);
+        S.src[0][1] = 1;
+        S.c[0][1] = h * 1458.0;
+        S.out[0] = T3;
+        S.nsrc[1] = 2;
+        S.src[1][0] = 0;
+        S.c[1][0] = h * (-42336.0 + 2.0 * 34992.0);
+        S.src[1][1] = 1;
+        S.c[1][1] = h * -34992.0;
+        S.out[1] = T4;
+        HIPCHK(ctx, launch_stage(S, s));
+      }
+      {
+        const int ls[1] = {3};
+        const double as[1] = {1.0};
+        act(T3, 1, ls, as, &D3);
+      }
+      {
+        const int ls[1] = {4};
+        const double as[1] = {1.0};
+        act(T4, 1, ls, as, &D4);
+      }
+      finish(C, D3, D4);
+    }
+  };
+  std::vector<lj_stats> log;
+  bool ok = true;
+  int pit = 0;
+  // ---- first try: every launch of the step enqueued back to back.  The
+  // first action runs the power iteration (unless a bound is given) and
+  // leaves the bound on the device for the others; statuses are read once
+  // at the end.  If some expansion was rejected, the step is redone below
+  // synchronously, with substeps, on the bound found.
+  const bool try_async = o.substeps <= 1 && !o.use_proposal;
+  double lam_found = o.bound;
+  if (try_async) {
+    struct Pending {
+      int K;
+      bool tiled;
+      hipEvent_t* ev;
+    };
+    // pairs for every launch of the step up front, so a pool flush cannot
+    // fall between a launch and its finish
+    if (ctx->timing && ctx->tev_next + kAsyncSlots > kTimingPairs) timing_flush(ctx);
+    std::vector<Pending> pend;
+    auto act_async = [&](const double* vec, int K, const int* ls, const double* as, double* const* outs) {
+      const int i = (int)pend.size();
+      if (i >= kAsyncSlots) invalid(ctx, "internal: too many launches in one step");
+      double sk[kMaxK];
+      for (int k = 0; k < K; ++k) sk[k] = as[k] * h;
+      BoundLink link;
+      double lam_host = 0.0;
+      if (o.bound > 0.0) {
+        lam_host = o.bound;
+      } else if (i == 0) {
+        link.dst = ctx->d_bound;
+      } else {
+        link.src = ctx->d_bound;
+      }
+      bool tiled = false;
+      hipEvent_t* ev = timing_pair(ctx);
+      launch_action(ctx, op, vec, K, ls, sk, lam_host, o.seed, o.pi_start, outs, o, tol, s, link, &ctx->h_pool[i],
+                    offsetof(LejaStatus, trace), ev, &tiled, false, true);
+      pend.push_back({K, tiled, ev});
+    };
+    scheme_steps(act_async);
+    HIPCHK(ctx, hipStreamSynchronize(s));
+    bool all = true;
+    for (size_t i = 0; i < pend.size(); ++i) {
+      const ActOut r = finish_action(ctx, op, ctx->h_pool[i], pend[i].ev, pend[i].tiled);
+      if (r.aborted) all = false;
+      lj_stats st;
+      std::memset(&st, 0, sizeof(st));
+      for (int k = 0; k < LJ_MAX_K; ++k) {
+        st.m_star[k] = -1;
+        st.substeps[k] = 1;
+      }
+      st.iters_total = r.iters;
+      st.power_iters = r.power_iters;
+      st.bound = r.lam;
+      st.c = r.c;
+      st.gamma = r.gamma;
+      st.converged = 1;
+      for (int k = 0; k < pend[i].K; ++k) {
+        if (r.state[k] == ACC_CONVERGED) {
+          st.m_star[k] = r.m_star[k];
+          st.err_est[k] = r.err[k];
+        } else {
+          st.converged = 0;
+          st.rejections = 1;
+          all = false;
+        }
+      }
+      if (i == 0) {
+        lam_found = r.lam;
+        pit = r.power_iters;
+      }
+      log.push_back(st);
+    }
+    if (all) {
+      if (stats)
+        for (size_t i = 0; i < log.size(); ++i) stats[i] = log[i];
+      return LJ_OK;
+    }
+    log.clear();
+    o.bound = lam_found;
+  }
+  // ---- the step, synchronously: one spectral bound for the whole step
+  if (!(o.bound > 0.0)) {
+    o.bound = run_bound(ctx, op, o, o.power_iters, o.seed, o.pi_start, s);
+    pit = o.power_iters;
+  }
+  auto act = [&](const double* vec, int K, const int* ls, const double* as, double* const* outs) {
+    lj_stats st;
+    const int rc = vertical_impl(ctx, op, vec, K, ls, as, h, tol, outs, o, &st, s);
+    if (rc != LJ_OK) ok = false;
+    log.push_back(st);
+  };
+  scheme_steps(act);
+  HIPCHK(ctx, hipStreamSynchronize(s));
+  if (!log.empty()) log[0].power_iters = pit;
+  if (stats)
+    for (size_t i = 0; i < log.size(); ++i) stats[i] = log[i];
+  return ok ? LJ_OK : LJ_ENOTCONV;
+}
+
 LJ_API int lj_step(lj_context* ctx, int scheme, const lj_operator* J, double h, double tol, double* u_out,
                    double* err, const lj_options* opt, lj_stats* stats, int nstats, int* ncalls, void* stream) {
   return guarded(ctx, [&]() {
@@ -1177,268 +1450,119 @@ LJ_API int lj_step(lj_context* ctx, int scheme, const lj_operator* J, double h, 
     const int want = (scheme == LJ_EXPRB2) ? 1 : (scheme == LJ_EXPRB43) ? 4 : 3;
     if (ncalls) *ncalls = want;
     if (stats && nstats < want) invalid(ctx, "nstats is smaller than the number of Leja calls of the scheme");
-    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-    const size_t n = nvals(op);
-    const double* u = op.state;
-    // the scheme's stages; `act` runs one (vertical) Leja call
-    // The scheme's stages; `act` runs one (vertical) Leja call.  Between the
-    // Leja calls: f(u) and v = h f(u) in one pass, the remainders and the
-    // vectors the next calls act on in one pass, the result and error
-    // estimate in one pass.
-    auto scheme_steps = [&](auto&& act) {
-      double* fu = slot(ctx, W_FU, n);
-      double* v = slot(ctx, W_V, n);
-      HIPCHK(ctx, launch_rhs_scaled(op, h, fu, v, s));
-      auto finish = [&](const double* X1, const double* X2, const double* X3) {
-        FinishArgs F;
-        F.n = (long)n;
-        F.u = u;
-        F.X1 = X1;
-        F.X2 = X2;
-        F.X3 = X3;
-        F.u_out = u_out;
-        F.err = err;
-        HIPCHK(ctx, launch_finish(F, s));
-      };
-      auto stage_args = [&]() {
-        StageArgs A;
-        std::memset(&A, 0, sizeof(A));
-        A.op = op;
-        A.fu = fu;
-        return A;
-      };
-      if (scheme == LJ_EXPRB2) {
-        double* A = slot(ctx, W_A, n);
-        const int ls[1] = {1};
-        const double as[1] = {1.0};
-        act(v, 1, ls, as, &A);
-        finish(A, nullptr, nullptr);
-      } else if (scheme == LJ_EXPRB43 || scheme == LJ_EXPRB43_U3) {
-        double* A = slot(ctx, W_A, n);
-        double* B = slot(ctx, W_B, n);
-        double* C = slot(ctx, W_C, n);
-        double* Ra = slot(ctx, W_RA, n);
-        double* T1 = slot(ctx, W_T1, n);
-        double* T3 = slot(ctx, W_T3, n);
-        double* T4 = slot(ctx, W_T4, n);
-        double* D3 = slot(ctx, W_D3, n);
-        {
-          const int ls[2] = {1, 1};
-          const double as[2] = {0.5, 1.0};
-          double* outs[2] = {A, B};
-          act(v, 2, ls, as, outs);
-        }
-        {  // R_a at u + A/2; T1 = h R_a (and R_a kept)
-          StageArgs S = stage_args();
-          S.nrem = 1;
-          S.nterm[0] = 1;
-          S.a[0][0] = 0.5;
-          S.X[0][0] = A;
-          S.nout = 2;
-          S.nsrc[0] = 1;
-          S.src[0][0] = 0;
-          S.c[0][0] = h;
-          S.out[0] = T1;
-          S.nsrc[1] = 1;
-          S.src[1][0] = 0;
-          S.c[1][0] = 1.0;
-          S.out[1] = Ra;
-          HIPCHK(ctx, launch_stage(S, s));
-        }
-        {
-          const int ls[1] = {1};
-          const double as[1] = {1.0};
-          act(T1, 1, ls, as, &C);
-        }
-        {  // R_b at u + B + C; T3 = 16 h R_a - 2 h R_b (and T4 = -48 h R_a + 12 h R_b)
-          StageArgs S = stage_args();
-          S.nrem = 1;
-          S.nterm[0] = 2;
-          S.a[0][0] = 1.0;
-          S.X[0][0] = B;
-          S.a[0][1] = 1.0;
-          S.X[0][1] = C;
-          S.P = Ra;
-          S.nout = (scheme == LJ_EXPRB43) ? 2 : 1;
-          S.nsrc[0] = 2;
-          S.src[0][0] = 2;
-          S.c[0][0] = 16.0 * h;
-          S.src[0][1] = 0;
-          S.c[0][1] = -2.0 * h;
-          S.out[0] = T3;
-          S.nsrc[1] = 2;
-          S.src[1][0] = 2;
-          S.c[1][0] = -48.0 * h;
-          S.src[1][1] = 0;
-          S.c[1][1] = 12.0 * h;
-          S.out[1] = T4;
-          HIPCHK(ctx, launch_stage(S, s));
-        }
-        {
-          const int ls[1] = {3};
-          const double as[1] = {1.0};
-          act(T3, 1, ls, as, &D3);
-        }
-        if (scheme == LJ_EXPRB43) {
-          double* D4 = slot(ctx, W_D4, n);
-          const int ls[1] = {4};
-          const double as[1] = {1.0};
-          act(T4, 1, ls, as, &D4);
-          finish(B, D3, D4);
-        } else {
-          finish(B, D3, nullptr);
-        }
-      } else {  // EPIRK4s3
-        double* A = slot(ctx, W_A, n);
-        double* B = slot(ctx, W_B, n);
-        double* C = slot(ctx, W_C, n);
-        double* T3 = slot(ctx, W_T3, n);
-        double* D3 = slot(ctx, W_D3, n);
-        double* T4 = slot(ctx, W_T4, n);
-        double* D4 = slot(ctx, W_D4, n);
-        {
-          const int ls[3] = {1, 1, 1};
-          const double as[3] = {1.0 / 8.0, 1.0 / 9.0, 1.0};
-          double* outs[3] = {A, B, C};
-          act(v, 3, ls, as, outs);
-        }
-        {  // R_a at u + A/8, R_b at u + B/9;
-           // h (1892 Ra + 1458 (Rb - 2 Ra)) and h (-42336 Ra - 34992 (Rb - 2 Ra))
-          StageArgs S = stage_args();
-          S.nrem = 2;
-          S.nterm[0] = 1;
-          S.a[0][0] = 1.0 / 8.0;
-          S.X[0][0] = A;
-          S.nterm[1] = 1;
-          S.a[1][0] = 1.0 / 9.0;
-          S.X[1][0] = B;
-          S.nout = 2;
-          S.nsrc[0] = 2;
-          S.src[0][0] = 0;
-          S.c[0][0] = h * (1892.0 - 2.0 * 1458.0);
-          S.src[0][1] = 1;
-          S.c[0][1] = h * 1458.0;
-          S.out[0] = T3;
-          S.nsrc[1] = 2;
-          S.src[1][0] = 0;
-          S.c[1][0] = h * (-42336.0 + 2.0 * 34992.0);
-          S.src[1][1] = 1;
-          S.c[1][1] = h * -34992.0;
-          S.out[1] = T4;
-          HIPCHK(ctx, launch_stage(S, s));
-        }
-        {
-          const int ls[1] = {3};
-          const double as[1] = {1.0};
-          act(T3, 1, ls, as, &D3);
-        }
-        {
-          const int ls[1] = {4};
-          const double as[1] = {1.0};
-          act(T4, 1, ls, as, &D4);
-        }
-        finish(C, D3, D4);
+    return step_impl(ctx, scheme, op, o, h, tol, u_out, err, stats, reinterpret_cast<hipStream_t>(stream));
+  });
+}
+
+// ---- variable step sizes (Sec. 2.3) -------------------------------------------
+namespace {
+// cost controller constants as printed (Sec. 2.3)
+constexpr double kCostAlpha = 0.65241444, kCostBeta = 0.26862269, kCostLambda = 1.37412002,
+                 kCostDelta = 0.64446017;
+// a rejected attempt is retried at this fraction of the traditional size: an
+// error estimate that falls more slowly than dt^{p+1} (stiff order
+// reduction) would otherwise creep down over many rejections
+constexpr double kRetrySafety = 0.9;
+
+double traditional_factor(double e, double tol, int p) {
+  if (e == 0.0) return INFINITY;
+  return std::pow(tol / e, 1.0 / (p + 1));
+}
+
+// g from the step sizes and costs per unit time of two consecutive accepted steps
+double cost_factor(double dt, double dt_prev, double c, double c_prev) {
+  const double D = (dt == dt_prev) ? 0.0 : (std::log(c) - std::log(c_prev)) / (std::log(dt) - std::log(dt_prev));
+  const double sf = std::exp(-kCostAlpha * std::tanh(kCostBeta * D));
+  if (sf >= 1.0 && sf < kCostLambda) return kCostLambda;
+  if (sf >= kCostDelta && sf < 1.0) return kCostDelta;
+  return sf;
+}
+}  // namespace
+
+LJ_API int lj_integrate(lj_context* ctx, int scheme, const lj_operator* J, double T, double dt0, double tol,
+                        double leja_tol, double* u_out, const lj_options* opt, lj_integrate_stats* stats,
+                        lj_step_record* log, int log_cap, int max_attempts, void* stream) {
+  return guarded(ctx, [&]() {
+    const OpDev op0 = make_op(ctx, J);
+    const Opts o = resolve(ctx, opt);
+    if (scheme != LJ_EPIRK4S3 && scheme != LJ_EXPRB43) invalid(ctx, "lj_integrate needs an embedded scheme");
+    if (op0.state == nullptr) invalid(ctx, "lj_integrate needs u(0) in J->state");
+    if (!(T >= 0.0) || !std::isfinite(T)) invalid(ctx, "T must be finite and >= 0");
+    if (!(dt0 > 0.0) || !std::isfinite(dt0)) invalid(ctx, "dt0 must be finite and > 0");
+    if (!(tol > 0.0) || !std::isfinite(tol)) invalid(ctx, "tol must be finite and > 0");
+    if (!(leja_tol > 0.0) || !std::isfinite(leja_tol)) invalid(ctx, "leja_tol must be finite and > 0");
+    if (log_cap < 0 || (log_cap > 0 && !log)) invalid(ctx, "log is NULL but log_cap > 0");
+    if (max_attempts < 1) invalid(ctx, "max_attempts must be >= 1");
+    check_vec(ctx, op0, u_out, "u_out");
+    if (u_out == op0.state) invalid(ctx, "u_out must not alias the state");
+    const hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    const size_t n = nvals(op0);
+    const int p = 3;  // order of the embedded (lower-order) solution of both schemes
+    double* ub[2] = {slot(ctx, W_IU0, n), slot(ctx, W_IU1, n)};
+    double* errv = slot(ctx, W_IERR, n);
+    HIPCHK(ctx, hipMemcpyAsync(ub[0], op0.state, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+    lj_integrate_stats st{};
+    int cur = 0, attempts = 0;
+    double t = 0.0, dt = dt0;
+    bool have_prev = false;
+    double prev_dt = 0.0, prev_rate = 0.0;
+    int rc = LJ_OK;
+    while (t < T) {
+      if (attempts >= max_attempts) {
+        rc = LJ_ENOTCONV;
+        break;
       }
-    };
-    std::vector<lj_stats> log;
-    bool ok = true;
-    int pit = 0;
-    // ---- first try: every launch of the step enqueued back to back.  The
-    // first action runs the power iteration (unless a bound is given) and
-    // leaves the bound on the device for the others; statuses are read once
-    // at the end.  If some expansion was rejected, the step is redone below
-    // synchronously, with substeps, on the bound found.
-    const bool try_async = o.substeps <= 1 && !o.use_proposal;
-    double lam_found = o.bound;
-    if (try_async) {
-      struct Pending {
-        int K;
-        bool tiled;
-        hipEvent_t* ev;
-      };
-      // pairs for every launch of the step up front, so a pool flush cannot
-      // fall between a launch and its finish
-      if (ctx->timing && ctx->tev_next + kAsyncSlots > kTimingPairs) timing_flush(ctx);
-      std::vector<Pending> pend;
-      auto act_async = [&](const double* vec, int K, const int* ls, const double* as, double* const* outs) {
-        const int i = (int)pend.size();
-        if (i >= kAsyncSlots) invalid(ctx, "internal: too many launches in one step");
-        double sk[kMaxK];
-        for (int k = 0; k < K; ++k) sk[k] = as[k] * h;
-        BoundLink link;
-        double lam_host = 0.0;
-        if (o.bound > 0.0) {
-          lam_host = o.bound;
-        } else if (i == 0) {
-          link.dst = ctx->d_bound;
-        } else {
-          link.src = ctx->d_bound;
-        }
-        bool tiled = false;
-        hipEvent_t* ev = timing_pair(ctx);
-        launch_action(ctx, op, vec, K, ls, sk, lam_host, o.seed, o.pi_start, outs, o, tol, s, link, &ctx->h_pool[i],
-                      offsetof(LejaStatus, trace), ev, &tiled, false, true);
-        pend.push_back({K, tiled, ev});
-      };
-      scheme_steps(act_async);
-      HIPCHK(ctx, hipStreamSynchronize(s));
-      bool all = true;
-      for (size_t i = 0; i < pend.size(); ++i) {
-        const ActOut r = finish_action(ctx, op, ctx->h_pool[i], pend[i].ev, pend[i].tiled);
-        if (r.aborted) all = false;
-        lj_stats st;
-        std::memset(&st, 0, sizeof(st));
-        for (int k = 0; k < LJ_MAX_K; ++k) {
-          st.m_star[k] = -1;
-          st.substeps[k] = 1;
-        }
-        st.iters_total = r.iters;
-        st.power_iters = r.power_iters;
-        st.bound = r.lam;
-        st.c = r.c;
-        st.gamma = r.gamma;
-        st.converged = 1;
-        for (int k = 0; k < pend[i].K; ++k) {
-          if (r.state[k] == ACC_CONVERGED) {
-            st.m_star[k] = r.m_star[k];
-            st.err_est[k] = r.err[k];
-          } else {
-            st.converged = 0;
-            st.rejections = 1;
-            all = false;
-          }
-        }
-        if (i == 0) {
-          lam_found = r.lam;
-          pit = r.power_iters;
-        }
-        log.push_back(st);
+      const bool last = dt >= T - t;
+      const double h = last ? T - t : dt;
+      OpDev op = op0;
+      op.state = ub[cur];
+      lj_stats calls[LJ_MAX_K];
+      const int src = step_impl(ctx, scheme, op, o, h, leja_tol, ub[cur ^ 1], errv, calls, s);
+      const int ncalls = (scheme == LJ_EXPRB43) ? 4 : 3;
+      int cost = 0;
+      bool ok = src == LJ_OK;
+      for (int i = 0; i < ncalls; ++i) {
+        cost += calls[i].iters_total + calls[i].power_iters;
+        ok = ok && calls[i].converged;
       }
-      if (all) {
-        if (stats)
-          for (size_t i = 0; i < log.size(); ++i) stats[i] = log[i];
-        return LJ_OK;
+      st.products += cost;
+      double e = INFINITY;
+      if (ok) {
+        HIPCHK(ctx, launch_sumsq2(errv, ub[cur ^ 1], (long)n, ctx->d_sumsq, ctx->d_sumsq + 2 * kSumsqBlocks, s));
+        HIPCHK(ctx, hipMemcpyAsync(ctx->h_sumsq, ctx->d_sumsq + 2 * kSumsqBlocks, 2 * sizeof(double),
+                                   hipMemcpyDeviceToHost, s));
+        HIPCHK(ctx, hipStreamSynchronize(s));
+        const double ne = std::sqrt(ctx->h_sumsq[0]), nu = std::sqrt(ctx->h_sumsq[1]);
+        e = nu > 0.0 ? ne / nu : ne;
       }
-      log.clear();
-      o.bound = lam_found;
+      const bool accept = ok && e <= tol;
+      if (log && attempts < log_cap) log[attempts] = lj_step_record{t, h, e, cost, accept ? 1 : 0};
+      ++attempts;
+      if (!ok) {
+        st.rejected += 1;
+        dt = 0.5 * h;
+      } else if (accept) {
+        st.accepted += 1;
+        t = last ? T : t + h;
+        cur ^= 1;
+        const double rate = cost / h;
+        const double d_trad = h * traditional_factor(e, tol, p);
+        const double d_cost = have_prev ? h * cost_factor(h, prev_dt, rate, prev_rate) : h * cost_factor(h, h, 1, 1);
+        have_prev = true;
+        prev_dt = h;
+        prev_rate = rate;
+        dt = std::min(d_trad, d_cost);
+      } else {
+        st.rejected += 1;
+        dt = kRetrySafety * h * traditional_factor(e, tol, p);
+      }
     }
-    // ---- the step, synchronously: one spectral bound for the whole step
-    if (!(o.bound > 0.0)) {
-      o.bound = run_bound(ctx, op, o, o.power_iters, o.seed, o.pi_start, s);
-      pit = o.power_iters;
-    }
-    auto act = [&](const double* vec, int K, const int* ls, const double* as, double* const* outs) {
-      lj_stats st;
-      const int rc = vertical_impl(ctx, op, vec, K, ls, as, h, tol, outs, o, &st, s);
-      if (rc != LJ_OK) ok = false;
-      log.push_back(st);
-    };
-    scheme_steps(act);
+    HIPCHK(ctx, hipMemcpyAsync(u_out, ub[cur], n * sizeof(double), hipMemcpyDeviceToDevice, s));
     HIPCHK(ctx, hipStreamSynchronize(s));
-    if (!log.empty()) log[0].power_iters = pit;
-    if (stats)
-      for (size_t i = 0; i < log.size(); ++i) stats[i] = log[i];
-    return ok ? LJ_OK : LJ_ENOTCONV;
+    st.t = t;
+    st.dt_next = dt;
+    if (stats) *stats = st;
+    return rc;
   });
 }
 
