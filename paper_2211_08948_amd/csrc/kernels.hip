@@ -603,9 +603,26 @@ __global__ __launch_bounds__(kBlock) void lj_action_tile(ActionParams P) {
   auto Y = [&](int b) { return lds + b * NE; };
   double* H = lds + P.lds_h;
   // extended points of this thread: e = threadIdx.x + k * kBlock (valid if < NE),
-  // tile coordinates packed as ex | ey << 16, linearisation state in registers
+  // tile coordinates packed as ex | ey << 16.
+  // The stencil is folded into five coefficients: (J x)(p) = fw x_W + fe x_E +
+  // fs x_S + fn x_N + e_d(p) x_C, e_d(p) the diagonal of J at the point (for
+  // Allen-Cahn the Laplacian's centre plus 1 - 3u^2).  Once the bound is known
+  // all five are divided by gamma and c / gamma is taken off the diagonal, so
+  // a Newton step is y = fw x_W + ... + (e_d(p) - xi) x_C: six FP64 operations
+  // instead of thirteen -- the same polynomial in J, rounded in another order.
   int e_xy[EPT];
-  double e_u[EPT];
+  double e_d[EPT];
+  double fw, fe, fs, fn;
+  if constexpr (KIND == OP_ALLENCAHN) {
+    fw = fe = op.c0 * op.idx2;
+    fs = fn = op.c0 * op.idy2;
+  } else {  // advection-diffusion: nu Lap x - a_x d_x x - a_y d_y x (centred)
+    fw = op.c0 * op.idx2 + op.c1 * op.i2dx;
+    fe = op.c0 * op.idx2 - op.c1 * op.i2dx;
+    fs = op.c0 * op.idy2 + op.c2 * op.i2dy;
+    fn = op.c0 * op.idy2 - op.c2 * op.i2dy;
+  }
+  const double d_lap = -2.0 * op.c0 * (op.idx2 + op.idy2);
   auto gidx = [&](int k) {
     const int ex = e_xy[k] & 0xffff, ey = e_xy[k] >> 16;
     int gx = (x0 - S + ex) % nx;
@@ -619,7 +636,12 @@ __global__ __launch_bounds__(kBlock) void lj_action_tile(ActionParams P) {
     const int e = threadIdx.x + k * kBlock;
     const int ey = e / EW;
     e_xy[k] = (e - ey * EW) | (ey << 16);
-    e_u[k] = (e < NE && StateUse<KIND>::value > 0) ? op.state[gidx(k)] : 0.0;
+    if constexpr (KIND == OP_ALLENCAHN) {
+      const double u = (e < NE) ? op.state[gidx(k)] : 0.0;
+      e_d[k] = d_lap + (1.0 - 3.0 * u * u);
+    } else {
+      e_d[k] = d_lap;
+    }
   }
   const int o = threadIdx.x;
   const bool own = o < w * h;
@@ -637,8 +659,10 @@ __global__ __launch_bounds__(kBlock) void lj_action_tile(ActionParams P) {
     t_last = t;
   };
 
-  // one Newton (leja) or power step on the region still exact after j steps
-  auto step = [&](int j, double shift, double gam, double rgam, double xim, bool leja) {
+  // one step on the region still exact after j steps: a power product (the
+  // coefficients of J, xim = 0) or a Newton step (the coefficients divided
+  // by gamma, xim = xi_{m-1})
+  auto step = [&](int j, double xim) {
     const double* src = Y(cur);
     double* dst = Y(cur ^ 1);
 #pragma unroll
@@ -647,16 +671,14 @@ __global__ __launch_bounds__(kBlock) void lj_action_tile(ActionParams P) {
       if (e >= NE) continue;
       const int ex = e_xy[k] & 0xffff, ey = e_xy[k] >> 16;
       if (ex < j || ex >= EW - j || ey < j || ey >= EH - j) continue;
-      double xv[5][2] = {}, uv[5][2] = {};
-      xv[0][0] = src[e];
-      xv[1][0] = src[e - 1];
-      xv[2][0] = src[e + 1];
-      xv[3][0] = src[e - EW];
-      xv[4][0] = src[e + EW];
-      uv[0][0] = e_u[k];
-      double out[2];
-      stencil_jv<KIND>(op, xv, uv, out);
-      dst[e] = leja ? div_rn(out[0] - shift * xv[0][0], gam, rgam) - xim * xv[0][0] : out[0];
+      const double xc = src[e], xw = src[e - 1], xe = src[e + 1], xs = src[e - EW], xn = src[e + EW];
+      double y;
+      if constexpr (KIND == OP_ALLENCAHN) {
+        y = fw * (xw + xe) + fs * (xs + xn);
+      } else {
+        y = fw * xw + fe * xe + fs * xs + fn * xn;
+      }
+      dst[e] = fma(e_d[k] - xim, xc, y);
     }
     __syncthreads();
     cur ^= 1;
@@ -734,7 +756,7 @@ __global__ __launch_bounds__(kBlock) void lj_action_tile(ActionParams P) {
         stage(0, x * x);
       }
       for (int j = 1; j <= steps; ++j) {
-        step(j, 0.0, 1.0, 1.0, 0.0, false);
+        step(j, 0.0);
         const double y = own ? Y(cur)[eo] : 0.0;
         stage(j, y * y);
       }
@@ -774,6 +796,14 @@ __global__ __launch_bounds__(kBlock) void lj_action_tile(ActionParams P) {
     grid_exit(P.barrier);
     return;
   }
+
+  // the Newton steps' coefficients: (J - c) / gamma
+  fw *= rgamma;
+  fe *= rgamma;
+  fs *= rgamma;
+  fn *= rgamma;
+#pragma unroll
+  for (int k = 0; k < EPT; ++k) e_d[k] = (e_d[k] - c) * rgamma;
 
   // ---- (2) divided differences up to the first super-step's last term (the
   // rest while barriers are pending), and y_0 = v on the extended tile
@@ -819,7 +849,7 @@ __global__ __launch_bounds__(kBlock) void lj_action_tile(ActionParams P) {
     for (int j = 1; j <= S; ++j) {
       if (j > steps) break;
       const int m = m0 + j;
-      step(j, c, gamma, rgamma, uniform(sh.xi[m - 1]), true);
+      step(j, uniform(sh.xi[m - 1]));
       const double y = own ? Y(cur)[eo] : 0.0;
       H[(j - 1) * kBlock + threadIdx.x] = y;
       stage((j - 1) * Q, y * y);
