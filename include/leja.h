@@ -62,13 +62,16 @@ typedef struct lj_context lj_context;
  *                       ncomp = 2, coef = {Du, Dv, a, b}
  *   LJ_OP_BURGERS2D     f = nu Lap u - (d/dx + d/dy)(u^2/2), J v = nu Lap v - (d/dx + d/dy)(u v);
  *                       coef = {nu}
+ *   LJ_OP_GRAYSCOTT2D   f = (a1 Lap u - u v^2 + a(1 - u), a2 Lap v + u v^2 - (a + b) v),
+ *                       ncomp = 2, coef = {a1, a2, a, b} (Sec. 3)
  * J is the exact Jacobian of the semi-discrete right-hand side at `state`. */
 typedef enum {
   LJ_OP_DIAG = 0,
   LJ_OP_ADVDIFF2D = 1,
   LJ_OP_ALLENCAHN2D = 2,
   LJ_OP_BRUSSELATOR2D = 3,
-  LJ_OP_BURGERS2D = 4
+  LJ_OP_BURGERS2D = 4,
+  LJ_OP_GRAYSCOTT2D = 5
 } lj_op_kind;
 
 typedef struct {
@@ -348,7 +351,15 @@ typedef struct {
   int64_t power_point_iters; /* grid points x power-iteration products */
   int64_t tiled_launches;    /* launches that used the LDS-tiled kernel */
   double kernel_ms;          /* summed event-measured duration */
+  int64_t aborts;            /* launches whose grid barrier gave up (counted whether or not timing is
+                                enabled; each was repeated with a cooperative launch) */
 } lj_timing;
+
+/* Test hook: when the environment variable LJ_FORCE_SPIN_LIMIT holds a
+ * positive number at lj_create, the first (ordinary) launch of every action
+ * bounds each grid-barrier wait by that many polls instead of the default
+ * 2^22.  A small value makes those launches give up, so the abort-and-retry
+ * path (the cooperative relaunch) runs; results are unchanged. */
 
 /* Diagnostics: the reduced norms the last Newton recurrence on ctx decided
  * on.  Row m-1 (m = 1..iterations) holds ||y_m||_2^2 followed by ||p_k||_2^2

@@ -14,8 +14,10 @@ Scales of one problem (grid spacing dx, dy; diffusion coefficient D):
   r(x)                                 local reaction rate of J: 1 - 3u^2
                                        (Allen-Cahn), -(d_x u + d_y u) with centred
                                        differences (Burgers), -(b+1) + 2uv
-                                       (Brusselator, first species), 0 otherwise
-  D = nu (adv.-diff., Burgers), eps (Allen-Cahn), max(Du, Dv) (Brusselator);
+                                       (Brusselator, first species), -v^2 - a
+                                       (Gray-Scott, first species), 0 otherwise
+  D = nu (adv.-diff., Burgers), eps (Allen-Cahn), max(Du, Dv) (Brusselator),
+  max(a1, a2) (Gray-Scott);
   for a diagonal operator sigma = max|lambda| and A = r = 0.
 State statistics (first component u, over all grid points): mean, standard
 deviation (population), max|u|, and g = max |grad u| dx in grid units,
@@ -69,6 +71,12 @@ def scales(prob):
         u, v = st[0::2], st[1::2]
         A = 0.0
         r = -(c[3] + 1.0) + 2.0 * u * v
+    elif kind == "grayscott":
+        D = max(c[0], c[1])
+        st = np.asarray(prob.state, dtype=np.float64)
+        v = st[1::2]
+        A = 0.0
+        r = -(v * v) - c[2]
     else:
         raise ValueError(kind)
     sigma = D * (1.0 / (dx * dx) + 1.0 / (dy * dy))

@@ -80,6 +80,15 @@ class Operator:
             (nu,) = p.coef
             q = u * u
             return nu * laplacian(u, nx, ny, dx, dy) - 0.5 * (ddx(q, nx, ny, dx) + ddy(q, nx, ny, dy))
+        if self.kind == "grayscott":
+            # Sec. 3: u_t = a1 Lap u - u v^2 + a (1 - u), v_t = a2 Lap v + u v^2 - (a + b) v
+            a1, a2, a, b = p.coef
+            U = u[0::2]
+            V = u[1::2]
+            out = np.empty_like(u)
+            out[0::2] = a1 * laplacian(U, nx, ny, dx, dy) - U * V * V + a * (1.0 - U)
+            out[1::2] = a2 * laplacian(V, nx, ny, dx, dy) + U * V * V - (a + b) * V
+            return out
         raise ValueError(self.kind)
 
     # --- Jacobian action J(state) v --------------------------------------
@@ -110,6 +119,16 @@ class Operator:
             (nu,) = p.coef
             q = s * v  # d/du of u^2/2 applied to v
             return nu * laplacian(v, nx, ny, dx, dy) - (ddx(q, nx, ny, dx) + ddy(q, nx, ny, dy))
+        if self.kind == "grayscott":
+            a1, a2, a, b = p.coef
+            U, V = s[0::2], s[1::2]
+            du, dv = v[0::2], v[1::2]
+            out = np.empty_like(v)
+            # d/du of (-u v^2 + a(1 - u)) = -v^2 - a ; d/dv = -2uv
+            out[0::2] = a1 * laplacian(du, nx, ny, dx, dy) + (-(V * V) - a) * du - 2.0 * U * V * dv
+            # d/du of (u v^2 - (a + b) v) = v^2 ; d/dv = 2uv - (a + b)
+            out[1::2] = a2 * laplacian(dv, nx, ny, dx, dy) + V * V * du + (2.0 * U * V - (a + b)) * dv
+            return out
         raise ValueError(self.kind)
 
     def remainder(self, x, fu=None) -> np.ndarray:

@@ -19,7 +19,7 @@ LJ_NFEATURES = 16
 LJ_MLP_NPARAM = 5378
 LJ_MLP_MODEL_FLOATS = 5414
 
-LJ_OP_DIAG, LJ_OP_ADVDIFF2D, LJ_OP_ALLENCAHN2D, LJ_OP_BRUSSELATOR2D, LJ_OP_BURGERS2D = range(5)
+LJ_OP_DIAG, LJ_OP_ADVDIFF2D, LJ_OP_ALLENCAHN2D, LJ_OP_BRUSSELATOR2D, LJ_OP_BURGERS2D, LJ_OP_GRAYSCOTT2D = range(6)
 LJ_EXPRB2, LJ_EXPRB43_U3, LJ_EXPRB43, LJ_EPIRK4S3 = 1, 2, 3, 4
 
 
@@ -67,7 +67,7 @@ class lj_timing(C.Structure):
     _fields_ = [
         ("launches", C.c_int64), ("iterations", C.c_int64), ("point_iters", C.c_int64),
         ("accum_point_iters", C.c_int64), ("power_point_iters", C.c_int64), ("tiled_launches", C.c_int64),
-        ("kernel_ms", C.c_double),
+        ("kernel_ms", C.c_double), ("aborts", C.c_int64),
     ]
 
 

@@ -5,7 +5,13 @@
 
 namespace lj {
 
-enum OpKind { OP_DIAG = 0, OP_ADVDIFF = 1, OP_ALLENCAHN = 2, OP_BRUSSELATOR = 3, OP_BURGERS = 4 };
+enum OpKind { OP_DIAG = 0, OP_ADVDIFF = 1, OP_ALLENCAHN = 2, OP_BRUSSELATOR = 3, OP_BURGERS = 4, OP_GRAYSCOTT = 5 };
+
+// default bound on the polls of one grid-barrier wait (see wait_at_least)
+constexpr unsigned int kGridSpinLimit = 1u << 22;
+
+// components per grid point of a family
+constexpr int family_ncomp(int kind) { return (kind == OP_BRUSSELATOR || kind == OP_GRAYSCOTT) ? 2 : 1; }
 
 constexpr int kMaxK = 4;                // accumulators sharing one Newton basis
 constexpr int kMaxL = 4;                // highest phi index
@@ -90,6 +96,7 @@ struct ActionParams {
   double* ybuf1;
   double* partials;       // 2 x kPartStride x gridDim partial sums, slot-major
   unsigned int* barrier;  // kBarrierWords words, zero at launch; left zero at exit
+  unsigned int spin_limit;  // polls before a barrier wait gives up (and the launch aborts)
   LejaStatus* status;     // out
   LejaStatus* status_host;  // optional: the status header also here (pinned host memory)
   // tiling of the LDS-resident kernel

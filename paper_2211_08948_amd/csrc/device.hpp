@@ -46,6 +46,15 @@ __device__ __forceinline__ void stencil_jv(const OpDev& op, const double (&x)[5]
     // d/du (b u - u^2 v) = b - 2uv,  d/dv = -u^2
     out[1] = Dv * lap5(op, x[0][1], x[1][1], x[2][1], x[3][1], x[4][1]) + (b - 2.0 * U * V) * x[0][0] -
              U * U * x[0][1];
+  } else if constexpr (KIND == OP_GRAYSCOTT) {
+    const double U = u[0][0], V = u[0][1];
+    const double a1 = op.c0, a2 = op.c1, a = op.c2, b = op.c3;
+    // d/du (-u v^2 + a(1 - u)) = -v^2 - a,  d/dv = -2uv
+    out[0] = a1 * lap5(op, x[0][0], x[1][0], x[2][0], x[3][0], x[4][0]) + (-(V * V) - a) * x[0][0] -
+             2.0 * U * V * x[0][1];
+    // d/du (u v^2 - (a + b) v) = v^2,  d/dv = 2uv - (a + b)
+    out[1] = a2 * lap5(op, x[0][1], x[1][1], x[2][1], x[3][1], x[4][1]) + V * V * x[0][0] +
+             (2.0 * U * V - (a + b)) * x[0][1];
   } else {  // OP_BURGERS: nu Lap x - (d/dx + d/dy)(u x)
     const double qe = u[2][0] * x[2][0], qw = u[1][0] * x[1][0];
     const double qn = u[4][0] * x[4][0], qs = u[3][0] * x[3][0];
@@ -130,6 +139,11 @@ __device__ __forceinline__ void rhs_values(const OpDev& op, const double (&x)[5]
     const double uuv = x[0][0] * x[0][0] * x[0][1];
     out[0] = Du * lap5(op, x[0][0], x[1][0], x[2][0], x[3][0], x[4][0]) + a - (b + 1.0) * x[0][0] + uuv;
     out[1] = Dv * lap5(op, x[0][1], x[1][1], x[2][1], x[3][1], x[4][1]) + b * x[0][0] - uuv;
+  } else if constexpr (KIND == OP_GRAYSCOTT) {
+    const double a1 = op.c0, a2 = op.c1, a = op.c2, b = op.c3;
+    const double uvv = x[0][0] * x[0][1] * x[0][1];
+    out[0] = a1 * lap5(op, x[0][0], x[1][0], x[2][0], x[3][0], x[4][0]) - uvv + a * (1.0 - x[0][0]);
+    out[1] = a2 * lap5(op, x[0][1], x[1][1], x[2][1], x[3][1], x[4][1]) + uvv - (a + b) * x[0][1];
   } else {
     const double c = x[0][0], w = x[1][0], e = x[2][0], s = x[3][0], n = x[4][0];
     if constexpr (KIND == OP_ADVDIFF) {
@@ -163,7 +177,7 @@ __device__ __forceinline__ void gather_x(const OpDev& op, const double* __restri
 template <int KIND>
 __device__ __forceinline__ void rhs_point(const OpDev& op, const double* __restrict__ x, int p,
                                           double out[2]) {
-  constexpr int NC = (KIND == OP_BRUSSELATOR) ? 2 : 1;
+  constexpr int NC = family_ncomp(KIND);
   double xv[5][2];
   gather_x<KIND, NC>(op, x, p, xv);
   rhs_values<KIND>(op, xv, (KIND == OP_DIAG) ? op.state[p] : 0.0, out);
@@ -375,13 +389,13 @@ struct NoOverlap {
 // abort word after kGridSpinLimit polls, every later wait returns at once, the
 // launch runs to its end, and the host sees the abort in the status and
 // relaunches cooperatively.  Returns false on abort.
-constexpr unsigned int kGridSpinLimit = 1u << 22;
 
-__device__ __forceinline__ bool wait_at_least(unsigned int* word, unsigned int target, unsigned int* abort_word) {
+__device__ __forceinline__ bool wait_at_least(unsigned int* word, unsigned int target, unsigned int* abort_word,
+                                              unsigned int spin_limit) {
   unsigned int spins = 0;
   while (__hip_atomic_load(word, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
     if (__hip_atomic_load(abort_word, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) return false;
-    if (++spins > kGridSpinLimit) {
+    if (++spins > spin_limit) {
       __hip_atomic_store(abort_word, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       return false;
     }
@@ -405,10 +419,18 @@ __device__ __forceinline__ unsigned int grid_aborted(unsigned int* base) {
 // overlaps that of the partial sums').  Each wave issues the loads of all its
 // rows of partials before summing any, so the reduction costs one memory
 // round trip.
+// The barrier state and the bound on each wait (kGridSpinLimit; a host may
+// pass a smaller one to force the abort path).
+struct GridSync {
+  unsigned int* base;
+  unsigned int spin_limit;
+};
+
 template <class Overlap = NoOverlap, class Prefetch = NoOverlap>
-__device__ __forceinline__ void grid_allreduce(unsigned int* base, unsigned int& epoch, double* area, int nq,
+__device__ __forceinline__ void grid_allreduce(const GridSync& gs, unsigned int& epoch, double* area, int nq,
                                                double* tot, Overlap&& overlap = Overlap{},
                                                Prefetch&& prefetch = Prefetch{}) {
+  unsigned int* base = gs.base;
   __builtin_amdgcn_s_waitcnt(0);  // this thread's loads and stores have completed
   __syncthreads();
   epoch += 1u;
@@ -424,10 +446,10 @@ __device__ __forceinline__ void grid_allreduce(unsigned int* base, unsigned int&
     const unsigned int old = __hip_atomic_fetch_add(gc, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     if (old == epoch * gsize - 1u) {
       __hip_atomic_fetch_add(base, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      (void)wait_at_least(base, epoch * ng, abort_word);
+      (void)wait_at_least(base, epoch * ng, abort_word, gs.spin_limit);
       __hip_atomic_store(gf, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     } else {
-      (void)wait_at_least(gf, epoch, abort_word);
+      (void)wait_at_least(gf, epoch, abort_word, gs.spin_limit);
     }
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
   } else if (threadIdx.x < agent) {
@@ -477,8 +499,8 @@ __device__ __forceinline__ void grid_allreduce(unsigned int* base, unsigned int&
   }
 }
 
-__device__ __forceinline__ void grid_barrier(unsigned int* base, unsigned int& epoch) {
-  grid_allreduce(base, epoch, nullptr, 0, nullptr);
+__device__ __forceinline__ void grid_barrier(const GridSync& gs, unsigned int& epoch) {
+  grid_allreduce(gs, epoch, nullptr, 0, nullptr);
 }
 
 // Call once per block after its last grid_barrier.  The last block to arrive

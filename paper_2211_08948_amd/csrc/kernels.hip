@@ -425,6 +425,7 @@ struct ActionShared {
 // ===========================================================================
 template <int KIND, int NC>
 __global__ __launch_bounds__(kBlock) void lj_action_stream(ActionParams P) {
+  const GridSync gsync{P.barrier, P.spin_limit};
   __shared__ ActionShared sh;
   const OpDev& op = P.op;
   const int npts = op.npts;
@@ -453,7 +454,7 @@ __global__ __launch_bounds__(kBlock) void lj_action_stream(ActionParams P) {
         for (int cc = 0; cc < NC; ++cc)
           store_shared(P.ybuf1 + NC * p + cc, 0.5 + splitmix_uniform(P.seed, (uint64_t)(NC * p + cc)));
       x0 = P.ybuf1;
-      grid_barrier(P.barrier, epoch);
+      grid_barrier(gsync, epoch);
     }
     double scale = 1.0;
     for (int k = 0; k < P.power_iters; ++k) {
@@ -471,7 +472,7 @@ __global__ __launch_bounds__(kBlock) void lj_action_stream(ActionParams P) {
         put_partial(my_partial(area, 0), wred[0]);
         put_partial(my_partial(area, 1), wred[1]);
       }
-      grid_allreduce(P.barrier, epoch, area, 2, sh.tot);
+      grid_allreduce(gsync, epoch, area, 2, sh.tot);
       const double nx = sqrt(sh.tot[0]);
       const double ny = sqrt(sh.tot[1]);
       lam = ny / nx;
@@ -528,7 +529,7 @@ __global__ __launch_bounds__(kBlock) void lj_action_stream(ActionParams P) {
     block_sum<kQ>(wred, sh.red);
     if (threadIdx.x == 0) put_partial(my_partial(partial_area(P.partials, epoch), 0), wred[0]);
   }
-  grid_allreduce(P.barrier, epoch, partial_area(P.partials, epoch), 1, sh.tot,
+  grid_allreduce(gsync, epoch, partial_area(P.partials, epoch), 1, sh.tot,
                  [&] { dd_advance(dd, K, 2, sh.xi, sh.coef); });
   const double nv = sqrt(sh.tot[0]);
   // The decision state is the same in every thread, so it lives once per block
@@ -561,7 +562,7 @@ __global__ __launch_bounds__(kBlock) void lj_action_stream(ActionParams P) {
         if (q <= K) put_partial(my_partial(area, q), acc[q]);
     }
     tick(kProfPublish);
-    grid_allreduce(P.barrier, epoch, area, 1 + K, sh.tot, [&] { dd_advance(dd, K, m + 2, sh.xi, sh.coef); });
+    grid_allreduce(gsync, epoch, area, 1 + K, sh.tot, [&] { dd_advance(dd, K, m + 2, sh.xi, sh.coef); });
     tick(kProfBarrier);
     if (threadIdx.x < 64)
       replay_decisions(sD, K, m - 1, 1, 1 + K, sh.tot, sh.coef, P.tol, P.relative, P.max_points, s_commit,
@@ -582,6 +583,7 @@ __global__ __launch_bounds__(kBlock) void lj_action_stream(ActionParams P) {
 // ===========================================================================
 template <int KIND, int S, int EPT>
 __global__ __launch_bounds__(kBlock) void lj_action_tile(ActionParams P) {
+  const GridSync gsync{P.barrier, P.spin_limit};
   static_assert(KIND == OP_ADVDIFF || KIND == OP_ALLENCAHN, "tiled kernel: scalar centre-state families");
   extern __shared__ double lds[];
   __shared__ ActionShared sh;
@@ -764,7 +766,7 @@ __global__ __launch_bounds__(kBlock) void lj_action_tile(ActionParams P) {
       double* yb = (par == 0) ? P.ybuf0 : P.ybuf1;
       if (own) store_shared(yb + go, Y(cur)[eo]);
       const bool more = done + steps < P.power_iters;
-      grid_allreduce(P.barrier, epoch, area, steps + 1, sh.tot, NoOverlap{}, [&] {
+      grid_allreduce(gsync, epoch, area, steps + 1, sh.tot, NoOverlap{}, [&] {
         if (more) fetch_halo(yb);
       });
       const double nprev = sh.tot[steps - 1], nlast = sh.tot[steps];
@@ -868,7 +870,7 @@ __global__ __launch_bounds__(kBlock) void lj_action_tile(ActionParams P) {
     if (own) store_shared(yb + go, Y(cur)[eo]);
     tick(kProfPublish);
     grid_allreduce(
-        P.barrier, epoch, area, nq, sh.tot, [&] { dd_advance(dd, K, m0 + steps + S, sh.xi, sh.coef); },
+        gsync, epoch, area, nq, sh.tot, [&] { dd_advance(dd, K, m0 + steps + S, sh.xi, sh.coef); },
         [&] { fetch_halo(yb); });
     tick(kProfBarrier);
     if (threadIdx.x < 64) {
@@ -1327,6 +1329,7 @@ void* action_stream_ptr(int kind) {
     case OP_ALLENCAHN: return reinterpret_cast<void*>(&lj_action_stream<OP_ALLENCAHN, 1>);
     case OP_BRUSSELATOR: return reinterpret_cast<void*>(&lj_action_stream<OP_BRUSSELATOR, 2>);
     case OP_BURGERS: return reinterpret_cast<void*>(&lj_action_stream<OP_BURGERS, 1>);
+    case OP_GRAYSCOTT: return reinterpret_cast<void*>(&lj_action_stream<OP_GRAYSCOTT, 2>);
   }
   return nullptr;
 }
@@ -1361,6 +1364,7 @@ void* batch_kernel_ptr(int kind, int bs) {
     LJ_BATCH_CASE(OP_ALLENCAHN, 1)
     LJ_BATCH_CASE(OP_BRUSSELATOR, 2)
     LJ_BATCH_CASE(OP_BURGERS, 1)
+    LJ_BATCH_CASE(OP_GRAYSCOTT, 2)
   }
 #undef LJ_BATCH_CASE
   return nullptr;
@@ -1397,6 +1401,7 @@ hipError_t launch_rhs(const OpDev& op, const double* u, double* f, hipStream_t s
     case OP_ALLENCAHN: rhs_t<OP_ALLENCAHN, 1>(op, u, f, s); break;
     case OP_BRUSSELATOR: rhs_t<OP_BRUSSELATOR, 2>(op, u, f, s); break;
     case OP_BURGERS: rhs_t<OP_BURGERS, 1>(op, u, f, s); break;
+    case OP_GRAYSCOTT: rhs_t<OP_GRAYSCOTT, 2>(op, u, f, s); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -1418,6 +1423,7 @@ hipError_t launch_rhs_scaled(const OpDev& op, double h, double* f, double* v, hi
     case OP_ALLENCAHN: rhs_scaled_t<OP_ALLENCAHN, 1>(op, h, f, v, s); break;
     case OP_BRUSSELATOR: rhs_scaled_t<OP_BRUSSELATOR, 2>(op, h, f, v, s); break;
     case OP_BURGERS: rhs_scaled_t<OP_BURGERS, 1>(op, h, f, v, s); break;
+    case OP_GRAYSCOTT: rhs_scaled_t<OP_GRAYSCOTT, 2>(op, h, f, v, s); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -1430,6 +1436,7 @@ hipError_t launch_stage(const StageArgs& A, hipStream_t s) {
     case OP_ALLENCAHN: stage_t<OP_ALLENCAHN, 1>(A, s); break;
     case OP_BRUSSELATOR: stage_t<OP_BRUSSELATOR, 2>(A, s); break;
     case OP_BURGERS: stage_t<OP_BURGERS, 1>(A, s); break;
+    case OP_GRAYSCOTT: stage_t<OP_GRAYSCOTT, 2>(A, s); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

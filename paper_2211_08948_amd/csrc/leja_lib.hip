@@ -69,6 +69,7 @@ struct lj_context {
   // timing: an event pair around each action launch; the elapsed times are
   // read when the counters are (lj_timing_read), not after every launch
   bool timing = false;
+  unsigned int forced_spin_limit = 0;  // LJ_FORCE_SPIN_LIMIT (test hook), 0: the default bound
   std::vector<hipEvent_t> tev;  // 2 * kTimingPairs, created when timing is first enabled
   int tev_next = 0;             // next free pair
   std::vector<int> tev_pending; // pairs whose launches finished but whose times are unread
@@ -166,10 +167,11 @@ void check_range(lj_context* ctx, const void* p, size_t bytes, const std::string
 
 OpDev make_op(lj_context* ctx, const lj_operator* J) {
   if (!J) invalid(ctx, "operator is NULL");
-  if (J->kind < LJ_OP_DIAG || J->kind > LJ_OP_BURGERS2D) invalid(ctx, "operator: unknown kind");
+  if (J->kind < LJ_OP_DIAG || J->kind > LJ_OP_GRAYSCOTT2D) invalid(ctx, "operator: unknown kind");
   if (J->nx < 1 || J->ny < 1) invalid(ctx, "operator: nx and ny must be >= 1");
-  const int want_nc = (J->kind == LJ_OP_BRUSSELATOR2D) ? 2 : 1;
-  if (J->ncomp != want_nc) invalid(ctx, "operator: ncomp must be 2 for the Brusselator and 1 otherwise");
+  const int want_nc = family_ncomp(J->kind);
+  if (J->ncomp != want_nc)
+    invalid(ctx, "operator: ncomp must be 2 for the Brusselator and Gray-Scott and 1 otherwise");
   const long long n = (long long)J->nx * J->ny * J->ncomp;
   if (n > (1ll << 30)) invalid(ctx, "operator: grid too large (more than 2^30 unknowns)");
   if (J->kind == LJ_OP_DIAG && J->ny != 1) invalid(ctx, "operator: DIAG needs ny == 1");
@@ -376,6 +378,7 @@ void launch_action(lj_context* ctx, const OpDev& op, const double* v, int K, con
   P.ybuf0 = slot(ctx, W_Y0, n);
   P.ybuf1 = slot(ctx, W_Y1, n);
   P.barrier = ctx->d_barrier;
+  P.spin_limit = (!cooperative && ctx->forced_spin_limit > 0) ? ctx->forced_spin_limit : kGridSpinLimit;
   P.status = ctx->d_status;
   // a header-only status into a slot of the pinned pool is written by the
   // kernel itself; otherwise it is copied after the launch
@@ -420,6 +423,7 @@ void launch_action(lj_context* ctx, const OpDev& op, const double* v, int K, con
 ActOut finish_action(lj_context* ctx, const OpDev& op, const LejaStatus& S, hipEvent_t* ev, bool tiled) {
   ActOut r;
   r.aborted = S.aborted != 0;
+  if (r.aborted) ctx->tm.aborts += 1;
   for (int k = 0; k < kMaxK; ++k) {
     r.state[k] = S.state[k];
     r.m_star[k] = S.m_star[k];
@@ -1000,6 +1004,10 @@ LJ_API int lj_create(lj_context** out, int hip_device) {
     if (const char* g = std::getenv("LJ_GRID")) ctx->grid_override = std::atoi(g);
     if (const char* g = std::getenv("LJ_NO_TILE")) ctx->force_stream = std::atoi(g);
     if (const char* g = std::getenv("LJ_COOP")) ctx->force_coop = std::atoi(g);
+    if (const char* g = std::getenv("LJ_FORCE_SPIN_LIMIT")) {
+      const long v = std::atol(g);
+      ctx->forced_spin_limit = v > 0 ? (unsigned int)std::min<long>(v, kGridSpinLimit) : 0u;
+    }
     if (const char* g = std::getenv("LJ_TILE")) {
       int tx = 0, ty = 0;
       if (std::sscanf(g, "%d,%d", &tx, &ty) == 2 && tx > 0 && ty > 0) {
@@ -1399,7 +1407,7 @@ int step_impl(lj_context* ctx, int scheme, const OpDev& op, Opts o, double h, do
           all = false;
         }
       }
-      if (i == 0) {
+      if (i == 0 && !r.aborted) {  // an aborted launch's bound is not to be trusted
         lam_found = r.lam;
         pit = r.power_iters;
       }

@@ -42,6 +42,9 @@ __device__ __forceinline__ void reaction_at(const OpDev& op, int p, double& u, d
       r = 1.0 - 3.0 * u * u;
     } else if constexpr (KIND == OP_BURGERS) {
       r = -((ue - uw) * op.i2dx + (un - us) * op.i2dy);
+    } else if constexpr (KIND == OP_GRAYSCOTT) {  // d/du of the first species' reaction
+      const double v = s[NC * q.c + 1];
+      r = -(v * v) - op.c2;
     } else {  // OP_BRUSSELATOR: d/du of the first species' reaction
       r = -(op.c3 + 1.0) + 2.0 * u * s[NC * q.c + 1];
     }
@@ -112,7 +115,7 @@ __global__ void lj_feature_finish(FeatureJob J, const FeatPartial* part, int npa
   if (op.kind == OP_DIAG) {
     sigma = P.lmax;
   } else {
-    const double D = (op.kind == OP_BRUSSELATOR) ? fmax(op.c0, op.c1) : op.c0;
+    const double D = (op.kind == OP_BRUSSELATOR || op.kind == OP_GRAYSCOTT) ? fmax(op.c0, op.c1) : op.c0;
     sigma = D * (op.idx2 + op.idy2);
     if (op.kind == OP_ADVDIFF) A = fabs(op.c1) * 2.0 * op.i2dx + fabs(op.c2) * 2.0 * op.i2dy;
     if (op.kind == OP_BURGERS) A = P.umax * 2.0 * (op.i2dx + op.i2dy);
@@ -438,6 +441,10 @@ hipError_t launch_features(const FeatureJob& J, FeatPartialBuf part, float* feat
       break;
     case OP_BURGERS:
       hipLaunchKernelGGL((lj_feature_partials<OP_BURGERS, 1>), dim3(nparts), dim3(256), 0, s, J.op,
+                         reinterpret_cast<FeatPartial*>(part));
+      break;
+    case OP_GRAYSCOTT:
+      hipLaunchKernelGGL((lj_feature_partials<OP_GRAYSCOTT, 2>), dim3(nparts), dim3(256), 0, s, J.op,
                          reinterpret_cast<FeatPartial*>(part));
       break;
     default:

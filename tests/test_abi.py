@@ -45,7 +45,7 @@ def test_struct_layout_matches_c(tmp_path):
                        "use_proposal"],
         "lj_stats": ["m_star", "substeps", "err_est", "iters_total", "converged", "bound", "gamma", "fallbacks",
                      "proposal_bound"],
-        "lj_timing": ["launches", "power_point_iters", "tiled_launches", "kernel_ms"],
+        "lj_timing": ["launches", "power_point_iters", "tiled_launches", "kernel_ms", "aborts"],
         "lj_batch_info_t": ["schedule", "nschedules", "tune_ms", "total_values", "alg_bytes"],
         "lj_integrate_stats": ["accepted", "rejected", "products", "t", "dt_next"],
         "lj_step_record": ["t", "dt", "err", "products", "accepted"],

@@ -14,7 +14,7 @@ from oracle.phi import phi
 from oracle.points import leja_points
 from oracle.power import power_iteration
 from workloads import (advdiff_bump, allen_cahn_noise, brusselator_perturbed, burgers_sines,
-                       diag_problem)
+                       diag_problem, gray_scott_spots)
 from workloads.problems import Problem
 
 pytestmark = pytest.mark.gpu
@@ -43,6 +43,7 @@ def small_problems():
         "allencahn_ragged": allen_cahn_noise(37, eps=1e-1, seed=7),
         "brusselator": brusselator_perturbed(48, D=2e-2, seed=3),
         "burgers": burgers_sines(64, nu=3e-2, seed=5),
+        "grayscott": gray_scott_spots(40, a1=2e-2, a2=1e-2, amp=0.02),
     }
 
 
@@ -356,6 +357,21 @@ def test_step_parity_brusselator(gpu):
     rc, sts, u, _ = gpu.step(prob, "EXPRB43_U3", h, TOL)
     assert rc == 0 and [s["m_star"][:len(b.m_star)] for s, b in zip(sts, log)] == [b.m_star for b in log]
     assert rel(u, u_orc) <= TOL
+
+
+@pytest.mark.parametrize("scheme", ["EXPRB43", "EPIRK4S3"])
+def test_step_parity_gray_scott(gpu, scheme):
+    # the two-species Gray-Scott system of Sec. 3 (spot initial state), one step
+    prob = gray_scott_spots(48, a1=1e-2, a2=5e-3, amp=0.02)
+    op = Operator(prob)
+    h = 10 * prob.h_cfl
+    lam = power_iteration(op.jv, prob.n, 20)
+    u_orc, e_orc, log = oracle_step(op, scheme, h, TOL, Options(bound=lam))
+    say("step gray-scott", scheme, [b.m_star for b in log])
+    rc, sts, u, e = gpu.step(prob, scheme, h, TOL, bound=lam)
+    assert rc == 0 and [s["m_star"][:len(b.m_star)] for s, b in zip(sts, log)] == [b.m_star for b in log]
+    assert rel(u, u_orc) <= TOL
+    assert np.linalg.norm(e - e_orc) <= 1e-8 * np.linalg.norm(e_orc) + 1e-12 * np.linalg.norm(u_orc)
 
 
 def test_step_parity_brusselator_full_size(gpu):

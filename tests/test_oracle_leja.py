@@ -14,7 +14,7 @@ from oracle.integrators import rk_reference, step
 from oracle.leja import Options, phi_action, phi_vertical
 from oracle.operators import Operator
 from oracle.phi import phi
-from workloads import advdiff_bump, allen_cahn_noise, brusselator_perturbed, diag_problem
+from workloads import advdiff_bump, allen_cahn_noise, brusselator_perturbed, diag_problem, gray_scott_spots
 from workloads.problems import Problem
 
 
@@ -63,7 +63,7 @@ def test_fourier_matches_dense_pade(cfg1):
     assert rel(ref_f, ref_d) <= 1e-13
 
 
-@pytest.mark.parametrize("kind", ["allencahn", "brusselator", "burgers"])
+@pytest.mark.parametrize("kind", ["allencahn", "brusselator", "burgers", "grayscott"])
 @pytest.mark.parametrize("l", [0, 1, 3])
 def test_dense_pade_small_grids(kind, l):
     if kind == "allencahn":
@@ -73,6 +73,8 @@ def test_dense_pade_small_grids(kind, l):
         # diffusion-dominated, as at 1024^2 with D = 2e-3: the reaction's unstable
         # pair (Re = 1/2) then sits just beyond the right end of the interval
         p = brusselator_perturbed(12, D=0.1, seed=8, amp=0.3)
+    elif kind == "grayscott":
+        p = gray_scott_spots(12, a1=2e-2, a2=1e-2, amp=0.05)
     else:
         # grid Peclet ~1.25: diffusion-dominated like the 2048^2 workload
         p = Problem("burgers", 16, 16, 1, 1 / 16, 1 / 16, (5e-2,),

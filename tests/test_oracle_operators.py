@@ -9,7 +9,7 @@ from oracle.exact import advdiff_symbol
 from oracle.operators import Operator
 from oracle.power import power_iteration
 from workloads import (advdiff_bump, allen_cahn_noise, brusselator_perturbed,
-                       burgers_sines)
+                       burgers_sines, gray_scott_spots)
 from workloads.problems import Problem
 
 
@@ -49,10 +49,13 @@ def _small(kind, nx=7, ny=5):
     if kind == "brusselator":
         return Problem(kind, nx, ny, 2, dx, dy, (0.03, 0.011, 1.0, 3.0),
                        rng.uniform(0.5, 3.5, 2 * nx * ny), 1.0)
+    if kind == "grayscott":
+        return Problem(kind, nx, ny, 2, dx, dy, (0.02, 0.007, 0.04, 0.06),
+                       rng.uniform(0.0, 1.0, 2 * nx * ny), 1.0)
     raise ValueError(kind)
 
 
-@pytest.mark.parametrize("kind", ["advdiff", "allencahn", "burgers", "brusselator"])
+@pytest.mark.parametrize("kind", ["advdiff", "allencahn", "burgers", "brusselator", "grayscott"])
 def test_jacobian_matches_kronecker_assembly(kind):
     p = _small(kind)
     op = Operator(p)
@@ -67,7 +70,7 @@ def test_jacobian_matches_kronecker_assembly(kind):
     elif kind == "burgers":
         (nu,) = p.coef
         ref = nu * lap - (dxo + dyo) @ np.diag(p.state)
-    else:
+    elif kind == "brusselator":
         Du, Dv, a, b = p.coef
         U, V = p.state[0::2], p.state[1::2]
         n = p.nx * p.ny
@@ -77,10 +80,20 @@ def test_jacobian_matches_kronecker_assembly(kind):
         blk[1::2, 0::2] = np.diag(b - 2 * U * V)
         blk[1::2, 1::2] = Dv * lap - np.diag(U * U)
         ref = blk
+    else:  # Gray-Scott: partial derivatives of -u v^2 + a(1 - u) and u v^2 - (a + b) v
+        a1, a2, a, b = p.coef
+        U, V = p.state[0::2], p.state[1::2]
+        n = p.nx * p.ny
+        blk = np.zeros((2 * n, 2 * n))
+        blk[0::2, 0::2] = a1 * lap + np.diag(-V * V - a)
+        blk[0::2, 1::2] = np.diag(-2 * U * V)
+        blk[1::2, 0::2] = np.diag(V * V)
+        blk[1::2, 1::2] = a2 * lap + np.diag(2 * U * V - (a + b))
+        ref = blk
     assert np.max(np.abs(J - ref)) <= 1e-12 * np.max(np.abs(ref))
 
 
-@pytest.mark.parametrize("kind", ["allencahn", "burgers", "brusselator"])
+@pytest.mark.parametrize("kind", ["allencahn", "burgers", "brusselator", "grayscott"])
 def test_jacobian_is_derivative_of_rhs(kind):
     p = _small(kind)
     op = Operator(p)
@@ -107,6 +120,14 @@ def test_brusselator_steady_state_is_fixed_point():
     st = np.empty(2 * p.nx * p.ny)
     st[0::2], st[1::2] = a, b / a
     assert np.max(np.abs(Operator(p).rhs(st))) <= 1e-15
+
+
+def test_gray_scott_trivial_state_is_fixed_point():
+    # (u, v) = (1, 0): no reaction (u v^2 = 0, a(1 - u) = 0, (a + b) v = 0) and no diffusion
+    p = _small("grayscott")
+    st = np.empty(2 * p.nx * p.ny)
+    st[0::2], st[1::2] = 1.0, 0.0
+    assert np.max(np.abs(Operator(p).rhs(st))) == 0.0
 
 
 def test_advdiff_fourier_modes_are_eigenvectors():
@@ -136,6 +157,9 @@ def test_workload_shapes_and_seeds():
     assert np.all(np.abs(br.state[0::2] - 1) <= 1e-2) and np.all(np.abs(br.state[1::2] - 3) <= 1e-2)
     bu = burgers_sines(64)
     assert abs(np.abs(bu.state).max() - 1.0) < 1e-15
+    gs = gray_scott_spots(64)
+    assert gs.ncomp == 2 and gs.n == 2 * 64 * 64
+    assert 0.0 <= gs.state[0::2].min() and gs.state[0::2].max() <= 1.0 and 0.9 < gs.state[1::2].max() <= 1.0
 
 
 # ------------------------------------------------------------ power iteration

@@ -12,6 +12,7 @@ from .problems import (  # noqa: F401
     brusselator_perturbed,
     burgers_sines,
     diag_problem,
+    gray_scott_spots,
     batch_instances,
     proposal_training_set,
     uniform_vector,

@@ -16,7 +16,7 @@ from dataclasses import dataclass, field
 
 import numpy as np
 
-KINDS = ("diag", "advdiff", "allencahn", "brusselator", "burgers")
+KINDS = ("diag", "advdiff", "allencahn", "brusselator", "burgers", "grayscott")
 
 
 @dataclass
@@ -114,6 +114,26 @@ def brusselator_perturbed(n: int = 1024, D: float = 2e-3, a: float = 1.0, b: flo
     st[:, 0] = a + amp * rng.uniform(-1.0, 1.0, size=n * n)
     st[:, 1] = b / a + amp * rng.uniform(-1.0, 1.0, size=n * n)
     return Problem("brusselator", n, n, 2, dx, dx, (D, D, a, b), st.ravel(), dx * dx / (4.0 * D))
+
+
+def gray_scott_spots(n: int = 1024, a1: float = 1e-3, a2: float = 1e-3, a: float = 0.04, b: float = 0.06,
+                     seed: int = 8, amp: float = 0.0) -> Problem:
+    """Gray-Scott u_t = a1 Lap u - u v^2 + a(1 - u), v_t = a2 Lap v + u v^2 - (a + b) v
+    on [0,1)^2, periodic (Sec. 3), with the initial state of Sec. 3:
+    u = 1 - exp(-150((x-1/2)^2 + (y-1/2)^2)), v = exp(-150((x-1/2)^2 + 2(y-1/2)^2)),
+    plus amp U[-1,1] noise (seeded).  State interleaved (u, v).  coef = (a1, a2, a, b)."""
+    dx = 1.0 / n
+    x = (np.arange(n) + 0.5) * dx
+    X, Y = np.meshgrid(x, x)  # row = y, column = x
+    u = 1.0 - np.exp(-150.0 * ((X - 0.5) ** 2 + (Y - 0.5) ** 2))
+    v = np.exp(-150.0 * ((X - 0.5) ** 2 + 2.0 * (Y - 0.5) ** 2))
+    st = np.empty((n * n, 2))
+    st[:, 0] = u.ravel()
+    st[:, 1] = v.ravel()
+    if amp > 0.0:
+        st += amp * _rng(seed).uniform(-1.0, 1.0, size=st.shape)
+    D = max(a1, a2)
+    return Problem("grayscott", n, n, 2, dx, dx, (a1, a2, a, b), st.ravel(), dx * dx / (4.0 * D))
 
 
 def burgers_sines(n: int = 2048, nu: float = 1e-3, seed: int = 5, modes: int = 8) -> Problem:
