@@ -9,6 +9,10 @@
   evaluated with scipy's Pade scaling-and-squaring expm (Sec. 1 names Pade and
   scaling-and-squaring as the dense methods).
 
+* pure diffusion with homogeneous Neumann boundaries on a cell-centred grid:
+  the 1D second difference with ghost = boundary cell has the DCT-II vectors
+  cos(pi k (i + 1/2) / n) as eigenvectors, eigenvalue -(4/dx^2) sin^2(pi k / 2n),
+  so w* = IDCT(phi_l(h lambda) DCT(v)) with the orthonormal 2D DCT-II;
 Complex phi_l for the Fourier symbol is evaluated through the same theorem on
 the scalar (l+1)x(l+1) augmented matrix, so this module does not reuse the
 oracle's phi.
@@ -79,3 +83,21 @@ def fourier_closed_form(sigma: np.ndarray, v: np.ndarray, l: int, h: float) -> n
         g[idx] = phi_scalar_expm(l, h * s)
     w = np.fft.ifft2(g * V)
     return w.real.ravel()
+
+
+def neumann_diffusion_eigs(nx, ny, dx, dy, alpha) -> np.ndarray:
+    """Eigenvalues lam[ky, kx] of alpha Lap (Neumann, cell-centred) on the DCT-II modes."""
+    lx = -4.0 / dx ** 2 * np.sin(np.pi * np.arange(nx) / (2.0 * nx)) ** 2
+    ly = -4.0 / dy ** 2 * np.sin(np.pi * np.arange(ny) / (2.0 * ny)) ** 2
+    return alpha * (ly[:, None] + lx[None, :])
+
+
+def dct_closed_form(lam: np.ndarray, v: np.ndarray, l: int, h: float) -> np.ndarray:
+    """w* = IDCT(phi_l(h lam) DCT(v)) for an operator the 2D DCT-II diagonalises."""
+    from scipy.fft import dctn, idctn
+    ny, nx = lam.shape
+    V = dctn(np.asarray(v, dtype=np.float64).reshape(ny, nx), type=2, norm="ortho")
+    g = np.empty_like(V)
+    for idx, x in np.ndenumerate(lam):
+        g[idx] = phi_scalar_expm(l, h * x).real
+    return idctn(g * V, type=2, norm="ortho").ravel()

@@ -9,19 +9,24 @@ plain definition the HIP feature kernel is checked against.
 Scales of one problem (grid spacing dx, dy; diffusion coefficient D):
   sigma = D (1/dx^2 + 1/dy^2)           diffusive rate
   A                                    advective rate: |a_x|/dx + |a_y|/dy for
-                                       advection-diffusion, max|u| (1/dx + 1/dy)
-                                       for Burgers, 0 otherwise
+                                       advection-diffusion, |beta| (1/dx + 1/dy)
+                                       for advection-diffusion-reaction,
+                                       max|u| (1/dx + 1/dy) for Burgers, 0
+                                       otherwise
   r(x)                                 local reaction rate of J: 1 - 3u^2
                                        (Allen-Cahn), -(d_x u + d_y u) with centred
                                        differences (Burgers), -(b+1) + 2uv
                                        (Brusselator, first species), -v^2 - a
-                                       (Gray-Scott, first species), 0 otherwise
+                                       (Gray-Scott, first species),
+                                       rate (-3u^2 + 3u - 1/2) (adv.-diff.-
+                                       reaction), 0 otherwise
   D = nu (adv.-diff., Burgers), eps (Allen-Cahn), max(Du, Dv) (Brusselator),
-  max(a1, a2) (Gray-Scott);
+  max(a1, a2) (Gray-Scott), alpha (adv.-diff.-reaction);
   for a diagonal operator sigma = max|lambda| and A = r = 0.
 State statistics (first component u, over all grid points): mean, standard
 deviation (population), max|u|, and g = max |grad u| dx in grid units,
-g = max sqrt(((u_E - u_W)/2)^2 + ((u_N - u_S)/2)^2).
+g = max sqrt(((u_E - u_W)/2)^2 + ((u_N - u_S)/2)^2), neighbours taken as the
+operator takes them (periodic, or the boundary cell itself for Neumann).
 
 features[0..15] =
   log10(h sigma), l/4, log10(1 + A/sigma), log10(1 + max(r_max,0)/sigma),
@@ -77,6 +82,11 @@ def scales(prob):
         v = st[1::2]
         A = 0.0
         r = -(v * v) - c[2]
+    elif kind == "adr":
+        D = c[0]
+        u = np.asarray(prob.state, dtype=np.float64)
+        A = abs(c[1]) * (1.0 / dx + 1.0 / dy)
+        r = c[2] * (-3.0 * u * u + 3.0 * u - 0.5)
     else:
         raise ValueError(kind)
     sigma = D * (1.0 / (dx * dx) + 1.0 / (dy * dy))
@@ -90,8 +100,13 @@ def state_stats(prob):
     st = np.asarray(prob.state, dtype=np.float64)
     u = st[0::prob.ncomp]
     U = u.reshape(prob.ny, prob.nx)
-    gx = (np.roll(U, -1, axis=1) - np.roll(U, 1, axis=1)) / 2.0
-    gy = (np.roll(U, -1, axis=0) - np.roll(U, 1, axis=0)) / 2.0
+    if prob.kind == "adr":  # Neumann: a boundary cell is its own ghost neighbour
+        P = np.pad(U, 1, mode="edge")
+        gx = (P[1:-1, 2:] - P[1:-1, :-2]) / 2.0
+        gy = (P[2:, 1:-1] - P[:-2, 1:-1]) / 2.0
+    else:
+        gx = (np.roll(U, -1, axis=1) - np.roll(U, 1, axis=1)) / 2.0
+        gy = (np.roll(U, -1, axis=0) - np.roll(U, 1, axis=0)) / 2.0
     g = float(np.max(np.sqrt(gx * gx + gy * gy)))
     return float(np.mean(u)), float(np.std(u)), float(np.max(np.abs(u))), g
 

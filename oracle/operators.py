@@ -1,7 +1,12 @@
 """Right-hand sides f(u) and Jacobian actions J(u)v of the test problems.
 
 Sec. 3: every spatial derivative is discretised with second-order centred
-differences.  The build runs the problems on periodic grids.  Sec. 1 writes the
+differences.  The problems run on periodic grids, except the advection-
+diffusion-reaction equation, which keeps the paper's homogeneous Neumann
+boundaries: on its cell-centred grid the ghost value beyond a boundary face
+equals the cell inside it (a reading: the paper does not state its grid or
+boundary discretisation), so the boundary rows of the second difference read
+(u_1 - u_0)/dx^2 and those of the first difference (u_1 - u_0)/(2 dx).  Sec. 1 writes the
 linearisation u_t = J(u^n) u + F(u^n); Sec. 2 and 4 apply J matrix-free.
 
 Reading of the Jacobian action: the paper computes J v "numerically" from RHS
@@ -41,6 +46,26 @@ def ddx(v, nx, ny, dx) -> np.ndarray:
 def ddy(v, nx, ny, dy) -> np.ndarray:
     V = _grid(v, nx, ny)
     return ((np.roll(V, -1, axis=0) - np.roll(V, 1, axis=0)) / (2.0 * dy)).ravel()
+
+
+def _neumann_neighbours(v, nx, ny):
+    """West, east, south and north values of every point with the boundary
+    cells' ghosts equal to the cells themselves (edge replication)."""
+    P = np.pad(_grid(v, nx, ny), 1, mode="edge")
+    return P[1:-1, :-2], P[1:-1, 2:], P[:-2, 1:-1], P[2:, 1:-1]
+
+
+def laplacian_neumann(v, nx, ny, dx, dy) -> np.ndarray:
+    """5-point Laplacian with homogeneous Neumann boundaries (cell-centred)."""
+    V = _grid(v, nx, ny)
+    w, e, s, n = _neumann_neighbours(v, nx, ny)
+    return ((w - 2.0 * V + e) / (dx * dx) + (s - 2.0 * V + n) / (dy * dy)).ravel()
+
+
+def grad_sum_neumann(v, nx, ny, dx, dy) -> np.ndarray:
+    """d_x v + d_y v by centred differences with homogeneous Neumann boundaries."""
+    w, e, s, n = _neumann_neighbours(v, nx, ny)
+    return ((e - w) / (2.0 * dx) + (n - s) / (2.0 * dy)).ravel()
 
 
 class Operator:
@@ -89,6 +114,12 @@ class Operator:
             out[0::2] = a1 * laplacian(U, nx, ny, dx, dy) - U * V * V + a * (1.0 - U)
             out[1::2] = a2 * laplacian(V, nx, ny, dx, dy) + U * V * V - (a + b) * V
             return out
+        if self.kind == "adr":
+            # Sec. 3: u_t = alpha Lap u + beta grad u + rate u (1 - u)(u - 1/2); the
+            # advection term read as beta (d_x u + d_y u)
+            alpha, beta, rate = p.coef
+            return (alpha * laplacian_neumann(u, nx, ny, dx, dy) + beta * grad_sum_neumann(u, nx, ny, dx, dy)
+                    + rate * u * (1.0 - u) * (u - 0.5))
         raise ValueError(self.kind)
 
     # --- Jacobian action J(state) v --------------------------------------
@@ -129,6 +160,11 @@ class Operator:
             # d/du of (u v^2 - (a + b) v) = v^2 ; d/dv = 2uv - (a + b)
             out[1::2] = a2 * laplacian(dv, nx, ny, dx, dy) + V * V * du + (2.0 * U * V - (a + b)) * dv
             return out
+        if self.kind == "adr":
+            alpha, beta, rate = p.coef
+            # d/du of u (1 - u)(u - 1/2) = -3u^2 + 3u - 1/2
+            return (alpha * laplacian_neumann(v, nx, ny, dx, dy) + beta * grad_sum_neumann(v, nx, ny, dx, dy)
+                    + rate * (-3.0 * s * s + 3.0 * s - 0.5) * v)
         raise ValueError(self.kind)
 
     def remainder(self, x, fu=None) -> np.ndarray:

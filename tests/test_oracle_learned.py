@@ -9,7 +9,7 @@ import pytest
 
 from oracle import features as F
 from oracle import mlp
-from workloads import advdiff_bump, allen_cahn_noise, burgers_sines
+from workloads import adr_neumann, advdiff_bump, allen_cahn_noise, burgers_sines
 from workloads.problems import Problem
 
 
@@ -71,6 +71,8 @@ def _features_by_loops(p, h, l):
     u = np.asarray(p.state, dtype=float)
 
     def at(i, j):
+        if p.kind == "adr":  # Neumann: a boundary cell is its own ghost neighbour
+            return u[min(max(j, 0), ny - 1) * nx + min(max(i, 0), nx - 1)]
         return u[(j % ny) * nx + (i % nx)]
 
     rs, gs = [], []
@@ -78,13 +80,20 @@ def _features_by_loops(p, h, l):
         for i in range(nx):
             if p.kind == "allencahn":
                 rs.append(1 - 3 * at(i, j) ** 2)
+            elif p.kind == "adr":
+                c = at(i, j)
+                rs.append(p.coef[2] * (3 * c - 3 * c * c - 0.5))
             else:  # burgers
                 rs.append(-((at(i + 1, j) - at(i - 1, j)) / (2 * p.dx) + (at(i, j + 1) - at(i, j - 1)) / (2 * p.dy)))
             gs.append(math.hypot((at(i + 1, j) - at(i - 1, j)) / 2, (at(i, j + 1) - at(i, j - 1)) / 2))
     D = p.coef[0]
     sigma = D * (1 / p.dx ** 2 + 1 / p.dy ** 2)
     umax = max(abs(x) for x in u)
-    A = umax * (1 / p.dx + 1 / p.dy) if p.kind == "burgers" else 0.0
+    A = 0.0
+    if p.kind == "burgers":
+        A = umax * (1 / p.dx + 1 / p.dy)
+    elif p.kind == "adr":
+        A = abs(p.coef[1]) * (1 / p.dx + 1 / p.dy)
     mean = sum(u) / len(u)
     std = math.sqrt(sum((x - mean) ** 2 for x in u) / len(u))
     rmax, rmin = max(rs), min(rs)
@@ -95,9 +104,14 @@ def _features_by_loops(p, h, l):
             math.log10(1 + h * sigma), 0.0]
 
 
-@pytest.mark.parametrize("kind", ["allencahn", "burgers"])
+@pytest.mark.parametrize("kind", ["allencahn", "burgers", "adr"])
 def test_features_match_pointwise_loops(kind):
-    p = allen_cahn_noise(12, eps=3e-3, seed=9) if kind == "allencahn" else burgers_sines(16, nu=2e-3, seed=9)
+    if kind == "allencahn":
+        p = allen_cahn_noise(12, eps=3e-3, seed=9)
+    elif kind == "adr":
+        p = adr_neumann(14, alpha=1e-2, amp=0.05, seed=9)
+    else:
+        p = burgers_sines(16, nu=2e-3, seed=9)
     h = 7.0 * p.h_cfl
     np.testing.assert_allclose(F.features(p, h, 2), _features_by_loops(p, h, 2), rtol=1e-13, atol=1e-15)
 

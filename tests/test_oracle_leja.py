@@ -9,12 +9,14 @@ import numpy as np
 import pytest
 
 import oracle.leja as leja
-from oracle.exact import advdiff_symbol, diag_closed_form, fourier_closed_form, phi_dense
+from oracle.exact import (advdiff_symbol, dct_closed_form, diag_closed_form, fourier_closed_form,
+                          neumann_diffusion_eigs, phi_dense)
 from oracle.integrators import rk_reference, step
 from oracle.leja import Options, phi_action, phi_vertical
 from oracle.operators import Operator
 from oracle.phi import phi
-from workloads import advdiff_bump, allen_cahn_noise, brusselator_perturbed, diag_problem, gray_scott_spots
+from workloads import (adr_neumann, advdiff_bump, allen_cahn_noise, brusselator_perturbed, diag_problem,
+                       gray_scott_spots)
 from workloads.problems import Problem
 
 
@@ -63,7 +65,23 @@ def test_fourier_matches_dense_pade(cfg1):
     assert rel(ref_f, ref_d) <= 1e-13
 
 
-@pytest.mark.parametrize("kind", ["allencahn", "brusselator", "burgers", "grayscott"])
+@pytest.mark.parametrize("l", [1, 2])
+def test_dct_closed_form_neumann_diffusion(l):
+    # pure diffusion with homogeneous Neumann boundaries (cell-centred): the
+    # 2D DCT-II diagonalises J
+    nx, ny, dx, dy, alpha = 32, 24, 1 / 32, 1 / 24, 1e-2
+    p = Problem("adr", nx, ny, 1, dx, dy, (alpha, 0.0, 0.0), np.zeros(nx * ny), dx * dx / (4 * alpha))
+    op = Operator(p)
+    v = np.random.default_rng(3).uniform(0, 1, p.n)
+    h = 10 * p.h_cfl
+    ref = dct_closed_form(neumann_diffusion_eigs(nx, ny, dx, dy, alpha), v, l, h)
+    w, st = phi_action(op, v, l, h, 1e-10)
+    assert st.converged and rel(w, ref) <= 1e-9
+    w, st = phi_action(op, v, l, h, 1e-14)
+    assert st.converged and rel(w, ref) <= 1e-12
+
+
+@pytest.mark.parametrize("kind", ["allencahn", "brusselator", "burgers", "grayscott", "adr"])
 @pytest.mark.parametrize("l", [0, 1, 3])
 def test_dense_pade_small_grids(kind, l):
     if kind == "allencahn":
@@ -75,6 +93,9 @@ def test_dense_pade_small_grids(kind, l):
         p = brusselator_perturbed(12, D=0.1, seed=8, amp=0.3)
     elif kind == "grayscott":
         p = gray_scott_spots(12, a1=2e-2, a2=1e-2, amp=0.05)
+    elif kind == "adr":
+        # grid Peclet |beta| dx / alpha < 2 (real spectrum), strong reaction
+        p = adr_neumann(12, alpha=0.1, beta=-1.0, rate=100.0, amp=0.05)
     else:
         # grid Peclet ~1.25: diffusion-dominated like the 2048^2 workload
         p = Problem("burgers", 16, 16, 1, 1 / 16, 1 / 16, (5e-2,),

@@ -29,6 +29,21 @@ def _d1(n, h):
     return (D / (2 * h)).tocsr()
 
 
+def _d2n(n, h):
+    # homogeneous Neumann, cell-centred: ghost u_{-1} = u_0, u_n = u_{n-1}
+    e = np.ones(n)
+    d = -2 * e
+    d[0] = d[-1] = -1.0
+    return (sp.diags([e[:-1], d, e[:-1]], [-1, 0, 1], shape=(n, n)) / (h * h)).tocsr()
+
+
+def _d1n(n, h):
+    e = np.ones(n)
+    d = np.zeros(n)
+    d[0], d[-1] = -1.0, 1.0
+    return (sp.diags([-e[:-1], d, e[:-1]], [-1, 0, 1], shape=(n, n)) / (2 * h)).tocsr()
+
+
 def _kron_ops(nx, ny, dx, dy):
     Ix, Iy = sp.identity(nx), sp.identity(ny)
     lap = sp.kron(Iy, _d2(nx, dx)) + sp.kron(_d2(ny, dy), Ix)
@@ -52,10 +67,12 @@ def _small(kind, nx=7, ny=5):
     if kind == "grayscott":
         return Problem(kind, nx, ny, 2, dx, dy, (0.02, 0.007, 0.04, 0.06),
                        rng.uniform(0.0, 1.0, 2 * nx * ny), 1.0)
+    if kind == "adr":
+        return Problem(kind, nx, ny, 1, dx, dy, (0.03, -1.7, 9.0), rng.uniform(-0.2, 1.2, nx * ny), 1.0)
     raise ValueError(kind)
 
 
-@pytest.mark.parametrize("kind", ["advdiff", "allencahn", "burgers", "brusselator", "grayscott"])
+@pytest.mark.parametrize("kind", ["advdiff", "allencahn", "burgers", "brusselator", "grayscott", "adr"])
 def test_jacobian_matches_kronecker_assembly(kind):
     p = _small(kind)
     op = Operator(p)
@@ -80,6 +97,14 @@ def test_jacobian_matches_kronecker_assembly(kind):
         blk[1::2, 0::2] = np.diag(b - 2 * U * V)
         blk[1::2, 1::2] = Dv * lap - np.diag(U * U)
         ref = blk
+    elif kind == "adr":
+        # Neumann boundaries: Kronecker sums of the 1D Neumann differences
+        alpha, beta, rate = p.coef
+        Ix, Iy = sp.identity(p.nx), sp.identity(p.ny)
+        lapn = (sp.kron(Iy, _d2n(p.nx, p.dx)) + sp.kron(_d2n(p.ny, p.dy), Ix)).toarray()
+        grad = (sp.kron(Iy, _d1n(p.nx, p.dx)) + sp.kron(_d1n(p.ny, p.dy), Ix)).toarray()
+        u = p.state
+        ref = alpha * lapn + beta * grad + np.diag(rate * (-3 * u * u + 3 * u - 0.5))
     else:  # Gray-Scott: partial derivatives of -u v^2 + a(1 - u) and u v^2 - (a + b) v
         a1, a2, a, b = p.coef
         U, V = p.state[0::2], p.state[1::2]
@@ -93,7 +118,7 @@ def test_jacobian_matches_kronecker_assembly(kind):
     assert np.max(np.abs(J - ref)) <= 1e-12 * np.max(np.abs(ref))
 
 
-@pytest.mark.parametrize("kind", ["allencahn", "burgers", "brusselator", "grayscott"])
+@pytest.mark.parametrize("kind", ["allencahn", "burgers", "brusselator", "grayscott", "adr"])
 def test_jacobian_is_derivative_of_rhs(kind):
     p = _small(kind)
     op = Operator(p)
@@ -128,6 +153,38 @@ def test_gray_scott_trivial_state_is_fixed_point():
     st = np.empty(2 * p.nx * p.ny)
     st[0::2], st[1::2] = 1.0, 0.0
     assert np.max(np.abs(Operator(p).rhs(st))) == 0.0
+
+
+def test_adr_constant_roots_are_fixed_points():
+    # u = 0, 1/2, 1 are roots of the reaction; Neumann differences of a constant vanish
+    p = _small("adr")
+    op = Operator(p)
+    for c in (0.0, 0.5, 1.0):
+        assert np.max(np.abs(op.rhs(np.full(p.n, c)))) == 0.0
+
+
+def test_adr_neumann_conserves_mass_without_advection_and_reaction():
+    # with ghost = boundary cell, the Neumann Laplacian's columns sum to zero
+    p = _small("adr")
+    p.coef = (0.03, 0.0, 0.0)
+    v = np.random.default_rng(4).standard_normal(p.n)
+    jv = Operator(p).jv(v)
+    assert abs(jv.sum()) <= 1e-12 * np.abs(jv).sum()
+
+
+def test_neumann_diffusion_dct_modes_are_eigenvectors():
+    # J cos(pi kx (i + 1/2)/nx) cos(pi ky (j + 1/2)/ny) = lam[ky, kx] (same mode):
+    # pins the Neumann boundary rows against the closed form used by the action pins
+    from oracle.exact import neumann_diffusion_eigs
+    p = _small("adr", 8, 6)
+    p.coef = (0.03, 0.0, 0.0)
+    op = Operator(p)
+    lam = neumann_diffusion_eigs(p.nx, p.ny, p.dx, p.dy, 0.03)
+    I, Jg = np.meshgrid(np.arange(p.nx), np.arange(p.ny), indexing="xy")
+    for a in range(p.ny):
+        for b in range(p.nx):
+            mode = (np.cos(np.pi * b * (I + 0.5) / p.nx) * np.cos(np.pi * a * (Jg + 0.5) / p.ny)).ravel()
+            assert np.allclose(op.jv(mode), lam[a, b] * mode, atol=1e-10 * max(1.0, abs(lam[a, b])))
 
 
 def test_advdiff_fourier_modes_are_eigenvectors():

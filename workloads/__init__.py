@@ -7,6 +7,7 @@ their inputs from it without sharing any computation.
 """
 from .problems import (  # noqa: F401
     Problem,
+    adr_neumann,
     advdiff_bump,
     allen_cahn_noise,
     brusselator_perturbed,

@@ -1,9 +1,11 @@
 """Seeded problem instances for the Leja phi-action workloads.
 
-Every instance is a periodic 2D grid problem of one of the families the paper
-uses as test problems (Section 3: advection-diffusion, Allen-Cahn, Brusselator;
-Burgers and a diagonal operator are added as a fifth family and as a closed-form
-check).  Grids are row-major with x fastest; two-component states are
+Every instance is a 2D grid problem of one of the families the paper uses as
+test problems (Section 3: advection-diffusion, Allen-Cahn, Brusselator,
+Gray-Scott, and the advection-diffusion-reaction equation, the last with
+homogeneous Neumann boundaries on a cell-centred grid, the others periodic;
+Burgers and a diagonal operator are added as a further family and as a
+closed-form check).  Grids are row-major with x fastest; two-component states are
 interleaved (u, v) per grid point.
 
 Only random draws and parameter bookkeeping live here: the operators, the
@@ -16,12 +18,13 @@ from dataclasses import dataclass, field
 
 import numpy as np
 
-KINDS = ("diag", "advdiff", "allencahn", "brusselator", "burgers", "grayscott")
+KINDS = ("diag", "advdiff", "allencahn", "brusselator", "burgers", "grayscott", "adr")
 
 
 @dataclass
 class Problem:
-    """A linearisation point of one PDE family on a periodic grid.
+    """A linearisation point of one PDE family on a 2D grid (periodic; 'adr':
+    homogeneous Neumann boundaries, cell-centred).
 
     kind   : one of KINDS
     nx, ny : grid points per axis
@@ -134,6 +137,23 @@ def gray_scott_spots(n: int = 1024, a1: float = 1e-3, a2: float = 1e-3, a: float
         st += amp * _rng(seed).uniform(-1.0, 1.0, size=st.shape)
     D = max(a1, a2)
     return Problem("grayscott", n, n, 2, dx, dx, (a1, a2, a, b), st.ravel(), dx * dx / (4.0 * D))
+
+
+def adr_neumann(n: int = 256, alpha: float = 1e-2, beta: float = -10.0, rate: float = 100.0,
+                seed: int = 9, amp: float = 0.0) -> Problem:
+    """Advection-diffusion-reaction u_t = alpha Lap u + beta (d_x + d_y) u + rate u (1 - u)(u - 1/2)
+    on [0,1]^2 with homogeneous Neumann boundaries (Sec. 3), on the cell-centred
+    grid x_i = (i + 1/2)/n, with the initial state of Sec. 3,
+    u = 256 (x y (1 - x)(1 - y))^2 + 0.3, plus amp U[-1,1] noise (seeded).
+    coef = (alpha, beta, rate)."""
+    dx = 1.0 / n
+    x = (np.arange(n) + 0.5) * dx
+    X, Y = np.meshgrid(x, x)  # row = y, column = x
+    u = 256.0 * (X * Y * (1.0 - X) * (1.0 - Y)) ** 2 + 0.3
+    if amp > 0.0:
+        u = u + amp * _rng(seed).uniform(-1.0, 1.0, size=u.shape)
+    return Problem("adr", n, n, 1, dx, dx, (alpha, beta, rate), u.ravel().astype(np.float64),
+                   dx * dx / (4.0 * alpha))
 
 
 def burgers_sines(n: int = 2048, nu: float = 1e-3, seed: int = 5, modes: int = 8) -> Problem:
