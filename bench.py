@@ -17,7 +17,8 @@ Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
                          phi_1..phi_3 per instance in one graph-captured launch,
                          against the per-instance plain path)
        python bench.py --form sweep   (the other workloads: advection-diffusion 32^2,
-                        Brusselator 1024^2 and Gray-Scott 1024^2 steps,
+                        Brusselator 1024^2 and Gray-Scott 1024^2 steps, an
+                        advection-diffusion-reaction 512^2 step (Neumann),
                         Allen-Cahn 1024^2..8192^2)
        python bench.py --form adaptive   (variable step sizes, EPIRK4s3 on 512^2 Allen-Cahn)
        python bench.py --copy-calibration   (plain copy kernel for counter scaling)
@@ -185,14 +186,15 @@ def bench_sweep(args):
     """The other measured workloads, one JSON line each (not the headline
     metric): advection-diffusion 32^2 phi_1 (latency: us per action), the
     Brusselator 1024^2 (EXPRB43-u3 steps + a stand-alone phi_2), Gray-Scott
-    1024^2 (EPIRK4s3 steps), and phi_1 on Allen-Cahn grids from 1024^2 to
+    1024^2 (EPIRK4s3 steps), advection-diffusion-reaction 512^2 with Neumann
+    boundaries (EPIRK4s3 steps), and phi_1 on Allen-Cahn grids from 1024^2 to
     8192^2 (the HBM-bound regime)."""
     import statistics
 
     import torch
 
     import paper_2211_08948_amd as lj
-    from workloads import advdiff_bump, allen_cahn_noise, brusselator_perturbed, gray_scott_spots
+    from workloads import adr_neumann, advdiff_bump, allen_cahn_noise, brusselator_perturbed, gray_scott_spots
     ctx = lj.Context(0)
 
     def timed(fn, reps):
@@ -263,6 +265,19 @@ def bench_sweep(args):
     line("gray-scott 1024x1024 periodic, a1 = a2 = 1e-3, a 0.04, b 0.06, spot initial state, h 10x CFL, "
          "tol 1e-10: one EPIRK4s3 step (5 actions)", "\u03c6_l(hJ)v actions/sec", 5 / dt, "phi-actions/s",
          dt * 1e3, tm, 2, {"m_star": [s["m_star"][:3] for s in s4]})
+
+    # advection-diffusion-reaction 512^2 (Sec. 3, Neumann boundaries, its initial
+    # state; alpha 1e-2, beta -10, rate 100): one EPIRK4s3 step
+    prob = adr_neumann(512, alpha=1e-2, beta=-10.0, rate=100.0)
+    op = lj.operator_from(prob, "cuda:0")
+    h = CFL_MULT * prob.h_cfl
+    u_out = torch.empty(prob.n, dtype=torch.float64, device="cuda:0")
+    err = torch.empty_like(u_out)
+    dt, tm, s5 = timed(lambda: lj.lj_step(ctx, "EPIRK4S3", op, h, TOL, u_out, err)[1], 20)
+    line("advection-diffusion-reaction 512x512, homogeneous Neumann, alpha 1e-2, beta -10, rate 100, "
+         "initial state 256(xy(1-x)(1-y))^2 + 0.3, h 10x CFL, tol 1e-10: one EPIRK4s3 step (5 actions)",
+         "\u03c6_l(hJ)v actions/sec", 5 / dt, "phi-actions/s", dt * 1e3, tm, 1,
+         {"m_star": [s["m_star"][:3] for s in s5]})
 
     # Allen-Cahn n^2, phi_1 of h f(u) at 10x CFL, bound given (Newton recurrence only)
     for n in (1024, 2048, 4096, 8192):

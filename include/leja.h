@@ -53,8 +53,8 @@ extern "C" {
 
 typedef struct lj_context lj_context;
 
-/* Operator families (Sec. 3 test problems on periodic grids, 2nd-order centred
- * differences).  coef[] meaning per kind:
+/* Operator families (Sec. 3 test problems, 2nd-order centred differences; the
+ * grids are periodic except for LJ_OP_ADR2D).  coef[] meaning per kind:
  *   LJ_OP_DIAG          J = diag(state); nx = n, ny = 1; coef unused
  *   LJ_OP_ADVDIFF2D     J = nu Lap - ax d/dx - ay d/dy;  coef = {nu, ax, ay}; state NULL
  *   LJ_OP_ALLENCAHN2D   f = eps Lap u + u - u^3, J = eps Lap + diag(1 - 3u^2); coef = {eps}
@@ -64,6 +64,11 @@ typedef struct lj_context lj_context;
  *                       coef = {nu}
  *   LJ_OP_GRAYSCOTT2D   f = (a1 Lap u - u v^2 + a(1 - u), a2 Lap v + u v^2 - (a + b) v),
  *                       ncomp = 2, coef = {a1, a2, a, b} (Sec. 3)
+ *   LJ_OP_ADR2D         f = alpha Lap u + beta (d/dx + d/dy) u + rate u (1 - u)(u - 1/2),
+ *                       J = alpha Lap + beta (d/dx + d/dy) + diag(rate (-3u^2 + 3u - 1/2));
+ *                       coef = {alpha, beta, rate} (Sec. 3, advection-diffusion-reaction).
+ *                       Homogeneous Neumann boundaries on a cell-centred grid: the
+ *                       ghost value beyond a boundary face equals the cell inside it.
  * J is the exact Jacobian of the semi-discrete right-hand side at `state`. */
 typedef enum {
   LJ_OP_DIAG = 0,
@@ -71,7 +76,8 @@ typedef enum {
   LJ_OP_ALLENCAHN2D = 2,
   LJ_OP_BRUSSELATOR2D = 3,
   LJ_OP_BURGERS2D = 4,
-  LJ_OP_GRAYSCOTT2D = 5
+  LJ_OP_GRAYSCOTT2D = 5,
+  LJ_OP_ADR2D = 6
 } lj_op_kind;
 
 typedef struct {

@@ -19,7 +19,8 @@ LJ_NFEATURES = 16
 LJ_MLP_NPARAM = 5378
 LJ_MLP_MODEL_FLOATS = 5414
 
-LJ_OP_DIAG, LJ_OP_ADVDIFF2D, LJ_OP_ALLENCAHN2D, LJ_OP_BRUSSELATOR2D, LJ_OP_BURGERS2D, LJ_OP_GRAYSCOTT2D = range(6)
+(LJ_OP_DIAG, LJ_OP_ADVDIFF2D, LJ_OP_ALLENCAHN2D, LJ_OP_BRUSSELATOR2D, LJ_OP_BURGERS2D, LJ_OP_GRAYSCOTT2D,
+ LJ_OP_ADR2D) = range(7)
 LJ_EXPRB2, LJ_EXPRB43_U3, LJ_EXPRB43, LJ_EPIRK4S3 = 1, 2, 3, 4
 
 

@@ -5,7 +5,19 @@
 
 namespace lj {
 
-enum OpKind { OP_DIAG = 0, OP_ADVDIFF = 1, OP_ALLENCAHN = 2, OP_BRUSSELATOR = 3, OP_BURGERS = 4, OP_GRAYSCOTT = 5 };
+enum OpKind {
+  OP_DIAG = 0,
+  OP_ADVDIFF = 1,
+  OP_ALLENCAHN = 2,
+  OP_BRUSSELATOR = 3,
+  OP_BURGERS = 4,
+  OP_GRAYSCOTT = 5,
+  OP_ADR = 6
+};
+
+// families with homogeneous Neumann boundaries (cell-centred grid: the ghost
+// beyond a boundary face holds the cell inside it); the others are periodic
+constexpr bool family_neumann(int kind) { return kind == OP_ADR; }
 
 // default bound on the polls of one grid-barrier wait (see wait_at_least)
 constexpr unsigned int kGridSpinLimit = 1u << 22;

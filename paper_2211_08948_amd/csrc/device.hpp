@@ -12,7 +12,9 @@
 namespace lj {
 
 // ---------------------------------------------------------------------------
-// Stencils.  Sec. 3: centred second-order differences; the grids are periodic.
+// Stencils.  Sec. 3: centred second-order differences; the grids are periodic
+// except for the Neumann families (family_neumann), whose boundary cells are
+// their own ghost neighbours.
 // Point p = j*nx + i; components of a two-component state are interleaved.
 //
 // stencil_jv evaluates (J x) at one point from values: x at the centre and the
@@ -55,6 +57,12 @@ __device__ __forceinline__ void stencil_jv(const OpDev& op, const double (&x)[5]
     // d/du (u v^2 - (a + b) v) = v^2,  d/dv = 2uv - (a + b)
     out[1] = a2 * lap5(op, x[0][1], x[1][1], x[2][1], x[3][1], x[4][1]) + V * V * x[0][0] +
              (2.0 * U * V - (a + b)) * x[0][1];
+  } else if constexpr (KIND == OP_ADR) {
+    // alpha Lap x + beta (d_x + d_y) x + rate (-3u^2 + 3u - 1/2) x
+    const double uc = u[0][0];
+    out[0] = op.c0 * lap5(op, x[0][0], x[1][0], x[2][0], x[3][0], x[4][0]) +
+             op.c1 * ((x[2][0] - x[1][0]) * op.i2dx + (x[4][0] - x[3][0]) * op.i2dy) +
+             op.c2 * (uc * (3.0 - 3.0 * uc) - 0.5) * x[0][0];
   } else {  // OP_BURGERS: nu Lap x - (d/dx + d/dy)(u x)
     const double qe = u[2][0] * x[2][0], qw = u[1][0] * x[1][0];
     const double qn = u[4][0] * x[4][0], qs = u[3][0] * x[3][0];
@@ -73,16 +81,18 @@ struct Nbr {
   int c, w, e, s, n;  // flat point indices of centre and the four neighbours
 };
 
+template <int KIND>
 __device__ __forceinline__ Nbr neighbours(const OpDev& op, int p) {
   const int nx = op.nx, ny = op.ny;
   const int j = p / nx;
   const int i = p - j * nx;
+  constexpr bool neu = family_neumann(KIND);
   Nbr r;
   r.c = p;
-  r.w = (i == 0) ? p + nx - 1 : p - 1;
-  r.e = (i == nx - 1) ? p - nx + 1 : p + 1;
-  r.s = (j == 0) ? p + (ny - 1) * nx : p - nx;
-  r.n = (j == ny - 1) ? p - (ny - 1) * nx : p + nx;
+  r.w = (i == 0) ? (neu ? p : p + nx - 1) : p - 1;
+  r.e = (i == nx - 1) ? (neu ? p : p - nx + 1) : p + 1;
+  r.s = (j == 0) ? (neu ? p : p + (ny - 1) * nx) : p - nx;
+  r.n = (j == ny - 1) ? (neu ? p : p - (ny - 1) * nx) : p + nx;
   return r;
 }
 
@@ -100,7 +110,7 @@ __device__ __forceinline__ void gather_point(const OpDev& op, const double* __re
     xv[0][0] = x[p];
     uv[0][0] = op.state[p];
   } else {
-    const Nbr q = neighbours(op, p);
+    const Nbr q = neighbours<KIND>(op, p);
     const int idx[5] = {q.c, q.w, q.e, q.s, q.n};
 #pragma unroll
     for (int t = 0; t < 5; ++t) {
@@ -150,6 +160,9 @@ __device__ __forceinline__ void rhs_values(const OpDev& op, const double (&x)[5]
       out[0] = op.c0 * lap5(op, c, w, e, s, n) - op.c1 * ((e - w) * op.i2dx) - op.c2 * ((n - s) * op.i2dy);
     } else if constexpr (KIND == OP_ALLENCAHN) {
       out[0] = op.c0 * lap5(op, c, w, e, s, n) + c - c * c * c;
+    } else if constexpr (KIND == OP_ADR) {
+      out[0] = op.c0 * lap5(op, c, w, e, s, n) + op.c1 * ((e - w) * op.i2dx + (n - s) * op.i2dy) +
+               op.c2 * (c * (1.0 - c) * (c - 0.5));
     } else {  // OP_BURGERS: nu Lap u - (1/2)(d/dx + d/dy)(u^2)
       out[0] = op.c0 * lap5(op, c, w, e, s, n) - 0.5 * ((e * e - w * w) * op.i2dx + (n * n - s * s) * op.i2dy);
     }
@@ -164,7 +177,7 @@ __device__ __forceinline__ void gather_x(const OpDev& op, const double* __restri
   if constexpr (KIND == OP_DIAG) {
     xv[0][0] = x[p];
   } else {
-    const Nbr q = neighbours(op, p);
+    const Nbr q = neighbours<KIND>(op, p);
     const int idx[5] = {q.c, q.w, q.e, q.s, q.n};
 #pragma unroll
     for (int t = 0; t < 5; ++t)

@@ -580,11 +580,17 @@ __global__ __launch_bounds__(kBlock) void lj_action_stream(ActionParams P) {
 // LDS-tiled action kernel with temporal blocking: one tile per block, one
 // owned point per thread, scalar families whose Jacobian reads the state at
 // the centre only.  EPT: extended (tile + halo) points per thread.
+// Neumann families: extended points outside the domain are ghosts held at
+// zero in both buffers, and a boundary cell's coefficient towards its ghost
+// is folded into its diagonal (the ghost equals the cell itself), so every
+// in-domain point stays exact through the super-step.
 // ===========================================================================
 template <int KIND, int S, int EPT>
 __global__ __launch_bounds__(kBlock) void lj_action_tile(ActionParams P) {
   const GridSync gsync{P.barrier, P.spin_limit};
-  static_assert(KIND == OP_ADVDIFF || KIND == OP_ALLENCAHN, "tiled kernel: scalar centre-state families");
+  static_assert(KIND == OP_ADVDIFF || KIND == OP_ALLENCAHN || KIND == OP_ADR,
+                "tiled kernel: scalar centre-state families");
+  constexpr bool kNeumann = family_neumann(KIND);
   extern __shared__ double lds[];
   __shared__ ActionShared sh;
   const OpDev& op = P.op;
@@ -614,10 +620,16 @@ __global__ __launch_bounds__(kBlock) void lj_action_tile(ActionParams P) {
   // instead of thirteen -- the same polynomial in J, rounded in another order.
   int e_xy[EPT];
   double e_d[EPT];
+  bool ghost[EPT];  // outside the domain (Neumann families only)
   double fw, fe, fs, fn;
   if constexpr (KIND == OP_ALLENCAHN) {
     fw = fe = op.c0 * op.idx2;
     fs = fn = op.c0 * op.idy2;
+  } else if constexpr (KIND == OP_ADR) {  // alpha Lap x + beta (d_x + d_y) x (centred)
+    fw = op.c0 * op.idx2 - op.c1 * op.i2dx;
+    fe = op.c0 * op.idx2 + op.c1 * op.i2dx;
+    fs = op.c0 * op.idy2 - op.c1 * op.i2dy;
+    fn = op.c0 * op.idy2 + op.c1 * op.i2dy;
   } else {  // advection-diffusion: nu Lap x - a_x d_x x - a_y d_y x (centred)
     fw = op.c0 * op.idx2 + op.c1 * op.i2dx;
     fe = op.c0 * op.idx2 - op.c1 * op.i2dx;
@@ -637,10 +649,21 @@ __global__ __launch_bounds__(kBlock) void lj_action_tile(ActionParams P) {
   for (int k = 0; k < EPT; ++k) {
     const int e = threadIdx.x + k * kBlock;
     const int ey = e / EW;
-    e_xy[k] = (e - ey * EW) | (ey << 16);
+    const int ex = e - ey * EW;
+    e_xy[k] = ex | (ey << 16);
+    const int ux = x0 - S + ex, uy = y0 - S + ey;  // unwrapped grid coordinates
+    ghost[k] = kNeumann && (ux < 0 || ux >= nx || uy < 0 || uy >= ny);
     if constexpr (KIND == OP_ALLENCAHN) {
       const double u = (e < NE) ? op.state[gidx(k)] : 0.0;
       e_d[k] = d_lap + (1.0 - 3.0 * u * u);
+    } else if constexpr (KIND == OP_ADR) {
+      const double u = (e < NE && !ghost[k]) ? op.state[gidx(k)] : 0.0;
+      double d = d_lap + op.c2 * (u * (3.0 - 3.0 * u) - 0.5);
+      if (ux == 0) d += fw;
+      if (ux == nx - 1) d += fe;
+      if (uy == 0) d += fs;
+      if (uy == ny - 1) d += fn;
+      e_d[k] = d;
     } else {
       e_d[k] = d_lap;
     }
@@ -671,6 +694,10 @@ __global__ __launch_bounds__(kBlock) void lj_action_tile(ActionParams P) {
     for (int k = 0; k < EPT; ++k) {
       const int e = threadIdx.x + k * kBlock;
       if (e >= NE) continue;
+      if (kNeumann && ghost[k]) {
+        dst[e] = 0.0;
+        continue;
+      }
       const int ex = e_xy[k] & 0xffff, ey = e_xy[k] >> 16;
       if (ex < j || ex >= EW - j || ey < j || ey >= EH - j) continue;
       const double xc = src[e], xw = src[e - 1], xe = src[e + 1], xs = src[e - EW], xn = src[e + EW];
@@ -698,7 +725,7 @@ __global__ __launch_bounds__(kBlock) void lj_action_tile(ActionParams P) {
 #pragma unroll
     for (int k = 0; k < EPT; ++k) {
       const int e = threadIdx.x + k * kBlock;
-      hv[k] = (e < NE && !inner(k)) ? g[gidx(k)] : 0.0;
+      hv[k] = (e < NE && !inner(k) && !ghost[k]) ? g[gidx(k)] : 0.0;
     }
   };
   auto put_halo = [&](double scale) {
@@ -747,7 +774,7 @@ __global__ __launch_bounds__(kBlock) void lj_action_tile(ActionParams P) {
       const int e = threadIdx.x + k * kBlock;
       if (e >= NE) continue;
       const int g = gidx(k);
-      Y(0)[e] = P.start ? P.start[g] : 0.5 + splitmix_uniform(P.seed, (uint64_t)g);
+      Y(0)[e] = ghost[k] ? 0.0 : (P.start ? P.start[g] : 0.5 + splitmix_uniform(P.seed, (uint64_t)g));
     }
     __syncthreads();
     int done = 0;
@@ -816,7 +843,7 @@ __global__ __launch_bounds__(kBlock) void lj_action_tile(ActionParams P) {
   dd_init(dd, K, P.l, P.s, P.max_points + 1, c, gamma, sh.xi, sh.coef, sh.fmax);
   double v_in[EPT];
 #pragma unroll
-  for (int k = 0; k < EPT; ++k) v_in[k] = ((int)threadIdx.x + k * kBlock < NE) ? P.v[gidx(k)] : 0.0;
+  for (int k = 0; k < EPT; ++k) v_in[k] = ((int)threadIdx.x + k * kBlock < NE && !ghost[k]) ? P.v[gidx(k)] : 0.0;
   dd_advance(dd, K, S, sh.xi, sh.coef);
   cur = 0;
 #pragma unroll
@@ -1207,7 +1234,7 @@ __global__ __launch_bounds__(256) void lj_stage_kernel(StageArgs A) {
   for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < op.npts; p += gridDim.x * blockDim.x) {
     int idx[5] = {p, p, p, p, p};
     if constexpr (KIND != OP_DIAG) {
-      const Nbr q = neighbours(op, p);
+      const Nbr q = neighbours<KIND>(op, p);
       idx[1] = q.w;
       idx[2] = q.e;
       idx[3] = q.s;
@@ -1330,6 +1357,7 @@ void* action_stream_ptr(int kind) {
     case OP_BRUSSELATOR: return reinterpret_cast<void*>(&lj_action_stream<OP_BRUSSELATOR, 2>);
     case OP_BURGERS: return reinterpret_cast<void*>(&lj_action_stream<OP_BURGERS, 1>);
     case OP_GRAYSCOTT: return reinterpret_cast<void*>(&lj_action_stream<OP_GRAYSCOTT, 2>);
+    case OP_ADR: return reinterpret_cast<void*>(&lj_action_stream<OP_ADR, 1>);
   }
   return nullptr;
 }
@@ -1346,6 +1374,12 @@ void* action_tile_ptr(int kind, int ept) {
       case 1: return reinterpret_cast<void*>(&lj_action_tile<OP_ADVDIFF, kMaxSuper, 1>);
       case 2: return reinterpret_cast<void*>(&lj_action_tile<OP_ADVDIFF, kMaxSuper, 2>);
       case 3: return reinterpret_cast<void*>(&lj_action_tile<OP_ADVDIFF, kMaxSuper, 3>);
+    }
+  } else if (kind == OP_ADR) {
+    switch (ept) {
+      case 1: return reinterpret_cast<void*>(&lj_action_tile<OP_ADR, kMaxSuper, 1>);
+      case 2: return reinterpret_cast<void*>(&lj_action_tile<OP_ADR, kMaxSuper, 2>);
+      case 3: return reinterpret_cast<void*>(&lj_action_tile<OP_ADR, kMaxSuper, 3>);
     }
   }
   return nullptr;
@@ -1365,6 +1399,7 @@ void* batch_kernel_ptr(int kind, int bs) {
     LJ_BATCH_CASE(OP_BRUSSELATOR, 2)
     LJ_BATCH_CASE(OP_BURGERS, 1)
     LJ_BATCH_CASE(OP_GRAYSCOTT, 2)
+    LJ_BATCH_CASE(OP_ADR, 1)
   }
 #undef LJ_BATCH_CASE
   return nullptr;
@@ -1402,6 +1437,7 @@ hipError_t launch_rhs(const OpDev& op, const double* u, double* f, hipStream_t s
     case OP_BRUSSELATOR: rhs_t<OP_BRUSSELATOR, 2>(op, u, f, s); break;
     case OP_BURGERS: rhs_t<OP_BURGERS, 1>(op, u, f, s); break;
     case OP_GRAYSCOTT: rhs_t<OP_GRAYSCOTT, 2>(op, u, f, s); break;
+    case OP_ADR: rhs_t<OP_ADR, 1>(op, u, f, s); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -1424,6 +1460,7 @@ hipError_t launch_rhs_scaled(const OpDev& op, double h, double* f, double* v, hi
     case OP_BRUSSELATOR: rhs_scaled_t<OP_BRUSSELATOR, 2>(op, h, f, v, s); break;
     case OP_BURGERS: rhs_scaled_t<OP_BURGERS, 1>(op, h, f, v, s); break;
     case OP_GRAYSCOTT: rhs_scaled_t<OP_GRAYSCOTT, 2>(op, h, f, v, s); break;
+    case OP_ADR: rhs_scaled_t<OP_ADR, 1>(op, h, f, v, s); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -1437,6 +1474,7 @@ hipError_t launch_stage(const StageArgs& A, hipStream_t s) {
     case OP_BRUSSELATOR: stage_t<OP_BRUSSELATOR, 2>(A, s); break;
     case OP_BURGERS: stage_t<OP_BURGERS, 1>(A, s); break;
     case OP_GRAYSCOTT: stage_t<OP_GRAYSCOTT, 2>(A, s); break;
+    case OP_ADR: stage_t<OP_ADR, 1>(A, s); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

@@ -167,7 +167,7 @@ void check_range(lj_context* ctx, const void* p, size_t bytes, const std::string
 
 OpDev make_op(lj_context* ctx, const lj_operator* J) {
   if (!J) invalid(ctx, "operator is NULL");
-  if (J->kind < LJ_OP_DIAG || J->kind > LJ_OP_GRAYSCOTT2D) invalid(ctx, "operator: unknown kind");
+  if (J->kind < LJ_OP_DIAG || J->kind > LJ_OP_ADR2D) invalid(ctx, "operator: unknown kind");
   if (J->nx < 1 || J->ny < 1) invalid(ctx, "operator: nx and ny must be >= 1");
   const int want_nc = family_ncomp(J->kind);
   if (J->ncomp != want_nc)

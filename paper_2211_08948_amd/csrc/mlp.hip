@@ -32,7 +32,7 @@ __device__ __forceinline__ void reaction_at(const OpDev& op, int p, double& u, d
   if constexpr (KIND == OP_DIAG || KIND == OP_ADVDIFF) {
     return;
   } else {
-    const Nbr q = neighbours(op, p);
+    const Nbr q = neighbours<KIND>(op, p);
     const double* s = op.state;
     u = s[NC * q.c];
     const double uw = s[NC * q.w], ue = s[NC * q.e], us = s[NC * q.s], un = s[NC * q.n];
@@ -42,6 +42,8 @@ __device__ __forceinline__ void reaction_at(const OpDev& op, int p, double& u, d
       r = 1.0 - 3.0 * u * u;
     } else if constexpr (KIND == OP_BURGERS) {
       r = -((ue - uw) * op.i2dx + (un - us) * op.i2dy);
+    } else if constexpr (KIND == OP_ADR) {  // d/du of rate u (1 - u)(u - 1/2)
+      r = op.c2 * (u * (3.0 - 3.0 * u) - 0.5);
     } else if constexpr (KIND == OP_GRAYSCOTT) {  // d/du of the first species' reaction
       const double v = s[NC * q.c + 1];
       r = -(v * v) - op.c2;
@@ -119,6 +121,7 @@ __global__ void lj_feature_finish(FeatureJob J, const FeatPartial* part, int npa
     sigma = D * (op.idx2 + op.idy2);
     if (op.kind == OP_ADVDIFF) A = fabs(op.c1) * 2.0 * op.i2dx + fabs(op.c2) * 2.0 * op.i2dy;
     if (op.kind == OP_BURGERS) A = P.umax * 2.0 * (op.i2dx + op.i2dy);
+    if (op.kind == OP_ADR) A = fabs(op.c1) * 2.0 * (op.i2dx + op.i2dy);
   }
   const double rmax = has_state ? P.rmax : 0.0, rmin = has_state ? P.rmin : 0.0;
   const double n = (double)op.npts;
@@ -445,6 +448,10 @@ hipError_t launch_features(const FeatureJob& J, FeatPartialBuf part, float* feat
       break;
     case OP_GRAYSCOTT:
       hipLaunchKernelGGL((lj_feature_partials<OP_GRAYSCOTT, 2>), dim3(nparts), dim3(256), 0, s, J.op,
+                         reinterpret_cast<FeatPartial*>(part));
+      break;
+    case OP_ADR:
+      hipLaunchKernelGGL((lj_feature_partials<OP_ADR, 1>), dim3(nparts), dim3(256), 0, s, J.op,
                          reinterpret_cast<FeatPartial*>(part));
       break;
     default:

@@ -70,6 +70,22 @@ def test_struct_layout_matches_c(tmp_path):
             assert int(out[f"{s}.{f}"]) == getattr(py[s], f).offset, (s, f)
 
 
+def test_enum_constants_match_c(tmp_path):
+    from paper_2211_08948_amd import _lib
+    names = ["LJ_OP_DIAG", "LJ_OP_ADVDIFF2D", "LJ_OP_ALLENCAHN2D", "LJ_OP_BRUSSELATOR2D", "LJ_OP_BURGERS2D",
+             "LJ_OP_GRAYSCOTT2D", "LJ_OP_ADR2D", "LJ_EXPRB2", "LJ_EXPRB43_U3", "LJ_EXPRB43", "LJ_EPIRK4S3",
+             "LJ_OK", "LJ_ENOTCONV", "LJ_EINVAL", "LJ_EHIP", "LJ_ENOMEM", "LJ_MAX_K", "LJ_MAX_L"]
+    prog = tmp_path / "en.c"
+    body = "".join(f'printf("{n} %d\\n", (int){n});' for n in names)
+    prog.write_text(f'#include <stdio.h>\n#include "{HEADER}"\nint main(void){{{body}return 0;}}\n')
+    exe = tmp_path / "en"
+    subprocess.run(["gcc", "-o", str(exe), str(prog)], check=True)
+    out = dict(l.rsplit(" ", 1) for l in subprocess.run([str(exe)], capture_output=True, text=True,
+                                                          check=True).stdout.split("\n") if l)
+    for n in names:
+        assert int(out[n]) == getattr(_lib, n), n
+
+
 def test_host_leja_table_matches_oracle(lib, xi101):
     # independent generators (grid search + Newton in C++, gap bisection in the
     # oracle) agree to a few ulps and in order

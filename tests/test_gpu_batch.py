@@ -14,7 +14,7 @@ from gpu_util import rel, say
 from oracle.leja import Options, phi_vertical
 from oracle.operators import Operator
 from oracle.power import power_iteration
-from workloads import allen_cahn_noise, batch_instances
+from workloads import adr_neumann, allen_cahn_noise, batch_instances
 
 pytestmark = pytest.mark.gpu
 TOL = 1e-10
@@ -65,6 +65,31 @@ def test_batch_matches_oracle_with_oracle_bound(env):
         assert st["m_star"] == so.m_star and st["substeps"] == so.substeps
         assert st["bound"] == bounds[i] and st["c"] == so.c and st["gamma"] == so.gamma
         assert st["power_iters"] == 0 and st["rejections"] == 0
+        for k in range(3):
+            assert rel(ws[i][k].cpu().numpy(), wo[k]) <= TOL
+    b.close()
+
+
+def test_batch_adr_neumann_matches_oracle(env):
+    # a batch of advection-diffusion-reaction instances (Neumann boundaries,
+    # Sec. 3 initial state plus noise, grid Peclet number <= 0.42), each side
+    # with its own power iteration
+    lj, torch, ctx = env
+    spec = [(24, 0.1), (37, 0.2), (48, 0.1), (31, 0.3)]
+    probs = [adr_neumann(n, alpha=a, beta=-1.0, rate=100.0, seed=50 + i, amp=0.02) for i, (n, a) in enumerate(spec)]
+    hs = [10.0 * p.h_cfl for p in probs]
+    vs = [h * Operator(p).rhs(p.state) for p, h in zip(probs, hs)]
+    b, ws, _ = make_batch(lj, torch, ctx, probs, hs, vs)
+    b.run()
+    rc, sts = b.stats()
+    assert rc == 0
+    for i, (p, h, v) in enumerate(zip(probs, hs, vs)):
+        wo, so = phi_vertical(Operator(p), v, LS, AS, h, TOL)
+        st = sts[i]
+        say("batch adr vs oracle", i, p.nx, st["m_star"], so.m_star, "s", st["substeps"], so.substeps,
+            "rej", st["rejections"], so.rejections, "iters", st["iters_total"], so.iters_total)
+        assert abs(st["bound"] - so.bound) <= 1e-12 * so.bound
+        assert st["m_star"] == so.m_star and st["substeps"] == so.substeps
         for k in range(3):
             assert rel(ws[i][k].cpu().numpy(), wo[k]) <= TOL
     b.close()

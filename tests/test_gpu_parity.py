@@ -7,13 +7,14 @@ import pytest
 
 from gpu_util import GpuRunner, rel, say
 from oracle.divdiff import divided_differences
+from oracle.exact import phi_dense
 from oracle.integrators import step as oracle_step
 from oracle.leja import Options, phi_action, phi_vertical
 from oracle.operators import Operator
 from oracle.phi import phi
 from oracle.points import leja_points
 from oracle.power import power_iteration
-from workloads import (advdiff_bump, allen_cahn_noise, brusselator_perturbed, burgers_sines,
+from workloads import (adr_neumann, advdiff_bump, allen_cahn_noise, brusselator_perturbed, burgers_sines,
                        diag_problem, gray_scott_spots)
 from workloads.problems import Problem
 
@@ -44,6 +45,10 @@ def small_problems():
         "brusselator": brusselator_perturbed(48, D=2e-2, seed=3),
         "burgers": burgers_sines(64, nu=3e-2, seed=5),
         "grayscott": gray_scott_spots(40, a1=2e-2, a2=1e-2, amp=0.02),
+        # Neumann boundaries, grid Peclet number ~0.1 (the advection-dominated,
+        # strongly non-normal case: test_noise_floor_regime_adr)
+        "adr": adr_neumann(96, alpha=0.1, beta=-1.0, rate=100.0, amp=0.02),
+        "adr_ragged": adr_neumann(37, alpha=0.3, beta=-1.0, rate=100.0, amp=0.02),
     }
 
 
@@ -372,6 +377,91 @@ def test_step_parity_gray_scott(gpu, scheme):
     assert rc == 0 and [s["m_star"][:len(b.m_star)] for s, b in zip(sts, log)] == [b.m_star for b in log]
     assert rel(u, u_orc) <= TOL
     assert np.linalg.norm(e - e_orc) <= 1e-8 * np.linalg.norm(e_orc) + 1e-12 * np.linalg.norm(u_orc)
+
+
+@pytest.mark.parametrize("scheme", ["EXPRB43", "EPIRK4S3"])
+def test_step_parity_adr(gpu, scheme):
+    # the advection-diffusion-reaction equation of Sec. 3 with its Neumann
+    # boundaries and its initial state, one step
+    prob = adr_neumann(64, alpha=0.1, beta=-10.0, rate=100.0)
+    op = Operator(prob)
+    h = 10 * prob.h_cfl
+    lam = power_iteration(op.jv, prob.n, 20)
+    u_orc, e_orc, log = oracle_step(op, scheme, h, TOL, Options(bound=lam))
+    say("step adr", scheme, [b.m_star for b in log])
+    rc, sts, u, e = gpu.step(prob, scheme, h, TOL, bound=lam)
+    assert rc == 0 and [s["m_star"][:len(b.m_star)] for s, b in zip(sts, log)] == [b.m_star for b in log]
+    assert rel(u, u_orc) <= TOL
+    assert np.linalg.norm(e - e_orc) <= 1e-8 * np.linalg.norm(e_orc) + 1e-12 * np.linalg.norm(u_orc)
+
+
+@pytest.mark.parametrize("env", [("LJ_NO_TILE", "1"), ("LJ_TILE", "16,16")])
+@pytest.mark.parametrize("name", ["adr", "adr_ragged"])
+def test_adr_parity_stream_and_small_tiles(env, name, monkeypatch):
+    # the Neumann boundary in the streaming kernel (neighbour index clamped)
+    # and in the tiled kernel with many tiles (ghost cells at the domain edge,
+    # ordinary halo cells between tiles); own power iteration on both sides
+    import paper_2211_08948_amd as lj
+    prob = small_problems()[name]
+    h = 10 * prob.h_cfl
+    v = _v_for(prob, h)
+    w_orc, st_orc = phi_action(Operator(prob), v, 1, h, TOL)
+    monkeypatch.setenv(*env)
+    r = GpuRunner()
+    monkeypatch.delenv(env[0])
+    try:
+        lj.lj_timing_read(r.ctx, reset=True)
+        lj.lj_timing_enable(r.ctx, True)
+        say("adr", name, env, st_orc.m_star, st_orc.substeps)
+        rc, st, w = r.action(prob, v, 1, h, TOL)
+        lj.lj_timing_enable(r.ctx, False)
+        tiled = lj.lj_timing_read(r.ctx, reset=True)["tiled_launches"]
+    finally:
+        r.ctx.close()
+    assert (tiled == 0) == (env[0] == "LJ_NO_TILE")
+    assert abs(st["bound"] - st_orc.bound) <= 1e-12 * st_orc.bound
+    assert st["m_star"] == st_orc.m_star and st["substeps"] == st_orc.substeps
+    assert rel(w, w_orc) <= TOL
+
+
+@pytest.mark.parametrize("n,alpha,beta,l", [(37, 0.1, -10.0, 0), (37, 0.1, -10.0, 1), (24, 0.1, -5.0, 1)])
+def test_noise_floor_regime_adr(gpu, n, alpha, beta, l):
+    """The paper's advection-dominated ADR coefficients on coarse grids (grid
+    Peclet number 2-3): J is strongly non-normal and the Newton basis grows
+    (||y_m|| reaches ~1e7 ||v||), so the stop test meets the divided
+    differences at their FP64 rounding floor (~1e-16 max|f|), and where the
+    first term dips under tol -- hence m*, the rejections and the substep
+    count -- is decided by rounding: the oracle itself changes its decisions
+    when its divided differences are perturbed at that level.  Unique here is
+    the action: both results must match dense Pade expm of the augmented
+    matrix within 10 s tol, s each side's substep count."""
+    prob = adr_neumann(n, alpha=alpha, beta=beta, rate=100.0, seed=50 if n == 24 else 9, amp=0.02)
+    op = Operator(prob)
+    h = 10 * prob.h_cfl
+    v = h * op.rhs(prob.state)
+    exact = phi_dense(h * op.dense(), v, l)
+    w_orc, st_orc = phi_action(op, v, l, h, TOL)
+    say("noise floor adr", n, beta, l, st_orc.m_star, st_orc.substeps)
+    rc, st, w = gpu.action(prob, v, l, h, TOL, bound=st_orc.bound)
+    say("  gpu", st["m_star"], st["substeps"], st["rejections"])
+    assert rc == 0 and st["converged"] and st_orc.converged
+    assert rel(w, exact) <= 10 * st["substeps"][0] * TOL
+    assert rel(w_orc, exact) <= 10 * st_orc.substeps[0] * TOL
+
+
+def test_action_parity_adr_512(gpu):
+    # 512^2, alpha = 1e-2, beta = -10, rate = 100 (grid Peclet 1.95), from the
+    # initial state of Sec. 3
+    prob = adr_neumann(512, alpha=1e-2, beta=-10.0, rate=100.0)
+    op = Operator(prob)
+    h = 10 * prob.h_cfl
+    v = h * op.rhs(prob.state)
+    lam = power_iteration(op.jv, prob.n, 20)
+    w_orc, st_orc = phi_action(op, v, 1, h, TOL, Options(bound=lam))
+    say("adr 512", st_orc.m_star)
+    rc, st, w = gpu.action(prob, v, 1, h, TOL, bound=lam)
+    assert rc == 0 and st["m_star"] == st_orc.m_star
+    assert rel(w, w_orc) <= TOL
 
 
 def test_step_parity_brusselator_full_size(gpu):

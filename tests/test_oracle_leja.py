@@ -323,3 +323,51 @@ def test_observed_order_allen_cahn():
             errs.append(np.linalg.norm(u1 - ref))
         rates = [np.log2(errs[i] / errs[i + 1]) for i in range(2)]
         assert rates[-1] >= order - 0.6, (scheme, errs, rates)
+
+
+# ------------------------------------------- rounding-decided stop decisions
+def _dd_noise(monkeypatch, seed):
+    """Adds FP64-rounding-sized noise (2e-16 max|f|, absolute) to every
+    divided-difference table the oracle forms."""
+    orig = leja.coefficients
+    rng = np.random.default_rng(seed)
+
+    def noisy(*a, **k):
+        d, fm = orig(*a, **k)
+        return np.asarray(d) + 2e-16 * fm * rng.standard_normal(len(d)), fm
+    monkeypatch.setattr(leja, "coefficients", noisy)
+
+
+def test_adr_advection_dominated_decisions_are_rounding_decided(monkeypatch):
+    # grid Peclet 2.08: the non-normal basis grows until the stop test meets
+    # the divided differences' rounding floor, so rounding-level changes move
+    # the substep count, while every result stays close to dense expm
+    p = adr_neumann(24, alpha=0.1, beta=-5.0, rate=100.0, seed=50, amp=0.02)
+    op = Operator(p)
+    h = 10 * p.h_cfl
+    v = h * op.rhs(p.state)
+    exact = phi_dense(h * op.dense(), v, 1)
+    seen = set()
+    for seed in (None, 1, 2, 3):
+        if seed is not None:
+            _dd_noise(monkeypatch, seed)
+        w, st = phi_action(op, v, 1, h, 1e-10)
+        seen.add(st.substeps[0])
+        assert st.converged and rel(w, exact) <= 10 * st.substeps[0] * 1e-10
+        monkeypatch.undo()
+    assert len(seen) >= 2
+
+
+def test_adr_near_normal_decisions_are_stable(monkeypatch):
+    # grid Peclet 0.1: the same perturbations leave every decision unchanged
+    p = adr_neumann(96, alpha=0.1, beta=-1.0, rate=100.0, amp=0.02)
+    op = Operator(p)
+    h = 10 * p.h_cfl
+    v = h * op.rhs(p.state)
+    for l in (0, 1):
+        ref = phi_action(op, v, l, h, 1e-10)[1]
+        for seed in (1, 2):
+            _dd_noise(monkeypatch, seed)
+            st = phi_action(op, v, l, h, 1e-10)[1]
+            monkeypatch.undo()
+            assert st.m_star == ref.m_star and st.substeps == ref.substeps
