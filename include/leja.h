@@ -163,6 +163,11 @@ LJ_API int lj_divided_differences(lj_context* ctx, int l, double s, double c, do
  * and LJ_OP_ADVDIFF2D this is J u. */
 LJ_API int lj_rhs(lj_context* ctx, const lj_operator* J, const double* u, double* f, void* stream);
 
+/* y = J(J->state) x, the Jacobian product of the operator family (Sec. 2.2
+ * applies J matrix-free; device in, device out, n values, y must not alias
+ * x). */
+LJ_API int lj_jv(lj_context* ctx, const lj_operator* J, const double* x, double* y, void* stream);
+
 /* ---- the action ---------------------------------------------------------- */
 
 /* w = phi_l(h J) v to tolerance tol (Sec. 2.2), 0 <= l <= LJ_MAX_L.
@@ -236,6 +241,52 @@ typedef struct {
 LJ_API int lj_integrate(lj_context* ctx, int scheme, const lj_operator* J, double T, double dt0, double tol,
                         double leja_tol, double* u_out, const lj_options* opt, lj_integrate_stats* stats,
                         lj_step_record* log, int log_cap, int max_attempts, void* stream);
+
+/* ---- user operators: matrix-free callbacks ----------------------------------- */
+
+/* Any right-hand side u' = f(u) of n unknowns, given as host callbacks that
+ * enqueue device work on `stream` (a hipStream_t) and return 0 on success
+ * (nonzero: the library call fails with LJ_EINVAL and the callback's code in
+ * lj_last_error).  Pointers passed to a callback are device vectors of n
+ * doubles owned by the library or the caller; a callback must not keep them
+ * after it returns and must not write any vector other than its output.
+ *   rhs(user, x, fx, stream):     fx = f(x)
+ *   jv(user, u, x, jx, stream):   jx = J(u) x, the Jacobian of f at u
+ * jv may be NULL: the library then forms finite-difference products
+ * J(u) x ~ (f(u + eps x) - f(u)) / eps with eps = sqrt(2^-52) (1 + ||u||) / ||x||
+ * (Sec. 4 computes the Jacobian product numerically; the step length is the
+ * usual choice of Jacobian-free Newton-Krylov methods, Knoll & Keyes 2004),
+ * f(u) evaluated once per call; their error is O(eps ||f''||) + O(2^-52 ||f|| / eps),
+ * about 1e-8 relative, far above tight tolerances.  rhs may be NULL for the
+ * actions when jv is given; the stage driver needs both f and J (R(x) =
+ * f(x) - f(u) - J(u)(x - u), Sec. 1).  The Newton recurrence, the stop and
+ * rejection tests, the divided differences and the power iteration run as
+ * library kernels between the callbacks, with the decisions taken on the
+ * device; the host reads them every few steps, so up to 3 products beyond
+ * the last needed one may be computed (and discarded). */
+typedef int (*lj_rhs_fn)(void* user, const double* x, double* fx, void* stream);
+typedef int (*lj_jv_fn)(void* user, const double* u, const double* x, double* jx, void* stream);
+
+typedef struct {
+  int64_t n;            /* unknowns, >= 1 */
+  lj_rhs_fn rhs;        /* f (may be NULL for actions with jv given) */
+  lj_jv_fn jv;          /* J(u) x (NULL: finite differences of rhs) */
+  void* user;           /* passed to the callbacks */
+  const double* state;  /* device: the linearisation state u (n values) */
+} lj_user_operator;
+
+/* lj_phi_action / lj_phi_vertical / lj_step for a user operator: the same
+ * method, options (except use_proposal, which needs a built-in family) and
+ * statistics; power iteration, substepping and the schemes as for the
+ * built-in families. */
+LJ_API int lj_user_phi_action(lj_context* ctx, const lj_user_operator* J, const double* v, double* w, int l,
+                              double h, double tol, const lj_options* opt, lj_stats* stats, void* stream);
+LJ_API int lj_user_phi_vertical(lj_context* ctx, const lj_user_operator* J, const double* v, int K,
+                                const int* l, const double* a, double h, double tol, double* const* w,
+                                const lj_options* opt, lj_stats* stats, void* stream);
+LJ_API int lj_user_step(lj_context* ctx, int scheme, const lj_user_operator* J, double h, double tol,
+                        double* u_out, double* err, const lj_options* opt, lj_stats* stats, int nstats,
+                        int* ncalls, void* stream);
 
 /* ---- batching form --------------------------------------------------------- */
 

@@ -10,6 +10,7 @@ contiguity) before their pointers cross the ABI.
 """
 from __future__ import annotations
 
+import contextlib
 import ctypes as C
 from dataclasses import dataclass
 from typing import Sequence
@@ -181,6 +182,151 @@ def lj_rhs(ctx: Context, J: Operator, u, f, stream=None) -> None:
     op = J.c_struct()
     ctx._check(ctx._lib.lj_rhs(ctx.handle, C.byref(op), _tensor_ptr(u, J.n, "u"), _tensor_ptr(f, J.n, "f"),
                                _stream_ptr(stream)), False)
+
+
+def lj_jv(ctx: Context, J: Operator, x, y, stream=None) -> None:
+    """y = J(J.state) x for a built-in family."""
+    op = J.c_struct()
+    ctx._check(ctx._lib.lj_jv(ctx.handle, C.byref(op), _tensor_ptr(x, J.n, "x"), _tensor_ptr(y, J.n, "y"),
+                              _stream_ptr(stream)), False)
+
+
+class _DeviceVector:
+    """n float64 values at a device address, exposed to torch.as_tensor through
+    the CUDA array interface (no copy)."""
+
+    def __init__(self, ptr: int, n: int):
+        self.__cuda_array_interface__ = {"shape": (n,), "typestr": "<f8", "data": (int(ptr), False),
+                                         "version": 2, "strides": None}
+
+
+def device_view(ptr: int, n: int):
+    """A torch tensor viewing n float64 values at device address ptr."""
+    import torch
+    return torch.as_tensor(_DeviceVector(ptr, n), device=torch.device("cuda", torch.cuda.current_device()))
+
+
+class UserOperator:
+    """An operator u' = f(u) of n unknowns given by Python callables on torch
+    tensors (lj_user_operator):
+
+        rhs(x, out):     out[:] = f(x)
+        jv(u, x, out):   out[:] = J(u) x
+
+    Either may be None (jv None: the library forms finite-difference products
+    from rhs; rhs None: actions only).  The callables run on the library's
+    stream, which is made torch's current stream for their duration.  An
+    exception raised in a callable makes the library call fail; it is re-raised
+    by the wrapper."""
+
+    def __init__(self, n: int, state, rhs=None, jv=None):
+        self.n = int(n)
+        self.state = state
+        self.errors: list = []
+        n_ = self.n
+
+        def on_stream(stream):
+            import torch
+            cur = torch.cuda.current_stream()
+            if stream is None or int(stream) == int(cur.cuda_stream):
+                return contextlib.nullcontext()
+            return torch.cuda.stream(torch.cuda.ExternalStream(int(stream)))
+
+        def rhs_c(user, x, fx, stream):
+            try:
+                with on_stream(stream):
+                    rhs(device_view(x, n_), device_view(fx, n_))
+                return 0
+            except BaseException as e:  # reported after the library call returns
+                self.errors.append(e)
+                return 1
+
+        def jv_c(user, u, x, jx, stream):
+            try:
+                with on_stream(stream):
+                    jv(device_view(u, n_), device_view(x, n_), device_view(jx, n_))
+                return 0
+            except BaseException as e:
+                self.errors.append(e)
+                return 1
+
+        self._rhs_c = _lib.lj_rhs_fn(rhs_c) if rhs is not None else _lib.lj_rhs_fn()
+        self._jv_c = _lib.lj_jv_fn(jv_c) if jv is not None else _lib.lj_jv_fn()
+
+    def c_struct(self) -> "_lib.lj_user_operator":
+        op = _lib.lj_user_operator()
+        op.n = self.n
+        op.rhs = self._rhs_c
+        op.jv = self._jv_c
+        op.user = None
+        op.state = _tensor_ptr(self.state, self.n, "user operator state").value
+        return op
+
+
+
+def _user_call(ctx: Context, U: UserOperator, rc: int):
+    """Raises for a failed call; a callback's own exception is chained."""
+    if U.errors:
+        e = U.errors[0]
+        U.errors.clear()
+        raise LejaError(rc, ctx.last_error()) from e
+    ctx._check(rc)
+
+
+def lj_user_phi_action(ctx: Context, U: UserOperator, v, w, l: int, h: float, tol: float,
+                       opt: lj_options | None = None, stream=None):
+    """w = phi_l(h J) v for a user operator.  Returns (rc, stats dict)."""
+    op = U.c_struct()
+    st = lj_stats()
+    rc = ctx._lib.lj_user_phi_action(ctx.handle, C.byref(op), _tensor_ptr(v, U.n, "v"), _tensor_ptr(w, U.n, "w"),
+                                     int(l), float(h), float(tol), C.byref(opt) if opt is not None else None,
+                                     C.byref(st), _stream_ptr(stream))
+    _user_call(ctx, U, rc)
+    return rc, st.as_dict(1)
+
+
+def lj_user_phi_vertical(ctx: Context, U: UserOperator, v, ls: Sequence[int], As: Sequence[float], h: float,
+                         tol: float, ws: Sequence, opt: lj_options | None = None, stream=None):
+    K = len(ls)
+    if len(As) != K or len(ws) != K:
+        raise ValueError("ls, As and ws must have the same length")
+    op = U.c_struct()
+    st = lj_stats()
+    larr = (C.c_int * K)(*[int(x) for x in ls])
+    aarr = (C.c_double * K)(*[float(x) for x in As])
+    warr = (C.c_void_p * K)(*[_tensor_ptr(w, U.n, f"w[{k}]").value for k, w in enumerate(ws)])
+    rc = ctx._lib.lj_user_phi_vertical(ctx.handle, C.byref(op), _tensor_ptr(v, U.n, "v"), K, larr, aarr,
+                                       float(h), float(tol), warr, C.byref(opt) if opt is not None else None,
+                                       C.byref(st), _stream_ptr(stream))
+    _user_call(ctx, U, rc)
+    return rc, st.as_dict(K)
+
+
+def lj_user_step(ctx: Context, scheme: str, U: UserOperator, h: float, tol: float, u_out, err=None,
+                 opt: lj_options | None = None, stream=None):
+    """One exponential-integrator step from U.state.  Returns (rc, list of stats dicts)."""
+    op = U.c_struct()
+    stats = (lj_stats * 4)()
+    ncalls = C.c_int()
+    rc = ctx._lib.lj_user_step(ctx.handle, SCHEMES[scheme], C.byref(op), float(h), float(tol),
+                               _tensor_ptr(u_out, U.n, "u_out"),
+                               _tensor_ptr(err, U.n, "err") if err is not None else None,
+                               C.byref(opt) if opt is not None else None, stats, 4, C.byref(ncalls),
+                               _stream_ptr(stream))
+    _user_call(ctx, U, rc)
+    return rc, [stats[i].as_dict() for i in range(ncalls.value)]
+
+
+def family_user_operator(ctx: Context, J: Operator, finite_difference: bool = False) -> UserOperator:
+    """A built-in family seen as a user operator (its lj_rhs and lj_jv as the
+    callbacks), e.g. to check the callback path against the fused one."""
+    def rhs(x, out):
+        lj_rhs(ctx, J, x, out)
+
+    def jv(u, x, out):
+        lj_jv(ctx, J, x, out)
+
+    return UserOperator(J.n, J.state, rhs=rhs, jv=None if finite_difference else jv)
 
 
 def lj_phi_action(ctx: Context, J: Operator, v, w, l: int, h: float, tol: float, opt: lj_options | None = None,

@@ -35,6 +35,17 @@ class lj_operator(C.Structure):
     ]
 
 
+# user-operator callbacks (lj_rhs_fn, lj_jv_fn)
+lj_rhs_fn = C.CFUNCTYPE(C.c_int, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p)
+lj_jv_fn = C.CFUNCTYPE(C.c_int, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p)
+
+
+class lj_user_operator(C.Structure):
+    _fields_ = [
+        ("n", C.c_int64), ("rhs", lj_rhs_fn), ("jv", lj_jv_fn), ("user", C.c_void_p), ("state", C.c_void_p),
+    ]
+
+
 class lj_options(C.Structure):
     _fields_ = [
         ("safety", C.c_double), ("power_iters", C.c_int32), ("max_points", C.c_int32),
@@ -110,6 +121,14 @@ _PROTOS = {
     "lj_divided_differences": (C.c_int, [_P, C.c_int, C.c_double, C.c_double, C.c_double, C.c_int,
                                          C.POINTER(C.c_double), _P]),
     "lj_rhs": (C.c_int, [_P, C.POINTER(lj_operator), _P, _P, _P]),
+    "lj_jv": (C.c_int, [_P, C.POINTER(lj_operator), _P, _P, _P]),
+    "lj_user_phi_action": (C.c_int, [_P, C.POINTER(lj_user_operator), _P, _P, C.c_int, C.c_double, C.c_double,
+                                     C.POINTER(lj_options), C.POINTER(lj_stats), _P]),
+    "lj_user_phi_vertical": (C.c_int, [_P, C.POINTER(lj_user_operator), _P, C.c_int, C.POINTER(C.c_int),
+                                       C.POINTER(C.c_double), C.c_double, C.c_double, C.POINTER(_P),
+                                       C.POINTER(lj_options), C.POINTER(lj_stats), _P]),
+    "lj_user_step": (C.c_int, [_P, C.c_int, C.POINTER(lj_user_operator), C.c_double, C.c_double, _P, _P,
+                               C.POINTER(lj_options), C.POINTER(lj_stats), C.c_int, C.POINTER(C.c_int), _P]),
     "lj_phi_action": (C.c_int, [_P, C.POINTER(lj_operator), _P, _P, C.c_int, C.c_double, C.c_double,
                                 C.POINTER(lj_options), C.POINTER(lj_stats), _P]),
     "lj_phi_vertical": (C.c_int, [_P, C.POINTER(lj_operator), _P, C.c_int, C.POINTER(C.c_int),

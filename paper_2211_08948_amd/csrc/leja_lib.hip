@@ -1,7 +1,8 @@
 // Host control of the Leja phi-action library: context, workspace, argument
 // checks, the rejection / substep logic, the vertical form and the stage
-// driver.  Every numerical step runs in the kernels of kernels.hip; this file
-// only orchestrates launches on the caller's stream.
+// driver.  Every numerical step runs in the kernels of kernels.hip (and, for
+// operators given as callbacks, user_kernels.hip); this file only
+// orchestrates launches on the caller's stream.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -19,6 +20,7 @@
 #include "common.hpp"
 #include "kernels.hpp"
 #include "mlp.hpp"
+#include "user_kernels.hpp"
 
 namespace lj {
 int leja_points_host(double* out, int count);
@@ -35,6 +37,8 @@ enum Slot {
   W_RA, W_T1,                      // R(a) kept for a later stage, the phi_1 input of EXPRB43
   W_T3, W_D3, W_T4, W_D4,          // phi_3 / phi_4 inputs and results
   W_IU0, W_IU1, W_IERR,            // variable-step integration: state ping-pong, error estimate
+  W_UJ, W_UPT, W_UY, W_UPA, W_UPB, // user operators: product, finite-difference point, power vectors
+  W_UFU, W_UXR, W_UD, W_UFX, W_UJD, W_UR0, W_UR1,  // f(u), stage remainders
   W_NSLOTS
 };
 
@@ -43,6 +47,13 @@ constexpr size_t kStaticLdsReserve = 40 * 1024;
 constexpr int kQ_batch = 1 + kMaxK;  // team partial sums per reduction
 constexpr int kAsyncSlots = 8;       // most action launches of one step
 constexpr int kTimingPairs = 1024;   // event pairs of the timing pool
+
+// An operator given as host callbacks (lj_user_operator) during one call.
+struct UserOp {
+  lj_user_operator J;
+  bool fd = false;             // finite-difference products from rhs
+  const double* fu = nullptr;  // f(u) (device), set when rhs is given
+};
 
 struct lj_context {
   int device = 0;
@@ -94,6 +105,13 @@ struct lj_context {
   float* d_pred = nullptr;   // kMaxK x 2
   double* d_sigma = nullptr;
   bool mlp_ready = false;
+  // user operators (callbacks): the operator of the running call, its
+  // decision state and pinned status, partial sums, the Leja table on the host
+  const UserOp* uop = nullptr;
+  UserState* d_ustate = nullptr;
+  UserStatus* h_ustatus = nullptr;  // pinned, coherent: written by the decision kernels
+  double* d_upart = nullptr;        // kUserBlocksMax * (1 + kMaxK)
+  std::vector<double> h_xi;
 };
 
 static std::string g_create_error;
@@ -472,9 +490,170 @@ hipEvent_t* timing_pair(lj_context* ctx) {
 // K accumulators phi_{l_k}(s_k J) v (K = 0: power iteration only), one
 // launch, synchronised.  The bound is lam_host when > 0, else the power
 // iteration runs inside the launch.
+// ---- user operators ------------------------------------------------------------
+// OpDev.kind of an operator given as callbacks: never passed to a family kernel
+// (run_action and the stage driver route it to the user path).
+constexpr int kUserKind = 100;
+
+bool is_user(const OpDev& op) { return op.kind == kUserKind; }
+
+void call_rhs(lj_context* ctx, const double* x, double* fx, hipStream_t s) {
+  const UserOp* U = ctx->uop;
+  if (!U->J.rhs) invalid(ctx, "user operator: rhs is NULL (needed here)");
+  const int rc = U->J.rhs(U->J.user, x, fx, reinterpret_cast<void*>(s));
+  if (rc != 0) invalid(ctx, "user rhs callback failed with code " + std::to_string(rc));
+}
+
+void call_jv(lj_context* ctx, const double* x, double* jx, hipStream_t s) {
+  const UserOp* U = ctx->uop;
+  const int rc = U->J.jv(U->J.user, U->J.state, x, jx, reinterpret_cast<void*>(s));
+  if (rc != 0) invalid(ctx, "user jv callback failed with code " + std::to_string(rc));
+}
+
+// out = J(u) x: the user's product, or a finite difference with its own step
+void user_jv(lj_context* ctx, const double* x, double* out, hipStream_t s) {
+  const UserOp* U = ctx->uop;
+  if (!U->fd) {
+    call_jv(ctx, x, out, s);
+    return;
+  }
+  const long n = (long)U->J.n;
+  HIPCHK(ctx, launch_user_fd_step(ctx->d_ustate, x, n, ctx->d_upart, s));
+  double* pt = slot(ctx, W_UPT, n);
+  HIPCHK(ctx, launch_user_fd_point(ctx->d_ustate, U->J.state, x, n, pt, s));
+  double* fx = slot(ctx, W_UJ, n);
+  call_rhs(ctx, pt, fx, s);
+  HIPCHK(ctx, launch_user_fd_quotient(ctx->d_ustate, fx, U->fu, n, out, s));
+}
+
+// Power iteration on a user operator (the products of the other paths, same
+// start vector and estimate): K products, x_{k+1} = J x_k / ||J x_k||.
+double user_power(lj_context* ctx, long n, int iters, uint64_t seed, const double* start, hipStream_t s) {
+  const UserOp* U = ctx->uop;
+  double* xa = slot(ctx, W_UPA, n);
+  double* xb = slot(ctx, W_UPB, n);
+  double* jb = slot(ctx, W_UJ, n);
+  double* yb = slot(ctx, W_UY, n);
+  double* pt = slot(ctx, W_UPT, n);
+  if (start) {
+    HIPCHK(ctx, hipMemcpyAsync(xa, start, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+  } else {
+    HIPCHK(ctx, launch_user_start_vector(xa, n, seed, s));
+  }
+  HIPCHK(ctx, launch_user_power_init(ctx->d_ustate, s));
+  double* cur = xa;
+  double* nxt = xb;
+  for (int k = 0; k < iters; ++k) {
+    if (U->fd) {
+      HIPCHK(ctx, launch_user_fd_step(ctx->d_ustate, cur, n, ctx->d_upart, s));
+      HIPCHK(ctx, launch_user_fd_point(ctx->d_ustate, U->J.state, cur, n, pt, s));
+      call_rhs(ctx, pt, jb, s);
+      HIPCHK(ctx, launch_user_power(ctx->d_ustate, cur, jb, U->fu, yb, nxt, n, ctx->d_upart, ctx->h_ustatus, s));
+    } else {
+      call_jv(ctx, cur, jb, s);
+      HIPCHK(ctx, launch_user_power(ctx->d_ustate, cur, jb, nullptr, nullptr, nxt, n, ctx->d_upart,
+                                    ctx->h_ustatus, s));
+    }
+    std::swap(cur, nxt);
+  }
+  HIPCHK(ctx, hipStreamSynchronize(s));
+  return ctx->h_ustatus->lam;
+}
+
+// Steps between the host's reads of the decisions: at most this many minus
+// one products past the last needed one are computed and discarded.
+constexpr int kUserPoll = 4;
+
+// One vertical Newton recurrence on a user operator (the run_action of the
+// callback path): power iteration unless lam_host > 0, divided differences,
+// then per step the user's product, the recurrence kernel and the decision
+// kernel.
+ActOut run_action_user(lj_context* ctx, const OpDev& op, const double* v, int K, const int* l, const double* s_k,
+                       double lam_host, uint64_t seed, const double* start, double* const* outs, const Opts& o,
+                       double tol, hipStream_t s) {
+  const UserOp* U = ctx->uop;
+  const long n = op.npts;
+  ActOut r;
+  std::memset(&r, 0, sizeof(r));
+  r.aborted = false;
+  for (int k = 0; k < kMaxK; ++k) {
+    r.state[k] = ACC_CONVERGED;
+    r.m_star[k] = -1;
+  }
+  double lam = lam_host;
+  if (!(lam > 0.0)) {
+    lam = user_power(ctx, n, o.power_iters, seed, start, s);
+    r.power_iters = o.power_iters;
+  }
+  const double alpha = -o.safety * lam;
+  const double c = 0.5 * (alpha + 0.0);
+  const double gamma = 0.25 * (0.0 - alpha);
+  r.lam = lam;
+  r.c = c;
+  r.gamma = gamma;
+  if (K == 0) return r;
+  if (!(gamma > 0.0)) invalid(ctx, "user operator: the spectral bound is zero (J v = 0 for the start vector)");
+  const double rgamma = 1.0 / gamma;
+  DDParams P;
+  std::memset(&P, 0, sizeof(P));
+  P.K = K;
+  for (int k = 0; k < K; ++k) {
+    P.l[k] = l[k];
+    P.s[k] = s_k[k];
+  }
+  P.npts = o.max_points + 1;
+  P.c = c;
+  P.gamma = gamma;
+  P.xi = ctx->d_xi;
+  P.coef = ctx->d_coef;
+  P.fmax = ctx->d_fmax;
+  HIPCHK(ctx, launch_divdiff(P, s));
+  UserRec R;
+  std::memset(&R, 0, sizeof(R));
+  R.n = n;
+  R.K = K;
+  R.coef = ctx->d_coef;
+  R.fmax = ctx->d_fmax;
+  for (int k = 0; k < K; ++k) R.p[k] = outs[k];
+  R.part = ctx->d_upart;
+  R.st = ctx->d_ustate;
+  R.host = ctx->h_ustatus;
+  HIPCHK(ctx, launch_user_rec_start(R, v, o.max_points, tol, o.relative, o.hump, U->fd ? 1 : 0, s));
+  double* yb[2] = {slot(ctx, W_Y0, n), slot(ctx, W_Y1, n)};
+  double* jb = slot(ctx, W_UJ, n);
+  double* pt = slot(ctx, W_UPT, n);
+  const double* yp = v;
+  HIPCHK(ctx, hipStreamSynchronize(s));
+  for (int m = 1; m <= o.max_points && !ctx->h_ustatus->done; ++m) {
+    if (U->fd) {
+      HIPCHK(ctx, launch_user_fd_point(ctx->d_ustate, U->J.state, yp, n, pt, s));
+      call_rhs(ctx, pt, jb, s);
+    } else {
+      call_jv(ctx, yp, jb, s);
+    }
+    double* y = yb[m & 1];
+    HIPCHK(ctx, launch_user_rec_step(R, m, jb, U->fd ? U->fu : nullptr, yp, y, c, gamma, rgamma,
+                                     ctx->h_xi[m - 1], s));
+    HIPCHK(ctx, launch_user_rec_decide(R, m, s));
+    yp = y;
+    if (m % kUserPoll == 0 || m == o.max_points) HIPCHK(ctx, hipStreamSynchronize(s));
+  }
+  HIPCHK(ctx, hipStreamSynchronize(s));
+  const UserStatus& S = *ctx->h_ustatus;
+  for (int k = 0; k < K; ++k) {
+    r.state[k] = S.state[k];
+    r.m_star[k] = S.m_star[k];
+    r.err[k] = S.err[k];
+  }
+  r.iters = S.iters;
+  r.vnorm = S.nv;
+  return r;
+}
+
 ActOut run_action(lj_context* ctx, const OpDev& op, const double* v, int K, const int* l, const double* s_k,
                   double lam_host, uint64_t seed, const double* start, double* const* outs, const Opts& o,
                   double tol, hipStream_t s) {
+  if (is_user(op)) return run_action_user(ctx, op, v, K, l, s_k, lam_host, seed, start, outs, o, tol, s);
   bool tiled = false;
   for (int attempt = 0; attempt < 2; ++attempt) {
     hipEvent_t* ev = timing_pair(ctx);
@@ -668,6 +847,63 @@ void check_action_args(lj_context* ctx, const OpDev& op, const double* v, int K,
       if (w[q] == w[k]) invalid(ctx, "the outputs w[k] must be distinct");
   }
 }
+
+// ---- user operators: per-call setup ------------------------------------------------
+void user_alloc(lj_context* ctx) {
+  if (!ctx->d_ustate) HIPCHK(ctx, hipMalloc(&ctx->d_ustate, sizeof(UserState)));
+  if (!ctx->h_ustatus) {
+    HIPCHK(ctx, hipHostMalloc(&ctx->h_ustatus, sizeof(UserStatus), hipHostMallocCoherent));
+    std::memset(ctx->h_ustatus, 0, sizeof(UserStatus));
+  }
+  if (!ctx->d_upart) HIPCHK(ctx, hipMalloc(&ctx->d_upart, (size_t)kUserBlocksMax * (1 + kMaxK) * sizeof(double)));
+  if (ctx->h_xi.empty()) {
+    ctx->h_xi.resize(kTable);
+    if (leja_points_host(ctx->h_xi.data(), kTable) != 0) invalid(ctx, "internal: Leja table");
+  }
+}
+
+// A call on a user operator: checks it, makes it the context's current user
+// operator, evaluates f(u) once when finite-difference products or the stage
+// driver need it, and ||u|| for the finite-difference step.
+struct UserScope {
+  lj_context* ctx;
+  UserOp U;
+  OpDev op;
+  UserScope(lj_context* c, const lj_user_operator* J, bool need_rhs, hipStream_t s) : ctx(c) {
+    if (!J) invalid(ctx, "user operator is NULL");
+    if (J->n < 1 || J->n > (1ll << 30)) invalid(ctx, "user operator: n must be in [1, 2^30]");
+    if (!J->jv && !J->rhs) invalid(ctx, "user operator: give jv, rhs or both");
+    if (need_rhs && !J->rhs) invalid(ctx, "user operator: the stage driver needs rhs");
+    if (!J->state) invalid(ctx, "user operator: state is NULL");
+    if (ctx->uop) invalid(ctx, "a user-operator call is already running on this context");
+    U.J = *J;
+    U.fd = (J->jv == nullptr);
+    std::memset(&op, 0, sizeof(op));
+    op.kind = kUserKind;
+    op.nx = (int)J->n;
+    op.ny = 1;
+    op.ncomp = 1;
+    op.npts = (int)J->n;
+    op.state = J->state;
+    check_vec(ctx, op, J->state, "user operator state");
+    user_alloc(ctx);
+    ctx->uop = &U;
+    try {
+      if (U.fd) {
+        double* fu = slot(ctx, W_UFU, (size_t)J->n);
+        call_rhs(ctx, J->state, fu, s);
+        U.fu = fu;
+        HIPCHK(ctx, launch_user_norm_u(ctx->d_ustate, J->state, (long)J->n, ctx->d_upart, s));
+      }
+    } catch (...) {
+      ctx->uop = nullptr;
+      throw;
+    }
+  }
+  ~UserScope() { ctx->uop = nullptr; }
+  UserScope(const UserScope&) = delete;
+  UserScope& operator=(const UserScope&) = delete;
+};
 
 // ---- learned proposal --------------------------------------------------------
 constexpr int kMaxEpochs = 4096;
@@ -1053,6 +1289,9 @@ LJ_API void lj_destroy(lj_context* ctx) {
   if (ctx->d_bound) (void)hipFree(ctx->d_bound);
   if (ctx->d_sumsq) (void)hipFree(ctx->d_sumsq);
   if (ctx->h_sumsq) (void)hipHostFree(ctx->h_sumsq);
+  if (ctx->d_ustate) (void)hipFree(ctx->d_ustate);
+  if (ctx->h_ustatus) (void)hipHostFree(ctx->h_ustatus);
+  if (ctx->d_upart) (void)hipFree(ctx->d_upart);
   delete ctx;
 }
 
@@ -1105,6 +1344,40 @@ LJ_API int lj_rhs(lj_context* ctx, const lj_operator* J, const double* u, double
     HIPCHK(ctx, launch_rhs(op, u, f, reinterpret_cast<hipStream_t>(stream)));
     return LJ_OK;
   });
+}
+
+LJ_API int lj_jv(lj_context* ctx, const lj_operator* J, const double* x, double* y, void* stream) {
+  return guarded(ctx, [&]() {
+    const OpDev op = make_op(ctx, J);
+    check_vec(ctx, op, x, "x");
+    check_vec(ctx, op, y, "y");
+    if (y == x) invalid(ctx, "y must not alias x");
+    if (y == op.state) invalid(ctx, "y must not alias the operator state");
+    HIPCHK(ctx, launch_family_jv(op, x, y, reinterpret_cast<hipStream_t>(stream)));
+    return LJ_OK;
+  });
+}
+
+LJ_API int lj_user_phi_vertical(lj_context* ctx, const lj_user_operator* J, const double* v, int K, const int* l,
+                                const double* a, double h, double tol, double* const* w, const lj_options* opt,
+                                lj_stats* stats, void* stream) {
+  return guarded(ctx, [&]() {
+    const hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    const Opts o = resolve(ctx, opt);
+    if (o.use_proposal) invalid(ctx, "the learned proposal needs a built-in operator family");
+    UserScope us(ctx, J, false, s);
+    check_action_args(ctx, us.op, v, K, l, a, h, tol, w);
+    if (o.pi_start) check_vec(ctx, us.op, o.pi_start, "pi_start");
+    lj_stats local;
+    return vertical_impl(ctx, us.op, v, K, l, a, h, tol, w, o, stats ? stats : &local, s);
+  });
+}
+
+LJ_API int lj_user_phi_action(lj_context* ctx, const lj_user_operator* J, const double* v, double* w, int l,
+                              double h, double tol, const lj_options* opt, lj_stats* stats, void* stream) {
+  const double a = 1.0;
+  double* ws[1] = {w};
+  return lj_user_phi_vertical(ctx, J, v, 1, &l, &a, h, tol, ws, opt, stats, stream);
 }
 
 LJ_API int lj_phi_vertical(lj_context* ctx, const lj_operator* J, const double* v, int K, const int* l,
@@ -1184,10 +1457,51 @@ int step_impl(lj_context* ctx, int scheme, const OpDev& op, Opts o, double h, do
   // Leja calls: f(u) and v = h f(u) in one pass, the remainders and the
   // vectors the next calls act on in one pass, the result and error
   // estimate in one pass.
+  // f(u) and h f(u); the stage remainders and combinations (one fused pass
+  // for a built-in family, callbacks and linear combinations for a user
+  // operator, in the same order of operations)
+  auto rhs_scaled = [&](double* fu, double* v) {
+    if (!is_user(op)) {
+      HIPCHK(ctx, launch_rhs_scaled(op, h, fu, v, s));
+      return;
+    }
+    call_rhs(ctx, u, fu, s);
+    const double* x[1] = {fu};
+    lincomb(ctx, n, v, 1, &h, x, s);
+  };
+  auto stage = [&](const StageArgs& S) {
+    if (!is_user(op)) {
+      HIPCHK(ctx, launch_stage(S, s));
+      return;
+    }
+    double* R[2] = {slot(ctx, W_UR0, n), slot(ctx, W_UR1, n)};
+    double* xr = slot(ctx, W_UXR, n);
+    double* d = slot(ctx, W_UD, n);
+    double* fx = slot(ctx, W_UFX, n);
+    double* jd = slot(ctx, W_UJD, n);
+    for (int r = 0; r < S.nrem; ++r) {  // R_r = (f(x_r) - f(u)) - J(u)(x_r - u)
+      const double ax[3] = {1.0, S.a[r][0], S.a[r][1]};
+      const double* xs[3] = {u, S.X[r][0], S.X[r][1]};
+      lincomb(ctx, n, xr, 1 + S.nterm[r], ax, xs, s);
+      const double ad[2] = {1.0, -1.0};
+      const double* ds[2] = {xr, u};
+      lincomb(ctx, n, d, 2, ad, ds, s);
+      call_rhs(ctx, xr, fx, s);
+      user_jv(ctx, d, jd, s);
+      const double ar[3] = {1.0, -1.0, -1.0};
+      const double* rs[3] = {fx, S.fu, jd};
+      lincomb(ctx, n, R[r], 3, ar, rs, s);
+    }
+    for (int o2 = 0; o2 < S.nout; ++o2) {
+      const double* src[2];
+      for (int t = 0; t < S.nsrc[o2]; ++t) src[t] = (S.src[o2][t] == 2) ? S.P : R[S.src[o2][t]];
+      lincomb(ctx, n, S.out[o2], S.nsrc[o2], S.c[o2], src, s);
+    }
+  };
   auto scheme_steps = [&](auto&& act) {
     double* fu = slot(ctx, W_FU, n);
     double* v = slot(ctx, W_V, n);
-    HIPCHK(ctx, launch_rhs_scaled(op, h, fu, v, s));
+    rhs_scaled(fu, v);
     auto finish = [&](const double* X1, const double* X2, const double* X3) {
       FinishArgs F;
       F.n = (long)n;
@@ -1242,7 +1556,7 @@ int step_impl(lj_context* ctx, int scheme, const OpDev& op, Opts o, double h, do
         S.src[1][0] = 0;
         S.c[1][0] = 1.0;
         S.out[1] = Ra;
-        HIPCHK(ctx, launch_stage(S, s));
+        stage(S);
       }
       {
         const int ls[1] = {1};
@@ -1271,7 +1585,7 @@ int step_impl(lj_context* ctx, int scheme, const OpDev& op, Opts o, double h, do
         S.src[1][1] = 0;
         S.c[1][1] = 12.0 * h;
         S.out[1] = T4;
-        HIPCHK(ctx, launch_stage(S, s));
+        stage(S);
       }
       {
         const int ls[1] = {3};
@@ -1324,7 +1638,7 @@ int step_impl(lj_context* ctx, int scheme, const OpDev& op, Opts o, double h, do
         S.src[1][1] = 1;
         S.c[1][1] = h * -34992.0;
         S.out[1] = T4;
-        HIPCHK(ctx, launch_stage(S, s));
+        stage(S);
       }
       {
         const int ls[1] = {3};
@@ -1347,7 +1661,7 @@ int step_impl(lj_context* ctx, int scheme, const OpDev& op, Opts o, double h, do
   // leaves the bound on the device for the others; statuses are read once
   // at the end.  If some expansion was rejected, the step is redone below
   // synchronously, with substeps, on the bound found.
-  const bool try_async = o.substeps <= 1 && !o.use_proposal;
+  const bool try_async = o.substeps <= 1 && !o.use_proposal && !is_user(op);
   double lam_found = o.bound;
   if (try_async) {
     struct Pending {
@@ -1459,6 +1773,30 @@ LJ_API int lj_step(lj_context* ctx, int scheme, const lj_operator* J, double h, 
     if (ncalls) *ncalls = want;
     if (stats && nstats < want) invalid(ctx, "nstats is smaller than the number of Leja calls of the scheme");
     return step_impl(ctx, scheme, op, o, h, tol, u_out, err, stats, reinterpret_cast<hipStream_t>(stream));
+  });
+}
+
+LJ_API int lj_user_step(lj_context* ctx, int scheme, const lj_user_operator* J, double h, double tol,
+                        double* u_out, double* err, const lj_options* opt, lj_stats* stats, int nstats,
+                        int* ncalls, void* stream) {
+  return guarded(ctx, [&]() {
+    const hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    Opts o = resolve(ctx, opt);
+    if (o.use_proposal) invalid(ctx, "the learned proposal needs a built-in operator family");
+    if (scheme < LJ_EXPRB2 || scheme > LJ_EPIRK4S3) invalid(ctx, "unknown scheme");
+    if (!std::isfinite(h)) invalid(ctx, "h must be finite");
+    if (!(tol > 0.0) || !std::isfinite(tol)) invalid(ctx, "tol must be finite and > 0");
+    UserScope us(ctx, J, true, s);
+    check_vec(ctx, us.op, u_out, "u_out");
+    if (u_out == us.op.state) invalid(ctx, "u_out must not alias the state");
+    if (err) {
+      check_vec(ctx, us.op, err, "err");
+      if (err == us.op.state || err == u_out) invalid(ctx, "err must not alias the state or u_out");
+    }
+    const int want = (scheme == LJ_EXPRB2) ? 1 : (scheme == LJ_EXPRB43) ? 4 : 3;
+    if (ncalls) *ncalls = want;
+    if (stats && nstats < want) invalid(ctx, "nstats is smaller than the number of Leja calls of the scheme");
+    return step_impl(ctx, scheme, us.op, o, h, tol, u_out, err, stats, s);
   });
 }
 

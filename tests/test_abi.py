@@ -37,7 +37,7 @@ def test_every_declared_symbol_is_exported(lib):
 
 def test_struct_layout_matches_c(tmp_path):
     from paper_2211_08948_amd._lib import (lj_batch_info_t, lj_integrate_stats, lj_operator, lj_options, lj_stats,
-                                           lj_step_record, lj_timing)
+                                           lj_step_record, lj_timing, lj_user_operator)
     prog = tmp_path / "sz.c"
     fields = {
         "lj_operator": ["kind", "nx", "dx", "coef", "state"],
@@ -49,6 +49,7 @@ def test_struct_layout_matches_c(tmp_path):
         "lj_batch_info_t": ["schedule", "nschedules", "tune_ms", "total_values", "alg_bytes"],
         "lj_integrate_stats": ["accepted", "rejected", "products", "t", "dt_next"],
         "lj_step_record": ["t", "dt", "err", "products", "accepted"],
+        "lj_user_operator": ["n", "rhs", "jv", "user", "state"],
     }
     lines = ['#include <stdio.h>', '#include <stddef.h>', f'#include "{HEADER}"', "int main(void){"]
     for s, fs in fields.items():
@@ -63,7 +64,7 @@ def test_struct_layout_matches_c(tmp_path):
                                                           check=True).stdout.split("\n") if l)
     py = {"lj_operator": lj_operator, "lj_options": lj_options, "lj_stats": lj_stats, "lj_timing": lj_timing,
           "lj_batch_info_t": lj_batch_info_t, "lj_integrate_stats": lj_integrate_stats,
-          "lj_step_record": lj_step_record}
+          "lj_step_record": lj_step_record, "lj_user_operator": lj_user_operator}
     for s, fs in fields.items():
         assert int(out[s]) == C.sizeof(py[s]), s
         for f in fs:
@@ -113,6 +114,10 @@ def test_null_arguments_are_rejected_without_device(lib):
     assert lib.lj_phi_action(None, None, None, None, 1, 1.0, 1e-10, None, None, None) == -1
     assert lib.lj_step(None, 1, None, 1.0, 1e-10, None, None, None, None, 0, None, None) == -1
     assert lib.lj_timing_enable(None, 1) == -1
+    assert lib.lj_jv(None, None, None, None, None) == -1
+    assert lib.lj_user_phi_action(None, None, None, None, 1, 1.0, 1e-10, None, None, None) == -1
+    assert lib.lj_user_phi_vertical(None, None, None, 1, None, None, 1.0, 1e-10, None, None, None, None) == -1
+    assert lib.lj_user_step(None, 1, None, 1.0, 1e-10, None, None, None, None, 0, None, None) == -1
     assert lib.lj_integrate(None, 4, None, 1.0, 0.1, 1e-6, 1e-10, None, None, None, None, 0, 10, None) == -1
     assert lib.lj_batch_run(None, None) == -1
     assert lib.lj_batch_stats(None, None, None) == -1
