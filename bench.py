@@ -21,6 +21,7 @@ Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
                         advection-diffusion-reaction 512^2 step (Neumann),
                         Allen-Cahn 1024^2..8192^2)
        python bench.py --form adaptive   (variable step sizes, EPIRK4s3 on 512^2 Allen-Cahn)
+       python bench.py --form user   (operators as callbacks: phi_1 on 512^2 Allen-Cahn, fused vs callbacks)
        python bench.py --copy-calibration   (plain copy kernel for counter scaling)
 """
 from __future__ import annotations
@@ -340,6 +341,56 @@ def bench_adaptive(args):
     print(json.dumps(rec), flush=True)
 
 
+def bench_user(args):
+    """The user-operator path (lj_user_*) on 512^2 Allen-Cahn, phi_1 of h f(u)
+    at 10x CFL with the bound given: the fused action kernel against the same
+    operator through callbacks (the library's own lj_jv / lj_rhs called from
+    Python), with analytic and with finite-difference products; one JSON line
+    per variant (not the headline metric)."""
+    import statistics
+
+    import torch
+
+    import paper_2211_08948_amd as lj
+    from workloads import allen_cahn_noise
+    prob = allen_cahn_noise(args.n, eps=1e-3, seed=2)
+    ctx = lj.Context(0)
+    J = lj.operator_from(prob, "cuda:0")
+    h = CFL_MULT * prob.h_cfl
+    f = torch.empty_like(J.state)
+    lj.lj_rhs(ctx, J, J.state, f)
+    v = (h * f).contiguous()
+    w = torch.empty_like(v)
+    lam = lj.lj_spectral_bound(ctx, J, 20)
+    o = lj.lj_default_options(bound=lam)
+    variants = [
+        ("fused action kernel", lambda: lj.lj_phi_action(ctx, J, v, w, 1, h, TOL, o)),
+        ("callbacks, analytic J v", lambda: lj.lj_user_phi_action(ctx, lj.family_user_operator(ctx, J), v, w, 1, h,
+                                                                 TOL, o)),
+        ("callbacks, finite-difference J v", lambda: lj.lj_user_phi_action(
+            ctx, lj.family_user_operator(ctx, J, finite_difference=True), v, w, 1, h, TOL, o)),
+    ]
+    for name, fn in variants:
+        for _ in range(2):
+            fn()
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(max(args.steps // 5, 5)):
+            t0 = time.perf_counter()
+            rc, st = fn()
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t0)
+        dt = statistics.median(ts)
+        m = st["m_star"][0]
+        rec = {"metric": "\u03c6_1 action time", "value": round(dt * 1e6, 1), "unit": "us", "n_gpus": 1,
+               "higher_is_better": False, "dtype": "f64", "data": "synthetic",
+               "config": {"workload": f"allen-cahn {args.n}x{args.n} periodic, eps 1e-3, u0~U[-0.1,0.1] seed 2, "
+                                      f"phi_1 at 10x CFL, bound given, tol 1e-10: {name}"},
+               "m_star": m, "us_per_product": round(dt * 1e6 / max(m, 1), 2)}
+        print(json.dumps(rec), flush=True)
+    ctx.close()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -348,7 +399,7 @@ def main():
     ap.add_argument("--n", type=int, default=512, help="grid points per axis (default: the 512^2 workload)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true")
-    ap.add_argument("--form", choices=["plain", "batch", "sweep", "adaptive"], default="plain")
+    ap.add_argument("--form", choices=["plain", "batch", "sweep", "adaptive", "user"], default="plain")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}): the multi-GPU path is not "
@@ -365,6 +416,9 @@ def main():
         return
     if args.form == "adaptive":
         bench_adaptive(args)
+        return
+    if args.form == "user":
+        bench_user(args)
         return
 
     import torch
