@@ -10,6 +10,10 @@ nonlinear remainders enter through R(x) = F(x) - F(u^n).  The schemes:
   phi_1(h J) on h f(u) run vertically (Sec. 5.4 text).  'EXPRB43_U3' stops at u_3.
 * EPIRK4s3 (Sec. 5.1 equation): phi_1 at 1/8, 1/9 and 1 on h f(u) vertically,
   then phi_3 and phi_4 individually (Sec. 5.1 text).
+* EPIRK4S3_LEKRY ("LeKry", Sec. 5.1 text): the same scheme with the two
+  internal stages phi_1(h/8 J), phi_1(h/9 J) by Leja (vertical), the third
+  stage's phi_1(hJ) h f(u) + phi_3(hJ) D_3 as one augmented exponential by
+  Krylov (oracle.krylov), and the phi_4 error term by Leja.
 
 One spectral bound is computed per step and shared by every action (J is fixed
 over the step; Sec. 4: the re-scaling is done once).  err = u_4 - u_3 for the
@@ -21,7 +25,8 @@ from dataclasses import replace
 
 import numpy as np
 
-from .leja import Options, phi_vertical
+from .krylov import KrylovOptions, phi_combination
+from .leja import Options, Stats, phi_vertical
 from .power import power_iteration
 
 
@@ -73,6 +78,22 @@ def step(op, scheme: str, h: float, tol: float, opt: Options | None = None):
         D3v = h * (1892.0 * Ra + 1458.0 * (Rb - 2.0 * Ra))
         (D3,) = act(D3v, [3], [1.0])
         u3 = u + C + D3
+        D4v = h * (-42336.0 * Ra - 34992.0 * (Rb - 2.0 * Ra))
+        (D4,) = act(D4v, [4], [1.0])
+        u4 = u3 + D4
+        out = (u4, u4 - u3)
+    elif scheme == "EPIRK4S3_LEKRY":
+        A, B = act(v, [1, 1], [1.0 / 8.0, 1.0 / 9.0])
+        a = u + A / 8.0
+        b = u + B / 9.0
+        Ra = op.remainder(a, fu)
+        Rb = op.remainder(b, fu)
+        D3v = h * (1892.0 * Ra + 1458.0 * (Rb - 2.0 * Ra))
+        # phi_1(hJ) (h f) + phi_3(hJ) D3v = sum_j phi_j(hJ) b_j h^j, b_1 = f, b_3 = D3v / h^3
+        K3, kst = phi_combination(op.jv, [None, fu, None, D3v / h ** 3], h, tol, KrylovOptions())
+        log.append(Stats(m_star=[kst.products], substeps=[kst.substeps], iters_total=kst.products,
+                         rejections=kst.rejections, converged=kst.converged))
+        u3 = u + K3
         D4v = h * (-42336.0 * Ra - 34992.0 * (Rb - 2.0 * Ra))
         (D4,) = act(D4v, [4], [1.0])
         u4 = u3 + D4
