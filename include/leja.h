@@ -190,7 +190,10 @@ typedef enum {
   LJ_EXPRB2 = 1,     /* u + phi_1(hJ) h f(u) */
   LJ_EXPRB43_U3 = 2, /* third-order u_3 of EXPRB43 (Sec. 5.4 equation) */
   LJ_EXPRB43 = 3,    /* fourth-order u_4 of EXPRB43, err = u_4 - u_3 */
-  LJ_EPIRK4S3 = 4    /* fourth-order u_4 of EPIRK4s3 (Sec. 5.1 equation), err = u_4 - u_3 */
+  LJ_EPIRK4S3 = 4,   /* fourth-order u_4 of EPIRK4s3 (Sec. 5.1 equation), err = u_4 - u_3 */
+  LJ_EPIRK4S3_LEKRY = 5 /* EPIRK4s3 as "LeKry" (Sec. 5.1 text): the internal stages by Leja (vertical),
+                           phi_1(hJ) h f(u) + phi_3(hJ) D_3 of u_3 as one Krylov exponential
+                           (lj_phi_combination, default Krylov options), the phi_4 term by Leja */
 } lj_scheme;
 
 /* One step from u = J->state with step size h: u_out (device) receives the
@@ -198,11 +201,43 @@ typedef enum {
  * u_4 - u_3 (zero-filled for schemes without one).  One power iteration per
  * step is shared by all actions.  stats (host) may be NULL; otherwise it is an
  * array of `nstats` entries receiving the statistics of the step's Leja calls
- * in order (EXPRB2: 1, EXPRB43_U3: 3, EXPRB43: 4, EPIRK4S3: 3); *ncalls (may be
+ * in order (EXPRB2: 1, EXPRB43_U3: 3, EXPRB43: 4, EPIRK4S3: 3, EPIRK4S3_LEKRY: 3 -- the
+ * vertical Leja call, the Krylov call, the phi_4 Leja call); *ncalls (may be
  * NULL) receives that count. */
 LJ_API int lj_step(lj_context* ctx, int scheme, const lj_operator* J, double h, double tol,
                    double* u_out, double* err, const lj_options* opt, lj_stats* stats,
                    int nstats, int* ncalls, void* stream);
+
+/* ---- Krylov: a linear combination of phi functions (Sec. 2.1) ------------------ */
+
+/* Options of the Krylov evaluation.  Fill with lj_default_krylov_options(). */
+typedef struct {
+  int32_t krylov_dim;   /* m, the Krylov space dimension per substep, 1..64; 30 */
+  int32_t window;       /* orthogonalise against the last `window` basis vectors (incomplete
+                           orthogonalisation as in KIOPS); 0: against all; 2 */
+  int32_t max_substeps; /* most accepted substeps (10x as many attempts); 1000 */
+  int32_t reserved;
+} lj_krylov_options;
+
+LJ_API void lj_default_krylov_options(lj_krylov_options* k);
+
+/* w = sum_{j=0}^{p} phi_j(h J) b_j h^j, 0 <= p <= 4, h >= 0: the first block of
+ * exp(h A~) [b_0; e_p] with the augmented matrix A~ = [[J, B], [0, K]],
+ * B = [b_p, ..., b_1], K the p x p shift (the theorem of Sec. 2.1), advanced
+ * in substeps.  Each substep builds an m-dimensional Krylov space of A~ by
+ * Arnoldi's process (classical Gram-Schmidt over the orthogonalisation
+ * window; a zero new vector ends the space, which is then exact), takes
+ * beta V_m exp(tau H_m) e_1, and accepts it when the estimate
+ * beta h_{m+1,m} tau |e_m^T phi_1(tau H_m) e_1| is at most tol (tau / h) ||w||;
+ * the next substep (or the retry of a rejected one, on the same basis) has
+ * size 0.9 tau (allowed / estimate)^{1/(m+1)}, clamped to [tau/10, 2 tau].
+ * b is a host array of p + 1 device pointers (NULL entries are zero vectors),
+ * w a device vector not aliasing any b[j] or the state.  stats (host, may be
+ * NULL): m_star[0] = iters_total = Jacobian products, substeps[0], rejections,
+ * converged, err_est[0] = the last accepted estimate.  LJ_ENOTCONV when the
+ * substep limit is reached (w then holds the value at the time reached). */
+LJ_API int lj_phi_combination(lj_context* ctx, const lj_operator* J, int p, const double* const* b, double h,
+                              double tol, double* w, const lj_krylov_options* kopt, lj_stats* stats, void* stream);
 
 /* ---- variable step sizes (Sec. 2.3) ------------------------------------------ */
 
@@ -287,6 +322,9 @@ LJ_API int lj_user_phi_vertical(lj_context* ctx, const lj_user_operator* J, cons
 LJ_API int lj_user_step(lj_context* ctx, int scheme, const lj_user_operator* J, double h, double tol,
                         double* u_out, double* err, const lj_options* opt, lj_stats* stats, int nstats,
                         int* ncalls, void* stream);
+LJ_API int lj_user_phi_combination(lj_context* ctx, const lj_user_operator* J, int p, const double* const* b,
+                                   double h, double tol, double* w, const lj_krylov_options* kopt, lj_stats* stats,
+                                   void* stream);
 
 /* ---- batching form --------------------------------------------------------- */
 

@@ -17,7 +17,7 @@ from typing import Sequence
 
 from . import _lib
 from ._lib import (  # noqa: F401
-    LJ_EHIP, LJ_EINVAL, LJ_ENOMEM, LJ_ENOTCONV, LJ_EPIRK4S3, LJ_EXPRB2, LJ_EXPRB43, LJ_EXPRB43_U3,
+    LJ_EHIP, LJ_EINVAL, LJ_ENOMEM, LJ_ENOTCONV, LJ_EPIRK4S3, LJ_EPIRK4S3_LEKRY, LJ_EXPRB2, LJ_EXPRB43, LJ_EXPRB43_U3,
     LJ_MAX_K, LJ_MAX_L, LJ_OK, LJ_OP_ADR2D, LJ_OP_ADVDIFF2D, LJ_OP_ALLENCAHN2D, LJ_OP_BRUSSELATOR2D, LJ_OP_BURGERS2D,
     LJ_OP_DIAG, LJ_OP_GRAYSCOTT2D, LejaLibraryError, lj_integrate_stats, lj_operator, lj_options, lj_stats, lj_step_record,
     lj_timing,
@@ -28,7 +28,8 @@ KIND_CODES = {
     "brusselator": LJ_OP_BRUSSELATOR2D, "burgers": LJ_OP_BURGERS2D, "grayscott": LJ_OP_GRAYSCOTT2D,
     "adr": LJ_OP_ADR2D,
 }
-SCHEMES = {"EXPRB2": LJ_EXPRB2, "EXPRB43_U3": LJ_EXPRB43_U3, "EXPRB43": LJ_EXPRB43, "EPIRK4S3": LJ_EPIRK4S3}
+SCHEMES = {"EXPRB2": LJ_EXPRB2, "EXPRB43_U3": LJ_EXPRB43_U3, "EXPRB43": LJ_EXPRB43, "EPIRK4S3": LJ_EPIRK4S3,
+           "EPIRK4S3_LEKRY": LJ_EPIRK4S3_LEKRY}
 
 
 class LejaError(RuntimeError):
@@ -315,6 +316,45 @@ def lj_user_step(ctx: Context, scheme: str, U: UserOperator, h: float, tol: floa
                                _stream_ptr(stream))
     _user_call(ctx, U, rc)
     return rc, [stats[i].as_dict() for i in range(ncalls.value)]
+
+
+def lj_default_krylov_options(**overrides) -> "_lib.lj_krylov_options":
+    k = _lib.lj_krylov_options()
+    lib().lj_default_krylov_options(C.byref(k))
+    for name, val in overrides.items():
+        setattr(k, name, val)
+    return k
+
+
+def _bvec(bs, n):
+    arr = (C.c_void_p * len(bs))()
+    for j, b in enumerate(bs):
+        arr[j] = None if b is None else _tensor_ptr(b, n, f"b[{j}]").value
+    return arr
+
+
+def lj_phi_combination(ctx: Context, J: Operator, bs: Sequence, h: float, tol: float, w, kopt=None, stream=None):
+    """w = sum_j phi_j(h J) b_j h^j (bs = [b_0, ..., b_p], None = zero) by Krylov.
+    Returns (rc, stats dict)."""
+    op = J.c_struct()
+    st = lj_stats()
+    rc = ctx._lib.lj_phi_combination(ctx.handle, C.byref(op), len(bs) - 1, _bvec(bs, J.n), float(h), float(tol),
+                                     _tensor_ptr(w, J.n, "w"), C.byref(kopt) if kopt is not None else None,
+                                     C.byref(st), _stream_ptr(stream))
+    ctx._check(rc)
+    return rc, st.as_dict(1)
+
+
+def lj_user_phi_combination(ctx: Context, U: "UserOperator", bs: Sequence, h: float, tol: float, w, kopt=None,
+                            stream=None):
+    op = U.c_struct()
+    st = lj_stats()
+    rc = ctx._lib.lj_user_phi_combination(ctx.handle, C.byref(op), len(bs) - 1, _bvec(bs, U.n), float(h),
+                                          float(tol), _tensor_ptr(w, U.n, "w"),
+                                          C.byref(kopt) if kopt is not None else None, C.byref(st),
+                                          _stream_ptr(stream))
+    _user_call(ctx, U, rc)
+    return rc, st.as_dict(1)
 
 
 def family_user_operator(ctx: Context, J: Operator, finite_difference: bool = False) -> UserOperator:

@@ -21,7 +21,7 @@ LJ_MLP_MODEL_FLOATS = 5414
 
 (LJ_OP_DIAG, LJ_OP_ADVDIFF2D, LJ_OP_ALLENCAHN2D, LJ_OP_BRUSSELATOR2D, LJ_OP_BURGERS2D, LJ_OP_GRAYSCOTT2D,
  LJ_OP_ADR2D) = range(7)
-LJ_EXPRB2, LJ_EXPRB43_U3, LJ_EXPRB43, LJ_EPIRK4S3 = 1, 2, 3, 4
+LJ_EXPRB2, LJ_EXPRB43_U3, LJ_EXPRB43, LJ_EPIRK4S3, LJ_EPIRK4S3_LEKRY = 1, 2, 3, 4, 5
 
 
 class LejaLibraryError(RuntimeError):
@@ -44,6 +44,11 @@ class lj_user_operator(C.Structure):
     _fields_ = [
         ("n", C.c_int64), ("rhs", lj_rhs_fn), ("jv", lj_jv_fn), ("user", C.c_void_p), ("state", C.c_void_p),
     ]
+
+
+class lj_krylov_options(C.Structure):
+    _fields_ = [("krylov_dim", C.c_int32), ("window", C.c_int32), ("max_substeps", C.c_int32),
+                ("reserved", C.c_int32)]
 
 
 class lj_options(C.Structure):
@@ -122,6 +127,11 @@ _PROTOS = {
                                          C.POINTER(C.c_double), _P]),
     "lj_rhs": (C.c_int, [_P, C.POINTER(lj_operator), _P, _P, _P]),
     "lj_jv": (C.c_int, [_P, C.POINTER(lj_operator), _P, _P, _P]),
+    "lj_default_krylov_options": (None, [C.POINTER(lj_krylov_options)]),
+    "lj_phi_combination": (C.c_int, [_P, C.POINTER(lj_operator), C.c_int, C.POINTER(_P), C.c_double, C.c_double,
+                                     _P, C.POINTER(lj_krylov_options), C.POINTER(lj_stats), _P]),
+    "lj_user_phi_combination": (C.c_int, [_P, C.POINTER(lj_user_operator), C.c_int, C.POINTER(_P), C.c_double,
+                                          C.c_double, _P, C.POINTER(lj_krylov_options), C.POINTER(lj_stats), _P]),
     "lj_user_phi_action": (C.c_int, [_P, C.POINTER(lj_user_operator), _P, _P, C.c_int, C.c_double, C.c_double,
                                      C.POINTER(lj_options), C.POINTER(lj_stats), _P]),
     "lj_user_phi_vertical": (C.c_int, [_P, C.POINTER(lj_user_operator), _P, C.c_int, C.POINTER(C.c_int),

@@ -1,0 +1,53 @@
+// Kernels of the Krylov evaluation of phi-function combinations (implemented
+// in krylov_kernels.hip): Arnoldi's process on the augmented matrix
+// A~ = [[J, B], [0, K]] of Sec. 2.1, with incomplete orthogonalisation.
+// Vectors are augmented: N grid values followed by p auxiliary entries.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace lj {
+
+constexpr int kKryBlock = 256;
+constexpr int kKryBlocksMax = 512;
+constexpr int kKryMaxDim = 64;   // largest Krylov dimension m
+constexpr int kKryMaxP = 4;      // highest phi index in a combination
+constexpr int kKryChunk = 8;     // window vectors per pass of the dot kernel
+
+int kry_grid(long n);
+
+// Arnoldi state shared by the kernels of one basis (device).
+struct KryDev {
+  long N;             // grid values
+  int p;              // auxiliary entries
+  long na;            // N + p, the augmented length
+  double* V;          // (m + 1) basis vectors, vector j at V + j * na
+  double* W;          // the product being orthogonalised (na)
+  const double* B[kKryMaxP];  // B = [b_p, ..., b_1] (nullptr: zero column)
+  double* H;          // (m + 1) x m Hessenberg matrix, row-major, row stride m
+  int m;              // Krylov dimension
+  double* part;       // kKryBlocksMax * (kKryMaxDim + 1) partial sums: dots, then norms
+  double* scalars;    // [0] beta, [1] breakdown column + 1 (0: none)
+};
+
+// V_0 = w / ||w||, scalars[0] = ||w|| (two kernels)
+hipError_t launch_kry_start(const KryDev& K, const double* w, hipStream_t s);
+// W[0:N] holds J V_j[0:N].  With tail: add B y (y = V_j[N:N+p]) and write
+// the shift K y into the tail first.  Then the dots <V_i, W> for window
+// entries d = d0 .. d0 + nd - 1 (i = lo + d, nd <= kKryChunk), partial sums
+// per block.  All dots are taken before W changes (classical Gram-Schmidt).
+hipError_t launch_kry_tail_dots(const KryDev& K, int j, int lo, int d0, int nd, bool tail, hipStream_t s);
+// the dots' sums (every block, block order) -> H[lo + d][j] for d < nd_total;
+// W -= h_d V_{lo+d} in order of d; partial sums of W^2
+hipError_t launch_kry_update(const KryDev& K, int j, int lo, int nd_total, hipStream_t s);
+// H[j+1][j] = ||W||; V_{j+1} = W / H[j+1][j] unless the basis broke down
+hipError_t launch_kry_scale(const KryDev& K, int j, hipStream_t s);
+// out = beta sum_{j < m} F_j V_j (augmented length)
+struct KryCoef {
+  double f[kKryMaxDim];
+};
+hipError_t launch_kry_combine(const KryDev& K, int m, double beta, const KryCoef& F, double* out, hipStream_t s);
+// w = [b_0 or 0; 0, ..., 0, 1]
+hipError_t launch_kry_init(double* w, const double* b0, long N, int p, hipStream_t s);
+
+}  // namespace lj

@@ -20,6 +20,7 @@
 #include "common.hpp"
 #include "kernels.hpp"
 #include "mlp.hpp"
+#include "krylov_kernels.hpp"
 #include "user_kernels.hpp"
 
 namespace lj {
@@ -39,6 +40,7 @@ enum Slot {
   W_IU0, W_IU1, W_IERR,            // variable-step integration: state ping-pong, error estimate
   W_UJ, W_UPT, W_UY, W_UPA, W_UPB, // user operators: product, finite-difference point, power vectors
   W_UFU, W_UXR, W_UD, W_UFX, W_UJD, W_UR0, W_UR1,  // f(u), stage remainders
+  W_KV, W_KW, W_KX, W_KC,          // Krylov: basis, product, augmented vector, LeKry third stage
   W_NSLOTS
 };
 
@@ -112,6 +114,10 @@ struct lj_context {
   UserStatus* h_ustatus = nullptr;  // pinned, coherent: written by the decision kernels
   double* d_upart = nullptr;        // kUserBlocksMax * (1 + kMaxK)
   std::vector<double> h_xi;
+  // Krylov: partial sums, Hessenberg matrix and scalars on the device, their pinned copy
+  double* d_kpart = nullptr;   // kKryBlocksMax * (kKryMaxDim + 1)
+  double* d_kH = nullptr;      // (kKryMaxDim + 1) * kKryMaxDim, then 2 scalars
+  double* h_kH = nullptr;      // pinned copy of d_kH
 };
 
 static std::string g_create_error;
@@ -1160,6 +1166,184 @@ int batch_tune(lj_batch* b) {
   return best;
 }
 
+// ---- Krylov evaluation of phi combinations (Sec. 2.1) ------------------------------
+struct KryOpts {
+  int m = 30;
+  int window = 2;
+  int max_substeps = 1000;
+};
+
+KryOpts resolve_krylov(lj_context* ctx, const lj_krylov_options* k) {
+  KryOpts r;
+  if (!k) return r;
+  r.m = k->krylov_dim;
+  r.window = k->window;
+  r.max_substeps = k->max_substeps;
+  if (r.m < 1 || r.m > kKryMaxDim) invalid(ctx, "krylov options: krylov_dim must be in [1, 64]");
+  if (r.window < 0) invalid(ctx, "krylov options: window must be >= 0");
+  if (r.max_substeps < 1) invalid(ctx, "krylov options: max_substeps must be >= 1");
+  return r;
+}
+
+// exp(A) of a small dense n x n matrix (row-major) by scaling and squaring of
+// a truncated Taylor series: A / 2^s with ||A / 2^s||_1 <= 1/2, 30 terms
+// (truncation below 2^-90 relative), then s squarings.
+void expm_small(const std::vector<double>& A, int n, std::vector<double>& E) {
+  double nrm = 0.0;
+  for (int c = 0; c < n; ++c) {
+    double col = 0.0;
+    for (int r = 0; r < n; ++r) col += std::fabs(A[(size_t)r * n + c]);
+    nrm = std::max(nrm, col);
+  }
+  int sq = 0;
+  if (nrm > 0.5) sq = (int)std::ceil(std::log2(nrm / 0.5));
+  const double scale = std::ldexp(1.0, -sq);
+  std::vector<double> X((size_t)n * n), T((size_t)n * n), T2((size_t)n * n);
+  for (size_t i = 0; i < X.size(); ++i) X[i] = A[i] * scale;
+  E.assign((size_t)n * n, 0.0);
+  for (int i = 0; i < n; ++i) E[(size_t)i * n + i] = 1.0;
+  T = E;  // X^k / k!
+  for (int k = 1; k <= 30; ++k) {
+    for (int r = 0; r < n; ++r)
+      for (int c = 0; c < n; ++c) {
+        double a = 0.0;
+        for (int q = 0; q < n; ++q) a += T[(size_t)r * n + q] * X[(size_t)q * n + c];
+        T2[(size_t)r * n + c] = a / (double)k;
+      }
+    T.swap(T2);
+    for (size_t i = 0; i < E.size(); ++i) E[i] += T[i];
+  }
+  for (int k = 0; k < sq; ++k) {
+    for (int r = 0; r < n; ++r)
+      for (int c = 0; c < n; ++c) {
+        double a = 0.0;
+        for (int q = 0; q < n; ++q) a += E[(size_t)r * n + q] * E[(size_t)q * n + c];
+        T2[(size_t)r * n + c] = a;
+      }
+    E.swap(T2);
+  }
+}
+
+// w = sum_{j=0}^{p} phi_j(h J) b_j h^j (b[j] may be nullptr) as the first block
+// of exp(h A~) [b_0; e_p], A~ = [[J, B], [0, K]] (Sec. 2.1 theorem), advanced
+// in substeps: each projects exp(tau A~) onto an m-dimensional Krylov space
+// (Arnoldi with an orthogonalisation window), accepts when the a-posteriori
+// estimate beta h_{m+1,m} tau |e_m^T phi_1(tau H_m) e_1| is at most
+// tol (tau / h) beta, and sizes the next substep from it; a rejected substep
+// reuses the basis with a smaller tau.
+int krylov_impl(lj_context* ctx, const OpDev& op, int p, const double* const* b, double h, double tol,
+                double* w_out, const KryOpts& ko, lj_stats* st, hipStream_t s) {
+  const long N = (long)nvals(op);
+  const long na = N + p;
+  const int m = ko.m;
+  if (!ctx->d_kpart)
+    HIPCHK(ctx, hipMalloc(&ctx->d_kpart, (size_t)kKryBlocksMax * (kKryMaxDim + 1) * sizeof(double)));
+  const size_t hsz = (size_t)(kKryMaxDim + 1) * kKryMaxDim + 2;
+  if (!ctx->d_kH) HIPCHK(ctx, hipMalloc(&ctx->d_kH, hsz * sizeof(double)));
+  if (!ctx->h_kH) HIPCHK(ctx, hipHostMalloc(&ctx->h_kH, hsz * sizeof(double), hipHostMallocDefault));
+  KryDev K;
+  std::memset(&K, 0, sizeof(K));
+  K.N = N;
+  K.p = p;
+  K.na = na;
+  K.V = slot(ctx, W_KV, (size_t)(m + 1) * na);
+  K.W = slot(ctx, W_KW, na);
+  for (int k = 0; k < p; ++k) K.B[k] = b[p - k];  // [b_p, ..., b_1]
+  K.H = ctx->d_kH;
+  K.m = m;
+  K.part = ctx->d_kpart;
+  K.scalars = ctx->d_kH + (size_t)(kKryMaxDim + 1) * kKryMaxDim;
+  double* X = slot(ctx, W_KX, na);
+  HIPCHK(ctx, launch_kry_init(X, b[0], N, p, s));
+  std::memset(st, 0, sizeof(*st));
+  for (int k = 0; k < LJ_MAX_K; ++k) {
+    st->m_star[k] = -1;
+    st->substeps[k] = 1;
+  }
+  bool converged = true;
+  int substeps = 0, rejections = 0, products = 0, attempts = 0;
+  double t = 0.0, tau = h, last_est = 0.0;
+  std::vector<double> Hm, Mx, E;
+  while (t < h) {
+    if (substeps >= ko.max_substeps || attempts >= 10 * ko.max_substeps) {
+      converged = false;
+      break;
+    }
+    HIPCHK(ctx, launch_kry_start(K, X, s));
+    HIPCHK(ctx, hipMemcpyAsync(ctx->h_kH + hsz - 2, K.scalars, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(ctx, hipStreamSynchronize(s));
+    if (!(ctx->h_kH[hsz - 2] > 0.0)) break;  // w = 0 stays 0
+    for (int j = 0; j < m; ++j) {
+      const double* vj = K.V + (size_t)j * na;
+      if (is_user(op)) {
+        user_jv(ctx, vj, K.W, s);
+      } else {
+        HIPCHK(ctx, launch_family_jv(op, vj, K.W, s));
+      }
+      const int lo = ko.window > 0 ? std::max(0, j - ko.window + 1) : 0;
+      const int ndt = j - lo + 1;
+      for (int d0 = 0; d0 < ndt; d0 += kKryChunk)
+        HIPCHK(ctx, launch_kry_tail_dots(K, j, lo, d0, std::min(kKryChunk, ndt - d0), d0 == 0, s));
+      HIPCHK(ctx, launch_kry_update(K, j, lo, ndt, s));
+      HIPCHK(ctx, launch_kry_scale(K, j, s));
+    }
+    HIPCHK(ctx, hipMemcpyAsync(ctx->h_kH, ctx->d_kH, hsz * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(ctx, hipStreamSynchronize(s));
+    const double beta = ctx->h_kH[hsz - 2];
+    const int brk = (int)ctx->h_kH[hsz - 1];  // breakdown at column brk - 1
+    const int me = brk > 0 ? brk : m;
+    products += me;
+    const bool exact = me < m;
+    // H_m with only the entries this basis wrote (the window and the subdiagonal)
+    Hm.assign((size_t)(me + 1) * me, 0.0);
+    for (int c = 0; c < me; ++c) {
+      const int lo = ko.window > 0 ? std::max(0, c - ko.window + 1) : 0;
+      for (int r = lo; r <= c + 1 && r <= me; ++r) Hm[(size_t)r * me + c] = ctx->h_kH[(size_t)r * m + c];
+    }
+    while (true) {
+      ++attempts;
+      tau = std::min(tau, h - t);
+      const int n1 = me + 1;
+      Mx.assign((size_t)n1 * n1, 0.0);
+      for (int r = 0; r < me; ++r)
+        for (int c = 0; c < me; ++c) Mx[(size_t)r * n1 + c] = tau * Hm[(size_t)r * me + c];
+      Mx[me] = 1.0;  // row 0, column me: e_1
+      expm_small(Mx, n1, E);
+      const double est = exact ? 0.0 : beta * Hm[(size_t)me * me + (me - 1)] * tau * std::fabs(E[(size_t)(me - 1) * n1 + me]);
+      const double allow = tol * (tau / h) * beta;
+      const double fac = (est == 0.0) ? 2.0
+                                      : std::min(2.0, std::max(0.1, 0.9 * std::pow(allow / est, 1.0 / (me + 1))));
+      if (est <= allow) {
+        KryCoef F;
+        std::memset(&F, 0, sizeof(F));
+        for (int c = 0; c < me; ++c) F.f[c] = E[(size_t)c * n1];
+        HIPCHK(ctx, launch_kry_combine(K, me, beta, F, X, s));
+        t = (tau >= h - t) ? h : t + tau;
+        ++substeps;
+        last_est = est;
+        tau *= fac;
+        break;
+      }
+      ++rejections;
+      tau *= fac;
+      if (attempts >= 10 * ko.max_substeps) {
+        converged = false;
+        break;
+      }
+    }
+    if (!converged) break;
+  }
+  HIPCHK(ctx, hipMemcpyAsync(w_out, X, (size_t)N * sizeof(double), hipMemcpyDeviceToDevice, s));
+  HIPCHK(ctx, hipStreamSynchronize(s));
+  st->m_star[0] = products;
+  st->substeps[0] = substeps;
+  st->iters_total = products;
+  st->rejections = rejections;
+  st->converged = converged ? 1 : 0;
+  st->err_est[0] = last_est;
+  return converged ? LJ_OK : LJ_ENOTCONV;
+}
+
 }  // namespace
 
 // ===========================================================================
@@ -1292,6 +1476,9 @@ LJ_API void lj_destroy(lj_context* ctx) {
   if (ctx->d_ustate) (void)hipFree(ctx->d_ustate);
   if (ctx->h_ustatus) (void)hipHostFree(ctx->h_ustatus);
   if (ctx->d_upart) (void)hipFree(ctx->d_upart);
+  if (ctx->d_kpart) (void)hipFree(ctx->d_kpart);
+  if (ctx->d_kH) (void)hipFree(ctx->d_kH);
+  if (ctx->h_kH) (void)hipHostFree(ctx->h_kH);
   delete ctx;
 }
 
@@ -1378,6 +1565,51 @@ LJ_API int lj_user_phi_action(lj_context* ctx, const lj_user_operator* J, const 
   const double a = 1.0;
   double* ws[1] = {w};
   return lj_user_phi_vertical(ctx, J, v, 1, &l, &a, h, tol, ws, opt, stats, stream);
+}
+
+LJ_API void lj_default_krylov_options(lj_krylov_options* k) {
+  if (!k) return;
+  const KryOpts d;
+  k->krylov_dim = d.m;
+  k->window = d.window;
+  k->max_substeps = d.max_substeps;
+  k->reserved = 0;
+}
+
+int combination_impl(lj_context* ctx, const OpDev& op, int p, const double* const* b, double h, double tol,
+                     double* w, const lj_krylov_options* kopt, lj_stats* stats, hipStream_t s) {
+  const KryOpts ko = resolve_krylov(ctx, kopt);
+  if (p < 0 || p > kKryMaxP) invalid(ctx, "p must be in [0, 4]");
+  if (!b) invalid(ctx, "b must not be NULL");
+  if (!(h >= 0.0) || !std::isfinite(h)) invalid(ctx, "h must be finite and >= 0");
+  if (!(tol > 0.0) || !std::isfinite(tol)) invalid(ctx, "tol must be finite and > 0");
+  check_vec(ctx, op, w, "w");
+  for (int j = 0; j <= p; ++j) {
+    if (!b[j]) continue;
+    check_vec(ctx, op, b[j], "b[j]");
+    if (b[j] == w) invalid(ctx, "w must not alias b[j]");
+  }
+  if (w == op.state) invalid(ctx, "w must not alias the operator state");
+  lj_stats local;
+  return krylov_impl(ctx, op, p, b, h, tol, w, ko, stats ? stats : &local, s);
+}
+
+LJ_API int lj_phi_combination(lj_context* ctx, const lj_operator* J, int p, const double* const* b, double h,
+                              double tol, double* w, const lj_krylov_options* kopt, lj_stats* stats, void* stream) {
+  return guarded(ctx, [&]() {
+    const OpDev op = make_op(ctx, J);
+    return combination_impl(ctx, op, p, b, h, tol, w, kopt, stats, reinterpret_cast<hipStream_t>(stream));
+  });
+}
+
+LJ_API int lj_user_phi_combination(lj_context* ctx, const lj_user_operator* J, int p, const double* const* b,
+                                   double h, double tol, double* w, const lj_krylov_options* kopt, lj_stats* stats,
+                                   void* stream) {
+  return guarded(ctx, [&]() {
+    const hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    UserScope us(ctx, J, false, s);
+    return combination_impl(ctx, us.op, p, b, h, tol, w, kopt, stats, s);
+  });
 }
 
 LJ_API int lj_phi_vertical(lj_context* ctx, const lj_operator* J, const double* v, int K, const int* l,
@@ -1498,6 +1730,12 @@ int step_impl(lj_context* ctx, int scheme, const OpDev& op, Opts o, double h, do
       lincomb(ctx, n, S.out[o2], S.nsrc[o2], S.c[o2], src, s);
     }
   };
+  std::vector<lj_stats> log;
+  bool ok = true;
+  auto krylov_log = [&](const lj_stats& kst, int rc) {
+    if (rc != LJ_OK) ok = false;
+    log.push_back(kst);
+  };
   auto scheme_steps = [&](auto&& act) {
     double* fu = slot(ctx, W_FU, n);
     double* v = slot(ctx, W_V, n);
@@ -1601,6 +1839,62 @@ int step_impl(lj_context* ctx, int scheme, const OpDev& op, Opts o, double h, do
       } else {
         finish(B, D3, nullptr);
       }
+    } else if (scheme == LJ_EPIRK4S3_LEKRY) {
+      // LeKry (Sec. 5.1 text): internal stages by Leja (vertical), the third
+      // stage's phi_1(hJ) h f(u) + phi_3(hJ) D_3 as one augmented exponential
+      // by Krylov (b_1 = f(u), b_3 = D_3 / h^3), the phi_4 error term by Leja
+      double* A = slot(ctx, W_A, n);
+      double* B = slot(ctx, W_B, n);
+      double* T3 = slot(ctx, W_T3, n);
+      double* T4 = slot(ctx, W_T4, n);
+      double* D4 = slot(ctx, W_D4, n);
+      double* KC = slot(ctx, W_KC, n);
+      {
+        const int ls[2] = {1, 1};
+        const double as[2] = {1.0 / 8.0, 1.0 / 9.0};
+        double* outs[2] = {A, B};
+        act(v, 2, ls, as, outs);
+      }
+      {
+        StageArgs S = stage_args();
+        S.nrem = 2;
+        S.nterm[0] = 1;
+        S.a[0][0] = 1.0 / 8.0;
+        S.X[0][0] = A;
+        S.nterm[1] = 1;
+        S.a[1][0] = 1.0 / 9.0;
+        S.X[1][0] = B;
+        S.nout = 2;
+        S.nsrc[0] = 2;
+        S.src[0][0] = 0;
+        S.c[0][0] = h * (1892.0 - 2.0 * 1458.0);
+        S.src[0][1] = 1;
+        S.c[0][1] = h * 1458.0;
+        S.out[0] = T3;
+        S.nsrc[1] = 2;
+        S.src[1][0] = 0;
+        S.c[1][0] = h * (-42336.0 + 2.0 * 34992.0);
+        S.src[1][1] = 1;
+        S.c[1][1] = h * -34992.0;
+        S.out[1] = T4;
+        stage(S);
+      }
+      {
+        double* b3 = slot(ctx, W_C, n);
+        const double a3 = 1.0 / (h * h * h);
+        const double* x3[1] = {T3};
+        lincomb(ctx, n, b3, 1, &a3, x3, s);
+        const double* bs[4] = {nullptr, fu, nullptr, b3};
+        lj_stats kst;
+        const int rc = krylov_impl(ctx, op, 3, bs, h, tol, KC, KryOpts{}, &kst, s);
+        krylov_log(kst, rc);
+      }
+      {
+        const int ls[1] = {4};
+        const double as[1] = {1.0};
+        act(T4, 1, ls, as, &D4);
+      }
+      finish(KC, nullptr, D4);
     } else {  // EPIRK4s3
       double* A = slot(ctx, W_A, n);
       double* B = slot(ctx, W_B, n);
@@ -1653,15 +1947,13 @@ int step_impl(lj_context* ctx, int scheme, const OpDev& op, Opts o, double h, do
       finish(C, D3, D4);
     }
   };
-  std::vector<lj_stats> log;
-  bool ok = true;
   int pit = 0;
   // ---- first try: every launch of the step enqueued back to back.  The
   // first action runs the power iteration (unless a bound is given) and
   // leaves the bound on the device for the others; statuses are read once
   // at the end.  If some expansion was rejected, the step is redone below
   // synchronously, with substeps, on the bound found.
-  const bool try_async = o.substeps <= 1 && !o.use_proposal && !is_user(op);
+  const bool try_async = o.substeps <= 1 && !o.use_proposal && !is_user(op) && scheme != LJ_EPIRK4S3_LEKRY;
   double lam_found = o.bound;
   if (try_async) {
     struct Pending {
@@ -1759,7 +2051,7 @@ LJ_API int lj_step(lj_context* ctx, int scheme, const lj_operator* J, double h, 
   return guarded(ctx, [&]() {
     const OpDev op = make_op(ctx, J);
     Opts o = resolve(ctx, opt);
-    if (scheme < LJ_EXPRB2 || scheme > LJ_EPIRK4S3) invalid(ctx, "unknown scheme");
+    if (scheme < LJ_EXPRB2 || scheme > LJ_EPIRK4S3_LEKRY) invalid(ctx, "unknown scheme");
     if (op.state == nullptr) invalid(ctx, "lj_step needs the state u in J->state");
     if (!std::isfinite(h)) invalid(ctx, "h must be finite");
     if (!(tol > 0.0) || !std::isfinite(tol)) invalid(ctx, "tol must be finite and > 0");
@@ -1769,7 +2061,7 @@ LJ_API int lj_step(lj_context* ctx, int scheme, const lj_operator* J, double h, 
       check_vec(ctx, op, err, "err");
       if (err == op.state || err == u_out) invalid(ctx, "err must not alias the state or u_out");
     }
-    const int want = (scheme == LJ_EXPRB2) ? 1 : (scheme == LJ_EXPRB43) ? 4 : 3;
+    const int want = (scheme == LJ_EXPRB2) ? 1 : (scheme == LJ_EXPRB43) ? 4 : 3;  // EPIRK4s3 (LeKry): 3
     if (ncalls) *ncalls = want;
     if (stats && nstats < want) invalid(ctx, "nstats is smaller than the number of Leja calls of the scheme");
     return step_impl(ctx, scheme, op, o, h, tol, u_out, err, stats, reinterpret_cast<hipStream_t>(stream));
@@ -1783,7 +2075,7 @@ LJ_API int lj_user_step(lj_context* ctx, int scheme, const lj_user_operator* J, 
     const hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     Opts o = resolve(ctx, opt);
     if (o.use_proposal) invalid(ctx, "the learned proposal needs a built-in operator family");
-    if (scheme < LJ_EXPRB2 || scheme > LJ_EPIRK4S3) invalid(ctx, "unknown scheme");
+    if (scheme < LJ_EXPRB2 || scheme > LJ_EPIRK4S3_LEKRY) invalid(ctx, "unknown scheme");
     if (!std::isfinite(h)) invalid(ctx, "h must be finite");
     if (!(tol > 0.0) || !std::isfinite(tol)) invalid(ctx, "tol must be finite and > 0");
     UserScope us(ctx, J, true, s);
@@ -1793,7 +2085,7 @@ LJ_API int lj_user_step(lj_context* ctx, int scheme, const lj_user_operator* J, 
       check_vec(ctx, us.op, err, "err");
       if (err == us.op.state || err == u_out) invalid(ctx, "err must not alias the state or u_out");
     }
-    const int want = (scheme == LJ_EXPRB2) ? 1 : (scheme == LJ_EXPRB43) ? 4 : 3;
+    const int want = (scheme == LJ_EXPRB2) ? 1 : (scheme == LJ_EXPRB43) ? 4 : 3;  // EPIRK4s3 (LeKry): 3
     if (ncalls) *ncalls = want;
     if (stats && nstats < want) invalid(ctx, "nstats is smaller than the number of Leja calls of the scheme");
     return step_impl(ctx, scheme, us.op, o, h, tol, u_out, err, stats, s);
@@ -1831,7 +2123,8 @@ LJ_API int lj_integrate(lj_context* ctx, int scheme, const lj_operator* J, doubl
   return guarded(ctx, [&]() {
     const OpDev op0 = make_op(ctx, J);
     const Opts o = resolve(ctx, opt);
-    if (scheme != LJ_EPIRK4S3 && scheme != LJ_EXPRB43) invalid(ctx, "lj_integrate needs an embedded scheme");
+    if (scheme != LJ_EPIRK4S3 && scheme != LJ_EXPRB43 && scheme != LJ_EPIRK4S3_LEKRY)
+      invalid(ctx, "lj_integrate needs an embedded scheme");
     if (op0.state == nullptr) invalid(ctx, "lj_integrate needs u(0) in J->state");
     if (!(T >= 0.0) || !std::isfinite(T)) invalid(ctx, "T must be finite and >= 0");
     if (!(dt0 > 0.0) || !std::isfinite(dt0)) invalid(ctx, "dt0 must be finite and > 0");

@@ -37,7 +37,7 @@ def test_every_declared_symbol_is_exported(lib):
 
 def test_struct_layout_matches_c(tmp_path):
     from paper_2211_08948_amd._lib import (lj_batch_info_t, lj_integrate_stats, lj_operator, lj_options, lj_stats,
-                                           lj_step_record, lj_timing, lj_user_operator)
+                                           lj_krylov_options, lj_step_record, lj_timing, lj_user_operator)
     prog = tmp_path / "sz.c"
     fields = {
         "lj_operator": ["kind", "nx", "dx", "coef", "state"],
@@ -50,6 +50,7 @@ def test_struct_layout_matches_c(tmp_path):
         "lj_integrate_stats": ["accepted", "rejected", "products", "t", "dt_next"],
         "lj_step_record": ["t", "dt", "err", "products", "accepted"],
         "lj_user_operator": ["n", "rhs", "jv", "user", "state"],
+        "lj_krylov_options": ["krylov_dim", "window", "max_substeps", "reserved"],
     }
     lines = ['#include <stdio.h>', '#include <stddef.h>', f'#include "{HEADER}"', "int main(void){"]
     for s, fs in fields.items():
@@ -64,7 +65,8 @@ def test_struct_layout_matches_c(tmp_path):
                                                           check=True).stdout.split("\n") if l)
     py = {"lj_operator": lj_operator, "lj_options": lj_options, "lj_stats": lj_stats, "lj_timing": lj_timing,
           "lj_batch_info_t": lj_batch_info_t, "lj_integrate_stats": lj_integrate_stats,
-          "lj_step_record": lj_step_record, "lj_user_operator": lj_user_operator}
+          "lj_step_record": lj_step_record, "lj_user_operator": lj_user_operator,
+          "lj_krylov_options": lj_krylov_options}
     for s, fs in fields.items():
         assert int(out[s]) == C.sizeof(py[s]), s
         for f in fs:
@@ -75,6 +77,7 @@ def test_enum_constants_match_c(tmp_path):
     from paper_2211_08948_amd import _lib
     names = ["LJ_OP_DIAG", "LJ_OP_ADVDIFF2D", "LJ_OP_ALLENCAHN2D", "LJ_OP_BRUSSELATOR2D", "LJ_OP_BURGERS2D",
              "LJ_OP_GRAYSCOTT2D", "LJ_OP_ADR2D", "LJ_EXPRB2", "LJ_EXPRB43_U3", "LJ_EXPRB43", "LJ_EPIRK4S3",
+             "LJ_EPIRK4S3_LEKRY",
              "LJ_OK", "LJ_ENOTCONV", "LJ_EINVAL", "LJ_EHIP", "LJ_ENOMEM", "LJ_MAX_K", "LJ_MAX_L"]
     prog = tmp_path / "en.c"
     body = "".join(f'printf("{n} %d\\n", (int){n});' for n in names)
@@ -115,6 +118,8 @@ def test_null_arguments_are_rejected_without_device(lib):
     assert lib.lj_step(None, 1, None, 1.0, 1e-10, None, None, None, None, 0, None, None) == -1
     assert lib.lj_timing_enable(None, 1) == -1
     assert lib.lj_jv(None, None, None, None, None) == -1
+    assert lib.lj_phi_combination(None, None, 1, None, 1.0, 1e-10, None, None, None, None) == -1
+    assert lib.lj_user_phi_combination(None, None, 1, None, 1.0, 1e-10, None, None, None, None) == -1
     assert lib.lj_user_phi_action(None, None, None, None, 1, 1.0, 1e-10, None, None, None) == -1
     assert lib.lj_user_phi_vertical(None, None, None, 1, None, None, 1.0, 1e-10, None, None, None, None) == -1
     assert lib.lj_user_step(None, 1, None, 1.0, 1e-10, None, None, None, None, 0, None, None) == -1
