@@ -22,6 +22,7 @@ Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
                         Allen-Cahn 1024^2..8192^2)
        python bench.py --form adaptive   (variable step sizes, EPIRK4s3 on 512^2 Allen-Cahn)
        python bench.py --form user   (operators as callbacks: phi_1 on 512^2 Allen-Cahn, fused vs callbacks)
+       python bench.py --form lekry  (EPIRK4s3 on 512^2 Allen-Cahn: all-Leja vs LeKry)
        python bench.py --copy-calibration   (plain copy kernel for counter scaling)
 """
 from __future__ import annotations
@@ -391,6 +392,46 @@ def bench_user(args):
     ctx.close()
 
 
+def bench_lekry(args):
+    """EPIRK4s3 on 512^2 Allen-Cahn at 10x CFL, bound given: all stages by
+    Leja (fused action kernels) against LeKry (Leja internal stages, the third
+    stage by Krylov); one JSON line each (not the headline metric)."""
+    import statistics
+
+    import torch
+
+    import paper_2211_08948_amd as lj
+    from workloads import allen_cahn_noise
+    prob = allen_cahn_noise(args.n, eps=1e-3, seed=2)
+    ctx = lj.Context(0)
+    J = lj.operator_from(prob, "cuda:0")
+    h = CFL_MULT * prob.h_cfl
+    lam = lj.lj_spectral_bound(ctx, J, 20)
+    o = lj.lj_default_options(bound=lam)
+    u_out = torch.empty_like(J.state)
+    err = torch.empty_like(u_out)
+    for scheme in ("EPIRK4S3", "EPIRK4S3_LEKRY"):
+        fn = lambda: lj.lj_step(ctx, scheme, J, h, TOL, u_out, err, o)
+        for _ in range(2):
+            fn()
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(max(args.steps // 5, 5)):
+            t0 = time.perf_counter()
+            rc, sts = fn()
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t0)
+        dt = statistics.median(ts)
+        rec = {"metric": "step time", "value": round(dt * 1e3, 4), "unit": "ms", "n_gpus": 1,
+               "higher_is_better": False, "dtype": "f64", "data": "synthetic",
+               "config": {"workload": f"allen-cahn {args.n}x{args.n} periodic, eps 1e-3, u0~U[-0.1,0.1] seed 2, "
+                                      f"one {scheme} step at 10x CFL, bound given, tol 1e-10"},
+               "calls": [{"m_star": s["m_star"][:3], "substeps": s["substeps"][:3], "products": s["iters_total"]}
+                         for s in sts]}
+        print(json.dumps(rec), flush=True)
+    ctx.close()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -399,7 +440,7 @@ def main():
     ap.add_argument("--n", type=int, default=512, help="grid points per axis (default: the 512^2 workload)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true")
-    ap.add_argument("--form", choices=["plain", "batch", "sweep", "adaptive", "user"], default="plain")
+    ap.add_argument("--form", choices=["plain", "batch", "sweep", "adaptive", "user", "lekry"], default="plain")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}): the multi-GPU path is not "
@@ -419,6 +460,9 @@ def main():
         return
     if args.form == "user":
         bench_user(args)
+        return
+    if args.form == "lekry":
+        bench_lekry(args)
         return
 
     import torch
