@@ -60,18 +60,22 @@ def diag_closed_form(lam: np.ndarray, v: np.ndarray, l: int, h: float, phi_fn) -
     return np.array([phi_fn(l, h * x) * vi for x, vi in zip(lam, v)])
 
 
-def advdiff_symbol(nx, ny, dx, dy, nu, ax, ay) -> np.ndarray:
-    """Fourier symbol sigma[ky, kx] of nu*Lap - ax*Dx - ay*Dy (centred, periodic).
+def advdiff_symbol_at(tx, ty, dx, dy, nu, ax, ay):
+    """Fourier symbol of nu*Lap - ax*Dx - ay*Dy (centred, periodic) for the
+    mode e^{i(theta_x i + theta_y j)} (theta may be arrays): the second
+    difference gives (2 cos theta - 2)/dx^2 and the centred first difference
+    i sin(theta)/dx."""
+    lap = (2.0 * np.cos(tx) - 2.0) / dx ** 2 + (2.0 * np.cos(ty) - 2.0) / dy ** 2
+    adv = 1j * (ax * np.sin(tx) / dx + ay * np.sin(ty) / dy)
+    return nu * lap - adv
 
-    For the mode e^{i(theta_x i + theta_y j)}: the second difference gives
-    (2 cos theta - 2)/dx^2 and the centred first difference i sin(theta)/dx.
-    """
+
+def advdiff_symbol(nx, ny, dx, dy, nu, ax, ay) -> np.ndarray:
+    """Fourier symbol sigma[ky, kx] of every mode of an nx x ny grid."""
     tx = 2.0 * np.pi * np.fft.fftfreq(nx)  # theta_x = 2 pi k / nx
     ty = 2.0 * np.pi * np.fft.fftfreq(ny)
     TX, TY = np.meshgrid(tx, ty, indexing="xy")
-    lap = (2.0 * np.cos(TX) - 2.0) / dx ** 2 + (2.0 * np.cos(TY) - 2.0) / dy ** 2
-    adv = 1j * (ax * np.sin(TX) / dx + ay * np.sin(TY) / dy)
-    return nu * lap - adv
+    return advdiff_symbol_at(TX, TY, dx, dy, nu, ax, ay)
 
 
 def fourier_closed_form(sigma: np.ndarray, v: np.ndarray, l: int, h: float) -> np.ndarray:

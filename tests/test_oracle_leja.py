@@ -371,3 +371,33 @@ def test_adr_near_normal_decisions_are_stable(monkeypatch):
             st = phi_action(op, v, l, h, 1e-10)[1]
             monkeypatch.undo()
             assert st.m_star == ref.m_star and st.substeps == ref.substeps
+
+
+def _mode_sum(n, modes, coef_fn, idx_i, idx_j):
+    """Re(sum_k A_k c_k e^{i(2 pi (kx i + ky j)/n + theta_k)}) at points (i, j)."""
+    out = np.zeros(len(idx_i))
+    for kx, ky, A, th in modes:
+        ph = 2 * np.pi * (kx * idx_i + ky * idx_j) / n + th
+        out += (A * coef_fn(kx, ky) * np.exp(1j * ph)).real
+    return out
+
+
+def test_fourier_mode_closed_form_any_size():
+    # the expected values of the maximum-size GPU test: for a sum of Fourier
+    # modes, J acts by the symbol and phi_l(hJ) by phi_l(h sigma), point by point
+    from oracle.exact import advdiff_symbol_at, phi_scalar_expm
+    from workloads import fourier_modes
+    n, nu = 48, 1.0
+    dx = 1.0 / n
+    a = nu / dx
+    p = Problem("advdiff", n, n, 1, dx, dx, (nu, a, a), None, dx * dx / (4 * nu))
+    op = Operator(p)
+    v, modes = fourier_modes(n, 3, seed=11, kmax=12)
+    jj, ii = np.divmod(np.arange(n * n), n)
+    sig = lambda kx, ky: advdiff_symbol_at(2 * np.pi * kx / n, 2 * np.pi * ky / n, dx, dx, nu, a, a)
+    assert np.allclose(_mode_sum(n, modes, lambda kx, ky: 1.0, ii, jj), v, atol=1e-12)
+    assert np.allclose(_mode_sum(n, modes, sig, ii, jj), op.jv(v), rtol=0, atol=1e-9 * np.max(np.abs(op.jv(v))))
+    h = 10 * p.h_cfl
+    ref = _mode_sum(n, modes, lambda kx, ky: phi_scalar_expm(1, h * sig(kx, ky)), ii, jj)
+    w, st = phi_action(op, v, 1, h, 1e-14)
+    assert st.converged and rel(w, ref) <= 1e-12

@@ -13,6 +13,7 @@ from .problems import (  # noqa: F401
     brusselator_perturbed,
     burgers_sines,
     diag_problem,
+    fourier_modes,
     gray_scott_spots,
     batch_instances,
     proposal_training_set,

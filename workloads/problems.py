@@ -156,6 +156,25 @@ def adr_neumann(n: int = 256, alpha: float = 1e-2, beta: float = -10.0, rate: fl
                    dx * dx / (4.0 * alpha))
 
 
+def fourier_modes(n: int, count: int = 3, seed: int = 11, kmax: int = 40):
+    """v[j, i] = sum_k A_k cos(2 pi (kx_k i + ky_k j) / n + theta_k) on an n x n
+    grid (flat, row-major), wave numbers uniform in [1, kmax], A ~ U[0.5, 1],
+    theta ~ U[0, 2 pi) (seeded).  Returns (v, [(kx, ky, A, theta), ...])."""
+    rng = _rng(seed)
+    modes = []
+    i = np.arange(n, dtype=np.float64)
+    v = np.zeros((n, n))
+    for _ in range(count):
+        kx, ky = (int(x) for x in rng.integers(1, kmax + 1, size=2))
+        A, th = float(rng.uniform(0.5, 1.0)), float(rng.uniform(0.0, 2.0 * np.pi))
+        ax = 2.0 * np.pi * kx * i / n + th
+        ay = 2.0 * np.pi * ky * i / n
+        # cos(ax + ay) = cos ax cos ay - sin ax sin ay, rows j, columns i
+        v += A * (np.outer(np.cos(ay), np.cos(ax)) - np.outer(np.sin(ay), np.sin(ax)))
+        modes.append((kx, ky, A, th))
+    return v.ravel(), modes
+
+
 def burgers_sines(n: int = 2048, nu: float = 1e-3, seed: int = 5, modes: int = 8) -> Problem:
     """Viscous Burgers u_t = nu Lap u - (1/2)(d_x + d_y)(u^2) on [0,1)^2.
 
