@@ -12,8 +12,8 @@ Sec. 2.3 (automatic step size control):
 Readings where the text is silent:
   * e_n = ||u_4 - u_3||_2 / ||u_4||_2, the embedded estimate relative to the
     new solution; a step is accepted when e_n <= tol;
-  * p is the order of the embedded lower-order solution (3 for EPIRK4s3 and
-    EXPRB43), so that e_n ~ dt^{p+1};
+  * p is the order of the embedded lower-order solution (3 for EPIRK4s3, its
+    LeKry form and EXPRB43), so that e_n ~ dt^{p+1};
   * c_n = the step's cost per unit time: its Jacobian-vector products
     (power iteration + Newton terms of every expansion, substeps included)
     divided by dt_n -- the controller's purpose is the least total cost to
@@ -45,7 +45,7 @@ BETA = 0.26862269
 LAMBDA = 1.37412002
 DELTA = 0.64446017
 
-EMBEDDED_ORDER = {"EPIRK4S3": 3, "EXPRB43": 3}
+EMBEDDED_ORDER = {"EPIRK4S3": 3, "EXPRB43": 3, "EPIRK4S3_LEKRY": 3}
 RETRY_SAFETY = 0.9  # retry after a rejection at 0.9 x the traditional size (a reading; see above)
 
 

@@ -53,6 +53,13 @@ def test_allen_cahn_epirk4s3_matches_oracle(gpu):
     assert orc.rejected >= 1  # the first size is too large: a rejection and a retry
 
 
+def test_allen_cahn_lekry_matches_oracle(gpu):
+    # the LeKry form of EPIRK4s3: the third stage by Krylov, its products
+    # counted in the cost controller's cost
+    prob = allen_cahn_noise(32, eps=1e-2, seed=2, amp=0.5)
+    _compare(gpu, prob, prob.state, 2.0 * prob.h_cfl, prob.h_cfl, 1e-6, "EPIRK4S3_LEKRY", 1e-12)
+
+
 def test_brusselator_exprb43_matches_oracle(gpu):
     prob = brusselator_perturbed(16, D=2e-2, seed=3, amp=0.3)
     _compare(gpu, prob, prob.state, 20.0 * prob.h_cfl, 2.0 * prob.h_cfl, 1e-5, "EXPRB43", 1e-12)
