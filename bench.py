@@ -23,6 +23,7 @@ Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
        python bench.py --form adaptive   (variable step sizes, EPIRK4s3 on 512^2 Allen-Cahn)
        python bench.py --form user   (operators as callbacks: phi_1 on 512^2 Allen-Cahn, fused vs callbacks)
        python bench.py --form lekry  (EPIRK4s3 on 512^2 Allen-Cahn: all-Leja vs LeKry)
+       python bench.py --form ceiling  (attainable HBM bandwidth: copy, read, Newton-step pattern)
        python bench.py --copy-calibration   (plain copy kernel for counter scaling)
 """
 from __future__ import annotations
@@ -432,6 +433,21 @@ def bench_lekry(args):
     ctx.close()
 
 
+def bench_ceiling(args):
+    """The attainable HBM bandwidth of the device (copy, read-only, and the
+    Newton step's 3-read 2-write pattern over 1 GiB vectors): the practical
+    ceiling to read the roofline fractions against (one JSON line)."""
+    import paper_2211_08948_amd as lj
+    bw = lj.lj_measure_bandwidth(1 << 30)
+    rec = {"metric": "attainable HBM bandwidth", "value": round(bw["newton_step"], 1), "unit": "GB/s", "n_gpus": 1,
+           "higher_is_better": True, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": "streaming FP64 kernels over 1 GiB vectors, 1024 blocks x 256 threads, best of 5"},
+           "copy_gbs": round(bw["copy"], 1), "read_gbs": round(bw["read"], 1),
+           "newton_step_gbs": round(bw["newton_step"], 1), "peak_gbs": HBM_PEAK_GBS,
+           "fractions_of_peak": {k: round(v / HBM_PEAK_GBS, 4) for k, v in bw.items()}}
+    print(json.dumps(rec), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -440,7 +456,8 @@ def main():
     ap.add_argument("--n", type=int, default=512, help="grid points per axis (default: the 512^2 workload)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true")
-    ap.add_argument("--form", choices=["plain", "batch", "sweep", "adaptive", "user", "lekry"], default="plain")
+    ap.add_argument("--form", choices=["plain", "batch", "sweep", "adaptive", "user", "lekry", "ceiling"],
+                    default="plain")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}): the multi-GPU path is not "
@@ -463,6 +480,9 @@ def main():
         return
     if args.form == "lekry":
         bench_lekry(args)
+        return
+    if args.form == "ceiling":
+        bench_ceiling(args)
         return
 
     import torch

@@ -434,6 +434,14 @@ LJ_API int lj_mlp_load(lj_context* ctx, const char* path);
 
 /* ---- measurement ------------------------------------------------------------ */
 
+/* Attainable HBM bandwidth of the current device (the ceiling the roofline
+ * fractions are read against): gbs[0] copy (1 read + 1 write), gbs[1] read
+ * only, gbs[2] the access pattern of a Newton step at one accumulator (3 reads
+ * + 2 writes), GB/s, best of 5 timed runs, streaming FP64 vectors of `bytes`
+ * each (>= 64 MiB, a multiple of 16).  Allocates and frees four such vectors
+ * on the current device; synchronises it.  No context needed. */
+LJ_API int lj_measure_bandwidth(long long bytes, double* gbs);
+
 /* Kernel timing of the phi-action kernel.  While enabled, the library
  * brackets every launch of that kernel (power iteration + divided differences
  * + Newton recurrence in one persistent launch) with HIP events on the launch

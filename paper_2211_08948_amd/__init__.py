@@ -318,6 +318,16 @@ def lj_user_step(ctx: Context, scheme: str, U: UserOperator, h: float, tol: floa
     return rc, [stats[i].as_dict() for i in range(ncalls.value)]
 
 
+def lj_measure_bandwidth(nbytes: int = 1 << 30) -> dict:
+    """Attainable HBM bandwidth (GB/s) of the current device: copy, read-only
+    and the Newton-step access pattern (3 reads + 2 writes)."""
+    out = (C.c_double * 3)()
+    rc = lib().lj_measure_bandwidth(int(nbytes), out)
+    if rc != LJ_OK:
+        raise LejaError(rc, "lj_measure_bandwidth")
+    return {"copy": out[0], "read": out[1], "newton_step": out[2]}
+
+
 def lj_default_krylov_options(**overrides) -> "_lib.lj_krylov_options":
     k = _lib.lj_krylov_options()
     lib().lj_default_krylov_options(C.byref(k))

@@ -15,7 +15,8 @@ ROOT = os.path.dirname(HERE)
 OUT = os.path.join(HERE, "libleja.so")
 ARCH = "gfx950"
 
-SOURCES = ["kernels.hip", "mlp.hip", "user_kernels.hip", "krylov_kernels.hip", "leja_lib.hip", "leja_points.cpp"]
+SOURCES = ["kernels.hip", "mlp.hip", "user_kernels.hip", "krylov_kernels.hip", "bandwidth.hip", "leja_lib.hip",
+           "leja_points.cpp"]
 HIP_FLAGS = [
     "-O3", "-std=c++17", f"--offload-arch={ARCH}", "-fPIC", "-Wall", "-Wno-unused-result",
     "-fvisibility=hidden",
