@@ -467,7 +467,8 @@ typedef struct {
 /* Diagnostics: the reduced norms the last Newton recurrence on ctx decided
  * on.  Row m-1 (m = 1..iterations) holds ||y_m||_2^2 followed by ||p_k||_2^2
  * (k < LJ_MAX_K) after term m, as summed on the device.  out is a host array
- * of rows x (1 + LJ_MAX_K) doubles; returns the number of rows written. */
+ * of rows x (1 + LJ_MAX_K) doubles; returns the number of rows written.
+ * Synchronises the device (the trace is read from device memory). */
 LJ_API int lj_last_trace(lj_context* ctx, double* out, int rows);
 
 /* Diagnostics: where block 0 of the last action launch spent its time, in

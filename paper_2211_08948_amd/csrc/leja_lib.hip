@@ -664,7 +664,7 @@ ActOut run_action(lj_context* ctx, const OpDev& op, const double* v, int K, cons
   for (int attempt = 0; attempt < 2; ++attempt) {
     hipEvent_t* ev = timing_pair(ctx);
     launch_action(ctx, op, v, K, l, s_k, lam_host, seed, start, outs, o, tol, s, BoundLink{}, ctx->h_status,
-                  sizeof(LejaStatus), ev, &tiled, attempt == 1);
+                  offsetof(LejaStatus, trace), ev, &tiled, attempt == 1, true);
     HIPCHK(ctx, hipStreamSynchronize(s));
     const ActOut r = finish_action(ctx, op, *ctx->h_status, ev, tiled);
     if (!r.aborted) return r;
@@ -1414,7 +1414,8 @@ LJ_API int lj_create(lj_context** out, int hip_device) {
     HIPCHK(ctx, hipMalloc(&ctx->d_barrier, kBarrierWords * sizeof(unsigned int)));
     HIPCHK(ctx, hipMemset(ctx->d_barrier, 0, kBarrierWords * sizeof(unsigned int)));
     HIPCHK(ctx, hipMalloc(&ctx->d_status, sizeof(LejaStatus)));
-    HIPCHK(ctx, hipHostMalloc(&ctx->h_status, sizeof(LejaStatus), hipHostMallocDefault));
+    // fine-grained: the action kernels write their status head here directly
+    HIPCHK(ctx, hipHostMalloc(&ctx->h_status, sizeof(LejaStatus), hipHostMallocCoherent));
     HIPCHK(ctx, hipHostMalloc(&ctx->h_coef, kMaxK * kTable * sizeof(double), hipHostMallocDefault));
     // fine-grained: the action kernels write their status headers here directly
     HIPCHK(ctx, hipHostMalloc(&ctx->h_pool, kAsyncSlots * sizeof(LejaStatus), hipHostMallocCoherent));
@@ -2207,10 +2208,19 @@ LJ_API int lj_integrate(lj_context* ctx, int scheme, const lj_operator* J, doubl
 
 LJ_API int lj_last_trace(lj_context* ctx, double* out, int rows) {
   if (!ctx || !out || rows < 0) return LJ_EINVAL;
-  const int have = ctx->h_status->iters;
+  // the trace stays in device memory (status heads reach the host directly):
+  // read the last launch's status, head and trace together
+  static_assert(sizeof(LejaStatus) < 16384, "status copied through the stack");
+  LejaStatus S;
+  if (hipSetDevice(ctx->device) != hipSuccess || hipDeviceSynchronize() != hipSuccess ||
+      hipMemcpy(&S, ctx->d_status, sizeof(S), hipMemcpyDeviceToHost) != hipSuccess) {
+    (void)hipGetLastError();
+    return LJ_EHIP;
+  }
+  const int have = S.iters;
   const int n = rows < have ? rows : have;
   for (int m = 0; m < n; ++m)
-    for (int q = 0; q < 1 + kMaxK; ++q) out[m * (1 + kMaxK) + q] = ctx->h_status->trace[m][q];
+    for (int q = 0; q < 1 + kMaxK; ++q) out[m * (1 + kMaxK) + q] = S.trace[m][q];
   return n;
 }
 
