@@ -579,13 +579,15 @@ __global__ __launch_bounds__(kBlock) void lj_action_stream(ActionParams P) {
 // ===========================================================================
 // LDS-tiled action kernel with temporal blocking: one tile per block, one
 // owned point per thread, scalar families whose Jacobian reads the state at
-// the centre only.  EPT: extended (tile + halo) points per thread.
+// the centre only.  EPT: extended (tile + halo) points per thread; KM: the
+// most accumulators the instance carries (1 for single actions and bounds,
+// which frees the registers of the other three).
 // Neumann families: extended points outside the domain are ghosts held at
 // zero in both buffers, and a boundary cell's coefficient towards its ghost
 // is folded into its diagonal (the ghost equals the cell itself), so every
 // in-domain point stays exact through the super-step.
 // ===========================================================================
-template <int KIND, int S, int EPT>
+template <int KIND, int S, int EPT, int KM>
 __global__ __launch_bounds__(kBlock) void lj_action_tile(ActionParams P) {
   const GridSync gsync{P.barrier, P.spin_limit};
   static_assert(KIND == OP_ADVDIFF || KIND == OP_ALLENCAHN || KIND == OP_ADR,
@@ -857,10 +859,10 @@ __global__ __launch_bounds__(kBlock) void lj_action_tile(ActionParams P) {
   // the decisions, everyone reads the outcome.
   __shared__ Decision sD;
   __shared__ int s_commit[kMaxK];
-  double pk[kMaxK];
+  double pk[KM];
   const double v_own = own ? Y(0)[eo] : 0.0;
 #pragma unroll
-  for (int k = 0; k < kMaxK; ++k) pk[k] = sh.coef[k * kTable] * v_own;
+  for (int k = 0; k < KM; ++k) pk[k] = sh.coef[k * kTable] * v_own;
   if (threadIdx.x == 0) decision_init(sD, K, 1.0, 0.0, sh.fmax);  // redone once ||v|| is known
   __syncthreads();
   double nv = 0.0;
@@ -868,12 +870,12 @@ __global__ __launch_bounds__(kBlock) void lj_action_tile(ActionParams P) {
   int m0 = 0;
   while (true) {
     const int steps = min(min(S, P.max_points - m0), uniform(sD.next));
-    bool act0[kMaxK];
+    bool act0[KM];
 #pragma unroll
-    for (int k = 0; k < kMaxK; ++k) act0[k] = (k < K) && (uniform(sD.st[k]) == ACC_RUNNING);
-    double ps[kMaxK];
+    for (int k = 0; k < KM; ++k) act0[k] = (k < K) && (uniform(sD.st[k]) == ACC_RUNNING);
+    double ps[KM];
 #pragma unroll
-    for (int k = 0; k < kMaxK; ++k) ps[k] = pk[k];
+    for (int k = 0; k < KM; ++k) ps[k] = pk[k];
 #pragma unroll
     for (int j = 1; j <= S; ++j) {
       if (j > steps) break;
@@ -883,7 +885,7 @@ __global__ __launch_bounds__(kBlock) void lj_action_tile(ActionParams P) {
       H[(j - 1) * kBlock + threadIdx.x] = y;
       stage((j - 1) * Q, y * y);
 #pragma unroll
-      for (int k = 0; k < kMaxK; ++k) {
+      for (int k = 0; k < KM; ++k) {
         if (!act0[k]) continue;
         ps[k] = ps[k] + uniform(sh.coef[k * kTable + m]) * y;
         stage((j - 1) * Q + 1 + k, ps[k] * ps[k]);
@@ -913,7 +915,7 @@ __global__ __launch_bounds__(kBlock) void lj_action_tile(ActionParams P) {
     tick(kProfDecide);
     // commit each accumulator's terms up to its stop index
 #pragma unroll
-    for (int k = 0; k < kMaxK; ++k) {
+    for (int k = 0; k < KM; ++k) {
       const int ck = uniform(s_commit[k]);
 #pragma unroll
       for (int j = 1; j <= S; ++j)
@@ -928,7 +930,7 @@ __global__ __launch_bounds__(kBlock) void lj_action_tile(ActionParams P) {
   }
   if (own) {
 #pragma unroll
-    for (int k = 0; k < kMaxK; ++k)
+    for (int k = 0; k < KM; ++k)
       if (k < K) P.p[k][go] = pk[k];
   }
   if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -1362,26 +1364,24 @@ void* action_stream_ptr(int kind) {
   return nullptr;
 }
 
-void* action_tile_ptr(int kind, int ept) {
-  if (kind == OP_ALLENCAHN) {
-    switch (ept) {
-      case 1: return reinterpret_cast<void*>(&lj_action_tile<OP_ALLENCAHN, kMaxSuper, 1>);
-      case 2: return reinterpret_cast<void*>(&lj_action_tile<OP_ALLENCAHN, kMaxSuper, 2>);
-      case 3: return reinterpret_cast<void*>(&lj_action_tile<OP_ALLENCAHN, kMaxSuper, 3>);
-    }
-  } else if (kind == OP_ADVDIFF) {
-    switch (ept) {
-      case 1: return reinterpret_cast<void*>(&lj_action_tile<OP_ADVDIFF, kMaxSuper, 1>);
-      case 2: return reinterpret_cast<void*>(&lj_action_tile<OP_ADVDIFF, kMaxSuper, 2>);
-      case 3: return reinterpret_cast<void*>(&lj_action_tile<OP_ADVDIFF, kMaxSuper, 3>);
-    }
-  } else if (kind == OP_ADR) {
-    switch (ept) {
-      case 1: return reinterpret_cast<void*>(&lj_action_tile<OP_ADR, kMaxSuper, 1>);
-      case 2: return reinterpret_cast<void*>(&lj_action_tile<OP_ADR, kMaxSuper, 2>);
-      case 3: return reinterpret_cast<void*>(&lj_action_tile<OP_ADR, kMaxSuper, 3>);
-    }
+void* action_tile_ptr(int kind, int ept, int K) {
+#define LJ_TILE_CASES(K_)                                                                            \
+  if (kind == K_) {                                                                                  \
+    switch (ept) {                                                                                   \
+      case 1: return km1 ? reinterpret_cast<void*>(&lj_action_tile<K_, kMaxSuper, 1, 1>)             \
+                         : reinterpret_cast<void*>(&lj_action_tile<K_, kMaxSuper, 1, kMaxK>);        \
+      case 2: return km1 ? reinterpret_cast<void*>(&lj_action_tile<K_, kMaxSuper, 2, 1>)             \
+                         : reinterpret_cast<void*>(&lj_action_tile<K_, kMaxSuper, 2, kMaxK>);        \
+      case 3: return km1 ? reinterpret_cast<void*>(&lj_action_tile<K_, kMaxSuper, 3, 1>)             \
+                         : reinterpret_cast<void*>(&lj_action_tile<K_, kMaxSuper, 3, kMaxK>);        \
+    }                                                                                                \
+    return nullptr;                                                                                  \
   }
+  const bool km1 = K <= 1;
+  LJ_TILE_CASES(OP_ALLENCAHN)
+  LJ_TILE_CASES(OP_ADVDIFF)
+  LJ_TILE_CASES(OP_ADR)
+#undef LJ_TILE_CASES
   return nullptr;
 }
 

@@ -50,7 +50,7 @@ struct FinishArgs {
 int persistent_block();  // threads per block of the action kernels
 int tile_halo();         // halo width = Newton steps per barrier of the tiled kernel
 void* action_stream_ptr(int kind);
-void* action_tile_ptr(int kind, int ept);  // nullptr if the family has no tiled kernel
+void* action_tile_ptr(int kind, int ept, int K);  // K accumulators; nullptr if the family has no tiled kernel
 
 hipError_t launch_divdiff(const DDParams& P, hipStream_t s);
 void* batch_kernel_ptr(int kind, int block_size);  // block_size in {256, 512, 1024}

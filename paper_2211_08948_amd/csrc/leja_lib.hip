@@ -297,7 +297,7 @@ struct TilePlan {
 
 TilePlan tile_plan(lj_context* ctx, const OpDev& op) {
   TilePlan best;
-  if (ctx->force_stream || action_tile_ptr(op.kind, 1) == nullptr) return best;
+  if (ctx->force_stream || action_tile_ptr(op.kind, 1, kMaxK) == nullptr) return best;
   const int S = tile_halo();
   const int B = persistent_block();
   static const int cand[][2] = {{32, 32}, {64, 16}, {32, 16}, {16, 16}, {16, 8}, {8, 8}};
@@ -412,7 +412,7 @@ void launch_action(lj_context* ctx, const OpDev& op, const double* v, int K, con
   int G = 0;
   size_t dyn = 0;
   if (tp.ok) {
-    fn = action_tile_ptr(op.kind, tp.ept);
+    fn = action_tile_ptr(op.kind, tp.ept, K);
     P.tx = tp.tx;
     P.ty = tp.ty;
     P.ntx = tp.ntx;
