@@ -630,7 +630,10 @@ ActOut run_action_user(lj_context* ctx, const OpDev& op, const double* v, int K,
   double* pt = slot(ctx, W_UPT, n);
   const double* yp = v;
   HIPCHK(ctx, hipStreamSynchronize(s));
-  for (int m = 1; m <= o.max_points && !ctx->h_ustatus->done; ++m) {
+  // written by the decision kernels; read between synchronisations as a hint
+  // (a stale value only enqueues a step whose work is discarded)
+  const volatile int* done = &ctx->h_ustatus->done;
+  for (int m = 1; m <= o.max_points && !*done; ++m) {
     if (U->fd) {
       HIPCHK(ctx, launch_user_fd_point(ctx->d_ustate, U->J.state, yp, n, pt, s));
       call_rhs(ctx, pt, jb, s);

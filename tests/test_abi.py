@@ -118,6 +118,10 @@ def test_null_arguments_are_rejected_without_device(lib):
     assert lib.lj_step(None, 1, None, 1.0, 1e-10, None, None, None, None, 0, None, None) == -1
     assert lib.lj_timing_enable(None, 1) == -1
     assert lib.lj_jv(None, None, None, None, None) == -1
+    out = (C.c_double * 3)()
+    assert lib.lj_measure_bandwidth(1 << 20, out) == -1  # below 64 MiB: refused before any device work
+    assert lib.lj_measure_bandwidth((64 << 20) + 8, out) == -1  # not a multiple of 16
+    assert lib.lj_measure_bandwidth(1 << 30, None) == -1
     assert lib.lj_phi_combination(None, None, 1, None, 1.0, 1e-10, None, None, None, None) == -1
     assert lib.lj_user_phi_combination(None, None, 1, None, 1.0, 1e-10, None, None, None, None) == -1
     assert lib.lj_user_phi_action(None, None, None, None, 1, 1.0, 1e-10, None, None, None) == -1
