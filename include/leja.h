@@ -325,6 +325,13 @@ LJ_API int lj_user_step(lj_context* ctx, int scheme, const lj_user_operator* J, 
 LJ_API int lj_user_phi_combination(lj_context* ctx, const lj_user_operator* J, int p, const double* const* b,
                                    double h, double tol, double* w, const lj_krylov_options* kopt, lj_stats* stats,
                                    void* stream);
+/* lj_integrate for a user operator: u(0) = J->state; each attempt linearises
+ * at its own state, which the callbacks receive as u (and finite-difference
+ * products re-evaluate f there).  Needs rhs. */
+LJ_API int lj_user_integrate(lj_context* ctx, int scheme, const lj_user_operator* J, double T, double dt0,
+                             double tol, double leja_tol, double* u_out, const lj_options* opt,
+                             lj_integrate_stats* stats, lj_step_record* log, int log_cap, int max_attempts,
+                             void* stream);
 
 /* ---- batching form --------------------------------------------------------- */
 

@@ -90,8 +90,10 @@ class Run:
 
 
 def integrate(prob, u0, T: float, dt0: float, tol: float, scheme: str = "EPIRK4S3", leja_tol: float | None = None,
-              opt: Options | None = None, max_attempts: int = 10000) -> Run:
-    """u(T) of u_t = f(u) from u(0) = u0 with variable steps (Sec. 2.3)."""
+              opt: Options | None = None, max_attempts: int = 10000, make_op=None) -> Run:
+    """u(T) of u_t = f(u) from u(0) = u0 with variable steps (Sec. 2.3).
+    make_op(u) builds the operator linearised at u (default: the family
+    operator of `prob`)."""
     if scheme not in EMBEDDED_ORDER:
         raise ValueError(f"{scheme} has no embedded error estimate")
     p = EMBEDDED_ORDER[scheme]
@@ -105,7 +107,7 @@ def integrate(prob, u0, T: float, dt0: float, tol: float, scheme: str = "EPIRK4S
             raise RuntimeError("too many step attempts")
         last = dt >= T - t
         h = T - t if last else dt
-        op = Operator(prob, state=u)
+        op = make_op(u) if make_op is not None else Operator(prob, state=u)
         u_new, err, log = step(op, scheme, h, lt, opt)
         ok = all(st.converged for st in log)
         cost = sum(st.iters_total + st.power_iters for st in log)

@@ -367,6 +367,23 @@ def lj_user_phi_combination(ctx: Context, U: "UserOperator", bs: Sequence, h: fl
     return rc, st.as_dict(1)
 
 
+def lj_user_integrate(ctx: Context, scheme: str, U: UserOperator, T: float, dt0: float, tol: float,
+                      leja_tol: float, u_out, opt: lj_options | None = None, log_cap: int = 1000,
+                      max_attempts: int = 100000, stream=None):
+    """u(T) from u(0) = U.state with variable steps (Sec. 2.3) for a user
+    operator.  Returns (rc, stats dict, list of attempted steps)."""
+    op = U.c_struct()
+    st = lj_integrate_stats()
+    recs = (lj_step_record * max(log_cap, 1))()
+    rc = ctx._lib.lj_user_integrate(ctx.handle, SCHEMES[scheme], C.byref(op), float(T), float(dt0), float(tol),
+                                    float(leja_tol), _tensor_ptr(u_out, U.n, "u_out"),
+                                    C.byref(opt) if opt is not None else None, C.byref(st), recs, int(log_cap),
+                                    int(max_attempts), _stream_ptr(stream))
+    _user_call(ctx, U, rc)
+    n = min(st.accepted + st.rejected, log_cap)
+    return rc, st.as_dict(), [recs[i].as_dict() for i in range(n)]
+
+
 def family_user_operator(ctx: Context, J: Operator, finite_difference: bool = False) -> UserOperator:
     """A built-in family seen as a user operator (its lj_rhs and lj_jv as the
     callbacks), e.g. to check the callback path against the fused one."""

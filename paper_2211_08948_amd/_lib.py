@@ -150,6 +150,9 @@ _PROTOS = {
     "lj_integrate": (C.c_int, [_P, C.c_int, C.POINTER(lj_operator), C.c_double, C.c_double, C.c_double,
                                C.c_double, _P, C.POINTER(lj_options), C.POINTER(lj_integrate_stats),
                                C.POINTER(lj_step_record), C.c_int, C.c_int, _P]),
+    "lj_user_integrate": (C.c_int, [_P, C.c_int, C.POINTER(lj_user_operator), C.c_double, C.c_double, C.c_double,
+                                    C.c_double, _P, C.POINTER(lj_options), C.POINTER(lj_integrate_stats),
+                                    C.POINTER(lj_step_record), C.c_int, C.c_int, _P]),
     "lj_last_trace": (C.c_int, [_P, C.POINTER(C.c_double), C.c_int]),
     "lj_last_profile": (C.c_int, [_P, C.POINTER(C.c_double)]),
     "lj_timing_enable": (C.c_int, [_P, C.c_int]),

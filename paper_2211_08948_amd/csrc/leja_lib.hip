@@ -2133,91 +2133,129 @@ double cost_factor(double dt, double dt_prev, double c, double c_prev) {
 }
 }  // namespace
 
+// Variable step sizes from u(0) = op0.state (Sec. 2.3).  before_step(u) runs
+// before every attempt with the state it linearises at (user operators
+// refresh their callbacks' state there).
+extern "C++" {
+template <class BeforeStep>
+int integrate_impl(lj_context* ctx, int scheme, const OpDev& op0, const Opts& o, double T, double dt0, double tol,
+                   double leja_tol, double* u_out, lj_integrate_stats* stats, lj_step_record* log, int log_cap,
+                   int max_attempts, hipStream_t s, BeforeStep&& before_step) {
+  if (scheme != LJ_EPIRK4S3 && scheme != LJ_EXPRB43 && scheme != LJ_EPIRK4S3_LEKRY)
+    invalid(ctx, "lj_integrate needs an embedded scheme");
+  if (op0.state == nullptr) invalid(ctx, "lj_integrate needs u(0) in J->state");
+  if (!(T >= 0.0) || !std::isfinite(T)) invalid(ctx, "T must be finite and >= 0");
+  if (!(dt0 > 0.0) || !std::isfinite(dt0)) invalid(ctx, "dt0 must be finite and > 0");
+  if (!(tol > 0.0) || !std::isfinite(tol)) invalid(ctx, "tol must be finite and > 0");
+  if (!(leja_tol > 0.0) || !std::isfinite(leja_tol)) invalid(ctx, "leja_tol must be finite and > 0");
+  if (log_cap < 0 || (log_cap > 0 && !log)) invalid(ctx, "log is NULL but log_cap > 0");
+  if (max_attempts < 1) invalid(ctx, "max_attempts must be >= 1");
+  check_vec(ctx, op0, u_out, "u_out");
+  if (u_out == op0.state) invalid(ctx, "u_out must not alias the state");
+  const size_t n = nvals(op0);
+  const int p = 3;  // order of the embedded (lower-order) solution of the schemes
+  double* ub[2] = {slot(ctx, W_IU0, n), slot(ctx, W_IU1, n)};
+  double* errv = slot(ctx, W_IERR, n);
+  HIPCHK(ctx, hipMemcpyAsync(ub[0], op0.state, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+  lj_integrate_stats st{};
+  int cur = 0, attempts = 0;
+  double t = 0.0, dt = dt0;
+  bool have_prev = false;
+  double prev_dt = 0.0, prev_rate = 0.0;
+  int rc = LJ_OK;
+  while (t < T) {
+    if (attempts >= max_attempts) {
+      rc = LJ_ENOTCONV;
+      break;
+    }
+    const bool last = dt >= T - t;
+    const double h = last ? T - t : dt;
+    OpDev op = op0;
+    op.state = ub[cur];
+    before_step(ub[cur]);
+    lj_stats calls[LJ_MAX_K];
+    const int src = step_impl(ctx, scheme, op, o, h, leja_tol, ub[cur ^ 1], errv, calls, s);
+    const int ncalls = (scheme == LJ_EXPRB43) ? 4 : 3;
+    int cost = 0;
+    bool ok = src == LJ_OK;
+    for (int i = 0; i < ncalls; ++i) {
+      cost += calls[i].iters_total + calls[i].power_iters;
+      ok = ok && calls[i].converged;
+    }
+    st.products += cost;
+    double e = INFINITY;
+    if (ok) {
+      HIPCHK(ctx, launch_sumsq2(errv, ub[cur ^ 1], (long)n, ctx->d_sumsq, ctx->d_sumsq + 2 * kSumsqBlocks, s));
+      HIPCHK(ctx, hipMemcpyAsync(ctx->h_sumsq, ctx->d_sumsq + 2 * kSumsqBlocks, 2 * sizeof(double),
+                                 hipMemcpyDeviceToHost, s));
+      HIPCHK(ctx, hipStreamSynchronize(s));
+      const double ne = std::sqrt(ctx->h_sumsq[0]), nu = std::sqrt(ctx->h_sumsq[1]);
+      e = nu > 0.0 ? ne / nu : ne;
+    }
+    const bool accept = ok && e <= tol;
+    if (log && attempts < log_cap) log[attempts] = lj_step_record{t, h, e, cost, accept ? 1 : 0};
+    ++attempts;
+    if (!ok) {
+      st.rejected += 1;
+      dt = 0.5 * h;
+    } else if (accept) {
+      st.accepted += 1;
+      t = last ? T : t + h;
+      cur ^= 1;
+      const double rate = cost / h;
+      const double d_trad = h * traditional_factor(e, tol, p);
+      const double d_cost = have_prev ? h * cost_factor(h, prev_dt, rate, prev_rate) : h * cost_factor(h, h, 1, 1);
+      have_prev = true;
+      prev_dt = h;
+      prev_rate = rate;
+      dt = std::min(d_trad, d_cost);
+    } else {
+      st.rejected += 1;
+      dt = kRetrySafety * h * traditional_factor(e, tol, p);
+    }
+  }
+  HIPCHK(ctx, hipMemcpyAsync(u_out, ub[cur], n * sizeof(double), hipMemcpyDeviceToDevice, s));
+  HIPCHK(ctx, hipStreamSynchronize(s));
+  st.t = t;
+  st.dt_next = dt;
+  if (stats) *stats = st;
+  return rc;
+}
+}  // extern "C++"
+
 LJ_API int lj_integrate(lj_context* ctx, int scheme, const lj_operator* J, double T, double dt0, double tol,
                         double leja_tol, double* u_out, const lj_options* opt, lj_integrate_stats* stats,
                         lj_step_record* log, int log_cap, int max_attempts, void* stream) {
   return guarded(ctx, [&]() {
     const OpDev op0 = make_op(ctx, J);
     const Opts o = resolve(ctx, opt);
-    if (scheme != LJ_EPIRK4S3 && scheme != LJ_EXPRB43 && scheme != LJ_EPIRK4S3_LEKRY)
-      invalid(ctx, "lj_integrate needs an embedded scheme");
-    if (op0.state == nullptr) invalid(ctx, "lj_integrate needs u(0) in J->state");
-    if (!(T >= 0.0) || !std::isfinite(T)) invalid(ctx, "T must be finite and >= 0");
-    if (!(dt0 > 0.0) || !std::isfinite(dt0)) invalid(ctx, "dt0 must be finite and > 0");
-    if (!(tol > 0.0) || !std::isfinite(tol)) invalid(ctx, "tol must be finite and > 0");
-    if (!(leja_tol > 0.0) || !std::isfinite(leja_tol)) invalid(ctx, "leja_tol must be finite and > 0");
-    if (log_cap < 0 || (log_cap > 0 && !log)) invalid(ctx, "log is NULL but log_cap > 0");
-    if (max_attempts < 1) invalid(ctx, "max_attempts must be >= 1");
-    check_vec(ctx, op0, u_out, "u_out");
-    if (u_out == op0.state) invalid(ctx, "u_out must not alias the state");
+    return integrate_impl(ctx, scheme, op0, o, T, dt0, tol, leja_tol, u_out, stats, log, log_cap, max_attempts,
+                          reinterpret_cast<hipStream_t>(stream), [](const double*) {});
+  });
+}
+
+LJ_API int lj_user_integrate(lj_context* ctx, int scheme, const lj_user_operator* J, double T, double dt0,
+                             double tol, double leja_tol, double* u_out, const lj_options* opt,
+                             lj_integrate_stats* stats, lj_step_record* log, int log_cap, int max_attempts,
+                             void* stream) {
+  return guarded(ctx, [&]() {
     const hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-    const size_t n = nvals(op0);
-    const int p = 3;  // order of the embedded (lower-order) solution of both schemes
-    double* ub[2] = {slot(ctx, W_IU0, n), slot(ctx, W_IU1, n)};
-    double* errv = slot(ctx, W_IERR, n);
-    HIPCHK(ctx, hipMemcpyAsync(ub[0], op0.state, n * sizeof(double), hipMemcpyDeviceToDevice, s));
-    lj_integrate_stats st{};
-    int cur = 0, attempts = 0;
-    double t = 0.0, dt = dt0;
-    bool have_prev = false;
-    double prev_dt = 0.0, prev_rate = 0.0;
-    int rc = LJ_OK;
-    while (t < T) {
-      if (attempts >= max_attempts) {
-        rc = LJ_ENOTCONV;
-        break;
+    const Opts o = resolve(ctx, opt);
+    if (o.use_proposal) invalid(ctx, "the learned proposal needs a built-in operator family");
+    UserScope us(ctx, J, true, s);
+    // the callbacks see the state of each attempt; finite differences need
+    // f(u) and ||u|| at it
+    auto before = [&](const double* u) {
+      us.U.J.state = u;
+      if (us.U.fd) {
+        double* fu = slot(ctx, W_UFU, (size_t)J->n);
+        call_rhs(ctx, u, fu, s);
+        us.U.fu = fu;
+        HIPCHK(ctx, launch_user_norm_u(ctx->d_ustate, u, (long)J->n, ctx->d_upart, s));
       }
-      const bool last = dt >= T - t;
-      const double h = last ? T - t : dt;
-      OpDev op = op0;
-      op.state = ub[cur];
-      lj_stats calls[LJ_MAX_K];
-      const int src = step_impl(ctx, scheme, op, o, h, leja_tol, ub[cur ^ 1], errv, calls, s);
-      const int ncalls = (scheme == LJ_EXPRB43) ? 4 : 3;
-      int cost = 0;
-      bool ok = src == LJ_OK;
-      for (int i = 0; i < ncalls; ++i) {
-        cost += calls[i].iters_total + calls[i].power_iters;
-        ok = ok && calls[i].converged;
-      }
-      st.products += cost;
-      double e = INFINITY;
-      if (ok) {
-        HIPCHK(ctx, launch_sumsq2(errv, ub[cur ^ 1], (long)n, ctx->d_sumsq, ctx->d_sumsq + 2 * kSumsqBlocks, s));
-        HIPCHK(ctx, hipMemcpyAsync(ctx->h_sumsq, ctx->d_sumsq + 2 * kSumsqBlocks, 2 * sizeof(double),
-                                   hipMemcpyDeviceToHost, s));
-        HIPCHK(ctx, hipStreamSynchronize(s));
-        const double ne = std::sqrt(ctx->h_sumsq[0]), nu = std::sqrt(ctx->h_sumsq[1]);
-        e = nu > 0.0 ? ne / nu : ne;
-      }
-      const bool accept = ok && e <= tol;
-      if (log && attempts < log_cap) log[attempts] = lj_step_record{t, h, e, cost, accept ? 1 : 0};
-      ++attempts;
-      if (!ok) {
-        st.rejected += 1;
-        dt = 0.5 * h;
-      } else if (accept) {
-        st.accepted += 1;
-        t = last ? T : t + h;
-        cur ^= 1;
-        const double rate = cost / h;
-        const double d_trad = h * traditional_factor(e, tol, p);
-        const double d_cost = have_prev ? h * cost_factor(h, prev_dt, rate, prev_rate) : h * cost_factor(h, h, 1, 1);
-        have_prev = true;
-        prev_dt = h;
-        prev_rate = rate;
-        dt = std::min(d_trad, d_cost);
-      } else {
-        st.rejected += 1;
-        dt = kRetrySafety * h * traditional_factor(e, tol, p);
-      }
-    }
-    HIPCHK(ctx, hipMemcpyAsync(u_out, ub[cur], n * sizeof(double), hipMemcpyDeviceToDevice, s));
-    HIPCHK(ctx, hipStreamSynchronize(s));
-    st.t = t;
-    st.dt_next = dt;
-    if (stats) *stats = st;
-    return rc;
+    };
+    return integrate_impl(ctx, scheme, us.op, o, T, dt0, tol, leja_tol, u_out, stats, log, log_cap, max_attempts,
+                          s, before);
   });
 }
 

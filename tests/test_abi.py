@@ -127,6 +127,7 @@ def test_null_arguments_are_rejected_without_device(lib):
     assert lib.lj_user_phi_action(None, None, None, None, 1, 1.0, 1e-10, None, None, None) == -1
     assert lib.lj_user_phi_vertical(None, None, None, 1, None, None, 1.0, 1e-10, None, None, None, None) == -1
     assert lib.lj_user_step(None, 1, None, 1.0, 1e-10, None, None, None, None, 0, None, None) == -1
+    assert lib.lj_user_integrate(None, 4, None, 1.0, 0.1, 1e-6, 1e-10, None, None, None, None, 0, 10, None) == -1
     assert lib.lj_integrate(None, 4, None, 1.0, 0.1, 1e-6, 1e-10, None, None, None, None, 0, 10, None) == -1
     assert lib.lj_batch_run(None, None) == -1
     assert lib.lj_batch_stats(None, None, None) == -1

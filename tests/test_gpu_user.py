@@ -246,3 +246,31 @@ def test_semilinear_end_to_end(env, scheme):
     assert rel(ug, Uo) <= 1e-9
     assert rel(ug, exact) <= 1.01 * e_orc + 1e-9
     assert e_orc < 1e-5
+
+
+def test_semilinear_variable_steps(env):
+    """Variable step sizes (Sec. 2.3) on the semilinear problem through the
+    callbacks: the same accepted and rejected attempts, step sizes and
+    product counts as the oracle's controller, the same u(1), and the exact
+    solution to within the accumulated step tolerances."""
+    from oracle import adaptive as A
+    lj, torch, ctx = env
+    N = 31
+    u0 = Semilinear(N).exact(0.0)
+    orc = A.integrate(None, u0, 1.0, 0.05, 1e-6, "EPIRK4S3", leja_tol=TOL, make_op=lambda u: Semilinear(N, u))
+    ts = TorchSemilinear(torch, N)
+    U = lj.UserOperator(N + 1, _dev(torch, u0), rhs=ts.rhs, jv=ts.jv)
+    out = torch.empty_like(U.state)
+    rc, st, recs = lj.lj_user_integrate(ctx, "EPIRK4S3", U, 1.0, 0.05, 1e-6, TOL, out)
+    say("semilinear adaptive", st, orc.accepted, orc.rejected, orc.products)
+    assert rc == 0 and st["t"] == 1.0
+    assert (st["accepted"], st["rejected"], st["products"]) == (orc.accepted, orc.rejected, orc.products)
+    for r, a in zip(recs, orc.attempts):
+        assert r["accepted"] == a.accepted and r["products"] == a.cost
+        # sizes follow (tol / e)^{1/4}; e is the norm of the difference of two
+        # close solutions, whose rounding leaves ~1e-5 of it different
+        assert r["dt"] == pytest.approx(a.dt, rel=1e-4)
+    u = out.cpu().numpy()
+    exact = Semilinear(N).exact(1.0)
+    assert rel(u, orc.u) <= 1e-9
+    assert rel(u, exact) <= 1e-6
