@@ -298,7 +298,11 @@ LJ_API int lj_integrate(lj_context* ctx, int scheme, const lj_operator* J, doubl
  * rejection tests, the divided differences and the power iteration run as
  * library kernels between the callbacks, with the decisions taken on the
  * device; the host reads them every few steps, so up to 3 products beyond
- * the last needed one may be computed (and discarded). */
+ * the last needed one may be computed (and discarded).  A callback may call
+ * lj_rhs and lj_jv on the same context; any other entry point that takes
+ * the context and returns a code fails with LJ_EINVAL when called from a
+ * callback (it would reuse the running call's workspace), and lj_destroy must
+ * not be called there. */
 typedef int (*lj_rhs_fn)(void* user, const double* x, double* fx, void* stream);
 typedef int (*lj_jv_fn)(void* user, const double* u, const double* x, double* jx, void* stream);
 

@@ -989,9 +989,17 @@ void propose(lj_context* ctx, const OpDev& op, int K, const int* l, const double
   substeps = 1 << e;
 }
 
+// Runs an entry point: device selection, error text, no exception across the
+// ABI.  While a user operator's callback runs (ctx->uop set), only the entry
+// points that use no workspace (lj_rhs, lj_jv: in_callback_ok) may be called
+// on the same context; the others would overwrite the running call's vectors.
 template <class F>
-int guarded(lj_context* ctx, F&& f) {
+int guarded(lj_context* ctx, F&& f, bool in_callback_ok = false) {
   if (!ctx) return LJ_EINVAL;
+  if (ctx->uop && !in_callback_ok) {
+    ctx->err = "only lj_rhs and lj_jv may be called on a context from its own user-operator callbacks";
+    return LJ_EINVAL;
+  }
   try {
     ctx->err.clear();
     int dev = -1;
@@ -1546,7 +1554,7 @@ LJ_API int lj_rhs(lj_context* ctx, const lj_operator* J, const double* u, double
     if (f == u) invalid(ctx, "f must not alias u");
     HIPCHK(ctx, launch_rhs(op, u, f, reinterpret_cast<hipStream_t>(stream)));
     return LJ_OK;
-  });
+  }, true);
 }
 
 LJ_API int lj_jv(lj_context* ctx, const lj_operator* J, const double* x, double* y, void* stream) {
@@ -1558,7 +1566,7 @@ LJ_API int lj_jv(lj_context* ctx, const lj_operator* J, const double* x, double*
     if (y == op.state) invalid(ctx, "y must not alias the operator state");
     HIPCHK(ctx, launch_family_jv(op, x, y, reinterpret_cast<hipStream_t>(stream)));
     return LJ_OK;
-  });
+  }, true);
 }
 
 LJ_API int lj_user_phi_vertical(lj_context* ctx, const lj_user_operator* J, const double* v, int K, const int* l,

@@ -173,6 +173,13 @@ def test_user_zero_vector_and_errors(env):
     with pytest.raises(lj.LejaError) as ei:
         lj.lj_user_phi_action(ctx, Ub, _dev(torch, v), w, 1, h, TOL, lj.lj_default_options(bound=100.0))
     assert isinstance(ei.value.__cause__, ValueError)
+    # a callback may not re-enter the library's workspace-using entry points
+    def reenter(u, x, out):
+        lj.lj_phi_action(ctx, J, x, out, 1, h, TOL, lj.lj_default_options(bound=100.0))
+    Ur = lj.UserOperator(prob.n, J.state, jv=reenter)
+    with pytest.raises(lj.LejaError) as ei:
+        lj.lj_user_phi_action(ctx, Ur, _dev(torch, v), w, 1, h, TOL, lj.lj_default_options(bound=100.0))
+    assert isinstance(ei.value.__cause__, lj.LejaError) and "callbacks" in str(ei.value.__cause__)
     # the stage driver needs rhs; the proposal needs a built-in family
     Uj = lj.UserOperator(prob.n, J.state, jv=lambda u, x, out: lj.lj_jv(ctx, J, x, out))
     with pytest.raises(lj.LejaError):
