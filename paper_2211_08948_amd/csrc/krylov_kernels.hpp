@@ -6,6 +6,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include "common.hpp"
+
 namespace lj {
 
 constexpr int kKryBlock = 256;
@@ -49,5 +51,29 @@ struct KryCoef {
 hipError_t launch_kry_combine(const KryDev& K, int m, double beta, const KryCoef& F, double* out, hipStream_t s);
 // w = [b_0 or 0; 0, ..., 0, 1]
 hipError_t launch_kry_init(double* w, const double* b0, long N, int p, hipStream_t s);
+
+// The whole basis in one persistent launch, for a built-in family and a
+// window of 1 .. kKryChunk vectors: beta = ||w|| and V_0, then per column j
+// the product J V_j with B y and K y, the window's dots (grid all-reduce),
+// the subtraction and the norm (grid all-reduce); V_{j+1} is never stored
+// apart from the next column's pass, which reads the previous orthogonalised
+// vector and divides by its norm on the fly.  Two barriers per column.
+// Writes what the per-pass kernels write (V_0 .. V_{m_eff - 1}, H, scalars
+// [0] and [1]) and scalars[2] = 1 when a grid barrier timed out (the launch
+// is then to be repeated cooperatively).  Blocks of kKryPBlock threads, at
+// most one per CU; every block must be resident at once.
+constexpr int kKryPBlock = 1024;
+struct KryArnoldi {
+  KryDev K;
+  OpDev op;
+  const double* w;         // start vector (augmented length), not modified
+  double* Wb[2];           // column j's product, in Wb[j & 1] (augmented length)
+  int window;              // 1 .. kKryChunk
+  double* partials;        // 2 x kPartStride x gridDim partial sums
+  unsigned int* barrier;   // grid barrier words, zero at launch (left zero)
+  unsigned int spin_limit; // bound on each barrier wait
+};
+// the kernel for a family (nullptr: no such family)
+const void* kry_arnoldi_ptr(int kind);
 
 }  // namespace lj

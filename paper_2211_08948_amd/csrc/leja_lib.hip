@@ -40,7 +40,7 @@ enum Slot {
   W_IU0, W_IU1, W_IERR,            // variable-step integration: state ping-pong, error estimate
   W_UJ, W_UPT, W_UY, W_UPA, W_UPB, // user operators: product, finite-difference point, power vectors
   W_UFU, W_UXR, W_UD, W_UFX, W_UJD, W_UR0, W_UR1,  // f(u), stage remainders
-  W_KV, W_KW, W_KX, W_KC,          // Krylov: basis, product, augmented vector, LeKry third stage
+  W_KV, W_KW, W_KW2, W_KX, W_KC,   // Krylov: basis, products, augmented vector, LeKry third stage
   W_NSLOTS
 };
 
@@ -83,6 +83,7 @@ struct lj_context {
   // read when the counters are (lj_timing_read), not after every launch
   bool timing = false;
   unsigned int forced_spin_limit = 0;  // LJ_FORCE_SPIN_LIMIT (test hook), 0: the default bound
+  int krylov_passes = 0;   // LJ_KRYLOV_PASSES=1: build Krylov bases with the per-pass kernels only
   std::vector<hipEvent_t> tev;  // 2 * kTimingPairs, created when timing is first enabled
   int tev_next = 0;             // next free pair
   std::vector<int> tev_pending; // pairs whose launches finished but whose times are unread
@@ -1261,7 +1262,7 @@ int krylov_impl(lj_context* ctx, const OpDev& op, int p, const double* const* b,
   const int m = ko.m;
   if (!ctx->d_kpart)
     HIPCHK(ctx, hipMalloc(&ctx->d_kpart, (size_t)kKryBlocksMax * (kKryMaxDim + 1) * sizeof(double)));
-  const size_t hsz = (size_t)(kKryMaxDim + 1) * kKryMaxDim + 2;
+  const size_t hsz = (size_t)(kKryMaxDim + 1) * kKryMaxDim + 3;  // H, then scalars [beta, breakdown, aborted]
   if (!ctx->d_kH) HIPCHK(ctx, hipMalloc(&ctx->d_kH, hsz * sizeof(double)));
   if (!ctx->h_kH) HIPCHK(ctx, hipHostMalloc(&ctx->h_kH, hsz * sizeof(double), hipHostMallocDefault));
   KryDev K;
@@ -1278,24 +1279,51 @@ int krylov_impl(lj_context* ctx, const OpDev& op, int p, const double* const* b,
   K.scalars = ctx->d_kH + (size_t)(kKryMaxDim + 1) * kKryMaxDim;
   double* X = slot(ctx, W_KX, na);
   HIPCHK(ctx, launch_kry_init(X, b[0], N, p, s));
-  std::memset(st, 0, sizeof(*st));
-  for (int k = 0; k < LJ_MAX_K; ++k) {
-    st->m_star[k] = -1;
-    st->substeps[k] = 1;
+  // built-in families with a window of at most kKryChunk vectors: the whole
+  // basis in one persistent launch; otherwise four launches per column
+  const bool persistent = !is_user(op) && ko.window >= 1 && ko.window <= kKryChunk && !ctx->krylov_passes;
+  KryArnoldi KA;
+  std::memset(&KA, 0, sizeof(KA));
+  const void* kfn = nullptr;
+  int KG = 0;
+  if (persistent) {
+    KA.K = K;
+    KA.op = op;
+    KA.w = X;
+    KA.Wb[0] = K.W;
+    KA.Wb[1] = slot(ctx, W_KW2, na);
+    KA.window = ko.window;
+    KG = grid_for(ctx, op.npts);
+    ensure_small(ctx, KG);
+    KA.partials = ctx->d_partials;
+    KA.barrier = ctx->d_barrier;
+    kfn = kry_arnoldi_ptr(op.kind);
+    if (!kfn) invalid(ctx, "operator kind has no Krylov kernel");
   }
-  bool converged = true;
-  int substeps = 0, rejections = 0, products = 0, attempts = 0;
-  double t = 0.0, tau = h, last_est = 0.0;
-  std::vector<double> Hm, Mx, E;
-  while (t < h) {
-    if (substeps >= ko.max_substeps || attempts >= 10 * ko.max_substeps) {
-      converged = false;
-      break;
+  // one basis from X; returns false when beta = 0
+  auto basis = [&]() -> bool {
+    if (persistent) {
+      for (int attempt = 0; attempt < 2; ++attempt) {
+        const bool coop = attempt > 0 || !coresident(ctx, kfn, KG, 0);
+        KA.spin_limit = (!coop && ctx->forced_spin_limit > 0) ? ctx->forced_spin_limit : kGridSpinLimit;
+        void* args[] = {&KA};
+        if (coop) {
+          HIPCHK(ctx, hipLaunchCooperativeKernel(kfn, dim3(KG), dim3(kKryPBlock), args, 0, s));
+        } else {
+          HIPCHK(ctx, hipLaunchKernel(kfn, dim3(KG), dim3(kKryPBlock), args, 0, s));
+        }
+        HIPCHK(ctx, hipMemcpyAsync(ctx->h_kH, ctx->d_kH, hsz * sizeof(double), hipMemcpyDeviceToHost, s));
+        HIPCHK(ctx, hipStreamSynchronize(s));
+        if (ctx->h_kH[hsz - 1] == 0.0) return ctx->h_kH[hsz - 3] > 0.0;
+        ctx->tm.aborts += 1;
+      }
+      ctx->err = "a Krylov basis launch aborted twice (grid barrier timed out)";
+      throw Fail{LJ_EHIP};
     }
     HIPCHK(ctx, launch_kry_start(K, X, s));
-    HIPCHK(ctx, hipMemcpyAsync(ctx->h_kH + hsz - 2, K.scalars, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(ctx, hipMemcpyAsync(ctx->h_kH + hsz - 3, K.scalars, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
     HIPCHK(ctx, hipStreamSynchronize(s));
-    if (!(ctx->h_kH[hsz - 2] > 0.0)) break;  // w = 0 stays 0
+    if (!(ctx->h_kH[hsz - 3] > 0.0)) return false;  // w = 0 stays 0
     for (int j = 0; j < m; ++j) {
       const double* vj = K.V + (size_t)j * na;
       if (is_user(op)) {
@@ -1310,10 +1338,27 @@ int krylov_impl(lj_context* ctx, const OpDev& op, int p, const double* const* b,
       HIPCHK(ctx, launch_kry_update(K, j, lo, ndt, s));
       HIPCHK(ctx, launch_kry_scale(K, j, s));
     }
-    HIPCHK(ctx, hipMemcpyAsync(ctx->h_kH, ctx->d_kH, hsz * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(ctx, hipMemcpyAsync(ctx->h_kH, ctx->d_kH, (hsz - 1) * sizeof(double), hipMemcpyDeviceToHost, s));
     HIPCHK(ctx, hipStreamSynchronize(s));
-    const double beta = ctx->h_kH[hsz - 2];
-    const int brk = (int)ctx->h_kH[hsz - 1];  // breakdown at column brk - 1
+    return true;
+  };
+  std::memset(st, 0, sizeof(*st));
+  for (int k = 0; k < LJ_MAX_K; ++k) {
+    st->m_star[k] = -1;
+    st->substeps[k] = 1;
+  }
+  bool converged = true;
+  int substeps = 0, rejections = 0, products = 0, attempts = 0;
+  double t = 0.0, tau = h, last_est = 0.0;
+  std::vector<double> Hm, Mx, E;
+  while (t < h) {
+    if (substeps >= ko.max_substeps || attempts >= 10 * ko.max_substeps) {
+      converged = false;
+      break;
+    }
+    if (!basis()) break;  // w = 0 stays 0
+    const double beta = ctx->h_kH[hsz - 3];
+    const int brk = (int)ctx->h_kH[hsz - 2];  // breakdown at column brk - 1
     const int me = brk > 0 ? brk : m;
     products += me;
     const bool exact = me < m;
@@ -1448,6 +1493,7 @@ LJ_API int lj_create(lj_context** out, int hip_device) {
     if (const char* g = std::getenv("LJ_GRID")) ctx->grid_override = std::atoi(g);
     if (const char* g = std::getenv("LJ_NO_TILE")) ctx->force_stream = std::atoi(g);
     if (const char* g = std::getenv("LJ_COOP")) ctx->force_coop = std::atoi(g);
+    if (const char* g = std::getenv("LJ_KRYLOV_PASSES")) ctx->krylov_passes = std::atoi(g);
     if (const char* g = std::getenv("LJ_FORCE_SPIN_LIMIT")) {
       const long v = std::atol(g);
       ctx->forced_spin_limit = v > 0 ? (unsigned int)std::min<long>(v, kGridSpinLimit) : 0u;

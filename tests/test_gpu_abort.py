@@ -52,3 +52,37 @@ def test_forced_barrier_abort_is_retried(name, monkeypatch):
     assert np.array_equal(got[2], ref[2])
     assert [s["m_star"] for s in got[4]] == [s["m_star"] for s in ref[4]]
     assert np.array_equal(got[5], ref[5])
+
+
+def _krylov(lj, torch, ctx, prob):
+    op = lj.operator_from(prob, "cuda:0")
+    f = torch.empty_like(op.state)
+    lj.lj_rhs(ctx, op, op.state, f)
+    w = torch.empty_like(f)
+    rc, st = lj.lj_phi_combination(ctx, op, [None, f, None, f], 10 * prob.h_cfl, 1e-10, w)
+    torch.cuda.synchronize()
+    return rc, st, w.cpu().numpy()
+
+
+def test_forced_barrier_abort_krylov_basis(monkeypatch):
+    """The persistent Krylov basis launch under the same hook: aborted, then
+    repeated cooperatively, bit for bit the unhooked result."""
+    import torch
+
+    import paper_2211_08948_amd as lj
+    prob = allen_cahn_noise(256, eps=1e-3, seed=2)
+    ref_ctx = lj.Context(0)
+    ref = _krylov(lj, torch, ref_ctx, prob)
+    ref_ctx.close()
+    monkeypatch.setenv("LJ_FORCE_SPIN_LIMIT", "2")
+    ctx = lj.Context(0)
+    monkeypatch.delenv("LJ_FORCE_SPIN_LIMIT")
+    lj.lj_timing_read(ctx, reset=True)
+    got = _krylov(lj, torch, ctx, prob)
+    aborts = lj.lj_timing_read(ctx, reset=True)["aborts"]
+    ctx.close()
+    say("forced abort krylov", aborts, ref[1]["substeps"], got[1]["substeps"])
+    assert aborts >= 1
+    assert got[0] == ref[0] == 0 and got[1]["substeps"] == ref[1]["substeps"]
+    assert got[1]["iters_total"] == ref[1]["iters_total"]
+    assert np.array_equal(got[2], ref[2])

@@ -47,7 +47,7 @@ def _bs(prob):
 
 
 @pytest.mark.parametrize("name", list(CASES))
-@pytest.mark.parametrize("window", [2, 0])
+@pytest.mark.parametrize("window", [2, 8, 0])
 @pytest.mark.parametrize("mult,m", [(10, 30), (30, 10)])
 def test_combination_parity(env, name, window, mult, m):
     lj, torch, ctx = env
@@ -66,6 +66,33 @@ def test_combination_parity(env, name, window, mult, m):
     assert st["substeps"] == [st_orc.substeps] and st["rejections"] == st_orc.rejections
     assert st["iters_total"] == st_orc.products
     assert rel(w.cpu().numpy(), w_orc) <= 1e-11
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_persistent_basis_matches_passes(env, name, monkeypatch):
+    """Windows of 1 .. 8 vectors build the basis in one persistent launch; the
+    hook LJ_KRYLOV_PASSES=1 forces the four-launches-per-column kernels.  The
+    two differ only in the order of the dot products' partial sums."""
+    lj, torch, ctx = env
+    prob = CASES[name]()
+    h = 30 * prob.h_cfl
+    bs = [None if b is None else _dev(torch, b) for b in _bs(prob)]
+    J = lj.operator_from(prob, "cuda:0")
+    monkeypatch.setenv("LJ_KRYLOV_PASSES", "1")
+    ctx_p = lj.Context(0)
+    monkeypatch.delenv("LJ_KRYLOV_PASSES")
+    for window in (1, 2, 8):
+        ko = lj.lj_default_krylov_options(krylov_dim=30, window=window)
+        w1 = torch.empty(prob.n, dtype=torch.float64, device="cuda:0")
+        w2 = torch.empty_like(w1)
+        rc1, st1 = lj.lj_phi_combination(ctx, J, bs, h, TOL, w1, ko)
+        rc2, st2 = lj.lj_phi_combination(ctx_p, J, bs, h, TOL, w2, ko)
+        say("persistent vs passes", name, window, st1["substeps"], st2["substeps"], st1["iters_total"])
+        assert rc1 == rc2 == 0
+        assert st1["substeps"] == st2["substeps"] and st1["rejections"] == st2["rejections"]
+        assert st1["iters_total"] == st2["iters_total"]
+        assert rel(w1.cpu().numpy(), w2.cpu().numpy()) <= 1e-13
+    ctx_p.close()
 
 
 def test_combination_matches_dense_pade(env):
