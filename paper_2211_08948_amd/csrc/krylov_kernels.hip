@@ -155,123 +155,201 @@ __device__ __forceinline__ void kry_point_range(int npts, int& p0, int& p1) {
   p1 = min(npts, p0 + chunk);
 }
 
+// One phase per column, one grid all-reduce per phase.  With u_j the
+// orthogonalised, not yet normalised vector of column j (u_0 = w) and
+// eta_j = ||u_j||, V_j = u_j / eta_j, the product is applied to u_j, and
+// A~ V_j = z_j / eta_j with z_j = A~ u_j (A~ is linear).  Phase k (0 <= k <= m):
+//   u_k = z_{k-1} / eta_{k-1} - h_{k-2,k-1} V_{k-2} - h_{k-1,k-1} V_{k-1}
+//   (the window's terms in that order; u_0 = w), formed at the point and,
+//   for the stencil, at its neighbours from z_{k-1}, u_{k-1} (V_{k-1} =
+//   u_{k-1} / eta_{k-1}) and the stored V_{k-2}, all written before the last
+//   barrier; V_{k-1} is stored; ||u_k||^2 partials; for k < m: z_k = A~ u_k
+//   and the window's dot partials <V_{k-1}, z_k> and <u_k, z_k>.
+// After the all-reduce: eta_k, H[k][k-1] = eta_k (k >= 1, breakdown below
+// 1e-300 ends the basis), H[k-1][k] = <V_{k-1}, z_k> / eta_k and
+// H[k][k] = <u_k, z_k> / eta_k / eta_k.  u and z alternate between two
+// buffers each, so a phase's gathers never race the next phase's writes.
+// Every load of a phase is unconditional (absent terms read a valid
+// stand-in and are multiplied by nothing), so all of a point's loads are in
+// flight at once: the phase costs one memory round trip, not one per term.
 template <int KIND, int NC>
 __global__ __launch_bounds__(kKryPBlock) void kry_arnoldi_kernel(KryArnoldi P) {
   const GridSync gs{P.barrier, P.spin_limit};
-  __shared__ double red[kKryChunk * (kKryPBlock / 64 + 1)];
-  __shared__ double tot[kKryChunk];
+  constexpr int kSlots = 3;  // <V_{k-1}, z_k>, <u_k, z_k>, ||u_k||^2
+  __shared__ double red[kSlots * (kKryPBlock / 64 + 1)];
+  __shared__ double tot[kSlots];
   const KryDev& K = P.K;
   const OpDev& op = P.op;
   const long N = K.N, na = K.na;
   const int np = K.p;
+  const int m = K.m;
   int p0, p1;
   kry_point_range(op.npts, p0, p1);
   // the auxiliary entries N .. N + np - 1 belong to block 0, one per thread
   const bool aux = blockIdx.x == 0 && (int)threadIdx.x < np;
   const long ia = N + threadIdx.x;
   unsigned int epoch = 0;
-
-  // beta = ||w||
-  double s1[1] = {0.0};
-  for (int p = p0 + (int)threadIdx.x; p < p1; p += blockDim.x)
+  double eta_prev = 1.0;    // eta_{k-1}
+  double h_a = 0.0;         // h_{k-2,k-1} (0 when outside the window)
+  double h_b = 0.0;         // h_{k-1,k-1}
+  bool two_prev = false;    // the window of column k-1 held V_{k-2}
+  for (int k = 0; k <= m; ++k) {
+    const double* Zp = P.Z[(k + 1) & 1];  // z_{k-1}
+    const double* Up = P.U[(k + 1) & 1];  // u_{k-1}
+    // V_{k-2}, or a valid stand-in whose term is not used
+    const double* Va = two_prev ? K.V + (size_t)(k - 2) * na : Up;
+    double* Uk = P.U[k & 1];
+    double* Zk = P.Z[k & 1];
+    double* Vprev = K.V + (size_t)(k > 0 ? k - 1 : 0) * na;
+    const bool prod = k < m;
+    const bool two = P.window >= 2 && k >= 1;  // column k's window holds V_{k-1}
+    // u_k from the loaded values at one element
+    auto u_from = [&](double z, double u1, double va) -> double {
+      double x = z / eta_prev;
+      if (two_prev) x = x - h_a * va;
+      return x - h_b * (u1 / eta_prev);
+    };
+    // tail of u_k (the same in every thread)
+    double y[kKryMaxP];
+    {
+      double zt[kKryMaxP], ut[kKryMaxP], vt[kKryMaxP];
 #pragma unroll
-    for (int c = 0; c < NC; ++c) s1[0] += P.w[NC * p + c] * P.w[NC * p + c];
-  if (aux) s1[0] += P.w[ia] * P.w[ia];
-  block_sum<1>(s1, red);
-  double* area = partial_area(P.partials, epoch);
-  if (threadIdx.x == 0) put_partial(my_partial(area, 0), s1[0]);
-  grid_allreduce(gs, epoch, area, 1, tot);
-  double hs = sqrt(tot[0]);
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
-    K.scalars[0] = hs;
-    K.scalars[1] = 0.0;
-  }
-  const double* src = P.w;  // V_j = src / hs
-  if (hs > 0.0) {
-    for (int j = 0; j < K.m; ++j) {
-      double* dst = P.Wb[j & 1];
-      double* vj = K.V + (size_t)j * na;
-      const int lo = max(0, j - P.window + 1);
-      const int nd = j - lo + 1;
-      double y[kKryMaxP];
+      for (int t = 0; t < kKryMaxP; ++t) {
+        const long e = N + min(t, max(np - 1, 0));
+        const bool ok = np > 0;
+        zt[t] = (k > 0 && ok) ? Zp[e] : 0.0;
+        ut[t] = (k > 0 && ok) ? Up[e] : 0.0;
+        vt[t] = (k > 0 && ok) ? Va[e] : 0.0;
+        if (k == 0) zt[t] = ok ? P.w[e] : 0.0;
+      }
 #pragma unroll
-      for (int k = 0; k < kKryMaxP; ++k) y[k] = (k < np) ? src[N + k] / hs : 0.0;
-      double acc[kKryChunk];
+      for (int t = 0; t < kKryMaxP; ++t) y[t] = (t < np) ? (k == 0 ? zt[t] : u_from(zt[t], ut[t], vt[t])) : 0.0;
+    }
+    double acc[kSlots] = {0.0, 0.0, 0.0};
+    for (int p = p0 + (int)threadIdx.x; p < p1; p += blockDim.x) {
+      double xv[5][2], uv[5][2], out[2], ucen[2];
 #pragma unroll
-      for (int d = 0; d < kKryChunk; ++d) acc[d] = 0.0;
-      // (1) x = J V_j + B y (grid part), x = K y (auxiliary part); the dots
-      for (int p = p0 + (int)threadIdx.x; p < p1; p += blockDim.x) {
-        double xv[5][2], uv[5][2], out[2];
-        gather_point<KIND, NC>(op, src, p, xv, uv);
+      for (int t = 0; t < 5; ++t) {
+        xv[t][0] = xv[t][1] = 0.0;
+        uv[t][0] = uv[t][1] = 0.0;
+      }
+      int idx[5];
+      if constexpr (KIND == OP_DIAG) {
+        idx[0] = idx[1] = idx[2] = idx[3] = idx[4] = p;
+      } else {
+        const Nbr q = neighbours<KIND>(op, p);
+        idx[0] = q.c;
+        idx[1] = q.w;
+        idx[2] = q.e;
+        idx[3] = q.s;
+        idx[4] = q.n;
+      }
+      constexpr int nt = (KIND == OP_DIAG) ? 1 : 5;
+      double zl[5][2], ul[5][2], vl[5][2];
 #pragma unroll
-        for (int t = 0; t < 5; ++t)
+      for (int t = 0; t < nt; ++t)
 #pragma unroll
-          for (int c = 0; c < NC; ++c) xv[t][c] = xv[t][c] / hs;
+        for (int c = 0; c < NC; ++c) {
+          const long e = (long)NC * idx[t] + c;
+          if (k == 0) {
+            zl[t][c] = P.w[e];
+            ul[t][c] = vl[t][c] = 0.0;
+          } else {
+            zl[t][c] = Zp[e];
+            ul[t][c] = Up[e];
+            vl[t][c] = Va[e];
+          }
+        }
+#pragma unroll
+      for (int t = 0; t < nt; ++t)
+#pragma unroll
+        for (int c = 0; c < NC; ++c) xv[t][c] = (k == 0) ? zl[t][c] : u_from(zl[t][c], ul[t][c], vl[t][c]);
+#pragma unroll
+      for (int c = 0; c < NC; ++c) ucen[c] = ul[0][c];
+      if (prod) {
+        if constexpr (KIND == OP_DIAG) {
+          uv[0][0] = op.state[p];
+        } else {
+          constexpr int su = StateUse<KIND>::value;
+#pragma unroll
+          for (int t = 0; t < su; ++t)
+#pragma unroll
+            for (int c = 0; c < NC; ++c) uv[t][c] = op.state[NC * idx[t] + c];
+        }
         stencil_jv<KIND>(op, xv, uv, out);
+      }
 #pragma unroll
-        for (int c = 0; c < NC; ++c) {
-          const long i = (long)NC * p + c;
-          const double v = xv[0][c];
-          store_shared(vj + i, v);
-          double x = out[c];
-          for (int k = 0; k < np; ++k)
-            if (K.B[k] != nullptr) x = x + y[k] * K.B[k][i];
-          store_shared(dst + i, x);
-#pragma unroll
-          for (int d = 0; d < kKryChunk; ++d)
-            if (d < nd) acc[d] += ((d == nd - 1) ? v : K.V[(size_t)(lo + d) * na + i]) * x;
+      for (int c = 0; c < NC; ++c) {
+        const long e = (long)NC * p + c;
+        const double u = xv[0][c];
+        double vk1 = 0.0;
+        if (k > 0) {
+          vk1 = ucen[c] / eta_prev;
+          store_shared(Vprev + e, vk1);
+        }
+        store_shared(Uk + e, u);
+        acc[2] += u * u;
+        if (prod) {
+          double z = out[c];
+          for (int t = 0; t < np; ++t)
+            if (K.B[t] != nullptr) z = z + y[t] * K.B[t][e];
+          store_shared(Zk + e, z);
+          if (two) acc[0] += vk1 * z;
+          acc[1] += u * z;
         }
       }
-      if (aux) {
-        const double v = src[ia] / hs;
-        store_shared(vj + ia, v);
-        const int t = threadIdx.x;
-        const double x = (t + 1 < np) ? y[t + 1] : 0.0;
-        store_shared(dst + ia, x);
-#pragma unroll
-        for (int d = 0; d < kKryChunk; ++d)
-          if (d < nd) acc[d] += ((d == nd - 1) ? v : K.V[(size_t)(lo + d) * na + ia]) * x;
+    }
+    if (aux) {
+      const int t = threadIdx.x;
+      const double u = y[t];
+      double vk1 = 0.0;
+      if (k > 0) {
+        vk1 = Up[ia] / eta_prev;
+        store_shared(Vprev + ia, vk1);
       }
-      block_sum<kKryChunk>(acc, red);
-      area = partial_area(P.partials, epoch);
-      if (threadIdx.x == 0) {
-#pragma unroll
-        for (int d = 0; d < kKryChunk; ++d)
-          if (d < nd) put_partial(my_partial(area, d), acc[d]);
+      store_shared(Uk + ia, u);
+      acc[2] += u * u;
+      if (prod) {
+        const double z = (t + 1 < np) ? y[t + 1] : 0.0;
+        store_shared(Zk + ia, z);
+        if (two) acc[0] += vk1 * z;
+        acc[1] += u * z;
       }
-      grid_allreduce(gs, epoch, area, nd, tot);
-      if (blockIdx.x == 0 && (int)threadIdx.x < nd) K.H[(size_t)(lo + threadIdx.x) * K.m + j] = tot[threadIdx.x];
-      // (2) x -= sum_d h_d V_{lo+d} in order of d; ||x||^2
-      double s2[1] = {0.0};
-      for (int p = p0 + (int)threadIdx.x; p < p1; p += blockDim.x)
-#pragma unroll
-        for (int c = 0; c < NC; ++c) {
-          const long i = (long)NC * p + c;
-          double x = dst[i];
-          for (int d = 0; d < nd; ++d) x = x - tot[d] * K.V[(size_t)(lo + d) * na + i];
-          store_shared(dst + i, x);
-          s2[0] += x * x;
-        }
-      if (aux) {
-        double x = dst[ia];
-        for (int d = 0; d < nd; ++d) x = x - tot[d] * K.V[(size_t)(lo + d) * na + ia];
-        store_shared(dst + ia, x);
-        s2[0] += x * x;
-      }
-      block_sum<1>(s2, red);
-      area = partial_area(P.partials, epoch);
-      if (threadIdx.x == 0) put_partial(my_partial(area, 0), s2[0]);
-      grid_allreduce(gs, epoch, area, 1, tot);
-      const double hn = sqrt(tot[0]);
-      const bool broke = !(hn > 1e-300);
+    }
+    block_sum<kSlots>(acc, red);
+    double* area = partial_area(P.partials, epoch);
+    if (threadIdx.x == 0) {
+      put_partial(my_partial(area, 0), acc[0]);
+      put_partial(my_partial(area, 1), acc[1]);
+      put_partial(my_partial(area, 2), acc[2]);
+    }
+    grid_allreduce(gs, epoch, area, kSlots, tot);
+    const double eta = sqrt(tot[2]);
+    if (k == 0) {
       if (blockIdx.x == 0 && threadIdx.x == 0) {
-        K.H[(size_t)(j + 1) * K.m + j] = hn;
-        if (broke) K.scalars[1] = (double)(j + 1);
+        K.scalars[0] = eta;
+        K.scalars[1] = 0.0;
+      }
+      if (!(eta > 0.0)) break;  // w = 0
+    } else {
+      const bool broke = !(eta > 1e-300);
+      if (blockIdx.x == 0 && threadIdx.x == 0) {
+        K.H[(size_t)k * m + (k - 1)] = eta;
+        if (broke) K.scalars[1] = (double)k;
       }
       if (broke) break;
-      src = dst;
-      hs = hn;
     }
+    if (!prod) break;
+    const double hk1 = tot[0] / eta;         // h_{k-1,k}
+    const double hkk = tot[1] / eta / eta;   // h_{k,k}
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      if (two) K.H[(size_t)(k - 1) * m + k] = hk1;
+      K.H[(size_t)k * m + k] = hkk;
+    }
+    h_a = two ? hk1 : 0.0;
+    h_b = hkk;
+    two_prev = two;
+    eta_prev = eta;
   }
   if (blockIdx.x == 0 && threadIdx.x == 0) K.scalars[2] = grid_aborted(P.barrier) != 0u ? 1.0 : 0.0;
   grid_exit(P.barrier);

@@ -53,22 +53,22 @@ hipError_t launch_kry_combine(const KryDev& K, int m, double beta, const KryCoef
 hipError_t launch_kry_init(double* w, const double* b0, long N, int p, hipStream_t s);
 
 // The whole basis in one persistent launch, for a built-in family and a
-// window of 1 .. kKryChunk vectors: beta = ||w|| and V_0, then per column j
-// the product J V_j with B y and K y, the window's dots (grid all-reduce),
-// the subtraction and the norm (grid all-reduce); V_{j+1} is never stored
-// apart from the next column's pass, which reads the previous orthogonalised
-// vector and divides by its norm on the fly.  Two barriers per column.
-// Writes what the per-pass kernels write (V_0 .. V_{m_eff - 1}, H, scalars
-// [0] and [1]) and scalars[2] = 1 when a grid barrier timed out (the launch
-// is then to be repeated cooperatively).  Blocks of kKryPBlock threads, at
-// most one per CU; every block must be resident at once.
+// window of 1 or 2 vectors, with one grid all-reduce per column: the
+// product is applied to the orthogonalised vector before its normalisation
+// (A~ is linear) and the window's dots, the next norm and the product share
+// one pass (see the kernel).  Writes what the per-pass kernels write
+// (V_0 .. V_{m_eff - 1}, H, scalars [0] and [1]) and scalars[2] = 1 when a
+// grid barrier timed out (the launch is then to be repeated cooperatively).
+// Blocks of kKryPBlock threads, at most one per CU; every block must be
+// resident at once.
 constexpr int kKryPBlock = 1024;
 struct KryArnoldi {
   KryDev K;
   OpDev op;
   const double* w;         // start vector (augmented length), not modified
-  double* Wb[2];           // column j's product, in Wb[j & 1] (augmented length)
-  int window;              // 1 .. kKryChunk
+  double* U[2];            // u_k in U[k & 1] (augmented length)
+  double* Z[2];            // z_k = A~ u_k in Z[k & 1] (augmented length)
+  int window;              // 1 or 2
   double* partials;        // 2 x kPartStride x gridDim partial sums
   unsigned int* barrier;   // grid barrier words, zero at launch (left zero)
   unsigned int spin_limit; // bound on each barrier wait

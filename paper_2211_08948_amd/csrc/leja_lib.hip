@@ -40,7 +40,8 @@ enum Slot {
   W_IU0, W_IU1, W_IERR,            // variable-step integration: state ping-pong, error estimate
   W_UJ, W_UPT, W_UY, W_UPA, W_UPB, // user operators: product, finite-difference point, power vectors
   W_UFU, W_UXR, W_UD, W_UFX, W_UJD, W_UR0, W_UR1,  // f(u), stage remainders
-  W_KV, W_KW, W_KW2, W_KX, W_KC,   // Krylov: basis, products, augmented vector, LeKry third stage
+  W_KV, W_KW, W_KX, W_KC,          // Krylov: basis, product, augmented vector, LeKry third stage
+  W_KU0, W_KU1, W_KZ0, W_KZ1,      // Krylov, one-launch basis: orthogonalised vectors and their products
   W_NSLOTS
 };
 
@@ -1279,9 +1280,9 @@ int krylov_impl(lj_context* ctx, const OpDev& op, int p, const double* const* b,
   K.scalars = ctx->d_kH + (size_t)(kKryMaxDim + 1) * kKryMaxDim;
   double* X = slot(ctx, W_KX, na);
   HIPCHK(ctx, launch_kry_init(X, b[0], N, p, s));
-  // built-in families with a window of at most kKryChunk vectors: the whole
-  // basis in one persistent launch; otherwise four launches per column
-  const bool persistent = !is_user(op) && ko.window >= 1 && ko.window <= kKryChunk && !ctx->krylov_passes;
+  // built-in families with a window of 1 or 2 vectors: the whole basis in
+  // one persistent launch; otherwise four launches per column
+  const bool persistent = !is_user(op) && ko.window >= 1 && ko.window <= 2 && !ctx->krylov_passes;
   KryArnoldi KA;
   std::memset(&KA, 0, sizeof(KA));
   const void* kfn = nullptr;
@@ -1290,8 +1291,10 @@ int krylov_impl(lj_context* ctx, const OpDev& op, int p, const double* const* b,
     KA.K = K;
     KA.op = op;
     KA.w = X;
-    KA.Wb[0] = K.W;
-    KA.Wb[1] = slot(ctx, W_KW2, na);
+    KA.U[0] = slot(ctx, W_KU0, na);
+    KA.U[1] = slot(ctx, W_KU1, na);
+    KA.Z[0] = slot(ctx, W_KZ0, na);
+    KA.Z[1] = slot(ctx, W_KZ1, na);
     KA.window = ko.window;
     KG = grid_for(ctx, op.npts);
     ensure_small(ctx, KG);
