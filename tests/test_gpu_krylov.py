@@ -95,6 +95,36 @@ def test_persistent_basis_matches_passes(env, name, monkeypatch):
     ctx_p.close()
 
 
+@pytest.mark.parametrize("passes", [False, True])
+def test_exact_breakdown(env, passes, monkeypatch):
+    """A constant on the periodic advection-diffusion grid: J c = 0 exactly, so
+    with b_0 = c (and b_1 = 0) A~ maps the start vector to 0 and the basis
+    ends at the breakdown after one vector: the projection is exact, one
+    substep, w = c.  With b_1 = c the space is invariant after two vectors
+    only up to rounding (A~ [c; 1] = [c; 0], A~ [c; 0] = 0): no breakdown in
+    floating point, the full basis is built on the rounding residue, and the
+    result is still c + h c."""
+    lj, torch, ctx0 = env
+    if passes:
+        monkeypatch.setenv("LJ_KRYLOV_PASSES", "1")
+    ctx = lj.Context(0)
+    monkeypatch.delenv("LJ_KRYLOV_PASSES", raising=False)
+    prob = CASES["advdiff"]()
+    op = Operator(prob)
+    c = np.full(prob.n, 0.75)
+    J = lj.operator_from(prob, "cuda:0")
+    w = torch.empty(prob.n, dtype=torch.float64, device="cuda:0")
+    h = 30 * prob.h_cfl
+    for bs, expect, prods in (([c], c, 1), ([c, 0 * c], c, 1), ([c, c], c + h * c, 30)):
+        w_orc, st_orc = phi_combination(op.jv, bs, h, TOL, KrylovOptions())
+        assert st_orc.products == prods and st_orc.substeps == 1
+        rc, st = lj.lj_phi_combination(ctx, J, [_dev(torch, b) for b in bs], h, TOL, w)
+        say("breakdown", "passes" if passes else "persistent", len(bs), st["iters_total"], st["substeps"])
+        assert rc == 0 and st["iters_total"] == prods and st["substeps"] == [1] and st["rejections"] == 0
+        assert rel(w.cpu().numpy(), expect) <= 1e-14 and rel(w_orc, expect) <= 1e-14
+    ctx.close()
+
+
 def test_combination_matches_dense_pade(env):
     lj, torch, ctx = env
     prob = allen_cahn_noise(16, eps=1e-2, seed=8)
