@@ -16,7 +16,7 @@ OUT = os.path.join(HERE, "libleja.so")
 ARCH = "gfx950"
 
 SOURCES = ["kernels.hip", "mlp.hip", "user_kernels.hip", "krylov_kernels.hip", "bandwidth.hip", "leja_lib.hip",
-           "leja_points.cpp"]
+           "leja_points.cpp", "small_expm.cpp"]
 HIP_FLAGS = [
     "-O3", "-std=c++17", f"--offload-arch={ARCH}", "-fPIC", "-Wall", "-Wno-unused-result",
     "-fvisibility=hidden",

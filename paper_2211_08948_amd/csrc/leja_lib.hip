@@ -21,6 +21,7 @@
 #include "kernels.hpp"
 #include "mlp.hpp"
 #include "krylov_kernels.hpp"
+#include "small_expm.hpp"
 #include "user_kernels.hpp"
 
 namespace lj {
@@ -1196,57 +1197,6 @@ KryOpts resolve_krylov(lj_context* ctx, const lj_krylov_options* k) {
   if (r.window < 0) invalid(ctx, "krylov options: window must be >= 0");
   if (r.max_substeps < 1) invalid(ctx, "krylov options: max_substeps must be >= 1");
   return r;
-}
-
-// C = A B for small dense n x n matrices (row-major), row by row so that the
-// inner loop runs over contiguous entries
-void matmul_small(const double* A, const double* B, double* C, int n) {
-  for (int i = 0; i < n * n; ++i) C[i] = 0.0;
-  for (int r = 0; r < n; ++r)
-    for (int q = 0; q < n; ++q) {
-      const double a = A[(size_t)r * n + q];
-      if (a == 0.0) continue;
-      const double* b = B + (size_t)q * n;
-      double* c = C + (size_t)r * n;
-      for (int j = 0; j < n; ++j) c[j] += a * b[j];
-    }
-}
-
-// exp(A) of a small dense n x n matrix (row-major) by scaling and squaring of
-// a truncated Taylor series (Moler and Van Loan): X = A / 2^s with
-// ||X||_1 <= 1/2, terms X^k / k! added until one falls below 2^-60 in every
-// entry (the rest of the series is then smaller than that term), at most 30,
-// then s squarings.
-void expm_small(const std::vector<double>& A, int n, std::vector<double>& E) {
-  double nrm = 0.0;
-  for (int c = 0; c < n; ++c) {
-    double col = 0.0;
-    for (int r = 0; r < n; ++r) col += std::fabs(A[(size_t)r * n + c]);
-    nrm = std::max(nrm, col);
-  }
-  int sq = 0;
-  if (nrm > 0.5) sq = (int)std::ceil(std::log2(nrm / 0.5));
-  const double scale = std::ldexp(1.0, -sq);
-  std::vector<double> X((size_t)n * n), T((size_t)n * n), T2((size_t)n * n);
-  for (size_t i = 0; i < X.size(); ++i) X[i] = A[i] * scale;
-  E.assign((size_t)n * n, 0.0);
-  for (int i = 0; i < n; ++i) E[(size_t)i * n + i] = 1.0;
-  T = E;  // X^k / k!
-  for (int k = 1; k <= 30; ++k) {
-    matmul_small(T.data(), X.data(), T2.data(), n);
-    double tmax = 0.0;
-    for (size_t i = 0; i < T2.size(); ++i) {
-      T2[i] /= (double)k;
-      tmax = std::max(tmax, std::fabs(T2[i]));
-    }
-    T.swap(T2);
-    for (size_t i = 0; i < E.size(); ++i) E[i] += T[i];
-    if (tmax <= 0x1p-60) break;
-  }
-  for (int k = 0; k < sq; ++k) {
-    matmul_small(E.data(), E.data(), T2.data(), n);
-    E.swap(T2);
-  }
 }
 
 // w = sum_{j=0}^{p} phi_j(h J) b_j h^j (b[j] may be nullptr) as the first block
