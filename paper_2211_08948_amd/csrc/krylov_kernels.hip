@@ -6,6 +6,8 @@
 // at once.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "device.hpp"
 #include "krylov_kernels.hpp"
 
@@ -124,11 +126,21 @@ __global__ __launch_bounds__(kKryBlock) void kry_scale_kernel(KryDev K, int j) {
     vn[i] = K.W[i] / hn;
 }
 
+// The sum runs over c in order; the basis entries are loaded eight at a time
+// before they are used, so eight loads per thread are in flight.
 __global__ __launch_bounds__(kKryBlock) void kry_combine_kernel(KryDev K, int m, double beta, KryCoef F,
                                                                double* __restrict__ out) {
   for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < K.na; i += (long)gridDim.x * blockDim.x) {
     double a = 0.0;
-    for (int c = 0; c < m; ++c) a += K.V[(size_t)c * K.na + i] * F.f[c];
+    int c = 0;
+    for (; c + 8 <= m; c += 8) {
+      double v[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) v[q] = K.V[(size_t)(c + q) * K.na + i];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) a += v[q] * F.f[c + q];
+    }
+    for (; c < m; ++c) a += K.V[(size_t)c * K.na + i] * F.f[c];
     out[i] = beta * a;
   }
 }
@@ -401,7 +413,9 @@ hipError_t launch_kry_scale(const KryDev& K, int j, hipStream_t s) {
 }
 
 hipError_t launch_kry_combine(const KryDev& K, int m, double beta, const KryCoef& F, double* out, hipStream_t s) {
-  hipLaunchKernelGGL(kry_combine_kernel, dim3(kry_grid(K.na)), dim3(kKryBlock), 0, s, K, m, beta, F, out);
+  // one entry per thread up to 4096 blocks: the pass reads m vectors
+  const long g = std::min<long>(std::max<long>((K.na + kKryBlock - 1) / kKryBlock, 1), 4096);
+  hipLaunchKernelGGL(kry_combine_kernel, dim3((int)g), dim3(kKryBlock), 0, s, K, m, beta, F, out);
   return hipGetLastError();
 }
 
