@@ -473,7 +473,15 @@ typedef struct {
  * positive number at lj_create, the first (ordinary) launch of every action
  * bounds each grid-barrier wait by that many polls instead of the default
  * 2^22.  A small value makes those launches give up, so the abort-and-retry
- * path (the cooperative relaunch) runs; results are unchanged. */
+ * path (the cooperative relaunch) runs; results are unchanged.  The same
+ * bound applies to the first launch of each one-launch Krylov basis
+ * (lj_phi_combination, the LeKry third stage).
+ *
+ * Test hook: LJ_KRYLOV_PASSES=1 at lj_create makes the Krylov evaluation of
+ * built-in families build every basis with four launches per column (the
+ * form user operators and windows wider than 2 always use) instead of one
+ * launch per basis; results agree up to the order of the dot products'
+ * partial sums. */
 
 /* Diagnostics: the reduced norms the last Newton recurrence on ctx decided
  * on.  Row m-1 (m = 1..iterations) holds ||y_m||_2^2 followed by ||p_k||_2^2
