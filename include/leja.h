@@ -193,7 +193,10 @@ typedef enum {
   LJ_EPIRK4S3 = 4,   /* fourth-order u_4 of EPIRK4s3 (Sec. 5.1 equation), err = u_4 - u_3 */
   LJ_EPIRK4S3_LEKRY = 5 /* EPIRK4s3 as "LeKry" (Sec. 5.1 text): the internal stages by Leja (vertical),
                            phi_1(hJ) h f(u) + phi_3(hJ) D_3 of u_3 as one Krylov exponential
-                           (lj_phi_combination, default Krylov options), the phi_4 term by Leja */
+                           (lj_phi_combination, default Krylov options), the phi_4 term by Leja */,
+  LJ_EPIRK4S3A = 6,  /* fourth-order u_4 of EPIRK4s3A (Sec. 5.2 equation: stages at 1/2 and 2/3),
+                        err = u_4 - u_3 */
+  LJ_EPIRK4S3A_LEKRY = 7 /* EPIRK4s3A as "LeKry" (Sec. 5.2 text), built like LJ_EPIRK4S3_LEKRY */
 } lj_scheme;
 
 /* One step from u = J->state with step size h: u_out (device) receives the
@@ -201,7 +204,7 @@ typedef enum {
  * u_4 - u_3 (zero-filled for schemes without one).  One power iteration per
  * step is shared by all actions.  stats (host) may be NULL; otherwise it is an
  * array of `nstats` entries receiving the statistics of the step's Leja calls
- * in order (EXPRB2: 1, EXPRB43_U3: 3, EXPRB43: 4, EPIRK4S3: 3, EPIRK4S3_LEKRY: 3 -- the
+ * in order (EXPRB2: 1, EXPRB43_U3: 3, EXPRB43: 4, EPIRK4S3 and EPIRK4S3A: 3, the LeKry forms: 3 -- the
  * vertical Leja call, the Krylov call, the phi_4 Leja call); *ncalls (may be
  * NULL) receives that count. */
 LJ_API int lj_step(lj_context* ctx, int scheme, const lj_operator* J, double h, double tol,
@@ -259,8 +262,8 @@ typedef struct {
   int32_t accepted;
 } lj_step_record;
 
-/* u(T) of u_t = f(u), u(0) = J->state, with the embedded schemes (LJ_EPIRK4S3
- * or LJ_EXPRB43) and the step size control of Sec. 2.3: a step is accepted when
+/* u(T) of u_t = f(u), u(0) = J->state, with the embedded schemes (LJ_EPIRK4S3,
+ * LJ_EPIRK4S3A, their LeKry forms, or LJ_EXPRB43) and the step size control of Sec. 2.3: a step is accepted when
  * e = ||u_4 - u_3||_2 / ||u_4||_2 <= tol; the next size is the smaller of the
  * traditional controller's dt (tol/e)^{1/(p+1)} (p = 3, the embedded order)
  * and the cost controller's, whose cost is the step's Jacobian-vector

@@ -45,7 +45,7 @@ BETA = 0.26862269
 LAMBDA = 1.37412002
 DELTA = 0.64446017
 
-EMBEDDED_ORDER = {"EPIRK4S3": 3, "EXPRB43": 3, "EPIRK4S3_LEKRY": 3}
+EMBEDDED_ORDER = {"EPIRK4S3": 3, "EXPRB43": 3, "EPIRK4S3_LEKRY": 3, "EPIRK4S3A": 3, "EPIRK4S3A_LEKRY": 3}
 RETRY_SAFETY = 0.9  # retry after a rejection at 0.9 x the traditional size (a reading; see above)
 
 

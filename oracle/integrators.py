@@ -14,6 +14,11 @@ nonlinear remainders enter through R(x) = F(x) - F(u^n).  The schemes:
   internal stages phi_1(h/8 J), phi_1(h/9 J) by Leja (vertical), the third
   stage's phi_1(hJ) h f(u) + phi_3(hJ) D_3 as one augmented exponential by
   Krylov (oracle.krylov), and the phi_4 error term by Leja.
+* EPIRK4s3A (Sec. 5.2 equation): the same structure with the internal stages
+  at 1/2 and 2/3, u_3 = u + phi_1(hJ) h f + phi_3(hJ) (32 R(a) - 27/2 R(b)) h
+  and u_4 = u_3 + phi_4(hJ) (-144 R(a) + 81 R(b)) h; phi_1 at 1/2, 2/3 and 1
+  vertically, the rest individually (Sec. 5.2 text).  EPIRK4S3A_LEKRY: its
+  LeKry form (Sec. 5.2 text), built like EPIRK4S3_LEKRY.
 
 One spectral bound is computed per step and shared by every action (J is fixed
 over the step; Sec. 4: the re-scaling is done once).  err = u_4 - u_3 for the
@@ -95,6 +100,27 @@ def step(op, scheme: str, h: float, tol: float, opt: Options | None = None):
                          rejections=kst.rejections, converged=kst.converged))
         u3 = u + K3
         D4v = h * (-42336.0 * Ra - 34992.0 * (Rb - 2.0 * Ra))
+        (D4,) = act(D4v, [4], [1.0])
+        u4 = u3 + D4
+        out = (u4, u4 - u3)
+    elif scheme in ("EPIRK4S3A", "EPIRK4S3A_LEKRY"):
+        lekry = scheme == "EPIRK4S3A_LEKRY"
+        ws = act(v, [1, 1] if lekry else [1, 1, 1], [0.5, 2.0 / 3.0] if lekry else [0.5, 2.0 / 3.0, 1.0])
+        A, B = ws[0], ws[1]
+        a = u + 0.5 * A
+        b = u + (2.0 / 3.0) * B
+        Ra = op.remainder(a, fu)
+        Rb = op.remainder(b, fu)
+        D3v = h * (32.0 * Ra - 13.5 * Rb)
+        if lekry:
+            K3, kst = phi_combination(op.jv, [None, fu, None, D3v / h ** 3], h, tol, KrylovOptions())
+            log.append(Stats(m_star=[kst.products], substeps=[kst.substeps], iters_total=kst.products,
+                             rejections=kst.rejections, converged=kst.converged))
+            u3 = u + K3
+        else:
+            (D3,) = act(D3v, [3], [1.0])
+            u3 = u + ws[2] + D3
+        D4v = h * (-144.0 * Ra + 81.0 * Rb)
         (D4,) = act(D4v, [4], [1.0])
         u4 = u3 + D4
         out = (u4, u4 - u3)

@@ -17,7 +17,7 @@ from typing import Sequence
 
 from . import _lib
 from ._lib import (  # noqa: F401
-    LJ_EHIP, LJ_EINVAL, LJ_ENOMEM, LJ_ENOTCONV, LJ_EPIRK4S3, LJ_EPIRK4S3_LEKRY, LJ_EXPRB2, LJ_EXPRB43, LJ_EXPRB43_U3,
+    LJ_EHIP, LJ_EINVAL, LJ_ENOMEM, LJ_ENOTCONV, LJ_EPIRK4S3, LJ_EPIRK4S3_LEKRY, LJ_EPIRK4S3A, LJ_EPIRK4S3A_LEKRY, LJ_EXPRB2, LJ_EXPRB43, LJ_EXPRB43_U3,
     LJ_MAX_K, LJ_MAX_L, LJ_OK, LJ_OP_ADR2D, LJ_OP_ADVDIFF2D, LJ_OP_ALLENCAHN2D, LJ_OP_BRUSSELATOR2D, LJ_OP_BURGERS2D,
     LJ_OP_DIAG, LJ_OP_GRAYSCOTT2D, LejaLibraryError, lj_integrate_stats, lj_operator, lj_options, lj_stats, lj_step_record,
     lj_timing,
@@ -29,7 +29,7 @@ KIND_CODES = {
     "adr": LJ_OP_ADR2D,
 }
 SCHEMES = {"EXPRB2": LJ_EXPRB2, "EXPRB43_U3": LJ_EXPRB43_U3, "EXPRB43": LJ_EXPRB43, "EPIRK4S3": LJ_EPIRK4S3,
-           "EPIRK4S3_LEKRY": LJ_EPIRK4S3_LEKRY}
+           "EPIRK4S3_LEKRY": LJ_EPIRK4S3_LEKRY, "EPIRK4S3A": LJ_EPIRK4S3A, "EPIRK4S3A_LEKRY": LJ_EPIRK4S3A_LEKRY}
 
 
 class LejaError(RuntimeError):

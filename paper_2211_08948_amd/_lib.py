@@ -21,7 +21,7 @@ LJ_MLP_MODEL_FLOATS = 5414
 
 (LJ_OP_DIAG, LJ_OP_ADVDIFF2D, LJ_OP_ALLENCAHN2D, LJ_OP_BRUSSELATOR2D, LJ_OP_BURGERS2D, LJ_OP_GRAYSCOTT2D,
  LJ_OP_ADR2D) = range(7)
-LJ_EXPRB2, LJ_EXPRB43_U3, LJ_EXPRB43, LJ_EPIRK4S3, LJ_EPIRK4S3_LEKRY = 1, 2, 3, 4, 5
+LJ_EXPRB2, LJ_EXPRB43_U3, LJ_EXPRB43, LJ_EPIRK4S3, LJ_EPIRK4S3_LEKRY, LJ_EPIRK4S3A, LJ_EPIRK4S3A_LEKRY = 1, 2, 3, 4, 5, 6, 7
 
 
 class LejaLibraryError(RuntimeError):

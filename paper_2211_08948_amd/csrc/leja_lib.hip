@@ -1759,6 +1759,13 @@ int step_impl(lj_context* ctx, int scheme, const OpDev& op, Opts o, double h, do
     if (rc != LJ_OK) ok = false;
     log.push_back(kst);
   };
+  // EPIRK4s3 (Sec. 5.1 equation) and EPIRK4s3A (Sec. 5.2 equation): the
+  // internal-stage coefficients and the R(a), R(b) weights of the phi_3 term
+  // of u_3 and of the phi_4 term of u_4 - u_3
+  const bool epa = (scheme == LJ_EPIRK4S3A || scheme == LJ_EPIRK4S3A_LEKRY);
+  const double g1 = epa ? 0.5 : 1.0 / 8.0, g2 = epa ? 2.0 / 3.0 : 1.0 / 9.0;
+  const double d3a = epa ? 32.0 : 1892.0 - 2.0 * 1458.0, d3b = epa ? -13.5 : 1458.0;
+  const double d4a = epa ? -144.0 : -42336.0 + 2.0 * 34992.0, d4b = epa ? 81.0 : -34992.0;
   auto scheme_steps = [&](auto&& act) {
     double* fu = slot(ctx, W_FU, n);
     double* v = slot(ctx, W_V, n);
@@ -1862,7 +1869,7 @@ int step_impl(lj_context* ctx, int scheme, const OpDev& op, Opts o, double h, do
       } else {
         finish(B, D3, nullptr);
       }
-    } else if (scheme == LJ_EPIRK4S3_LEKRY) {
+    } else if (scheme == LJ_EPIRK4S3_LEKRY || scheme == LJ_EPIRK4S3A_LEKRY) {
       // LeKry (Sec. 5.1 text): internal stages by Leja (vertical), the third
       // stage's phi_1(hJ) h f(u) + phi_3(hJ) D_3 as one augmented exponential
       // by Krylov (b_1 = f(u), b_3 = D_3 / h^3), the phi_4 error term by Leja
@@ -1874,7 +1881,7 @@ int step_impl(lj_context* ctx, int scheme, const OpDev& op, Opts o, double h, do
       double* KC = slot(ctx, W_KC, n);
       {
         const int ls[2] = {1, 1};
-        const double as[2] = {1.0 / 8.0, 1.0 / 9.0};
+        const double as[2] = {g1, g2};
         double* outs[2] = {A, B};
         act(v, 2, ls, as, outs);
       }
@@ -1882,23 +1889,23 @@ int step_impl(lj_context* ctx, int scheme, const OpDev& op, Opts o, double h, do
         StageArgs S = stage_args();
         S.nrem = 2;
         S.nterm[0] = 1;
-        S.a[0][0] = 1.0 / 8.0;
+        S.a[0][0] = g1;
         S.X[0][0] = A;
         S.nterm[1] = 1;
-        S.a[1][0] = 1.0 / 9.0;
+        S.a[1][0] = g2;
         S.X[1][0] = B;
         S.nout = 2;
         S.nsrc[0] = 2;
         S.src[0][0] = 0;
-        S.c[0][0] = h * (1892.0 - 2.0 * 1458.0);
+        S.c[0][0] = h * d3a;
         S.src[0][1] = 1;
-        S.c[0][1] = h * 1458.0;
+        S.c[0][1] = h * d3b;
         S.out[0] = T3;
         S.nsrc[1] = 2;
         S.src[1][0] = 0;
-        S.c[1][0] = h * (-42336.0 + 2.0 * 34992.0);
+        S.c[1][0] = h * d4a;
         S.src[1][1] = 1;
-        S.c[1][1] = h * -34992.0;
+        S.c[1][1] = h * d4b;
         S.out[1] = T4;
         stage(S);
       }
@@ -1918,7 +1925,7 @@ int step_impl(lj_context* ctx, int scheme, const OpDev& op, Opts o, double h, do
         act(T4, 1, ls, as, &D4);
       }
       finish(KC, nullptr, D4);
-    } else {  // EPIRK4s3
+    } else {  // EPIRK4s3, EPIRK4s3A
       double* A = slot(ctx, W_A, n);
       double* B = slot(ctx, W_B, n);
       double* C = slot(ctx, W_C, n);
@@ -1928,32 +1935,32 @@ int step_impl(lj_context* ctx, int scheme, const OpDev& op, Opts o, double h, do
       double* D4 = slot(ctx, W_D4, n);
       {
         const int ls[3] = {1, 1, 1};
-        const double as[3] = {1.0 / 8.0, 1.0 / 9.0, 1.0};
+        const double as[3] = {g1, g2, 1.0};
         double* outs[3] = {A, B, C};
         act(v, 3, ls, as, outs);
       }
-      {  // R_a at u + A/8, R_b at u + B/9;
-         // h (1892 Ra + 1458 (Rb - 2 Ra)) and h (-42336 Ra - 34992 (Rb - 2 Ra))
+      {  // R_a at u + g1 A, R_b at u + g2 B;
+         // h (d3a Ra + d3b Rb) and h (d4a Ra + d4b Rb)
         StageArgs S = stage_args();
         S.nrem = 2;
         S.nterm[0] = 1;
-        S.a[0][0] = 1.0 / 8.0;
+        S.a[0][0] = g1;
         S.X[0][0] = A;
         S.nterm[1] = 1;
-        S.a[1][0] = 1.0 / 9.0;
+        S.a[1][0] = g2;
         S.X[1][0] = B;
         S.nout = 2;
         S.nsrc[0] = 2;
         S.src[0][0] = 0;
-        S.c[0][0] = h * (1892.0 - 2.0 * 1458.0);
+        S.c[0][0] = h * d3a;
         S.src[0][1] = 1;
-        S.c[0][1] = h * 1458.0;
+        S.c[0][1] = h * d3b;
         S.out[0] = T3;
         S.nsrc[1] = 2;
         S.src[1][0] = 0;
-        S.c[1][0] = h * (-42336.0 + 2.0 * 34992.0);
+        S.c[1][0] = h * d4a;
         S.src[1][1] = 1;
-        S.c[1][1] = h * -34992.0;
+        S.c[1][1] = h * d4b;
         S.out[1] = T4;
         stage(S);
       }
@@ -1976,7 +1983,8 @@ int step_impl(lj_context* ctx, int scheme, const OpDev& op, Opts o, double h, do
   // leaves the bound on the device for the others; statuses are read once
   // at the end.  If some expansion was rejected, the step is redone below
   // synchronously, with substeps, on the bound found.
-  const bool try_async = o.substeps <= 1 && !o.use_proposal && !is_user(op) && scheme != LJ_EPIRK4S3_LEKRY;
+  const bool try_async = o.substeps <= 1 && !o.use_proposal && !is_user(op) && scheme != LJ_EPIRK4S3_LEKRY &&
+                         scheme != LJ_EPIRK4S3A_LEKRY;
   double lam_found = o.bound;
   if (try_async) {
     struct Pending {
@@ -2074,7 +2082,7 @@ LJ_API int lj_step(lj_context* ctx, int scheme, const lj_operator* J, double h, 
   return guarded(ctx, [&]() {
     const OpDev op = make_op(ctx, J);
     Opts o = resolve(ctx, opt);
-    if (scheme < LJ_EXPRB2 || scheme > LJ_EPIRK4S3_LEKRY) invalid(ctx, "unknown scheme");
+    if (scheme < LJ_EXPRB2 || scheme > LJ_EPIRK4S3A_LEKRY) invalid(ctx, "unknown scheme");
     if (op.state == nullptr) invalid(ctx, "lj_step needs the state u in J->state");
     if (!std::isfinite(h)) invalid(ctx, "h must be finite");
     if (!(tol > 0.0) || !std::isfinite(tol)) invalid(ctx, "tol must be finite and > 0");
@@ -2098,7 +2106,7 @@ LJ_API int lj_user_step(lj_context* ctx, int scheme, const lj_user_operator* J, 
     const hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     Opts o = resolve(ctx, opt);
     if (o.use_proposal) invalid(ctx, "the learned proposal needs a built-in operator family");
-    if (scheme < LJ_EXPRB2 || scheme > LJ_EPIRK4S3_LEKRY) invalid(ctx, "unknown scheme");
+    if (scheme < LJ_EXPRB2 || scheme > LJ_EPIRK4S3A_LEKRY) invalid(ctx, "unknown scheme");
     if (!std::isfinite(h)) invalid(ctx, "h must be finite");
     if (!(tol > 0.0) || !std::isfinite(tol)) invalid(ctx, "tol must be finite and > 0");
     UserScope us(ctx, J, true, s);
@@ -2148,7 +2156,8 @@ template <class BeforeStep>
 int integrate_impl(lj_context* ctx, int scheme, const OpDev& op0, const Opts& o, double T, double dt0, double tol,
                    double leja_tol, double* u_out, lj_integrate_stats* stats, lj_step_record* log, int log_cap,
                    int max_attempts, hipStream_t s, BeforeStep&& before_step) {
-  if (scheme != LJ_EPIRK4S3 && scheme != LJ_EXPRB43 && scheme != LJ_EPIRK4S3_LEKRY)
+  if (scheme != LJ_EPIRK4S3 && scheme != LJ_EXPRB43 && scheme != LJ_EPIRK4S3_LEKRY && scheme != LJ_EPIRK4S3A &&
+      scheme != LJ_EPIRK4S3A_LEKRY)
     invalid(ctx, "lj_integrate needs an embedded scheme");
   if (op0.state == nullptr) invalid(ctx, "lj_integrate needs u(0) in J->state");
   if (!(T >= 0.0) || !std::isfinite(T)) invalid(ctx, "T must be finite and >= 0");

@@ -77,7 +77,7 @@ def test_enum_constants_match_c(tmp_path):
     from paper_2211_08948_amd import _lib
     names = ["LJ_OP_DIAG", "LJ_OP_ADVDIFF2D", "LJ_OP_ALLENCAHN2D", "LJ_OP_BRUSSELATOR2D", "LJ_OP_BURGERS2D",
              "LJ_OP_GRAYSCOTT2D", "LJ_OP_ADR2D", "LJ_EXPRB2", "LJ_EXPRB43_U3", "LJ_EXPRB43", "LJ_EPIRK4S3",
-             "LJ_EPIRK4S3_LEKRY",
+             "LJ_EPIRK4S3_LEKRY", "LJ_EPIRK4S3A", "LJ_EPIRK4S3A_LEKRY",
              "LJ_OK", "LJ_ENOTCONV", "LJ_EINVAL", "LJ_EHIP", "LJ_ENOMEM", "LJ_MAX_K", "LJ_MAX_L"]
     prog = tmp_path / "en.c"
     body = "".join(f'printf("{n} %d\\n", (int){n});' for n in names)

@@ -58,6 +58,7 @@ def test_allen_cahn_lekry_matches_oracle(gpu):
     # counted in the cost controller's cost
     prob = allen_cahn_noise(32, eps=1e-2, seed=2, amp=0.5)
     _compare(gpu, prob, prob.state, 2.0 * prob.h_cfl, prob.h_cfl, 1e-6, "EPIRK4S3_LEKRY", 1e-12)
+    _compare(gpu, prob, prob.state, 2.0 * prob.h_cfl, prob.h_cfl, 1e-6, "EPIRK4S3A", 1e-12)
 
 
 def test_brusselator_exprb43_matches_oracle(gpu):

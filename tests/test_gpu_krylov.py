@@ -181,24 +181,25 @@ def test_user_combination_parity(env):
     assert rel(w.cpu().numpy(), w_orc) <= 1e-11
 
 
-def test_lekry_step_parity(env):
+@pytest.mark.parametrize("base", ["EPIRK4S3", "EPIRK4S3A"])
+def test_lekry_step_parity(env, base):
     lj, torch, ctx = env
     prob = allen_cahn_noise(96, eps=2e-2, seed=2)
     op = Operator(prob)
     h = 10 * prob.h_cfl
     lam = power_iteration(op.jv, prob.n, 20)
-    u_orc, e_orc, log = oracle_step(op, "EPIRK4S3_LEKRY", h, TOL, Options(bound=lam))
+    u_orc, e_orc, log = oracle_step(op, base + "_LEKRY", h, TOL, Options(bound=lam))
     J = lj.operator_from(prob, "cuda:0")
     u_out = torch.empty(prob.n, dtype=torch.float64, device="cuda:0")
     err = torch.empty_like(u_out)
-    rc, sts = lj.lj_step(ctx, "EPIRK4S3_LEKRY", J, h, TOL, u_out, err, lj.lj_default_options(bound=lam))
+    rc, sts = lj.lj_step(ctx, base + "_LEKRY", J, h, TOL, u_out, err, lj.lj_default_options(bound=lam))
     say("lekry", [s["m_star"][:2] for s in sts], [b.m_star for b in log])
     assert rc == 0 and len(sts) == 3
     assert sts[0]["m_star"][:2] == log[0].m_star and sts[2]["m_star"][:1] == log[2].m_star
     assert sts[1]["substeps"][0] == log[1].substeps[0] and sts[1]["iters_total"] == log[1].iters_total
     assert rel(u_out.cpu().numpy(), u_orc) <= TOL
     assert np.linalg.norm(err.cpu().numpy() - e_orc) <= 1e-8 * np.linalg.norm(e_orc) + 1e-12 * np.linalg.norm(u_orc)
-    # the same scheme as EPIRK4s3, its third stage evaluated by Krylov
+    # the same scheme as the all-Leja form, its third stage evaluated by Krylov
     u4 = torch.empty_like(u_out)
-    rc, _ = lj.lj_step(ctx, "EPIRK4S3", J, h, TOL, u4, None, lj.lj_default_options(bound=lam))
+    rc, _ = lj.lj_step(ctx, base, J, h, TOL, u4, None, lj.lj_default_options(bound=lam))
     assert rel(u_out.cpu().numpy(), u4.cpu().numpy()) <= 1e-9

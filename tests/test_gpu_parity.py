@@ -336,7 +336,7 @@ def test_invalid_arguments_raise(gpu):
 
 
 # --------------------------------------------------------------- stage driver
-@pytest.mark.parametrize("scheme", ["EXPRB2", "EXPRB43_U3", "EXPRB43", "EPIRK4S3"])
+@pytest.mark.parametrize("scheme", ["EXPRB2", "EXPRB43_U3", "EXPRB43", "EPIRK4S3", "EPIRK4S3A"])
 def test_step_parity_allen_cahn(gpu, scheme):
     prob = allen_cahn_noise(96, eps=2e-2, seed=2)
     op = Operator(prob)

@@ -88,13 +88,14 @@ def test_breakdown_gives_the_exact_result():
     assert np.count_nonzero(w) == 1
 
 
-def test_lekry_step_equals_epirk4s3():
+@pytest.mark.parametrize("base", ["EPIRK4S3", "EPIRK4S3A"])
+def test_lekry_step_equals_epirk4s3(base):
     # the same scheme: u_4 and the embedded error agree within the tolerances
     p = allen_cahn_noise(48, eps=2e-2, seed=2)
     op = Operator(p)
     h = 10 * p.h_cfl
     lam = power_iteration(op.jv, p.n, 20)
-    u_e, e_e, _ = step(op, "EPIRK4S3", h, 1e-12, Options(bound=lam))
-    u_k, e_k, log = step(op, "EPIRK4S3_LEKRY", h, 1e-12, Options(bound=lam))
+    u_e, e_e, _ = step(op, base, h, 1e-12, Options(bound=lam))
+    u_k, e_k, log = step(op, base + "_LEKRY", h, 1e-12, Options(bound=lam))
     assert len(log) == 3 and all(b.converged for b in log)
     assert rel(u_k, u_e) <= 1e-10 and rel(e_k, e_e) <= 1e-6

@@ -278,7 +278,7 @@ def orig_points(n):
 
 
 # --------------------------------------------------------------- stage driver
-@pytest.mark.parametrize("scheme", ["EXPRB2", "EXPRB43", "EXPRB43_U3", "EPIRK4S3"])
+@pytest.mark.parametrize("scheme", ["EXPRB2", "EXPRB43", "EXPRB43_U3", "EPIRK4S3", "EPIRK4S3A"])
 def test_linear_problem_every_scheme_is_exact_exponential(cfg1, scheme):
     # f(u) = J u  =>  R = 0 and u + h phi_1(hJ) J u = e^{hJ} u
     p, v, op, sig = cfg1
@@ -294,11 +294,12 @@ def test_linear_problem_every_scheme_is_exact_exponential(cfg1, scheme):
 def test_printed_coefficients_satisfy_stiff_order_conditions():
     # With R(U_i) = O(c_i^2) the weights b_i(z) must give sum b_i c_i^2 = 2 phi_3
     # (order 3) and sum b_i c_i^3 = 6 phi_4 (order 4).  Weights as (phi_3, phi_4)
-    # coefficient pairs, from the equations of Sec. 5.1 and 5.4.
+    # coefficient pairs, from the equations of Sec. 5.1, 5.2 and 5.4.
     F = Fraction
     epirk = {F(1, 8): (F(1892) - 2 * F(1458), F(-42336) + 2 * F(34992)), F(1, 9): (F(1458), F(-34992))}
+    epirk_a = {F(1, 2): (F(32), F(-144)), F(2, 3): (F(-27, 2), F(81))}
     exprb = {F(1, 2): (F(16), F(-48)), F(1): (F(-2), F(12))}
-    for tab in (epirk, exprb):
+    for tab in (epirk, epirk_a, exprb):
         c2 = [sum(b[i] * c ** 2 for c, b in tab.items()) for i in (0, 1)]
         c3 = [sum(b[i] * c ** 3 for c, b in tab.items()) for i in (0, 1)]
         assert c2 == [2, 0] and c3 == [0, 6]
@@ -313,7 +314,7 @@ def test_observed_order_allen_cahn():
     u0 = (0.5 + 0.3 * np.cos(np.pi * X) * np.sin(np.pi * Y)).ravel()
     base = Problem("allencahn", n, n, 1, 2 / n, 2 / n, (0.02,), u0, 1.0)
     mk = lambda u: Operator(base, state=u)  # noqa: E731
-    expect = {"EXPRB2": 3, "EXPRB43_U3": 4, "EXPRB43": 5, "EPIRK4S3": 5}
+    expect = {"EXPRB2": 3, "EXPRB43_U3": 4, "EXPRB43": 5, "EPIRK4S3": 5, "EPIRK4S3A": 5}
     for scheme, order in expect.items():
         errs = []
         hs = [0.4, 0.2, 0.1]
