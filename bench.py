@@ -411,7 +411,7 @@ def bench_lekry(args):
     o = lj.lj_default_options(bound=lam)
     u_out = torch.empty_like(J.state)
     err = torch.empty_like(u_out)
-    for scheme in ("EPIRK4S3", "EPIRK4S3_LEKRY"):
+    for scheme in ("EPIRK4S3", "EPIRK4S3_LEKRY", "EPIRK4S3A", "EPIRK4S3A_LEKRY"):
         fn = lambda: lj.lj_step(ctx, scheme, J, h, TOL, u_out, err, o)
         for _ in range(2):
             fn()
