@@ -263,7 +263,8 @@ typedef struct {
 } lj_step_record;
 
 /* u(T) of u_t = f(u), u(0) = J->state, with the embedded schemes (LJ_EPIRK4S3,
- * LJ_EPIRK4S3A, their LeKry forms, or LJ_EXPRB43) and the step size control of Sec. 2.3: a step is accepted when
+ * LJ_EPIRK4S3A, their LeKry forms, or LJ_EXPRB43) and the step size control
+ * of Sec. 2.3: a step is accepted when
  * e = ||u_4 - u_3||_2 / ||u_4||_2 <= tol; the next size is the smaller of the
  * traditional controller's dt (tol/e)^{1/(p+1)} (p = 3, the embedded order)
  * and the cost controller's, whose cost is the step's Jacobian-vector

@@ -222,7 +222,7 @@ class TorchSemilinear:
         out[N] = 0.0
 
 
-@pytest.mark.parametrize("scheme", ["EXPRB43", "EPIRK4S3", "EPIRK4S3_LEKRY"])
+@pytest.mark.parametrize("scheme", ["EXPRB43", "EPIRK4S3", "EPIRK4S3_LEKRY", "EPIRK4S3A"])
 def test_semilinear_end_to_end(env, scheme):
     """Eight steps of h = 1/8 to t = 1 from the exact initial state; each step
     linearised at the GPU's own state with the oracle's bound at the oracle's

@@ -59,7 +59,7 @@ def _oracle_step(op, scheme, h, tol, bound):
     return step(op, scheme, h, tol, Options(bound=bound))
 
 
-@pytest.mark.parametrize("scheme", ["EXPRB43", "EPIRK4S3"])
+@pytest.mark.parametrize("scheme", ["EXPRB43", "EPIRK4S3", "EPIRK4S3A"])
 def test_schemes_converge_to_the_exact_solution(scheme):
     # end-to-end: the error at t = 1 is the integrator's alone and falls with
     # order ~4 (both schemes are fourth order) as the step is halved
