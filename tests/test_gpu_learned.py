@@ -198,3 +198,49 @@ def test_trained_proposal_saves_work(env):
             prop += r["proposal"]["products"]
     say("products plain vs proposal", plain, prop)
     assert prop < 0.85 * plain
+
+
+def test_proposal_action_matches_oracle(env):
+    """The learned form against the oracle: once the network has proposed
+    (bound, s), the action is the plain method's at that bound and substep
+    count, so the oracle run with the same (bound, s) must give the same
+    point counts and agree to 1e-10; where the proposal's attempt failed and
+    the plain path took over, the oracle's plain run on the fallback's bound
+    must match instead.  Uses the committed trained model."""
+    import os
+
+    from oracle.leja import Options, phi_action
+    from oracle.operators import Operator
+    from paper_2211_08948_amd.proposal import MODEL_FILE
+    from gpu_util import rel
+    lj, torch, ctx = env
+    lj.lj_mlp_load(ctx, MODEL_FILE)
+    assert os.path.exists(MODEL_FILE)
+    p1, v1 = advdiff_bump()
+    cases = [(p1, v1), (allen_cahn_noise(64, eps=1e-2, seed=3), None), (burgers_sines(64, nu=3e-2, seed=5), None),
+             (allen_cahn_noise(37, eps=1e-1, seed=7), None)]
+    used = 0
+    for prob, v0 in cases:
+        op = Operator(prob)
+        J = lj.operator_from(prob, "cuda:0")
+        for hm in (1.0, 10.0, 100.0):
+            h = hm * prob.h_cfl
+            v = v0 if v0 is not None else h * op.rhs(prob.state)
+            vd = torch.as_tensor(v, dtype=torch.float64, device="cuda:0").contiguous()
+            for l in (1, 3):
+                w = torch.empty_like(vd)
+                rc, st = lj.lj_phi_action(ctx, J, vd, w, l, h, TOL, lj.lj_default_options(use_proposal=1))
+                torch.cuda.synchronize()
+                pb, ps = st["proposal_bound"], st["proposal_substeps"]
+                if st["fallbacks"] == 0:
+                    o = Options(bound=pb, substeps=ps if ps > 1 else None, max_substeps=ps)
+                    used += 1
+                else:
+                    o = Options(bound=st["bound"])
+                w_orc, st_orc = phi_action(op, v, l, h, TOL, o)
+                say("proposal vs oracle", prob.kind, prob.nx, hm, l, pb, ps, st["fallbacks"], st["m_star"],
+                    st_orc.m_star)
+                assert rc == 0 and st["converged"] and st_orc.converged
+                assert st["m_star"] == st_orc.m_star and st["substeps"] == st_orc.substeps
+                assert rel(w.cpu().numpy(), w_orc) <= TOL
+    assert used >= 6  # the proposal itself, not only its fallback, is checked

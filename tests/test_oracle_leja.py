@@ -214,6 +214,110 @@ def test_zero_vector_and_nonfinite(cfg1):
     assert not st.converged
 
 
+# ------------------------------------------------------- hump rejection (C.7)
+def _term_ratios(lam, v, l, T, c, gamma, xi, M):
+    """e_m / (||v|| max_j |f_j|), m = 1..M, for a diagonal J = diag(lam), with
+    the Newton basis in closed form, y_m = prod_{j<m} ((lam - c)/gamma - xi_j) v
+    elementwise (nothing of the oracle's recurrence).  Two sets of
+    coefficients: the exact divided differences of phi_l at the scaled nodes
+    (60 digits, phi_l from its Sec. 1 definition), and the FP64 table of
+    oracle.divdiff on oracle.phi's node values (each pinned on its own
+    against 50-digit values); at high orders the FP64 table is rounding
+    noise amplified, so only the same FP64 node values reproduce it."""
+    import mpmath as mp
+    from oracle.divdiff import divided_differences
+    mp.mp.dps = 60
+
+    def phi_mp(z):
+        if z == 0:
+            return 1 / mp.factorial(l)
+        s = mp.e ** z
+        for k in range(l):
+            s -= z ** k / mp.factorial(k)
+        return s / z ** l
+
+    f = [phi_mp(mp.mpf(T) * (mp.mpf(c) + mp.mpf(gamma) * mp.mpf(x))) for x in xi[:M + 1]]
+    d = list(f)
+    for k in range(1, M + 1):
+        for j in range(M, k - 1, -1):
+            d[j] = (d[j] - d[j - 1]) / (mp.mpf(xi[j]) - mp.mpf(xi[j - k]))
+    f64 = [phi(l, T * (c + gamma * x)) for x in xi[:M + 1]]
+    d64 = divided_differences(f64, xi[:M + 1])
+    scale = np.linalg.norm(v) * max(abs(x) for x in f64)
+    q = (np.asarray(lam) - c) / gamma
+    y = np.array(v, dtype=np.float64)
+    exact, fp64 = [], []
+    for m in range(1, M + 1):
+        y = (q - xi[m - 1]) * y
+        ny = np.linalg.norm(y)
+        exact.append(abs(float(d[m])) * ny / scale)
+        fp64.append(abs(d64[m]) * ny / scale)
+    return np.array(exact), np.array(fp64)
+
+
+@pytest.mark.parametrize("l,hump", [(0, 1e4), (1, 1e4), (3, 1e2)])
+def test_hump_rejection_index(l, hump, xi101):
+    """Sec. 2.2, last paragraph: with many Leja points the divided differences
+    are round-off prone, and an expansion that does not settle is rejected.
+    With the bound at 0.6 of the true spectral radius the diagonal operator's
+    eigenvalues near -500 map to -4.4 on the Leja scale and the Newton basis
+    grows geometrically.  In exact arithmetic the coefficients still fall
+    faster (every term ratio stays below 1), but the FP64 rounding of the
+    table is amplified by the basis and the terms pass hump_max ||v|| max|f|
+    (C.7) long before max_points.  The oracle must reject at exactly the
+    first m at which the term ratio crosses hump_max (the crossing is by
+    more than 1 % either side, far beyond the rounding of the basis, so no
+    rounding order decides it), and
+    with no hump limit the same run must go on to max_points."""
+    p = diag_problem(400, -500.0, seed=3)
+    op = Operator(p)
+    v = np.random.default_rng(5).uniform(-1, 1, 400)
+    lam, h = 300.0, 0.02
+    c, gamma = leja.interval(lam, 1.25)
+    exact, fp64 = _term_ratios(p.state, v, l, h, c, gamma, xi101, 100)
+    assert np.all(exact < 1.0)
+    assert np.any(fp64 > hump)
+    expect = int(np.argmax(fp64 > hump)) + 1
+    assert fp64[expect - 1] > 1.01 * hump and np.all(fp64[:expect - 1] < hump / 1.01)
+    r = leja.newton_recurrence(op.jv, v, [l], [1.0], h, c, gamma, 1e-10, Options(hump_max=hump))
+    assert r.reason == ["hump"] and not r.converged[0] and r.iters == expect
+    r = leja.newton_recurrence(op.jv, v, [l], [1.0], h, c, gamma, 1e-10, Options(hump_max=1e300))
+    assert r.reason == ["maxpts"] and r.iters == 100
+
+
+@pytest.mark.parametrize("l", [0, 1, 3])
+def test_hump_rejection_then_substeps_reach_closed_form(l):
+    """After a hump rejection the action is redone with s = 2, 4, ...; the
+    substeps shrink tau gamma until the terms decay faster than the basis
+    grows, and the result is phi_l(hJ)v within 10 s tol."""
+    p = diag_problem(400, -500.0, seed=3)
+    op = Operator(p)
+    v = np.random.default_rng(5).uniform(-1, 1, 400)
+    h = 0.02
+    w, st = phi_action(op, v, l, h, 1e-10, Options(bound=300.0))
+    assert st.converged and st.rejections >= 1 and st.substeps[0] >= 2
+    ref = diag_closed_form(p.state, v, l, h, phi)
+    assert rel(w, ref) <= 10 * st.substeps[0] * 1e-10
+
+
+@pytest.mark.parametrize("l", [0, 1, 3])
+def test_small_hump_limit_forces_substeps(l):
+    """With the right bound the first term of an expansion at a large
+    tau gamma is about 0.45 ||v|| max|f|, so hump_max = 0.2 rejects at m = 1
+    until the substeps make tau gamma small: s = 8 here (the first term then
+    falls to 0.45 (1 - e^{-4 tau gamma}) ||v|| max|f| ~ 0.18), and the result
+    is phi_l(hJ)v within 10 s tol."""
+    p = diag_problem(400, -500.0, seed=3)
+    op = Operator(p)
+    v = np.random.default_rng(5).uniform(-1, 1, 400)
+    h = 0.0064
+    w, st = phi_action(op, v, l, h, 1e-10, Options(bound=500.0, hump_max=0.2))
+    assert st.converged and st.substeps == [8] and st.rejections == 3
+    assert rel(w, diag_closed_form(p.state, v, l, h, phi)) <= 80 * 1e-10
+    w1, st1 = phi_action(op, v, l, h, 1e-10, Options(bound=500.0))
+    assert st1.substeps == [1] and st1.rejections == 0
+
+
 # ------------------------------------------------------------ planted mistakes
 def test_planted_mistakes_are_caught(cfg1, monkeypatch):
     """Each plausible slip in the oracle makes a pin fail: the Fourier closed
