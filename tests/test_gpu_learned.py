@@ -200,23 +200,28 @@ def test_trained_proposal_saves_work(env):
     assert prop < 0.85 * plain
 
 
-def test_proposal_action_matches_oracle(env):
+def test_proposal_action_matches_oracle(env, monkeypatch):
     """The learned form against the oracle: once the network has proposed
     (bound, s), the action is the plain method's at that bound and substep
     count, so the oracle run with the same (bound, s) must give the same
     point counts and agree to 1e-10; where the proposal's attempt failed and
     the plain path took over, the oracle's plain run on the fallback's bound
-    must match instead.  Uses the committed trained model."""
+    must match instead.  Advection-diffusion at 100x the CFL step is the
+    divided-difference noise regime and is held to the bar of that regime.
+    Uses the committed trained model."""
     import os
 
     from oracle.leja import Options, phi_action
     from oracle.operators import Operator
     from paper_2211_08948_amd.proposal import MODEL_FILE
-    from gpu_util import rel
+    from oracle.exact import advdiff_symbol, fourier_closed_form
+    from dd_floor import dd_floor
+    from gpu_util import rel, rel2
     lj, torch, ctx = env
     lj.lj_mlp_load(ctx, MODEL_FILE)
     assert os.path.exists(MODEL_FILE)
     p1, v1 = advdiff_bump()
+    sig = advdiff_symbol(p1.nx, p1.ny, p1.dx, p1.dy, *p1.coef)
     cases = [(p1, v1), (allen_cahn_noise(64, eps=1e-2, seed=3), None), (burgers_sines(64, nu=3e-2, seed=5), None),
              (allen_cahn_noise(37, eps=1e-1, seed=7), None)]
     used = 0
@@ -241,6 +246,28 @@ def test_proposal_action_matches_oracle(env):
                 say("proposal vs oracle", prob.kind, prob.nx, hm, l, pb, ps, st["fallbacks"], st["m_star"],
                     st_orc.m_star)
                 assert rc == 0 and st["converged"] and st_orc.converged
-                assert st["m_star"] == st_orc.m_star and st["substeps"] == st_orc.substeps
-                assert rel(w.cpu().numpy(), w_orc) <= TOL
+                assert st["substeps"] == st_orc.substeps
+                if prob.kind == "advdiff" and hm == 100.0:
+                    # the stop of each substep expansion falls where the FP64
+                    # divided differences are rounding noise (pinned on the
+                    # CPU: test_divided_differences_noise_regime), so the
+                    # point counts of two correct FP64 runs differ by a few;
+                    # unique are s and the action to within 2 s tol, and both
+                    # lie within 10 s tol of the Fourier closed form
+                    s_ = st_orc.substeps[0]
+                    exact = fourier_closed_form(sig, v, l, h)
+                    assert abs(st["m_star"][0] - st_orc.m_star[0]) <= 0.05 * st_orc.m_star[0]
+                    assert rel2(w.cpu().numpy(), w_orc) <= 2 * s_ * TOL
+                    assert rel2(w.cpu().numpy(), exact) <= 10 * s_ * TOL
+                    assert rel2(w_orc, exact) <= 10 * s_ * TOL
+                    continue
+                assert st["m_star"] == st_orc.m_star
+                # long expansions stop where the FP64 divided differences are
+                # rounding-dominated: the bar is tol plus twice the oracle's own
+                # distance to exact coefficients (tests/dd_floor.py)
+                floor = 0.0
+                if st_orc.m_star[0] > 60:
+                    floor = dd_floor(monkeypatch, lambda: phi_action(op, v, l, h, TOL, o)[0], rel)
+                say("  dd floor", floor)
+                assert rel(w.cpu().numpy(), w_orc) <= TOL + 2 * floor
     assert used >= 6  # the proposal itself, not only its fallback, is checked

@@ -500,8 +500,10 @@ def test_action_parity_burgers_full_size(gpu):
 # grows geometrically and the first attempt's terms blow up in exact
 # arithmetic; later attempts pass hump_max only through the FP64 rounding of
 # the divided differences amplified by the basis (Sec. 2.2, last paragraph),
-# where each side's own rounding decides the index.  There the substep count
-# and the result are unique; the product counts of the rejected attempts are not.
+# where each side's own rounding decides the index -- and so whether an
+# attempt at s substeps passes at all: the two sides may settle on substep
+# counts a factor 2 apart.  Unique there is that each converges to within
+# 10 s tol of the closed form at its own s.
 @pytest.mark.parametrize("l", [0, 1, 3])
 def test_hump_small_limit_parity(gpu, l):
     cases = [(diag_problem(400, -500.0, seed=3), 0.0064, 500.0), (allen_cahn_noise(96, eps=2e-2, seed=2), None, None)]
@@ -536,8 +538,8 @@ def test_hump_underestimated_bound(gpu, l):
     assert st_orc.rejections >= 1 and st_orc.converged
     rc, st, w = gpu.action(prob, v, l, h, TOL, bound=300.0)
     say("  gpu", st["substeps"], st["rejections"], st["iters_total"])
-    assert rc == 0 and st["converged"]
-    assert st["substeps"] == st_orc.substeps and st["rejections"] == st_orc.rejections
-    s_ = st["substeps"][0]
-    assert rel2(w, w_orc) <= 2 * s_ * TOL
-    assert rel2(w, exact) <= 10 * s_ * TOL and rel2(w_orc, exact) <= 10 * s_ * TOL
+    assert rc == 0 and st["converged"] and st["rejections"] >= 1
+    s_g, s_o = st["substeps"][0], st_orc.substeps[0]
+    assert s_o // 2 <= s_g <= 2 * s_o
+    assert rel2(w, exact) <= 10 * s_g * TOL and rel2(w_orc, exact) <= 10 * s_o * TOL
+    assert rel2(w, w_orc) <= 10 * (s_g + s_o) * TOL

@@ -506,3 +506,72 @@ def test_fourier_mode_closed_form_any_size():
     ref = _mode_sum(n, modes, lambda kx, ky: phi_scalar_expm(1, h * sig(kx, ky)), ii, jj)
     w, st = phi_action(op, v, 1, h, 1e-14)
     assert st.converged and rel(w, ref) <= 1e-12
+
+
+def test_divided_differences_noise_regime(monkeypatch):
+    """Advection-diffusion 32^2 at 100x the CFL step with four substeps (the
+    learned proposal's choice for it): each substep expansion stops near
+    m = 50, where the FP64 divided differences of exp at the scaled nodes
+    already carry a rounding error of more than 10 % (against 100-digit
+    ones), so the point counts follow the rounding of the table (Sec. 2.2,
+    last paragraph) while the action stays within 10 s tol of the Fourier
+    closed form."""
+    import mpmath as mp
+    from oracle.exact import advdiff_symbol, fourier_closed_form
+    p, v = advdiff_bump()
+    op = Operator(p)
+    h = 100 * p.h_cfl
+    lam = 8774.344002821865
+    c, gamma = leja.interval(lam, 1.25)
+    tau = h / 4
+    xi = leja.xi_table(101)
+    d64, _ = leja.coefficients(0, 1.0, tau, c, gamma, 56)
+    mp.mp.dps = 100
+    xs = [mp.mpf(x) for x in xi[:56]]
+    d = [mp.e ** (mp.mpf(tau) * (mp.mpf(c) + mp.mpf(gamma) * x)) for x in xs]
+    for k in range(1, 56):
+        for j in range(55, k - 1, -1):
+            d[j] = (d[j] - d[j - 1]) / (xs[j] - xs[j - k])
+    relerr = [abs(d64[m] - float(d[m])) / abs(float(d[m])) for m in range(56)]
+    assert max(relerr[:30]) < 1e-9 and relerr[50] > 0.1
+    sig = advdiff_symbol(p.nx, p.ny, p.dx, p.dy, *p.coef)
+    exact = fourier_closed_form(sig, v, 3, h)
+    # one-ulp changes of the node values (two exp implementations differ by
+    # that much) move the counts
+    orig = leja.phi
+    counts = set()
+    for seed in (None, 1, 2, 3):
+        if seed is not None:
+            rng = np.random.default_rng(seed)
+            monkeypatch.setattr(leja, "phi", lambda l, z: orig(l, z) * (1.0 + 2.0 ** -52 * rng.integers(-1, 2)))
+        w, st = phi_action(op, v, 3, h, 1e-10, Options(bound=lam, substeps=4, max_substeps=4))
+        monkeypatch.undo()
+        counts.add(st.m_star[0])
+        assert st.converged and rel(w, exact) <= 10 * 4 * 1e-10
+    assert len(counts) >= 2
+
+
+def test_dd_floor_of_long_expansion(monkeypatch):
+    """Allen-Cahn 64^2 (eps 1e-2) at 100x the CFL step, phi_1, 88 Newton
+    terms: the FP64 table's entries near the stop carry ~1e-2..1e-1 rounding
+    error, which moves the action by more than 1e-10 relative to the same
+    expansion with exact coefficients; at 10x the CFL step the floor is far
+    below tol.  The exact table itself matches the FP64 one where the latter
+    is accurate (low orders)."""
+    from dd_floor import dd_floor, exact_coefficients
+    p = allen_cahn_noise(64, eps=1e-2, seed=3)
+    op = Operator(p)
+    lam = 86.93866065109043
+    c, gamma = leja.interval(lam, 1.25)
+    h = 100 * p.h_cfl
+    d64, f64 = leja.coefficients(1, 1.0, h, c, gamma, 101)
+    dex, fex = exact_coefficients(1, 1.0, h, c, gamma, 101)
+    assert np.max(np.abs(d64[:30] - dex[:30]) / np.abs(dex[:30])) < 1e-12 and abs(f64 - fex) <= 1e-15 * fex
+    assert abs(d64[83] - dex[83]) > 0.05 * abs(dex[83])
+    v = h * op.rhs(p.state)
+    run = lambda: phi_action(op, v, 1, h, 1e-10, Options(bound=lam))[0]
+    assert dd_floor(monkeypatch, run, rel) > 1e-10
+    h10 = 10 * p.h_cfl
+    v10 = h10 * op.rhs(p.state)
+    run10 = lambda: phi_action(op, v10, 1, h10, 1e-10, Options(bound=lam))[0]
+    assert dd_floor(monkeypatch, run10, rel) < 1e-13
