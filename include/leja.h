@@ -176,6 +176,25 @@ LJ_API int lj_phi_action(lj_context* ctx, const lj_operator* J, const double* v,
                          int l, double h, double tol, const lj_options* opt, lj_stats* stats,
                          void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * action as lj_phi_action, with the same arguments, results and errors, but
+ * the call allocates nothing -- its Newton-basis vectors, partial sums and
+ * substep vectors lie in one file-scope device array of
+ * LJ_NOALLOC_SCRATCH_BYTES per GPU (held from the first lj_create on that GPU
+ * until the process ends; barrier words and status stay in the context,
+ * allocated by lj_create).  Needs (2 + (l + 3 if substeps may be taken, i.e.
+ * max_substeps > 1 or substeps > 1; l = 0: 2)) vectors of n doubles plus
+ * 2 * 48 * CUs doubles of partial sums, each rounded up to 256 bytes; a larger
+ * action returns LJ_EINVAL with the sizes in lj_last_error.  use_proposal = 1
+ * is rejected (LJ_EINVAL).  Every call on one GPU shares that GPU's array and
+ * leaves its last contents there: calls that overlap on one GPU (several
+ * streams, threads or contexts) race and must be serialised by the caller. */
+#define LJ_NOALLOC_SCRATCH_BYTES (32u << 20)
+LJ_API int lj_phi_action_noalloc(lj_context* ctx, const lj_operator* J, const double* v, double* w,
+                                 int l, double h, double tol, const lj_options* opt,
+                                 lj_stats* stats, void* stream);
+
 /* Vertical form (Sec. 4): w[k] = phi_{l[k]}(a[k] h J) v for k < K <= LJ_MAX_K,
  * all on one Newton basis; l, a, w are host arrays of K entries (w[k] device
  * pointers, pairwise distinct).  Accumulators that are rejected on the shared

@@ -19,7 +19,7 @@ from . import _lib
 from ._lib import (  # noqa: F401
     LJ_EHIP, LJ_EINVAL, LJ_ENOMEM, LJ_ENOTCONV, LJ_EPIRK4S3, LJ_EPIRK4S3_LEKRY, LJ_EPIRK4S3A, LJ_EPIRK4S3A_LEKRY, LJ_EXPRB2, LJ_EXPRB43, LJ_EXPRB43_U3,
     LJ_MAX_K, LJ_MAX_L, LJ_OK, LJ_OP_ADR2D, LJ_OP_ADVDIFF2D, LJ_OP_ALLENCAHN2D, LJ_OP_BRUSSELATOR2D, LJ_OP_BURGERS2D,
-    LJ_OP_DIAG, LJ_OP_GRAYSCOTT2D, LejaLibraryError, lj_integrate_stats, lj_operator, lj_options, lj_stats, lj_step_record,
+    LJ_NOALLOC_SCRATCH_BYTES, LJ_OP_DIAG, LJ_OP_GRAYSCOTT2D, LejaLibraryError, lj_integrate_stats, lj_operator, lj_options, lj_stats, lj_step_record,
     lj_timing,
 )
 
@@ -404,6 +404,20 @@ def lj_phi_action(ctx: Context, J: Operator, v, w, l: int, h: float, tol: float,
     rc = ctx._lib.lj_phi_action(ctx.handle, C.byref(op), _tensor_ptr(v, J.n, "v"), _tensor_ptr(w, J.n, "w"),
                                 int(l), float(h), float(tol), C.byref(opt) if opt is not None else None,
                                 C.byref(st), _stream_ptr(stream))
+    ctx._check(rc)
+    return rc, st.as_dict(1)
+
+
+def lj_phi_action_noalloc(ctx: Context, J: Operator, v, w, l: int, h: float, tol: float,
+                          opt: lj_options | None = None, stream=None):
+    """lj_phi_action without device allocation: the workspace lies in the
+    library's per-device scratch array.  Returns (return code, stats dict)."""
+    op = J.c_struct()
+    st = lj_stats()
+    rc = ctx._lib.lj_phi_action_noalloc(ctx.handle, C.byref(op), _tensor_ptr(v, J.n, "v"),
+                                        _tensor_ptr(w, J.n, "w"), int(l), float(h), float(tol),
+                                        C.byref(opt) if opt is not None else None, C.byref(st),
+                                        _stream_ptr(stream))
     ctx._check(rc)
     return rc, st.as_dict(1)
 

@@ -15,6 +15,7 @@ LJ_OK, LJ_ENOTCONV, LJ_EINVAL, LJ_EHIP, LJ_ENOMEM = 0, 1, -1, -2, -3
 LJ_MAX_K = 4
 LJ_MAX_L = 4
 LJ_MAX_POINTS = 100
+LJ_NOALLOC_SCRATCH_BYTES = 32 << 20
 LJ_NFEATURES = 16
 LJ_MLP_NPARAM = 5378
 LJ_MLP_MODEL_FLOATS = 5414
@@ -142,6 +143,8 @@ _PROTOS = {
                                C.POINTER(lj_options), C.POINTER(lj_stats), C.c_int, C.POINTER(C.c_int), _P]),
     "lj_phi_action": (C.c_int, [_P, C.POINTER(lj_operator), _P, _P, C.c_int, C.c_double, C.c_double,
                                 C.POINTER(lj_options), C.POINTER(lj_stats), _P]),
+    "lj_phi_action_noalloc": (C.c_int, [_P, C.POINTER(lj_operator), _P, _P, C.c_int, C.c_double, C.c_double,
+                                        C.POINTER(lj_options), C.POINTER(lj_stats), _P]),
     "lj_phi_vertical": (C.c_int, [_P, C.POINTER(lj_operator), _P, C.c_int, C.POINTER(C.c_int),
                                   C.POINTER(C.c_double), C.c_double, C.c_double, C.POINTER(_P),
                                   C.POINTER(lj_options), C.POINTER(lj_stats), _P]),

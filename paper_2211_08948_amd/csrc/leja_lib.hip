@@ -11,6 +11,7 @@
 #include <algorithm>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <numeric>
 #include <string>
 #include <unordered_map>
@@ -51,6 +52,17 @@ constexpr size_t kStaticLdsReserve = 40 * 1024;
 constexpr int kQ_batch = 1 + kMaxK;  // team partial sums per reduction
 constexpr int kAsyncSlots = 8;       // most action launches of one step
 constexpr int kTimingPairs = 1024;   // event pairs of the timing pool
+
+// Device memory of the allocation-free entry point (lj_phi_action_noalloc):
+// one file-scope array that every GPU the library runs on holds from the
+// first context creation on it until the process ends.  In host code the name
+// `scratch` is only a stand-in; its device address on each device comes from
+// hipGetSymbolAddress at context creation (g_scratch_addr).
+constexpr size_t kScratchBytes = (size_t)LJ_NOALLOC_SCRATCH_BYTES;
+constexpr int kScratchDevices = 64;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+static double* g_scratch_addr[kScratchDevices] = {};
+static std::mutex g_scratch_mu;
 
 // An operator given as host callbacks (lj_user_operator) during one call.
 struct UserOp {
@@ -121,6 +133,14 @@ struct lj_context {
   double* d_kpart = nullptr;   // kKryBlocksMax * (kKryMaxDim + 1)
   double* d_kH = nullptr;      // (kKryMaxDim + 1) * kKryMaxDim, then 2 scalars
   double* h_kH = nullptr;      // pinned copy of d_kH
+  // allocation-free calls: this device's scratch array (device address), and
+  // while such a call runs, where its workspace vectors and partial sums lie
+  // in it (in doubles from its start; index W_NSLOTS: the partial sums)
+  double* scratch = nullptr;
+  bool in_noalloc = false;
+  size_t scratch_next = 0;
+  size_t scratch_off[W_NSLOTS + 1] = {};
+  size_t scratch_len[W_NSLOTS + 1] = {};
 };
 
 static std::string g_create_error;
@@ -145,7 +165,25 @@ struct Fail {
   throw Fail{LJ_EINVAL};
 }
 
+// A region of the scratch array for workspace slot s (W_NSLOTS: the partial
+// sums) during an allocation-free call: handed out once per call in order of
+// first use, 256-byte aligned.  The entry point has checked the total first.
+double* scratch_region(lj_context* ctx, int s, size_t n) {
+  if (ctx->scratch_len[s] < n) {
+    const size_t rn = (n + 31) & ~(size_t)31;
+    if ((ctx->scratch_next + rn) * sizeof(double) > kScratchBytes) {
+      ctx->err = "allocation-free call: scratch array exhausted";
+      throw Fail{LJ_EINVAL};
+    }
+    ctx->scratch_off[s] = ctx->scratch_next;
+    ctx->scratch_len[s] = rn;
+    ctx->scratch_next += rn;
+  }
+  return ctx->scratch + ctx->scratch_off[s];
+}
+
 double* slot(lj_context* ctx, int s, size_t n) {
+  if (ctx->in_noalloc) return scratch_region(ctx, s, n);
   if (ctx->vec_cap[s] < n) {
     if (ctx->vec[s]) (void)hipFree(ctx->vec[s]);
     ctx->vec[s] = nullptr;
@@ -431,8 +469,12 @@ void launch_action(lj_context* ctx, const OpDev& op, const double* v, int K, con
     fn = action_stream_ptr(op.kind);
     G = grid_for(ctx, op.npts);
   }
-  ensure_small(ctx, G);
-  P.partials = ctx->d_partials;
+  if (ctx->in_noalloc) {
+    P.partials = scratch_region(ctx, W_NSLOTS, (size_t)2 * kPartStride * G);
+  } else {
+    ensure_small(ctx, G);
+    P.partials = ctx->d_partials;
+  }
   void* args[] = {&P};
   if (ev) HIPCHK(ctx, hipEventRecord(ev[0], s));
   if (cooperative || !coresident(ctx, fn, G, dyn)) {
@@ -1443,6 +1485,19 @@ LJ_API int lj_create(lj_context** out, int hip_device) {
     HIPCHK(ctx, hipMalloc(&ctx->d_bound, sizeof(double)));
     HIPCHK(ctx, hipMalloc(&ctx->d_sumsq, (2 * kSumsqBlocks + 2) * sizeof(double)));
     HIPCHK(ctx, hipHostMalloc(&ctx->h_sumsq, 2 * sizeof(double), hipHostMallocDefault));
+    if (hip_device < kScratchDevices) {  // once per device, with the device current
+      std::lock_guard<std::mutex> lock(g_scratch_mu);
+      if (!g_scratch_addr[hip_device]) {
+        void* addr = nullptr;
+        HIPCHK(ctx, hipGetSymbolAddress(&addr, HIP_SYMBOL(scratch)));
+        if (!addr) {
+          ctx->err = "hipGetSymbolAddress(scratch) returned no address";
+          throw Fail{LJ_EHIP};
+        }
+        g_scratch_addr[hip_device] = static_cast<double*>(addr);
+      }
+      ctx->scratch = g_scratch_addr[hip_device];
+    }
     if (const char* g = std::getenv("LJ_GRID")) ctx->grid_override = std::atoi(g);
     if (const char* g = std::getenv("LJ_NO_TILE")) ctx->force_stream = std::atoi(g);
     if (const char* g = std::getenv("LJ_COOP")) ctx->force_coop = std::atoi(g);
@@ -1700,6 +1755,48 @@ LJ_API int lj_phi_action(lj_context* ctx, const lj_operator* J, const double* v,
   const double a = 1.0;
   double* ws[1] = {w};
   return lj_phi_vertical(ctx, J, v, 1, &l, &a, h, tol, ws, opt, stats, stream);
+}
+
+// Doubles of scratch an allocation-free phi_l action on n values needs at
+// most: the two Newton-basis vectors, the partial sums of the largest grid,
+// and, when substeps may be taken, phi_1..phi_l at the substep plus three
+// propagation vectors (l = 0: two).
+size_t noalloc_need(const lj_context* ctx, size_t n, int l, const Opts& o) {
+  auto r = [](size_t x) { return (x + 31) & ~(size_t)31; };
+  size_t d = 2 * r(n) + r((size_t)2 * kPartStride * ctx->num_cus);
+  if (o.max_substeps > 1 || o.substeps > 1) d += (size_t)(l > 0 ? l + 3 : 2) * r(n);
+  return d;
+}
+
+LJ_API int lj_phi_action_noalloc(lj_context* ctx, const lj_operator* J, const double* v, double* w, int l,
+                                 double h, double tol, const lj_options* opt, lj_stats* stats, void* stream) {
+  return guarded(ctx, [&]() {
+    if (!ctx->scratch) invalid(ctx, "lj_phi_action_noalloc: no scratch array on this device");
+    const OpDev op = make_op(ctx, J);
+    const Opts o = resolve(ctx, opt);
+    if (o.use_proposal) invalid(ctx, "lj_phi_action_noalloc: use_proposal is not supported");
+    const double a = 1.0;
+    double* ws[1] = {w};
+    check_action_args(ctx, op, v, 1, &l, &a, h, tol, ws);
+    if (o.pi_start) check_vec(ctx, op, o.pi_start, "pi_start");
+    const size_t need = noalloc_need(ctx, nvals(op), l, o) * sizeof(double);
+    if (need > kScratchBytes)
+      invalid(ctx, "lj_phi_action_noalloc: this action needs " + std::to_string(need) +
+                       " bytes of scratch, more than the " + std::to_string(kScratchBytes) +
+                       " the allocation-free path holds (use lj_phi_action)");
+    struct Scope {
+      lj_context* c;
+      explicit Scope(lj_context* c_) : c(c_) {
+        c->in_noalloc = true;
+        c->scratch_next = 0;
+        for (int i = 0; i <= W_NSLOTS; ++i) c->scratch_len[i] = 0;
+      }
+      ~Scope() { c->in_noalloc = false; }
+    } scope(ctx);
+    lj_stats local;
+    lj_stats* st = stats ? stats : &local;
+    return vertical_impl(ctx, op, v, 1, &l, &a, h, tol, ws, o, st, reinterpret_cast<hipStream_t>(stream));
+  });
 }
 
 // One step of `scheme` from u = op.state (arguments validated by the caller):
