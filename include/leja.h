@@ -384,12 +384,20 @@ LJ_API int lj_user_integrate(lj_context* ctx, int scheme, const lj_user_operator
  * applies to instances without their own bound).  The buffers must stay valid
  * while the batch exists.
  *
+ * An accumulator that the instance's shared Newton basis rejects (Sec. 2.2,
+ * last paragraph) is redone inside the same launch with s = 2, 4, ...
+ * (up to opt->max_substeps) substeps: phi_1..phi_l at h/s in one recurrence,
+ * then s - 1 exponentials and combinations (lj_phi_action's substepping),
+ * on the instance's bound; with max_substeps >= 2 the batch holds
+ * max(max_k l[k], 1) + 1 extra vectors per instance for it.
+ *
  * lj_batch_run replays the graph on `stream` without synchronising.
- * lj_batch_stats synchronises `stream`, reads the per-instance outcome into
- * per_instance (n entries, may be NULL) and redoes every accumulator the batch
- * rejected with the plain path and substeps (on the bound the batch found),
- * counting the batch attempt as a rejection; returns LJ_ENOTCONV if some
- * accumulator still failed.  lj_batch_destroy synchronises the device first. */
+ * lj_batch_stats synchronises `stream` and reads the per-instance outcome
+ * into per_instance (n entries, may be NULL): the shared basis's rejection
+ * and every failed substep attempt count as rejections, m_star and substeps
+ * describe the accepted attempt, iters_total every Newton step; returns
+ * LJ_ENOTCONV if some accumulator failed at every substep count.
+ * lj_batch_destroy synchronises the device first. */
 typedef struct lj_batch lj_batch;
 
 typedef struct {

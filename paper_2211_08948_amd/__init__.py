@@ -534,8 +534,8 @@ class Batch:
         self.ctx._check(self.ctx._lib.lj_batch_run(self.handle, _stream_ptr(stream)), False)
 
     def stats(self, stream=None):
-        """Synchronises, returns (rc, per-instance stats dicts); rejected
-        accumulators are redone by the plain path first."""
+        """Synchronises, returns (rc, per-instance stats dicts); accumulators
+        the shared basis rejected were substepped inside the launch."""
         st = (lj_stats * self.n)()
         rc = self.ctx._lib.lj_batch_stats(self.handle, st, _stream_ptr(stream))
         self.ctx._check(rc)

@@ -127,15 +127,20 @@ struct BatchItem {
   double* y1;
   double s[kMaxK];    // a_k * h of this instance
   double lam_in;      // > 0: spectral bound given; else power iteration
+  double* sub;        // substep vectors: phi_1..phi_l at the substep, then e^{tau J} w
+  size_t nsub_stride; // values between consecutive substep vectors (the instance's length)
 };
 
 // What the batch kernel reports per instance.
 struct BatchStatus {
   int state[kMaxK];
-  int m_star[kMaxK];
+  int m_star[kMaxK];           // Newton steps of the accepted attempt (substeps: all its recurrences)
   double err[kMaxK];
-  int iters;
-  int accum_iters;
+  int substeps[kMaxK];         // substeps of the accepted attempt (1: the shared basis)
+  int iters;                   // Newton steps of every recurrence of the instance
+  int accum_iters;             // accumulator updates of every recurrence
+  int vec_passes;              // vectors read or written by the substep combinations
+  int rejections;              // the shared basis's rejection (0 or 1) plus every failed substep attempt
   int power_iters;
   int block;                   // block that ran the instance
   double vnorm, lam, c, gamma;
@@ -153,6 +158,7 @@ struct BatchParams {
   uint64_t seed;
   double safety;
   int max_points;
+  int max_substeps;
   int relative;
   double tol;
   double hump;

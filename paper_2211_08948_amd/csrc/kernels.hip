@@ -1013,8 +1013,13 @@ __global__ __launch_bounds__(BS) void lj_batch_kernel(BatchParams B) {
   __shared__ double tot[kQ];
   __shared__ Decision sD;
   __shared__ int s_commit[kMaxK];
-  __shared__ double s_s[kMaxK];
+  __shared__ double s_s[kMaxK];   // (l, s) of the accumulators of the running recurrence
+  __shared__ int s_l[kMaxK];
+  __shared__ double s_s0[kMaxK];  // a_k h of the instance
   __shared__ int s_flag;
+  __shared__ int s_iters, s_accum, s_vecs, s_rej;  // the instance's running counts
+  __shared__ int f_state[kMaxK], f_mst[kMaxK], f_sub[kMaxK];
+  __shared__ double f_err[kMaxK];
   for (int i = threadIdx.x; i < kTable; i += BS) xi[i] = B.xi[i];
   const int K = B.K;
   const int T = B.team;
@@ -1071,7 +1076,10 @@ __global__ __launch_bounds__(BS) void lj_batch_kernel(BatchParams B) {
     double* pp[kMaxK];
 #pragma unroll
     for (int k = 0; k < kMaxK; ++k) pp[k] = (k < K) ? it->p[k] : nullptr;
-    if (threadIdx.x < kMaxK) s_s[threadIdx.x] = ((int)threadIdx.x < K) ? it->s[threadIdx.x] : 0.0;
+    if (threadIdx.x < kMaxK) {
+      s_s[threadIdx.x] = ((int)threadIdx.x < K) ? it->s[threadIdx.x] : 0.0;
+      s_s0[threadIdx.x] = s_s[threadIdx.x];
+    }
 
     // (1) spectral bound
     double lam = it->lam_in;
@@ -1106,68 +1114,249 @@ __global__ __launch_bounds__(BS) void lj_batch_kernel(BatchParams B) {
     interval(lam, B.safety, c, gamma);
     const double rgamma = uniform(1.0 / gamma);
 
-    // (2) divided differences, every member for itself
-    __syncthreads();
-    {
-      DivDiff dd;
-      dd_init(dd, K, B.l, s_s, B.max_points + 1, c, gamma, xi, coef, fmaxk);
-      dd_advance(dd, K, B.max_points, xi, coef);
-    }
-    __syncthreads();
-
-    // (3) m = 0: p_k = d_{k,0} v and ||v||^2
-    double a0[1] = {0.0};
-    for (int p = pb + (int)threadIdx.x; p < pe; p += BS) {
+    // out = sum_q alpha[q] x_q over this member's points (write-through
+    // stores: the next recurrence reads out at the neighbours), then a team
+    // barrier; the same rounding as the library's linear combinations
+    auto combine = [&](double* out, int nin, const double* alpha, const double* const* xs) {
+      for (int p = pb + (int)threadIdx.x; p < pe; p += BS) {
 #pragma unroll
-      for (int cc = 0; cc < NC; ++cc) {
-        const int idx = NC * p + cc;
-        const double vv = v[idx];
-        a0[0] += vv * vv;
-#pragma unroll
-        for (int k = 0; k < kMaxK; ++k)
-          if (k < K) pp[k][idx] = coef[k * kTable] * vv;
+        for (int cc = 0; cc < NC; ++cc) {
+          const int idx = NC * p + cc;
+          double t = alpha[0] * xs[0][idx];
+          for (int q = 1; q < nin; ++q) t = fma(alpha[q], xs[q][idx], t);
+          store_shared(out + idx, t);
+        }
       }
-    }
-    block_sum<1>(a0, red);
-    team_sum(red + NW, 1);
-    const double nv = sqrt(tot[0]);
-    if (threadIdx.x < 64) decision_init(sD, K, nv, B.hump, fmaxk);
-    __syncthreads();
+      if (threadIdx.x == 0) s_vecs += nin + 1;
+      team_barrier(ctr, tepoch, T, B.queue + 1);
+    };
 
-    // (4) Newton recurrence
-    const double* src = v;
-    for (int m = 1; m <= B.max_points && uniform(sD.n_active) > 0; ++m) {
-      double* dst = (m & 1) ? y1 : y0;
-      const double xim = uniform(xi[m - 1]);
-      double dk[kMaxK];
-      bool act[kMaxK];
+    // (2)-(5) the instance's Newton recurrences, one after another through
+    // one recurrence body:
+    //   phase 0: the shared basis, outputs w_k = phi_{l_k}(a_k h J) v;
+    // then each accumulator the shared basis rejected is redone alone with
+    // s = 2, 4, ... substeps of tau = a_k h / s, advancing
+    // w(t) = t^l phi_l(t J) v by w(t + tau) = e^{tau J} w(t)
+    //   + sum_j tau^j t^{l-j} / (l-j)! phi_j(tau J) v (the result scaled by (a_k h)^l):
+    //   phase 1 (l > 0): phi_1..phi_l of tau J on v in one recurrence,
+    //            then w = phi_l / s^l,
+    //   phase 2: exponential number i of tau J (l > 0: on w, then w = e +
+    //            the phi_j terms, i = 1 .. s-1; l = 0: the chain from v,
+    //            i = 0 .. s-1).
+    if (threadIdx.x < kMaxK) {
+      s_l[threadIdx.x] = B.l[threadIdx.x];
+      f_sub[threadIdx.x] = 1;
+    }
+    if (threadIdx.x == 0) {
+      s_iters = 0;
+      s_accum = 0;
+      s_vecs = 0;
+      s_rej = 0;
+    }
+    double nv = 0.0;
+    int phase = 0, kk = -1, lk = 0, ns = 1, si = 0, used0 = 0;
+    double tau = 0.0;
+    double* const sub0 = it->sub;
+    const size_t stride = it->nsub_stride;
+#pragma unroll 1
+    for (;;) {
+      // ---- the recurrence of this phase: input, accumulators, outputs
+      const double* vin = v;
+      int Kr = K;
+      double* outs[kMaxK];
 #pragma unroll
-      for (int k = 0; k < kMaxK; ++k) {
-        act[k] = (k < K) && (uniform(sD.st[k]) == ACC_RUNNING);
-        dk[k] = act[k] ? uniform(coef[k * kTable + m]) : 0.0;
+      for (int k = 0; k < kMaxK; ++k) outs[k] = pp[k];
+      if (phase == 1) {
+        Kr = lk;
+#pragma unroll
+        for (int k = 0; k < kMaxK; ++k) outs[k] = (k < lk) ? sub0 + (size_t)k * stride : nullptr;
+        if (threadIdx.x < kMaxK) {
+          s_l[threadIdx.x] = threadIdx.x + 1;
+          s_s[threadIdx.x] = tau;
+        }
+      } else if (phase == 2) {
+        Kr = 1;
+        if (lk > 0) {
+          vin = pp[kk];
+          outs[0] = sub0 + (size_t)lk * stride;
+        } else {
+          vin = (si == 0) ? v : (((si - 1) & 1) ? sub0 + stride : sub0);
+          outs[0] = (si == ns - 1) ? pp[kk] : ((si & 1) ? sub0 + stride : sub0);
+        }
+        if (threadIdx.x == 0) {
+          s_l[0] = 0;
+          s_s[0] = tau;
+        }
       }
-      double acc[kQ] = {0.0, 0.0, 0.0, 0.0, 0.0};
-      newton_pass<KIND, NC, true, kBatchUnroll>(op, src, dst, pp, act, dk, c, gamma, rgamma, xim,
-                                                pb + (int)threadIdx.x, pe, BS, acc);
-      block_sum<kQ>(acc, red);
-      team_sum(red + kQ * NW, 1 + K);
-      if (threadIdx.x < 64)
-        replay_decisions(sD, K, m - 1, 1, 1 + K, tot, coef, B.tol, B.relative, B.max_points, s_commit, nullptr);
       __syncthreads();
-      src = dst;
+      {
+        DivDiff dd;
+        dd_init(dd, Kr, s_l, s_s, B.max_points + 1, c, gamma, xi, coef, fmaxk);
+        dd_advance(dd, Kr, B.max_points, xi, coef);
+      }
+      __syncthreads();
+      // m = 0: p_k = d_{k,0} v and ||v||^2
+      double a0[1] = {0.0};
+      for (int p = pb + (int)threadIdx.x; p < pe; p += BS) {
+#pragma unroll
+        for (int cc = 0; cc < NC; ++cc) {
+          const int idx = NC * p + cc;
+          const double vv = vin[idx];
+          a0[0] += vv * vv;
+#pragma unroll
+          for (int k = 0; k < kMaxK; ++k)
+            if (k < Kr) outs[k][idx] = coef[k * kTable] * vv;
+        }
+      }
+      block_sum<1>(a0, red);
+      team_sum(red + NW, 1);
+      if (phase == 0) nv = sqrt(tot[0]);
+      if (threadIdx.x < 64) decision_init(sD, Kr, sqrt(tot[0]), B.hump, fmaxk);
+      __syncthreads();
+      // Newton steps
+      const double* src = vin;
+      for (int m = 1; m <= B.max_points && uniform(sD.n_active) > 0; ++m) {
+        double* dst = (m & 1) ? y1 : y0;
+        const double xim = uniform(xi[m - 1]);
+        double dk[kMaxK];
+        bool act[kMaxK];
+#pragma unroll
+        for (int k = 0; k < kMaxK; ++k) {
+          act[k] = (k < Kr) && (uniform(sD.st[k]) == ACC_RUNNING);
+          dk[k] = act[k] ? uniform(coef[k * kTable + m]) : 0.0;
+        }
+        double acc[kQ] = {0.0, 0.0, 0.0, 0.0, 0.0};
+        newton_pass<KIND, NC, true, kBatchUnroll>(op, src, dst, outs, act, dk, c, gamma, rgamma, xim,
+                                                  pb + (int)threadIdx.x, pe, BS, acc);
+        block_sum<kQ>(acc, red);
+        team_sum(red + kQ * NW, 1 + Kr);
+        if (threadIdx.x < 64)
+          replay_decisions(sD, Kr, m - 1, 1, 1 + Kr, tot, coef, B.tol, B.relative, B.max_points, s_commit, nullptr);
+        __syncthreads();
+        src = dst;
+      }
+      if (threadIdx.x == 0) {
+        s_iters += sD.iters;
+        s_accum += sD.accum_iters;
+      }
+      __syncthreads();
+
+      // ---- what follows this recurrence
+      bool next_acc = false;  // go on with the next rejected accumulator
+      bool attempt_failed = false;
+      if (phase == 0) {
+        if (threadIdx.x < kMaxK) {
+          const int k = threadIdx.x;
+          f_state[k] = (k < K) ? sD.st[k] : ACC_CONVERGED;
+          f_mst[k] = (k < K) ? sD.mst[k] : -1;
+          f_err[k] = (k < K) ? sD.err[k] : 0.0;
+        }
+        __syncthreads();
+        bool any = false;
+#pragma unroll 1
+        for (int k = 0; k < K; ++k) any = any || (uniform(f_state[k]) != ACC_CONVERGED);
+        if (any && threadIdx.x == 0) s_rej = 1;
+        next_acc = true;
+      } else if (phase == 1) {
+        bool ok = true;
+#pragma unroll 1
+        for (int j = 0; j < lk; ++j) ok = ok && (uniform(sD.st[j]) == ACC_CONVERGED);
+        if (ok) {
+          double sl = 1.0;  // s^l, exact
+#pragma unroll 1
+          for (int j = 0; j < lk; ++j) sl *= (double)ns;
+          const double a1[1] = {1.0 / sl};
+          const double* x1[1] = {sub0 + (size_t)(lk - 1) * stride};
+          combine(pp[kk], 1, a1, x1);
+          phase = 2;
+          si = 1;
+          if (si == ns) next_acc = true;  // (s >= 2 here, so never)
+        } else {
+          attempt_failed = true;
+        }
+      } else {
+        if (uniform(sD.st[0]) != ACC_CONVERGED) {
+          attempt_failed = true;
+        } else {
+          if (lk > 0) {
+            double sl = 1.0;
+#pragma unroll 1
+            for (int j = 0; j < lk; ++j) sl *= (double)ns;
+            double al[1 + kMaxK];
+            const double* xs[1 + kMaxK];
+            al[0] = 1.0;
+            xs[0] = sub0 + (size_t)lk * stride;
+            double fact = 1.0;  // (l - j)!
+#pragma unroll 1
+            for (int j = lk; j >= 1; --j) {
+              if (j < lk) fact *= (double)(lk - j);
+              double ip = 1.0;  // i^(l-j), exact
+#pragma unroll 1
+              for (int q = 0; q < lk - j; ++q) ip *= (double)si;
+              al[j] = ip / (fact * sl);
+              xs[j] = sub0 + (size_t)(j - 1) * stride;
+            }
+            combine(pp[kk], lk + 1, al, xs);
+          }
+          si += 1;
+          if (si == ns) {  // the attempt succeeded
+            if (threadIdx.x == 0) {
+              f_state[kk] = ACC_CONVERGED;
+              f_mst[kk] = s_iters - used0;
+              f_err[kk] = 0.0;
+              f_sub[kk] = ns;
+            }
+            next_acc = true;
+          }
+        }
+      }
+      if (attempt_failed) {
+        if (threadIdx.x == 0) s_rej += 1;
+        ns *= 2;
+        if (ns > B.max_substeps) {
+          if (threadIdx.x == 0) {
+            f_mst[kk] = -1;
+            f_sub[kk] = ns / 2;
+          }
+          next_acc = true;
+        }
+      }
+      __syncthreads();
+      if (next_acc) {  // the next accumulator the shared basis rejected, if any
+        int k = kk + 1;
+#pragma unroll 1
+        for (;;) {
+          while (k < K && uniform(f_state[k]) == ACC_CONVERGED) ++k;
+          if (k >= K || B.max_substeps >= 2) break;
+          ++k;  // no substeps allowed: it stays rejected (m* -1, s 1)
+        }
+        if (k >= K) break;
+        kk = k;
+        lk = B.l[k];
+        ns = 2;
+      }
+      if (next_acc || attempt_failed) {  // start an attempt at ns substeps
+        tau = uniform(s_s0[kk]) / (double)ns;
+        phase = (lk > 0) ? 1 : 2;
+        si = 0;
+        used0 = uniform(s_iters);
+      }
     }
 
-    // (5) outcome of this instance
+    // (6) outcome of this instance
     if (rank == 0 && threadIdx.x == 0) {
       BatchStatus* S = B.status + inst;
 #pragma unroll
       for (int k = 0; k < kMaxK; ++k) {
-        S->state[k] = sD.st[k];
-        S->m_star[k] = sD.mst[k];
-        S->err[k] = sD.err[k];
+        S->state[k] = f_state[k];
+        S->m_star[k] = f_mst[k];
+        S->err[k] = f_err[k];
+        S->substeps[k] = f_sub[k];
       }
-      S->iters = sD.iters;
-      S->accum_iters = sD.accum_iters;
+      S->iters = s_iters;
+      S->accum_iters = s_accum;
+      S->vec_passes = s_vecs;
+      S->rejections = s_rej;
       S->power_iters = pit;
       S->vnorm = nv;
       S->lam = lam;

@@ -1097,6 +1097,7 @@ struct lj_batch {
   double* d_team_part = nullptr;
   int max_blocks = 0;
   double* d_work = nullptr;
+  double* d_sub = nullptr;  // substep vectors of every instance
   hipStream_t cs = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
@@ -1120,6 +1121,7 @@ void batch_release(lj_batch* b) {
   if (b->d_queue) (void)hipFree(b->d_queue);
   if (b->d_team_part) (void)hipFree(b->d_team_part);
   if (b->d_work) (void)hipFree(b->d_work);
+  if (b->d_sub) (void)hipFree(b->d_sub);
   delete b;
 }
 
@@ -2617,8 +2619,13 @@ LJ_API int lj_batch_create(lj_context* ctx, const lj_operator* ops, int n, const
       b->nval.push_back((long long)nvals(op));
       b->total_values += (long long)nvals(op);
     }
-    // device-side description
+    // device-side description: two basis vectors per instance, and, when
+    // substeps may be taken, max(l, 1) + 1 substep vectors per instance
     HIPCHK(ctx, hipMalloc(&b->d_work, (size_t)2 * b->total_values * sizeof(double)));
+    int lmax = 0;
+    for (int k = 0; k < K; ++k) lmax = std::max(lmax, l[k]);
+    const int nsub = (b->o.max_substeps >= 2) ? std::max(lmax, 1) + 1 : 0;
+    if (nsub > 0) HIPCHK(ctx, hipMalloc(&b->d_sub, (size_t)nsub * b->total_values * sizeof(double)));
     std::vector<BatchItem> items(n);
     size_t off = 0;
     for (int i = 0; i < n; ++i) {
@@ -2632,6 +2639,8 @@ LJ_API int lj_batch_create(lj_context* ctx, const lj_operator* ops, int n, const
       }
       it.y0 = b->d_work + off;
       it.y1 = b->d_work + off + b->nval[i];
+      it.sub = (nsub > 0) ? b->d_sub + (size_t)nsub * off / 2 : nullptr;
+      it.nsub_stride = (size_t)b->nval[i];
       off += 2 * (size_t)b->nval[i];
       it.lam_in = (bounds && bounds[i] > 0.0) ? bounds[i] : (b->o.bound > 0.0 ? b->o.bound : 0.0);
     }
@@ -2658,6 +2667,7 @@ LJ_API int lj_batch_create(lj_context* ctx, const lj_operator* ops, int n, const
     P.seed = b->o.seed;
     P.safety = b->o.safety;
     P.max_points = b->o.max_points;
+    P.max_substeps = b->o.max_substeps;
     P.relative = b->o.relative;
     P.tol = tol;
     P.hump = b->o.hump;
@@ -2704,8 +2714,8 @@ LJ_API int lj_batch_stats(lj_batch* b, lj_stats* per_instance, void* stream) {
     double bytes = 0.0;
     for (int i = 0; i < b->n; ++i) {
       const BatchStatus& S = b->h_status[i];
-      bytes += (double)b->nval[i] *
-               (24.0 * S.iters + 16.0 * S.accum_iters + 24.0 * S.power_iters + 8.0 + 8.0 * b->K);
+      bytes += (double)b->nval[i] * (24.0 * S.iters + 16.0 * S.accum_iters + 24.0 * S.power_iters + 8.0 +
+                                      8.0 * b->K + 8.0 * S.vec_passes);
       lj_stats st;
       std::memset(&st, 0, sizeof(st));
       for (int k = 0; k < LJ_MAX_K; ++k) {
@@ -2717,44 +2727,18 @@ LJ_API int lj_batch_stats(lj_batch* b, lj_stats* per_instance, void* stream) {
       st.bound = S.lam;
       st.c = S.c;
       st.gamma = S.gamma;
-      std::vector<int> pend_l;
-      std::vector<double> pend_a;
-      std::vector<double*> pend_w;
-      std::vector<int> pend_k;
+      st.rejections = S.rejections;
+      st.converged = 1;
       for (int k = 0; k < b->K; ++k) {
+        st.substeps[k] = S.substeps[k];
         if (S.state[k] == ACC_CONVERGED) {
           st.m_star[k] = S.m_star[k];
           st.err_est[k] = S.err[k];
         } else {
-          pend_k.push_back(k);
-          pend_l.push_back(b->l[k]);
-          pend_a.push_back(b->a[k]);
-          pend_w.push_back(b->w[(size_t)i * b->K + k]);
-        }
-      }
-      st.converged = 1;
-      if (!pend_k.empty()) {
-        // the batch attempt was rejected: redo those accumulators with the
-        // plain path and substeps, on the bound the batch found
-        st.rejections = 1;
-        Opts o = b->o;
-        o.bound = S.lam;
-        o.substeps = 2;
-        lj_stats fb;
-        const int r = vertical_impl(ctx, b->ops[i], b->v[i], (int)pend_k.size(), pend_l.data(), pend_a.data(),
-                                    b->h[i], b->tol, pend_w.data(), o, &fb, s);
-        st.iters_total += fb.iters_total;
-        st.rejections += fb.rejections;
-        for (size_t q = 0; q < pend_k.size(); ++q) {
-          st.m_star[pend_k[q]] = fb.m_star[q];
-          st.substeps[pend_k[q]] = fb.substeps[q];
-          st.err_est[pend_k[q]] = fb.err_est[q];
-        }
-        if (r != LJ_OK) {
           st.converged = 0;
-          all_ok = false;
         }
       }
+      if (!st.converged) all_ok = false;
       if (per_instance) per_instance[i] = st;
     }
     b->alg_bytes = bytes;

@@ -575,3 +575,33 @@ def test_dd_floor_of_long_expansion(monkeypatch):
     v10 = h10 * op.rhs(p.state)
     run10 = lambda: phi_action(op, v10, 1, h10, 1e-10, Options(bound=lam))[0]
     assert dd_floor(monkeypatch, run10, rel) < 1e-13
+
+
+def test_batch_rejection_regime_is_rounding_decided():
+    """Instance 46 of the 256-instance ensemble (128^2, eps 1.5e-4, h 10x
+    CFL): the reaction eigenvalue +1 lies outside the interval, the Newton
+    basis grows, and whether the attempts at s = 2, 4 pass the hump test is
+    decided by the rounding of the divided differences -- one-ulp changes of
+    the node values move the substep count between 4 and 8, while each run
+    converges."""
+    from oracle.power import power_iteration
+    from workloads import batch_instances
+    p = batch_instances()[46]
+    op = Operator(p)
+    h = 10 * p.h_cfl
+    v = h * op.rhs(p.state)
+    lam = power_iteration(op.jv, p.n, 20)
+    orig = leja.phi
+    seen = set()
+    try:
+        for seed in (None, 1, 3):
+            if seed is not None:
+                rng = np.random.default_rng(seed)
+                leja.phi = lambda l, z: orig(l, z) * (1.0 + 2.0 ** -52 * rng.integers(-1, 2))
+            _, so = phi_vertical(op, v, [1, 2, 3], [1.0] * 3, h, 1e-10, Options(bound=lam))
+            leja.phi = orig
+            assert so.converged
+            seen.add(max(so.substeps))
+    finally:
+        leja.phi = orig
+    assert seen == {4, 8}
