@@ -31,6 +31,7 @@ constexpr int kMaxPoints = 100;         // most Newton terms
 constexpr int kTable = kMaxPoints + 1;  // Leja nodes kept on the device
 constexpr int kBarrierWords = 32 * 19;  // words of one grid-barrier state (zero at launch)
 constexpr int kPartStride = 48;         // partial sums per block and barrier slot
+constexpr int kRegPartStride = 96;      // the same for the register-tiled kernel (16 steps x (1 + K) + 1)
 constexpr int kMaxSuper = 8;            // Newton steps per barrier in the tiled kernel (max)
 
 // Operator as the kernels see it: coefficients plus precomputed reciprocals.

@@ -939,6 +939,430 @@ __global__ __launch_bounds__(kBlock) void lj_action_tile(ActionParams P) {
   grid_exit(P.barrier);
 }
 
+// ===========================================================================
+// Register-tiled action kernel with temporal blocking, for the periodic
+// scalar families whose Jacobian reads the state at the centre only
+// (Allen-Cahn, advection-diffusion).  One block of 8 waves per CU owns a
+// 32 x 32 tile; the tile extended by kRegS = 16 points on every side is
+// 64 x 64 and lives in registers: lane c of every wave holds column c, wave w
+// rows 8w .. 8w+7.  A step takes the west and east neighbours from the
+// adjacent lanes (DPP wave shifts), north and south from the lane's own
+// registers, and the outer neighbours of a wave's first and last rows from
+// the adjacent waves through LDS (one workgroup barrier per step).  Values at
+// the borders of the extended tile go stale by one column / row per step, so
+// after 16 steps exactly the owned 32 x 32 points are exact: up to 16 Newton
+// steps run between grid barriers, with the halo recomputed in registers.
+// The owned points' basis values of the super-step go to LDS (the history
+// the commit replays when an accumulator stops inside a super-step); the
+// accumulators run speculatively in registers, and the committed values are
+// kept in the output vectors between super-steps.  Per point and step the
+// arithmetic is that of lj_action_tile (the same folded stencil), so the
+// results are term for term those of the untiled recurrence up to that
+// stencil's rounding.
+// ===========================================================================
+constexpr int kRegS = 16;                        // steps per super-step = halo width
+constexpr int kRegTile = 32;                     // owned tile edge
+constexpr int kRegWaves = 8;
+constexpr int kRegRows = 8;                      // extended rows per wave
+constexpr int kRegBlock = 64 * kRegWaves;
+constexpr int kRegSlots = kRegS * (1 + kMaxK) + 1;  // reduced values per super-step, at most
+static_assert(kRegWaves * kRegRows == kRegTile + 2 * kRegS && kRegTile + 2 * kRegS == 64, "64 x 64 extended tile");
+static_assert(kRegSlots <= kRegPartStride, "partial-sum slots");
+
+struct RegShared {
+  double xi[kTable];
+  double coef[kMaxK * kTable];
+  double fmax[kMaxK];
+  double tot[kRegSlots];
+  double stg[kRegSlots][8];            // per step and value: row sums of the owned waves 2..5, lanes 16-31 / 32-47
+  double xrow[2][2 * kRegWaves][64];   // [parity][2 w: first row of wave w, 2 w + 1: its last row][lane]
+  Decision D;
+  int commit[kMaxK];
+};
+
+// Partial sums of one super-step: slot q of block b at area[q * G + b].
+__device__ __forceinline__ double* reg_area(double* partials, unsigned int epoch) {
+  return partials + (size_t)(epoch & 1u) * kRegPartStride * gridDim.x;
+}
+
+// After a grid barrier: totals of slots [0, nq) of `area` into tot (LDS);
+// wave w adds the slots w, w + 8, ..., CH of them per round, lane t the blocks
+// t, t + 64, t + 128, t + 192 (G <= 256) in that order, then the wave sums
+// its lanes -- the same fixed order in every block.  All loads of a round are
+// issued before any sum.
+template <int CH>
+__device__ __forceinline__ void reg_reduce(const double* area, int nq, double* tot) {
+  const int G = gridDim.x;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  for (int r0 = 0; r0 * kRegWaves < nq; r0 += CH) {
+    double v[CH][4];
+#pragma unroll
+    for (int r = 0; r < CH; ++r) {
+      const int q = w + kRegWaves * (r0 + r);
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        const int b = lane + 64 * c;
+        v[r][c] = (q < nq && b < G) ? area[(size_t)q * G + b] : 0.0;
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < CH; ++r) {
+      const int q = w + kRegWaves * (r0 + r);
+      const double a = ((v[r][0] + v[r][1]) + v[r][2]) + v[r][3];
+      const double t = wave_sum(a);
+      if (q < nq && lane == 0) tot[q] = t;
+    }
+  }
+  __syncthreads();
+}
+
+template <int KIND, int KM, bool FULL>
+__global__ __launch_bounds__(kRegBlock) void lj_action_reg(ActionParams P) {
+  static_assert(KIND == OP_ADVDIFF || KIND == OP_ALLENCAHN, "register-tiled kernel: periodic scalar families");
+  constexpr int CH = (KM == 1) ? 5 : 3;  // rows of partial sums per wave and load round
+  const GridSync gsync{P.barrier, P.spin_limit};
+  extern __shared__ double Hist[];  // kRegS x 1024: basis values of the owned points per step
+  __shared__ RegShared sh;
+  const OpDev& op = P.op;
+  const int K = P.K;
+  const int Q = 1 + K;
+  const int nx = op.nx, ny = op.ny;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  for (int i = threadIdx.x; i < kTable; i += kRegBlock) sh.xi[i] = P.xi[i];
+
+  // ---- tile geometry: owned w x h points at (x0, y0); lane = extended column,
+  // rows 8 wv + i of the extended tile (extended origin at x0 - 16, y0 - 16)
+  const int tb = xcd_chunk(blockIdx.x, gridDim.x);
+  const int x0 = (tb % P.ntx) * kRegTile, y0 = (tb / P.ntx) * kRegTile;
+  const int w = min(kRegTile, nx - x0), h = min(kRegTile, ny - y0);
+  int gxc = (x0 - kRegS + lane) % nx;  // this lane's global column (periodic)
+  if (gxc < 0) gxc += nx;
+  auto grow = [&](int i) {  // global row of extended row 8 wv + i
+    int gy = (y0 - kRegS + kRegRows * wv + i) % ny;
+    if (gy < 0) gy += ny;
+    return gy;
+  };
+  const bool lane_own = lane >= kRegS && lane < kRegS + w;
+  const bool owned_wave = wv >= 2 && wv < 6;  // rows 16 .. 47
+  auto row_own = [&](int i) {
+    const int r = kRegRows * wv + i - kRegS;
+    return r >= 0 && r < h;
+  };
+  auto own = [&](int i) { return FULL ? (owned_wave && lane_own) : (lane_own && row_own(i)); };
+  // a value of an owned point, zero elsewhere (called by the owned waves only:
+  // in a full tile the row sums taken there, lanes 16-31 and 32-47, see owned
+  // points only, so no mask is needed)
+  auto ownv = [&](int i, double v) { return FULL ? v : (own(i) ? v : 0.0); };
+  auto hidx = [&](int i) { return (kRegRows * wv + i - kRegS) * kRegTile + (lane - kRegS); };
+  auto gown = [&](int i) { return (y0 + kRegRows * wv + i - kRegS) * nx + x0 + lane - kRegS; };
+
+  // folded stencil as in lj_action_tile: (J x)(p) = fw x_W + fe x_E + fs x_S +
+  // fn x_N + e_d(p) x_C
+  double fw, fe, fs, fn;
+  if constexpr (KIND == OP_ALLENCAHN) {
+    fw = fe = op.c0 * op.idx2;
+    fs = fn = op.c0 * op.idy2;
+  } else {
+    fw = op.c0 * op.idx2 + op.c1 * op.i2dx;
+    fe = op.c0 * op.idx2 - op.c1 * op.i2dx;
+    fs = op.c0 * op.idy2 + op.c2 * op.i2dy;
+    fn = op.c0 * op.idy2 - op.c2 * op.i2dy;
+  }
+  const double d_lap = -2.0 * op.c0 * (op.idx2 + op.idy2);
+  double x[kRegRows], dg[kRegRows];
+#pragma unroll
+  for (int i = 0; i < kRegRows; ++i) {
+    if constexpr (KIND == OP_ALLENCAHN) {
+      const double u = op.state[(size_t)grow(i) * nx + gxc];
+      dg[i] = d_lap + (1.0 - 3.0 * u * u);
+    } else {
+      dg[i] = d_lap;
+    }
+  }
+
+  unsigned int epoch = 0;
+  int par = 0;     // row-exchange buffer
+  int ypar = 0;    // global exchange vector
+  unsigned long long prof[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  unsigned long long t_last = wall_clock64();
+  auto tick = [&](int phase) {
+    const unsigned long long t = wall_clock64();
+    prof[phase] += t - t_last;
+    t_last = t;
+  };
+
+  // one step of x <- A x on the whole extended tile, A = the folded stencil
+  // with diagonal dg - xim
+  auto step = [&](double xim) {
+    double* xr = &sh.xrow[par][0][0];
+    xr[(2 * wv) * 64 + lane] = x[0];
+    xr[(2 * wv + 1) * 64 + lane] = x[kRegRows - 1];
+    __syncthreads();
+    const double above = xr[(2 * ((wv + kRegWaves - 1) % kRegWaves) + 1) * 64 + lane];
+    const double below = xr[(2 * ((wv + 1) % kRegWaves)) * 64 + lane];
+    par ^= 1;
+    double prev = above;
+#pragma unroll
+    for (int i = 0; i < kRegRows; ++i) {
+      const double xc = x[i];
+      const double xn = (i < kRegRows - 1) ? x[i + 1] : below;
+      const double xw = dpp_move<0x138>(xc);  // wave_shr:1 -- lane c - 1
+      const double xe = dpp_move<0x130>(xc);  // wave_shl:1 -- lane c + 1
+      double y;
+      if constexpr (KIND == OP_ALLENCAHN) {
+        y = fw * (xw + xe) + fs * (prev + xn);
+      } else {
+        y = fw * xw + fe * xe + fs * prev + fn * xn;
+      }
+      x[i] = fma(dg[i] - xim, xc, y);
+      prev = xc;
+    }
+  };
+  // row sums of one value per owned point (owned waves only): lanes 31 and 47
+  // hold the sums of lanes 16-31 and 32-47
+  auto stage = [&](int slot, double a) {
+    const double t = row_sum(a);
+    if (lane == 31 || lane == 47) sh.stg[slot][(wv - 2) * 2 + (lane >> 4) - 1] = t;
+  };
+  // block totals of the staged slots -> this barrier's partial-sum area
+  auto publish = [&](int nq) {
+    __syncthreads();
+    double* area = reg_area(P.partials, epoch);
+    for (int q = threadIdx.x; q < nq; q += kRegBlock) {
+      double t = 0.0;
+#pragma unroll
+      for (int e = 0; e < 8; ++e) t += sh.stg[q][e];
+      store_shared(area + (size_t)q * gridDim.x + blockIdx.x, t);
+    }
+    return area;
+  };
+  // the owned points' current values to the exchange vector; after the
+  // barrier the halo (every position outside the owned points) is reloaded
+  // from it, scaled
+  auto put_owned = [&]() {
+    double* yb = ypar ? P.ybuf1 : P.ybuf0;
+    if (owned_wave) {
+#pragma unroll
+      for (int i = 0; i < kRegRows; ++i)
+        if (own(i)) store_shared(yb + gown(i), x[i]);
+    }
+  };
+  auto fetch_halo = [&]() {
+    const double* yb = ypar ? P.ybuf1 : P.ybuf0;
+#pragma unroll
+    for (int i = 0; i < kRegRows; ++i)
+      if (!own(i)) x[i] = yb[(size_t)grow(i) * nx + gxc];
+  };
+
+  // sum of squares of the owned points' current values over this lane's rows
+  // (two interleaved partial sums, then added)
+  auto sumsq_own = [&]() {
+    double a0 = 0.0, a1 = 0.0;
+#pragma unroll
+    for (int i = 0; i < kRegRows; i += 2) {
+      const double t0 = ownv(i, x[i]), t1 = ownv(i + 1, x[i + 1]);
+      a0 = fma(t0, t0, a0);
+      a1 = fma(t1, t1, a1);
+    }
+    return a0 + a1;
+  };
+
+  // ---- (1) spectral bound: up to 16 products between barriers, normalised per barrier
+  double lam = (P.lam_src != nullptr && !P.do_power) ? *P.lam_src : P.lam_in;
+  int pit = 0;
+  if (P.do_power) {
+#pragma unroll
+    for (int i = 0; i < kRegRows; ++i) {
+      const size_t g = (size_t)grow(i) * nx + gxc;
+      x[i] = P.start ? P.start[g] : 0.5 + splitmix_uniform(P.seed, (uint64_t)g);
+    }
+    int done = 0;
+    while (done < P.power_iters) {
+      const int steps = min(kRegS, P.power_iters - done);
+      if (owned_wave) stage(0, sumsq_own());
+      for (int j = 1; j <= steps; ++j) {
+        step(0.0);
+        if (owned_wave) stage(j, sumsq_own());
+      }
+      double* area = publish(steps + 1);
+      put_owned();
+      const bool more = done + steps < P.power_iters;
+      grid_allreduce(gsync, epoch, nullptr, 0, nullptr, NoOverlap{}, [&] {
+        if (more) fetch_halo();
+      });
+      reg_reduce<CH>(area, steps + 1, sh.tot);
+      const double nprev = sh.tot[steps - 1], nlast = sh.tot[steps];
+      done += steps;
+      pit = done;
+      lam = sqrt(nlast) / sqrt(nprev);
+      if (nlast == 0.0) {
+        lam = 0.0;
+        break;
+      }
+      if (more) {
+        const double sc = 1.0 / sqrt(nlast);
+#pragma unroll
+        for (int i = 0; i < kRegRows; ++i) x[i] *= sc;
+        ypar ^= 1;
+      }
+    }
+  }
+  lam = uniform(lam);
+  if (P.lam_out != nullptr && blockIdx.x == 0 && threadIdx.x == 0) *P.lam_out = lam;
+  double c, gamma;
+  interval(lam, P.safety, c, gamma);
+  const double rgamma = uniform(1.0 / gamma);
+  tick(kProfPower);
+  if (K == 0) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      Decision D;
+      decision_init(D, 0, 1.0, 0.0, sh.fmax);
+      store_status(P, D, pit, (int)epoch, 0.0, lam, c, gamma, prof);
+    }
+    grid_exit(P.barrier);
+    return;
+  }
+
+  // the Newton steps' coefficients: (J - c) / gamma
+  fw *= rgamma;
+  fe *= rgamma;
+  fs *= rgamma;
+  fn *= rgamma;
+#pragma unroll
+  for (int i = 0; i < kRegRows; ++i) dg[i] = (dg[i] - c) * rgamma;
+
+  // ---- (2) divided differences up to the first super-step's last term (the
+  // rest while barriers are pending), and y_0 = v on the extended tile
+  __syncthreads();
+  DivDiff dd;
+  dd_init(dd, K, P.l, P.s, P.max_points + 1, c, gamma, sh.xi, sh.coef, sh.fmax);
+#pragma unroll
+  for (int i = 0; i < kRegRows; ++i) x[i] = P.v[(size_t)grow(i) * nx + gxc];
+  dd_advance(dd, K, kRegS, sh.xi, sh.coef);
+  __syncthreads();
+  tick(kProfDivdiff);
+
+  // ---- (3) Newton recurrence in super-steps of up to 16.  Committed
+  // accumulator values live in the outputs between super-steps: p_k = d_{k,0} v.
+  double ps[KM][kRegRows];
+  double v_sq = 0.0;
+  if (owned_wave) {
+#pragma unroll
+    for (int k = 0; k < KM; ++k) {
+      const double d0 = sh.coef[k * kTable];
+#pragma unroll
+      for (int i = 0; i < kRegRows; ++i) {
+        ps[k][i] = d0 * x[i];
+        if (k < K && own(i)) P.p[k][gown(i)] = ps[k][i];
+      }
+    }
+    v_sq = sumsq_own();
+  }
+  if (threadIdx.x == 0) decision_init(sh.D, K, 1.0, 0.0, sh.fmax);  // redone once ||v|| is known
+  __syncthreads();
+  double nv = 0.0;
+  bool first = true;
+  int m0 = 0;
+  while (true) {
+    const int steps = min(min(kRegS, P.max_points - m0), uniform(sh.D.next));
+    bool act0[KM];
+#pragma unroll
+    for (int k = 0; k < KM; ++k) act0[k] = (k < K) && (uniform(sh.D.st[k]) == ACC_RUNNING);
+    // the super-step's nodes and coefficients, lane j holding those of step
+    // m0 + 1 + j (read per step with readlane: no LDS wait in the loop)
+    const double xiv = (lane < steps) ? sh.xi[m0 + lane] : 0.0;
+    double cfv[KM];
+#pragma unroll
+    for (int k = 0; k < KM; ++k) cfv[k] = (lane < steps && act0[k]) ? sh.coef[k * kTable + m0 + 1 + lane] : 0.0;
+    for (int j = 1; j <= steps; ++j) {
+      step(read_lane(xiv, j - 1));
+      if (owned_wave) {
+        if (FULL) {
+          if (lane_own) {
+#pragma unroll
+            for (int i = 0; i < kRegRows; ++i) Hist[(j - 1) * (kRegTile * kRegTile) + hidx(i)] = x[i];
+          }
+        } else {
+#pragma unroll
+          for (int i = 0; i < kRegRows; ++i)
+            if (own(i)) Hist[(j - 1) * (kRegTile * kRegTile) + hidx(i)] = x[i];
+        }
+        stage((j - 1) * Q, sumsq_own());
+#pragma unroll
+        for (int k = 0; k < KM; ++k) {
+          if (!act0[k]) continue;
+          const double dk = read_lane(cfv[k], j - 1);
+          double b0 = 0.0, b1 = 0.0;
+#pragma unroll
+          for (int i = 0; i < kRegRows; i += 2) {
+            ps[k][i] = ps[k][i] + dk * x[i];
+            ps[k][i + 1] = ps[k][i + 1] + dk * x[i + 1];
+            const double t0 = ownv(i, ps[k][i]), t1 = ownv(i + 1, ps[k][i + 1]);
+            b0 = fma(t0, t0, b0);
+            b1 = fma(t1, t1, b1);
+          }
+          stage((j - 1) * Q + 1 + k, b0 + b1);
+        }
+      }
+    }
+    tick(kProfSteps);
+    if (first && owned_wave) stage(steps * Q, v_sq);  // ||v||^2 rides on the first barrier
+    const int nq = steps * Q + (first ? 1 : 0);
+    double* area = publish(nq);
+    put_owned();
+    tick(kProfPublish);
+    grid_allreduce(
+        gsync, epoch, nullptr, 0, nullptr, [&] { dd_advance(dd, K, m0 + steps + kRegS, sh.xi, sh.coef); },
+        [&] { fetch_halo(); });
+    reg_reduce<CH>(area, nq, sh.tot);
+    tick(kProfBarrier);
+    if (threadIdx.x < 64) {
+      if (first) {
+        nv = sqrt(sh.tot[steps * Q]);
+        decision_init(sh.D, K, nv, P.hump, sh.fmax);
+      }
+      replay_decisions(sh.D, K, m0, steps, Q, sh.tot, sh.coef, P.tol, P.relative, P.max_points, sh.commit,
+                       blockIdx.x == 0 ? P.status->trace : nullptr);
+    }
+    first = false;
+    __syncthreads();
+    tick(kProfDecide);
+    // commit: an accumulator that ran through the super-step keeps its
+    // speculative sum; one that stopped inside it adds its terms up to its
+    // stop index to the committed value, from the history
+    if (owned_wave) {
+#pragma unroll
+      for (int k = 0; k < KM; ++k) {
+        if (k >= K) continue;
+        const int ck = uniform(sh.commit[k]);
+        if (ck == 0) continue;
+        if (ck < steps) {
+#pragma unroll
+          for (int i = 0; i < kRegRows; ++i) {
+            if (!own(i)) continue;
+            double pk = P.p[k][gown(i)];
+            for (int j = 1; j <= ck; ++j)
+              pk = pk + uniform(sh.coef[k * kTable + m0 + j]) * Hist[(j - 1) * (kRegTile * kRegTile) + hidx(i)];
+            ps[k][i] = pk;
+          }
+        }
+#pragma unroll
+        for (int i = 0; i < kRegRows; ++i)
+          if (own(i)) P.p[k][gown(i)] = ps[k][i];
+      }
+    }
+    m0 += steps;
+    ypar ^= 1;
+    tick(kProfCommit);
+    if (sh.D.n_active == 0 || m0 >= P.max_points) break;
+    __syncthreads();  // the commit's history reads precede the next super-step's writes
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    store_status(P, sh.D, pit, (int)epoch, nv, lam, c, gamma, prof);
+  }
+  grid_exit(P.barrier);
+}
+
 // ---------------------------------------------------------------------------
 // Stand-alone divided differences (the lj_divided_differences entry point);
 // the same dd_init / dd_advance the action kernels run.
@@ -1573,6 +1997,24 @@ void* action_tile_ptr(int kind, int ept, int K) {
 #undef LJ_TILE_CASES
   return nullptr;
 }
+
+void* action_reg_ptr(int kind, int K, bool full) {
+#define LJ_REG_CASE(K_)                                                                                  \
+  if (kind == K_) {                                                                                      \
+    if (K <= 1)                                                                                          \
+      return full ? reinterpret_cast<void*>(&lj_action_reg<K_, 1, true>)                                 \
+                  : reinterpret_cast<void*>(&lj_action_reg<K_, 1, false>);                               \
+    return full ? reinterpret_cast<void*>(&lj_action_reg<K_, kMaxK, true>)                               \
+                : reinterpret_cast<void*>(&lj_action_reg<K_, kMaxK, false>);                             \
+  }
+  LJ_REG_CASE(OP_ALLENCAHN)
+  LJ_REG_CASE(OP_ADVDIFF)
+#undef LJ_REG_CASE
+  return nullptr;
+}
+int reg_block() { return kRegBlock; }
+size_t reg_lds_bytes() { return (size_t)kRegS * kRegTile * kRegTile * sizeof(double); }
+size_t reg_static_lds() { return sizeof(RegShared); }
 
 void* batch_kernel_ptr(int kind, int bs) {
 #define LJ_BATCH_CASE(K_, NC_)                                                          \

@@ -50,6 +50,10 @@ struct FinishArgs {
 int persistent_block();  // threads per block of the action kernels
 int tile_halo();         // halo width = Newton steps per barrier of the tiled kernel
 void* action_stream_ptr(int kind);
+void* action_reg_ptr(int kind, int K, bool full);  // register-tiled kernel (full: every tile 32 x 32); nullptr if the family has none
+int reg_block();                        // its threads per block
+size_t reg_lds_bytes();                 // its dynamic LDS (step history)
+size_t reg_static_lds();                // its static LDS
 void* action_tile_ptr(int kind, int ept, int K);  // K accumulators; nullptr if the family has no tiled kernel
 
 hipError_t launch_divdiff(const DDParams& P, hipStream_t s);

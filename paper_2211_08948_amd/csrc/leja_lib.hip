@@ -88,7 +88,8 @@ struct lj_context {
   LejaStatus* h_status = nullptr;  // pinned
   double* h_coef = nullptr;        // pinned
   int grid_override = 0;   // LJ_GRID: blocks of the streaming kernel
-  int force_stream = 0;    // LJ_NO_TILE=1: never use the LDS-tiled kernel
+  int force_stream = 0;    // LJ_NO_TILE=1: never use the LDS-tiled or register-tiled kernels
+  int no_reg = 0;          // LJ_NO_REG=1: never use the register-tiled kernel
   int force_coop = 0;      // LJ_COOP=1: always launch the action kernels cooperatively
   std::map<std::pair<const void*, size_t>, int> occupancy;  // blocks per CU of (kernel, dynamic LDS)
   int tile_override_x = 0; // LJ_TILE=tx,ty: tile shape of the LDS-tiled kernel
@@ -304,8 +305,9 @@ void ensure_small(lj_context* ctx, int blocks) {
     if (ctx->d_partials) (void)hipFree(ctx->d_partials);
     ctx->d_partials = nullptr;
     ctx->partial_cap = 0;
-    // two partial-sum areas of kPartStride * blocks doubles (see grid_allreduce)
-    if (hipMalloc(&ctx->d_partials, (size_t)2 * blocks * kPartStride * sizeof(double)) != hipSuccess) {
+    // two partial-sum areas of kRegPartStride * blocks doubles (the larger of
+    // the two action kernels' strides; see grid_allreduce and reg_area)
+    if (hipMalloc(&ctx->d_partials, (size_t)2 * blocks * kRegPartStride * sizeof(double)) != hipSuccess) {
       ctx->err = "partials allocation failed";
       throw Fail{LJ_ENOMEM};
     }
@@ -372,6 +374,31 @@ TilePlan tile_plan(lj_context* ctx, const OpDev& op) {
   return best;
 }
 
+// Register-tiled kernel: 32 x 32 tiles, at most one per CU (and at most 256,
+// the partial-sum reduction's assumption), the step history in dynamic LDS.
+struct RegPlan {
+  bool ok = false;
+  bool full = false;  // every tile is 32 x 32
+  int ntx = 0, nty = 0;
+  size_t lds = 0;
+};
+
+RegPlan reg_plan(lj_context* ctx, const OpDev& op, int K) {
+  RegPlan r;
+  if (ctx->force_stream || ctx->no_reg || ctx->tile_override_x > 0 || action_reg_ptr(op.kind, K, true) == nullptr)
+    return r;
+  const int ntx = (op.nx + 31) / 32, nty = (op.ny + 31) / 32;
+  const long G = (long)ntx * nty;
+  if (G > ctx->num_cus || G > 256) return r;
+  if (reg_lds_bytes() + reg_static_lds() > (size_t)ctx->lds_max) return r;
+  r.ok = true;
+  r.full = op.nx % 32 == 0 && op.ny % 32 == 0;
+  r.ntx = ntx;
+  r.nty = nty;
+  r.lds = reg_lds_bytes();
+  return r;
+}
+
 // ---- one phi-action launch ------------------------------------------------
 struct ActOut {
   bool aborted;  // a grid barrier timed out: the launch must be repeated cooperatively
@@ -392,13 +419,13 @@ struct BoundLink {
 // Whether every block of a G-block launch of `fn` fits on the device at once,
 // so that a plain launch keeps them co-resident (the cooperative launch
 // guarantees it but costs ~12 us more per launch).
-bool coresident(lj_context* ctx, const void* fn, int G, size_t dyn) {
+bool coresident(lj_context* ctx, const void* fn, int G, size_t dyn, int block) {
   if (ctx->force_coop) return false;
   const auto key = std::make_pair(fn, dyn);
   auto it = ctx->occupancy.find(key);
   int nb = 0;
   if (it == ctx->occupancy.end()) {
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, persistent_block(), dyn) != hipSuccess) {
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, block, dyn) != hipSuccess) {
       (void)hipGetLastError();
       nb = 0;
     }
@@ -448,11 +475,26 @@ void launch_action(lj_context* ctx, const OpDev& op, const double* v, int K, con
   // a header-only status into a slot of the pinned pool is written by the
   // kernel itself; otherwise it is copied after the launch
   P.status_host = direct_status ? status_dst : nullptr;
-  const TilePlan tp = tile_plan(ctx, op);
+  const RegPlan rp = reg_plan(ctx, op, K);
+  const TilePlan tp = rp.ok ? TilePlan{} : tile_plan(ctx, op);
   void* fn = nullptr;
   int G = 0;
   size_t dyn = 0;
-  if (tp.ok) {
+  int block = persistent_block();
+  if (rp.ok) {
+    fn = action_reg_ptr(op.kind, K, rp.full);
+    P.tx = 32;
+    P.ty = 32;
+    P.ntx = rp.ntx;
+    P.nty = rp.nty;
+    G = rp.ntx * rp.nty;
+    dyn = rp.lds;
+    block = reg_block();
+    if (dyn > 64 * 1024 && ctx->dyn_lds[fn] < dyn) {
+      HIPCHK(ctx, hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn));
+      ctx->dyn_lds[fn] = dyn;
+    }
+  } else if (tp.ok) {
     fn = action_tile_ptr(op.kind, tp.ept, K);
     P.tx = tp.tx;
     P.ty = tp.ty;
@@ -470,21 +512,21 @@ void launch_action(lj_context* ctx, const OpDev& op, const double* v, int K, con
     G = grid_for(ctx, op.npts);
   }
   if (ctx->in_noalloc) {
-    P.partials = scratch_region(ctx, W_NSLOTS, (size_t)2 * kPartStride * G);
+    P.partials = scratch_region(ctx, W_NSLOTS, (size_t)2 * kRegPartStride * G);
   } else {
     ensure_small(ctx, G);
     P.partials = ctx->d_partials;
   }
   void* args[] = {&P};
   if (ev) HIPCHK(ctx, hipEventRecord(ev[0], s));
-  if (cooperative || !coresident(ctx, fn, G, dyn)) {
-    HIPCHK(ctx, hipLaunchCooperativeKernel(fn, dim3(G), dim3(persistent_block()), args, (unsigned)dyn, s));
+  if (cooperative || !coresident(ctx, fn, G, dyn, block)) {
+    HIPCHK(ctx, hipLaunchCooperativeKernel(fn, dim3(G), dim3(block), args, (unsigned)dyn, s));
   } else {
-    HIPCHK(ctx, hipLaunchKernel(fn, dim3(G), dim3(persistent_block()), args, (unsigned)dyn, s));
+    HIPCHK(ctx, hipLaunchKernel(fn, dim3(G), dim3(block), args, (unsigned)dyn, s));
   }
   if (ev) HIPCHK(ctx, hipEventRecord(ev[1], s));
   if (!direct_status) HIPCHK(ctx, hipMemcpyAsync(status_dst, ctx->d_status, status_bytes, hipMemcpyDeviceToHost, s));
-  if (tiled) *tiled = tp.ok;
+  if (tiled) *tiled = tp.ok || rp.ok;
 }
 
 // Outcome of a launch whose status has arrived; accumulates the timing
@@ -1301,7 +1343,7 @@ int krylov_impl(lj_context* ctx, const OpDev& op, int p, const double* const* b,
   auto basis = [&]() -> bool {
     if (persistent) {
       for (int attempt = 0; attempt < 2; ++attempt) {
-        const bool coop = attempt > 0 || !coresident(ctx, kfn, KG, 0);
+        const bool coop = attempt > 0 || !coresident(ctx, kfn, KG, 0, persistent_block());
         KA.spin_limit = (!coop && ctx->forced_spin_limit > 0) ? ctx->forced_spin_limit : kGridSpinLimit;
         void* args[] = {&KA};
         if (coop) {
@@ -1502,6 +1544,7 @@ LJ_API int lj_create(lj_context** out, int hip_device) {
     }
     if (const char* g = std::getenv("LJ_GRID")) ctx->grid_override = std::atoi(g);
     if (const char* g = std::getenv("LJ_NO_TILE")) ctx->force_stream = std::atoi(g);
+    if (const char* g = std::getenv("LJ_NO_REG")) ctx->no_reg = std::atoi(g);
     if (const char* g = std::getenv("LJ_COOP")) ctx->force_coop = std::atoi(g);
     if (const char* g = std::getenv("LJ_KRYLOV_PASSES")) ctx->krylov_passes = std::atoi(g);
     if (const char* g = std::getenv("LJ_FORCE_SPIN_LIMIT")) {
@@ -1765,7 +1808,7 @@ LJ_API int lj_phi_action(lj_context* ctx, const lj_operator* J, const double* v,
 // propagation vectors (l = 0: two).
 size_t noalloc_need(const lj_context* ctx, size_t n, int l, const Opts& o) {
   auto r = [](size_t x) { return (x + 31) & ~(size_t)31; };
-  size_t d = 2 * r(n) + r((size_t)2 * kPartStride * ctx->num_cus);
+  size_t d = 2 * r(n) + r((size_t)2 * kRegPartStride * ctx->num_cus);
   if (o.max_substeps > 1 || o.substeps > 1) d += (size_t)(l > 0 ? l + 3 : 2) * r(n);
   return d;
 }
