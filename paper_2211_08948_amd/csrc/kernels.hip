@@ -974,7 +974,7 @@ struct RegShared {
   double coef[kMaxK * kTable];
   double fmax[kMaxK];
   double tot[kRegSlots];
-  double stg[kRegSlots][8];            // per step and value: row sums of the owned waves 2..5, lanes 16-31 / 32-47
+  double stg[kRegSlots][4];            // per step and value: the sums of the owned waves 2..5 (lanes 16-47)
   double xrow[2][2 * kRegWaves][64];   // [parity][2 w: first row of wave w, 2 w + 1: its last row][lane]
   Decision D;
   int commit[kMaxK];
@@ -1093,6 +1093,19 @@ __global__ __launch_bounds__(kRegBlock) void lj_action_reg(ActionParams P) {
 
   // one step of x <- A x on the whole extended tile, A = the folded stencil
   // with diagonal dg - xim
+  // (the interior rows 1..6 are formed while the neighbours' rows are read)
+  auto point = [&](int i, double xs, double xn, double xim) {
+    const double xc = x[i];
+    const double xw = dpp_move<0x138>(xc);  // wave_shr:1 -- lane c - 1
+    const double xe = dpp_move<0x130>(xc);  // wave_shl:1 -- lane c + 1
+    double y;
+    if constexpr (KIND == OP_ALLENCAHN) {
+      y = fw * (xw + xe) + fs * (xs + xn);
+    } else {
+      y = fw * xw + fe * xe + fs * xs + fn * xn;
+    }
+    return fma(dg[i] - xim, xc, y);
+  };
   auto step = [&](double xim) {
     double* xr = &sh.xrow[par][0][0];
     xr[(2 * wv) * 64 + lane] = x[0];
@@ -1101,37 +1114,27 @@ __global__ __launch_bounds__(kRegBlock) void lj_action_reg(ActionParams P) {
     const double above = xr[(2 * ((wv + kRegWaves - 1) % kRegWaves) + 1) * 64 + lane];
     const double below = xr[(2 * ((wv + 1) % kRegWaves)) * 64 + lane];
     par ^= 1;
-    double prev = above;
+    double y[kRegRows];
 #pragma unroll
-    for (int i = 0; i < kRegRows; ++i) {
-      const double xc = x[i];
-      const double xn = (i < kRegRows - 1) ? x[i + 1] : below;
-      const double xw = dpp_move<0x138>(xc);  // wave_shr:1 -- lane c - 1
-      const double xe = dpp_move<0x130>(xc);  // wave_shl:1 -- lane c + 1
-      double y;
-      if constexpr (KIND == OP_ALLENCAHN) {
-        y = fw * (xw + xe) + fs * (prev + xn);
-      } else {
-        y = fw * xw + fe * xe + fs * prev + fn * xn;
-      }
-      x[i] = fma(dg[i] - xim, xc, y);
-      prev = xc;
-    }
+    for (int i = 1; i < kRegRows - 1; ++i) y[i] = point(i, x[i - 1], x[i + 1], xim);
+    y[0] = point(0, above, x[1], xim);
+    y[kRegRows - 1] = point(kRegRows - 1, x[kRegRows - 2], below, xim);
+#pragma unroll
+    for (int i = 0; i < kRegRows; ++i) x[i] = y[i];
   };
   // row sums of one value per owned point (owned waves only): lanes 31 and 47
   // hold the sums of lanes 16-31 and 32-47
   auto stage = [&](int slot, double a) {
     const double t = row_sum(a);
-    if (lane == 31 || lane == 47) sh.stg[slot][(wv - 2) * 2 + (lane >> 4) - 1] = t;
+    const double u = read_lane(t, 31) + read_lane(t, 47);
+    if (lane == 0) sh.stg[slot][wv - 2] = u;
   };
   // block totals of the staged slots -> this barrier's partial-sum area
   auto publish = [&](int nq) {
     __syncthreads();
     double* area = reg_area(P.partials, epoch);
     for (int q = threadIdx.x; q < nq; q += kRegBlock) {
-      double t = 0.0;
-#pragma unroll
-      for (int e = 0; e < 8; ++e) t += sh.stg[q][e];
+      const double t = (sh.stg[q][0] + sh.stg[q][1]) + (sh.stg[q][2] + sh.stg[q][3]);
       store_shared(area + (size_t)q * gridDim.x + blockIdx.x, t);
     }
     return area;
@@ -1287,10 +1290,13 @@ __global__ __launch_bounds__(kRegBlock) void lj_action_reg(ActionParams P) {
           for (int i = 0; i < kRegRows; ++i)
             if (own(i)) Hist[(j - 1) * (kRegTile * kRegTile) + hidx(i)] = x[i];
         }
-        stage((j - 1) * Q, sumsq_own());
+        // ||y||^2 and, for every accumulator (a frozen one adds 0 * y, which
+        // leaves its sum unchanged), the new p_k and ||p_k||^2; the row sums
+        // of all 1 + KM values run side by side
+        double t[1 + KM];
+        t[0] = sumsq_own();
 #pragma unroll
         for (int k = 0; k < KM; ++k) {
-          if (!act0[k]) continue;
           const double dk = read_lane(cfv[k], j - 1);
           double b0 = 0.0, b1 = 0.0;
 #pragma unroll
@@ -1301,7 +1307,24 @@ __global__ __launch_bounds__(kRegBlock) void lj_action_reg(ActionParams P) {
             b0 = fma(t0, t0, b0);
             b1 = fma(t1, t1, b1);
           }
-          stage((j - 1) * Q + 1 + k, b0 + b1);
+          t[1 + k] = b0 + b1;
+        }
+#pragma unroll
+        for (int q = 0; q < 1 + KM; ++q) t[q] += dpp_move<0x111>(t[q]);
+#pragma unroll
+        for (int q = 0; q < 1 + KM; ++q) t[q] += dpp_move<0x112>(t[q]);
+#pragma unroll
+        for (int q = 0; q < 1 + KM; ++q) t[q] += dpp_move<0x114>(t[q]);
+#pragma unroll
+        for (int q = 0; q < 1 + KM; ++q) t[q] += dpp_move<0x118>(t[q]);
+        double u[1 + KM];
+#pragma unroll
+        for (int q = 0; q < 1 + KM; ++q) u[q] = read_lane(t[q], 31) + read_lane(t[q], 47);
+        if (lane == 0) {
+          sh.stg[(j - 1) * Q][wv - 2] = u[0];
+#pragma unroll
+          for (int k = 0; k < KM; ++k)
+            if (k < K) sh.stg[(j - 1) * Q + 1 + k][wv - 2] = u[1 + k];
         }
       }
     }
