@@ -104,6 +104,9 @@ typedef struct {
   int32_t use_proposal;   /* 1: the learned proposal supplies the bound and the substep count
                              (lj_phi_action / lj_phi_vertical); the plain path is the fallback; 0 */
   int32_t reserved;
+  const double* bound_device; /* device: when bound == 0 and this is not NULL, the launches read
+                             lambda_hat from this address in stream order (no power iteration),
+                             e.g. lj_bound_device(ctx) after an lj_step; NULL */
 } lj_options;
 
 /* Per-call statistics (host struct).  For a vertical call entry k describes
@@ -194,6 +197,28 @@ LJ_API int lj_phi_action(lj_context* ctx, const lj_operator* J, const double* v,
 LJ_API int lj_phi_action_noalloc(lj_context* ctx, const lj_operator* J, const double* v, double* w,
                                  int l, double h, double tol, const lj_options* opt,
                                  lj_stats* stats, void* stream);
+
+/* Deferred synchronisation.  A time integrator needs the results of a step
+ * only when it takes the next decision, so steps and actions issued back to
+ * back on one stream need not each wait for the device.  Between
+ * lj_defer_begin and lj_defer_end, lj_step (built-in operators, no substeps
+ * requested, no learned proposal, not LeKry) and lj_phi_action (built-in
+ * operators, no substeps requested, no learned proposal) only enqueue their
+ * launches and return LJ_OK at once; other such calls return LJ_EINVAL.
+ * Their stats are filled by lj_defer_end, so the caller's stats arrays must
+ * stay valid until then.  lj_defer_end synchronises `stream` once and reads
+ * every deferred expansion's status; if one was rejected (or a launch
+ * aborted), that call and every deferred call after it are redone
+ * synchronously, in call order, with substeps where needed -- so the inputs
+ * of deferred calls (J->state, v) must not be overwritten by later deferred
+ * calls.  At most 64 launches (about 8 steps) may be deferred at once.
+ * Returns LJ_ENOTCONV if a redone expansion still failed. */
+LJ_API int lj_defer_begin(lj_context* ctx);
+LJ_API int lj_defer_end(lj_context* ctx, void* stream);
+/* Device address where lj_step leaves the spectral bound of its step (its
+ * first action's power iteration) for its other actions; valid in stream
+ * order until the next lj_step on the context. */
+LJ_API const double* lj_bound_device(const lj_context* ctx);
 
 /* Vertical form (Sec. 4): w[k] = phi_{l[k]}(a[k] h J) v for k < K <= LJ_MAX_K,
  * all on one Newton basis; l, a, w are host arrays of K entries (w[k] device

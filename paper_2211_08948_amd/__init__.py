@@ -109,6 +109,8 @@ def lj_default_options(**overrides) -> lj_options:
     for k, v in overrides.items():
         if k == "pi_start":
             v = C.c_void_p(v.data_ptr()) if v is not None else None
+        if k == "bound_device" and v is not None and not isinstance(v, int):
+            v = v.data_ptr()  # a float64 device tensor holding the bound
         setattr(o, k, v)
     return o
 
@@ -453,6 +455,67 @@ def lj_step(ctx: Context, scheme: str, J: Operator, h: float, tol: float, u_out,
                           _stream_ptr(stream))
     ctx._check(rc)
     return rc, [stats[i].as_dict() for i in range(ncalls.value)]
+
+
+def lj_bound_device(ctx: Context) -> int:
+    """Device address of the bound the last lj_step left for its actions."""
+    return ctx._lib.lj_bound_device(ctx.handle) or 0
+
+
+class Deferred:
+    """Deferred synchronisation (lj_defer_begin / lj_defer_end): steps and
+    actions issued through it are only enqueued; leaving the with-block
+    synchronises once (lj_defer_end) and fills `results`, one (rc, stats) per
+    call in the form lj_step / lj_phi_action return.  Inputs of the calls must
+    not be overwritten by later calls of the same block."""
+
+    def __init__(self, ctx: Context, stream=None):
+        self.ctx = ctx
+        self.stream = stream
+        self._calls = []  # (kind, stats array, count) plus the objects the library points at
+        self.results = None
+        self.rc = None
+
+    def __enter__(self):
+        self.ctx._check(self.ctx._lib.lj_defer_begin(self.ctx.handle), False)
+        return self
+
+    def step(self, scheme: str, J: Operator, h: float, tol: float, u_out, err=None, opt: lj_options | None = None):
+        op = J.c_struct()
+        stats = (lj_stats * 4)()
+        ncalls = C.c_int()
+        rc = self.ctx._lib.lj_step(self.ctx.handle, SCHEMES[scheme], C.byref(op), float(h), float(tol),
+                                   _tensor_ptr(u_out, J.n, "u_out"),
+                                   _tensor_ptr(err, J.n, "err") if err is not None else None,
+                                   C.byref(opt) if opt is not None else None, stats, 4, C.byref(ncalls),
+                                   _stream_ptr(self.stream))
+        self.ctx._check(rc)
+        self._calls.append(("step", stats, ncalls, (op, opt, J, u_out, err)))
+        return len(self._calls) - 1
+
+    def phi_action(self, J: Operator, v, w, l: int, h: float, tol: float, opt: lj_options | None = None):
+        op = J.c_struct()
+        st = lj_stats()
+        rc = self.ctx._lib.lj_phi_action(self.ctx.handle, C.byref(op), _tensor_ptr(v, J.n, "v"),
+                                         _tensor_ptr(w, J.n, "w"), int(l), float(h), float(tol),
+                                         C.byref(opt) if opt is not None else None, C.byref(st),
+                                         _stream_ptr(self.stream))
+        self.ctx._check(rc)
+        self._calls.append(("action", st, None, (op, opt, J, v, w)))
+        return len(self._calls) - 1
+
+    def __exit__(self, et, ev, tb):
+        rc = self.ctx._lib.lj_defer_end(self.ctx.handle, _stream_ptr(self.stream))
+        self.rc = rc
+        if et is None:
+            self.ctx._check(rc)
+        self.results = []
+        for kind, st, count, _ in self._calls:
+            if kind == "step":
+                self.results.append((rc, [st[i].as_dict() for i in range(count.value)]))
+            else:
+                self.results.append((rc, st.as_dict(1)))
+        return False
 
 
 def lj_integrate(ctx: Context, scheme: str, J: Operator, T: float, dt0: float, tol: float, leja_tol: float, u_out,

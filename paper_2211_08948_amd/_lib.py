@@ -58,6 +58,7 @@ class lj_options(C.Structure):
         ("hump_max", C.c_double), ("max_substeps", C.c_int32), ("relative_tol", C.c_int32),
         ("bound", C.c_double), ("substeps", C.c_int32), ("power_seed", C.c_uint64),
         ("pi_start", C.c_void_p), ("use_proposal", C.c_int32), ("reserved", C.c_int32),
+        ("bound_device", C.c_void_p),
     ]
 
 
@@ -143,6 +144,9 @@ _PROTOS = {
                                C.POINTER(lj_options), C.POINTER(lj_stats), C.c_int, C.POINTER(C.c_int), _P]),
     "lj_phi_action": (C.c_int, [_P, C.POINTER(lj_operator), _P, _P, C.c_int, C.c_double, C.c_double,
                                 C.POINTER(lj_options), C.POINTER(lj_stats), _P]),
+    "lj_defer_begin": (C.c_int, [_P]),
+    "lj_defer_end": (C.c_int, [_P, _P]),
+    "lj_bound_device": (C.c_void_p, [_P]),
     "lj_phi_action_noalloc": (C.c_int, [_P, C.POINTER(lj_operator), _P, _P, C.c_int, C.c_double, C.c_double,
                                         C.POINTER(lj_options), C.POINTER(lj_stats), _P]),
     "lj_phi_vertical": (C.c_int, [_P, C.POINTER(lj_operator), _P, C.c_int, C.POINTER(C.c_int),

@@ -51,6 +51,7 @@ enum Slot {
 constexpr size_t kStaticLdsReserve = 40 * 1024;
 constexpr int kQ_batch = 1 + kMaxK;  // team partial sums per reduction
 constexpr int kAsyncSlots = 8;       // most action launches of one step
+constexpr int kPoolSlots = 64;       // status heads of launches not yet read (one step, or a deferral)
 constexpr int kTimingPairs = 1024;   // event pairs of the timing pool
 
 // Device memory of the allocation-free entry point (lj_phi_action_noalloc):
@@ -106,7 +107,7 @@ struct lj_context {
   std::unordered_map<const void*, size_t> dyn_lds;  // dynamic LDS limit set per kernel
   // launches of a step enqueued back to back: their status heads, event pairs
   // and the bound the first one leaves for the others
-  LejaStatus* h_pool = nullptr;  // pinned, kAsyncSlots entries
+  LejaStatus* h_pool = nullptr;  // pinned, kPoolSlots entries
   double* d_bound = nullptr;
   double* d_sumsq = nullptr;   // 2 * kSumsqBlocks partials + 2 totals
   double* h_sumsq = nullptr;   // pinned, 2 totals
@@ -134,6 +135,11 @@ struct lj_context {
   double* d_kpart = nullptr;   // kKryBlocksMax * (kKryMaxDim + 1)
   double* d_kH = nullptr;      // (kKryMaxDim + 1) * kKryMaxDim, then 2 scalars
   double* h_kH = nullptr;      // pinned copy of d_kH
+  // deferred synchronisation (lj_defer_begin / lj_defer_end): the calls
+  // enqueued since lj_defer_begin and the next free slot of the status pool
+  bool deferring = false;
+  int defer_next = 0;
+  struct DeferState* defer = nullptr;
   // allocation-free calls: this device's scratch array (device address), and
   // while such a call runs, where its workspace vectors and partial sums lie
   // in it (in doubles from its start; index W_NSLOTS: the partial sums)
@@ -211,6 +217,7 @@ struct Opts {
   int substeps;
   uint64_t seed;
   const double* pi_start;
+  const double* bound_device;  // the bound read by the launch from device memory (when bound == 0)
 };
 
 Opts resolve(lj_context* ctx, const lj_options* o) {
@@ -218,7 +225,7 @@ Opts resolve(lj_context* ctx, const lj_options* o) {
   lj_default_options(&d);
   if (!o) o = &d;
   Opts r{o->use_proposal, o->safety, o->power_iters, o->max_points, o->hump_max, o->max_substeps,
-         o->relative_tol, o->bound, o->substeps, o->power_seed, o->pi_start};
+         o->relative_tol, o->bound, o->substeps, o->power_seed, o->pi_start, o->bound > 0.0 ? nullptr : o->bound_device};
   if (!(r.safety > 0.0) || !std::isfinite(r.safety)) invalid(ctx, "options: safety must be > 0");
   if (r.power_iters < 1 || r.power_iters > 100000) invalid(ctx, "options: power_iters out of range");
   if (r.max_points < 1 || r.max_points > kMaxPoints) invalid(ctx, "options: max_points must be in [1, 100]");
@@ -409,6 +416,39 @@ struct ActOut {
   int power_iters;
   double lam, c, gamma, vnorm;
 };
+
+// A launch whose status head is read later: its slot in the pinned pool.
+struct PendingLaunch {
+  int slot;
+  int K;
+  bool tiled;
+  hipEvent_t* ev;
+};
+
+// A call enqueued in a deferral, with what lj_defer_end needs to complete
+// it: its launches' status slots, and its arguments for a synchronous redo.
+struct DeferredCall {
+  bool is_step = false;
+  int scheme = 0;  // step
+  OpDev op{};
+  Opts o{};
+  double h = 0.0, tol = 0.0;
+  double* u_out = nullptr;  // step
+  double* err = nullptr;    // step
+  const double* v = nullptr;  // action
+  double* w = nullptr;        // action
+  int l = 0;                  // action
+  lj_stats* stats = nullptr;  // the caller's, filled by lj_defer_end
+  std::vector<PendingLaunch> launches;
+};
+
+}  // namespace
+
+struct DeferState {
+  std::vector<DeferredCall> calls;
+};
+
+namespace {
 
 // Where the bound of a launch comes from and goes to (device pointers, or none).
 struct BoundLink {
@@ -751,9 +791,11 @@ ActOut run_action(lj_context* ctx, const OpDev& op, const double* v, int K, cons
                   double tol, hipStream_t s) {
   if (is_user(op)) return run_action_user(ctx, op, v, K, l, s_k, lam_host, seed, start, outs, o, tol, s);
   bool tiled = false;
+  BoundLink link;
+  if (!(lam_host > 0.0) && o.bound_device) link.src = o.bound_device;
   for (int attempt = 0; attempt < 2; ++attempt) {
     hipEvent_t* ev = timing_pair(ctx);
-    launch_action(ctx, op, v, K, l, s_k, lam_host, seed, start, outs, o, tol, s, BoundLink{}, ctx->h_status,
+    launch_action(ctx, op, v, K, l, s_k, lam_host, seed, start, outs, o, tol, s, link, ctx->h_status,
                   offsetof(LejaStatus, trace), ev, &tiled, attempt == 1, true);
     HIPCHK(ctx, hipStreamSynchronize(s));
     const ActOut r = finish_action(ctx, op, *ctx->h_status, ev, tiled);
@@ -871,6 +913,15 @@ bool substepped(lj_context* ctx, const OpDev& op, const double* v, int l, double
   return false;
 }
 
+// A bound the caller keeps in device memory, read on the host (synchronises).
+double bound_to_host(lj_context* ctx, const double* dev, hipStream_t s) {
+  double lam = 0.0;
+  HIPCHK(ctx, hipMemcpyAsync(&lam, dev, sizeof(double), hipMemcpyDeviceToHost, s));
+  HIPCHK(ctx, hipStreamSynchronize(s));
+  if (!(lam > 0.0) || !std::isfinite(lam)) invalid(ctx, "options: bound_device holds no positive finite bound");
+  return lam;
+}
+
 // Vertical action (the core of lj_phi_action / lj_phi_vertical / lj_step).
 int vertical_impl(lj_context* ctx, const OpDev& op, const double* v, int K, const int* l, const double* a,
                   double h, double tol, double* const* w, const Opts& o, lj_stats* st, hipStream_t s) {
@@ -881,6 +932,7 @@ int vertical_impl(lj_context* ctx, const OpDev& op, const double* v, int K, cons
   }
   double lam = o.bound > 0.0 ? o.bound : 0.0;
   int s0 = (o.substeps > 1) ? o.substeps : 1;
+  if (!(lam > 0.0) && o.bound_device && (s0 > 1 || is_user(op))) lam = bound_to_host(ctx, o.bound_device, s);
   std::vector<int> pending;
   if (s0 == 1) {
     double sk[kMaxK];
@@ -1473,6 +1525,7 @@ LJ_API void lj_default_options(lj_options* opt) {
   opt->substeps = 0;
   opt->power_seed = 0x5EED;
   opt->pi_start = nullptr;
+  opt->bound_device = nullptr;
 }
 
 LJ_API const char* lj_last_error(const lj_context* ctx) {
@@ -1525,7 +1578,7 @@ LJ_API int lj_create(lj_context** out, int hip_device) {
     HIPCHK(ctx, hipHostMalloc(&ctx->h_status, sizeof(LejaStatus), hipHostMallocCoherent));
     HIPCHK(ctx, hipHostMalloc(&ctx->h_coef, kMaxK * kTable * sizeof(double), hipHostMallocDefault));
     // fine-grained: the action kernels write their status headers here directly
-    HIPCHK(ctx, hipHostMalloc(&ctx->h_pool, kAsyncSlots * sizeof(LejaStatus), hipHostMallocCoherent));
+    HIPCHK(ctx, hipHostMalloc(&ctx->h_pool, kPoolSlots * sizeof(LejaStatus), hipHostMallocCoherent));
     HIPCHK(ctx, hipMalloc(&ctx->d_bound, sizeof(double)));
     HIPCHK(ctx, hipMalloc(&ctx->d_sumsq, (2 * kSumsqBlocks + 2) * sizeof(double)));
     HIPCHK(ctx, hipHostMalloc(&ctx->h_sumsq, 2 * sizeof(double), hipHostMallocDefault));
@@ -1602,6 +1655,7 @@ LJ_API void lj_destroy(lj_context* ctx) {
   if (ctx->d_kpart) (void)hipFree(ctx->d_kpart);
   if (ctx->d_kH) (void)hipFree(ctx->d_kH);
   if (ctx->h_kH) (void)hipHostFree(ctx->h_kH);
+  delete ctx->defer;
   delete ctx;
 }
 
@@ -1795,12 +1849,102 @@ LJ_API int lj_phi_vertical(lj_context* ctx, const lj_operator* J, const double* 
   });
 }
 
+int step_impl(lj_context* ctx, int scheme, const OpDev& op, Opts o, double h, double tol, double* u_out, double* err,
+              lj_stats* stats, hipStream_t s);
+bool collect_async(lj_context* ctx, const OpDev& op, const std::vector<PendingLaunch>& pend,
+                   std::vector<lj_stats>& log, double& lam_found, int& pit);
+
 LJ_API int lj_phi_action(lj_context* ctx, const lj_operator* J, const double* v, double* w, int l, double h,
                          double tol, const lj_options* opt, lj_stats* stats, void* stream) {
   const double a = 1.0;
   double* ws[1] = {w};
+  if (ctx && ctx->deferring) {
+    return guarded(ctx, [&]() {
+      const OpDev op = make_op(ctx, J);
+      const Opts o = resolve(ctx, opt);
+      check_action_args(ctx, op, v, 1, &l, &a, h, tol, ws);
+      if (o.pi_start) check_vec(ctx, op, o.pi_start, "pi_start");
+      if (o.use_proposal || o.substeps > 1)
+        invalid(ctx, "an action with substeps or the learned proposal cannot be deferred: call lj_defer_end first");
+      const int slot = ctx->defer_next;
+      if (slot + 1 > kPoolSlots) invalid(ctx, "too many deferred launches: call lj_defer_end");
+      if (ctx->timing && ctx->tev_next + 1 > kTimingPairs) timing_flush(ctx);
+      const hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+      BoundLink link;
+      if (!(o.bound > 0.0) && o.bound_device) link.src = o.bound_device;
+      const double sk = h;
+      bool tiled = false;
+      hipEvent_t* ev = timing_pair(ctx);
+      launch_action(ctx, op, v, 1, &l, &sk, o.bound > 0.0 ? o.bound : 0.0, o.seed, o.pi_start, ws, o, tol, s, link,
+                    &ctx->h_pool[slot], offsetof(LejaStatus, trace), ev, &tiled, false, true);
+      DeferredCall dc;
+      dc.op = op;
+      dc.o = o;
+      dc.h = h;
+      dc.tol = tol;
+      dc.v = v;
+      dc.w = w;
+      dc.l = l;
+      dc.stats = stats;
+      dc.launches.push_back({slot, 1, tiled, ev});
+      ctx->defer->calls.push_back(dc);
+      ctx->defer_next = slot + 1;
+      return LJ_OK;
+    });
+  }
   return lj_phi_vertical(ctx, J, v, 1, &l, &a, h, tol, ws, opt, stats, stream);
 }
+
+LJ_API int lj_defer_begin(lj_context* ctx) {
+  return guarded(ctx, [&]() {
+    if (ctx->deferring) invalid(ctx, "lj_defer_begin: a deferral is already open");
+    if (!ctx->defer) ctx->defer = new DeferState();
+    ctx->defer->calls.clear();
+    ctx->defer_next = 0;
+    ctx->deferring = true;
+    return LJ_OK;
+  });
+}
+
+LJ_API int lj_defer_end(lj_context* ctx, void* stream) {
+  return guarded(ctx, [&]() {
+    if (!ctx->deferring) invalid(ctx, "lj_defer_end: no deferral is open");
+    ctx->deferring = false;
+    std::vector<DeferredCall> calls;
+    calls.swap(ctx->defer->calls);
+    ctx->defer_next = 0;
+    const hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    HIPCHK(ctx, hipStreamSynchronize(s));
+    bool ok = true;
+    bool redo = false;  // from the first failed call on, every call is redone in order
+    for (DeferredCall& dc : calls) {
+      if (!redo) {
+        std::vector<lj_stats> log;
+        double lam_found = dc.o.bound;
+        int pit = 0;
+        if (collect_async(ctx, dc.op, dc.launches, log, lam_found, pit)) {
+          if (dc.stats)
+            for (size_t i = 0; i < log.size(); ++i) dc.stats[i] = log[i];
+          continue;
+        }
+        redo = true;
+      }
+      int rc;
+      if (dc.is_step) {
+        rc = step_impl(ctx, dc.scheme, dc.op, dc.o, dc.h, dc.tol, dc.u_out, dc.err, dc.stats, s);
+      } else {
+        lj_stats local;
+        const double a = 1.0;
+        double* ws[1] = {dc.w};
+        rc = vertical_impl(ctx, dc.op, dc.v, 1, &dc.l, &a, dc.h, dc.tol, ws, dc.o, dc.stats ? dc.stats : &local, s);
+      }
+      if (rc != LJ_OK) ok = false;
+    }
+    return ok ? LJ_OK : LJ_ENOTCONV;
+  });
+}
+
+LJ_API const double* lj_bound_device(const lj_context* ctx) { return ctx ? ctx->d_bound : nullptr; }
 
 // Doubles of scratch an allocation-free phi_l action on n values needs at
 // most: the two Newton-basis vectors, the partial sums of the largest grid,
@@ -1842,6 +1986,48 @@ LJ_API int lj_phi_action_noalloc(lj_context* ctx, const lj_operator* J, const do
     lj_stats* st = stats ? stats : &local;
     return vertical_impl(ctx, op, v, 1, &l, &a, h, tol, ws, o, st, reinterpret_cast<hipStream_t>(stream));
   });
+}
+
+// Statistics of the launches of an asynchronous pass (their status heads in
+// the pinned pool): one lj_stats per launch into `log`; lam_found / pit take
+// the first launch's bound and power products.  Returns false if an
+// expansion was rejected or a launch aborted (the caller redoes the work
+// synchronously).
+bool collect_async(lj_context* ctx, const OpDev& op, const std::vector<PendingLaunch>& pend,
+                   std::vector<lj_stats>& log, double& lam_found, int& pit) {
+  bool all = true;
+  for (size_t i = 0; i < pend.size(); ++i) {
+    const ActOut r = finish_action(ctx, op, ctx->h_pool[pend[i].slot], pend[i].ev, pend[i].tiled);
+    if (r.aborted) all = false;
+    lj_stats st;
+    std::memset(&st, 0, sizeof(st));
+    for (int k = 0; k < LJ_MAX_K; ++k) {
+      st.m_star[k] = -1;
+      st.substeps[k] = 1;
+    }
+    st.iters_total = r.iters;
+    st.power_iters = r.power_iters;
+    st.bound = r.lam;
+    st.c = r.c;
+    st.gamma = r.gamma;
+    st.converged = 1;
+    for (int k = 0; k < pend[i].K; ++k) {
+      if (r.state[k] == ACC_CONVERGED) {
+        st.m_star[k] = r.m_star[k];
+        st.err_est[k] = r.err[k];
+      } else {
+        st.converged = 0;
+        st.rejections = 1;
+        all = false;
+      }
+    }
+    if (i == 0 && !r.aborted) {  // an aborted launch's bound is not to be trusted
+      lam_found = r.lam;
+      pit = r.power_iters;
+    }
+    log.push_back(st);
+  }
+  return all;
 }
 
 // One step of `scheme` from u = op.state (arguments validated by the caller):
@@ -2123,21 +2309,22 @@ int step_impl(lj_context* ctx, int scheme, const OpDev& op, Opts o, double h, do
   // ---- first try: every launch of the step enqueued back to back.  The
   // first action runs the power iteration (unless a bound is given) and
   // leaves the bound on the device for the others; statuses are read once
-  // at the end.  If some expansion was rejected, the step is redone below
-  // synchronously, with substeps, on the bound found.
+  // at the end (or, in a deferral, by lj_defer_end).  If some expansion was
+  // rejected, the step is redone below synchronously, with substeps, on the
+  // bound found.
   const bool try_async = o.substeps <= 1 && !o.use_proposal && !is_user(op) && scheme != LJ_EPIRK4S3_LEKRY &&
                          scheme != LJ_EPIRK4S3A_LEKRY;
+  if (ctx->deferring && !try_async)
+    invalid(ctx, "this step cannot be deferred (substeps, the learned proposal, a user operator or LeKry): "
+                 "call lj_defer_end first");
   double lam_found = o.bound;
   if (try_async) {
-    struct Pending {
-      int K;
-      bool tiled;
-      hipEvent_t* ev;
-    };
+    const int base = ctx->deferring ? ctx->defer_next : 0;
+    if (base + kAsyncSlots > kPoolSlots) invalid(ctx, "too many deferred launches: call lj_defer_end");
     // pairs for every launch of the step up front, so a pool flush cannot
     // fall between a launch and its finish
     if (ctx->timing && ctx->tev_next + kAsyncSlots > kTimingPairs) timing_flush(ctx);
-    std::vector<Pending> pend;
+    std::vector<PendingLaunch> pend;
     auto act_async = [&](const double* vec, int K, const int* ls, const double* as, double* const* outs) {
       const int i = (int)pend.size();
       if (i >= kAsyncSlots) invalid(ctx, "internal: too many launches in one step");
@@ -2147,6 +2334,8 @@ int step_impl(lj_context* ctx, int scheme, const OpDev& op, Opts o, double h, do
       double lam_host = 0.0;
       if (o.bound > 0.0) {
         lam_host = o.bound;
+      } else if (o.bound_device) {
+        link.src = o.bound_device;
       } else if (i == 0) {
         link.dst = ctx->d_bound;
       } else {
@@ -2154,45 +2343,29 @@ int step_impl(lj_context* ctx, int scheme, const OpDev& op, Opts o, double h, do
       }
       bool tiled = false;
       hipEvent_t* ev = timing_pair(ctx);
-      launch_action(ctx, op, vec, K, ls, sk, lam_host, o.seed, o.pi_start, outs, o, tol, s, link, &ctx->h_pool[i],
-                    offsetof(LejaStatus, trace), ev, &tiled, false, true);
-      pend.push_back({K, tiled, ev});
+      launch_action(ctx, op, vec, K, ls, sk, lam_host, o.seed, o.pi_start, outs, o, tol, s, link,
+                    &ctx->h_pool[base + i], offsetof(LejaStatus, trace), ev, &tiled, false, true);
+      pend.push_back({base + i, K, tiled, ev});
     };
     scheme_steps(act_async);
-    HIPCHK(ctx, hipStreamSynchronize(s));
-    bool all = true;
-    for (size_t i = 0; i < pend.size(); ++i) {
-      const ActOut r = finish_action(ctx, op, ctx->h_pool[i], pend[i].ev, pend[i].tiled);
-      if (r.aborted) all = false;
-      lj_stats st;
-      std::memset(&st, 0, sizeof(st));
-      for (int k = 0; k < LJ_MAX_K; ++k) {
-        st.m_star[k] = -1;
-        st.substeps[k] = 1;
-      }
-      st.iters_total = r.iters;
-      st.power_iters = r.power_iters;
-      st.bound = r.lam;
-      st.c = r.c;
-      st.gamma = r.gamma;
-      st.converged = 1;
-      for (int k = 0; k < pend[i].K; ++k) {
-        if (r.state[k] == ACC_CONVERGED) {
-          st.m_star[k] = r.m_star[k];
-          st.err_est[k] = r.err[k];
-        } else {
-          st.converged = 0;
-          st.rejections = 1;
-          all = false;
-        }
-      }
-      if (i == 0 && !r.aborted) {  // an aborted launch's bound is not to be trusted
-        lam_found = r.lam;
-        pit = r.power_iters;
-      }
-      log.push_back(st);
+    if (ctx->deferring) {
+      DeferredCall dc;
+      dc.is_step = true;
+      dc.scheme = scheme;
+      dc.op = op;
+      dc.o = o;
+      dc.h = h;
+      dc.tol = tol;
+      dc.u_out = u_out;
+      dc.err = err;
+      dc.stats = stats;
+      dc.launches = pend;
+      ctx->defer->calls.push_back(dc);
+      ctx->defer_next = base + (int)pend.size();
+      return LJ_OK;
     }
-    if (all) {
+    HIPCHK(ctx, hipStreamSynchronize(s));
+    if (collect_async(ctx, op, pend, log, lam_found, pit)) {
       if (stats)
         for (size_t i = 0; i < log.size(); ++i) stats[i] = log[i];
       return LJ_OK;
@@ -2201,7 +2374,9 @@ int step_impl(lj_context* ctx, int scheme, const OpDev& op, Opts o, double h, do
     o.bound = lam_found;
   }
   // ---- the step, synchronously: one spectral bound for the whole step
-  if (!(o.bound > 0.0)) {
+  if (!(o.bound > 0.0) && o.bound_device) {
+    o.bound = bound_to_host(ctx, o.bound_device, s);
+  } else if (!(o.bound > 0.0)) {
     o.bound = run_bound(ctx, op, o, o.power_iters, o.seed, o.pi_start, s);
     pit = o.power_iters;
   }
