@@ -105,6 +105,35 @@ __device__ void dd_init(DivDiff& D, int K, const int* l, const double* s, int n,
   }
 }
 
+// dd_init with the phi values computed by every thread of the block (one
+// (accumulator, node) pair per thread and round, staged in coef), then taken
+// by the wave that owns the accumulator's table: the same values, in a
+// fraction of the time one wave needs for all of them.  Called by every
+// thread; ends with a block barrier.
+__device__ void dd_init_par(DivDiff& D, int K, const int* l, const double* s, int n, double c, double gamma,
+                            const double* xi, double* coef, double* fmax_out) {
+#pragma clang fp contract(off)
+  for (int t = threadIdx.x; t < K * kTable; t += blockDim.x) {
+    const int k = t / kTable, j = t - k * kTable;
+    if (j < n) coef[t] = phi_dev(l[k], s[k] * (c + gamma * xi[j]));
+  }
+  __syncthreads();
+  const int wid = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
+  D.order = 0;
+  D.n = n;
+  D.d0 = 0.0;
+  D.d1 = 0.0;
+  if (wid < K) {
+    const int j0 = lane, j1 = lane + 64;
+    if (j0 < n) D.d0 = coef[wid * kTable + j0];
+    if (j1 < n && j1 < kTable) D.d1 = coef[wid * kTable + j1];
+    const double m = wave_max(fmax(fabs(D.d0), fabs(D.d1)));
+    if (lane == 0) fmax_out[wid] = m;
+  }
+  __syncthreads();
+}
+
 // Orders up to min(upto, n - 1); writes the entries that became final.
 __device__ void dd_advance(DivDiff& D, int K, int upto, const double* xi, double* coef) {
 #pragma clang fp contract(off)
@@ -1173,6 +1202,10 @@ __global__ __launch_bounds__(kRegBlock) void lj_action_reg(ActionParams P) {
   // ---- (1) spectral bound: up to 16 products between barriers, normalised per barrier
   double lam = (P.lam_src != nullptr && !P.do_power) ? *P.lam_src : P.lam_in;
   int pit = 0;
+  if (!P.do_power && K > 0) {  // y_0 = v: the loads fly while the bound and the table are formed
+#pragma unroll
+    for (int i = 0; i < kRegRows; ++i) x[i] = P.v[(size_t)grow(i) * nx + gxc];
+  }
   if (P.do_power) {
 #pragma unroll
     for (int i = 0; i < kRegRows; ++i) {
@@ -1235,12 +1268,15 @@ __global__ __launch_bounds__(kRegBlock) void lj_action_reg(ActionParams P) {
   for (int i = 0; i < kRegRows; ++i) dg[i] = (dg[i] - c) * rgamma;
 
   // ---- (2) divided differences up to the first super-step's last term (the
-  // rest while barriers are pending), and y_0 = v on the extended tile
+  // rest while barriers are pending), and y_0 = v on the extended tile (a
+  // launch without power iteration issued v's loads at its start)
   __syncthreads();
-  DivDiff dd;
-  dd_init(dd, K, P.l, P.s, P.max_points + 1, c, gamma, sh.xi, sh.coef, sh.fmax);
+  if (P.do_power) {
 #pragma unroll
-  for (int i = 0; i < kRegRows; ++i) x[i] = P.v[(size_t)grow(i) * nx + gxc];
+    for (int i = 0; i < kRegRows; ++i) x[i] = P.v[(size_t)grow(i) * nx + gxc];
+  }
+  DivDiff dd;
+  dd_init_par(dd, K, P.l, P.s, P.max_points + 1, c, gamma, sh.xi, sh.coef, sh.fmax);
   dd_advance(dd, K, kRegS, sh.xi, sh.coef);
   __syncthreads();
   tick(kProfDivdiff);
