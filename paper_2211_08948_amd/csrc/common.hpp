@@ -33,6 +33,7 @@ constexpr int kBarrierWords = 32 * 19;  // words of one grid-barrier state (zero
 constexpr int kPartStride = 48;         // partial sums per block and barrier slot
 constexpr int kRegPartStride = 96;      // the same for the register-tiled kernel (16 steps x (1 + K) + 1)
 constexpr int kMaxSuper = 8;            // Newton steps per barrier in the tiled kernel (max)
+constexpr int kRegSnap = 5;             // accumulator snapshots before a predicted stop (several-tile kernel)
 
 // Operator as the kernels see it: coefficients plus precomputed reciprocals.
 struct OpDev {
@@ -115,6 +116,13 @@ struct ActionParams {
   // tiling of the LDS-resident kernel
   int tx, ty, ntx, nty;   // tile size and tiles per axis (gridDim = ntx * nty)
   int lds_h;              // offset (doubles) of the step history in dynamic LDS
+  // several tiles per block (register-tiled kernel on large grids): a third
+  // exchange vector, a second buffer per accumulator (committed and
+  // speculative values alternate between it and the output), and K x kRegSnap
+  // vectors of accumulator values at the steps before a super-step's last
+  double* ybuf2;
+  double* pw[kMaxK];
+  double* snap;
 };
 
 // ---- batching form ---------------------------------------------------------

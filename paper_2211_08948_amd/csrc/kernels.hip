@@ -200,6 +200,7 @@ struct Decision {
   int iters;
   int accum_iters;
   int next;  // predicted steps to the last stop (a length for the next super-step)
+  int next_local;  // the same from the decay over the super-step's last four steps
 };
 
 __device__ __forceinline__ void decision_init(Decision& D, int K, double nv, double hump_max, const double* fmaxk) {
@@ -207,6 +208,7 @@ __device__ __forceinline__ void decision_init(Decision& D, int K, double nv, dou
   D.iters = 0;
   D.accum_iters = 0;
   D.next = kMaxPoints;
+  D.next_local = kMaxPoints;
 #pragma unroll
   for (int k = 0; k < kMaxK; ++k) {
     D.st[k] = (k < K) ? ACC_RUNNING : ACC_CONVERGED;
@@ -286,7 +288,11 @@ __device__ void replay_decisions(Decision& D, int K, int m0, int steps, int Q, c
   // of the next batch of speculative steps depends on it, never a decision.
   // (single precision suffices for a length; the same inputs give the same
   // length in every block)
-  int need = 0;
+  // The decay usually steepens as the expansion converges, so the rate over
+  // the last four steps alone often predicts a shorter (and closer)
+  // remainder; the kernel for which an overshoot costs more than a short
+  // extra super-step (several tiles per block) takes the smaller of the two.
+  int need = 0, need_loc = 0;
   {
     float lq = 0.0f;
     if (run0 && j < steps && oc == ACC_RUNNING) {
@@ -295,19 +301,28 @@ __device__ void replay_decisions(Decision& D, int K, int m0, int steps, int Q, c
     }
     const float l_first = lq;  // lanes k < 4 hold step m0 + 1 of accumulator k themselves
     const float l_last = __shfl(lq, 4 * max(steps - 1, 0) + k, 64);
+    const int w = min(4, steps - 1);
+    const float l_mid = __shfl(lq, 4 * max(steps - 1 - w, 0) + k, 64);
+    auto extrapolate = [&](float rate) {
+      const int n = (rate > 0.0f && l_last < 64.0f * rate) ? (int)ceilf(l_last / rate) + 1 : kMaxPoints;
+      return max(n, 1);
+    };
     if (lane < kMaxK && still) {
-      const float rate = (steps > 1) ? (l_first - l_last) / (float)(steps - 1) : 0.0f;
-      need = (rate > 0.0f && l_last < 64.0f * rate) ? (int)ceilf(l_last / rate) + 1 : kMaxPoints;
-      need = max(need, 1);
+      need = extrapolate((steps > 1) ? (l_first - l_last) / (float)(steps - 1) : 0.0f);
+      need_loc = extrapolate((w > 0) ? (l_mid - l_last) / (float)w : 0.0f);
     }
   }
   const int need_all = max(max(__builtin_amdgcn_readlane(need, 0), __builtin_amdgcn_readlane(need, 1)),
                            max(__builtin_amdgcn_readlane(need, 2), __builtin_amdgcn_readlane(need, 3)));
+  const int need_loc_all =
+      max(max(__builtin_amdgcn_readlane(need_loc, 0), __builtin_amdgcn_readlane(need_loc, 1)),
+          max(__builtin_amdgcn_readlane(need_loc, 2), __builtin_amdgcn_readlane(need_loc, 3)));
   if (lane == 0) {
     D.n_active = __builtin_popcountll(alive);
     if (cmax > 0) D.iters = m0 + cmax;
     D.accum_iters += c0 + c1 + c2 + c3;
     D.next = need_all;
+    D.next_local = need_loc_all;
   }
   if (trace != nullptr) {
     for (int t = lane; t < cmax * kQ; t += 64) {
@@ -1422,6 +1437,485 @@ __global__ __launch_bounds__(kRegBlock) void lj_action_reg(ActionParams P) {
   grid_exit(P.barrier);
 }
 
+// ===========================================================================
+// The register-tiled kernel on grids of more 32 x 32 tiles than CUs (the grid
+// a multiple of 32 in both directions).  Each block owns a contiguous range
+// of tiles and, per super-step, takes every one of them through the same up
+// to 16 steps in turn: load the extended tile (from the previous super-step's
+// exchange vector) and the state, step in registers exactly as the one-tile
+// kernel does, store the owned points.  Because a block may still read the
+// previous exchange vector while a faster one writes the next, three of them
+// rotate.  The committed value of accumulator k lives in one of two buffers
+// (the output, or its workspace) and each super-step writes the speculative
+// value into the other: when k ran through the super-step the two swap
+// roles.  When it stopped inside, the block runs the super-step again from
+// its input (still intact: it is two vectors behind the next write) up to the
+// last such stop and adds to the committed value the terms up to each
+// accumulator's own stop index, in the forward order -- the same values the
+// one-tile kernel takes from its LDS history, without writing a history.
+// When the super-step's length comes from the predicted stop, the
+// accumulators' values at its last kRegSnap steps but one are also stored:
+// a stop there (the likely case) is a copy of the snapshot instead.
+// Norm partials are summed over the block's tiles in tile order.
+// ===========================================================================
+template <int KIND, int KM>
+__global__ __launch_bounds__(kRegBlock) void lj_action_regm(ActionParams P) {
+  static_assert(KIND == OP_ADVDIFF || KIND == OP_ALLENCAHN, "register-tiled kernel: periodic scalar families");
+  constexpr int CH = (KM == 1) ? 5 : 3;
+  const GridSync gsync{P.barrier, P.spin_limit};
+  __shared__ RegShared sh;
+  const OpDev& op = P.op;
+  const int K = P.K;
+  const int Q = 1 + K;
+  const int nx = op.nx, ny = op.ny;
+  const size_t N = (size_t)nx * ny;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  for (int i = threadIdx.x; i < kTable; i += kRegBlock) sh.xi[i] = P.xi[i];
+  const int T = P.ntx * P.nty;
+  const int bb = xcd_chunk(blockIdx.x, gridDim.x);
+  const int tb0 = (int)((long)bb * T / gridDim.x), tb1 = (int)((long)(bb + 1) * T / gridDim.x);
+  const bool lane_own = lane >= kRegS && lane < kRegS + kRegTile;
+  const bool owned_wave = wv >= 2 && wv < 6;
+  const bool own = owned_wave && lane_own;
+  int x0 = 0, y0 = 0;
+  auto set_tile = [&](int t) {
+    x0 = (t % P.ntx) * kRegTile;
+    y0 = (t / P.ntx) * kRegTile;
+  };
+  auto gidx = [&](int i) {  // global index of extended point (lane, row 8 wv + i), periodic
+    int gx = (x0 - kRegS + lane) % nx;
+    if (gx < 0) gx += nx;
+    int gy = (y0 - kRegS + kRegRows * wv + i) % ny;
+    if (gy < 0) gy += ny;
+    return (size_t)gy * nx + gx;
+  };
+  // owned point of row i (own only)
+  auto gown = [&](int i) { return (size_t)(y0 + kRegRows * wv + i - kRegS) * nx + x0 + lane - kRegS; };
+
+  double fw, fe, fs, fn;
+  if constexpr (KIND == OP_ALLENCAHN) {
+    fw = fe = op.c0 * op.idx2;
+    fs = fn = op.c0 * op.idy2;
+  } else {
+    fw = op.c0 * op.idx2 + op.c1 * op.i2dx;
+    fe = op.c0 * op.idx2 - op.c1 * op.i2dx;
+    fs = op.c0 * op.idy2 + op.c2 * op.i2dy;
+    fn = op.c0 * op.idy2 - op.c2 * op.i2dy;
+  }
+  const double d_lap = -2.0 * op.c0 * (op.idx2 + op.idy2);
+  double dshift = 0.0, dscale = 1.0;  // the diagonal as (e_d - dshift) * dscale
+  double x[kRegRows], dg[kRegRows];
+  auto load_state = [&]() {
+#pragma unroll
+    for (int i = 0; i < kRegRows; ++i) {
+      double e;
+      if constexpr (KIND == OP_ALLENCAHN) {
+        const double u = op.state[gidx(i)];
+        e = d_lap + (1.0 - 3.0 * u * u);
+      } else {
+        e = d_lap;
+      }
+      dg[i] = (dscale == 1.0 && dshift == 0.0) ? e : (e - dshift) * dscale;
+    }
+  };
+  auto yb = [&](int i) { return i == 0 ? P.ybuf0 : (i == 1 ? P.ybuf1 : P.ybuf2); };
+
+  unsigned int epoch = 0;
+  int par = 0;
+  unsigned long long prof[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  unsigned long long t_last = wall_clock64();
+  auto tick = [&](int phase) {
+    const unsigned long long t = wall_clock64();
+    prof[phase] += t - t_last;
+    t_last = t;
+  };
+  auto point = [&](int i, double xs, double xn, double xim) {
+    const double xc = x[i];
+    const double xw = dpp_move<0x138>(xc);
+    const double xe = dpp_move<0x130>(xc);
+    double y;
+    if constexpr (KIND == OP_ALLENCAHN) {
+      y = fw * (xw + xe) + fs * (xs + xn);
+    } else {
+      y = fw * xw + fe * xe + fs * xs + fn * xn;
+    }
+    return fma(dg[i] - xim, xc, y);
+  };
+  auto step = [&](double xim) {
+    double* xr = &sh.xrow[par][0][0];
+    xr[(2 * wv) * 64 + lane] = x[0];
+    xr[(2 * wv + 1) * 64 + lane] = x[kRegRows - 1];
+    __syncthreads();
+    const double above = xr[(2 * ((wv + kRegWaves - 1) % kRegWaves) + 1) * 64 + lane];
+    const double below = xr[(2 * ((wv + 1) % kRegWaves)) * 64 + lane];
+    par ^= 1;
+    double y[kRegRows];
+#pragma unroll
+    for (int i = 1; i < kRegRows - 1; ++i) y[i] = point(i, x[i - 1], x[i + 1], xim);
+    y[0] = point(0, above, x[1], xim);
+    y[kRegRows - 1] = point(kRegRows - 1, x[kRegRows - 2], below, xim);
+#pragma unroll
+    for (int i = 0; i < kRegRows; ++i) x[i] = y[i];
+  };
+  auto sumsq = [&]() {  // owned waves: this lane's rows (lanes 16-47 are owned points in a full tile)
+    double a0 = 0.0, a1 = 0.0;
+#pragma unroll
+    for (int i = 0; i < kRegRows; i += 2) {
+      a0 = fma(x[i], x[i], a0);
+      a1 = fma(x[i + 1], x[i + 1], a1);
+    }
+    return a0 + a1;
+  };
+  // add this tile's sums of slots (one value per owned wave) to the staging area
+  auto stage_add = [&](int slot, double a) {
+    const double t = row_sum(a);
+    const double u = read_lane(t, 31) + read_lane(t, 47);
+    if (lane == 0) sh.stg[slot][wv - 2] += u;
+  };
+  auto zero_stage = [&](int nq) {
+    for (int q = threadIdx.x; q < nq * 4; q += kRegBlock) sh.stg[q >> 2][q & 3] = 0.0;
+    __syncthreads();
+  };
+  auto publish = [&](int nq) {
+    __syncthreads();
+    double* area = reg_area(P.partials, epoch);
+    for (int q = threadIdx.x; q < nq; q += kRegBlock) {
+      const double t = (sh.stg[q][0] + sh.stg[q][1]) + (sh.stg[q][2] + sh.stg[q][3]);
+      store_shared(area + (size_t)q * gridDim.x + blockIdx.x, t);
+    }
+    return area;
+  };
+  auto put_owned = [&](double* dst) {
+    if (own) {
+#pragma unroll
+      for (int i = 0; i < kRegRows; ++i) store_shared(dst + gown(i), x[i]);
+    }
+  };
+
+  // ---- (1) spectral bound: up to 16 products per super-step over all tiles,
+  // normalised per super-step
+  double lam = (P.lam_src != nullptr && !P.do_power) ? *P.lam_src : P.lam_in;
+  int pit = 0;
+  int r = 0;  // exchange vector read this super-step; the next one is written
+  if (P.do_power) {
+    int done = 0;
+    double sc = 1.0;
+    while (done < P.power_iters) {
+      const int steps = min(kRegS, P.power_iters - done);
+      zero_stage(steps + 1);
+      for (int t = tb0; t < tb1; ++t) {
+        set_tile(t);
+        load_state();
+#pragma unroll
+        for (int i = 0; i < kRegRows; ++i) {
+          const size_t g = gidx(i);
+          x[i] = (done == 0) ? (P.start ? P.start[g] : 0.5 + splitmix_uniform(P.seed, (uint64_t)g))
+                             : sc * yb(r)[g];
+        }
+        if (owned_wave) stage_add(0, sumsq());
+        for (int j = 1; j <= steps; ++j) {
+          step(0.0);
+          if (owned_wave) stage_add(j, sumsq());
+        }
+        put_owned(yb((r + 1) % 3));
+      }
+      double* area = publish(steps + 1);
+      grid_allreduce(gsync, epoch, nullptr, 0, nullptr);
+      reg_reduce<CH>(area, steps + 1, sh.tot);
+      const double nprev = sh.tot[steps - 1], nlast = sh.tot[steps];
+      done += steps;
+      pit = done;
+      lam = sqrt(nlast) / sqrt(nprev);
+      if (nlast == 0.0) {
+        lam = 0.0;
+        break;
+      }
+      sc = 1.0 / sqrt(nlast);
+      r = (r + 1) % 3;
+    }
+  }
+  lam = uniform(lam);
+  if (P.lam_out != nullptr && blockIdx.x == 0 && threadIdx.x == 0) *P.lam_out = lam;
+  double c, gamma;
+  interval(lam, P.safety, c, gamma);
+  const double rgamma = uniform(1.0 / gamma);
+  tick(kProfPower);
+  if (K == 0) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      Decision D;
+      decision_init(D, 0, 1.0, 0.0, sh.fmax);
+      store_status(P, D, pit, (int)epoch, 0.0, lam, c, gamma, prof);
+    }
+    grid_exit(P.barrier);
+    return;
+  }
+  fw *= rgamma;
+  fe *= rgamma;
+  fs *= rgamma;
+  fn *= rgamma;
+  dshift = c;
+  dscale = rgamma;
+
+  // ---- (2) divided differences
+  __syncthreads();
+  DivDiff dd;
+  dd_init_par(dd, K, P.l, P.s, P.max_points + 1, c, gamma, sh.xi, sh.coef, sh.fmax);
+  dd_advance(dd, K, kRegS, sh.xi, sh.coef);
+  __syncthreads();
+  tick(kProfDivdiff);
+
+  // ---- (3) Newton recurrence in super-steps of up to 16 over all tiles
+  if (threadIdx.x == 0) decision_init(sh.D, K, 1.0, 0.0, sh.fmax);  // redone once ||v|| is known
+  __syncthreads();
+  double nv = 0.0;
+  bool first = true;
+  int m0 = 0;
+  bool cpar[KM], fin[KM];  // committed value in the workspace / final value in the output
+#pragma unroll
+  for (int k = 0; k < KM; ++k) cpar[k] = fin[k] = false;
+  const double* src = P.v;  // input of the current super-step
+  // run the current super-step again from its input for the accumulators in
+  // `sel`, adding to each committed value its terms up to its own stop index
+  // ck[k] (<= cmax), and write the sums to the outputs
+  auto replay = [&](const bool* sel, const int* ck, int cmax) {
+    double cf[KM];
+#pragma unroll
+    for (int k = 0; k < KM; ++k) cf[k] = (sel[k] && lane < ck[k]) ? sh.coef[k * kTable + m0 + 1 + lane] : 0.0;
+    const double xiv = (lane < cmax) ? sh.xi[m0 + lane] : 0.0;
+    for (int t = tb0; t < tb1; ++t) {
+      set_tile(t);
+      load_state();
+#pragma unroll
+      for (int i = 0; i < kRegRows; ++i) x[i] = src[gidx(i)];
+      double ps[KM][kRegRows];
+      if (own) {
+#pragma unroll
+        for (int k = 0; k < KM; ++k) {
+          if (!sel[k]) continue;
+          const double* cb = cpar[k] ? P.pw[k] : P.p[k];
+#pragma unroll
+          for (int i = 0; i < kRegRows; ++i) ps[k][i] = cb[gown(i)];
+        }
+      }
+      for (int j = 1; j <= cmax; ++j) {
+        step(read_lane(xiv, j - 1));
+#pragma unroll
+        for (int k = 0; k < KM; ++k) {
+          if (!sel[k] || j > ck[k]) continue;
+          const double dk = read_lane(cf[k], j - 1);
+          if (own) {
+#pragma unroll
+            for (int i = 0; i < kRegRows; ++i) ps[k][i] = ps[k][i] + dk * x[i];
+          }
+        }
+      }
+      if (own) {
+#pragma unroll
+        for (int k = 0; k < KM; ++k) {
+          if (!sel[k]) continue;
+#pragma unroll
+          for (int i = 0; i < kRegRows; ++i) P.p[k][gown(i)] = ps[k][i];
+        }
+      }
+    }
+  };
+  while (true) {
+    const int pred = min(uniform(sh.D.next), uniform(sh.D.next_local));  // predicted last stop (+1)
+    const int steps = min(min(kRegS, P.max_points - m0), pred);
+    bool act0[KM];
+#pragma unroll
+    for (int k = 0; k < KM; ++k) act0[k] = (k < K) && (uniform(sh.D.st[k]) == ACC_RUNNING);
+    const double xiv = (lane < steps) ? sh.xi[m0 + lane] : 0.0;
+    double cfv[KM];
+#pragma unroll
+    for (int k = 0; k < KM; ++k) cfv[k] = (lane < steps && act0[k]) ? sh.coef[k * kTable + m0 + 1 + lane] : 0.0;
+    const int nq = steps * Q + (first ? 1 : 0);
+    src = first ? P.v : yb(r);
+    const bool snap = pred <= kRegS;  // the length is the predicted stop
+    zero_stage(nq);
+    for (int t = tb0; t < tb1; ++t) {
+      set_tile(t);
+      load_state();
+#pragma unroll
+      for (int i = 0; i < kRegRows; ++i) x[i] = src[gidx(i)];
+      double ps[KM][kRegRows];
+      if (own) {
+#pragma unroll
+        for (int k = 0; k < KM; ++k) {
+          if (!act0[k]) continue;
+          if (first) {
+            const double d0 = sh.coef[k * kTable];
+#pragma unroll
+            for (int i = 0; i < kRegRows; ++i) {
+              ps[k][i] = d0 * x[i];
+              P.p[k][gown(i)] = ps[k][i];  // the committed value p_k = d_{k,0} v
+            }
+          } else {
+            const double* cb = cpar[k] ? P.pw[k] : P.p[k];
+#pragma unroll
+            for (int i = 0; i < kRegRows; ++i) ps[k][i] = cb[gown(i)];
+          }
+        }
+      }
+      if (first && owned_wave) stage_add(steps * Q, sumsq());
+      for (int j = 1; j <= steps; ++j) {
+        step(read_lane(xiv, j - 1));
+        if (owned_wave) {
+          double tq[1 + KM];
+          tq[0] = sumsq();
+#pragma unroll
+          for (int k = 0; k < KM; ++k) {
+            const double dk = read_lane(cfv[k], j - 1);
+            double b0 = 0.0, b1 = 0.0;
+#pragma unroll
+            for (int i = 0; i < kRegRows; i += 2) {
+              ps[k][i] = ps[k][i] + dk * x[i];
+              ps[k][i + 1] = ps[k][i + 1] + dk * x[i + 1];
+              b0 = fma(ps[k][i], ps[k][i], b0);
+              b1 = fma(ps[k][i + 1], ps[k][i + 1], b1);
+            }
+            tq[1 + k] = b0 + b1;
+          }
+          const int d = steps - j;  // snapshot d - 1 holds the values after step m0 + j
+          if (snap && d >= 1 && d <= kRegSnap && own) {
+#pragma unroll
+            for (int k = 0; k < KM; ++k) {
+              if (!act0[k]) continue;
+              double* sn = P.snap + (size_t)(k * kRegSnap + d - 1) * N;
+#pragma unroll
+              for (int i = 0; i < kRegRows; ++i) sn[gown(i)] = ps[k][i];
+            }
+          }
+#pragma unroll
+          for (int q = 0; q < 1 + KM; ++q) tq[q] += dpp_move<0x111>(tq[q]);
+#pragma unroll
+          for (int q = 0; q < 1 + KM; ++q) tq[q] += dpp_move<0x112>(tq[q]);
+#pragma unroll
+          for (int q = 0; q < 1 + KM; ++q) tq[q] += dpp_move<0x114>(tq[q]);
+#pragma unroll
+          for (int q = 0; q < 1 + KM; ++q) tq[q] += dpp_move<0x118>(tq[q]);
+          double uq[1 + KM];
+#pragma unroll
+          for (int q = 0; q < 1 + KM; ++q) uq[q] = read_lane(tq[q], 31) + read_lane(tq[q], 47);
+          if (lane == 0) {
+            sh.stg[(j - 1) * Q][wv - 2] += uq[0];
+#pragma unroll
+            for (int k = 0; k < KM; ++k)
+              if (k < K) sh.stg[(j - 1) * Q + 1 + k][wv - 2] += uq[1 + k];
+          }
+        }
+      }
+      put_owned(yb((r + 1) % 3));
+      if (own) {  // the speculative values go to the buffer that is not the committed one
+#pragma unroll
+        for (int k = 0; k < KM; ++k) {
+          if (!act0[k]) continue;
+          double* sb = cpar[k] ? P.p[k] : P.pw[k];
+#pragma unroll
+          for (int i = 0; i < kRegRows; ++i) sb[gown(i)] = ps[k][i];
+        }
+      }
+    }
+    tick(kProfSteps);
+    double* area = publish(nq);
+    tick(kProfPublish);
+    grid_allreduce(gsync, epoch, nullptr, 0, nullptr,
+                   [&] { dd_advance(dd, K, m0 + steps + kRegS, sh.xi, sh.coef); });
+    reg_reduce<CH>(area, nq, sh.tot);
+    tick(kProfBarrier);
+    if (threadIdx.x < 64) {
+      if (first) {
+        nv = sqrt(sh.tot[steps * Q]);
+        decision_init(sh.D, K, nv, P.hump, sh.fmax);
+      }
+      replay_decisions(sh.D, K, m0, steps, Q, sh.tot, sh.coef, P.tol, P.relative, P.max_points, sh.commit,
+                       blockIdx.x == 0 ? P.status->trace : nullptr);
+    }
+    __syncthreads();
+    tick(kProfDecide);
+    // commit: a run-through accumulator's speculative buffer becomes the
+    // committed one; those that stopped inside the super-step take the
+    // committed value plus the terms up to their stop index (forward order),
+    // formed by running the super-step again up to the last such stop
+    bool redo[KM], fromsnap[KM];
+    int ck[KM];
+    int cmax = -1;
+    bool anysnap = false;
+#pragma unroll
+    for (int k = 0; k < KM; ++k) {
+      ck[k] = act0[k] ? uniform(sh.commit[k]) : 0;
+      const bool in = act0[k] && ck[k] < steps;
+      fromsnap[k] = in && snap && ck[k] >= 1 && steps - ck[k] <= kRegSnap;
+      redo[k] = in && !fromsnap[k];
+      anysnap = anysnap || fromsnap[k];
+      if (redo[k]) cmax = max(cmax, ck[k]);
+      if (act0[k] && !in) cpar[k] = !cpar[k];
+    }
+    if (anysnap) {
+      for (int t = tb0; t < tb1; ++t) {
+        set_tile(t);
+        if (!own) continue;
+#pragma unroll
+        for (int k = 0; k < KM; ++k) {
+          if (!fromsnap[k]) continue;
+          const double* sn = P.snap + (size_t)(k * kRegSnap + steps - ck[k] - 1) * N;
+#pragma unroll
+          for (int i = 0; i < kRegRows; ++i) P.p[k][gown(i)] = sn[gown(i)];
+        }
+      }
+#pragma unroll
+      for (int k = 0; k < KM; ++k) {
+        if (!fromsnap[k]) continue;
+        fin[k] = true;
+        cpar[k] = false;
+      }
+    }
+    if (cmax >= 0) {
+      if constexpr (KM == 1) {
+        replay(redo, ck, cmax);
+      } else {
+        // one accumulator at a time keeps the register state of the
+        // four-accumulator instance within the file
+#pragma unroll
+        for (int k = 0; k < KM; ++k) {
+          if (!redo[k]) continue;
+          bool one[KM];
+#pragma unroll
+          for (int q = 0; q < KM; ++q) one[q] = (q == k);
+          replay(one, ck, ck[k]);
+        }
+      }
+#pragma unroll
+      for (int k = 0; k < KM; ++k) {
+        if (!redo[k]) continue;
+        fin[k] = true;
+        cpar[k] = false;
+      }
+    }
+    m0 += steps;
+    r = (r + 1) % 3;
+    first = false;
+    tick(kProfCommit);
+    if (sh.D.n_active == 0 || m0 >= P.max_points) break;
+    __syncthreads();
+  }
+  // accumulators whose committed value sits in the workspace: to the output
+#pragma unroll
+  for (int k = 0; k < KM; ++k) {
+    if (k >= K || fin[k] || !cpar[k]) continue;
+    for (int t = tb0; t < tb1; ++t) {
+      set_tile(t);
+      if (!own) continue;
+#pragma unroll
+      for (int i = 0; i < kRegRows; ++i) P.p[k][gown(i)] = P.pw[k][gown(i)];
+    }
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    store_status(P, sh.D, pit, (int)epoch, nv, lam, c, gamma, prof);
+  }
+  grid_exit(P.barrier);
+}
+
 // ---------------------------------------------------------------------------
 // Stand-alone divided differences (the lj_divided_differences entry point);
 // the same dd_init / dd_advance the action kernels run.
@@ -2071,7 +2565,17 @@ void* action_reg_ptr(int kind, int K, bool full) {
 #undef LJ_REG_CASE
   return nullptr;
 }
+void* action_regm_ptr(int kind, int K) {
+  if (kind == OP_ALLENCAHN)
+    return K <= 1 ? reinterpret_cast<void*>(&lj_action_regm<OP_ALLENCAHN, 1>)
+                  : reinterpret_cast<void*>(&lj_action_regm<OP_ALLENCAHN, kMaxK>);
+  if (kind == OP_ADVDIFF)
+    return K <= 1 ? reinterpret_cast<void*>(&lj_action_regm<OP_ADVDIFF, 1>)
+                  : reinterpret_cast<void*>(&lj_action_regm<OP_ADVDIFF, kMaxK>);
+  return nullptr;
+}
 int reg_block() { return kRegBlock; }
+int reg_steps() { return kRegS; }
 size_t reg_lds_bytes() { return (size_t)kRegS * kRegTile * kRegTile * sizeof(double); }
 size_t reg_static_lds() { return sizeof(RegShared); }
 

@@ -44,6 +44,7 @@ enum Slot {
   W_UFU, W_UXR, W_UD, W_UFX, W_UJD, W_UR0, W_UR1,  // f(u), stage remainders
   W_KV, W_KW, W_KX, W_KC,          // Krylov: basis, product, augmented vector, LeKry third stage
   W_KU0, W_KU1, W_KZ0, W_KZ1,      // Krylov, one-launch basis: orthogonalised vectors and their products
+  W_Y2, W_PW0, W_PW1, W_PW2, W_PW3, W_SNAP,  // register-tiled kernel with several tiles per block
   W_NSLOTS
 };
 
@@ -381,12 +382,15 @@ TilePlan tile_plan(lj_context* ctx, const OpDev& op) {
   return best;
 }
 
-// Register-tiled kernel: 32 x 32 tiles, at most one per CU (and at most 256,
-// the partial-sum reduction's assumption), the step history in dynamic LDS.
+// Register-tiled kernel: 32 x 32 tiles, one per block with the step history
+// in dynamic LDS when they fit one per CU (at most 256, the partial-sum
+// reduction's assumption), else several per block (full tiles only).
 struct RegPlan {
   bool ok = false;
-  bool full = false;  // every tile is 32 x 32
+  bool full = false;   // every tile is 32 x 32
+  bool multi = false;  // more tiles than blocks: several per block
   int ntx = 0, nty = 0;
+  int blocks = 0;
   size_t lds = 0;
 };
 
@@ -395,13 +399,28 @@ RegPlan reg_plan(lj_context* ctx, const OpDev& op, int K) {
   if (ctx->force_stream || ctx->no_reg || ctx->tile_override_x > 0 || action_reg_ptr(op.kind, K, true) == nullptr)
     return r;
   const int ntx = (op.nx + 31) / 32, nty = (op.ny + 31) / 32;
-  const long G = (long)ntx * nty;
-  if (G > ctx->num_cus || G > 256) return r;
+  const long T = (long)ntx * nty;
+  const bool full = op.nx % 32 == 0 && op.ny % 32 == 0;
+  if (T > ctx->num_cus || T > 256) {
+    // several tiles per block: full tiles only, not in the allocation-free
+    // path (it needs 3 + 4K workspace vectors)
+    if (!full || ctx->in_noalloc || action_regm_ptr(op.kind, K) == nullptr) return r;
+    if (reg_static_lds() > (size_t)ctx->lds_max) return r;
+    r.ok = true;
+    r.full = true;
+    r.multi = true;
+    r.ntx = ntx;
+    r.nty = nty;
+    r.blocks = std::min(ctx->num_cus, 256);
+    r.lds = 0;
+    return r;
+  }
   if (reg_lds_bytes() + reg_static_lds() > (size_t)ctx->lds_max) return r;
   r.ok = true;
-  r.full = op.nx % 32 == 0 && op.ny % 32 == 0;
+  r.full = full;
   r.ntx = ntx;
   r.nty = nty;
+  r.blocks = (int)T;
   r.lds = reg_lds_bytes();
   return r;
 }
@@ -522,14 +541,19 @@ void launch_action(lj_context* ctx, const OpDev& op, const double* v, int K, con
   size_t dyn = 0;
   int block = persistent_block();
   if (rp.ok) {
-    fn = action_reg_ptr(op.kind, K, rp.full);
+    fn = rp.multi ? action_regm_ptr(op.kind, K) : action_reg_ptr(op.kind, K, rp.full);
     P.tx = 32;
     P.ty = 32;
     P.ntx = rp.ntx;
     P.nty = rp.nty;
-    G = rp.ntx * rp.nty;
+    G = rp.blocks;
     dyn = rp.lds;
     block = reg_block();
+    if (rp.multi) {
+      P.ybuf2 = slot(ctx, W_Y2, n);
+      for (int k = 0; k < K; ++k) P.pw[k] = slot(ctx, W_PW0 + k, n);
+      P.snap = slot(ctx, W_SNAP, (size_t)K * kRegSnap * n);
+    }
     if (dyn > 64 * 1024 && ctx->dyn_lds[fn] < dyn) {
       HIPCHK(ctx, hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn));
       ctx->dyn_lds[fn] = dyn;

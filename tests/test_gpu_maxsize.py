@@ -3,15 +3,19 @@ outputs are checked at sampled points against closed forms that hold at any
 size, computed by the oracle's pinned routines one point at a time.
 
 * advection-diffusion on an 8192 x 8192 periodic grid (67M points, the
-  largest grid of the measured sweep; streaming kernel) from a sum of three
-  Fourier modes: J acts by the stencil's symbol, so phi_1(hJ)v is the same
-  sum with each amplitude times phi_1(h sigma_k);
+  largest grid of the measured sweep) from a sum of three Fourier modes: J
+  acts by the stencil's symbol, so phi_1(hJ)v is the same sum with each
+  amplitude times phi_1(h sigma_k); through the register-tiled kernel with
+  several tiles per block (the default at this size) and through the
+  streaming kernel (LJ_NO_TILE=1 at context creation);
 * a diagonal operator of 2^28 entries (2 GiB per vector): w_i = phi_1(h
   lambda_i) v_i.
 
 The Leja stop test bounds the 2-norm error relative to the result (~tol); the
 sampled relative RMS error estimates it, and the largest sampled error is
 bounded loosely as a guard against localised indexing mistakes."""
+import os
+
 import numpy as np
 import pytest
 
@@ -46,15 +50,22 @@ def _check(w_s, ref_s, what):
     assert mx <= 1e-7
 
 
-def test_advdiff_8192_fourier_modes(env):
+@pytest.mark.parametrize("kernel", ["register", "stream"])
+def test_advdiff_8192_fourier_modes(env, kernel):
     lj, torch, ctx = env
+    if kernel == "stream":
+        os.environ["LJ_NO_TILE"] = "1"
+        try:
+            ctx = lj.Context(0)
+        finally:
+            del os.environ["LJ_NO_TILE"]
     n, nu = 8192, 1.0
     dx = 1.0 / n
     a = nu / dx  # grid Peclet number 1
     prob = Problem("advdiff", n, n, 1, dx, dx, (nu, a, a), None, dx * dx / (4 * nu))
     v, modes = fourier_modes(n, 3, seed=11, kmax=40)
     h = 10 * prob.h_cfl
-    say("advdiff 8192^2", modes)
+    say("advdiff 8192^2", kernel, modes)
     J = lj.operator_from(prob, "cuda:0")
     vd = torch.as_tensor(v, device="cuda:0")
     del v
@@ -65,7 +76,8 @@ def test_advdiff_8192_fourier_modes(env):
     torch.cuda.synchronize()
     lj.lj_timing_enable(ctx, False)
     tm = lj.lj_timing_read(ctx, reset=True)
-    assert rc == 0 and st["converged"] and tm["tiled_launches"] == 0
+    assert rc == 0 and st["converged"]
+    assert tm["tiled_launches"] == (1 if kernel == "register" else 0)
     rng = np.random.default_rng(12)
     idx = rng.integers(0, n * n, size=NSAMPLE)
     jj, ii = np.divmod(idx, n)
@@ -76,7 +88,9 @@ def test_advdiff_8192_fourier_modes(env):
         ref += (A * phi_scalar_expm(1, h * sig) * np.exp(1j * ph)).real
     w_s = w[torch.as_tensor(idx, device="cuda:0")].cpu().numpy()
     del vd, w
-    _check(w_s, ref, f"advdiff 8192^2 m*={st['m_star']}")
+    if kernel == "stream":
+        ctx.close()
+    _check(w_s, ref, f"advdiff 8192^2 {kernel} m*={st['m_star']}")
 
 
 def test_diag_2p28(env):
