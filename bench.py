@@ -234,76 +234,82 @@ def bench_sweep(args):
         lj.lj_timing_enable(ctx, False)
         return statistics.median(ts), lj.lj_timing_read(ctx, reset=True), out
 
-    def line(workload, metric, value, unit, ms, tm, ncomp, extra, bound="hbm"):
+    def line(workload, metric, value, unit, ms, tm, ncomp, extra, bound="hbm", traffic_file=None):
         launches = max(tm["launches"], 1)
         avg_ms = tm["kernel_ms"] / launches
         bpl = algorithmic_bytes(tm, ncomp) / launches
         ach = bpl / (avg_ms * 1e-3) / 1e9
+        traffic = measured_traffic(traffic_file) if traffic_file else None
         rec = {"metric": metric, "value": round(value, 2), "unit": unit, "n_gpus": 1, "ms_per_step": round(ms, 4),
                "dtype": "f64", "data": "synthetic", "config": {"workload": workload},
                "roofline": {"bound": bound, "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                             "frac": round(ach / HBM_PEAK_GBS, 4), "avg_launch_us": round(avg_ms * 1e3, 2),
-                            "algorithmic_bytes_per_launch": round(bpl)}}
+                            "algorithmic_bytes_per_launch": round(bpl), "traffic": traffic,
+                            "dram_gbs": round(traffic / (avg_ms * 1e-3) / 1e9, 1) if traffic else None}}
         rec.update(extra)
         print(json.dumps(rec), flush=True)
 
-    # advection-diffusion 32^2, grid Peclet 1, phi_1 at 10x CFL
-    prob, v0 = advdiff_bump()
-    op = lj.operator_from(prob, "cuda:0")
-    v = torch.as_tensor(v0, dtype=torch.float64, device="cuda:0")
-    w = torch.empty_like(v)
-    h = CFL_MULT * prob.h_cfl
-    dt, tm, (rc, st) = timed(lambda: lj.lj_phi_action(ctx, op, v, w, 1, h, TOL), 50)
-    line("advection-diffusion 32x32, nu 1, grid Peclet 1, bump + noise seed 1, phi_1 at 10x CFL, tol 1e-10",
-         "\u00b5s per \u03c6_1 action", dt * 1e6, "us", dt * 1e3, tm, 1, {"m_star": st["m_star"][0]},
-         bound="latency")
+    def others(timed, line):
+        # advection-diffusion 32^2, grid Peclet 1, phi_1 at 10x CFL
+        prob, v0 = advdiff_bump()
+        op = lj.operator_from(prob, "cuda:0")
+        v = torch.as_tensor(v0, dtype=torch.float64, device="cuda:0")
+        w = torch.empty_like(v)
+        h = CFL_MULT * prob.h_cfl
+        dt, tm, (rc, st) = timed(lambda: lj.lj_phi_action(ctx, op, v, w, 1, h, TOL), 50)
+        line("advection-diffusion 32x32, nu 1, grid Peclet 1, bump + noise seed 1, phi_1 at 10x CFL, tol 1e-10",
+             "\u00b5s per \u03c6_1 action", dt * 1e6, "us", dt * 1e3, tm, 1, {"m_star": st["m_star"][0]},
+             bound="latency")
 
-    # Brusselator 1024^2: EXPRB43-u3 steps + a stand-alone phi_2
-    prob = brusselator_perturbed()
-    op = lj.operator_from(prob, "cuda:0")
-    h = CFL_MULT * prob.h_cfl
-    u_out = torch.empty(prob.n, dtype=torch.float64, device="cuda:0")
-    f = torch.empty_like(u_out)
-    lj.lj_rhs(ctx, op, op.state, f)
-    v = (h * f).contiguous()
-    w = torch.empty_like(v)
+        # Brusselator 1024^2: EXPRB43-u3 steps + a stand-alone phi_2
+        prob = brusselator_perturbed()
+        op = lj.operator_from(prob, "cuda:0")
+        h = CFL_MULT * prob.h_cfl
+        u_out = torch.empty(prob.n, dtype=torch.float64, device="cuda:0")
+        f = torch.empty_like(u_out)
+        lj.lj_rhs(ctx, op, op.state, f)
+        v = (h * f).contiguous()
+        w = torch.empty_like(v)
 
-    def bstep():
-        _, s3 = lj.lj_step(ctx, "EXPRB43_U3", op, h, TOL, u_out)
-        lj.lj_phi_action(ctx, op, v, w, 2, h, TOL, lj.lj_default_options(bound=s3[0]["bound"]))
-        return s3
+        def bstep():
+            _, s3 = lj.lj_step(ctx, "EXPRB43_U3", op, h, TOL, u_out)
+            lj.lj_phi_action(ctx, op, v, w, 2, h, TOL, lj.lj_default_options(bound=s3[0]["bound"]))
+            return s3
 
-    dt, tm, s3 = timed(bstep, 10)
-    line("brusselator 1024x1024 periodic, D 2e-3, a 1, b 3, perturbation seed 3, h 10x CFL, tol 1e-10: "
-         "one EXPRB43-u3 step + a phi_2 action (5 actions)", "\u03c6_l(hJ)v actions/sec", 5 / dt,
-         "phi-actions/s", dt * 1e3, tm, 2, {"m_star": [s["m_star"][:2] for s in s3]})
+        dt, tm, s3 = timed(bstep, 10)
+        line("brusselator 1024x1024 periodic, D 2e-3, a 1, b 3, perturbation seed 3, h 10x CFL, tol 1e-10: "
+             "one EXPRB43-u3 step + a phi_2 action (5 actions)", "\u03c6_l(hJ)v actions/sec", 5 / dt,
+             "phi-actions/s", dt * 1e3, tm, 2, {"m_star": [s["m_star"][:2] for s in s3]})
 
-    # Gray-Scott 1024^2 (Sec. 3 spots, a1 = a2 = 1e-3): one EPIRK4s3 step
-    prob = gray_scott_spots(1024, a1=1e-3, a2=1e-3)
-    op = lj.operator_from(prob, "cuda:0")
-    h = CFL_MULT * prob.h_cfl
-    u_out = torch.empty(prob.n, dtype=torch.float64, device="cuda:0")
-    err = torch.empty_like(u_out)
-    dt, tm, s4 = timed(lambda: lj.lj_step(ctx, "EPIRK4S3", op, h, TOL, u_out, err)[1], 10)
-    line("gray-scott 1024x1024 periodic, a1 = a2 = 1e-3, a 0.04, b 0.06, spot initial state, h 10x CFL, "
-         "tol 1e-10: one EPIRK4s3 step (5 actions)", "\u03c6_l(hJ)v actions/sec", 5 / dt, "phi-actions/s",
-         dt * 1e3, tm, 2, {"m_star": [s["m_star"][:3] for s in s4]})
+        # Gray-Scott 1024^2 (Sec. 3 spots, a1 = a2 = 1e-3): one EPIRK4s3 step
+        prob = gray_scott_spots(1024, a1=1e-3, a2=1e-3)
+        op = lj.operator_from(prob, "cuda:0")
+        h = CFL_MULT * prob.h_cfl
+        u_out = torch.empty(prob.n, dtype=torch.float64, device="cuda:0")
+        err = torch.empty_like(u_out)
+        dt, tm, s4 = timed(lambda: lj.lj_step(ctx, "EPIRK4S3", op, h, TOL, u_out, err)[1], 10)
+        line("gray-scott 1024x1024 periodic, a1 = a2 = 1e-3, a 0.04, b 0.06, spot initial state, h 10x CFL, "
+             "tol 1e-10: one EPIRK4s3 step (5 actions)", "\u03c6_l(hJ)v actions/sec", 5 / dt, "phi-actions/s",
+             dt * 1e3, tm, 2, {"m_star": [s["m_star"][:3] for s in s4]})
 
-    # advection-diffusion-reaction 512^2 (Sec. 3, Neumann boundaries, its initial
-    # state; alpha 1e-2, beta -10, rate 100): one EPIRK4s3 step
-    prob = adr_neumann(512, alpha=1e-2, beta=-10.0, rate=100.0)
-    op = lj.operator_from(prob, "cuda:0")
-    h = CFL_MULT * prob.h_cfl
-    u_out = torch.empty(prob.n, dtype=torch.float64, device="cuda:0")
-    err = torch.empty_like(u_out)
-    dt, tm, s5 = timed(lambda: lj.lj_step(ctx, "EPIRK4S3", op, h, TOL, u_out, err)[1], 20)
-    line("advection-diffusion-reaction 512x512, homogeneous Neumann, alpha 1e-2, beta -10, rate 100, "
-         "initial state 256(xy(1-x)(1-y))^2 + 0.3, h 10x CFL, tol 1e-10: one EPIRK4s3 step (5 actions)",
-         "\u03c6_l(hJ)v actions/sec", 5 / dt, "phi-actions/s", dt * 1e3, tm, 1,
-         {"m_star": [s["m_star"][:3] for s in s5]}, bound="latency")
+        # advection-diffusion-reaction 512^2 (Sec. 3, Neumann boundaries, its initial
+        # state; alpha 1e-2, beta -10, rate 100): one EPIRK4s3 step
+        prob = adr_neumann(512, alpha=1e-2, beta=-10.0, rate=100.0)
+        op = lj.operator_from(prob, "cuda:0")
+        h = CFL_MULT * prob.h_cfl
+        u_out = torch.empty(prob.n, dtype=torch.float64, device="cuda:0")
+        err = torch.empty_like(u_out)
+        dt, tm, s5 = timed(lambda: lj.lj_step(ctx, "EPIRK4S3", op, h, TOL, u_out, err)[1], 20)
+        line("advection-diffusion-reaction 512x512, homogeneous Neumann, alpha 1e-2, beta -10, rate 100, "
+             "initial state 256(xy(1-x)(1-y))^2 + 0.3, h 10x CFL, tol 1e-10: one EPIRK4s3 step (5 actions)",
+             "\u03c6_l(hJ)v actions/sec", 5 / dt, "phi-actions/s", dt * 1e3, tm, 1,
+             {"m_star": [s["m_star"][:3] for s in s5]}, bound="latency")
 
+
+    if not args.sweep_n:
+        others(timed, line)
     # Allen-Cahn n^2, phi_1 of h f(u) at 10x CFL, bound given (Newton recurrence only)
-    for n in (1024, 2048, 4096, 8192):
+    for n in ((args.sweep_n,) if args.sweep_n else (1024, 2048, 4096, 8192)):
         prob = allen_cahn_noise(n, eps=1e-3, seed=2)
         op = lj.operator_from(prob, "cuda:0")
         h = CFL_MULT * prob.h_cfl
@@ -314,9 +320,19 @@ def bench_sweep(args):
         lam = lj.lj_spectral_bound(ctx, op, 20)
         o = lj.lj_default_options(bound=lam)
         dt, tm, (rc, st) = timed(lambda: lj.lj_phi_action(ctx, op, v, w, 1, h, TOL, o), 10 if n < 8192 else 4)
+        # the register-tiled kernel (several 32 x 32 tiles per block) keeps 16
+        # Newton steps per pass over HBM: its time goes to the steps' arithmetic
+        # and workgroup synchronisation, not to memory traffic; with
+        # LJ_NO_TILE=1 the streaming kernel runs and streams from HBM
+        tiled = tm["tiled_launches"] > 0
+        tf = None
+        if n == 4096:
+            tf = os.path.join(ROOT, "profiles", "action_regm_allen_cahn_4096_traffic.json" if tiled
+                              else "action_stream_allen_cahn_4096_traffic.json")
         line(f"allen-cahn {n}x{n} periodic, eps 1e-3, u0~U[-0.1,0.1] seed 2, phi_1 at 10x CFL, bound given, "
              "tol 1e-10", "\u03c6_l(hJ)v actions/sec", 1 / dt, "phi-actions/s", dt * 1e3, tm, 1,
-             {"m_star": st["m_star"][0]})
+             {"m_star": st["m_star"][0], "kernel": "register-tiled" if tiled else "streaming"},
+             bound="latency" if tiled else "hbm", traffic_file=tf)
     ctx.close()
 
 
@@ -558,17 +574,32 @@ def bench_lekry(args):
 
 
 def bench_ceiling(args):
-    """The attainable HBM bandwidth of the device (copy, read-only, and the
-    Newton step's 3-read 2-write pattern over 1 GiB vectors): the practical
-    ceiling to read the roofline fractions against (one JSON line)."""
+    """The attainable HBM bandwidth of the device: copy, read-only, and the
+    Newton step's 3-read 2-write pattern over 1 GiB vectors, at launch shapes
+    from 256 to 16384 blocks of 256 or 1024 threads, 1, 2 or 4 accesses in
+    flight per thread and vector, ordinary or non-temporal loads and stores;
+    the best of each pattern is the practical ceiling to read the roofline
+    fractions against (one JSON line, every shape listed in it)."""
     import paper_2211_08948_amd as lj
-    bw = lj.lj_measure_bandwidth(1 << 30)
-    rec = {"metric": "attainable HBM bandwidth", "value": round(bw["newton_step"], 1), "unit": "GB/s", "n_gpus": 1,
-           "higher_is_better": True, "dtype": "f64", "data": "synthetic",
-           "config": {"workload": "streaming FP64 kernels over 1 GiB vectors, 1024 blocks x 256 threads, best of 5"},
-           "copy_gbs": round(bw["copy"], 1), "read_gbs": round(bw["read"], 1),
-           "newton_step_gbs": round(bw["newton_step"], 1), "peak_gbs": HBM_PEAK_GBS,
-           "fractions_of_peak": {k: round(v / HBM_PEAK_GBS, 4) for k, v in bw.items()}}
+    shapes = []
+    for nt in (False, True):
+        for threads in (256, 1024):
+            for blocks in (256, 1024, 4096, 16384):
+                for unroll in (1, 2, 4):
+                    bw = lj.lj_measure_bandwidth_shape(1 << 30, blocks, threads, unroll, nt)
+                    shapes.append({"blocks": blocks, "threads": threads, "unroll": unroll, "nontemporal": nt,
+                                   **{k: round(v, 1) for k, v in bw.items()}})
+                    log(json.dumps(shapes[-1]))
+    best = {k: max(shapes, key=lambda r: r[k]) for k in ("copy", "read", "newton_step")}
+    rec = {"metric": "attainable HBM bandwidth", "value": best["newton_step"]["newton_step"], "unit": "GB/s",
+           "n_gpus": 1, "higher_is_better": True, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": "streaming FP64 kernels over 1 GiB vectors, best of 5 per shape; value: the "
+                                  "Newton-step pattern (3 reads + 2 writes) at its best shape"},
+           "copy_gbs": best["copy"]["copy"], "read_gbs": best["read"]["read"],
+           "newton_step_gbs": best["newton_step"]["newton_step"], "peak_gbs": HBM_PEAK_GBS,
+           "fractions_of_peak": {k: round(best[k][k] / HBM_PEAK_GBS, 4) for k in best},
+           "best_shapes": {k: {q: best[k][q] for q in ("blocks", "threads", "unroll", "nontemporal")} for k in best},
+           "shapes": shapes}
     print(json.dumps(rec), flush=True)
 
 
@@ -580,6 +611,8 @@ def main():
     ap.add_argument("--n", type=int, default=512, help="grid points per axis (default: the 512^2 workload)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true")
+    ap.add_argument("--sweep-n", type=int, default=0,
+                    help="--form sweep: run only the Allen-Cahn phi_1 line at this grid size (for profiling)")
     ap.add_argument("--form", choices=["plain", "batch", "sweep", "stiffness", "adaptive", "user", "lekry", "ceiling"],
                     default="plain")
     args = ap.parse_args()

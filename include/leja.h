@@ -509,6 +509,15 @@ LJ_API int lj_mlp_load(lj_context* ctx, const char* path);
  * on the current device; synchronises it.  No context needed. */
 LJ_API int lj_measure_bandwidth(long long bytes, double* gbs);
 
+/* The same three patterns at a chosen launch shape: `blocks` (1 .. 2^20)
+ * blocks of `threads` (64 .. 1024, a multiple of 64) threads, each thread
+ * keeping `unroll` (1, 2 or 4) 16-byte accesses per vector in flight, with
+ * ordinary (nontemporal = 0) or non-temporal loads and stores (1).
+ * lj_measure_bandwidth is this call at 1024 x 256, unroll 1, ordinary
+ * accesses.  LJ_EINVAL for arguments out of range (nothing allocated). */
+LJ_API int lj_measure_bandwidth_shape(long long bytes, int blocks, int threads, int unroll, int nontemporal,
+                                      double* gbs);
+
 /* Kernel timing of the phi-action kernel.  While enabled, the library
  * brackets every launch of that kernel (power iteration + divided differences
  * + Newton recurrence in one persistent launch) with HIP events on the launch

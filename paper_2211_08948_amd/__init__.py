@@ -330,6 +330,18 @@ def lj_measure_bandwidth(nbytes: int = 1 << 30) -> dict:
     return {"copy": out[0], "read": out[1], "newton_step": out[2]}
 
 
+def lj_measure_bandwidth_shape(nbytes: int, blocks: int, threads: int, unroll: int = 1,
+                               nontemporal: bool = False) -> dict:
+    """The same patterns at a chosen launch shape, accesses in flight per
+    thread and load/store flavour (non-temporal or ordinary)."""
+    out = (C.c_double * 3)()
+    rc = lib().lj_measure_bandwidth_shape(int(nbytes), int(blocks), int(threads), int(unroll),
+                                          1 if nontemporal else 0, out)
+    if rc != LJ_OK:
+        raise LejaError(rc, "lj_measure_bandwidth_shape")
+    return {"copy": out[0], "read": out[1], "newton_step": out[2]}
+
+
 def lj_default_krylov_options(**overrides) -> "_lib.lj_krylov_options":
     k = _lib.lj_krylov_options()
     lib().lj_default_krylov_options(C.byref(k))

@@ -130,6 +130,8 @@ _PROTOS = {
     "lj_rhs": (C.c_int, [_P, C.POINTER(lj_operator), _P, _P, _P]),
     "lj_jv": (C.c_int, [_P, C.POINTER(lj_operator), _P, _P, _P]),
     "lj_measure_bandwidth": (C.c_int, [C.c_longlong, C.POINTER(C.c_double)]),
+    "lj_measure_bandwidth_shape": (C.c_int, [C.c_longlong, C.c_int, C.c_int, C.c_int, C.c_int,
+                                             C.POINTER(C.c_double)]),
     "lj_default_krylov_options": (None, [C.POINTER(lj_krylov_options)]),
     "lj_phi_combination": (C.c_int, [_P, C.POINTER(lj_operator), C.c_int, C.POINTER(_P), C.c_double, C.c_double,
                                      _P, C.POINTER(lj_krylov_options), C.POINTER(lj_stats), _P]),

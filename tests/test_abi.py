@@ -122,6 +122,13 @@ def test_null_arguments_are_rejected_without_device(lib):
     assert lib.lj_measure_bandwidth(1 << 20, out) == -1  # below 64 MiB: refused before any device work
     assert lib.lj_measure_bandwidth((64 << 20) + 8, out) == -1  # not a multiple of 16
     assert lib.lj_measure_bandwidth(1 << 30, None) == -1
+    # shaped probe: launch shape, accesses in flight and vector size checked first
+    assert lib.lj_measure_bandwidth_shape(1 << 30, 0, 256, 1, 0, out) == -1
+    assert lib.lj_measure_bandwidth_shape(1 << 30, 1024, 100, 1, 0, out) == -1
+    assert lib.lj_measure_bandwidth_shape(1 << 30, 1024, 2048, 1, 0, out) == -1
+    assert lib.lj_measure_bandwidth_shape(1 << 30, 1024, 256, 3, 0, out) == -1
+    assert lib.lj_measure_bandwidth_shape(1 << 20, 1024, 256, 1, 0, out) == -1
+    assert lib.lj_measure_bandwidth_shape(1 << 30, 1024, 256, 2, 1, None) == -1
     assert lib.lj_phi_combination(None, None, 1, None, 1.0, 1e-10, None, None, None, None) == -1
     assert lib.lj_user_phi_combination(None, None, 1, None, 1.0, 1e-10, None, None, None, None) == -1
     assert lib.lj_user_phi_action(None, None, None, None, 1, 1.0, 1e-10, None, None, None) == -1
