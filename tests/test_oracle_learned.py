@@ -1,6 +1,9 @@
 """Pins of the learned-proposal oracle (features and the FP64 network): closed
 forms of the features on special states, an independent loop-based feature
-computation on tiny grids, central finite differences for the back-propagated
+computation on tiny grids, the Gershgorin bound against the row sums of the
+dense Jacobian assembled column by column from the oracle's own product
+J e_q (every family, Neumann boundaries and grids so small that stencil
+places coincide), central finite differences for the back-propagated
 gradient, and the closed form of Adam's first step."""
 import math
 
@@ -9,7 +12,9 @@ import pytest
 
 from oracle import features as F
 from oracle import mlp
-from workloads import adr_neumann, advdiff_bump, allen_cahn_noise, burgers_sines
+from oracle.operators import Operator
+from workloads import (adr_neumann, advdiff_bump, allen_cahn_noise, brusselator_perturbed, burgers_sines,
+                       diag_problem, gray_scott_spots)
 from workloads.problems import Problem
 
 
@@ -19,8 +24,10 @@ def test_feature_count_and_pure_diffusion():
     f = F.features(p, h, 1)
     assert f.shape == (16,)
     sigma = 2.0 * (1 / p.dx ** 2 + 1 / p.dy ** 2)
-    assert f[0] == pytest.approx(math.log10(h * sigma), rel=1e-15)
-    assert f[1] == 0.25 and f[14] == pytest.approx(math.log10(1 + h * sigma))
+    # pure diffusion: |centre| = 2 sigma, the four neighbours add 2 sigma
+    assert F.gershgorin(p) == pytest.approx(4.0 * sigma, rel=1e-15)
+    assert f[0] == pytest.approx(math.log10(4.0 * h * sigma), rel=1e-15)
+    assert f[1] == 0.25 and f[14] == pytest.approx(math.log10(4.0))
     # no advection, no reaction, no state
     assert np.all(f[[2, 3, 4, 5, 6, 7, 8, 9, 10, 11, 13, 15]] == 0.0)
     assert f[12] == pytest.approx(math.log10(32 * 32) / 7)
@@ -47,6 +54,8 @@ def test_allen_cahn_constant_state():
     assert f[6] == pytest.approx(math.log10(1 + 0.5 * r))
     assert f[8] == pytest.approx(1.0) and f[9] == pytest.approx(0.0, abs=1e-15)
     assert f[10] == pytest.approx(math.log10(1.3)) and f[11] == 0.0
+    # |-2 sigma + r| + 2 sigma with 2 sigma > r
+    assert F.gershgorin(p) == pytest.approx(4.0 * sigma - r, rel=1e-14)
 
 
 def test_burgers_single_sine_closed_form():
@@ -75,9 +84,34 @@ def _features_by_loops(p, h, l):
             return u[min(max(j, 0), ny - 1) * nx + min(max(i, 0), nx - 1)]
         return u[(j % ny) * nx + (i % nx)]
 
-    rs, gs = [], []
+    rs, gs, rows = [], [], []
+    D0 = p.coef[0]
     for j in range(ny):
         for i in range(nx):
+            # Gershgorin row of (i, j): entries per neighbour grid point, then |.|
+            ent = {}
+
+            def put(ii, jj, a):
+                if p.kind == "adr":
+                    key = (min(max(ii, 0), nx - 1), min(max(jj, 0), ny - 1))
+                else:
+                    key = (ii % nx, jj % ny)
+                ent[key] = ent.get(key, 0.0) + a
+            cx, cy = D0 / p.dx ** 2, D0 / p.dy ** 2
+            if p.kind == "allencahn":
+                put(i, j, -2 * (cx + cy) + 1 - 3 * at(i, j) ** 2)
+                put(i - 1, j, cx), put(i + 1, j, cx), put(i, j - 1, cy), put(i, j + 1, cy)
+            elif p.kind == "adr":
+                c = at(i, j)
+                be = p.coef[1]
+                put(i, j, -2 * (cx + cy) + p.coef[2] * (3 * c - 3 * c * c - 0.5))
+                put(i - 1, j, cx - be / (2 * p.dx)), put(i + 1, j, cx + be / (2 * p.dx))
+                put(i, j - 1, cy - be / (2 * p.dy)), put(i, j + 1, cy + be / (2 * p.dy))
+            else:  # burgers
+                put(i, j, -2 * (cx + cy))
+                put(i - 1, j, cx + at(i - 1, j) / (2 * p.dx)), put(i + 1, j, cx - at(i + 1, j) / (2 * p.dx))
+                put(i, j - 1, cy + at(i, j - 1) / (2 * p.dy)), put(i, j + 1, cy - at(i, j + 1) / (2 * p.dy))
+            rows.append(sum(abs(a) for a in ent.values()))
             if p.kind == "allencahn":
                 rs.append(1 - 3 * at(i, j) ** 2)
             elif p.kind == "adr":
@@ -97,11 +131,12 @@ def _features_by_loops(p, h, l):
     mean = sum(u) / len(u)
     std = math.sqrt(sum((x - mean) ** 2 for x in u) / len(u))
     rmax, rmin = max(rs), min(rs)
-    return [math.log10(h * sigma), l / 4, math.log10(1 + A / sigma), math.log10(1 + max(rmax, 0) / sigma),
+    G = max(rows)
+    return [math.log10(h * G), l / 4, math.log10(1 + A / sigma), math.log10(1 + max(rmax, 0) / sigma),
             math.log10(1 + max(-rmin, 0) / sigma), math.log10(1 + h * A), math.log10(1 + h * max(rmax, 0)),
             math.log10(1 + h * max(-rmin, 0)), mean / umax, std / umax, math.log10(1 + umax),
             math.log10(1 + max(gs)), math.log10(nx * ny) / 7, math.log10(p.dx / p.dy),
-            math.log10(1 + h * sigma), 0.0]
+            math.log10(G / sigma), 0.0]
 
 
 @pytest.mark.parametrize("kind", ["allencahn", "burgers", "adr"])
@@ -118,9 +153,59 @@ def test_features_match_pointwise_loops(kind):
 
 def test_targets():
     p = allen_cahn_noise(16, eps=1e-2, seed=2)
-    sigma, _, _ = F.scales(p)
-    t = F.targets(p, 4.0 * sigma, 8)
-    assert t[0] == pytest.approx(math.log(4.0)) and t[1] == 3.0
+    G = F.gershgorin(p)
+    t = F.targets(p, 0.5 * G, 8)
+    assert t[0] == pytest.approx(math.log(0.5)) and t[1] == 3.0
+
+
+def _dense_row_sum_max(p):
+    """max_i sum_j |J_ij| with column q of J = the oracle's J e_q."""
+    op = Operator(p)
+    n = p.n
+    J = np.empty((n, n))
+    for q in range(n):
+        e = np.zeros(n)
+        e[q] = 1.0
+        J[:, q] = op.jv(e)
+    return float(np.max(np.sum(np.abs(J), axis=1)))
+
+
+def _tiny(kind, nx, ny, seed):
+    rng = np.random.default_rng(seed)
+    dx, dy = 1.0 / nx, 1.3 / ny
+    if kind == "advdiff":
+        return Problem("advdiff", nx, ny, 1, dx, dy, (0.7, 9.0, -4.0), None, 1.0)
+    if kind == "allencahn":
+        return Problem("allencahn", nx, ny, 1, dx, dy, (2e-2,), rng.uniform(-1.2, 1.2, nx * ny), 1.0)
+    if kind == "burgers":
+        return Problem("burgers", nx, ny, 1, dx, dy, (3e-2,), rng.uniform(-2.0, 2.0, nx * ny), 1.0)
+    if kind == "adr":
+        return Problem("adr", nx, ny, 1, dx, dy, (1e-2, -10.0, 100.0), rng.uniform(-0.5, 1.5, nx * ny), 1.0)
+    if kind == "brusselator":
+        return Problem("brusselator", nx, ny, 2, dx, dy, (2e-3, 5e-3, 1.0, 3.0), rng.uniform(0.0, 4.0, 2 * nx * ny),
+                       1.0)
+    return Problem("grayscott", nx, ny, 2, dx, dy, (1e-3, 2e-3, 0.04, 0.06), rng.uniform(0.0, 1.0, 2 * nx * ny), 1.0)
+
+
+@pytest.mark.parametrize("kind", ["advdiff", "allencahn", "burgers", "adr", "brusselator", "grayscott"])
+@pytest.mark.parametrize("shape", [(7, 5), (2, 3), (1, 4)])
+def test_gershgorin_equals_dense_row_sums(kind, shape):
+    p = _tiny(kind, *shape, seed=3 + shape[0])
+    assert F.gershgorin(p) == pytest.approx(_dense_row_sum_max(p), rel=1e-13)
+
+
+def test_gershgorin_workload_states_and_diagonal():
+    for p in (allen_cahn_noise(8, eps=1e-2, seed=4), burgers_sines(8, nu=2e-3, seed=4), adr_neumann(6, seed=4),
+              brusselator_perturbed(6, seed=4), gray_scott_spots(8)):
+        assert F.gershgorin(p) == pytest.approx(_dense_row_sum_max(p), rel=1e-13), p.kind
+    d = diag_problem(50, -1e3, seed=5)
+    assert F.gershgorin(d) == pytest.approx(float(np.max(np.abs(d.state))), rel=0)
+    # the Gershgorin bound bounds the spectral radius
+    for kind in ("burgers", "adr", "brusselator"):
+        p = _tiny(kind, 6, 5, seed=11)
+        op = Operator(p)
+        J = np.stack([op.jv(np.eye(p.n)[q]) for q in range(p.n)], axis=1)
+        assert np.max(np.abs(np.linalg.eigvals(J))) <= F.gershgorin(p) * (1 + 1e-12)
 
 
 # ------------------------------------------------------------------ network
