@@ -455,27 +455,47 @@ LJ_API void lj_batch_destroy(lj_batch* b);
 /* Not in the paper: a small network proposes, for an action phi_l(hJ)v, the
  * spectral bound (replacing the power iteration of Sec. 2.2) and the substep
  * count (skipping expansions that would be rejected).  With
- * opt->use_proposal = 1, lj_phi_action / lj_phi_vertical compute the features,
- * run the network, and attempt the expansion once with bound =
- * LJ_PROPOSAL_MARGIN * sigma * exp(out[0]) (sigma the diffusive rate of the
- * features) and s = 2^round(out[1]) substeps; every accumulator that this
- * attempt does not converge is redone by the plain path (power iteration,
+ * opt->use_proposal = 1, lj_phi_action / lj_phi_vertical compute on the
+ * device the features and the Gershgorin bound G of J (the largest absolute
+ * row sum of J at the state: a bound of its spectral radius), run the
+ * network and decide there: bound = LJ_PROPOSAL_MARGIN * G * exp(out[0])
+ * (the network corrects the Gershgorin bound; out[0] is the largest over
+ * the K actions) and s = 2^round(out[1]) substeps (largest over the
+ * actions).  The attempt's launch reads both from device memory, so no host
+ * round trip separates the decision from the expansion; when s > 1 that
+ * launch returns at once and the host, which reads its status anyway, runs
+ * the substepped attempt at the bound it read.  Every accumulator that the
+ * attempt does not converge (or all of them, when the bound is not usable or
+ * s exceeds opt->max_substeps) is redone by the plain path (power iteration,
  * then s = 1, 2, 4, ...), whose stop test remains the judge of the error.
+ * lj_stats.proposal_bound / proposal_substeps report the decision.
  *
  * Network: 16 -> 64 -> 64 -> 2, tanh hidden units, FP32; inputs and targets
  * standardised with constants kept in the model.  Model layout (floats):
  * W1 (64x16, row-major), b1 (64), W2 (64x64), b2 (64), W3 (2x64), b3 (2),
  * feature mean (16), feature std (16), target mean (2), target std (2).
- * Targets: ln(bound / sigma) and log2(accepted substeps).  Features: 16
- * dimensionless numbers of the operator, its state, h and l (the 16 values
- * are documented with the CPU reference implementation). */
+ * Targets: ln(bound / G) and log2(accepted substeps).  Features: 16
+ * dimensionless numbers of the operator, its state, h and l, among them
+ * log10(h G) and log10(G / sigma) with sigma the diffusive rate (the 16
+ * values are documented with the CPU reference implementation). */
 #define LJ_NFEATURES 16
 #define LJ_MLP_NPARAM 5378
 #define LJ_MLP_MODEL_FLOATS 5414
-#define LJ_PROPOSAL_MARGIN 1.1
+#define LJ_PROPOSAL_MARGIN 1.02
 
 /* feats (device, 16 floats) = the features of phi_l(h J) v. */
 LJ_API int lj_features(lj_context* ctx, const lj_operator* J, double h, int l, float* feats, void* stream);
+/* *bound (host) = the Gershgorin bound of J at its state: the largest sum of
+ * absolute entries of a row of the Jacobian the action kernels apply (a
+ * boundary cell's own-neighbour entries summed first).  One reduction pass
+ * over the state; synchronises the stream.  Built-in families only. */
+LJ_API int lj_gershgorin_bound(lj_context* ctx, const lj_operator* J, double* bound, void* stream);
+/* One training record of the network for phi_l(h J) v whose plain run used
+ * spectral bound `bound` (> 0) and accepted `substeps` (a power of two):
+ * feats (device, 16 floats) as lj_features, targets (device, 2 floats) =
+ * ln(bound / G), log2(substeps).  Enqueued on the stream, no host wait. */
+LJ_API int lj_proposal_record(lj_context* ctx, const lj_operator* J, double h, int l, double bound, int substeps,
+                              float* feats, float* targets, void* stream);
 /* Glorot-uniform weights from SplitMix64(seed) in parameter order, zero
  * biases, identity standardisation, Adam state cleared. */
 LJ_API int lj_mlp_init(lj_context* ctx, uint64_t seed);

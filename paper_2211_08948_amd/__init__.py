@@ -19,7 +19,7 @@ from . import _lib
 from ._lib import (  # noqa: F401
     LJ_EHIP, LJ_EINVAL, LJ_ENOMEM, LJ_ENOTCONV, LJ_EPIRK4S3, LJ_EPIRK4S3_LEKRY, LJ_EPIRK4S3A, LJ_EPIRK4S3A_LEKRY, LJ_EXPRB2, LJ_EXPRB43, LJ_EXPRB43_U3,
     LJ_MAX_K, LJ_MAX_L, LJ_OK, LJ_OP_ADR2D, LJ_OP_ADVDIFF2D, LJ_OP_ALLENCAHN2D, LJ_OP_BRUSSELATOR2D, LJ_OP_BURGERS2D,
-    LJ_NOALLOC_SCRATCH_BYTES, LJ_OP_DIAG, LJ_OP_GRAYSCOTT2D, LejaLibraryError, lj_integrate_stats, lj_operator, lj_options, lj_stats, lj_step_record,
+    LJ_NOALLOC_SCRATCH_BYTES, LJ_OP_DIAG, LJ_OP_GRAYSCOTT2D, LJ_PROPOSAL_MARGIN, LejaLibraryError, lj_integrate_stats, lj_operator, lj_options, lj_stats, lj_step_record,
     lj_timing,
 )
 
@@ -662,6 +662,24 @@ def lj_features(ctx: Context, J: Operator, h: float, l: int, feats, stream=None)
     op = J.c_struct()
     ctx._check(ctx._lib.lj_features(ctx.handle, C.byref(op), float(h), int(l),
                                     _ftensor_ptr(feats, _lib.LJ_NFEATURES, "feats"), _stream_ptr(stream)), False)
+
+
+def lj_gershgorin_bound(ctx: Context, J: Operator, stream=None) -> float:
+    """The Gershgorin bound of J at its state (largest absolute row sum)."""
+    op = J.c_struct()
+    out = C.c_double(0.0)
+    ctx._check(ctx._lib.lj_gershgorin_bound(ctx.handle, C.byref(op), C.byref(out), _stream_ptr(stream)), False)
+    return out.value
+
+
+def lj_proposal_record(ctx: Context, J: Operator, h: float, l: int, bound: float, substeps: int, feats, targets,
+                       stream=None) -> None:
+    """feats (float32 CUDA tensor of 16) and targets (of 2) of one training
+    record: the features of phi_l(h J) v, ln(bound / G), log2(substeps)."""
+    op = J.c_struct()
+    ctx._check(ctx._lib.lj_proposal_record(ctx.handle, C.byref(op), float(h), int(l), float(bound), int(substeps),
+                                           _ftensor_ptr(feats, _lib.LJ_NFEATURES, "feats"),
+                                           _ftensor_ptr(targets, 2, "targets"), _stream_ptr(stream)), False)
 
 
 def lj_mlp_init(ctx: Context, seed: int = 6) -> None:

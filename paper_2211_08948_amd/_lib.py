@@ -19,6 +19,7 @@ LJ_NOALLOC_SCRATCH_BYTES = 32 << 20
 LJ_NFEATURES = 16
 LJ_MLP_NPARAM = 5378
 LJ_MLP_MODEL_FLOATS = 5414
+LJ_PROPOSAL_MARGIN = 1.02
 
 (LJ_OP_DIAG, LJ_OP_ADVDIFF2D, LJ_OP_ALLENCAHN2D, LJ_OP_BRUSSELATOR2D, LJ_OP_BURGERS2D, LJ_OP_GRAYSCOTT2D,
  LJ_OP_ADR2D) = range(7)
@@ -175,6 +176,9 @@ _PROTOS = {
     "lj_batch_timeline": (C.c_int, [_P, C.POINTER(C.c_int), C.POINTER(C.c_double), C.POINTER(C.c_double)]),
     "lj_batch_destroy": (None, [_P]),
     "lj_features": (C.c_int, [_P, C.POINTER(lj_operator), C.c_double, C.c_int, _P, _P]),
+    "lj_gershgorin_bound": (C.c_int, [_P, C.POINTER(lj_operator), C.POINTER(C.c_double), _P]),
+    "lj_proposal_record": (C.c_int, [_P, C.POINTER(lj_operator), C.c_double, C.c_int, C.c_double, C.c_int, _P, _P,
+                                     _P]),
     "lj_mlp_init": (C.c_int, [_P, C.c_uint64]),
     "lj_mlp_train": (C.c_int, [_P, _P, _P, C.c_int, C.c_int, C.c_int, C.c_float, C.c_int, C.POINTER(C.c_float), _P]),
     "lj_mlp_predict": (C.c_int, [_P, _P, C.c_int, _P, _P]),

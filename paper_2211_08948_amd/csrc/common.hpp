@@ -57,7 +57,9 @@ struct LejaStatus {
   int power_iters;      // Jacobian products of the power iteration (0 if skipped)
   int barriers;         // grid barriers used
   int aborted;          // 1: a grid barrier timed out (blocks not co-resident); results invalid
-  int pad;
+  int skipped;          // != 0: the launch did no work because the learned proposal's decision
+                        // (ActionParams.skip_src) asked for that many substeps (> 1) or had no
+                        // usable bound (-1)
   double vnorm;         // ||v||_2
   double lam, c, gamma; // bound used and the interval it gives
   // reduced totals of every decided Newton step m = 1..iters:
@@ -92,6 +94,7 @@ struct ActionParams {
   const double* start;    // explicit power-iteration start vector or nullptr
   double lam_in;
   const double* lam_src;  // if set (and do_power == 0): the bound is read from here (device)
+  const int* skip_src;    // if set: the launch returns at once unless *skip_src == 1 (device)
   double* lam_out;        // if set: the bound used is written here (device)
   double safety;
   // expansion

@@ -333,7 +333,8 @@ __device__ void replay_decisions(Decision& D, int K, int m0, int steps, int Q, c
 }
 
 __device__ __forceinline__ void write_status(LejaStatus* S, const Decision& D, int pit, int barriers, double nv,
-                                             double lam, double c, double gamma, unsigned int* barrier_base) {
+                                             double lam, double c, double gamma, unsigned int* barrier_base,
+                                             int skipped) {
 #pragma unroll
   for (int k = 0; k < kMaxK; ++k) {
     S->state[k] = D.st[k];
@@ -345,6 +346,7 @@ __device__ __forceinline__ void write_status(LejaStatus* S, const Decision& D, i
   S->power_iters = pit;
   S->barriers = barriers;
   S->aborted = grid_aborted(barrier_base) != 0u ? 1 : 0;
+  S->skipped = skipped;
   S->vnorm = nv;
   S->lam = lam;
   S->c = c;
@@ -356,13 +358,31 @@ __device__ __forceinline__ void write_status(LejaStatus* S, const Decision& D, i
 // there, so that the host needs no copy after the launch.
 __device__ __forceinline__ void store_status(const ActionParams& P, const Decision& D, int pit, int barriers,
                                              double nv, double lam, double c, double gamma,
-                                             const unsigned long long (&prof)[8]) {
-  write_status(P.status, D, pit, barriers, nv, lam, c, gamma, P.barrier);
+                                             const unsigned long long (&prof)[8], int skipped = 0) {
+  write_status(P.status, D, pit, barriers, nv, lam, c, gamma, P.barrier, skipped);
   for (int q = 0; q < 8; ++q) P.status->prof[q] = prof[q];
   if (P.status_host != nullptr) {
-    write_status(P.status_host, D, pit, barriers, nv, lam, c, gamma, P.barrier);
+    write_status(P.status_host, D, pit, barriers, nv, lam, c, gamma, P.barrier, skipped);
     for (int q = 0; q < 8; ++q) P.status_host->prof[q] = prof[q];
   }
+}
+
+// The learned proposal's attempt at one expansion (skip_src set) does no work
+// when the proposal's decision, made on the device before the launch, asked
+// for substeps or found no usable bound (*skip_src != 1): block 0 records the
+// request and the bound in the status, every block leaves.  Returns true
+// then; called by every thread with the same arguments.
+__device__ __forceinline__ bool skip_launch(const ActionParams& P, double lam, const unsigned long long (&prof)[8]) {
+  if (P.skip_src == nullptr) return false;
+  const int sk = __builtin_amdgcn_readfirstlane(*P.skip_src);
+  if (sk == 1) return false;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    Decision D;
+    decision_init(D, 0, 1.0, 0.0, nullptr);
+    store_status(P, D, 0, 0, 0.0, lam, 0.0, 0.0, prof, sk);
+  }
+  grid_exit(P.barrier);
+  return true;
 }
 
 // ---------------------------------------------------------------------------
@@ -489,6 +509,7 @@ __global__ __launch_bounds__(kBlock) void lj_action_stream(ActionParams P) {
 
   // (1) spectral bound
   double lam = (P.lam_src != nullptr && !P.do_power) ? *P.lam_src : P.lam_in;
+  if (skip_launch(P, lam, prof)) return;
   int pit = 0;
   if (P.do_power) {
     const double* x0 = P.start;
@@ -813,6 +834,7 @@ __global__ __launch_bounds__(kBlock) void lj_action_tile(ActionParams P) {
 
   // ---- (1) spectral bound: S products between barriers, normalised per barrier
   double lam = (P.lam_src != nullptr && !P.do_power) ? *P.lam_src : P.lam_in;
+  if (skip_launch(P, lam, prof)) return;
   int pit = 0;
   if (P.do_power) {
 #pragma unroll
@@ -1216,6 +1238,7 @@ __global__ __launch_bounds__(kRegBlock) void lj_action_reg(ActionParams P) {
 
   // ---- (1) spectral bound: up to 16 products between barriers, normalised per barrier
   double lam = (P.lam_src != nullptr && !P.do_power) ? *P.lam_src : P.lam_in;
+  if (skip_launch(P, lam, prof)) return;
   int pit = 0;
   if (!P.do_power && K > 0) {  // y_0 = v: the loads fly while the bound and the table are formed
 #pragma unroll
@@ -1595,6 +1618,7 @@ __global__ __launch_bounds__(kRegBlock) void lj_action_regm(ActionParams P) {
   // ---- (1) spectral bound: up to 16 products per super-step over all tiles,
   // normalised per super-step
   double lam = (P.lam_src != nullptr && !P.do_power) ? *P.lam_src : P.lam_in;
+  if (skip_launch(P, lam, prof)) return;
   int pit = 0;
   int r = 0;  // exchange vector read this super-step; the next one is written
   if (P.do_power) {

@@ -123,7 +123,8 @@ struct lj_context {
   void* d_featpart = nullptr;
   float* d_feats = nullptr;  // kMaxK x 16
   float* d_pred = nullptr;   // kMaxK x 2
-  double* d_sigma = nullptr;
+  double* d_gers = nullptr;            // Gershgorin bound of the last feature pass
+  ProposalOut* d_prop = nullptr;       // the learned proposal's decision (device)
   bool mlp_ready = false;
   // user operators (callbacks): the operator of the running call, its
   // decision state and pinned status, partial sums, the Leja table on the host
@@ -219,6 +220,7 @@ struct Opts {
   uint64_t seed;
   const double* pi_start;
   const double* bound_device;  // the bound read by the launch from device memory (when bound == 0)
+  const int* skip_src = nullptr;  // the learned proposal's substep decision (device), see skip_launch
 };
 
 Opts resolve(lj_context* ctx, const lj_options* o) {
@@ -428,6 +430,7 @@ RegPlan reg_plan(lj_context* ctx, const OpDev& op, int K) {
 // ---- one phi-action launch ------------------------------------------------
 struct ActOut {
   bool aborted;  // a grid barrier timed out: the launch must be repeated cooperatively
+  int skipped;   // the launch did no work: the proposal's request (LejaStatus.skipped)
   int state[kMaxK];
   int m_star[kMaxK];
   double err[kMaxK];
@@ -512,6 +515,7 @@ void launch_action(lj_context* ctx, const OpDev& op, const double* v, int K, con
   P.start = start;
   P.lam_in = lam_host;
   P.lam_src = link.src;
+  P.skip_src = o.skip_src;
   P.lam_out = link.dst;
   P.safety = o.safety;
   P.v = v;
@@ -598,6 +602,7 @@ void launch_action(lj_context* ctx, const OpDev& op, const double* v, int K, con
 ActOut finish_action(lj_context* ctx, const OpDev& op, const LejaStatus& S, hipEvent_t* ev, bool tiled) {
   ActOut r;
   r.aborted = S.aborted != 0;
+  r.skipped = S.skipped;
   if (r.aborted) ctx->tm.aborts += 1;
   for (int k = 0; k < kMaxK; ++k) {
     r.state[k] = S.state[k];
@@ -958,29 +963,48 @@ int vertical_impl(lj_context* ctx, const OpDev& op, const double* v, int K, cons
   int s0 = (o.substeps > 1) ? o.substeps : 1;
   if (!(lam > 0.0) && o.bound_device && (s0 > 1 || is_user(op))) lam = bound_to_host(ctx, o.bound_device, s);
   std::vector<int> pending;
+  Opts os = o;  // the later launches never take the learned proposal's skip
+  os.skip_src = nullptr;
+  bool interval_needed = (s0 > 1);
   if (s0 == 1) {
     double sk[kMaxK];
     for (int k = 0; k < K; ++k) sk[k] = a[k] * h;
     ActOut r = run_action(ctx, op, v, K, l, sk, lam, o.seed, o.pi_start, w, o, tol, s);
-    st->power_iters = r.power_iters;
-    st->iters_total += r.iters;
-    lam = r.lam;
-    st->bound = r.lam;
-    st->c = r.c;
-    st->gamma = r.gamma;
-    for (int k = 0; k < K; ++k) {
-      if (r.state[k] == ACC_CONVERGED) {
-        st->m_star[k] = r.m_star[k];
-        st->err_est[k] = r.err[k];
-      } else {
-        pending.push_back(k);
-      }
+    if (o.skip_src != nullptr) {  // the learned proposal's attempt (lj_phi_vertical)
+      st->proposal_bound = r.skipped >= 0 ? r.lam : 0.0;
+      st->proposal_substeps = r.skipped == 0 ? 1 : (r.skipped > 0 ? r.skipped : 0);
     }
-    if (!pending.empty()) st->rejections += 1;
-    s0 = 2;
-  } else {
+    if (r.skipped < 0) return LJ_ENOTCONV;  // no usable proposal: every accumulator pending
+    if (r.skipped > 1) {
+      // the proposal asked for substeps and the launch did no work: one
+      // attempt at that count with the bound it read
+      os.max_substeps = r.skipped;
+      os.bound_device = nullptr;
+      lam = r.lam;
+      s0 = r.skipped;
+      interval_needed = true;
+    } else {
+      st->power_iters = r.power_iters;
+      st->iters_total += r.iters;
+      lam = r.lam;
+      st->bound = r.lam;
+      st->c = r.c;
+      st->gamma = r.gamma;
+      for (int k = 0; k < K; ++k) {
+        if (r.state[k] == ACC_CONVERGED) {
+          st->m_star[k] = r.m_star[k];
+          st->err_est[k] = r.err[k];
+        } else {
+          pending.push_back(k);
+        }
+      }
+      if (!pending.empty()) st->rejections += 1;
+      s0 = 2;
+    }
+  }
+  if (interval_needed) {
     if (!(lam > 0.0)) {
-      lam = run_bound(ctx, op, o, o.power_iters, o.seed, o.pi_start, s);
+      lam = run_bound(ctx, op, os, o.power_iters, o.seed, o.pi_start, s);
       st->power_iters = o.power_iters;
     }
     double c = 0.0, gamma = 0.0;
@@ -996,7 +1020,7 @@ int vertical_impl(lj_context* ctx, const OpDev& op, const double* v, int K, cons
   }
   bool all_ok = true;
   for (int k : pending) {
-    if (!substepped(ctx, op, v, l[k], a[k] * h, s0, lam, o, tol, w[k], st, k, s)) all_ok = false;
+    if (!substepped(ctx, op, v, l[k], a[k] * h, s0, lam, os, tol, w[k], st, k, s)) all_ok = false;
   }
   st->converged = all_ok ? 1 : 0;
   return all_ok ? LJ_OK : LJ_ENOTCONV;
@@ -1090,7 +1114,8 @@ void mlp_alloc(lj_context* ctx) {
   HIPCHK(ctx, hipMalloc(&ctx->d_featpart, feature_partial_bytes()));
   HIPCHK(ctx, hipMalloc(&ctx->d_feats, kMaxK * kMlpIn * sizeof(float)));
   HIPCHK(ctx, hipMalloc(&ctx->d_pred, kMaxK * kMlpOut * sizeof(float)));
-  HIPCHK(ctx, hipMalloc(&ctx->d_sigma, sizeof(double)));
+  HIPCHK(ctx, hipMalloc(&ctx->d_gers, sizeof(double)));
+  HIPCHK(ctx, hipMalloc(&ctx->d_prop, sizeof(ProposalOut)));
 }
 
 // Glorot uniform weights a (2U - 1), a = sqrt(6 / (fan_in + fan_out)), U the
@@ -1122,9 +1147,13 @@ void check_fvec(lj_context* ctx, const void* p, size_t count, const char* what) 
   check_range(ctx, p, count * sizeof(float), what);
 }
 
-// The proposal for the K actions phi_{l_k}(a_k h J) v: bound and substeps.
-void propose(lj_context* ctx, const OpDev& op, int K, const int* l, const double* a, double h, hipStream_t s,
-             double& bound, int& substeps) {
+// The proposal for the K actions phi_{l_k}(a_k h J) v, decided on the
+// device: features of (J, a_k h, l_k) with the Gershgorin bound G of J, the
+// network, and the decision kernel, which writes the bound and the substep
+// count into ctx->d_prop.  Nothing is read back: the attempt's launch reads
+// both from there.
+void propose(lj_context* ctx, const OpDev& op, int K, const int* l, const double* a, double h, int max_substeps,
+             hipStream_t s) {
   if (!ctx->mlp_ready) invalid(ctx, "use_proposal: no trained network (lj_mlp_train, lj_mlp_set or lj_mlp_load)");
   FeatureJob J;
   std::memset(&J, 0, sizeof(J));
@@ -1134,22 +1163,9 @@ void propose(lj_context* ctx, const OpDev& op, int K, const int* l, const double
     J.h[k] = a[k] * h;
     J.l[k] = l[k];
   }
-  HIPCHK(ctx, launch_features(J, ctx->d_featpart, ctx->d_feats, ctx->d_sigma, s));
+  HIPCHK(ctx, launch_features(J, ctx->d_featpart, ctx->d_feats, ctx->d_gers, s));
   HIPCHK(ctx, launch_mlp_forward(ctx->d_model, ctx->d_feats, K, ctx->d_pred, s));
-  float pred[kMaxK * kMlpOut];
-  double sigma = 0.0;
-  HIPCHK(ctx, hipMemcpyAsync(pred, ctx->d_pred, K * kMlpOut * sizeof(float), hipMemcpyDeviceToHost, s));
-  HIPCHK(ctx, hipMemcpyAsync(&sigma, ctx->d_sigma, sizeof(double), hipMemcpyDeviceToHost, s));
-  HIPCHK(ctx, hipStreamSynchronize(s));
-  double lb = pred[0], ls = pred[1];
-  for (int k = 1; k < K; ++k) {
-    lb = std::max(lb, (double)pred[kMlpOut * k]);
-    ls = std::max(ls, (double)pred[kMlpOut * k + 1]);
-  }
-  bound = LJ_PROPOSAL_MARGIN * sigma * std::exp(std::min(lb, 50.0));
-  if (!(bound > 0.0) || !std::isfinite(bound)) bound = 0.0;  // unusable: the plain path decides
-  const int e = (int)std::lround(std::min(std::max(ls, 0.0), 20.0));
-  substeps = 1 << e;
+  HIPCHK(ctx, launch_proposal_decide(ctx->d_pred, K, ctx->d_gers, LJ_PROPOSAL_MARGIN, max_substeps, ctx->d_prop, s));
 }
 
 // Runs an entry point: device selection, error text, no exception across the
@@ -1664,7 +1680,8 @@ LJ_API void lj_destroy(lj_context* ctx) {
   if (ctx->d_featpart) (void)hipFree(ctx->d_featpart);
   if (ctx->d_feats) (void)hipFree(ctx->d_feats);
   if (ctx->d_pred) (void)hipFree(ctx->d_pred);
-  if (ctx->d_sigma) (void)hipFree(ctx->d_sigma);
+  if (ctx->d_gers) (void)hipFree(ctx->d_gers);
+  if (ctx->d_prop) (void)hipFree(ctx->d_prop);
   if (ctx->h_status) (void)hipHostFree(ctx->h_status);
   if (ctx->h_coef) (void)hipHostFree(ctx->h_coef);
   for (hipEvent_t e : ctx->tev)
@@ -1825,23 +1842,17 @@ LJ_API int lj_phi_vertical(lj_context* ctx, const lj_operator* J, const double* 
     lj_stats* st = stats ? stats : &local;
     const hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     if (!o.use_proposal) return vertical_impl(ctx, op, v, K, l, a, h, tol, w, o, st, s);
-    // learned proposal: one attempt with the proposed bound and substeps ...
-    double pb = 0.0;
-    int ps = 1;
-    propose(ctx, op, K, l, a, h, s, pb, ps);
-    int rc = LJ_ENOTCONV;
-    if (pb > 0.0 && ps <= o.max_substeps) {
-      Opts o1 = o;
-      o1.bound = pb;
-      o1.substeps = (ps > 1) ? ps : 0;
-      o1.max_substeps = ps;
-      rc = vertical_impl(ctx, op, v, K, l, a, h, tol, w, o1, st, s);
-    } else {
-      std::memset(st, 0, sizeof(*st));
-      for (int k = 0; k < LJ_MAX_K; ++k) st->m_star[k] = -1;
-    }
-    st->proposal_bound = pb;
-    st->proposal_substeps = ps;
+    // learned proposal: one attempt with the bound and substeps that the
+    // device decides (propose); the attempt's launch reads both, so the host
+    // waits only for the launch's status, as on the plain path ...
+    propose(ctx, op, K, l, a, h, o.max_substeps, s);
+    Opts o1 = o;
+    o1.bound = 0.0;
+    o1.bound_device = &ctx->d_prop->bound;
+    o1.skip_src = &ctx->d_prop->sub;
+    o1.substeps = 0;
+    o1.max_substeps = 1;
+    const int rc = vertical_impl(ctx, op, v, K, l, a, h, tol, w, o1, st, s);
     if (rc == LJ_OK) return LJ_OK;
     // ... and the plain path for every accumulator it did not converge
     std::vector<int> pk, pl;
@@ -2680,7 +2691,48 @@ LJ_API int lj_features(lj_context* ctx, const lj_operator* J, double h, int l, f
     Jb.K = 1;
     Jb.h[0] = h;
     Jb.l[0] = l;
-    HIPCHK(ctx, launch_features(Jb, ctx->d_featpart, feats, ctx->d_sigma, reinterpret_cast<hipStream_t>(stream)));
+    HIPCHK(ctx, launch_features(Jb, ctx->d_featpart, feats, ctx->d_gers, reinterpret_cast<hipStream_t>(stream)));
+    return LJ_OK;
+  });
+}
+
+LJ_API int lj_gershgorin_bound(lj_context* ctx, const lj_operator* J, double* bound, void* stream) {
+  return guarded(ctx, [&]() {
+    const OpDev op = make_op(ctx, J);
+    if (!bound) invalid(ctx, "bound is NULL");
+    if (is_user(op)) invalid(ctx, "lj_gershgorin_bound needs a built-in operator family");
+    mlp_alloc(ctx);
+    FeatureJob Jb;
+    std::memset(&Jb, 0, sizeof(Jb));
+    Jb.op = op;
+    const hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    HIPCHK(ctx, launch_features(Jb, ctx->d_featpart, nullptr, ctx->d_gers, s));
+    HIPCHK(ctx, hipMemcpyAsync(bound, ctx->d_gers, sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(ctx, hipStreamSynchronize(s));
+    return LJ_OK;
+  });
+}
+
+LJ_API int lj_proposal_record(lj_context* ctx, const lj_operator* J, double h, int l, double bound, int substeps,
+                              float* feats, float* targets, void* stream) {
+  return guarded(ctx, [&]() {
+    const OpDev op = make_op(ctx, J);
+    if (!std::isfinite(h) || !(h > 0.0)) invalid(ctx, "h must be finite and > 0");
+    if (l < 0 || l > LJ_MAX_L) invalid(ctx, "l must be in [0, 4]");
+    if (!std::isfinite(bound) || !(bound > 0.0)) invalid(ctx, "bound must be finite and > 0");
+    if (substeps < 1 || (substeps & (substeps - 1)) != 0) invalid(ctx, "substeps must be a power of two >= 1");
+    check_fvec(ctx, feats, kMlpIn, "feats");
+    check_fvec(ctx, targets, kMlpOut, "targets");
+    mlp_alloc(ctx);
+    FeatureJob Jb;
+    std::memset(&Jb, 0, sizeof(Jb));
+    Jb.op = op;
+    Jb.K = 1;
+    Jb.h[0] = h;
+    Jb.l[0] = l;
+    const hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    HIPCHK(ctx, launch_features(Jb, ctx->d_featpart, feats, ctx->d_gers, s));
+    HIPCHK(ctx, launch_proposal_targets(ctx->d_gers, bound, substeps, targets, s));
     return LJ_OK;
   });
 }

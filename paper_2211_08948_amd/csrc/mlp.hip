@@ -21,7 +21,62 @@ namespace lj {
 // ---------------------------------------------------------------------------
 struct FeatPartial {
   double sum, sumsq, umax, gmax, rmax, rmin, lmax;  // lmax: max|diagonal| (diagonal operators)
+  double gers;                                      // max over rows of sum_j |J_ij| (Gershgorin)
 };
+
+// Largest absolute row sum of J over the NC rows of point p (the Gershgorin
+// bound of the spectral radius, rows of p).  The entries of those rows are
+// read off stencil_jv -- the product the action kernels apply -- with a unit
+// value in one of the five stencil places and one component at a time;
+// places that are the same grid point (a Neumann boundary cell is its own
+// neighbour; tiny periodic grids) are summed before the absolute value.
+template <int KIND, int NC>
+__device__ double gershgorin_rows(const OpDev& op, int p) {
+  const Nbr q = neighbours<KIND>(op, p);
+  const int idx[5] = {q.c, q.w, q.e, q.s, q.n};
+  double uv[5][2] = {{0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}};
+  if (StateUse<KIND>::value > 0 || KIND == OP_DIAG) {
+#pragma unroll
+    for (int t = 0; t < 5; ++t)
+#pragma unroll
+      for (int c = 0; c < NC; ++c) uv[t][c] = op.state[NC * idx[t] + c];
+  }
+  double co[5][2][2];  // co[place][input component][output component]
+#pragma unroll
+  for (int t = 0; t < 5; ++t) {
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      double x[5][2] = {{0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}};
+      x[t][c] = 1.0;
+      double out[2] = {0.0, 0.0};
+      stencil_jv<KIND>(op, x, uv, out);
+      co[t][c][0] = out[0];
+      co[t][c][1] = out[1];
+    }
+  }
+  double best = 0.0;
+#pragma unroll
+  for (int cc = 0; cc < NC; ++cc) {
+    double row = 0.0;
+#pragma unroll
+    for (int t = 0; t < 5; ++t) {
+      bool seen = false;
+#pragma unroll
+      for (int t2 = 0; t2 < t; ++t2) seen = seen || (idx[t2] == idx[t]);
+      if (seen) continue;
+#pragma unroll
+      for (int c = 0; c < NC; ++c) {
+        double a = 0.0;
+#pragma unroll
+        for (int t2 = t; t2 < 5; ++t2)
+          if (idx[t2] == idx[t]) a += co[t2][c][cc];
+        row += fabs(a);
+      }
+    }
+    best = fmax(best, row);
+  }
+  return best;
+}
 
 // local reaction rate r(p) of J and the first state component u(p)
 template <int KIND, int NC>
@@ -56,7 +111,9 @@ __device__ __forceinline__ void reaction_at(const OpDev& op, int p, double& u, d
 template <int KIND, int NC>
 __global__ __launch_bounds__(256) void lj_feature_partials(OpDev op, FeatPartial* part) {
   double sum = 0.0, sumsq = 0.0, umax = 0.0, gmax = 0.0, rmax = -INFINITY, rmin = INFINITY, lmax = 0.0;
+  double gers = 0.0;
   for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < op.npts; p += gridDim.x * blockDim.x) {
+    gers = fmax(gers, gershgorin_rows<KIND, NC>(op, p));
     double u, r, g;
     reaction_at<KIND, NC>(op, p, u, r, g);
     sum += u;
@@ -67,9 +124,9 @@ __global__ __launch_bounds__(256) void lj_feature_partials(OpDev op, FeatPartial
     rmin = fmin(rmin, r);
     if constexpr (KIND == OP_DIAG) lmax = fmax(lmax, fabs(op.state[p]));
   }
-  __shared__ double red[7][4];
+  __shared__ double red[8][4];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  double v[7] = {wave_sum(sum), wave_sum(sumsq), umax, gmax, rmax, rmin, lmax};
+  double v[8] = {wave_sum(sum), wave_sum(sumsq), umax, gmax, rmax, rmin, lmax, gers};
 #pragma unroll
   for (int off = 32; off >= 1; off >>= 1) {
     v[2] = fmax(v[2], __shfl_xor(v[2], off, 64));
@@ -77,12 +134,13 @@ __global__ __launch_bounds__(256) void lj_feature_partials(OpDev op, FeatPartial
     v[4] = fmax(v[4], __shfl_xor(v[4], off, 64));
     v[5] = fmin(v[5], __shfl_xor(v[5], off, 64));
     v[6] = fmax(v[6], __shfl_xor(v[6], off, 64));
+    v[7] = fmax(v[7], __shfl_xor(v[7], off, 64));
   }
   if (lane == 0)
-    for (int i = 0; i < 7; ++i) red[i][w] = v[i];
+    for (int i = 0; i < 8; ++i) red[i][w] = v[i];
   __syncthreads();
   if (threadIdx.x == 0) {
-    FeatPartial P{0.0, 0.0, 0.0, 0.0, -INFINITY, INFINITY, 0.0};
+    FeatPartial P{0.0, 0.0, 0.0, 0.0, -INFINITY, INFINITY, 0.0, 0.0};
     for (int ww = 0; ww < (int)(blockDim.x >> 6); ++ww) {
       P.sum += red[0][ww];
       P.sumsq += red[1][ww];
@@ -91,18 +149,20 @@ __global__ __launch_bounds__(256) void lj_feature_partials(OpDev op, FeatPartial
       P.rmax = fmax(P.rmax, red[4][ww]);
       P.rmin = fmin(P.rmin, red[5][ww]);
       P.lmax = fmax(P.lmax, red[6][ww]);
+      P.gers = fmax(P.gers, red[7][ww]);
     }
     part[blockIdx.x] = P;
   }
 }
 
 // Combines the block partials in block order and writes the features of the
-// K actions (h_k, l_k) as rows of 16 floats; sigma_out receives sigma.
+// K actions (h_k, l_k) as rows of 16 floats (feats may be NULL); gers_out
+// receives the Gershgorin bound G.
 __global__ void lj_feature_finish(FeatureJob J, const FeatPartial* part, int nparts, float* feats,
-                                  double* sigma_out) {
+                                  double* gers_out) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
   const OpDev& op = J.op;
-  FeatPartial P{0.0, 0.0, 0.0, 0.0, -INFINITY, INFINITY, 0.0};
+  FeatPartial P{0.0, 0.0, 0.0, 0.0, -INFINITY, INFINITY, 0.0, 0.0};
   for (int b = 0; b < nparts; ++b) {
     P.sum += part[b].sum;
     P.sumsq += part[b].sumsq;
@@ -111,7 +171,11 @@ __global__ void lj_feature_finish(FeatureJob J, const FeatPartial* part, int npa
     P.rmax = fmax(P.rmax, part[b].rmax);
     P.rmin = fmin(P.rmin, part[b].rmin);
     P.lmax = fmax(P.lmax, part[b].lmax);
+    P.gers = fmax(P.gers, part[b].gers);
   }
+  const double G = P.gers;
+  *gers_out = G;
+  if (feats == nullptr) return;
   const bool has_state = !(op.kind == OP_DIAG || op.kind == OP_ADVDIFF);
   double sigma, A = 0.0;
   if (op.kind == OP_DIAG) {
@@ -137,7 +201,7 @@ __global__ void lj_feature_finish(FeatureJob J, const FeatPartial* part, int npa
   for (int k = 0; k < J.K; ++k) {
     const double h = J.h[k];
     float* f = feats + 16 * k;
-    f[0] = (float)log10(h * sigma);
+    f[0] = (float)log10(h * G);
     f[1] = (float)(J.l[k] / 4.0);
     f[2] = (float)log10(1.0 + A / sigma);
     f[3] = (float)log10(1.0 + fmax(rmax, 0.0) / sigma);
@@ -151,10 +215,36 @@ __global__ void lj_feature_finish(FeatureJob J, const FeatPartial* part, int npa
     f[11] = (float)log10(1.0 + gmax);
     f[12] = (float)(log10(n) / 7.0);
     f[13] = (float)log10(dx_over_dy);
-    f[14] = (float)log10(1.0 + h * sigma);
+    f[14] = (float)log10(G / sigma);
     f[15] = (float)(op.ncomp - 1);
   }
-  *sigma_out = sigma;
+}
+
+// The proposal from the network's outputs pred (K rows of 2): bound =
+// margin * G * exp(max_k pred[k][0]) and s = 2^round(max_k pred[k][1]) (s in
+// 1 .. 2^20); out->sub = s, or -1 when the bound is not usable or s exceeds
+// max_substeps (the caller then takes the plain path).
+__global__ void lj_proposal_decide(const float* pred, int K, const double* gers, double margin, int max_substeps,
+                                   ProposalOut* out) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  double lb = pred[0], ls = pred[1];
+  for (int k = 1; k < K; ++k) {
+    lb = fmax(lb, (double)pred[kMlpOut * k]);
+    ls = fmax(ls, (double)pred[kMlpOut * k + 1]);
+  }
+  const double bound = margin * (*gers) * exp(fmin(lb, 50.0));
+  const int e = (int)rint(fmin(fmax(ls, 0.0), 20.0));
+  const int sub = 1 << e;
+  const bool ok = bound > 0.0 && isfinite(bound) && sub <= max_substeps;
+  out->bound = ok ? bound : 0.0;
+  out->sub = ok ? sub : -1;
+}
+
+// Training targets of one record: ln(bound / G) and log2(substeps).
+__global__ void lj_proposal_targets(const double* gers, double bound, int substeps, float* target) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  target[0] = (float)log(bound / *gers);
+  target[1] = (float)log2((double)substeps);
 }
 
 // ---------------------------------------------------------------------------
@@ -422,7 +512,7 @@ __global__ void lj_mlp_normalize_kernel(float* model, const float* X, const floa
 // ---------------------------------------------------------------------------
 // Launch wrappers
 // ---------------------------------------------------------------------------
-hipError_t launch_features(const FeatureJob& J, FeatPartialBuf part, float* feats, double* sigma_out,
+hipError_t launch_features(const FeatureJob& J, FeatPartialBuf part, float* feats, double* gers_out,
                            hipStream_t s) {
   const int nparts = kFeatureBlocks;
   switch (J.op.kind) {
@@ -458,7 +548,18 @@ hipError_t launch_features(const FeatureJob& J, FeatPartialBuf part, float* feat
       return hipErrorInvalidValue;
   }
   hipLaunchKernelGGL(lj_feature_finish, dim3(1), dim3(64), 0, s, J, reinterpret_cast<const FeatPartial*>(part),
-                     nparts, feats, sigma_out);
+                     nparts, feats, gers_out);
+  return hipGetLastError();
+}
+
+hipError_t launch_proposal_decide(const float* pred, int K, const double* gers, double margin, int max_substeps,
+                                  ProposalOut* out, hipStream_t s) {
+  hipLaunchKernelGGL(lj_proposal_decide, dim3(1), dim3(64), 0, s, pred, K, gers, margin, max_substeps, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_proposal_targets(const double* gers, double bound, int substeps, float* target, hipStream_t s) {
+  hipLaunchKernelGGL(lj_proposal_targets, dim3(1), dim3(64), 0, s, gers, bound, substeps, target);
   return hipGetLastError();
 }
 

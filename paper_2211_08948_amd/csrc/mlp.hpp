@@ -30,11 +30,24 @@ struct FeatureJob {
   int l[kMaxK];
 };
 
+// The learned proposal's decision, written on the device: the bound and the
+// substep count of the attempt (sub = -1: no usable proposal).
+struct ProposalOut {
+  double bound;
+  int sub;
+  int pad;
+};
+
 using FeatPartialBuf = void*;
 size_t feature_partial_bytes();
 
-hipError_t launch_features(const FeatureJob& J, FeatPartialBuf part, float* feats, double* sigma_out,
+// Features of the K actions of J (rows of 16 floats; feats may be NULL) and
+// the Gershgorin bound G of J (gers_out, device).
+hipError_t launch_features(const FeatureJob& J, FeatPartialBuf part, float* feats, double* gers_out,
                            hipStream_t s);
+hipError_t launch_proposal_decide(const float* pred, int K, const double* gers, double margin, int max_substeps,
+                                  ProposalOut* out, hipStream_t s);
+hipError_t launch_proposal_targets(const double* gers, double bound, int substeps, float* target, hipStream_t s);
 hipError_t launch_mlp_forward(const float* model, const float* X, int n, float* out, hipStream_t s);
 hipError_t launch_mlp_grad(const float* model, const float* X, const float* T, int n, float* rows, float* grad,
                            float* loss, hipStream_t s);

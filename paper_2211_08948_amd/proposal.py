@@ -7,23 +7,28 @@ network kernels); this module only assembles inputs and collects statistics.
     python -m paper_2211_08948_amd.proposal train  --records N --out FILE.bin
     python -m paper_2211_08948_amd.proposal evaluate --model FILE.bin [--n 2048]
 
-Records: for each problem of the seeded training sweep (advection-diffusion
-and Allen-Cahn, workloads.proposal_training_set) one batched vertical run of
-phi_1, phi_2, phi_3 of v (the bump input, or h f(u)) with the instance's own
-power-iteration bound; each accumulator gives one record (features of
-(J, h, l); targets ln(bound / sigma), log2(accepted substeps)).
+Records: for each problem of the seeded training sweep (advection-diffusion,
+Allen-Cahn and Burgers on grids of 32^2 to 512^2,
+workloads.proposal_training_set)
+one batched vertical run of phi_1, phi_2, phi_3 of v (the bump input, or
+h f(u)) with the instance's own power-iteration bound; each accumulator gives
+one record, formed by the library (lj_proposal_record): features of (J, h, l)
+and targets ln(bound / G), log2(accepted substeps), G the Gershgorin bound.
 """
 from __future__ import annotations
 
 import argparse
 import json
-import math
 import os
 import sys
 import time
 
 TOL = 1e-10
 LS = (1, 2, 3)
+# grid sizes of the training sweep and their relative frequencies (the large
+# grids are few: a 512^2 instance costs 64 times a 64^2 one)
+TRAIN_SIZES = (32, 48, 64, 96, 128, 192, 256, 384, 512)
+TRAIN_WEIGHTS = (6, 6, 6, 6, 6, 1, 1, 0.5, 0.5)
 MODEL_FILE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "proposal_mlp.bin")
 
 
@@ -32,18 +37,19 @@ def _lj():
     return lj
 
 
-def make_records(ctx, count: int, seed: int = 7, chunk: int = 512, hmult=(1.0, 100.0), log=print):
+def make_records(ctx, count: int, seed: int = 7, chunk: int = 256, hmult=(1.0, 100.0), sizes=TRAIN_SIZES,
+                 weights=TRAIN_WEIGHTS, log=print):
     """(feats n x 16, targets n x 2) float32 CUDA tensors, 3 records per problem;
-    h / h_cfl log-uniform on `hmult`."""
+    h / h_cfl log-uniform on `hmult`, n uniform over `sizes`."""
     import torch
 
     from workloads import proposal_training_set
     lj = _lj()
-    items = proposal_training_set((count + 2) // 3, seed=seed, hmult=hmult)
+    items = proposal_training_set((count + 2) // 3, seed=seed, hmult=hmult, sizes=sizes, weights=weights)
     feats, targs = [], []
     os.environ["LJ_BATCH_SCHEDULE"] = "0"  # no per-chunk tuning: one block per instance
     try:
-        for fam in ("advdiff", "allencahn"):
+        for fam in ("advdiff", "allencahn", "burgers"):
             fam_items = [it for it in items if it[0].kind == fam]
             for c0 in range(0, len(fam_items), chunk):
                 part = fam_items[c0:c0 + chunk]
@@ -65,20 +71,13 @@ def make_records(ctx, count: int, seed: int = 7, chunk: int = 512, hmult=(1.0, 1
                 _, sts = b.stats()
                 b.close()
                 fb = torch.empty((len(part) * len(LS), 16), dtype=torch.float32, device="cuda:0")
-                for i, (op, h) in enumerate(zip(ops, hs)):
+                tb = torch.empty((len(part) * len(LS), 2), dtype=torch.float32, device="cuda:0")
+                for i, (op, h, st) in enumerate(zip(ops, hs, sts)):
                     for k, l in enumerate(LS):
-                        lj.lj_features(ctx, op, h, l, fb[i * len(LS) + k])
-                fh = fb.cpu()
-                t = torch.empty((len(part) * len(LS), 2), dtype=torch.float32)
-                for i, (st, h) in enumerate(zip(sts, hs)):
-                    for k in range(len(LS)):
                         r = i * len(LS) + k
-                        sigma = 10.0 ** float(fh[r, 0]) / h
-                        s = max(int(st["substeps"][k]), 1)
-                        t[r, 0] = math.log(st["bound"] / sigma)
-                        t[r, 1] = math.log2(s)
+                        lj.lj_proposal_record(ctx, op, h, l, st["bound"], max(int(st["substeps"][k]), 1), fb[r], tb[r])
                 feats.append(fb)
-                targs.append(t.to("cuda:0"))
+                targs.append(tb)
                 log(f"records: {fam} {c0 + len(part)}/{len(fam_items)}", flush=True)
     finally:
         os.environ.pop("LJ_BATCH_SCHEDULE", None)
@@ -90,39 +89,12 @@ def make_records(ctx, count: int, seed: int = 7, chunk: int = 512, hmult=(1.0, 1
     return X[perm].contiguous(), T[perm].contiguous()
 
 
-def gershgorin_bound(prob) -> float:
-    """A closed-form bound of the spectral radius of J (Gershgorin discs of the
-    5-point Jacobian at the problem's state), the no-iteration baseline the
-    proposal is compared with.  Host-side NumPy over the state."""
-    import numpy as np
-    dx, dy = prob.dx, prob.dy
-    if prob.kind == "burgers":
-        nu = prob.coef[0]
-        U = np.asarray(prob.state, dtype=np.float64).reshape(prob.ny, prob.nx)
-        diag = 2.0 * nu * (1.0 / dx ** 2 + 1.0 / dy ** 2)
-        off = (np.abs(nu / dx ** 2 - np.roll(U, -1, axis=1) / (2 * dx))
-               + np.abs(nu / dx ** 2 + np.roll(U, 1, axis=1) / (2 * dx))
-               + np.abs(nu / dy ** 2 - np.roll(U, -1, axis=0) / (2 * dy))
-               + np.abs(nu / dy ** 2 + np.roll(U, 1, axis=0) / (2 * dy)))
-        return float(np.max(diag + off))
-    if prob.kind == "allencahn":
-        eps = prob.coef[0]
-        u = np.asarray(prob.state, dtype=np.float64)
-        lap = 2.0 * eps * (1.0 / dx ** 2 + 1.0 / dy ** 2)
-        return float(np.max(np.abs(-lap + 1.0 - 3.0 * u * u)) + lap)
-    if prob.kind == "advdiff":
-        nu, ax, ay = prob.coef[0], prob.coef[1], prob.coef[2]
-        diag = 2.0 * nu * (1.0 / dx ** 2 + 1.0 / dy ** 2)
-        return diag + abs(nu / dx ** 2 - ax / (2 * dx)) + abs(nu / dx ** 2 + ax / (2 * dx)) \
-            + abs(nu / dy ** 2 - ay / (2 * dy)) + abs(nu / dy ** 2 + ay / (2 * dy))
-    raise ValueError(f"no Gershgorin bound for {prob.kind}")
-
-
-def compare(ctx, prob, h, l, v=None, gershgorin=False):
+def compare(ctx, prob, h, l, v=None, gershgorin=False, reps=1):
     """One action by the plain method and by the proposal (and, if asked, with
-    the closed-form Gershgorin bound and no power iteration): statistics, wall
-    time of each, and the relative difference of the proposal's result to the
-    plain one."""
+    the Gershgorin bound of J computed by the library in place of the power
+    iteration, its cost included in the time): statistics, wall time of each
+    (median of `reps` timed calls after a warm-up), and the relative
+    difference of the proposal's result to the plain one."""
     import torch
     lj = _lj()
     op = lj.operator_from(prob, "cuda:0")
@@ -134,17 +106,25 @@ def compare(ctx, prob, h, l, v=None, gershgorin=False):
         vd = torch.as_tensor(v, dtype=torch.float64, device="cuda:0").contiguous()
     out = {}
     res = {}
-    variants = [("plain", lj.lj_default_options()), ("proposal", lj.lj_default_options(use_proposal=1))]
-    if gershgorin:
-        variants.append(("gershgorin", lj.lj_default_options(bound=gershgorin_bound(prob))))
-    for name, opt in variants:
+
+    def run(name, w):
+        if name == "gershgorin":
+            opt = lj.lj_default_options(bound=lj.lj_gershgorin_bound(ctx, op))
+        else:
+            opt = lj.lj_default_options(use_proposal=1 if name == "proposal" else 0)
+        return lj.lj_phi_action(ctx, op, vd, w, l, h, TOL, opt)
+
+    for name in ("plain", "proposal") + (("gershgorin",) if gershgorin else ()):
         w = torch.empty_like(vd)
-        lj.lj_phi_action(ctx, op, vd, w, l, h, TOL, opt)  # warm-up
+        run(name, w)  # warm-up
         torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        rc, st = lj.lj_phi_action(ctx, op, vd, w, l, h, TOL, opt)
-        torch.cuda.synchronize()
-        st["ms"] = (time.perf_counter() - t0) * 1e3
+        ts = []
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            rc, st = run(name, w)
+            torch.cuda.synchronize()
+            ts.append((time.perf_counter() - t0) * 1e3)
+        st["ms"] = sorted(ts)[len(ts) // 2]
         st["rc"] = rc
         st["products"] = st["iters_total"] + st["power_iters"]
         out[name] = st
@@ -153,15 +133,16 @@ def compare(ctx, prob, h, l, v=None, gershgorin=False):
     return out
 
 
-def evaluate(ctx, n: int = 2048, hmults=(1, 10, 30, 100, 300), log=print):
-    """Viscous Burgers on n^2 (the learned form's target workload): plain vs
-    proposal for phi_1..phi_3 at each h / h_cfl."""
+def evaluate(ctx, n: int = 2048, hmults=(1, 10, 30, 100, 300), reps: int = 5, log=print):
+    """Viscous Burgers on n^2 (nu = 1e-3, the state of seed 5; the training
+    sweep's Burgers problems are at most 512^2 and other seeds): plain vs
+    proposal vs the Gershgorin bound for phi_1..phi_3 at each h / h_cfl."""
     from workloads import burgers_sines
     prob = burgers_sines(n)
     rows = []
     for hm in hmults:
         for l in LS:
-            r = compare(ctx, prob, hm * prob.h_cfl, l, gershgorin=True)
+            r = compare(ctx, prob, hm * prob.h_cfl, l, gershgorin=True, reps=reps)
             rows.append({"hmult": hm, "l": l, **{f"{k}_{f}": r[k][f] for k in ("plain", "proposal", "gershgorin")
                                                   for f in ("ms", "products", "rejections", "substeps", "rc")},
                          "fallback": r["proposal"]["fallbacks"], "rel_diff": r["rel_diff"],
@@ -200,7 +181,7 @@ def main(argv=None):
         P = torch.empty((X.shape[0], 2), dtype=torch.float32, device="cuda:0")
         lj.lj_mlp_predict(ctx, X, P)
         err = (P - T).abs().mean(dim=0).tolist()
-        print(f"mean |error|: ln(bound/sigma) {err[0]:.4f}, log2(s) {err[1]:.4f}", flush=True)
+        print(f"mean |error|: ln(bound/G) {err[0]:.4f}, log2(s) {err[1]:.4f}", flush=True)
         lj.lj_mlp_save(ctx, args.out)
         print(json.dumps({"records": int(X.shape[0]), "epochs": args.epochs, "loss_first": losses[0],
                           "loss_last": losses[-1], "mae": err, "gen_s": t1 - t0, "train_s": t2 - t1}), flush=True)

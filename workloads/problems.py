@@ -211,25 +211,38 @@ def batch_instances(count: int = 256, seed: int = 4, sizes=(128, 192, 256, 384, 
     return out
 
 
-def proposal_training_set(count: int, seed: int = 7, sizes=(32, 48, 64, 96, 128), hmult=(1.0, 100.0)):
-    """Seeded sweep of the two training families of the learned proposal:
-    advection-diffusion (grid Peclet log-uniform on [0.1, 4], Gaussian-bump
-    input) and Allen-Cahn (eps log-uniform on [1e-4, 1e-1], noise amplitude
-    U[0.05, 1]), n uniform over `sizes`, h / h_cfl log-uniform on `hmult`.
+def proposal_training_set(count: int, seed: int = 7, sizes=(32, 48, 64, 96, 128), hmult=(1.0, 100.0),
+                          weights=None, families=("advdiff", "allencahn", "burgers")):
+    """Seeded sweep of the training families of the learned proposal, drawn
+    in turn with equal probability: advection-diffusion (grid Peclet
+    log-uniform on [0.1, 4], Gaussian-bump input), Allen-Cahn (eps log-uniform
+    on [1e-4, 1e-1], noise amplitude U[0.05, 1]) and viscous Burgers (nu
+    log-uniform on [1e-4, 3e-2], eight random sine modes); n drawn from
+    `sizes` (uniformly, or with the relative `weights`), h / h_cfl
+    log-uniform on `hmult`.
 
-    Returns a list of (problem, h, v) with v None for Allen-Cahn (the caller
-    uses h f(u) there) and the bump vector for advection-diffusion."""
+    Returns a list of (problem, h, v) with v None for Allen-Cahn and Burgers
+    (the caller uses h f(u) there) and the bump vector for
+    advection-diffusion."""
     rng = _rng(seed)
+    pw = None
+    if weights is not None:
+        pw = np.asarray(weights, dtype=np.float64)
+        pw = pw / pw.sum()
     out = []
     for i in range(count):
-        n = int(rng.choice(np.asarray(sizes)))
+        n = int(rng.choice(np.asarray(sizes), p=pw))
         hm = float(np.exp(rng.uniform(np.log(hmult[0]), np.log(hmult[1]))))
-        if rng.uniform() < 0.5:
+        fam = families[int(rng.integers(0, len(families)))]
+        if fam == "advdiff":
             pe = float(np.exp(rng.uniform(np.log(0.1), np.log(4.0))))
             prob, v = advdiff_bump(n, nu=1.0, peclet=pe, seed=70000 + i)
-        else:
+        elif fam == "allencahn":
             eps = float(np.exp(rng.uniform(np.log(1e-4), np.log(1e-1))))
             amp = float(rng.uniform(0.05, 1.0))
             prob, v = allen_cahn_noise(n, eps=eps, seed=70000 + i, amp=amp), None
+        else:
+            nu = float(np.exp(rng.uniform(np.log(1e-4), np.log(3e-2))))
+            prob, v = burgers_sines(n, nu=nu, seed=70000 + i), None
         out.append((prob, hm * prob.h_cfl, v))
     return out
