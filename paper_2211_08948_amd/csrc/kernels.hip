@@ -2581,6 +2581,12 @@ void* action_reg_ptr(int kind, int K, bool full) {
     if (K <= 1)                                                                                          \
       return full ? reinterpret_cast<void*>(&lj_action_reg<K_, 1, true>)                                 \
                   : reinterpret_cast<void*>(&lj_action_reg<K_, 1, false>);                               \
+    if (K == 2)                                                                                          \
+      return full ? reinterpret_cast<void*>(&lj_action_reg<K_, 2, true>)                                 \
+                  : reinterpret_cast<void*>(&lj_action_reg<K_, 2, false>);                               \
+    if (K == 3)                                                                                          \
+      return full ? reinterpret_cast<void*>(&lj_action_reg<K_, 3, true>)                                 \
+                  : reinterpret_cast<void*>(&lj_action_reg<K_, 3, false>);                               \
     return full ? reinterpret_cast<void*>(&lj_action_reg<K_, kMaxK, true>)                               \
                 : reinterpret_cast<void*>(&lj_action_reg<K_, kMaxK, false>);                             \
   }
