@@ -427,21 +427,21 @@ __device__ __forceinline__ void power_pass(const OpDev& op, const double* __rest
 // One Newton step (Sec. 2.2 display): y = ((J - c) x)/gamma - xi x, and for
 // every active accumulator p_k += d_k y; acc[0] += y^2, acc[1+k] += p_k^2.
 // rgamma = 1/gamma (the quotient is div_rn).
-template <int KIND, int NC, bool SHARED, int U>
+template <int KIND, int NC, bool SHARED, int U, int KM = kMaxK>
 __device__ __forceinline__ void newton_pass(const OpDev& op, const double* __restrict__ src,
                                             double* __restrict__ dst, double* const (&pp)[kMaxK],
                                             const bool (&act)[kMaxK], const double (&dk)[kMaxK], double c,
                                             double gamma, double rgamma, double xim, int pbeg, int pend,
-                                            int stride, double (&acc)[kQ]) {
+                                            int stride, double (&acc)[1 + KM]) {
   for (int p0 = pbeg; p0 < pend; p0 += stride * U) {
-    double xv[U][5][2], uv[U][5][2], pv[U][kMaxK][2];
+    double xv[U][5][2], uv[U][5][2], pv[U][KM][2];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const int p = p0 + u * stride;
       if (p >= pend) continue;
       gather_point<KIND, NC>(op, src, p, xv[u], uv[u]);
 #pragma unroll
-      for (int k = 0; k < kMaxK; ++k)
+      for (int k = 0; k < KM; ++k)
 #pragma unroll
         for (int cc = 0; cc < NC; ++cc) pv[u][k][cc] = act[k] ? pp[k][NC * p + cc] : 0.0;
     }
@@ -463,7 +463,7 @@ __device__ __forceinline__ void newton_pass(const OpDev& op, const double* __res
         }
         acc[0] += y * y;
 #pragma unroll
-        for (int k = 0; k < kMaxK; ++k) {
+        for (int k = 0; k < KM; ++k) {
           if (act[k]) {
             const double pk = pv[u][k][cc] + dk[k] * y;
             pp[k][idx] = pk;
@@ -487,7 +487,7 @@ struct ActionShared {
 // ===========================================================================
 // Streaming action kernel (any grid size): one pass over HBM per Newton step.
 // ===========================================================================
-template <int KIND, int NC>
+template <int KIND, int NC, int KM>
 __global__ __launch_bounds__(kBlock) void lj_action_stream(ActionParams P) {
   const GridSync gsync{P.barrier, P.spin_limit};
   __shared__ ActionShared sh;
@@ -584,7 +584,7 @@ __global__ __launch_bounds__(kBlock) void lj_action_stream(ActionParams P) {
         const double vv = P.v[idx];
         a0 += vv * vv;
 #pragma unroll
-        for (int k = 0; k < kMaxK; ++k)
+        for (int k = 0; k < KM; ++k)
           if (k < K) P.p[k][idx] = sh.coef[k * kTable] * vv;
       }
     }
@@ -612,18 +612,22 @@ __global__ __launch_bounds__(kBlock) void lj_action_stream(ActionParams P) {
     bool act[kMaxK];
 #pragma unroll
     for (int k = 0; k < kMaxK; ++k) {
-      act[k] = (k < K) && (uniform(sD.st[k]) == ACC_RUNNING);
+      act[k] = (k < KM) && (k < K) && (uniform(sD.st[k]) == ACC_RUNNING);
       dk[k] = act[k] ? uniform(sh.coef[k * kTable + m]) : 0.0;
     }
-    double acc[kQ] = {0.0, 0.0, 0.0, 0.0, 0.0};
-    newton_pass<KIND, NC, true, 1>(op, src, dst, P.p, act, dk, c, gamma, rgamma, xim, p0 + (int)threadIdx.x,
-                                   p1, blockDim.x, acc);
+    double acc[1 + KM];
+#pragma unroll
+    for (int q = 0; q < 1 + KM; ++q) acc[q] = 0.0;
+    // one point per thread at a time: two in flight measured no faster on
+    // HBM-bound grids and spill at the 128-VGPR limit of 1024-thread blocks
+    newton_pass<KIND, NC, true, 1, KM>(op, src, dst, P.p, act, dk, c, gamma, rgamma, xim, p0 + (int)threadIdx.x,
+                                       p1, blockDim.x, acc);
     tick(kProfSteps);
-    block_sum<kQ>(acc, sh.red);
+    block_sum(acc, sh.red);
     double* area = partial_area(P.partials, epoch);
     if (threadIdx.x == 0) {
 #pragma unroll
-      for (int q = 0; q < kQ; ++q)
+      for (int q = 0; q < 1 + KM; ++q)
         if (q <= K) put_partial(my_partial(area, q), acc[q]);
     }
     tick(kProfPublish);
@@ -2541,16 +2545,21 @@ __global__ void lj_sumsq2_final(const double* __restrict__ part, int G, double* 
 int persistent_block() { return kBlock; }
 int tile_halo() { return kMaxSuper; }
 
-void* action_stream_ptr(int kind) {
+void* action_stream_ptr(int kind, int K) {
+#define LJ_STREAM_CASE(K_, NC_)                                                                     \
+  case K_:                                                                                          \
+    return K <= 1 ? reinterpret_cast<void*>(&lj_action_stream<K_, NC_, 1>)                          \
+                  : reinterpret_cast<void*>(&lj_action_stream<K_, NC_, kMaxK>);
   switch (kind) {
-    case OP_DIAG: return reinterpret_cast<void*>(&lj_action_stream<OP_DIAG, 1>);
-    case OP_ADVDIFF: return reinterpret_cast<void*>(&lj_action_stream<OP_ADVDIFF, 1>);
-    case OP_ALLENCAHN: return reinterpret_cast<void*>(&lj_action_stream<OP_ALLENCAHN, 1>);
-    case OP_BRUSSELATOR: return reinterpret_cast<void*>(&lj_action_stream<OP_BRUSSELATOR, 2>);
-    case OP_BURGERS: return reinterpret_cast<void*>(&lj_action_stream<OP_BURGERS, 1>);
-    case OP_GRAYSCOTT: return reinterpret_cast<void*>(&lj_action_stream<OP_GRAYSCOTT, 2>);
-    case OP_ADR: return reinterpret_cast<void*>(&lj_action_stream<OP_ADR, 1>);
+    LJ_STREAM_CASE(OP_DIAG, 1)
+    LJ_STREAM_CASE(OP_ADVDIFF, 1)
+    LJ_STREAM_CASE(OP_ALLENCAHN, 1)
+    LJ_STREAM_CASE(OP_BRUSSELATOR, 2)
+    LJ_STREAM_CASE(OP_BURGERS, 1)
+    LJ_STREAM_CASE(OP_GRAYSCOTT, 2)
+    LJ_STREAM_CASE(OP_ADR, 1)
   }
+#undef LJ_STREAM_CASE
   return nullptr;
 }
 

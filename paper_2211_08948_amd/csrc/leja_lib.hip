@@ -576,7 +576,7 @@ void launch_action(lj_context* ctx, const OpDev& op, const double* v, int K, con
       ctx->dyn_lds[fn] = dyn;
     }
   } else {
-    fn = action_stream_ptr(op.kind);
+    fn = action_stream_ptr(op.kind, K);
     G = grid_for(ctx, op.npts);
   }
   if (ctx->in_noalloc) {
