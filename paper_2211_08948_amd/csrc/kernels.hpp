@@ -53,7 +53,7 @@ void* action_stream_ptr(int kind, int K);  // K accumulators
 void* action_reg_ptr(int kind, int K, bool full);  // register-tiled kernel (full: every tile 32 x 32); nullptr if the family has none
 void* action_regm_ptr(int kind, int K);  // several tiles per block (grids of more tiles than CUs)
 int reg_block();                        // its threads per block
-int reg_steps();                        // steps per super-step (history vectors of the several-tile form)
+int reg_steps();                        // Newton steps per super-step
 size_t reg_lds_bytes();                 // its dynamic LDS (step history)
 size_t reg_static_lds();                // its static LDS
 void* action_tile_ptr(int kind, int ept, int K);  // K accumulators; nullptr if the family has no tiled kernel
