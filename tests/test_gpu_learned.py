@@ -171,6 +171,45 @@ def test_device_decision_skip_and_fallback(env):
     assert float(torch.linalg.norm(w - w0) / torch.linalg.norm(w0)) == 0.0
 
 
+@pytest.mark.parametrize("case", ["burgers-stream", "adr-tile", "allencahn-several-tiles"])
+def test_device_decision_skip_in_every_kernel(env, case):
+    """The proposal's skipped launch (s > 1 asked for) in each action kernel:
+    the streaming kernel (Burgers), the LDS-tiled kernel (advection-diffusion-
+    reaction, Neumann) and the register-tiled kernel with several tiles per
+    block (Allen-Cahn 576^2, 324 tiles); the substepped attempt at the bound
+    the launch read is checked against the oracle at the same (bound, s)."""
+    from oracle.leja import Options, phi_action
+    from oracle.operators import Operator
+    from gpu_util import rel
+    lj, torch, ctx = env
+    # (the advection-diffusion-reaction operator is far from normal at these
+    # grid Peclet numbers: the plain method itself substeps 4 times at 2x CFL
+    # on 256^2, so the proposal asks for 8 there)
+    if case == "burgers-stream":
+        p, mult, e = burgers_sines(64, nu=3e-2, seed=5), 20.0, 1
+    elif case == "adr-tile":
+        p, mult, e = adr_neumann(256, amp=0.05, seed=3), 2.0, 3
+    else:
+        p, mult, e = allen_cahn_noise(576, eps=1e-3, seed=2), 20.0, 1
+    s = 2 ** e
+    op = Operator(p)
+    J = lj.operator_from(p, "cuda:0")
+    h = mult * p.h_cfl
+    v = h * op.rhs(p.state)
+    vd = torch.as_tensor(v, device="cuda:0")
+    lj.lj_mlp_set(ctx, _constant_model([math.log(1.1), float(e)]))
+    w = torch.empty_like(vd)
+    rc, st = lj.lj_phi_action(ctx, J, vd, w, 2, h, TOL, lj.lj_default_options(use_proposal=1))
+    torch.cuda.synchronize()
+    say("skip", case, st["proposal_bound"], st["proposal_substeps"], st["fallbacks"], st["m_star"])
+    assert rc == 0 and st["fallbacks"] == 0 and st["proposal_substeps"] == s and st["substeps"][0] == s
+    pb = lj.LJ_PROPOSAL_MARGIN * OF.gershgorin(p) * math.exp(np.float32(math.log(1.1)))
+    assert st["proposal_bound"] == pytest.approx(pb, rel=1e-6)
+    w_orc, st_orc = phi_action(op, v, 2, h, TOL, Options(bound=st["proposal_bound"], substeps=s, max_substeps=s))
+    assert st["m_star"] == st_orc.m_star and st["substeps"] == st_orc.substeps
+    assert rel(w.cpu().numpy(), w_orc) <= 2 * s * TOL
+
+
 def test_forward_matches_oracle(env):
     lj, torch, ctx = env
     flat, th, mu, sd, tmu, tsd = _model_with_norm()
