@@ -1,10 +1,12 @@
 """The register-tiled kernel with several 32 x 32 tiles per block (grids of
 more tiles than CUs): actions, the vertical form with accumulators that stop
-inside a super-step (the commit from the global history), power iteration,
-rejections with substeps and a scheme step, against the oracle on the same
-seeded inputs; and against the streaming kernel on the same inputs.
-Sizes: 576^2 (324 tiles, one or two per block), 1024^2 (four per block) and
-a non-square 1024 x 320 advection-diffusion grid."""
+inside a super-step (the commit from a snapshot or a rerun of the
+super-step), power iteration, rejections with substeps and a scheme step,
+against the oracle on the same seeded inputs; and against the streaming
+kernel on the same inputs.  Sizes: 576^2 (324 tiles, one or two per block),
+1024^2 (four per block) and a non-square 1024 x 320 advection-diffusion
+grid; a 600^2 grid (not a whole number of tiles) goes to the streaming
+kernel."""
 import os
 
 import numpy as np
@@ -153,3 +155,24 @@ def test_multitile_matches_streaming_kernel(gpu, ac1024):
         assert rel(w, w2.cpu().numpy()) <= 1e-12
     finally:
         ctx2.close()
+
+
+def test_ragged_large_grid_streams(gpu):
+    # 600 is not a multiple of 32: more tiles than CUs and ragged ones, so
+    # the action runs on the streaming kernel; against the oracle
+    prob = allen_cahn_noise(600, eps=1e-3, seed=4)
+    op = Operator(prob)
+    h = 10 * prob.h_cfl
+    v = h * op.rhs(prob.state)
+    lam = power_iteration(op.jv, prob.n, 20)
+    w_orc, st_orc = phi_action(op, v, 2, h, TOL, Options(bound=lam))
+    say("ragged 600^2", st_orc.m_star)
+    lj = gpu.lj
+    lj.lj_timing_read(gpu.ctx, reset=True)
+    lj.lj_timing_enable(gpu.ctx, True)
+    rc, st, w = gpu.action(prob, v, 2, h, TOL, bound=lam)
+    lj.lj_timing_enable(gpu.ctx, False)
+    tm = lj.lj_timing_read(gpu.ctx, reset=True)
+    assert tm["tiled_launches"] == 0
+    assert rc == 0 and st["m_star"] == st_orc.m_star
+    assert rel(w, w_orc) <= TOL
