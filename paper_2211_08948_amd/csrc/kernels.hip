@@ -1465,8 +1465,9 @@ __global__ __launch_bounds__(kRegBlock) void lj_action_reg(ActionParams P) {
 }
 
 // ===========================================================================
-// The register-tiled kernel on grids of more 32 x 32 tiles than CUs (the grid
-// a multiple of 32 in both directions).  Each block owns a contiguous range
+// The register-tiled kernel on grids of more 32 x 32 tiles than CUs (tiles in
+// the last column and row may be narrower, FULL = false: their points outside
+// the grid are masked as in the one-tile kernel).  Each block owns a contiguous range
 // of tiles and, per super-step, takes every one of them through the same up
 // to 16 steps in turn: load the extended tile (from the previous super-step's
 // exchange vector) and the state, step in registers exactly as the one-tile
@@ -1485,7 +1486,7 @@ __global__ __launch_bounds__(kRegBlock) void lj_action_reg(ActionParams P) {
 // a stop there (the likely case) is a copy of the snapshot instead.
 // Norm partials are summed over the block's tiles in tile order.
 // ===========================================================================
-template <int KIND, int KM>
+template <int KIND, int KM, bool FULL>
 __global__ __launch_bounds__(kRegBlock) void lj_action_regm(ActionParams P) {
   static_assert(KIND == OP_ADVDIFF || KIND == OP_ALLENCAHN, "register-tiled kernel: periodic scalar families");
   constexpr int CH = (KM == 1) ? 5 : 3;
@@ -1501,13 +1502,44 @@ __global__ __launch_bounds__(kRegBlock) void lj_action_regm(ActionParams P) {
   const int T = P.ntx * P.nty;
   const int bb = xcd_chunk(blockIdx.x, gridDim.x);
   const int tb0 = (int)((long)bb * T / gridDim.x), tb1 = (int)((long)(bb + 1) * T / gridDim.x);
-  const bool lane_own = lane >= kRegS && lane < kRegS + kRegTile;
   const bool owned_wave = wv >= 2 && wv < 6;
-  const bool own = owned_wave && lane_own;
-  int x0 = 0, y0 = 0;
+  // the tile's owned w x h points at (x0, y0); this wave's owned rows are
+  // its first nr (the same for the whole wave)
+  int x0 = 0, y0 = 0, w = kRegTile, nr = owned_wave ? kRegRows : 0;
   auto set_tile = [&](int t) {
     x0 = (t % P.ntx) * kRegTile;
     y0 = (t / P.ntx) * kRegTile;
+    if constexpr (!FULL) {
+      w = min(kRegTile, nx - x0);
+      const int h = min(kRegTile, ny - y0);
+      nr = uniform(owned_wave ? min(kRegRows, max(0, h - kRegRows * (wv - 2))) : 0);
+    }
+  };
+  // lanes that may own points of the tile (in a full tile: own all 8 rows'),
+  // and within them whether row i's point is owned
+  const bool own_any = owned_wave && lane >= kRegS && lane < kRegS + kRegTile;
+  auto own = [&](int i) { return FULL || (lane < kRegS + w && i < nr); };
+  // sum of squares of this lane's owned values t[0..7] (owned waves only;
+  // the row sums taken there, lanes 16-31 and 32-47, see no other lanes, so
+  // a full tile needs no mask)
+  auto sq_own = [&](const double (&t)[kRegRows]) {
+    double a0 = 0.0, a1 = 0.0;
+    if (FULL || nr == kRegRows) {
+#pragma unroll
+      for (int i = 0; i < kRegRows; i += 2) {
+        a0 = fma(t[i], t[i], a0);
+        a1 = fma(t[i + 1], t[i + 1], a1);
+      }
+    } else {
+#pragma unroll
+      for (int i = 0; i < kRegRows; i += 2) {
+        const double u0 = i < nr ? t[i] : 0.0, u1 = i + 1 < nr ? t[i + 1] : 0.0;
+        a0 = fma(u0, u0, a0);
+        a1 = fma(u1, u1, a1);
+      }
+    }
+    const double a = a0 + a1;
+    return (FULL || lane < kRegS + w) ? a : 0.0;
   };
   auto gidx = [&](int i) {  // global index of extended point (lane, row 8 wv + i), periodic
     int gx = (x0 - kRegS + lane) % nx;
@@ -1516,7 +1548,9 @@ __global__ __launch_bounds__(kRegBlock) void lj_action_regm(ActionParams P) {
     if (gy < 0) gy += ny;
     return (size_t)gy * nx + gx;
   };
-  // owned point of row i (own only)
+  // owned point of row i (own(i) only; there the same as gidx(i), which a
+  // ragged tile's lanes of own_any read from instead: in range everywhere,
+  // their values at points not owned are left out of every sum and store)
   auto gown = [&](int i) { return (size_t)(y0 + kRegRows * wv + i - kRegS) * nx + x0 + lane - kRegS; };
 
   double fw, fe, fs, fn;
@@ -1584,15 +1618,7 @@ __global__ __launch_bounds__(kRegBlock) void lj_action_regm(ActionParams P) {
 #pragma unroll
     for (int i = 0; i < kRegRows; ++i) x[i] = y[i];
   };
-  auto sumsq = [&]() {  // owned waves: this lane's rows (lanes 16-47 are owned points in a full tile)
-    double a0 = 0.0, a1 = 0.0;
-#pragma unroll
-    for (int i = 0; i < kRegRows; i += 2) {
-      a0 = fma(x[i], x[i], a0);
-      a1 = fma(x[i + 1], x[i + 1], a1);
-    }
-    return a0 + a1;
-  };
+  auto sumsq = [&]() { return sq_own(x); };  // owned waves: this lane's owned points
   // add this tile's sums of slots (one value per owned wave) to the staging area
   auto stage_add = [&](int slot, double a) {
     const double t = row_sum(a);
@@ -1613,9 +1639,10 @@ __global__ __launch_bounds__(kRegBlock) void lj_action_regm(ActionParams P) {
     return area;
   };
   auto put_owned = [&](double* dst) {
-    if (own) {
+    if (own_any) {
 #pragma unroll
-      for (int i = 0; i < kRegRows; ++i) store_shared(dst + gown(i), x[i]);
+      for (int i = 0; i < kRegRows; ++i)
+        if (own(i)) store_shared(dst + gown(i), x[i]);
     }
   };
 
@@ -1716,13 +1743,13 @@ __global__ __launch_bounds__(kRegBlock) void lj_action_regm(ActionParams P) {
 #pragma unroll
       for (int i = 0; i < kRegRows; ++i) x[i] = src[gidx(i)];
       double ps[KM][kRegRows];
-      if (own) {
+      if (own_any) {
 #pragma unroll
         for (int k = 0; k < KM; ++k) {
           if (!sel[k]) continue;
           const double* cb = cpar[k] ? P.pw[k] : P.p[k];
 #pragma unroll
-          for (int i = 0; i < kRegRows; ++i) ps[k][i] = cb[gown(i)];
+          for (int i = 0; i < kRegRows; ++i) ps[k][i] = cb[FULL ? gown(i) : gidx(i)];
         }
       }
       for (int j = 1; j <= cmax; ++j) {
@@ -1731,18 +1758,19 @@ __global__ __launch_bounds__(kRegBlock) void lj_action_regm(ActionParams P) {
         for (int k = 0; k < KM; ++k) {
           if (!sel[k] || j > ck[k]) continue;
           const double dk = read_lane(cf[k], j - 1);
-          if (own) {
+          if (own_any) {
 #pragma unroll
             for (int i = 0; i < kRegRows; ++i) ps[k][i] = ps[k][i] + dk * x[i];
           }
         }
       }
-      if (own) {
+      if (own_any) {
 #pragma unroll
         for (int k = 0; k < KM; ++k) {
           if (!sel[k]) continue;
 #pragma unroll
-          for (int i = 0; i < kRegRows; ++i) P.p[k][gown(i)] = ps[k][i];
+          for (int i = 0; i < kRegRows; ++i)
+            if (own(i)) P.p[k][gown(i)] = ps[k][i];
         }
       }
     }
@@ -1767,7 +1795,7 @@ __global__ __launch_bounds__(kRegBlock) void lj_action_regm(ActionParams P) {
 #pragma unroll
       for (int i = 0; i < kRegRows; ++i) x[i] = src[gidx(i)];
       double ps[KM][kRegRows];
-      if (own) {
+      if (own_any) {
 #pragma unroll
         for (int k = 0; k < KM; ++k) {
           if (!act0[k]) continue;
@@ -1776,12 +1804,12 @@ __global__ __launch_bounds__(kRegBlock) void lj_action_regm(ActionParams P) {
 #pragma unroll
             for (int i = 0; i < kRegRows; ++i) {
               ps[k][i] = d0 * x[i];
-              P.p[k][gown(i)] = ps[k][i];  // the committed value p_k = d_{k,0} v
+              if (own(i)) P.p[k][gown(i)] = ps[k][i];  // the committed value p_k = d_{k,0} v
             }
           } else {
             const double* cb = cpar[k] ? P.pw[k] : P.p[k];
 #pragma unroll
-            for (int i = 0; i < kRegRows; ++i) ps[k][i] = cb[gown(i)];
+            for (int i = 0; i < kRegRows; ++i) ps[k][i] = cb[FULL ? gown(i) : gidx(i)];
           }
         }
       }
@@ -1794,24 +1822,19 @@ __global__ __launch_bounds__(kRegBlock) void lj_action_regm(ActionParams P) {
 #pragma unroll
           for (int k = 0; k < KM; ++k) {
             const double dk = read_lane(cfv[k], j - 1);
-            double b0 = 0.0, b1 = 0.0;
 #pragma unroll
-            for (int i = 0; i < kRegRows; i += 2) {
-              ps[k][i] = ps[k][i] + dk * x[i];
-              ps[k][i + 1] = ps[k][i + 1] + dk * x[i + 1];
-              b0 = fma(ps[k][i], ps[k][i], b0);
-              b1 = fma(ps[k][i + 1], ps[k][i + 1], b1);
-            }
-            tq[1 + k] = b0 + b1;
+            for (int i = 0; i < kRegRows; ++i) ps[k][i] = ps[k][i] + dk * x[i];
+            tq[1 + k] = sq_own(ps[k]);
           }
           const int d = steps - j;  // snapshot d - 1 holds the values after step m0 + j
-          if (snap && d >= 1 && d <= kRegSnap && own) {
+          if (snap && d >= 1 && d <= kRegSnap && own_any) {
 #pragma unroll
             for (int k = 0; k < KM; ++k) {
               if (!act0[k]) continue;
               double* sn = P.snap + (size_t)(k * kRegSnap + d - 1) * N;
 #pragma unroll
-              for (int i = 0; i < kRegRows; ++i) sn[gown(i)] = ps[k][i];
+              for (int i = 0; i < kRegRows; ++i)
+                if (own(i)) sn[gown(i)] = ps[k][i];
             }
           }
 #pragma unroll
@@ -1834,13 +1857,14 @@ __global__ __launch_bounds__(kRegBlock) void lj_action_regm(ActionParams P) {
         }
       }
       put_owned(yb((r + 1) % 3));
-      if (own) {  // the speculative values go to the buffer that is not the committed one
+      if (own_any) {  // the speculative values go to the buffer that is not the committed one
 #pragma unroll
         for (int k = 0; k < KM; ++k) {
           if (!act0[k]) continue;
           double* sb = cpar[k] ? P.p[k] : P.pw[k];
 #pragma unroll
-          for (int i = 0; i < kRegRows; ++i) sb[gown(i)] = ps[k][i];
+          for (int i = 0; i < kRegRows; ++i)
+            if (own(i)) sb[gown(i)] = ps[k][i];
         }
       }
     }
@@ -1882,13 +1906,14 @@ __global__ __launch_bounds__(kRegBlock) void lj_action_regm(ActionParams P) {
     if (anysnap) {
       for (int t = tb0; t < tb1; ++t) {
         set_tile(t);
-        if (!own) continue;
+        if (!own_any) continue;
 #pragma unroll
         for (int k = 0; k < KM; ++k) {
           if (!fromsnap[k]) continue;
           const double* sn = P.snap + (size_t)(k * kRegSnap + steps - ck[k] - 1) * N;
 #pragma unroll
-          for (int i = 0; i < kRegRows; ++i) P.p[k][gown(i)] = sn[gown(i)];
+          for (int i = 0; i < kRegRows; ++i)
+            if (own(i)) P.p[k][gown(i)] = sn[gown(i)];
         }
       }
 #pragma unroll
@@ -1933,9 +1958,10 @@ __global__ __launch_bounds__(kRegBlock) void lj_action_regm(ActionParams P) {
     if (k >= K || fin[k] || !cpar[k]) continue;
     for (int t = tb0; t < tb1; ++t) {
       set_tile(t);
-      if (!own) continue;
+      if (!own_any) continue;
 #pragma unroll
-      for (int i = 0; i < kRegRows; ++i) P.p[k][gown(i)] = P.pw[k][gown(i)];
+      for (int i = 0; i < kRegRows; ++i)
+        if (own(i)) P.p[k][gown(i)] = P.pw[k][gown(i)];
     }
   }
   if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -2604,13 +2630,18 @@ void* action_reg_ptr(int kind, int K, bool full) {
 #undef LJ_REG_CASE
   return nullptr;
 }
-void* action_regm_ptr(int kind, int K) {
-  if (kind == OP_ALLENCAHN)
-    return K <= 1 ? reinterpret_cast<void*>(&lj_action_regm<OP_ALLENCAHN, 1>)
-                  : reinterpret_cast<void*>(&lj_action_regm<OP_ALLENCAHN, kMaxK>);
-  if (kind == OP_ADVDIFF)
-    return K <= 1 ? reinterpret_cast<void*>(&lj_action_regm<OP_ADVDIFF, 1>)
-                  : reinterpret_cast<void*>(&lj_action_regm<OP_ADVDIFF, kMaxK>);
+void* action_regm_ptr(int kind, int K, bool full) {
+#define LJ_REGM_CASE(K_)                                                                                 \
+  if (kind == K_) {                                                                                      \
+    if (K <= 1)                                                                                          \
+      return full ? reinterpret_cast<void*>(&lj_action_regm<K_, 1, true>)                                \
+                  : reinterpret_cast<void*>(&lj_action_regm<K_, 1, false>);                              \
+    return full ? reinterpret_cast<void*>(&lj_action_regm<K_, kMaxK, true>)                              \
+                : reinterpret_cast<void*>(&lj_action_regm<K_, kMaxK, false>);                            \
+  }
+  LJ_REGM_CASE(OP_ALLENCAHN)
+  LJ_REGM_CASE(OP_ADVDIFF)
+#undef LJ_REGM_CASE
   return nullptr;
 }
 int reg_block() { return kRegBlock; }

@@ -51,7 +51,7 @@ int persistent_block();  // threads per block of the action kernels
 int tile_halo();         // halo width = Newton steps per barrier of the tiled kernel
 void* action_stream_ptr(int kind, int K);  // K accumulators
 void* action_reg_ptr(int kind, int K, bool full);  // register-tiled kernel (full: every tile 32 x 32); nullptr if the family has none
-void* action_regm_ptr(int kind, int K);  // several tiles per block (grids of more tiles than CUs)
+void* action_regm_ptr(int kind, int K, bool full);  // several tiles per block (grids of more tiles than CUs)
 int reg_block();                        // its threads per block
 int reg_steps();                        // Newton steps per super-step
 size_t reg_lds_bytes();                 // its dynamic LDS (step history)

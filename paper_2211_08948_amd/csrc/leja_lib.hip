@@ -386,7 +386,7 @@ TilePlan tile_plan(lj_context* ctx, const OpDev& op) {
 
 // Register-tiled kernel: 32 x 32 tiles, one per block with the step history
 // in dynamic LDS when they fit one per CU (at most 256, the partial-sum
-// reduction's assumption), else several per block (full tiles only).
+// reduction's assumption), else several per block.
 struct RegPlan {
   bool ok = false;
   bool full = false;   // every tile is 32 x 32
@@ -404,12 +404,12 @@ RegPlan reg_plan(lj_context* ctx, const OpDev& op, int K) {
   const long T = (long)ntx * nty;
   const bool full = op.nx % 32 == 0 && op.ny % 32 == 0;
   if (T > ctx->num_cus || T > 256) {
-    // several tiles per block: full tiles only, not in the allocation-free
-    // path (it needs 3 + 4K workspace vectors)
-    if (!full || ctx->in_noalloc || action_regm_ptr(op.kind, K) == nullptr) return r;
+    // several tiles per block: not in the allocation-free path (it needs
+    // 3 + (1 + kRegSnap) K workspace vectors)
+    if (ctx->in_noalloc || action_regm_ptr(op.kind, K, full) == nullptr) return r;
     if (reg_static_lds() > (size_t)ctx->lds_max) return r;
     r.ok = true;
-    r.full = true;
+    r.full = full;
     r.multi = true;
     r.ntx = ntx;
     r.nty = nty;
@@ -545,7 +545,7 @@ void launch_action(lj_context* ctx, const OpDev& op, const double* v, int K, con
   size_t dyn = 0;
   int block = persistent_block();
   if (rp.ok) {
-    fn = rp.multi ? action_regm_ptr(op.kind, K) : action_reg_ptr(op.kind, K, rp.full);
+    fn = rp.multi ? action_regm_ptr(op.kind, K, rp.full) : action_reg_ptr(op.kind, K, rp.full);
     P.tx = 32;
     P.ty = 32;
     P.ntx = rp.ntx;

@@ -5,8 +5,8 @@ super-step), power iteration, rejections with substeps and a scheme step,
 against the oracle on the same seeded inputs; and against the streaming
 kernel on the same inputs.  Sizes: 576^2 (324 tiles, one or two per block),
 1024^2 (four per block) and a non-square 1024 x 320 advection-diffusion
-grid; a 600^2 grid (not a whole number of tiles) goes to the streaming
-kernel."""
+grid; ragged grids (600^2, 1000 x 300: the last column and row of tiles
+narrower) on the same kernel."""
 import os
 
 import numpy as np
@@ -157,22 +157,98 @@ def test_multitile_matches_streaming_kernel(gpu, ac1024):
         ctx2.close()
 
 
-def test_ragged_large_grid_streams(gpu):
-    # 600 is not a multiple of 32: more tiles than CUs and ragged ones, so
-    # the action runs on the streaming kernel; against the oracle
+@pytest.fixture(scope="module")
+def ac600():
+    # 600 = 18 * 32 + 24: 19 x 19 = 361 tiles (more than CUs), those of the
+    # last column and row 24 points wide
     prob = allen_cahn_noise(600, eps=1e-3, seed=4)
     op = Operator(prob)
-    h = 10 * prob.h_cfl
-    v = h * op.rhs(prob.state)
-    lam = power_iteration(op.jv, prob.n, 20)
-    w_orc, st_orc = phi_action(op, v, 2, h, TOL, Options(bound=lam))
-    say("ragged 600^2", st_orc.m_star)
+    return prob, op, power_iteration(op.jv, prob.n, 20)
+
+
+def _tiled(gpu, fn):
     lj = gpu.lj
     lj.lj_timing_read(gpu.ctx, reset=True)
     lj.lj_timing_enable(gpu.ctx, True)
-    rc, st, w = gpu.action(prob, v, 2, h, TOL, bound=lam)
-    lj.lj_timing_enable(gpu.ctx, False)
+    try:
+        out = fn()
+    finally:
+        lj.lj_timing_enable(gpu.ctx, False)
     tm = lj.lj_timing_read(gpu.ctx, reset=True)
-    assert tm["tiled_launches"] == 0
+    return out, tm
+
+
+@pytest.mark.parametrize("l", [1, 2])
+def test_ragged_600_action(gpu, ac600, l):
+    prob, op, lam = ac600
+    h = 10 * prob.h_cfl
+    v = h * op.rhs(prob.state)
+    w_orc, st_orc = phi_action(op, v, l, h, TOL, Options(bound=lam))
+    say("ragged 600^2", l, st_orc.m_star)
+    (rc, st, w), tm = _tiled(gpu, lambda: gpu.action(prob, v, l, h, TOL, bound=lam))
+    assert tm["tiled_launches"] == tm["launches"] >= 1  # the register-tiled kernel ran
     assert rc == 0 and st["m_star"] == st_orc.m_star
     assert rel(w, w_orc) <= TOL
+
+
+def test_ragged_600_vertical_own_bound(gpu, ac600):
+    # the power iteration, a stop inside the first super-step (the commit from
+    # a snapshot or a rerun) and four accumulators' instance on ragged tiles
+    prob, op, lam = ac600
+    h = 10 * prob.h_cfl
+    v = h * op.rhs(prob.state)
+    ls, As = [1, 1, 1], [1 / 8, 1 / 9, 1.0]
+    ws_orc, st_orc = phi_vertical(op, v, ls, As, h, TOL)
+    say("ragged 600^2 vertical", st_orc.m_star)
+    assert min(st_orc.m_star) < 16 < max(st_orc.m_star)
+    (rc, st, ws), tm = _tiled(gpu, lambda: gpu.vertical(prob, v, ls, As, h, TOL))
+    assert tm["tiled_launches"] == tm["launches"] >= 1
+    assert rc == 0 and st["m_star"] == st_orc.m_star
+    assert abs(st["bound"] - st_orc.bound) <= 1e-12 * st_orc.bound
+    for a, b in zip(ws, ws_orc):
+        assert rel(a, b) <= TOL
+
+
+def test_ragged_advdiff_nonsquare(gpu):
+    # 1000 x 300: 32 x 10 = 320 tiles, the last column 8 wide, the last row 12 high
+    nx, ny = 1000, 300
+    dx = 1.0 / nx
+    a = 1.0 / dx
+    prob = Problem("advdiff", nx, ny, 1, dx, dx, (1.0, a, 0.5 * a), None, dx * dx / 4.0)
+    op = Operator(prob)
+    rng = np.random.default_rng(13)
+    v = rng.standard_normal(prob.n)
+    h = 10 * prob.h_cfl
+    lam = power_iteration(op.jv, prob.n, 20)
+    w_orc, st_orc = phi_action(op, v, 1, h, TOL, Options(bound=lam))
+    say("ragged advdiff 1000x300", st_orc.m_star)
+    (rc, st, w), tm = _tiled(gpu, lambda: gpu.action(prob, v, 1, h, TOL, bound=lam))
+    assert tm["tiled_launches"] == tm["launches"] >= 1
+    assert rc == 0 and st["m_star"] == st_orc.m_star
+    assert rel(w, w_orc) <= TOL
+
+
+def test_ragged_matches_streaming_kernel(gpu, ac600):
+    """The ragged grid through the streaming kernel (LJ_NO_REG=1 at context
+    creation): identical point counts, results within 1e-12."""
+    import paper_2211_08948_amd as lj
+    prob, op, lam = ac600
+    h = 30 * prob.h_cfl
+    v = h * op.rhs(prob.state)
+    rc, st, w = gpu.action(prob, v, 1, h, TOL, bound=lam)
+    os.environ["LJ_NO_REG"] = "1"
+    try:
+        ctx2 = lj.Context(0)
+    finally:
+        del os.environ["LJ_NO_REG"]
+    try:
+        J = gpu.op(prob)
+        vd = gpu.dev(v)
+        w2 = gpu.torch.empty_like(vd)
+        rc2, st2 = lj.lj_phi_action(ctx2, J, vd, w2, 1, h, TOL, lj.lj_default_options(bound=lam))
+        gpu.torch.cuda.synchronize()
+        say("ragged vs streaming", st["m_star"], st2["m_star"])
+        assert rc == rc2 == 0 and st["m_star"] == st2["m_star"]
+        assert rel(w, w2.cpu().numpy()) <= 1e-12
+    finally:
+        ctx2.close()
