@@ -236,8 +236,11 @@ __device__ __forceinline__ double phi_series(double z) {
   return s;
 }
 
-// l in [0, kMaxL]; the callers validate it
-__device__ __noinline__ double phi_dev(int l, double z) {
+// l in [0, kMaxL]; the callers validate it.  phi_eval is the inline form:
+// a call waits at its entry for every memory operation its caller has in
+// flight, so a kernel that issued its input loads first and evaluates phi
+// while they arrive takes this one; the others call phi_dev, out of line.
+__device__ __forceinline__ double phi_eval(int l, double z) {
   if (fabs(z) <= 2.0) {
     switch (l) {
       case 0: return phi_series<0>(z);
@@ -255,6 +258,7 @@ __device__ __noinline__ double phi_dev(int l, double z) {
   }
   return p;
 }
+__device__ __noinline__ double phi_dev(int l, double z) { return phi_eval(l, z); }
 
 // ---------------------------------------------------------------------------
 // Cross-lane moves and reductions on DPP (data-parallel primitives: lane

@@ -109,13 +109,14 @@ __device__ void dd_init(DivDiff& D, int K, const int* l, const double* s, int n,
 // (accumulator, node) pair per thread and round, staged in coef), then taken
 // by the wave that owns the accumulator's table: the same values, in a
 // fraction of the time one wave needs for all of them.  Called by every
-// thread; ends with a block barrier.
+// thread; ends with a block barrier.  phi is inline here: the register-tiled
+// kernels' loads of v, issued at launch, stay in flight meanwhile.
 __device__ void dd_init_par(DivDiff& D, int K, const int* l, const double* s, int n, double c, double gamma,
                             const double* xi, double* coef, double* fmax_out) {
 #pragma clang fp contract(off)
   for (int t = threadIdx.x; t < K * kTable; t += blockDim.x) {
     const int k = t / kTable, j = t - k * kTable;
-    if (j < n) coef[t] = phi_dev(l[k], s[k] * (c + gamma * xi[j]));
+    if (j < n) coef[t] = phi_eval(l[k], s[k] * (c + gamma * xi[j]));
   }
   __syncthreads();
   const int wid = threadIdx.x >> 6;
@@ -1048,6 +1049,8 @@ struct RegShared {
   double xrow[2][2 * kRegWaves][64];   // [parity][2 w: first row of wave w, 2 w + 1: its last row][lane]
   Decision D;
   int commit[kMaxK];
+  int lk[kMaxK];     // l_k and s_k of the launch (read from LDS by the divided differences)
+  double sk[kMaxK];
 };
 
 // Partial sums of one super-step: slot q of block b at area[q * G + b].
@@ -1098,7 +1101,13 @@ __global__ __launch_bounds__(kRegBlock) void lj_action_reg(ActionParams P) {
   const int Q = 1 + K;
   const int nx = op.nx, ny = op.ny;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  for (int i = threadIdx.x; i < kTable; i += kRegBlock) sh.xi[i] = P.xi[i];
+  static_assert(kTable <= kRegBlock, "one Leja node per thread");
+  // the nodes, l_k and s_k go to LDS just before the divided differences;
+  // their loads are issued here with the state's and the bound's (indices
+  // clamped in range: no branch, so no load waits for another)
+  const double xi_t = P.xi[min((int)threadIdx.x, kTable - 1)];
+  const int l_t = P.l[min((int)threadIdx.x, kMaxK - 1)];
+  const double s_t = P.s[min((int)threadIdx.x, kMaxK - 1)];
 
   // ---- tile geometry: owned w x h points at (x0, y0); lane = extended column,
   // rows 8 wv + i of the extended tile (extended origin at x0 - 16, y0 - 16)
@@ -1244,10 +1253,6 @@ __global__ __launch_bounds__(kRegBlock) void lj_action_reg(ActionParams P) {
   double lam = (P.lam_src != nullptr && !P.do_power) ? *P.lam_src : P.lam_in;
   if (skip_launch(P, lam, prof)) return;
   int pit = 0;
-  if (!P.do_power && K > 0) {  // y_0 = v: the loads fly while the bound and the table are formed
-#pragma unroll
-    for (int i = 0; i < kRegRows; ++i) x[i] = P.v[(size_t)grow(i) * nx + gxc];
-  }
   if (P.do_power) {
 #pragma unroll
     for (int i = 0; i < kRegRows; ++i) {
@@ -1309,16 +1314,21 @@ __global__ __launch_bounds__(kRegBlock) void lj_action_reg(ActionParams P) {
 #pragma unroll
   for (int i = 0; i < kRegRows; ++i) dg[i] = (dg[i] - c) * rgamma;
 
-  // ---- (2) divided differences up to the first super-step's last term (the
-  // rest while barriers are pending), and y_0 = v on the extended tile (a
-  // launch without power iteration issued v's loads at its start)
-  __syncthreads();
-  if (P.do_power) {
+  // ---- (2) y_0 = v on the extended tile, and the divided differences up to
+  // the first super-step's last term (the rest while barriers are pending).
+  // v's loads are issued first and stay in flight while the table is formed:
+  // it reads LDS only (the nodes, l_k and s_k), so nothing waits on them
+  // before the first use of y_0
 #pragma unroll
-    for (int i = 0; i < kRegRows; ++i) x[i] = P.v[(size_t)grow(i) * nx + gxc];
+  for (int i = 0; i < kRegRows; ++i) x[i] = P.v[(size_t)grow(i) * nx + gxc];
+  if (threadIdx.x < kTable) sh.xi[threadIdx.x] = xi_t;
+  if (threadIdx.x < kMaxK) {
+    sh.lk[threadIdx.x] = l_t;
+    sh.sk[threadIdx.x] = s_t;
   }
+  __syncthreads();
   DivDiff dd;
-  dd_init_par(dd, K, P.l, P.s, P.max_points + 1, c, gamma, sh.xi, sh.coef, sh.fmax);
+  dd_init_par(dd, K, sh.lk, sh.sk, P.max_points + 1, c, gamma, sh.xi, sh.coef, sh.fmax);
   dd_advance(dd, K, kRegS, sh.xi, sh.coef);
   __syncthreads();
   tick(kProfDivdiff);
