@@ -61,23 +61,18 @@ __device__ __forceinline__ void point_range(int npts, int& p0, int& p1) {
 // After `order` orders the entries d_0..d_order are final, so the table can be
 // advanced lazily: the Newton step m needs d_m only, and the action kernels
 // advance it a few orders at a time while their blocks wait at a grid
-// barrier.  The state lives in the registers of waves 0..K-1.
+// barrier.  The state lives in the registers of waves 0..K-1.  The nodes
+// 64..100 are needed only by recurrences longer than 64 terms, so their half
+// of the column lags: it catches up (same operations, same values) once an
+// entry there is asked for, taking node 63's value after each order from h63.
 // ---------------------------------------------------------------------------
 struct DivDiff {
-  double d0, d1;  // current column at nodes j0 = lane, j1 = lane + 64
+  double d0, d1;  // current column at nodes j0 = lane (after `order` orders), j1 = lane + 64 (after `order1`)
+  double h63;     // lane k (k <= 63): d_63 after order k
   int order;      // orders done
+  int order1;     // orders done on the nodes j1
   int n;          // nodes
 };
-
-__device__ __forceinline__ void dd_denoms(int n, double x0, double x1, const double* xi, int order, double& den0,
-                                          double& den1) {
-  const int lane = threadIdx.x & 63;
-  const int j0 = lane, j1 = lane + 64;
-  const double xa = xi[min(max(j0 - order, 0), kTable - 1)];
-  const double xb = xi[min(max(j1 - order, 0), kTable - 1)];
-  den0 = (j0 >= order && j0 < n) ? x0 - xa : 1.0;
-  den1 = (j1 >= order && j1 < n) ? x1 - xb : 1.0;
-}
 
 // phi values at the nodes, fmax[k] = max_j |f_j|, coef[k * kTable] = d_0.
 // Called by every thread; waves >= K do nothing.
@@ -87,9 +82,11 @@ __device__ void dd_init(DivDiff& D, int K, const int* l, const double* s, int n,
   const int wid = threadIdx.x >> 6;
   const int lane = threadIdx.x & 63;
   D.order = 0;
+  D.order1 = 0;
   D.n = n;
   D.d0 = 0.0;
   D.d1 = 0.0;
+  D.h63 = 0.0;
   if (wid >= K) return;
   const int lk = l[wid];
   const double sk = s[wid];
@@ -98,6 +95,7 @@ __device__ void dd_init(DivDiff& D, int K, const int* l, const double* s, int n,
   const double x1 = (j1 < kTable) ? xi[j1] : 0.0;
   if (j0 < n) D.d0 = phi_dev(lk, sk * (c + gamma * x0));
   if (j1 < n) D.d1 = phi_dev(lk, sk * (c + gamma * x1));
+  D.h63 = read_lane(D.d0, 63);
   const double m = wave_max(fmax(fabs(D.d0), fabs(D.d1)));
   if (lane == 0) {
     fmax_out[wid] = m;
@@ -122,13 +120,16 @@ __device__ void dd_init_par(DivDiff& D, int K, const int* l, const double* s, in
   const int wid = threadIdx.x >> 6;
   const int lane = threadIdx.x & 63;
   D.order = 0;
+  D.order1 = 0;
   D.n = n;
   D.d0 = 0.0;
   D.d1 = 0.0;
+  D.h63 = 0.0;
   if (wid < K) {
     const int j0 = lane, j1 = lane + 64;
     if (j0 < n) D.d0 = coef[wid * kTable + j0];
     if (j1 < n && j1 < kTable) D.d1 = coef[wid * kTable + j1];
+    D.h63 = read_lane(D.d0, 63);
     const double m = wave_max(fmax(fabs(D.d0), fabs(D.d1)));
     if (lane == 0) fmax_out[wid] = m;
   }
@@ -144,36 +145,54 @@ __device__ void dd_advance(DivDiff& D, int K, int upto, const double* xi, double
   const int n = D.n;
   const int last = min(upto, n - 1);
   if (last <= D.order) return;
-  const int first = D.order + 1;
   const int j0 = lane, j1 = lane + 64;
-  const double x0 = xi[j0];
-  const double x1 = (j1 < kTable) ? xi[j1] : 0.0;
-  double d0 = D.d0, d1 = D.d1;
-  double den0, den1;
-  dd_denoms(n, x0, x1, xi, first, den0, den1);
-  double r0 = 1.0 / den0, r1 = 1.0 / den1;
-  for (int order = first; order <= last; ++order) {
-    double nden0, nden1;
-    dd_denoms(n, x0, x1, xi, order + 1, nden0, nden1);
-    const double nr0 = 1.0 / nden0, nr1 = 1.0 / nden1;
-    const double p0 = wave_shift_up(d0);
-    double p1 = wave_shift_up(d1);
-    const double last0 = read_lane(d0, 63);
-    if (lane == 0) p1 = last0;
-    const double t0 = d0 - p0, t1 = d1 - p1;
-    const double q0 = div_rn(t0, den0, r0), q1 = div_rn(t1, den1, r1);
-    if (j0 >= order && j0 < n) d0 = q0;
-    if (j1 >= order && j1 < n) d1 = q1;
-    den0 = nden0;
-    den1 = nden1;
-    r0 = nr0;
-    r1 = nr1;
+  // nodes 0..63: an order k changes the entries j >= k only, so orders up to
+  // min(last, 63).  The next order's denominator comes from the nodes moved
+  // up one lane (DPP), and its reciprocal forms while this order's chain runs.
+  const int first = D.order + 1;
+  const int last0 = min(last, 63);
+  if (first <= last0) {
+    const double x0 = xi[j0];
+    double d0 = D.d0, h63 = D.h63;
+    double xs0 = xi[max(j0 - first, 0)];  // node j0 - order (lanes j0 >= order)
+    double den0 = (j0 >= first && j0 < n) ? x0 - xs0 : 1.0;
+    double r0 = 1.0 / den0;
+    for (int order = first; order <= last0; ++order) {
+      xs0 = wave_shift_up(xs0);
+      const double nden0 = (j0 >= order + 1 && j0 < n) ? x0 - xs0 : 1.0;
+      const double nr0 = 1.0 / nden0;
+      const double p0 = wave_shift_up(d0);
+      const double q0 = div_rn(d0 - p0, den0, r0);
+      if (j0 >= order && j0 < n) d0 = q0;
+      const double t63 = read_lane(d0, 63);
+      if (lane == order) h63 = t63;
+      den0 = nden0;
+      r0 = nr0;
+    }
+    D.d0 = d0;
+    D.h63 = h63;
+    if (j0 >= first && j0 <= last0) coef[wid * kTable + j0] = d0;
   }
-  D.d0 = d0;
-  D.d1 = d1;
+  // nodes 64..100, once an entry there is asked for: the orders they missed,
+  // with node 63's value after order k - 1 (constant from order 63 on)
+  if (last >= 64) {
+    const int f1 = D.order1 + 1;
+    const double x1 = (j1 < kTable) ? xi[j1] : 0.0;
+    double d1 = D.d1;
+    for (int order = f1; order <= last; ++order) {
+      const double xb = xi[min(max(j1 - order, 0), kTable - 1)];
+      const double den1 = (j1 >= order && j1 < n) ? x1 - xb : 1.0;
+      double p1 = wave_shift_up(d1);
+      const double left = read_lane(D.h63, min(order - 1, 63));
+      if (lane == 0) p1 = left;
+      const double q1 = div_rn(d1 - p1, den1, 1.0 / den1);
+      if (j1 >= order && j1 < n) d1 = q1;
+    }
+    D.d1 = d1;
+    D.order1 = last;
+    if (j1 >= f1 && j1 <= last) coef[wid * kTable + j1] = d1;
+  }
   D.order = last;
-  if (j0 >= first && j0 <= last) coef[wid * kTable + j0] = d0;
-  if (j1 >= first && j1 <= last) coef[wid * kTable + j1] = d1;
 }
 
 // The interval of Sec. 2.2: alpha = -safety * lambda, beta = 0, c the midpoint,
