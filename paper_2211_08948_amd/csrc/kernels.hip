@@ -310,8 +310,9 @@ __device__ void replay_decisions(Decision& D, int K, int m0, int steps, int Q, c
   // length in every block)
   // The decay usually steepens as the expansion converges, so the rate over
   // the last four steps alone often predicts a shorter (and closer)
-  // remainder; the kernel for which an overshoot costs more than a short
-  // extra super-step (several tiles per block) takes the smaller of the two.
+  // remainder; the register-tiled kernels take the smaller of the two (on
+  // the 512^2 bench step it saves more overshooting steps than the extra
+  // super-steps it causes cost), the LDS-tiled one the whole-batch rate.
   int need = 0, need_loc = 0;
   {
     float lq = 0.0f;
@@ -1374,7 +1375,7 @@ __global__ __launch_bounds__(kRegBlock) void lj_action_reg(ActionParams P) {
   bool first = true;
   int m0 = 0;
   while (true) {
-    const int steps = min(min(kRegS, P.max_points - m0), uniform(sh.D.next));
+    const int steps = min(min(kRegS, P.max_points - m0), min(uniform(sh.D.next), uniform(sh.D.next_local)));
     bool act0[KM];
 #pragma unroll
     for (int k = 0; k < KM; ++k) act0[k] = (k < K) && (uniform(sh.D.st[k]) == ACC_RUNNING);
