@@ -1073,6 +1073,13 @@ struct RegShared {
   double sk[kMaxK];
 };
 
+// Compile-time tag of a tile's shape in the several-tile kernel: full (every
+// point of lanes 16-47 in the owned waves is owned) or ragged (masked).
+template <bool B>
+struct TileTag {
+  static constexpr bool full = B;
+};
+
 // Partial sums of one super-step: slot q of block b at area[q * G + b].
 __device__ __forceinline__ double* reg_area(double* partials, unsigned int epoch) {
   return partials + (size_t)(epoch & 1u) * kRegPartStride * gridDim.x;
@@ -1536,6 +1543,7 @@ __global__ __launch_bounds__(kRegBlock) void lj_action_regm(ActionParams P) {
   // the tile's owned w x h points at (x0, y0); this wave's owned rows are
   // its first nr (the same for the whole wave)
   int x0 = 0, y0 = 0, w = kRegTile, nr = owned_wave ? kRegRows : 0;
+  bool tfull = true;  // the current tile is 32 x 32
   auto set_tile = [&](int t) {
     x0 = (t % P.ntx) * kRegTile;
     y0 = (t / P.ntx) * kRegTile;
@@ -1543,18 +1551,32 @@ __global__ __launch_bounds__(kRegBlock) void lj_action_regm(ActionParams P) {
       w = min(kRegTile, nx - x0);
       const int h = min(kRegTile, ny - y0);
       nr = uniform(owned_wave ? min(kRegRows, max(0, h - kRegRows * (wv - 2))) : 0);
+      tfull = w == kRegTile && h == kRegTile;
+    }
+  };
+  // runs body(tag) on the current tile: a ragged grid's full tiles take the
+  // unmasked form too (the masks cost registers the steps need)
+  auto per_tile = [&](auto&& body) {
+    if constexpr (FULL) {
+      body(TileTag<true>{});
+    } else {
+      if (tfull) {
+        body(TileTag<true>{});
+      } else {
+        body(TileTag<false>{});
+      }
     }
   };
   // lanes that may own points of the tile (in a full tile: own all 8 rows'),
   // and within them whether row i's point is owned
   const bool own_any = owned_wave && lane >= kRegS && lane < kRegS + kRegTile;
-  auto own = [&](int i) { return FULL || (lane < kRegS + w && i < nr); };
+  auto own = [&](auto tg, int i) { return decltype(tg)::full || (lane < kRegS + w && i < nr); };
   // sum of squares of this lane's owned values t[0..7] (owned waves only;
   // the row sums taken there, lanes 16-31 and 32-47, see no other lanes, so
   // a full tile needs no mask)
-  auto sq_own = [&](const double (&t)[kRegRows]) {
+  auto sq_own = [&](auto tg, const double (&t)[kRegRows]) {
     double a0 = 0.0, a1 = 0.0;
-    if (FULL || nr == kRegRows) {
+    if (decltype(tg)::full || nr == kRegRows) {
 #pragma unroll
       for (int i = 0; i < kRegRows; i += 2) {
         a0 = fma(t[i], t[i], a0);
@@ -1569,7 +1591,7 @@ __global__ __launch_bounds__(kRegBlock) void lj_action_regm(ActionParams P) {
       }
     }
     const double a = a0 + a1;
-    return (FULL || lane < kRegS + w) ? a : 0.0;
+    return (decltype(tg)::full || lane < kRegS + w) ? a : 0.0;
   };
   auto gidx = [&](int i) {  // global index of extended point (lane, row 8 wv + i), periodic
     int gx = (x0 - kRegS + lane) % nx;
@@ -1648,7 +1670,7 @@ __global__ __launch_bounds__(kRegBlock) void lj_action_regm(ActionParams P) {
 #pragma unroll
     for (int i = 0; i < kRegRows; ++i) x[i] = y[i];
   };
-  auto sumsq = [&]() { return sq_own(x); };  // owned waves: this lane's owned points
+  auto sumsq = [&](auto tg) { return sq_own(tg, x); };  // owned waves: this lane's owned points
   // add this tile's sums of slots (one value per owned wave) to the staging area
   auto stage_add = [&](int slot, double a) {
     const double t = row_sum(a);
@@ -1668,11 +1690,11 @@ __global__ __launch_bounds__(kRegBlock) void lj_action_regm(ActionParams P) {
     }
     return area;
   };
-  auto put_owned = [&](double* dst) {
+  auto put_owned = [&](auto tg, double* dst) {
     if (own_any) {
 #pragma unroll
       for (int i = 0; i < kRegRows; ++i)
-        if (own(i)) store_shared(dst + gown(i), x[i]);
+        if (own(tg, i)) store_shared(dst + gown(i), x[i]);
     }
   };
 
@@ -1690,19 +1712,21 @@ __global__ __launch_bounds__(kRegBlock) void lj_action_regm(ActionParams P) {
       zero_stage(steps + 1);
       for (int t = tb0; t < tb1; ++t) {
         set_tile(t);
-        load_state();
+        per_tile([&](auto tg) {
+          load_state();
 #pragma unroll
-        for (int i = 0; i < kRegRows; ++i) {
-          const size_t g = gidx(i);
-          x[i] = (done == 0) ? (P.start ? P.start[g] : 0.5 + splitmix_uniform(P.seed, (uint64_t)g))
-                             : sc * yb(r)[g];
-        }
-        if (owned_wave) stage_add(0, sumsq());
-        for (int j = 1; j <= steps; ++j) {
-          step(0.0);
-          if (owned_wave) stage_add(j, sumsq());
-        }
-        put_owned(yb((r + 1) % 3));
+          for (int i = 0; i < kRegRows; ++i) {
+            const size_t g = gidx(i);
+            x[i] = (done == 0) ? (P.start ? P.start[g] : 0.5 + splitmix_uniform(P.seed, (uint64_t)g))
+                               : sc * yb(r)[g];
+          }
+          if (owned_wave) stage_add(0, sumsq(tg));
+          for (int j = 1; j <= steps; ++j) {
+            step(0.0);
+            if (owned_wave) stage_add(j, sumsq(tg));
+          }
+          put_owned(tg, yb((r + 1) % 3));
+        });
       }
       double* area = publish(steps + 1);
       grid_allreduce(gsync, epoch, nullptr, 0, nullptr);
@@ -1769,40 +1793,42 @@ __global__ __launch_bounds__(kRegBlock) void lj_action_regm(ActionParams P) {
     const double xiv = (lane < cmax) ? sh.xi[m0 + lane] : 0.0;
     for (int t = tb0; t < tb1; ++t) {
       set_tile(t);
-      load_state();
+      per_tile([&](auto tg) {
+        load_state();
 #pragma unroll
-      for (int i = 0; i < kRegRows; ++i) x[i] = src[gidx(i)];
-      double ps[KM][kRegRows];
-      if (own_any) {
+        for (int i = 0; i < kRegRows; ++i) x[i] = src[gidx(i)];
+        double ps[KM][kRegRows];
+        if (own_any) {
 #pragma unroll
-        for (int k = 0; k < KM; ++k) {
-          if (!sel[k]) continue;
-          const double* cb = cpar[k] ? P.pw[k] : P.p[k];
+          for (int k = 0; k < KM; ++k) {
+            if (!sel[k]) continue;
+            const double* cb = cpar[k] ? P.pw[k] : P.p[k];
 #pragma unroll
-          for (int i = 0; i < kRegRows; ++i) ps[k][i] = cb[FULL ? gown(i) : gidx(i)];
-        }
-      }
-      for (int j = 1; j <= cmax; ++j) {
-        step(read_lane(xiv, j - 1));
-#pragma unroll
-        for (int k = 0; k < KM; ++k) {
-          if (!sel[k] || j > ck[k]) continue;
-          const double dk = read_lane(cf[k], j - 1);
-          if (own_any) {
-#pragma unroll
-            for (int i = 0; i < kRegRows; ++i) ps[k][i] = ps[k][i] + dk * x[i];
+            for (int i = 0; i < kRegRows; ++i) ps[k][i] = cb[decltype(tg)::full ? gown(i) : gidx(i)];
           }
         }
-      }
-      if (own_any) {
+        for (int j = 1; j <= cmax; ++j) {
+          step(read_lane(xiv, j - 1));
 #pragma unroll
-        for (int k = 0; k < KM; ++k) {
-          if (!sel[k]) continue;
+          for (int k = 0; k < KM; ++k) {
+            if (!sel[k] || j > ck[k]) continue;
+            const double dk = read_lane(cf[k], j - 1);
+            if (own_any) {
 #pragma unroll
-          for (int i = 0; i < kRegRows; ++i)
-            if (own(i)) P.p[k][gown(i)] = ps[k][i];
+              for (int i = 0; i < kRegRows; ++i) ps[k][i] = ps[k][i] + dk * x[i];
+            }
+          }
         }
-      }
+        if (own_any) {
+#pragma unroll
+          for (int k = 0; k < KM; ++k) {
+            if (!sel[k]) continue;
+#pragma unroll
+            for (int i = 0; i < kRegRows; ++i)
+              if (own(tg, i)) P.p[k][gown(i)] = ps[k][i];
+          }
+        }
+      });
     }
   };
   while (true) {
@@ -1821,82 +1847,84 @@ __global__ __launch_bounds__(kRegBlock) void lj_action_regm(ActionParams P) {
     zero_stage(nq);
     for (int t = tb0; t < tb1; ++t) {
       set_tile(t);
-      load_state();
+      per_tile([&](auto tg) {
+        load_state();
 #pragma unroll
-      for (int i = 0; i < kRegRows; ++i) x[i] = src[gidx(i)];
-      double ps[KM][kRegRows];
-      if (own_any) {
-#pragma unroll
-        for (int k = 0; k < KM; ++k) {
-          if (!act0[k]) continue;
-          if (first) {
-            const double d0 = sh.coef[k * kTable];
-#pragma unroll
-            for (int i = 0; i < kRegRows; ++i) {
-              ps[k][i] = d0 * x[i];
-              if (own(i)) P.p[k][gown(i)] = ps[k][i];  // the committed value p_k = d_{k,0} v
-            }
-          } else {
-            const double* cb = cpar[k] ? P.pw[k] : P.p[k];
-#pragma unroll
-            for (int i = 0; i < kRegRows; ++i) ps[k][i] = cb[FULL ? gown(i) : gidx(i)];
-          }
-        }
-      }
-      if (first && owned_wave) stage_add(steps * Q, sumsq());
-      for (int j = 1; j <= steps; ++j) {
-        step(read_lane(xiv, j - 1));
-        if (owned_wave) {
-          double tq[1 + KM];
-          tq[0] = sumsq();
+        for (int i = 0; i < kRegRows; ++i) x[i] = src[gidx(i)];
+        double ps[KM][kRegRows];
+        if (own_any) {
 #pragma unroll
           for (int k = 0; k < KM; ++k) {
-            const double dk = read_lane(cfv[k], j - 1);
+            if (!act0[k]) continue;
+            if (first) {
+              const double d0 = sh.coef[k * kTable];
 #pragma unroll
-            for (int i = 0; i < kRegRows; ++i) ps[k][i] = ps[k][i] + dk * x[i];
-            tq[1 + k] = sq_own(ps[k]);
-          }
-          const int d = steps - j;  // snapshot d - 1 holds the values after step m0 + j
-          if (snap && d >= 1 && d <= kRegSnap && own_any) {
+              for (int i = 0; i < kRegRows; ++i) {
+                ps[k][i] = d0 * x[i];
+                if (own(tg, i)) P.p[k][gown(i)] = ps[k][i];  // the committed value p_k = d_{k,0} v
+              }
+            } else {
+              const double* cb = cpar[k] ? P.pw[k] : P.p[k];
 #pragma unroll
-            for (int k = 0; k < KM; ++k) {
-              if (!act0[k]) continue;
-              double* sn = P.snap + (size_t)(k * kRegSnap + d - 1) * N;
-#pragma unroll
-              for (int i = 0; i < kRegRows; ++i)
-                if (own(i)) sn[gown(i)] = ps[k][i];
+              for (int i = 0; i < kRegRows; ++i) ps[k][i] = cb[decltype(tg)::full ? gown(i) : gidx(i)];
             }
           }
+        }
+        if (first && owned_wave) stage_add(steps * Q, sumsq(tg));
+        for (int j = 1; j <= steps; ++j) {
+          step(read_lane(xiv, j - 1));
+          if (owned_wave) {
+            double tq[1 + KM];
+            tq[0] = sumsq(tg);
 #pragma unroll
-          for (int q = 0; q < 1 + KM; ++q) tq[q] += dpp_move<0x111>(tq[q]);
+            for (int k = 0; k < KM; ++k) {
+              const double dk = read_lane(cfv[k], j - 1);
 #pragma unroll
-          for (int q = 0; q < 1 + KM; ++q) tq[q] += dpp_move<0x112>(tq[q]);
+              for (int i = 0; i < kRegRows; ++i) ps[k][i] = ps[k][i] + dk * x[i];
+              tq[1 + k] = sq_own(tg, ps[k]);
+            }
+            const int d = steps - j;  // snapshot d - 1 holds the values after step m0 + j
+            if (snap && d >= 1 && d <= kRegSnap && own_any) {
 #pragma unroll
-          for (int q = 0; q < 1 + KM; ++q) tq[q] += dpp_move<0x114>(tq[q]);
+              for (int k = 0; k < KM; ++k) {
+                if (!act0[k]) continue;
+                double* sn = P.snap + (size_t)(k * kRegSnap + d - 1) * N;
 #pragma unroll
-          for (int q = 0; q < 1 + KM; ++q) tq[q] += dpp_move<0x118>(tq[q]);
-          double uq[1 + KM];
+                for (int i = 0; i < kRegRows; ++i)
+                  if (own(tg, i)) sn[gown(i)] = ps[k][i];
+              }
+            }
 #pragma unroll
-          for (int q = 0; q < 1 + KM; ++q) uq[q] = read_lane(tq[q], 31) + read_lane(tq[q], 47);
-          if (lane == 0) {
-            sh.stg[(j - 1) * Q][wv - 2] += uq[0];
+            for (int q = 0; q < 1 + KM; ++q) tq[q] += dpp_move<0x111>(tq[q]);
 #pragma unroll
-            for (int k = 0; k < KM; ++k)
-              if (k < K) sh.stg[(j - 1) * Q + 1 + k][wv - 2] += uq[1 + k];
+            for (int q = 0; q < 1 + KM; ++q) tq[q] += dpp_move<0x112>(tq[q]);
+#pragma unroll
+            for (int q = 0; q < 1 + KM; ++q) tq[q] += dpp_move<0x114>(tq[q]);
+#pragma unroll
+            for (int q = 0; q < 1 + KM; ++q) tq[q] += dpp_move<0x118>(tq[q]);
+            double uq[1 + KM];
+#pragma unroll
+            for (int q = 0; q < 1 + KM; ++q) uq[q] = read_lane(tq[q], 31) + read_lane(tq[q], 47);
+            if (lane == 0) {
+              sh.stg[(j - 1) * Q][wv - 2] += uq[0];
+#pragma unroll
+              for (int k = 0; k < KM; ++k)
+                if (k < K) sh.stg[(j - 1) * Q + 1 + k][wv - 2] += uq[1 + k];
+            }
           }
         }
-      }
-      put_owned(yb((r + 1) % 3));
-      if (own_any) {  // the speculative values go to the buffer that is not the committed one
+        put_owned(tg, yb((r + 1) % 3));
+        if (own_any) {  // the speculative values go to the buffer that is not the committed one
 #pragma unroll
-        for (int k = 0; k < KM; ++k) {
-          if (!act0[k]) continue;
-          double* sb = cpar[k] ? P.p[k] : P.pw[k];
+          for (int k = 0; k < KM; ++k) {
+            if (!act0[k]) continue;
+            double* sb = cpar[k] ? P.p[k] : P.pw[k];
 #pragma unroll
-          for (int i = 0; i < kRegRows; ++i)
-            if (own(i)) sb[gown(i)] = ps[k][i];
+            for (int i = 0; i < kRegRows; ++i)
+              if (own(tg, i)) sb[gown(i)] = ps[k][i];
+          }
         }
-      }
+      });
     }
     tick(kProfSteps);
     double* area = publish(nq);
@@ -1943,7 +1971,7 @@ __global__ __launch_bounds__(kRegBlock) void lj_action_regm(ActionParams P) {
           const double* sn = P.snap + (size_t)(k * kRegSnap + steps - ck[k] - 1) * N;
 #pragma unroll
           for (int i = 0; i < kRegRows; ++i)
-            if (own(i)) P.p[k][gown(i)] = sn[gown(i)];
+            if (own(TileTag<FULL>{}, i)) P.p[k][gown(i)] = sn[gown(i)];
         }
       }
 #pragma unroll
@@ -1991,7 +2019,7 @@ __global__ __launch_bounds__(kRegBlock) void lj_action_regm(ActionParams P) {
       if (!own_any) continue;
 #pragma unroll
       for (int i = 0; i < kRegRows; ++i)
-        if (own(i)) P.p[k][gown(i)] = P.pw[k][gown(i)];
+        if (own(TileTag<FULL>{}, i)) P.p[k][gown(i)] = P.pw[k][gown(i)];
     }
   }
   if (blockIdx.x == 0 && threadIdx.x == 0) {
