@@ -697,7 +697,7 @@ def main():
     achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
     traffic = measured_traffic()
     log(f"step {dt / args.steps * 1e3:.3f} ms; action kernel: {tm['launches'] / args.steps:.1f} launches/step "
-        f"({tm['tiled_launches']} of {tm['launches']} LDS-tiled), {avg_ms * 1e3:.1f} us avg, "
+        f"({tm['tiled_launches']} of {tm['launches']} tiled), {avg_ms * 1e3:.1f} us avg, "
         f"{tm['iterations'] / launches:.1f} Newton + {tm['power_point_iters'] / launches / max(prob.n, 1):.1f} "
         f"power products per launch, {avg_ms * 1e3 * launches / max(tm['iterations'] + tm['power_point_iters'] / prob.n, 1):.2f} "
         f"us per product")

@@ -548,7 +548,8 @@ typedef struct {
   int64_t point_iters;       /* grid points x Newton iterations */
   int64_t accum_point_iters; /* grid points x sum over iterations of active accumulators */
   int64_t power_point_iters; /* grid points x power-iteration products */
-  int64_t tiled_launches;    /* launches that used the LDS-tiled kernel */
+  int64_t tiled_launches;    /* launches that ran a tiled kernel (register-tiled or LDS-tiled: several
+                                Newton steps per grid barrier) instead of the streaming one */
   double kernel_ms;          /* summed event-measured duration */
   int64_t aborts;            /* launches whose grid barrier gave up (counted whether or not timing is
                                 enabled; each was repeated with a cooperative launch) */
