@@ -228,6 +228,28 @@ def test_ragged_advdiff_nonsquare(gpu):
     assert rel(w, w_orc) <= TOL
 
 
+def test_ragged_advdiff_vertical(gpu):
+    # the four-accumulator instance on ragged tiles (1000 x 300, as above):
+    # phi_1..phi_3 at a_k = 1/3, 1/2, 1 sharing one basis, with stops inside
+    # a super-step, against the oracle
+    nx, ny = 1000, 300
+    dx = 1.0 / nx
+    a = 1.0 / dx
+    prob = Problem("advdiff", nx, ny, 1, dx, dx, (1.0, a, 0.5 * a), None, dx * dx / 4.0)
+    op = Operator(prob)
+    v = np.random.default_rng(14).standard_normal(prob.n)
+    h = 10 * prob.h_cfl
+    lam = power_iteration(op.jv, prob.n, 20)
+    ls, As = [1, 2, 3], [1 / 3, 1 / 2, 1.0]
+    ws_orc, st_orc = phi_vertical(op, v, ls, As, h, TOL, Options(bound=lam))
+    say("ragged advdiff vertical", st_orc.m_star)
+    (rc, st, ws), tm = _tiled(gpu, lambda: gpu.vertical(prob, v, ls, As, h, TOL, bound=lam))
+    assert tm["tiled_launches"] == tm["launches"] >= 1
+    assert rc == 0 and st["m_star"] == st_orc.m_star
+    for x, y in zip(ws, ws_orc):
+        assert rel(x, y) <= TOL
+
+
 def test_ragged_matches_streaming_kernel(gpu, ac600):
     """The ragged grid through the streaming kernel (LJ_NO_REG=1 at context
     creation): identical point counts, results within 1e-12."""
