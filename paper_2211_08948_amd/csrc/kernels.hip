@@ -1289,19 +1289,21 @@ __global__ __launch_bounds__(kRegBlock) void lj_action_reg(ActionParams P) {
     int done = 0;
     while (done < P.power_iters) {
       const int steps = min(kRegS, P.power_iters - done);
-      if (owned_wave) stage(0, sumsq_own());
+      // only the last two norms are read (the bound and the rescaling):
+      // slot 0 holds ||x|| before the last product, slot 1 after it
+      if (owned_wave && steps == 1) stage(0, sumsq_own());
       for (int j = 1; j <= steps; ++j) {
         step(0.0);
-        if (owned_wave) stage(j, sumsq_own());
+        if (owned_wave && j >= steps - 1) stage(j - (steps - 1), sumsq_own());
       }
-      double* area = publish(steps + 1);
+      double* area = publish(2);
       put_owned();
       const bool more = done + steps < P.power_iters;
       grid_allreduce(gsync, epoch, nullptr, 0, nullptr, NoOverlap{}, [&] {
         if (more) fetch_halo();
       });
-      reg_reduce<CH>(area, steps + 1, sh.tot);
-      const double nprev = sh.tot[steps - 1], nlast = sh.tot[steps];
+      reg_reduce<CH>(area, 2, sh.tot);
+      const double nprev = sh.tot[0], nlast = sh.tot[1];
       done += steps;
       pit = done;
       lam = sqrt(nlast) / sqrt(nprev);
@@ -1709,7 +1711,7 @@ __global__ __launch_bounds__(kRegBlock) void lj_action_regm(ActionParams P) {
     double sc = 1.0;
     while (done < P.power_iters) {
       const int steps = min(kRegS, P.power_iters - done);
-      zero_stage(steps + 1);
+      zero_stage(2);  // the two norms read: before and after the last product
       for (int t = tb0; t < tb1; ++t) {
         set_tile(t);
         per_tile([&](auto tg) {
@@ -1720,18 +1722,18 @@ __global__ __launch_bounds__(kRegBlock) void lj_action_regm(ActionParams P) {
             x[i] = (done == 0) ? (P.start ? P.start[g] : 0.5 + splitmix_uniform(P.seed, (uint64_t)g))
                                : sc * yb(r)[g];
           }
-          if (owned_wave) stage_add(0, sumsq(tg));
+          if (owned_wave && steps == 1) stage_add(0, sumsq(tg));
           for (int j = 1; j <= steps; ++j) {
             step(0.0);
-            if (owned_wave) stage_add(j, sumsq(tg));
+            if (owned_wave && j >= steps - 1) stage_add(j - (steps - 1), sumsq(tg));
           }
           put_owned(tg, yb((r + 1) % 3));
         });
       }
-      double* area = publish(steps + 1);
+      double* area = publish(2);
       grid_allreduce(gsync, epoch, nullptr, 0, nullptr);
-      reg_reduce<CH>(area, steps + 1, sh.tot);
-      const double nprev = sh.tot[steps - 1], nlast = sh.tot[steps];
+      reg_reduce<CH>(area, 2, sh.tot);
+      const double nprev = sh.tot[0], nlast = sh.tot[1];
       done += steps;
       pit = done;
       lam = sqrt(nlast) / sqrt(nprev);
